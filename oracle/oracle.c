@@ -1,0 +1,908 @@
+/*
+ * oracle.c -- plain FP64 CPU oracle (TEST INFRASTRUCTURE ONLY; see oracle.h).
+ *
+ * Written to be checked by eye against the paper and the model reading listed
+ * in oracle.h: every step is done in the most direct way (dense matrices, a
+ * full sort of candidates, dense LU), with no blocking or fusion.
+ */
+#include "oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------ */
+/* small vector / quaternion helpers                                   */
+/* ------------------------------------------------------------------ */
+
+static double dot3(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+static void cross3(const double *a, const double *b, double *o)
+{
+    double t0 = a[1] * b[2] - a[2] * b[1];
+    double t1 = a[2] * b[0] - a[0] * b[2];
+    double t2 = a[0] * b[1] - a[1] * b[0];
+    o[0] = t0; o[1] = t1; o[2] = t2;
+}
+static double norm3(const double *a) { return sqrt(dot3(a, a)); }
+
+/* Hamilton product, quaternions stored (w, x, y, z). */
+static void qmul(const double *a, const double *b, double *o)
+{
+    double w = a[0] * b[0] - a[1] * b[1] - a[2] * b[2] - a[3] * b[3];
+    double x = a[0] * b[1] + a[1] * b[0] + a[2] * b[3] - a[3] * b[2];
+    double y = a[0] * b[2] - a[1] * b[3] + a[2] * b[0] + a[3] * b[1];
+    double z = a[0] * b[3] + a[1] * b[2] - a[2] * b[1] + a[3] * b[0];
+    o[0] = w; o[1] = x; o[2] = y; o[3] = z;
+}
+
+/* Rotation matrix of a unit quaternion, row-major. */
+static void qmat(const double *q, double R[9])
+{
+    double w = q[0], x = q[1], y = q[2], z = q[3];
+    R[0] = 1 - 2 * (y * y + z * z); R[1] = 2 * (x * y - w * z);     R[2] = 2 * (x * z + w * y);
+    R[3] = 2 * (x * y + w * z);     R[4] = 1 - 2 * (x * x + z * z); R[5] = 2 * (y * z - w * x);
+    R[6] = 2 * (x * z - w * y);     R[7] = 2 * (y * z + w * x);     R[8] = 1 - 2 * (x * x + y * y);
+}
+static void matvec(const double R[9], const double *v, double *o)
+{
+    double a = R[0] * v[0] + R[1] * v[1] + R[2] * v[2];
+    double b = R[3] * v[0] + R[4] * v[1] + R[5] * v[2];
+    double c = R[6] * v[0] + R[7] * v[1] + R[8] * v[2];
+    o[0] = a; o[1] = b; o[2] = c;
+}
+static void mattvec(const double R[9], const double *v, double *o)
+{
+    double a = R[0] * v[0] + R[3] * v[1] + R[6] * v[2];
+    double b = R[1] * v[0] + R[4] * v[1] + R[7] * v[2];
+    double c = R[2] * v[0] + R[5] * v[1] + R[8] * v[2];
+    o[0] = a; o[1] = b; o[2] = c;
+}
+
+/* Quaternion of a rotation by angle th about unit axis a. */
+static void qaxis(const double *a, double th, double *q)
+{
+    double s = sin(0.5 * th);
+    q[0] = cos(0.5 * th); q[1] = s * a[0]; q[2] = s * a[1]; q[3] = s * a[2];
+}
+
+/* Exponential map of a rotation vector th (world frame), with the series
+ * form near zero. */
+static void qexp(const double *th, double *q)
+{
+    double a = norm3(th);
+    if (a < 1e-4) {
+        double a2 = a * a;
+        double c = 1.0 - a2 / 8.0;
+        double s = 0.5 - a2 / 48.0;
+        q[0] = c; q[1] = s * th[0]; q[2] = s * th[1]; q[3] = s * th[2];
+    } else {
+        double s = sin(0.5 * a) / a;
+        q[0] = cos(0.5 * a); q[1] = s * th[0]; q[2] = s * th[1]; q[3] = s * th[2];
+    }
+}
+
+static void qnormalize(double *q)
+{
+    double n = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+    q[0] /= n; q[1] /= n; q[2] /= n; q[3] /= n;
+}
+
+/* ------------------------------------------------------------------ */
+/* hand forward kinematics                                             */
+/* ------------------------------------------------------------------ */
+
+/* Link table row (20 doubles): parent, joint0, joint1, axis0(3), axis1(3),
+ * offset translation(3, in the parent's tip frame), offset rotation (w,x,y,z),
+ * length, radius, 2 reserved.  A link's frame is the parent's tip frame, moved
+ * by the offset, then turned about axis0 by u[joint0] and about axis1 by
+ * u[joint1]; the capsule runs from the frame origin along local +x. */
+void or_hand_fk(const or_model *m, const double *u, double *seg)
+{
+    int L = m->L;
+    double *tipq = (double *)malloc(sizeof(double) * 4 * (size_t)L);
+    double *tipp = (double *)malloc(sizeof(double) * 3 * (size_t)L);
+    for (int l = 0; l < L; ++l) {
+        const double *h = m->hand + (size_t)l * OR_HAND_STRIDE;
+        int parent = (int)h[0], j0 = (int)h[1], j1 = (int)h[2];
+        double pq[4] = {1, 0, 0, 0}, pp[3] = {0, 0, 0};
+        if (parent >= 0) {
+            memcpy(pq, tipq + 4 * parent, sizeof pq);
+            memcpy(pp, tipp + 3 * parent, sizeof pp);
+        }
+        double Rp[9];
+        qmat(pq, Rp);
+        double off[3];
+        matvec(Rp, h + 9, off);
+        double o[3] = {pp[0] + off[0], pp[1] + off[1], pp[2] + off[2]};
+        double q[4];
+        qmul(pq, h + 12, q);
+        if (j0 >= 0) {
+            double qj[4], t[4];
+            qaxis(h + 3, u[j0], qj);
+            qmul(q, qj, t);
+            memcpy(q, t, sizeof q);
+        }
+        if (j1 >= 0) {
+            double qj[4], t[4];
+            qaxis(h + 6, u[j1], qj);
+            qmul(q, qj, t);
+            memcpy(q, t, sizeof q);
+        }
+        double R[9];
+        qmat(q, R);
+        double len = h[16];
+        double b[3] = {o[0] + len * R[0], o[1] + len * R[3], o[2] + len * R[6]};
+        memcpy(tipq + 4 * l, q, sizeof q);
+        memcpy(tipp + 3 * l, b, sizeof b);
+        double *s = seg + 6 * l;
+        s[0] = o[0]; s[1] = o[1]; s[2] = o[2];
+        s[3] = b[0]; s[4] = b[1]; s[5] = b[2];
+    }
+    free(tipq);
+    free(tipp);
+}
+
+/* ------------------------------------------------------------------ */
+/* narrow phase                                                        */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+    double d;
+    int32_t key;
+} cand_t;
+
+static int cand_cmp(const void *pa, const void *pb)
+{
+    const cand_t *a = (const cand_t *)pa, *b = (const cand_t *)pb;
+    if (a->d < b->d) return -1;
+    if (a->d > b->d) return 1;
+    return (a->key > b->key) - (a->key < b->key);
+}
+
+/* Sphere (centre c, radius rho) against link l (capsule seg0[l], radius R)
+ * or, for l == L, the table plane z = 0.  Fills d, n, p, vlink. */
+static void pair_geometry(const or_model *m, const double *seg0, const double *seg1, int l,
+                          const double *c, double rho, double *d, double *n, double *p, double *vl)
+{
+    int L = m->L;
+    if (l == L) {
+        *d = c[2] - rho;
+        n[0] = 0; n[1] = 0; n[2] = 1;
+        p[0] = c[0]; p[1] = c[1]; p[2] = c[2] - rho;
+        vl[0] = vl[1] = vl[2] = 0;
+        return;
+    }
+    const double *a = seg0 + 6 * l, *b = seg0 + 6 * l + 3;
+    const double *a1 = seg1 + 6 * l, *b1 = seg1 + 6 * l + 3;
+    double R = m->hand[(size_t)l * OR_HAND_STRIDE + 17];
+    double ab[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]};
+    double ca[3] = {c[0] - a[0], c[1] - a[1], c[2] - a[2]};
+    double L2 = dot3(ab, ab);
+    double s = 0.0;
+    if (sqrt(L2) >= 1e-9) {
+        s = dot3(ca, ab) / L2;
+        if (s < 0) s = 0;
+        if (s > 1) s = 1;
+    }
+    double ps[3] = {a[0] + s * ab[0], a[1] + s * ab[1], a[2] + s * ab[2]};
+    double del[3] = {c[0] - ps[0], c[1] - ps[1], c[2] - ps[2]};
+    double dist = norm3(del);
+    *d = dist - rho - R;
+    if (dist < 1e-7) {
+        double ex[3] = {1, 0, 0}, ey[3] = {0, 1, 0}, t[3];
+        cross3(ab, ex, t);
+        if (norm3(t) <= 1e-12) cross3(ab, ey, t);
+        if (norm3(t) <= 1e-12) { t[0] = 0; t[1] = 0; t[2] = 1; }
+        double nt = norm3(t);
+        n[0] = t[0] / nt; n[1] = t[1] / nt; n[2] = t[2] / nt;
+    } else {
+        n[0] = del[0] / dist; n[1] = del[1] / dist; n[2] = del[2] / dist;
+    }
+    p[0] = c[0] - rho * n[0]; p[1] = c[1] - rho * n[1]; p[2] = c[2] - rho * n[2];
+    double dt = m->dt;
+    for (int i = 0; i < 3; ++i) {
+        double va = (a1[i] - a[i]) / dt, vb = (b1[i] - b[i]) / dt;
+        vl[i] = (1 - s) * va + s * vb;
+    }
+}
+
+/* Tangent frame: e is the axis where |n_i| is smallest (lowest index on ties),
+ * t1 = normalize(n x e), t2 = n x t1. */
+static void tangent_frame(const double *n, double *t1, double *t2)
+{
+    int e = 0;
+    if (fabs(n[1]) < fabs(n[e])) e = 1;
+    if (fabs(n[2]) < fabs(n[e])) e = 2;
+    double ev[3] = {0, 0, 0};
+    ev[e] = 1;
+    cross3(n, ev, t1);
+    double nt = norm3(t1);
+    t1[0] /= nt; t1[1] /= nt; t1[2] /= nt;
+    cross3(n, t1, t2);
+}
+
+/* ------------------------------------------------------------------ */
+/* Fischer-Burmeister function for the second-order cone                */
+/* ------------------------------------------------------------------ */
+
+/* Jordan algebra on R x R^2: x o y = (x.y, x0 ybar + y0 xbar).
+ * For one contact with impulse r and velocity u (both in n,t1,t2):
+ *   x = kappa (mu r_n, r_t),  y = (u_n + mu sqrt(|u_t|^2 + delta^2), mu u_t),
+ *   w = sqrt(x o x + y o y + 2 delta^2 e),  Phi = x + y - w.
+ * If Jx / Jy are non-NULL they receive dPhi/dr and dPhi/du (3x3, row-major). */
+static void fb_contact(const or_model *m, double mu, const double *r, const double *u,
+                       double *Phi, double *Jx, double *Jy)
+{
+    double kap = m->kappa, del = m->fb_delta;
+    double x[3] = {kap * mu * r[0], kap * r[1], kap * r[2]};
+    double st = sqrt(u[1] * u[1] + u[2] * u[2] + del * del);
+    double y[3] = {u[0] + mu * st, mu * u[1], mu * u[2]};
+    /* z = x o x + y o y + 2 delta^2 e */
+    double z0 = dot3(x, x) + dot3(y, y) + 2 * del * del;
+    double zb[2] = {2 * (x[0] * x[1] + y[0] * y[1]), 2 * (x[0] * x[2] + y[0] * y[2])};
+    double nz = sqrt(zb[0] * zb[0] + zb[1] * zb[1]);
+    /* spectral values and square root */
+    double l1 = z0 - nz, l2 = z0 + nz;
+    double s1 = sqrt(l1), s2 = sqrt(l2);
+    double w[3];
+    w[0] = 0.5 * (s1 + s2);
+    if (nz > 0) {
+        double f = 0.5 * (s2 - s1) / nz;
+        w[1] = f * zb[0];
+        w[2] = f * zb[1];
+    } else {
+        w[1] = 0;
+        w[2] = 0;
+    }
+    for (int i = 0; i < 3; ++i) Phi[i] = x[i] + y[i] - w[i];
+    if (!Jx) return;
+
+    /* L_a = [[a0, abar^T], [abar, a0 I]] (arrow matrix of a). */
+    double Lx[9] = {x[0], x[1], x[2], x[1], x[0], 0, x[2], 0, x[0]};
+    double Ly[9] = {y[0], y[1], y[2], y[1], y[0], 0, y[2], 0, y[0]};
+    double Lw[9] = {w[0], w[1], w[2], w[1], w[0], 0, w[2], 0, w[0]};
+    /* inverse of L_w by the textbook 3x3 adjugate formula */
+    double inv[9];
+    {
+        const double *a = Lw;
+        double c00 = a[4] * a[8] - a[5] * a[7];
+        double c01 = a[5] * a[6] - a[3] * a[8];
+        double c02 = a[3] * a[7] - a[4] * a[6];
+        double det = a[0] * c00 + a[1] * c01 + a[2] * c02;
+        inv[0] = c00 / det;
+        inv[1] = (a[2] * a[7] - a[1] * a[8]) / det;
+        inv[2] = (a[1] * a[5] - a[2] * a[4]) / det;
+        inv[3] = c01 / det;
+        inv[4] = (a[0] * a[8] - a[2] * a[6]) / det;
+        inv[5] = (a[2] * a[3] - a[0] * a[5]) / det;
+        inv[6] = c02 / det;
+        inv[7] = (a[1] * a[6] - a[0] * a[7]) / det;
+        inv[8] = (a[0] * a[4] - a[1] * a[3]) / det;
+    }
+    double Dx[9], Dy[9];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            double sx = 0, sy = 0;
+            for (int k = 0; k < 3; ++k) {
+                sx += inv[3 * i + k] * Lx[3 * k + j];
+                sy += inv[3 * i + k] * Ly[3 * k + j];
+            }
+            Dx[3 * i + j] = (i == j ? 1.0 : 0.0) - sx;
+            Dy[3 * i + j] = (i == j ? 1.0 : 0.0) - sy;
+        }
+    /* dx/dr = kappa diag(mu, 1, 1);  dy/du = [[1, mu that^T], [0, mu I]] */
+    double Sx[9] = {kap * mu, 0, 0, 0, kap, 0, 0, 0, kap};
+    double Sy[9] = {1, mu * u[1] / st, mu * u[2] / st, 0, mu, 0, 0, 0, mu};
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            double a = 0, b = 0;
+            for (int k = 0; k < 3; ++k) {
+                a += Dx[3 * i + k] * Sx[3 * k + j];
+                b += Dy[3 * i + k] * Sy[3 * k + j];
+            }
+            Jx[3 * i + j] = a;
+            Jy[3 * i + j] = b;
+        }
+}
+
+/* Dense LU with partial pivoting: solves A z = rhs in place (A n x n,
+ * row-major, destroyed).  Returns 0 on success, -1 on an exactly zero pivot. */
+static int lu_solve(int n, double *A, double *rhs)
+{
+    for (int k = 0; k < n; ++k) {
+        int piv = k;
+        double best = fabs(A[(size_t)k * n + k]);
+        for (int i = k + 1; i < n; ++i) {
+            double v = fabs(A[(size_t)i * n + k]);
+            if (v > best) { best = v; piv = i; }
+        }
+        if (best == 0.0) return -1;
+        if (piv != k) {
+            for (int j = 0; j < n; ++j) {
+                double t = A[(size_t)k * n + j];
+                A[(size_t)k * n + j] = A[(size_t)piv * n + j];
+                A[(size_t)piv * n + j] = t;
+            }
+            double t = rhs[k]; rhs[k] = rhs[piv]; rhs[piv] = t;
+        }
+        for (int i = k + 1; i < n; ++i) {
+            double f = A[(size_t)i * n + k] / A[(size_t)k * n + k];
+            A[(size_t)i * n + k] = f;
+            for (int j = k + 1; j < n; ++j) A[(size_t)i * n + j] -= f * A[(size_t)k * n + j];
+            rhs[i] -= f * rhs[k];
+        }
+    }
+    for (int k = n - 1; k >= 0; --k) {
+        double s = rhs[k];
+        for (int j = k + 1; j < n; ++j) s -= A[(size_t)k * n + j] * rhs[j];
+        rhs[k] = s / A[(size_t)k * n + k];
+    }
+    return 0;
+}
+
+/* u = W r + u_free (n = 3C). */
+static void apply_W(int n, const double *W, const double *r, const double *uf, double *u)
+{
+    for (int i = 0; i < n; ++i) {
+        double s = uf[i];
+        for (int j = 0; j < n; ++j) s += W[(size_t)i * n + j] * r[j];
+        u[i] = s;
+    }
+}
+
+static double merit(const or_model *m, int C, double mu, const double *W, const double *uf, const double *r,
+                    double *ubuf)
+{
+    int n = 3 * C;
+    apply_W(n, W, r, uf, ubuf);
+    double psi = 0;
+    for (int c = 0; c < C; ++c) {
+        double Phi[3];
+        fb_contact(m, mu, r + 3 * c, ubuf + 3 * c, Phi, NULL, NULL);
+        psi += 0.5 * dot3(Phi, Phi);
+    }
+    return psi;
+}
+
+/* ------------------------------------------------------------------ */
+/* one environment step                                                */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+    double x[3], q[4], R[9], Iinv[9], vs[3], ws[3];
+    double mass, mu;
+    int ncand, C;
+    or_contact *cc; /* [C] */
+    double *J;      /* [3C][6] */
+    double *uf;     /* [3C]    */
+    double *W;      /* [3C][3C] */
+} sys_t;
+
+static void sys_free(sys_t *y)
+{
+    free(y->cc); free(y->J); free(y->uf); free(y->W);
+}
+
+/* Steps 1-8 of the model: pose, free velocity, candidates, the C_max cap,
+ * contact frames, Jacobian, compliant Delassus matrix W and free velocity. */
+static void build_system(const or_model *m, const double *seg0, const double *seg1, int type,
+                         const double *st, const double *pr, sys_t *y)
+{
+    const int L = m->L, Cmax = m->C_max;
+    const double dt = m->dt;
+    const double mass = pr[0], mu = pr[1];
+    const double *fp = pr + 2;
+    const double *inv = m->inv_inertia + 3 * type;
+    const int S = m->n_spheres[type];
+    const double *sph = m->spheres + (size_t)type * m->S_max * 4;
+    y->mass = mass;
+    y->mu = mu;
+
+    /* 1. pose, rotation, inverse mass matrix */
+    double *x = y->x, *q = y->q, *R = y->R;
+    x[0] = st[0]; x[1] = st[1]; x[2] = st[2];
+    q[0] = st[3]; q[1] = st[4]; q[2] = st[5]; q[3] = st[6];
+    qnormalize(q);
+    qmat(q, R);
+    double v[3] = {st[7], st[8], st[9]}, w[3] = {st[10], st[11], st[12]};
+    /* I_w^{-1} = R diag(inv/m) R^T */
+    double *Iinv = y->Iinv;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            double s = 0;
+            for (int k = 0; k < 3; ++k) s += R[3 * i + k] * (inv[k] / mass) * R[3 * j + k];
+            Iinv[3 * i + j] = s;
+        }
+
+    /* 2. free velocity */
+    double *vs = y->vs, *ws = y->ws;
+    for (int i = 0; i < 3; ++i) {
+        vs[i] = v[i] + dt * (m->gravity[i] + fp[i] / mass);
+        ws[i] = w[i];
+    }
+
+    /* 3-5. candidates */
+    int npair = S * (L + 1);
+    cand_t *cand = (cand_t *)malloc(sizeof(cand_t) * (size_t)(npair > 0 ? npair : 1));
+    int ncand = 0;
+    for (int k = 0; k < S; ++k) {
+        double c[3];
+        matvec(R, sph + 4 * k, c);
+        c[0] += x[0]; c[1] += x[1]; c[2] += x[2];
+        double rho = sph[4 * k + 3];
+        for (int l = 0; l <= L; ++l) {
+            double d, n[3], p[3], vl[3];
+            pair_geometry(m, seg0, seg1, l, c, rho, &d, n, p, vl);
+            if (d < m->margin) {
+                cand[ncand].d = d;
+                cand[ncand].key = k * (L + 1) + l;
+                ++ncand;
+            }
+        }
+    }
+    /* 6. cap: the C_max smallest (d, key) */
+    qsort(cand, (size_t)ncand, sizeof(cand_t), cand_cmp);
+    int C = ncand < Cmax ? ncand : Cmax;
+    y->ncand = ncand;
+    y->C = C;
+
+    /* 7-8. contact frames, Jacobian, W, u_free */
+    or_contact *cc = (or_contact *)calloc((size_t)(C > 0 ? C : 1), sizeof(or_contact));
+    int n3 = 3 * C;
+    double *J = (double *)calloc((size_t)(n3 > 0 ? n3 : 1) * 6, sizeof(double));
+    double *uf = (double *)calloc((size_t)(n3 > 0 ? n3 : 1), sizeof(double));
+    for (int c = 0; c < C; ++c) {
+        int key = cand[c].key;
+        int k = key / (L + 1), l = key % (L + 1);
+        double ctr[3];
+        matvec(R, sph + 4 * k, ctr);
+        ctr[0] += x[0]; ctr[1] += x[1]; ctr[2] += x[2];
+        or_contact *o = cc + c;
+        o->key = key;
+        o->link = l;
+        pair_geometry(m, seg0, seg1, l, ctr, sph[4 * k + 3], &o->d, o->n, o->p, o->vlink);
+        tangent_frame(o->n, o->t1, o->t2);
+        double rho[3] = {o->p[0] - x[0], o->p[1] - x[1], o->p[2] - x[2]};
+        const double *dirs[3] = {o->n, o->t1, o->t2};
+        /* velocity of the object's material point at p under (vs, ws) */
+        double wr_[3];
+        cross3(ws, rho, wr_);
+        double vp[3] = {vs[0] + wr_[0], vs[1] + wr_[1], vs[2] + wr_[2]};
+        for (int i = 0; i < 3; ++i) {
+            double *row = J + (size_t)(3 * c + i) * 6;
+            double rc[3];
+            cross3(rho, dirs[i], rc);
+            row[0] = dirs[i][0]; row[1] = dirs[i][1]; row[2] = dirs[i][2];
+            row[3] = rc[0]; row[4] = rc[1]; row[5] = rc[2];
+            uf[3 * c + i] = dot3(dirs[i], vp) - dot3(dirs[i], o->vlink);
+        }
+        /* speculative gap d/dt for d >= 0, Baumgarte erp*d/dt when penetrating */
+        double bn = o->d >= 0 ? o->d / dt : m->erp * o->d / dt;
+        uf[3 * c] += bn;
+    }
+    /* W = J M^{-1} J^T + eps I with M^{-1} = diag(I3/m, Iinv) */
+    double *W = (double *)calloc((size_t)(n3 > 0 ? n3 * n3 : 1), sizeof(double));
+    for (int i = 0; i < n3; ++i) {
+        const double *ri = J + (size_t)i * 6;
+        double mi[6];
+        mi[0] = ri[0] / mass; mi[1] = ri[1] / mass; mi[2] = ri[2] / mass;
+        matvec(Iinv, ri + 3, mi + 3);
+        for (int j = 0; j < n3; ++j) {
+            const double *rj = J + (size_t)j * 6;
+            double s = 0;
+            for (int t = 0; t < 6; ++t) s += mi[t] * rj[t];
+            W[(size_t)i * n3 + j] = s + (i == j ? m->compliance : 0.0);
+        }
+    }
+    free(cand);
+    y->cc = cc;
+    y->J = J;
+    y->uf = uf;
+    y->W = W;
+}
+
+int or_env_system(const or_model *m, const double *seg0, const double *seg1, int type,
+                  const double *st, const double *pr, or_contact *cont, double *W_out, double *uf_out)
+{
+    sys_t y;
+    build_system(m, seg0, seg1, type, st, pr, &y);
+    int n3 = 3 * y.C;
+    for (int c = 0; c < y.C; ++c) cont[c] = y.cc[c];
+    memcpy(W_out, y.W, sizeof(double) * (size_t)n3 * n3);
+    memcpy(uf_out, y.uf, sizeof(double) * (size_t)n3);
+    sys_free(&y);
+    return y.C;
+}
+
+int or_env_step(const or_model *m, const double *seg0, const double *seg1, int type,
+                double *st, double *pr, int32_t *wkey, double *wr,
+                or_contact *cont_out, or_diag *dg)
+{
+    const int Cmax = m->C_max;
+    const double dt = m->dt;
+    const double *inv = m->inv_inertia + 3 * type;
+    sys_t y;
+    build_system(m, seg0, seg1, type, st, pr, &y);
+    const double mass = y.mass, mu = y.mu;
+    const double *x = y.x, *q = y.q, *R = y.R, *Iinv = y.Iinv, *vs = y.vs, *ws = y.ws;
+    const int C = y.C, ncand = y.ncand;
+    or_contact *cc = y.cc;
+    const double *J = y.J, *uf = y.uf, *W = y.W;
+    int n3 = 3 * C;
+
+    /* 10. warm start and Newton */
+    double *r = (double *)calloc((size_t)(n3 > 0 ? n3 : 1), sizeof(double));
+    for (int c = 0; c < C; ++c)
+        for (int j = 0; j < Cmax; ++j)
+            if (wkey[j] == cc[c].key) {
+                r[3 * c] = wr[3 * j]; r[3 * c + 1] = wr[3 * j + 1]; r[3 * c + 2] = wr[3 * j + 2];
+                break;
+            }
+    double *u = (double *)calloc((size_t)(n3 > 0 ? n3 : 1), sizeof(double));
+    double *A = (double *)calloc((size_t)(n3 > 0 ? n3 * n3 : 1), sizeof(double));
+    double *Phi = (double *)calloc((size_t)(n3 > 0 ? n3 : 1), sizeof(double));
+    double *dr = (double *)calloc((size_t)(n3 > 0 ? n3 : 1), sizeof(double));
+    double *rt = (double *)calloc((size_t)(n3 > 0 ? n3 : 1), sizeof(double));
+    int iters = 0, nfull = 0;
+    double psi_first = 0, psi = 0;
+    if (C > 0) {
+        int maxit = m->converged ? m->conv_max_iters : m->newton_iters;
+        for (int it = 0; it < maxit; ++it) {
+            apply_W(n3, W, r, uf, u);
+            psi = 0;
+            memset(A, 0, sizeof(double) * (size_t)n3 * n3);
+            for (int c = 0; c < C; ++c) {
+                double Jx[9], Jy[9];
+                fb_contact(m, mu, r + 3 * c, u + 3 * c, Phi + 3 * c, Jx, Jy);
+                psi += 0.5 * dot3(Phi + 3 * c, Phi + 3 * c);
+                /* rows of block c: A = Jx (block diagonal) + Jy W */
+                for (int i = 0; i < 3; ++i) {
+                    double *Arow = A + (size_t)(3 * c + i) * n3;
+                    for (int j = 0; j < 3; ++j) Arow[3 * c + j] += Jx[3 * i + j];
+                    for (int col = 0; col < n3; ++col) {
+                        double s = 0;
+                        for (int k = 0; k < 3; ++k) s += Jy[3 * i + k] * W[(size_t)(3 * c + k) * n3 + col];
+                        Arow[col] += s;
+                    }
+                }
+            }
+            if (it == 0) psi_first = psi;
+            if (m->converged && psi < m->conv_tol) break;
+            for (int i = 0; i < n3; ++i) dr[i] = -Phi[i];
+            if (lu_solve(n3, A, dr) != 0) break;
+            /* Armijo backtracking on Psi = 1/2 |Phi|^2 */
+            double alpha = 0.125;
+            double a = 1.0;
+            for (int t = 0; t < 4; ++t, a *= 0.5) {
+                for (int i = 0; i < n3; ++i) rt[i] = r[i] + a * dr[i];
+                double pt = merit(m, C, mu, W, uf, rt, u);
+                if (pt <= (1.0 - 2.0 * m->armijo_sigma * a) * psi) { alpha = a; break; }
+            }
+            if (alpha == 1.0) ++nfull;
+            for (int i = 0; i < n3; ++i) r[i] += alpha * dr[i];
+            ++iters;
+        }
+        psi = merit(m, C, mu, W, uf, r, u);
+    }
+
+    /* 11. integrate */
+    double dv[3] = {0, 0, 0}, dL[3] = {0, 0, 0};
+    for (int c = 0; c < C; ++c)
+        for (int i = 0; i < 3; ++i) {
+            const double *row = J + (size_t)(3 * c + i) * 6;
+            for (int t = 0; t < 3; ++t) { dv[t] += row[t] * r[3 * c + i]; dL[t] += row[3 + t] * r[3 * c + i]; }
+        }
+    double dw[3];
+    matvec(Iinv, dL, dw);
+    double vp[3], wp[3];
+    for (int i = 0; i < 3; ++i) {
+        vp[i] = vs[i] + dv[i] / mass;
+        wp[i] = ws[i] + dw[i];
+    }
+    double xn[3] = {x[0] + dt * vp[0], x[1] + dt * vp[1], x[2] + dt * vp[2]};
+    double th[3] = {dt * wp[0], dt * wp[1], dt * wp[2]};
+    double eq[4], qn[4];
+    qexp(th, eq);
+    qmul(eq, q, qn);
+    qnormalize(qn);
+    /* omega remap that conserves world angular momentum:
+     * h = I_w(q) w+, w_next = I_w(q_next)^{-1} h; locked axes (inv = 0) carry
+     * no momentum. */
+    double wb[3], hb[3], h[3];
+    mattvec(R, wp, wb);
+    for (int i = 0; i < 3; ++i) hb[i] = inv[i] > 0 ? wb[i] * mass / inv[i] : 0.0;
+    matvec(R, hb, h);
+    double Rn[9], hn[3], wn[3];
+    qmat(qn, Rn);
+    mattvec(Rn, h, hn);
+    for (int i = 0; i < 3; ++i) hn[i] *= inv[i] / mass;
+    matvec(Rn, hn, wn);
+
+    st[0] = xn[0]; st[1] = xn[1]; st[2] = xn[2];
+    st[3] = qn[0]; st[4] = qn[1]; st[5] = qn[2]; st[6] = qn[3];
+    st[7] = vp[0]; st[8] = vp[1]; st[9] = vp[2];
+    st[10] = wn[0]; st[11] = wn[1]; st[12] = wn[2];
+    pr[2] = pr[3] = pr[4] = 0.0;
+
+    /* warm cache for the next step */
+    for (int j = 0; j < Cmax; ++j) {
+        wkey[j] = -1;
+        wr[3 * j] = wr[3 * j + 1] = wr[3 * j + 2] = 0;
+    }
+    for (int c = 0; c < C; ++c) {
+        wkey[c] = cc[c].key;
+        wr[3 * c] = r[3 * c]; wr[3 * c + 1] = r[3 * c + 1]; wr[3 * c + 2] = r[3 * c + 2];
+    }
+    if (cont_out) {
+        if (C > 0) apply_W(n3, W, r, uf, u);
+        for (int c = 0; c < C; ++c) {
+            for (int i = 0; i < 3; ++i) { cc[c].r[i] = r[3 * c + i]; cc[c].u[i] = u[3 * c + i]; }
+            cont_out[c] = cc[c];
+        }
+    }
+    if (dg) {
+        dg->n_candidates = ncand;
+        dg->n_contacts = C;
+        dg->iters = iters;
+        dg->n_full_steps = nfull;
+        dg->psi_first = psi_first;
+        dg->psi_final = psi;
+    }
+    free(r); free(u); free(A); free(Phi); free(dr); free(rt);
+    sys_free(&y);
+    return C;
+}
+
+/* ------------------------------------------------------------------ */
+/* observation and cost                                                */
+/* ------------------------------------------------------------------ */
+
+/* Force on each sensor link exerted by the object over the step:
+ * c_l = -(1/dt) sum_{contacts on l} (r_n n + r_t1 t1 + r_t2 t2);
+ * obs = (|c_l|, c_l/|c_l|), with the direction zeroed at or below tau_c.
+ * Table contacts are not sensed. */
+void or_observe(const or_model *m, int nc, const or_contact *cont, double *obs)
+{
+    int L = m->L;
+    double *f = (double *)calloc((size_t)L * 3, sizeof(double));
+    for (int c = 0; c < nc; ++c) {
+        int l = cont[c].link;
+        if (l >= L) continue;
+        for (int i = 0; i < 3; ++i)
+            f[3 * l + i] -= (cont[c].r[0] * cont[c].n[i] + cont[c].r[1] * cont[c].t1[i] + cont[c].r[2] * cont[c].t2[i]) / m->dt;
+    }
+    for (int l = 0; l < L; ++l) {
+        double mag = norm3(f + 3 * l);
+        obs[4 * l] = mag;
+        for (int i = 0; i < 3; ++i) obs[4 * l + 1 + i] = mag > m->tau_contact ? f[3 * l + i] / mag : 0.0;
+    }
+    free(f);
+}
+
+/* Step cost: sum over sensors of w_mag (|c|-|c_gt|)^2 + w_dir |c_hat - c_hat_gt|^2. */
+double or_step_cost(const or_model *m, const double *obs, const double *obs_gt)
+{
+    double s = 0;
+    for (int l = 0; l < m->L; ++l) {
+        const double *a = obs + 4 * l, *b = obs_gt + 4 * l;
+        double dm = a[0] - b[0];
+        double dd[3] = {a[1] - b[1], a[2] - b[2], a[3] - b[3]};
+        s += m->w_mag * dm * dm + m->w_dir * dot3(dd, dd);
+    }
+    return s;
+}
+
+void or_batch_step(const or_model *m, int K, const int32_t *env_type,
+                   const double *u_prev, const double *u,
+                   double *state, double *params, int32_t *wkey, double *wr,
+                   or_contact *cont, or_diag *diag, double *obs)
+{
+    int L = m->L, Cmax = m->C_max;
+    double *seg0 = (double *)malloc(sizeof(double) * 6 * (size_t)L);
+    double *seg1 = (double *)malloc(sizeof(double) * 6 * (size_t)L);
+    or_hand_fk(m, u_prev, seg0);
+    or_hand_fk(m, u, seg1);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int i = 0; i < K; ++i) {
+        or_contact local[OR_MAX_CMAX];
+        or_contact *cp = cont ? cont + (size_t)i * Cmax : local;
+        int nc = or_env_step(m, seg0, seg1, env_type[i], state + 13 * (size_t)i, params + 5 * (size_t)i,
+                             wkey + (size_t)i * Cmax, wr + (size_t)i * Cmax * 3, cp, diag ? diag + i : NULL);
+        if (cont)
+            for (int c = nc; c < Cmax; ++c) { memset(cp + c, 0, sizeof(or_contact)); cp[c].key = -1; }
+        if (obs) or_observe(m, nc, cp, obs + (size_t)i * L * 4);
+    }
+    free(seg0);
+    free(seg1);
+}
+
+void or_batch_cost(const or_model *m, int K, int G, const int32_t *group_start,
+                   const double *obs, const double *obs_gt, double *cost_sum)
+{
+    int L = m->L;
+    for (int g = 0; g < G; ++g)
+        for (int i = group_start[g]; i < group_start[g + 1] && i < K; ++i)
+            cost_sum[i] += or_step_cost(m, obs + (size_t)i * L * 4, obs_gt + (size_t)g * L * 4);
+}
+
+int or_argmin(int n, const double *v)
+{
+    int best = 0;
+    double bv = INFINITY;
+    for (int i = 0; i < n; ++i) {
+        double x = isnan(v[i]) ? INFINITY : v[i];
+        if (x < bv) { bv = x; best = i; }
+    }
+    return best;
+}
+
+/* ------------------------------------------------------------------ */
+/* Philox4x32-10 and the population-based resampler                    */
+/* ------------------------------------------------------------------ */
+
+/* Philox4x32 with 10 rounds: each round multiplies words 0 and 2 by the two
+ * published multipliers, mixes the high halves with the other words and the
+ * round key, and the key is bumped by the two Weyl constants between rounds. */
+void or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+    const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        uint64_t p0 = (uint64_t)M0 * c0;
+        uint64_t p1 = (uint64_t)M1 * c2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n1 = lo1;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
+        uint32_t n3 = lo0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+        k0 += W0;
+        k1 += W1;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+static double u01(uint32_t x) { return ((double)x + 0.5) * (1.0 / 4294967296.0); }
+
+/* Two standard normals from two Philox words (Box-Muller). */
+static void box_muller(uint32_t a, uint32_t b, double *n0, double *n1)
+{
+    double u = u01(a), v = u01(b);
+    double rad = sqrt(-2.0 * log(u));
+    double ang = 2.0 * M_PI * v;
+    *n0 = rad * cos(ang);
+    *n1 = rad * sin(ang);
+}
+
+typedef struct {
+    double c;
+    int32_t i;
+} rank_t;
+
+static int rank_cmp(const void *pa, const void *pb)
+{
+    const rank_t *a = (const rank_t *)pa, *b = (const rank_t *)pb;
+    if (a->c < b->c) return -1;
+    if (a->c > b->c) return 1;
+    return (a->i > b->i) - (a->i < b->i);
+}
+
+void or_resample_pbo(const or_model *m, const or_resample_cfg *rc, int K, int G,
+                     const int32_t *group_start, uint32_t window_idx,
+                     double *cost_sum, double *state, double *params,
+                     int32_t *wkey, double *wr, int32_t *parent)
+{
+    int Cmax = m->C_max;
+    (void)K;
+    uint32_t key[2] = {(uint32_t)(rc->seed & 0xffffffffu), (uint32_t)(rc->seed >> 32)};
+    for (int g = 0; g < G; ++g) {
+        int lo = group_start[g], hi = group_start[g + 1];
+        int n = hi - lo;
+        if (n <= 0) continue;
+        /* rank by (cost, index) ascending; NaN ranks as +inf */
+        rank_t *rk = (rank_t *)malloc(sizeof(rank_t) * (size_t)n);
+        for (int j = 0; j < n; ++j) {
+            double c = cost_sum[lo + j];
+            rk[j].c = isnan(c) ? INFINITY : c;
+            rk[j].i = lo + j;
+        }
+        qsort(rk, (size_t)n, sizeof(rank_t), rank_cmp);
+        int kb = (int)floor((double)n * rc->elite_frac);
+        if (kb < 1) kb = 1;
+        if (kb > n) kb = n;
+        for (int t = 0; t < kb; ++t) parent[rk[t].i] = -1;
+        for (int t = kb; t < n; ++t) {
+            int j = rk[t].i;
+            uint32_t ctr[4] = {(uint32_t)j, window_idx, 0u, 0u}, w[4];
+            or_philox4x32_10(ctr, key, w);
+            int pr_rank = (int)(((uint64_t)w[0] * (uint64_t)kb) >> 32);
+            int p = rk[pr_rank].i;
+            parent[j] = p;
+            memcpy(state + 13 * (size_t)j, state + 13 * (size_t)p, 13 * sizeof(double));
+            memcpy(params + 5 * (size_t)j, params + 5 * (size_t)p, 5 * sizeof(double));
+            memcpy(wkey + (size_t)j * Cmax, wkey + (size_t)p * Cmax, (size_t)Cmax * sizeof(int32_t));
+            memcpy(wr + (size_t)j * Cmax * 3, wr + (size_t)p * Cmax * 3, (size_t)Cmax * 3 * sizeof(double));
+            /* exploration: parameter noise (Sec. III-D, N(theta, Sigma_theta))
+             * and a random force on the object (N(0, Sigma_v)) */
+            double nrm[6];
+            uint32_t c1[4] = {(uint32_t)j, window_idx, 1u, 0u}, c2[4] = {(uint32_t)j, window_idx, 2u, 0u}, w1[4], w2[4];
+            or_philox4x32_10(c1, key, w1);
+            or_philox4x32_10(c2, key, w2);
+            box_muller(w1[0], w1[1], &nrm[0], &nrm[1]);
+            box_muller(w1[2], w1[3], &nrm[2], &nrm[3]);
+            box_muller(w2[0], w2[1], &nrm[4], &nrm[5]);
+            double *pp = params + 5 * (size_t)j;
+            double mu = pp[1] + rc->sigma_mu * nrm[0];
+            double ms = pp[0] + rc->sigma_m * nrm[1];
+            pp[1] = mu < rc->mu_lo ? rc->mu_lo : (mu > rc->mu_hi ? rc->mu_hi : mu);
+            pp[0] = ms < rc->m_lo ? rc->m_lo : (ms > rc->m_hi ? rc->m_hi : ms);
+            pp[2] = rc->sigma_f * nrm[2];
+            pp[3] = rc->sigma_f * nrm[3];
+            pp[4] = rc->sigma_f * nrm[4];
+        }
+        free(rk);
+        for (int j = lo; j < hi; ++j) cost_sum[j] = 0.0;
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* ADD metric                                                          */
+/* ------------------------------------------------------------------ */
+
+double or_add(const or_model *m, int type, const double *pa, const double *pb)
+{
+    int S = m->n_spheres[type];
+    const double *sph = m->spheres + (size_t)type * m->S_max * 4;
+    double qa[4] = {pa[3], pa[4], pa[5], pa[6]}, qb[4] = {pb[3], pb[4], pb[5], pb[6]};
+    qnormalize(qa);
+    qnormalize(qb);
+    double Ra[9], Rb[9];
+    qmat(qa, Ra);
+    qmat(qb, Rb);
+    double s = 0;
+    for (int k = 0; k < S; ++k) {
+        double a[3], b[3];
+        matvec(Ra, sph + 4 * k, a);
+        matvec(Rb, sph + 4 * k, b);
+        double d[3] = {(a[0] - b[0]) + (pa[0] - pb[0]), (a[1] - b[1]) + (pa[1] - pb[1]), (a[2] - b[2]) + (pa[2] - pb[2])};
+        s += norm3(d);
+    }
+    return S > 0 ? s / S : 0.0;
+}
+
+/* ------------------------------------------------------------------ */
+/* window cost of one environment (for finite-difference gradients)     */
+/* ------------------------------------------------------------------ */
+
+double or_window_cost(const or_model *m, int type, const double *st0, const double *pr0,
+                      const int32_t *wkey0, const double *wr0, int T,
+                      const double *u_seq, const double *obs_gt)
+{
+    int L = m->L, D = m->D, Cmax = m->C_max;
+    double st[13], pr[5];
+    memcpy(st, st0, sizeof st);
+    memcpy(pr, pr0, sizeof pr);
+    int32_t wkey[OR_MAX_CMAX];
+    double wr[OR_MAX_CMAX * 3];
+    for (int j = 0; j < Cmax; ++j) {
+        wkey[j] = wkey0 ? wkey0[j] : -1;
+        for (int i = 0; i < 3; ++i) wr[3 * j + i] = wr0 ? wr0[3 * j + i] : 0.0;
+    }
+    double *seg0 = (double *)malloc(sizeof(double) * 6 * (size_t)L);
+    double *seg1 = (double *)malloc(sizeof(double) * 6 * (size_t)L);
+    double *obs = (double *)malloc(sizeof(double) * 4 * (size_t)L);
+    or_contact cont[OR_MAX_CMAX];
+    double total = 0;
+    for (int t = 0; t < T; ++t) {
+        or_hand_fk(m, u_seq + (size_t)t * D, seg0);
+        or_hand_fk(m, u_seq + (size_t)(t + 1) * D, seg1);
+        int nc = or_env_step(m, seg0, seg1, type, st, pr, wkey, wr, cont, NULL);
+        or_observe(m, nc, cont, obs);
+        total += or_step_cost(m, obs, obs_gt + (size_t)t * L * 4);
+    }
+    free(seg0); free(seg1); free(obs);
+    return total;
+}

@@ -1,0 +1,148 @@
+/*
+ * oracle.h -- plain FP64 CPU oracle for sample-based in-hand pose tracking
+ * (Liang et al., "In-Hand Object Pose Tracking via Contact Feedback and
+ * GPU-Accelerated Robotic Simulation", arXiv 2002.12160).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load this library.  The product path
+ * (libpt + its Python binding) never links, imports or calls it, and the two
+ * share no source: no headers, helpers, tables or constants.
+ *
+ * What it computes (Sec. III-A..III-D, Alg. 1 of the paper): one step of the
+ * world model s_{t+1} = f(s_t, u_t, theta) for each of K perturbed simulations
+ * (a rigid object made of spheres, a kinematic capsule hand driven by the same
+ * joint command u_t in every simulation, a table plane, Coulomb friction), the
+ * per-sensor contact-force observation, the step cost against the observed
+ * one, the running window cost and its argmin (Eq. 1-2), the population-based
+ * resampler (Sec. III-D.3) and the ADD error metric (Sec. IV).
+ *
+ * The paper does not specify its simulator's internals; the discrete model
+ * below is the reading fixed for this project (sphere-set object, capsule
+ * links, speculative contacts with Baumgarte depenetration, a compliant
+ * Delassus operator, Coulomb friction written as a second-order-cone
+ * complementarity problem solved by a smoothed Fischer-Burmeister Newton
+ * method with Armijo backtracking).  The oracle forms the full 3C x 3C Newton
+ * matrix and solves it by dense LU with partial pivoting.
+ *
+ * Parity pins: closed forms (free fall, momentum, resting force, sliding
+ * onset), the NCP certificate on converged solves, single-contact brute-force
+ * mode enumeration, narrow-phase brute force, Philox known-answer vectors,
+ * cost / argmin / ADD identities (see tests/test_oracle_*.py).
+ *
+ * Layouts are env-major (AoS), all doubles:
+ *   state  [K][13]  x(3) q(4: w,x,y,z) v(3) w(3), world frame
+ *   params [K][5]   m, mu, f_pert(3)
+ *   warm   key [K][C_max] int32 (-1 = empty), r [K][C_max][3]
+ *   obs    [K][L][4] |c|, c_hat(3)
+ */
+#ifndef PT_ORACLE_H
+#define PT_ORACLE_H
+
+#include <stdint.h>
+
+#define OR_HAND_STRIDE 20
+#define OR_MAX_CMAX 64
+
+typedef struct {
+    int32_t L, D, n_types, S_max, C_max;
+    int32_t newton_iters;   /* fixed-N mode: exactly this many iterations      */
+    int32_t converged;      /* 1: iterate until Psi < conv_tol or conv_max     */
+    int32_t conv_max_iters;
+    double conv_tol;
+    double dt;
+    double gravity[3];
+    double margin, erp, compliance, kappa, fb_delta, armijo_sigma;
+    double tau_contact, w_mag, w_dir;
+    const double *hand;        /* [L][20] link table                            */
+    const double *spheres;     /* [n_types][S_max][4] body-frame centre, radius */
+    const int32_t *n_spheres;  /* [n_types]                                     */
+    const double *inv_inertia; /* [n_types][3] principal inverse inertia per unit mass (0 = locked axis) */
+} or_model;
+
+typedef struct {
+    int32_t key, link;         /* key = k*(L+1)+l ; link == L is the table      */
+    double d;                  /* signed gap                                    */
+    double n[3], t1[3], t2[3]; /* contact frame, n points from link to object   */
+    double p[3];               /* contact point on the object                   */
+    double vlink[3];           /* velocity of the link surface point            */
+    double r[3];               /* impulse on the object in (n,t1,t2)            */
+    double u[3];               /* relative velocity W r + u_free in (n,t1,t2)   */
+} or_contact;
+
+typedef struct {
+    int32_t n_candidates;      /* pairs with d < margin                         */
+    int32_t n_contacts;        /* after the C_max cap                           */
+    int32_t iters;             /* Newton iterations run                         */
+    int32_t n_full_steps;      /* iterations that accepted alpha = 1            */
+    double psi_first;          /* merit at the first iterate                    */
+    double psi_final;          /* merit at the returned impulses                */
+} or_diag;
+
+/* Forward kinematics of the kinematic hand at joint vector u[D]:
+ * seg[L][6] = segment endpoints a(3), b(3) in the world frame. */
+void or_hand_fk(const or_model *m, const double *u, double *seg);
+
+/* One step of one environment.  seg0 = FK(u_{t-1}), seg1 = FK(u_t).
+ * st[13], pr[5], wkey[C_max], wr[C_max*3] are updated in place.
+ * cont[C_max] (may be NULL) receives the solved contacts; dg may be NULL.
+ * Returns the number of contacts. */
+int or_env_step(const or_model *m, const double *seg0, const double *seg1, int type,
+                double *st, double *pr, int32_t *wkey, double *wr,
+                or_contact *cont, or_diag *dg);
+
+/* The contact system of one environment at its current state, without
+ * stepping: the capped contacts cont[C], the compliant Delassus matrix
+ * W[3C][3C] and the free relative velocity uf[3C] (callers size the buffers
+ * for C_max).  Returns C. */
+int or_env_system(const or_model *m, const double *seg0, const double *seg1, int type,
+                  const double *st, const double *pr, or_contact *cont, double *W, double *uf);
+
+/* Per-sensor observation from a step's contacts: obs[L][4]. */
+void or_observe(const or_model *m, int nc, const or_contact *cont, double *obs);
+
+/* Step cost of one simulation's observation against the observed one. */
+double or_step_cost(const or_model *m, const double *obs, const double *obs_gt);
+
+/* Batched step over K environments (OpenMP over environments).
+ * u_prev/u: [D].  cont [K][C_max], diag [K], obs [K][L][4] may be NULL. */
+void or_batch_step(const or_model *m, int K, const int32_t *env_type,
+                   const double *u_prev, const double *u,
+                   double *state, double *params, int32_t *wkey, double *wr,
+                   or_contact *cont, or_diag *diag, double *obs);
+
+/* cost_sum[i] += step cost of obs[i] against obs_gt[group(i)] for K envs in
+ * G contiguous groups (group_start[G+1]). */
+void or_batch_cost(const or_model *m, int K, int G, const int32_t *group_start,
+                   const double *obs, const double *obs_gt, double *cost_sum);
+
+/* Lowest index of the minimum over n values (NaN counts as +inf). */
+int or_argmin(int n, const double *v);
+
+/* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11). */
+void or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+
+typedef struct {
+    double elite_frac, sigma_mu, sigma_m, sigma_f, mu_lo, mu_hi, m_lo, m_hi;
+    uint64_t seed;
+} or_resample_cfg;
+
+/* Population-based resampling (Sec. III-D.3) of K envs in G contiguous groups.
+ * parent[K] receives -1 for kept elites, else the source env index.
+ * cost_sum is zeroed on exit. */
+void or_resample_pbo(const or_model *m, const or_resample_cfg *rc, int K, int G,
+                     const int32_t *group_start, uint32_t window_idx,
+                     double *cost_sum, double *state, double *params,
+                     int32_t *wkey, double *wr, int32_t *parent);
+
+/* ADD (Sec. IV): mean distance of the object's sphere centres between pose a
+ * and pose b (each x(3), q(4)). */
+double or_add(const or_model *m, int type, const double *pose_a, const double *pose_b);
+
+/* Window cost of a single environment over T steps: sum of step costs
+ * against obs_gt[T][L][4]; u_seq[T+1][D] with u_seq[0] the command before
+ * the window.  Inputs are not modified. */
+double or_window_cost(const or_model *m, int type, const double *st0, const double *pr0,
+                      const int32_t *wkey0, const double *wr0, int T,
+                      const double *u_seq, const double *obs_gt);
+
+#endif
