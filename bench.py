@@ -1,0 +1,220 @@
+"""Benchmark of the data-parallel hot path of sample-based in-hand pose
+tracking on one MI355X.
+
+A "step" is one world step of the whole population with the observation and
+the cost (Alg. 1: step every simulation with the same command, observe, add
+the step cost against the observed contact forces, update the argmin), plus
+the population-based resampling every T steps; the observed forces come from
+a separate batch holding the unperturbed ("real") simulation, stepped with
+the same commands.  Inputs are seeded and synthetic (the paper's YCB objects
+and teleoperation trajectories are not available): a 4-finger + palm capsule
+hand on sinusoidal joint commands and a 64-sphere ellipsoid on a table.
+
+Default workload: 256 simulations, 300 steps at 30 Hz, plain per-step
+launches (the "plain256" scene).  The same run also times the batched path
+(one persistent kernel per 10-step window, replayed from a HIP graph) on the
+same workload.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=300, help="timed world steps")
+    ap.add_argument("--warmup", type=int, default=30, help="untimed world steps first")
+    ap.add_argument("--config", default="plain256")
+    ap.add_argument("--solve-precision", type=int, default=64, choices=[32, 64])
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-steps", type=int, default=300)
+    ap.add_argument("--profile", action="store_true", help="short run for the profiler (no CPU baseline)")
+    return ap.parse_args()
+
+
+# algorithmic floating-point operations (an FMA counts 2), counted from the
+# arithmetic the step performs; see the design doc for the derivation
+FLOP_SPHERE = 21            # c_k = x + R s_k
+FLOP_PAIR = 30              # sphere-capsule signed gap (plane: 1)
+FLOP_ENV = 420              # pose, inertia, free velocity, integration, observation
+FLOP_CONTACT_SETUP = 130    # frame, Jacobian, free relative velocity
+FLOP_CONTACT_ITER = 830     # per Newton iteration: FB value+Jacobian, 3x3 solves, 6x6 contribution, dr, W dr, one merit
+FLOP_ENV_ITER = 370         # per Newton iteration: 6x6 assembly and LU, velocity updates
+
+
+def algorithmic_flops(S, L, N, env_steps, contacts, plane_pairs=True):
+    per_env = FLOP_ENV + S * FLOP_SPHERE + S * L * FLOP_PAIR + (S if plane_pairs else 0) + N * FLOP_ENV_ITER
+    return env_steps * per_env + contacts * (FLOP_CONTACT_SETUP + N * FLOP_CONTACT_ITER)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (the population would shard "
+                                   "across GPUs by simulation, see DESIGN.md)"}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2002_12160_amd import pt
+    from paper_2002_12160_amd import scene as S
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    cfg = S.CONFIGS[args.config]
+    total_steps = args.warmup + args.steps
+    T = cfg.T
+    sc = S.make_scene(cfg, steps=max(total_steps, cfg.steps) + 1)
+    K, G, L = sc.K, sc.G, sc.L
+    u_all = torch.as_tensor(sc.u.astype(np.float32), device=dev)
+
+    def make():
+        return (pt.Batch.from_scene(sc, solve_precision=args.solve_precision),
+                pt.Batch.from_scene(sc, hidden=True, solve_precision=args.solve_precision))
+
+    # ---------------- plain per-step path ----------------------------------
+    main_b, hid_b = make()
+    cost = torch.zeros(K, device=dev)
+    best = torch.zeros(G, dtype=torch.int32, device=dev)
+    parent = torch.zeros(K, dtype=torch.int32, device=dev)
+    obs = main_b.new_obs()
+    gt = hid_b.new_obs()
+    stream = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    window = 0
+
+    def plain_step(t, timed_idx=None):
+        nonlocal window
+        up, u = u_all[max(t - 1, 0)], u_all[t]
+        hid_b.step(up, u)
+        hid_b.observe(gt)
+        if timed_idx is not None:
+            ev[timed_idx][0].record(stream)
+        main_b.step(up, u)
+        if timed_idx is not None:
+            ev[timed_idx][1].record(stream)
+        main_b.observe(obs)
+        main_b.cost(obs, gt, cost, best)
+        if (t + 1) % T == 0:
+            main_b.resample(cost, window, parent)
+            window += 1
+
+    for t in range(args.warmup):
+        plain_step(t)
+    torch.cuda.synchronize()
+    stats0 = main_b.read_stats()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        plain_step(args.warmup + i, i)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    stats1 = main_b.read_stats()
+    step_ms = [a.elapsed_time(b) for a, b in ev]
+    env_steps = K * args.steps
+    plain_value = env_steps / wall
+    d_env = stats1["env_steps"] - stats0["env_steps"]
+    d_con = stats1["contacts"] - stats0["contacts"]
+    d_cand = stats1["candidates"] - stats0["candidates"]
+    S_sph = int(sc.n_spheres[0])
+    flops = algorithmic_flops(S_sph, L, cfg.newton_iters, d_env, d_con)
+    step_kernel_s = sum(step_ms) / 1e3
+    achieved_tflops = flops / step_kernel_s / 1e12
+    main_b.close()
+    hid_b.close()
+
+    result = {
+        "metric": "env-steps/sec (step+observe+cost)",
+        "value": round(plain_value, 1),
+        "unit": "env-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.solve_precision == 32 else "f32+f64solve",
+        "data": "synthetic",
+        "config": {"workload": f"{cfg.name}: {K} simulations + {G} observed, {args.steps} timed steps at "
+                               f"{1 / cfg.consts.dt:.0f} Hz, {L} capsule links, {S_sph}-sphere object, "
+                               f"C_max={cfg.C_max}, {cfg.newton_iters} Newton iterations, PBO every {T} steps",
+                   "path": "plain per-step launches", "solve_precision": args.solve_precision},
+        "per_step_ms": {"p50": round(float(np.median(step_ms)), 4), "p99": round(float(np.quantile(step_ms, 0.99)), 4)},
+        "budget_30hz_met": bool(wall / args.steps < 1.0 / 30.0),
+        "contacts_per_env_step": round(d_con / max(d_env, 1), 2),
+        "candidates_per_env_step": round(d_cand / max(d_env, 1), 2),
+        "roofline": {"bound": "alu", "kernel": "k_step (with its hand-kinematics launch)",
+                     "achieved": round(achieved_tflops, 4), "peak": 78.6 if args.solve_precision == 64 else 157.3,
+                     "unit": "TFLOP/s", "frac": None, "traffic": None,
+                     "flop_per_env_step": round(flops / max(d_env, 1), 1),
+                     "avg_launch_us": round(step_kernel_s / args.steps * 1e6, 2)},
+    }
+    result["roofline"]["frac"] = round(result["roofline"]["achieved"] / result["roofline"]["peak"], 6)
+
+    # ---------------- batched path (persistent kernel + graph) -------------
+    if not args.no_batched:
+        main_b, hid_b = make()
+        n_win = max(1, args.steps // T)
+        n_warm = max(1, args.warmup // T)
+        u_win = torch.empty((T + 1, sc.D), device=dev)
+        gtw = torch.zeros((T, 4, L, G), device=dev)
+        costb = torch.zeros(K, device=dev)
+        bestb = torch.zeros(G, dtype=torch.int32, device=dev)
+        parentb = torch.zeros(K, dtype=torch.int32, device=dev)
+        costh = torch.zeros(G, device=dev)
+        gt_dummy = torch.zeros((T, 4, L, G), device=dev)
+
+        def window_run(w):
+            t0_ = w * T
+            u_win.copy_(u_all[max(t0_ - 1, 0): t0_ + T] if t0_ > 0 else
+                        torch.cat([u_all[:1], u_all[:T]], 0))
+            hid_b.run_window(u_win, gt_dummy, costh, None, gtw, graph=True)
+            main_b.run_window(u_win, gtw, costb, bestb, None, graph=True)
+            main_b.resample(costb, w, parentb)
+
+        # the observed batch writes its observations straight into gtw
+        tuned = main_b.autotune(u_win.copy_(torch.cat([u_all[:1], u_all[:T]], 0)), gtw)
+        for w in range(n_warm):
+            window_run(w)
+        torch.cuda.synchronize()
+        tb0 = time.perf_counter()
+        for w in range(n_warm, n_warm + n_win):
+            window_run(w)
+        torch.cuda.synchronize()
+        bwall = time.perf_counter() - tb0
+        result["batched"] = {"value": round(K * T * n_win / bwall, 1), "unit": "env-steps/s",
+                             "windows": n_win, "ms_per_step": round(bwall / (n_win * T) * 1e3, 4),
+                             "waves_per_workgroup": tuned, "speedup_vs_plain": round(K * T * n_win / bwall / plain_value, 3)}
+        main_b.close()
+        hid_b.close()
+
+    # ---------------- CPU baseline: the FP64 oracle ----------------------
+    if not args.no_cpu_baseline and not args.profile:
+        import oracle
+        nthreads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        osc = S.make_scene(cfg, steps=args.cpu_sample_steps + 1)
+        tr = oracle.Tracker(osc)
+        c0 = time.perf_counter()
+        for _ in range(args.cpu_sample_steps):
+            tr.step()
+        csec = time.perf_counter() - c0
+        result["cpu_baseline"] = {"value": round(osc.K * args.cpu_sample_steps / csec, 2), "unit": "env-steps/s",
+                                  "cores": nthreads, "kind": "oracle",
+                                  "sample": f"first {args.cpu_sample_steps} steps of the same workload, all {osc.K} "
+                                            f"simulations + {osc.G} observed, FP64 dense-Newton oracle, "
+                                            f"{csec:.1f} s"}
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

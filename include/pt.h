@@ -1,0 +1,203 @@
+/*
+ * pt.h -- C ABI of libpt, the MI355X (gfx950) library for the data-parallel
+ * hot path of sample-based in-hand object pose tracking (Liang et al.,
+ * arXiv 2002.12160).
+ *
+ * The method (Sec. III-B, Alg. 1): K simulations of a robot hand and an
+ * object, initialised around a pose estimate with perturbed poses and
+ * physics parameters, are stepped in lockstep with the real robot's joint
+ * command u_t (s_{t+1} = f(s_t, u_t, theta), Sec. III-A); each simulation's
+ * contact-sensor observation is compared with the observed one by a cost
+ * (Eq. 3); costs are averaged over a window of T steps (Eq. 1) whose argmin
+ * is the pose estimate (Eq. 2); every T steps a sample-based optimiser
+ * resamples the population (Sec. III-D).
+ *
+ * World model (the paper leaves its simulator's internals open; this is the
+ * reading implemented here and by the test oracle): a kinematic hand of L
+ * capsule links driven by u_t, an object of spheres resting on a table plane
+ * z = 0, speculative contacts kept when the signed gap d < margin and capped
+ * at the C_max smallest (d, key) with key = k*(L+1)+l (l == L: the table),
+ * Baumgarte depenetration erp*d/dt, a compliant Delassus operator
+ * W = J M^-1 J^T + compliance*I and Coulomb friction written as a
+ * second-order-cone complementarity problem, solved by exactly newton_iters
+ * iterations of a smoothed Fischer-Burmeister Newton method (smoothing
+ * fb_delta, impulse scale kappa) with Armijo backtracking over
+ * alpha in {1, 1/2, 1/4, 1/8} (sigma = armijo_sigma, 1/8 if none passes),
+ * warm-started from the previous step's impulses of the same keys; then
+ * semi-implicit Euler with a quaternion exponential update and a remap of
+ * the angular velocity that conserves world angular momentum.
+ *
+ * Conventions
+ *   - Every buffer argument is a DEVICE pointer to caller-owned contiguous
+ *     float32/int32 memory (torch tensors) unless stated "host".
+ *   - Every call is asynchronous on the given HIP stream; nothing here
+ *     synchronises the device except pt_read_stats and pt_autotune.
+ *   - Device memory is allocated only by pt_create_batch (scene tables,
+ *     internal scratch) and freed by pt_destroy_batch.
+ *   - Return value: PT_OK (0) or an error code; pt_last_error() returns a
+ *     thread-local message for the last failing call on that thread.
+ *     Argument and shape errors are detected before any launch.  Kernel
+ *     faults surface as PT_E_HIP at a later call or at stream sync.
+ *   - A simulation whose state becomes non-finite is not an error: its cost
+ *     becomes NaN, which ranks as +inf in the argmin and the resampler (the
+ *     paper's divergent samples, Sec. III-E), so it is replaced at the next
+ *     resampling.  Contacts beyond C_max are dropped (counted in stats).
+ *   - One host thread per batch at a time.
+ *
+ * Layouts (SoA, environment index fastest where it is per-environment):
+ *   state  [13][K]    x(3), q(4: w,x,y,z), v(3), omega(3), world frame
+ *   params [5][K]     mass, mu, f_pert(3) (f_pert acts for one step, then 0)
+ *   warm   [K][C_max][4]  key (int32 bits, -1 = empty), r(3) in (n,t1,t2)
+ *   obs    [4][L][K]  |c_l|, c_hat_l(3): force on sensor link l by the object
+ *   obs_gt [4][L][G]  observed force per group (the layout pt_observe gives
+ *                     for the batch of the G observed simulations)
+ *   hand   [L][20]    host: parent, joint0, joint1, axis0(3), axis1(3),
+ *                     offset(3), offset quaternion(4), length, radius, 2 spare
+ */
+#ifndef PT_H
+#define PT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#if defined(__GNUC__)
+#define PT_API __attribute__((visibility("default")))
+#else
+#define PT_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pt_batch_s *pt_batch;
+typedef void *pt_stream; /* a hipStream_t; NULL = the null stream */
+
+typedef enum {
+    PT_OK = 0,
+    PT_E_ARG = 1,         /* invalid argument, shape or size                 */
+    PT_E_HIP = 2,         /* a HIP runtime call failed                       */
+    PT_E_STATE = 3,       /* call not valid in the batch's current state     */
+    PT_E_CAPTURE = 4,     /* graph capture / instantiation failed            */
+    PT_E_UNSUPPORTED = 5  /* size beyond the library's limits                */
+} pt_status;
+
+#define PT_HAND_STRIDE 20
+#define PT_MAX_CMAX 64
+#define PT_MAX_LINKS 62
+#define PT_MAX_SPHERES 256
+
+typedef struct {
+    /* sizes */
+    int32_t K;            /* simulations in this batch, >= 1                      */
+    int32_t G;            /* contiguous groups (one observed env each), >= 1      */
+    int32_t L;            /* capsule links = contact sensors, 1..PT_MAX_LINKS     */
+    int32_t D;            /* joints, >= 0                                         */
+    int32_t n_types;      /* object types, >= 1                                   */
+    int32_t S_max;        /* row stride of the sphere table, 1..PT_MAX_SPHERES    */
+    int32_t C_max;        /* contact cap per simulation, 1..PT_MAX_CMAX           */
+    int32_t newton_iters; /* Newton iterations per step, 0..100                   */
+    int32_t T;            /* optimiser window length (steps), >= 1                */
+    int32_t solve_precision; /* contact-solve arithmetic: 64 (float64, 0 = default)
+                                or 32 (float32); geometry is float32 either way  */
+    /* model constants */
+    float dt, gravity[3], margin, erp, compliance, kappa, fb_delta, armijo_sigma;
+    float tau_contact, w_mag, w_dir;
+    /* population-based resampling (Sec. III-D.3) */
+    float elite_frac, sigma_mu, sigma_m, sigma_f, mu_lo, mu_hi, m_lo, m_hi;
+    uint64_t seed;                 /* Philox4x32-10 key                          */
+    /* scene tables: HOST pointers, copied to the device by pt_create_batch  */
+    const float *hand;             /* [L][20]                                    */
+    const float *spheres;          /* [n_types][S_max][4] body-frame centre, radius */
+    const int32_t *n_spheres;      /* [n_types], each 1..S_max                   */
+    const float *inv_inertia;      /* [n_types][3] principal 1/I per unit mass   */
+    const int32_t *env_type;       /* [K] in [0, n_types)                        */
+    const int32_t *group_start;    /* [G+1], 0 = g0 < ... < gG = K               */
+    /* simulation state: DEVICE pointers, caller-owned, bound for the batch's life */
+    float *state;                  /* [13][K]                                    */
+    float *params;                 /* [5][K]                                     */
+    float *warm;                   /* [K][C_max][4]                              */
+} pt_batch_desc;
+
+/* Creates a batch: validates the descriptor (PT_E_ARG / PT_E_UNSUPPORTED),
+ * copies the scene tables to the device and allocates internal scratch
+ * (hand segments, a contact buffer [K][C_max][4], counters).  The caller's
+ * state/params/warm buffers are used in place and must outlive the batch.
+ * On success *out receives the handle. */
+PT_API pt_status pt_create_batch(const pt_batch_desc *desc, pt_batch *out);
+
+/* Frees everything pt_create_batch allocated (after synchronising the
+ * device); the caller's buffers are untouched.  NULL is accepted. */
+PT_API pt_status pt_destroy_batch(pt_batch b);
+
+/* One world step of all K simulations (Alg. 1: "step simulation" with the
+ * same command in every simulation).  u_prev, u: device [D] joint commands
+ * of the previous and the current step (the hand moves from FK(u_prev) to
+ * FK(u) during the step; pass u_prev == u for the first step).  Updates
+ * state, params (f_pert consumed) and warm in place and keeps the solved
+ * contacts for pt_observe. */
+PT_API pt_status pt_step(pt_batch b, const float *u_prev, const float *u, pt_stream s);
+
+/* Per-sensor observation of the last pt_step (Sec. III-A: the force vector
+ * of each contact sensor): obs[4][L][K] = (|c_l|, c_l/|c_l|) with
+ * c_l = -(1/dt) sum over contacts on link l of the impulse on the object,
+ * the direction set to 0 when |c_l| <= tau_contact.  Table contacts are not
+ * sensed. */
+PT_API pt_status pt_observe(pt_batch b, float *obs, pt_stream s);
+
+/* Step cost (Eq. 3, here the force-magnitude and force-direction terms):
+ * cost_sum[i] += sum_l w_mag (|c_l| - |c^gt_l|)^2 + w_dir |c_hat_l - c_hat^gt_l|^2
+ * against obs_gt[.][l][g(i)] of its group g(i), then best[g] = argmin of cost_sum over group g
+ * (Eq. 2; ties -> lowest index, NaN ranks as +inf).  best may be NULL. */
+PT_API pt_status pt_cost(pt_batch b, const float *obs, const float *obs_gt, float *cost_sum, int32_t *best,
+                  pt_stream s);
+
+/* Population-based optimiser (PBO, Sec. III-D.3), per group: rank by
+ * (cost_sum, index) with NaN as +inf; the K_best = max(1, floor(K_g *
+ * elite_frac)) lowest are kept unchanged (parent = -1); every other
+ * simulation j copies the state, params and warm cache of the elite of rank
+ * floor(w0 * K_best / 2^32), w = Philox4x32-10(key = seed, counter =
+ * (j, window_idx, 0, 0)), then explores: mu and mass get Gaussian noise
+ * (sigma_mu, sigma_m; clamped to [mu_lo, mu_hi], [m_lo, m_hi]) and f_pert a
+ * Gaussian force (sigma_f per axis; Sec. III-D: perturbation forces), the
+ * normals drawn by Box-Muller from counters (j, window_idx, 1, 0) and
+ * (j, window_idx, 2, 0).  cost_sum is zeroed.  parent [K] may be NULL. */
+PT_API pt_status pt_resample(pt_batch b, float *cost_sum, uint32_t window_idx, int32_t *parent, pt_stream s);
+
+/* Batched execution of one optimiser window: T steps of every simulation
+ * with the per-step observation and cost fused, in one persistent kernel
+ * (environments pulled from a work queue, state kept on chip for all T
+ * steps), replayed from a captured HIP graph when graph != 0.
+ *   u_win      [T+1][D]   u_win[0] is the command before the window
+ *   obs_gt_win [T][4][L][G]
+ *   cost_sum   [K]        accumulated (not reset)
+ *   best       [G]        argmin of cost_sum after the window (may be NULL)
+ *   obs_out    [T][4][L][K] or NULL
+ * Equivalent to T rounds of pt_step/pt_observe/pt_cost. */
+PT_API pt_status pt_run_window(pt_batch b, const float *u_win, const float *obs_gt_win, float *cost_sum,
+                        int32_t *best, float *obs_out, int32_t graph, pt_stream s);
+
+/* Chooses the persistent kernel's environments per workgroup (waves per
+ * workgroup, {1,2,4,8}) by timing windows on scratch copies of the state;
+ * the batch's own buffers are not modified.  Synchronises the stream.
+ * result (host, may be NULL) receives the chosen value. */
+PT_API pt_status pt_autotune(pt_batch b, const float *u_win, const float *obs_gt_win, int32_t *result, pt_stream s);
+
+/* Sets the persistent kernel's environments per workgroup (1, 2, 4 or 8)
+ * by hand instead of through pt_autotune.  PT_E_UNSUPPORTED if that many
+ * simulations' LDS does not fit in one workgroup. */
+PT_API pt_status pt_set_tuning(pt_batch b, int32_t waves_per_workgroup);
+
+/* Reads the batch's cumulative counters (host out[4]): environment-steps,
+ * narrow-phase candidates (d < margin), contacts solved, contacts dropped by
+ * the cap.  Synchronises the stream. */
+PT_API pt_status pt_read_stats(pt_batch b, int64_t *out, pt_stream s);
+
+/* Message of the last failing call on this thread ("" if none). */
+PT_API const char *pt_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PT_H */

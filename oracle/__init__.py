@@ -56,7 +56,8 @@ class Contact(C.Structure):
 
 class Diag(C.Structure):
     _fields_ = [("n_candidates", C.c_int32), ("n_contacts", C.c_int32), ("iters", C.c_int32),
-                ("n_full_steps", C.c_int32), ("psi_first", C.c_double), ("psi_final", C.c_double)]
+                ("n_full_steps", C.c_int32), ("psi_first", C.c_double), ("psi_final", C.c_double),
+                ("d_last_kept", C.c_double), ("d_first_dropped", C.c_double)]
 
 
 class ResampleCfg(C.Structure):
@@ -70,7 +71,8 @@ CONTACT_DTYPE = np.dtype([("key", np.int32), ("link", np.int32), ("d", np.float6
                           ("p", np.float64, 3), ("vlink", np.float64, 3), ("r", np.float64, 3),
                           ("u", np.float64, 3)])
 DIAG_DTYPE = np.dtype([("n_candidates", np.int32), ("n_contacts", np.int32), ("iters", np.int32),
-                       ("n_full_steps", np.int32), ("psi_first", np.float64), ("psi_final", np.float64)])
+                       ("n_full_steps", np.int32), ("psi_first", np.float64), ("psi_final", np.float64),
+                       ("d_last_kept", np.float64), ("d_first_dropped", np.float64)])
 assert CONTACT_DTYPE.itemsize == C.sizeof(Contact)
 assert DIAG_DTYPE.itemsize == C.sizeof(Diag)
 

@@ -372,6 +372,7 @@ typedef struct {
     double x[3], q[4], R[9], Iinv[9], vs[3], ws[3];
     double mass, mu;
     int ncand, C;
+    double d_last_kept, d_first_dropped;
     or_contact *cc; /* [C] */
     double *J;      /* [3C][6] */
     double *uf;     /* [3C]    */
@@ -445,6 +446,8 @@ static void build_system(const or_model *m, const double *seg0, const double *se
     int C = ncand < Cmax ? ncand : Cmax;
     y->ncand = ncand;
     y->C = C;
+    y->d_last_kept = C > 0 ? cand[C - 1].d : -INFINITY;
+    y->d_first_dropped = ncand > C ? cand[C].d : INFINITY;
 
     /* 7-8. contact frames, Jacobian, W, u_free */
     or_contact *cc = (or_contact *)calloc((size_t)(C > 0 ? C : 1), sizeof(or_contact));
@@ -647,6 +650,8 @@ int or_env_step(const or_model *m, const double *seg0, const double *seg1, int t
         dg->n_full_steps = nfull;
         dg->psi_first = psi_first;
         dg->psi_final = psi;
+        dg->d_last_kept = y.d_last_kept;
+        dg->d_first_dropped = y.d_first_dropped;
     }
     free(r); free(u); free(A); free(Phi); free(dr); free(rt);
     sys_free(&y);

@@ -76,6 +76,8 @@ typedef struct {
     int32_t n_full_steps;      /* iterations that accepted alpha = 1            */
     double psi_first;          /* merit at the first iterate                    */
     double psi_final;          /* merit at the returned impulses                */
+    double d_last_kept;        /* gap of the last contact kept by the cap       */
+    double d_first_dropped;    /* gap of the first candidate the cap drops (+inf if none) */
 } or_diag;
 
 /* Forward kinematics of the kinematic hand at joint vector u[D]:

@@ -1,0 +1,429 @@
+// pt_api.hip -- host side of libpt: the C ABI declared in include/pt.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/pt.h"
+#include "pt_internal.h"
+
+using pt::Consts;
+using pt::Tables;
+
+namespace {
+
+thread_local std::string g_err;
+
+pt_status fail(pt_status code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+pt_status fail(pt_status code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                              \
+    do {                                                                                           \
+        hipError_t e_ = (expr);                                                                    \
+        if (e_ != hipSuccess) return fail(PT_E_HIP, "%s: %s", #expr, hipGetErrorString(e_));     \
+    } while (0)
+
+struct GraphKey {
+    const void *p[5];
+    int wpb;
+    bool operator==(const GraphKey &o) const
+    {
+        for (int i = 0; i < 5; ++i)
+            if (p[i] != o.p[i]) return false;
+        return wpb == o.wpb;
+    }
+};
+
+}  // namespace
+
+struct pt_batch_s {
+    Consts P;
+    pt::ResampleArgs R;
+    int n_types;
+    int device;
+    int num_cu;
+    // device tables
+    float *d_hand = nullptr, *d_spheres = nullptr, *d_inv = nullptr;
+    int32_t *d_nsph = nullptr, *d_type = nullptr, *d_group_of = nullptr, *d_group_start = nullptr;
+    int32_t *d_order = nullptr, *d_queue = nullptr;
+    int64_t *d_stats = nullptr;
+    // scratch
+    float *d_seg = nullptr;      // [L][16]
+    float *d_seg_win = nullptr;  // [T][L][16]
+    float *d_contacts = nullptr; // [K][C_max][4]
+    // caller-owned state
+    float *state, *params, *warm;
+    // host copies
+    std::vector<int32_t> group_start;
+    int max_group = 0;
+    // batched-path configuration
+    int wpb = 4;
+    int step_wpb = 4;
+    hipStream_t capture_stream = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    GraphKey graph_key{};
+    bool has_graph = false;
+};
+
+namespace {
+
+pt_status validate(const pt_batch_desc *d)
+{
+    if (!d) return fail(PT_E_ARG, "desc is NULL");
+    if (d->K < 1) return fail(PT_E_ARG, "K must be >= 1 (got %d)", d->K);
+    if (d->G < 1 || d->G > d->K) return fail(PT_E_ARG, "G must be in [1, K] (got %d)", d->G);
+    if (d->L < 1 || d->L > PT_MAX_LINKS) return fail(PT_E_UNSUPPORTED, "L must be in [1, %d] (got %d)", PT_MAX_LINKS, d->L);
+    if (d->D < 0) return fail(PT_E_ARG, "D must be >= 0");
+    if (d->n_types < 1) return fail(PT_E_ARG, "n_types must be >= 1");
+    if (d->S_max < 1 || d->S_max > PT_MAX_SPHERES)
+        return fail(PT_E_UNSUPPORTED, "S_max must be in [1, %d] (got %d)", PT_MAX_SPHERES, d->S_max);
+    if (d->C_max < 1 || d->C_max > PT_MAX_CMAX)
+        return fail(PT_E_UNSUPPORTED, "C_max must be in [1, %d] (got %d)", PT_MAX_CMAX, d->C_max);
+    if (d->newton_iters < 0 || d->newton_iters > 100) return fail(PT_E_ARG, "newton_iters must be in [0, 100]");
+    if (d->T < 1) return fail(PT_E_ARG, "T must be >= 1");
+    if (d->solve_precision != 0 && d->solve_precision != 32 && d->solve_precision != 64)
+        return fail(PT_E_ARG, "solve_precision must be 32 or 64 (or 0 for the default, 64)");
+    if (!(d->dt > 0.f) || !std::isfinite(d->dt)) return fail(PT_E_ARG, "dt must be positive and finite");
+    if (!(d->kappa > 0.f) || !(d->fb_delta > 0.f)) return fail(PT_E_ARG, "kappa and fb_delta must be positive");
+    if (!(d->compliance >= 0.f)) return fail(PT_E_ARG, "compliance must be >= 0");
+    if (!(d->elite_frac > 0.f && d->elite_frac <= 1.f)) return fail(PT_E_ARG, "elite_frac must be in (0, 1]");
+    if (!(d->mu_lo <= d->mu_hi) || !(d->m_lo <= d->m_hi) || !(d->m_lo > 0.f))
+        return fail(PT_E_ARG, "invalid parameter clamp ranges");
+    if (!d->hand || !d->spheres || !d->n_spheres || !d->inv_inertia || !d->env_type || !d->group_start)
+        return fail(PT_E_ARG, "scene table pointer is NULL");
+    if (!d->state || !d->params || !d->warm) return fail(PT_E_ARG, "state/params/warm pointer is NULL");
+    for (int l = 0; l < d->L; ++l) {
+        const float *h = d->hand + (size_t)l * PT_HAND_STRIDE;
+        int parent = (int)h[0], j0 = (int)h[1], j1 = (int)h[2];
+        if (parent < -1 || parent >= l) return fail(PT_E_ARG, "link %d: parent %d must be -1 or a lower index", l, parent);
+        if (j0 < -1 || j0 >= d->D || j1 < -1 || j1 >= d->D) return fail(PT_E_ARG, "link %d: joint index out of range", l);
+        if (!(h[16] >= 0.f) || !(h[17] >= 0.f)) return fail(PT_E_ARG, "link %d: negative length or radius", l);
+    }
+    for (int t = 0; t < d->n_types; ++t)
+        if (d->n_spheres[t] < 1 || d->n_spheres[t] > d->S_max)
+            return fail(PT_E_ARG, "n_spheres[%d] = %d must be in [1, S_max]", t, d->n_spheres[t]);
+    for (int i = 0; i < d->K; ++i)
+        if (d->env_type[i] < 0 || d->env_type[i] >= d->n_types) return fail(PT_E_ARG, "env_type[%d] out of range", i);
+    if (d->group_start[0] != 0 || d->group_start[d->G] != d->K)
+        return fail(PT_E_ARG, "group_start must begin at 0 and end at K");
+    for (int g = 0; g < d->G; ++g)
+        if (d->group_start[g + 1] <= d->group_start[g]) return fail(PT_E_ARG, "groups must be non-empty and increasing");
+    return PT_OK;
+}
+
+int round_up(int a, int b) { return (a + b - 1) / b * b; }
+
+}  // namespace
+
+extern "C" {
+
+const char *pt_last_error(void) { return g_err.c_str(); }
+
+pt_status pt_create_batch(const pt_batch_desc *d, pt_batch *out)
+{
+    if (!out) return fail(PT_E_ARG, "out is NULL");
+    *out = nullptr;
+    pt_status st = validate(d);
+    if (st != PT_OK) return st;
+    const int max_cand = round_up(d->S_max * (d->L + 1), 64);
+    const size_t wave_lds = pt::wave_lds_bytes(max_cand);
+    if (wave_lds > 160 * 1024)
+        return fail(PT_E_UNSUPPORTED, "S_max*(L+1) = %d candidates need %zu B of LDS per simulation (> 160 KiB)",
+                    d->S_max * (d->L + 1), wave_lds);
+
+    pt_batch b = new pt_batch_s();
+    Consts &P = b->P;
+    P.K = d->K; P.G = d->G; P.L = d->L; P.D = d->D; P.S_max = d->S_max; P.C_max = d->C_max;
+    P.newton_iters = d->newton_iters; P.T = d->T; P.max_cand = max_cand;
+    P.solve_fp64 = d->solve_precision == 32 ? 0 : 1;
+    P.dt = d->dt; P.gx = d->gravity[0]; P.gy = d->gravity[1]; P.gz = d->gravity[2];
+    P.margin = d->margin; P.erp = d->erp; P.compliance = d->compliance; P.kappa = d->kappa;
+    P.fb_delta = d->fb_delta; P.armijo_sigma = d->armijo_sigma;
+    P.tau_contact = d->tau_contact; P.w_mag = d->w_mag; P.w_dir = d->w_dir;
+    b->R = {d->elite_frac, d->sigma_mu, d->sigma_m, d->sigma_f, d->mu_lo, d->mu_hi, d->m_lo, d->m_hi, d->seed};
+    b->n_types = d->n_types;
+    b->state = d->state;
+    b->params = d->params;
+    b->warm = d->warm;
+    b->group_start.assign(d->group_start, d->group_start + d->G + 1);
+    for (int g = 0; g < d->G; ++g) b->max_group = std::max(b->max_group, b->group_start[g + 1] - b->group_start[g]);
+    if ((size_t)8 * b->max_group > 160 * 1024) {
+        delete b;
+        return fail(PT_E_UNSUPPORTED, "group of %d simulations exceeds the resampler's LDS (max 20480)", b->max_group);
+    }
+
+    auto cleanup = [&](pt_status code) {
+        pt_destroy_batch(b);
+        return code;
+    };
+#define HIP_TRY_C(expr)                                                                            \
+    do {                                                                                           \
+        hipError_t e_ = (expr);                                                                    \
+        if (e_ != hipSuccess) return cleanup(fail(PT_E_HIP, "%s: %s", #expr, hipGetErrorString(e_))); \
+    } while (0)
+
+    HIP_TRY_C(hipGetDevice(&b->device));
+    HIP_TRY_C(hipDeviceGetAttribute(&b->num_cu, hipDeviceAttributeMultiprocessorCount, b->device));
+    HIP_TRY_C(set_lds_limits(160 * 1024));
+
+    const size_t K = d->K;
+    std::vector<int32_t> group_of(K), order(K);
+    for (int g = 0; g < d->G; ++g)
+        for (int i = d->group_start[g]; i < d->group_start[g + 1]; ++i) group_of[i] = g;
+    // persistent-kernel work order: simulations with more spheres first
+    for (size_t i = 0; i < K; ++i) order[i] = (int32_t)i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int c) {
+        return d->n_spheres[d->env_type[a]] > d->n_spheres[d->env_type[c]];
+    });
+
+    HIP_TRY_C(hipMalloc(&b->d_hand, sizeof(float) * d->L * PT_HAND_STRIDE));
+    HIP_TRY_C(hipMalloc(&b->d_spheres, sizeof(float) * d->n_types * d->S_max * 4));
+    HIP_TRY_C(hipMalloc(&b->d_inv, sizeof(float) * d->n_types * 3));
+    HIP_TRY_C(hipMalloc(&b->d_nsph, sizeof(int32_t) * d->n_types));
+    HIP_TRY_C(hipMalloc(&b->d_type, sizeof(int32_t) * K));
+    HIP_TRY_C(hipMalloc(&b->d_group_of, sizeof(int32_t) * K));
+    HIP_TRY_C(hipMalloc(&b->d_group_start, sizeof(int32_t) * (d->G + 1)));
+    HIP_TRY_C(hipMalloc(&b->d_order, sizeof(int32_t) * K));
+    HIP_TRY_C(hipMalloc(&b->d_queue, sizeof(int32_t) * 4));
+    HIP_TRY_C(hipMalloc(&b->d_stats, sizeof(int64_t) * 4));
+    HIP_TRY_C(hipMalloc(&b->d_seg, sizeof(float) * d->L * pt::SEG_STRIDE));
+    HIP_TRY_C(hipMalloc(&b->d_seg_win, sizeof(float) * (size_t)d->T * d->L * pt::SEG_STRIDE));
+    HIP_TRY_C(hipMalloc(&b->d_contacts, sizeof(float) * K * d->C_max * 4));
+    HIP_TRY_C(hipMemcpy(b->d_hand, d->hand, sizeof(float) * d->L * PT_HAND_STRIDE, hipMemcpyHostToDevice));
+    HIP_TRY_C(hipMemcpy(b->d_spheres, d->spheres, sizeof(float) * d->n_types * d->S_max * 4, hipMemcpyHostToDevice));
+    HIP_TRY_C(hipMemcpy(b->d_inv, d->inv_inertia, sizeof(float) * d->n_types * 3, hipMemcpyHostToDevice));
+    HIP_TRY_C(hipMemcpy(b->d_nsph, d->n_spheres, sizeof(int32_t) * d->n_types, hipMemcpyHostToDevice));
+    HIP_TRY_C(hipMemcpy(b->d_type, d->env_type, sizeof(int32_t) * K, hipMemcpyHostToDevice));
+    HIP_TRY_C(hipMemcpy(b->d_group_of, group_of.data(), sizeof(int32_t) * K, hipMemcpyHostToDevice));
+    HIP_TRY_C(hipMemcpy(b->d_group_start, d->group_start, sizeof(int32_t) * (d->G + 1), hipMemcpyHostToDevice));
+    HIP_TRY_C(hipMemcpy(b->d_order, order.data(), sizeof(int32_t) * K, hipMemcpyHostToDevice));
+    HIP_TRY_C(hipMemset(b->d_queue, 0, sizeof(int32_t) * 4));
+    HIP_TRY_C(hipMemset(b->d_stats, 0, sizeof(int64_t) * 4));
+    HIP_TRY_C(hipMemset(b->d_contacts, 0, sizeof(float) * K * d->C_max * 4));
+    HIP_TRY_C(hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking));
+    // environments per workgroup within the LDS budget (autotuned later)
+    b->wpb = 4;
+    while (b->wpb > 1 && (size_t)b->wpb * wave_lds > 160 * 1024) b->wpb >>= 1;
+    b->step_wpb = b->wpb;
+#undef HIP_TRY_C
+    *out = b;
+    return PT_OK;
+}
+
+pt_status pt_destroy_batch(pt_batch b)
+{
+    if (!b) return PT_OK;
+    (void)hipDeviceSynchronize();
+    if (b->has_graph) (void)hipGraphExecDestroy(b->graph_exec);
+    if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
+    void *ptrs[] = {b->d_hand, b->d_spheres, b->d_inv, b->d_nsph, b->d_type, b->d_group_of, b->d_group_start,
+                    b->d_order, b->d_queue, b->d_stats, b->d_seg, b->d_seg_win, b->d_contacts};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    delete b;
+    return PT_OK;
+}
+
+static Tables tables_of(const pt_batch b)
+{
+    Tables tb;
+    tb.hand = b->d_hand;
+    tb.spheres = b->d_spheres;
+    tb.n_spheres = b->d_nsph;
+    tb.inv_inertia = b->d_inv;
+    tb.env_type = b->d_type;
+    tb.group_of = b->d_group_of;
+    return tb;
+}
+
+pt_status pt_step(pt_batch b, const float *u_prev, const float *u, pt_stream s)
+{
+    if (!b) return fail(PT_E_ARG, "batch is NULL");
+    if (b->P.D > 0 && (!u_prev || !u)) return fail(PT_E_ARG, "u_prev/u is NULL");
+    hipStream_t st = (hipStream_t)s;
+    HIP_TRY(launch_hand_fk(b->d_hand, b->P.L, b->P.dt, u_prev, u, 0, 1, b->d_seg, st));
+    HIP_TRY(launch_step(b->P, tables_of(b), b->d_seg, b->state, b->params, b->warm, b->d_contacts, b->d_stats,
+                        b->step_wpb, st));
+    return PT_OK;
+}
+
+pt_status pt_observe(pt_batch b, float *obs, pt_stream s)
+{
+    if (!b) return fail(PT_E_ARG, "batch is NULL");
+    if (!obs) return fail(PT_E_ARG, "obs is NULL");
+    HIP_TRY(launch_observe(b->P, b->d_contacts, obs, (hipStream_t)s));
+    return PT_OK;
+}
+
+pt_status pt_cost(pt_batch b, const float *obs, const float *obs_gt, float *cost_sum, int32_t *best, pt_stream s)
+{
+    if (!b) return fail(PT_E_ARG, "batch is NULL");
+    if (!obs || !obs_gt || !cost_sum) return fail(PT_E_ARG, "obs/obs_gt/cost_sum is NULL");
+    hipStream_t st = (hipStream_t)s;
+    HIP_TRY(launch_cost(b->P, b->d_group_of, obs, obs_gt, cost_sum, st));
+    if (best) HIP_TRY(launch_argmin(b->P.G, b->d_group_start, cost_sum, best, st));
+    return PT_OK;
+}
+
+pt_status pt_resample(pt_batch b, float *cost_sum, uint32_t window_idx, int32_t *parent, pt_stream s)
+{
+    if (!b) return fail(PT_E_ARG, "batch is NULL");
+    if (!cost_sum) return fail(PT_E_ARG, "cost_sum is NULL");
+    HIP_TRY(launch_resample(b->P, b->R, b->d_group_start, b->max_group, window_idx, cost_sum, b->state, b->params,
+                            b->warm, parent, (hipStream_t)s));
+    return PT_OK;
+}
+
+// the launches of one window, in stream order
+static pt_status enqueue_window(pt_batch b, const float *u_win, const float *obs_gt_win, float *cost_sum,
+                                int32_t *best, float *obs_out, int wpb, float *state, float *params, float *warm,
+                                hipStream_t st)
+{
+    const Consts &P = b->P;
+    int bpc = 0;
+    HIP_TRY(window_occupancy(wpb, P.max_cand, P.solve_fp64 != 0, &bpc));
+    if (bpc < 1) return fail(PT_E_UNSUPPORTED, "persistent kernel does not fit with %d waves per workgroup", wpb);
+    int want = (P.K + wpb - 1) / wpb;
+    int blocks = std::min(want, bpc * b->num_cu);
+    HIP_TRY(launch_hand_fk(b->d_hand, P.L, P.dt, u_win, u_win + P.D, P.D, P.T, b->d_seg_win, st));
+    HIP_TRY(launch_reset_queue(b->d_queue, st));
+    HIP_TRY(launch_window(P, tables_of(b), b->d_seg_win, state, params, warm, obs_gt_win, cost_sum, obs_out,
+                          b->d_order, b->d_queue, b->d_stats, wpb, blocks, st));
+    if (best) HIP_TRY(launch_argmin(P.G, b->d_group_start, cost_sum, best, st));
+    return PT_OK;
+}
+
+pt_status pt_run_window(pt_batch b, const float *u_win, const float *obs_gt_win, float *cost_sum, int32_t *best,
+                        float *obs_out, int32_t graph, pt_stream s)
+{
+    if (!b) return fail(PT_E_ARG, "batch is NULL");
+    if (!u_win || !obs_gt_win || !cost_sum) return fail(PT_E_ARG, "u_win/obs_gt_win/cost_sum is NULL");
+    hipStream_t st = (hipStream_t)s;
+    if (!graph)
+        return enqueue_window(b, u_win, obs_gt_win, cost_sum, best, obs_out, b->wpb, b->state, b->params, b->warm, st);
+    GraphKey key{{u_win, obs_gt_win, cost_sum, best, obs_out}, b->wpb};
+    if (!b->has_graph || !(key == b->graph_key)) {
+        if (b->has_graph) {
+            HIP_TRY(hipStreamSynchronize(st));
+            HIP_TRY(hipGraphExecDestroy(b->graph_exec));
+            b->has_graph = false;
+        }
+        hipGraph_t g = nullptr;
+        HIP_TRY(hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal));
+        pt_status cs = enqueue_window(b, u_win, obs_gt_win, cost_sum, best, obs_out, b->wpb, b->state, b->params,
+                                      b->warm, b->capture_stream);
+        hipError_t ec = hipStreamEndCapture(b->capture_stream, &g);
+        if (cs != PT_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return cs;
+        }
+        if (ec != hipSuccess) return fail(PT_E_CAPTURE, "hipStreamEndCapture: %s", hipGetErrorString(ec));
+        hipError_t ei = hipGraphInstantiate(&b->graph_exec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ei != hipSuccess) return fail(PT_E_CAPTURE, "hipGraphInstantiate: %s", hipGetErrorString(ei));
+        b->graph_key = key;
+        b->has_graph = true;
+    }
+    HIP_TRY(hipGraphLaunch(b->graph_exec, st));
+    return PT_OK;
+}
+
+pt_status pt_autotune(pt_batch b, const float *u_win, const float *obs_gt_win, int32_t *result, pt_stream s)
+{
+    if (!b) return fail(PT_E_ARG, "batch is NULL");
+    if (!u_win || !obs_gt_win) return fail(PT_E_ARG, "u_win/obs_gt_win is NULL");
+    hipStream_t st = (hipStream_t)s;
+    const Consts &P = b->P;
+    const size_t K = P.K;
+    const size_t n_state = 13 * K, n_params = 5 * K, n_warm = K * P.C_max * 4;
+    float *tmp = nullptr;
+    HIP_TRY(hipMalloc(&tmp, sizeof(float) * (n_state + n_params + n_warm + K)));
+    float *ts = tmp, *tp = ts + n_state, *tw = tp + n_params, *tc = tw + n_warm;
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    const size_t wave_lds = pt::wave_lds_bytes(P.max_cand);
+    int best_wpb = b->wpb;
+    float best_ms = 1e30f;
+    pt_status rc = PT_OK;
+    for (int wpb : {1, 2, 4, 8}) {
+        if ((size_t)wpb * wave_lds > 160 * 1024) continue;
+        float total = 0.f;
+        for (int rep = 0; rep < 3 && rc == PT_OK; ++rep) {
+            if (hipMemcpyAsync(ts, b->state, sizeof(float) * n_state, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+                hipMemcpyAsync(tp, b->params, sizeof(float) * n_params, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+                hipMemcpyAsync(tw, b->warm, sizeof(float) * n_warm, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+                hipMemsetAsync(tc, 0, sizeof(float) * K, st) != hipSuccess) {
+                rc = fail(PT_E_HIP, "autotune scratch copy failed");
+                break;
+            }
+            (void)hipEventRecord(e0, st);
+            rc = enqueue_window(b, u_win, obs_gt_win, tc, nullptr, nullptr, wpb, ts, tp, tw, st);
+            (void)hipEventRecord(e1, st);
+            if (rc != PT_OK) break;
+            if (hipEventSynchronize(e1) != hipSuccess) {
+                rc = fail(PT_E_HIP, "autotune: window failed");
+                break;
+            }
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (rep > 0) total += ms;  // first run warms up
+        }
+        if (rc != PT_OK) break;
+        if (total < best_ms) {
+            best_ms = total;
+            best_wpb = wpb;
+        }
+    }
+    (void)hipStreamSynchronize(st);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipFree(tmp);
+    if (rc != PT_OK) return rc;
+    if (best_wpb != b->wpb && b->has_graph) {
+        (void)hipGraphExecDestroy(b->graph_exec);
+        b->has_graph = false;
+    }
+    b->wpb = best_wpb;
+    if (result) *result = best_wpb;
+    return PT_OK;
+}
+
+pt_status pt_set_tuning(pt_batch b, int32_t wpb)
+{
+    if (!b) return fail(PT_E_ARG, "batch is NULL");
+    if (wpb != 1 && wpb != 2 && wpb != 4 && wpb != 8) return fail(PT_E_ARG, "waves per workgroup must be 1, 2, 4 or 8");
+    if ((size_t)wpb * pt::wave_lds_bytes(b->P.max_cand) > 160 * 1024)
+        return fail(PT_E_UNSUPPORTED, "%d simulations per workgroup exceed the LDS", wpb);
+    if (wpb != b->wpb && b->has_graph) {
+        HIP_TRY(hipDeviceSynchronize());
+        HIP_TRY(hipGraphExecDestroy(b->graph_exec));
+        b->has_graph = false;
+    }
+    b->wpb = wpb;
+    return PT_OK;
+}
+
+pt_status pt_read_stats(pt_batch b, int64_t *out, pt_stream s)
+{
+    if (!b || !out) return fail(PT_E_ARG, "batch/out is NULL");
+    HIP_TRY(hipStreamSynchronize((hipStream_t)s));
+    HIP_TRY(hipMemcpy(out, b->d_stats, sizeof(int64_t) * 4, hipMemcpyDeviceToHost));
+    return PT_OK;
+}
+
+}  // extern "C"

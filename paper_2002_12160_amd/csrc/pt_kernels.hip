@@ -1,0 +1,602 @@
+// pt_kernels.hip -- HIP kernels of libpt for CDNA4 (gfx950).
+//
+//   k_hand_fk      forward kinematics of the kinematic hand, once per step
+//                  (shared by every simulation: the same command u_t drives
+//                  all of them, Alg. 1)
+//   k_step         plain path: one simulation step per wavefront; contacts
+//                  written to HBM for the observation kernel
+//   k_observe      per-sensor contact force of the last step
+//   k_cost         step cost against the observed force, running sum (Eq. 1)
+//   k_argmin       per-group argmin of the running cost (Eq. 2)
+//   k_resample     population-based resampling with Philox4x32-10 (Sec. III-D.3)
+//   k_window       batched path: persistent kernel running T steps with the
+//                  observation and cost fused, state kept on chip
+#include "pt_internal.h"
+
+namespace pt {
+
+// ---------------------------------------------------------------------
+// hand kinematics (double precision: it runs once per step for the whole
+// population, and the link velocities are differences of positions)
+// ---------------------------------------------------------------------
+__device__ void quat_to_mat_d(const double *q, double *R)
+{
+    double w = q[0], x = q[1], y = q[2], z = q[3];
+    R[0] = 1 - 2 * (y * y + z * z); R[1] = 2 * (x * y - w * z);     R[2] = 2 * (x * z + w * y);
+    R[3] = 2 * (x * y + w * z);     R[4] = 1 - 2 * (x * x + z * z); R[5] = 2 * (y * z - w * x);
+    R[6] = 2 * (x * z - w * y);     R[7] = 2 * (y * z + w * x);     R[8] = 1 - 2 * (x * x + y * y);
+}
+
+__device__ void quat_mul_d(const double *a, const double *b, double *o)
+{
+    double w = a[0] * b[0] - a[1] * b[1] - a[2] * b[2] - a[3] * b[3];
+    double x = a[0] * b[1] + a[1] * b[0] + a[2] * b[3] - a[3] * b[2];
+    double y = a[0] * b[2] - a[1] * b[3] + a[2] * b[0] + a[3] * b[1];
+    double z = a[0] * b[3] + a[1] * b[2] - a[2] * b[1] + a[3] * b[0];
+    o[0] = w; o[1] = x; o[2] = y; o[3] = z;
+}
+
+__device__ void fk_one(const float *__restrict__ hand, int L, const float *__restrict__ u, double *tq, double *tp,
+                       double *seg_a, double *seg_b)
+{
+    for (int l = 0; l < L; ++l) {
+        const float *h = hand + l * HAND_STRIDE;
+        int parent = (int)h[0], j0 = (int)h[1], j1 = (int)h[2];
+        double pq[4] = {1, 0, 0, 0}, pp[3] = {0, 0, 0};
+        if (parent >= 0) {
+            for (int i = 0; i < 4; ++i) pq[i] = tq[4 * parent + i];
+            for (int i = 0; i < 3; ++i) pp[i] = tp[3 * parent + i];
+        }
+        double Rp[9];
+        quat_to_mat_d(pq, Rp);
+        double off[3] = {h[9], h[10], h[11]};
+        double o[3] = {pp[0] + Rp[0] * off[0] + Rp[1] * off[1] + Rp[2] * off[2],
+                       pp[1] + Rp[3] * off[0] + Rp[4] * off[1] + Rp[5] * off[2],
+                       pp[2] + Rp[6] * off[0] + Rp[7] * off[1] + Rp[8] * off[2]};
+        double qo[4] = {h[12], h[13], h[14], h[15]};
+        double q[4];
+        quat_mul_d(pq, qo, q);
+        if (j0 >= 0) {
+            double th = u[j0], s = sin(0.5 * th);
+            double qj[4] = {cos(0.5 * th), s * h[3], s * h[4], s * h[5]}, t[4];
+            quat_mul_d(q, qj, t);
+            for (int i = 0; i < 4; ++i) q[i] = t[i];
+        }
+        if (j1 >= 0) {
+            double th = u[j1], s = sin(0.5 * th);
+            double qj[4] = {cos(0.5 * th), s * h[6], s * h[7], s * h[8]}, t[4];
+            quat_mul_d(q, qj, t);
+            for (int i = 0; i < 4; ++i) q[i] = t[i];
+        }
+        double R[9];
+        quat_to_mat_d(q, R);
+        double len = h[16];
+        double b[3] = {o[0] + len * R[0], o[1] + len * R[3], o[2] + len * R[6]};
+        for (int i = 0; i < 4; ++i) tq[4 * l + i] = q[i];
+        for (int i = 0; i < 3; ++i) {
+            tp[3 * l + i] = b[i];
+            seg_a[3 * l + i] = o[i];
+            seg_b[3 * l + i] = b[i];
+        }
+    }
+}
+
+// grid: one block per step; u_prev/u for step t at u_prev + t*stride.
+__global__ void k_hand_fk(const float *__restrict__ hand, int L, float dt, const float *__restrict__ u_prev,
+                          const float *__restrict__ u, int stride, float *__restrict__ seg_out)
+{
+    __shared__ double tq[2][MAX_LINKS * 4], tp[2][MAX_LINKS * 3], sa[2][MAX_LINKS * 3], sb[2][MAX_LINKS * 3];
+    const int t = blockIdx.x;
+    if (threadIdx.x < 2) {
+        int w = threadIdx.x;
+        const float *uu = (w == 0 ? u_prev : u) + (size_t)t * stride;
+        fk_one(hand, L, uu, tq[w], tp[w], sa[w], sb[w]);
+    }
+    __syncthreads();
+    const double idt = 1.0 / (double)dt;
+    for (int l = threadIdx.x; l < L; l += blockDim.x) {
+        float *s = seg_out + ((size_t)t * L + l) * SEG_STRIDE;
+        float a0[3], ab[3];
+        for (int i = 0; i < 3; ++i) {
+            a0[i] = (float)sa[0][3 * l + i];
+            ab[i] = (float)(sb[0][3 * l + i] - sa[0][3 * l + i]);
+        }
+        float L2 = ab[0] * ab[0] + ab[1] * ab[1] + ab[2] * ab[2];
+        float inv = sqrtf(L2) >= 1e-9f ? 1.f / L2 : 0.f;
+        for (int i = 0; i < 3; ++i) {
+            s[i] = a0[i];
+            s[4 + i] = ab[i];
+            s[8 + i] = (float)((sa[1][3 * l + i] - sa[0][3 * l + i]) * idt);
+            s[12 + i] = (float)((sb[1][3 * l + i] - sb[0][3 * l + i]) * idt);
+        }
+        s[3] = hand[l * HAND_STRIDE + 17];
+        s[7] = inv;
+        s[11] = 0.f;
+        s[15] = 0.f;
+    }
+}
+
+// ---------------------------------------------------------------------
+// helpers shared by the plain and the batched kernels
+// ---------------------------------------------------------------------
+__device__ __forceinline__ WaveLds carve_lds(char *base, int wave_in_block, int max_cand)
+{
+    char *p = base + (size_t)wave_in_block * wave_lds_bytes(max_cand);
+    WaveLds w;
+    w.cand_d = reinterpret_cast<float *>(p);
+    w.cand_k = reinterpret_cast<int *>(p + 4 * (size_t)max_cand);
+    w.sel = reinterpret_cast<int *>(p + 8 * (size_t)max_cand);
+    w.wkey = w.sel + WAVE;
+    w.wr = reinterpret_cast<float *>(w.wkey + WAVE);
+    return w;
+}
+
+__device__ __forceinline__ float *contact_stage(const WaveLds &w) { return w.wr + 3 * WAVE; }  // [64][4]
+
+__device__ __forceinline__ void load_body(const float *__restrict__ state, const float *__restrict__ params, int K,
+                                          int e, Body &B)
+{
+    B.x[0] = state[0 * K + e]; B.x[1] = state[1 * K + e]; B.x[2] = state[2 * K + e];
+    B.q[0] = state[3 * K + e]; B.q[1] = state[4 * K + e]; B.q[2] = state[5 * K + e]; B.q[3] = state[6 * K + e];
+    B.v[0] = state[7 * K + e]; B.v[1] = state[8 * K + e]; B.v[2] = state[9 * K + e];
+    B.w[0] = state[10 * K + e]; B.w[1] = state[11 * K + e]; B.w[2] = state[12 * K + e];
+    B.m = params[0 * K + e]; B.mu = params[1 * K + e];
+    B.f[0] = params[2 * K + e]; B.f[1] = params[3 * K + e]; B.f[2] = params[4 * K + e];
+}
+
+__device__ __forceinline__ void store_body(float *__restrict__ state, float *__restrict__ params, int K, int e,
+                                           const Body &B)
+{
+    if (lane_id() == 0) {
+        state[0 * K + e] = B.x[0]; state[1 * K + e] = B.x[1]; state[2 * K + e] = B.x[2];
+        state[3 * K + e] = B.q[0]; state[4 * K + e] = B.q[1]; state[5 * K + e] = B.q[2]; state[6 * K + e] = B.q[3];
+        state[7 * K + e] = B.v[0]; state[8 * K + e] = B.v[1]; state[9 * K + e] = B.v[2];
+        state[10 * K + e] = B.w[0]; state[11 * K + e] = B.w[1]; state[12 * K + e] = B.w[2];
+        params[2 * K + e] = B.f[0]; params[3 * K + e] = B.f[1]; params[4 * K + e] = B.f[2];
+    }
+}
+
+__device__ __forceinline__ void load_warm(const float *__restrict__ warm, int C_max, int e, int &wkey, float *wr)
+{
+    const int lane = lane_id();
+    wkey = -1;
+    wr[0] = wr[1] = wr[2] = 0.f;
+    if (lane < C_max) {
+        float4 w = *reinterpret_cast<const float4 *>(warm + ((size_t)e * C_max + lane) * WARM_STRIDE);
+        wkey = __float_as_int(w.x);
+        wr[0] = w.y; wr[1] = w.z; wr[2] = w.w;
+    }
+}
+
+__device__ __forceinline__ void store_warm(float *__restrict__ warm, int C_max, int e, int wkey, const float *wr)
+{
+    const int lane = lane_id();
+    if (lane < C_max)
+        *reinterpret_cast<float4 *>(warm + ((size_t)e * C_max + lane) * WARM_STRIDE) =
+            make_float4(__int_as_float(wkey), wr[0], wr[1], wr[2]);
+}
+
+__device__ __forceinline__ void flush_stats(int64_t *stats, const StepStats &st, int64_t steps)
+{
+    if (lane_id() == 0) {
+        atomicAdd((unsigned long long *)&stats[0], (unsigned long long)steps);
+        atomicAdd((unsigned long long *)&stats[1], (unsigned long long)st.cand);
+        atomicAdd((unsigned long long *)&stats[2], (unsigned long long)st.contacts);
+        atomicAdd((unsigned long long *)&stats[3], (unsigned long long)st.dropped);
+    }
+}
+
+// per-sensor force from the contacts staged in LDS ([64][4]: link bits,
+// impulse on the object), summed in contact order; lane l < L gets
+// (|c_l|, c_hat_l).  Returns false on lanes >= L.
+__device__ __forceinline__ bool sensor_force(const Consts &P, const float *stage, float *o)
+{
+    const int lane = lane_id();
+    float f0 = 0.f, f1 = 0.f, f2 = 0.f;
+    for (int c = 0; c < P.C_max; ++c) {
+        const float4 rec = *reinterpret_cast<const float4 *>(stage + 4 * c);
+        if (__float_as_int(rec.x) == lane) {
+            f0 += rec.y; f1 += rec.z; f2 += rec.w;
+        }
+    }
+    float idt = 1.f / P.dt;
+    f0 = -f0 * idt; f1 = -f1 * idt; f2 = -f2 * idt;
+    float mag = sqrtf(f0 * f0 + f1 * f1 + f2 * f2);
+    bool on = mag > P.tau_contact;
+    float im = on ? 1.f / mag : 0.f;
+    o[0] = mag; o[1] = on ? f0 * im : 0.f; o[2] = on ? f1 * im : 0.f; o[3] = on ? f2 * im : 0.f;
+    return lane < P.L;
+}
+
+__device__ __forceinline__ float sensor_cost(const Consts &P, const float *o, const float *gt)
+{
+    float dm = o[0] - gt[0];
+    float d1 = o[1] - gt[1], d2 = o[2] - gt[2], d3 = o[3] - gt[3];
+    return P.w_mag * dm * dm + P.w_dir * (d1 * d1 + d2 * d2 + d3 * d3);
+}
+
+// ---------------------------------------------------------------------
+// plain path
+// ---------------------------------------------------------------------
+template <typename SR>
+__global__ __launch_bounds__(512) void k_step(Consts P, Tables tb, const float *__restrict__ seg,
+                                               float *__restrict__ state, float *__restrict__ params,
+                                               float *__restrict__ warm, float *__restrict__ contacts,
+                                               int64_t *__restrict__ stats)
+{
+    extern __shared__ __align__(16) char smem[];
+    const int wib = threadIdx.x / WAVE;
+    const int e = blockIdx.x * (blockDim.x / WAVE) + wib;
+    if (e >= P.K) return;
+    WaveLds lds = carve_lds(smem, wib, P.max_cand);
+    const int type = tb.env_type[e];
+    const int S = tb.n_spheres[type];
+    const float *sph = tb.spheres + (size_t)type * P.S_max * 4;
+    const float *inv = tb.inv_inertia + 3 * type;
+    Body B;
+    load_body(state, params, P.K, e, B);
+    int wkey;
+    float wr[3];
+    load_warm(warm, P.C_max, e, wkey, wr);
+    StepStats st = {0, 0, 0};
+    int link;
+    float imp[3];
+    env_step<SR>(P, seg, sph, S, inv, B, wkey, wr, link, imp, lds, st);
+    store_body(state, params, P.K, e, B);
+    store_warm(warm, P.C_max, e, wkey, wr);
+    const int lane = lane_id();
+    if (lane < P.C_max)
+        *reinterpret_cast<float4 *>(contacts + ((size_t)e * P.C_max + lane) * 4) =
+            make_float4(__int_as_float(link), imp[0], imp[1], imp[2]);
+    flush_stats(stats, st, 1);
+}
+
+// one wavefront per simulation, lanes over sensors
+__global__ __launch_bounds__(256) void k_observe(Consts P, const float *__restrict__ contacts, float *__restrict__ obs)
+{
+    __shared__ __align__(16) float stage[4][WAVE * 4];
+    const int wib = threadIdx.x / WAVE;
+    const int e = blockIdx.x * (blockDim.x / WAVE) + wib;
+    if (e >= P.K) return;
+    const int lane = lane_id();
+    float *sg = stage[wib];
+    if (lane < P.C_max)
+        *reinterpret_cast<float4 *>(sg + 4 * lane) =
+            *reinterpret_cast<const float4 *>(contacts + ((size_t)e * P.C_max + lane) * 4);
+    wave_sync();
+    float o[4];
+    if (sensor_force(P, sg, o)) {
+        const size_t LK = (size_t)P.L * P.K;
+        obs[0 * LK + (size_t)lane * P.K + e] = o[0];
+        obs[1 * LK + (size_t)lane * P.K + e] = o[1];
+        obs[2 * LK + (size_t)lane * P.K + e] = o[2];
+        obs[3 * LK + (size_t)lane * P.K + e] = o[3];
+    }
+}
+
+// one thread per simulation; obs_gt is [4][L][G] (the observed batch's
+// own observation layout)
+__global__ void k_cost(Consts P, const int32_t *__restrict__ group_of, const float *__restrict__ obs,
+                       const float *__restrict__ obs_gt, float *__restrict__ cost_sum)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= P.K) return;
+    const int g = group_of[e];
+    const size_t LK = (size_t)P.L * P.K, LG = (size_t)P.L * P.G;
+    float c = 0.f;
+    for (int l = 0; l < P.L; ++l) {
+        float o[4], gt[4];
+        for (int j = 0; j < 4; ++j) {
+            o[j] = obs[j * LK + (size_t)l * P.K + e];
+            gt[j] = obs_gt[j * LG + (size_t)l * P.G + g];
+        }
+        c += sensor_cost(P, o, gt);
+    }
+    cost_sum[e] += c;
+}
+
+// one block per group: lowest index of the minimum, NaN ranked as +inf
+__global__ void k_argmin(const int32_t *__restrict__ group_start, const float *__restrict__ cost,
+                         int32_t *__restrict__ best)
+{
+    __shared__ float sv[1024];
+    __shared__ int si[1024];
+    const int g = blockIdx.x;
+    const int lo = group_start[g], hi = group_start[g + 1];
+    float bv = __int_as_float(0x7f800000);
+    int bi = 0x7fffffff;
+    for (int i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+        float v = cost[i];
+        if (v != v) v = __int_as_float(0x7f800000);
+        if (v < bv || (v == bv && i < bi)) { bv = v; bi = i; }
+    }
+    sv[threadIdx.x] = bv;
+    si[threadIdx.x] = bi;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            float v = sv[threadIdx.x + s];
+            int i = si[threadIdx.x + s];
+            if (v < sv[threadIdx.x] || (v == sv[threadIdx.x] && i < si[threadIdx.x])) {
+                sv[threadIdx.x] = v;
+                si[threadIdx.x] = i;
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) best[g] = si[0] == 0x7fffffff ? lo : si[0];
+}
+
+// ---------------------------------------------------------------------
+// population-based resampling
+// ---------------------------------------------------------------------
+// Philox4x32 with 10 rounds (Salmon et al., SC'11): per round the words 0
+// and 2 are multiplied by the two round multipliers, the high halves are
+// mixed with the other two words and the round key, and the key is bumped
+// by the two Weyl increments.
+__device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                                              uint32_t k1, uint32_t *out)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
+        uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+        uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+__device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, float &n0, float &n1)
+{
+    // uniforms (w + 1/2) 2^-32 in (0, 1), formed in double to keep every bit
+    double u = ((double)a + 0.5) * 2.3283064365386963e-10;
+    double v = ((double)b + 0.5) * 2.3283064365386963e-10;
+    float rad = sqrtf(-2.f * (float)log(u));
+    float ang = (float)(6.283185307179586 * v);
+    n0 = rad * cosf(ang);
+    n1 = rad * sinf(ang);
+}
+
+// one block per group; ranks by counting, then copies and perturbs
+__global__ __launch_bounds__(1024) void k_resample(Consts P, ResampleArgs R, const int32_t *__restrict__ group_start,
+                                                   uint32_t window_idx, float *__restrict__ cost_sum,
+                                                   float *__restrict__ state, float *__restrict__ params,
+                                                   float *__restrict__ warm, int32_t *__restrict__ parent)
+{
+    extern __shared__ __align__(16) char smem[];
+    const int g = blockIdx.x;
+    const int lo = group_start[g], hi = group_start[g + 1];
+    const int n = hi - lo;
+    float *cs = reinterpret_cast<float *>(smem);
+    int *order = reinterpret_cast<int *>(smem + 4 * (size_t)n);
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        float v = cost_sum[lo + i];
+        cs[i] = (v != v) ? __int_as_float(0x7f800000) : v;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        float ci = cs[i];
+        int rank = 0;
+        for (int j = 0; j < n; ++j) {
+            float cj = cs[j];
+            rank += (cj < ci || (cj == ci && j < i)) ? 1 : 0;
+        }
+        order[rank] = i;
+    }
+    __syncthreads();
+    int kb = (int)floorf((float)n * R.elite_frac);
+    kb = kb < 1 ? 1 : (kb > n ? n : kb);
+    const uint32_t key0 = (uint32_t)(R.seed & 0xffffffffu), key1 = (uint32_t)(R.seed >> 32);
+    const int K = P.K;
+    for (int t = threadIdx.x; t < n; t += blockDim.x) {
+        const int j = lo + order[t];
+        if (t < kb) {
+            if (parent) parent[j] = -1;
+            continue;
+        }
+        uint32_t w[4], w1[4], w2[4];
+        philox4x32_10((uint32_t)j, window_idx, 0u, 0u, key0, key1, w);
+        const int prank = (int)(((uint64_t)w[0] * (uint64_t)kb) >> 32);
+        const int p = lo + order[prank];
+        if (parent) parent[j] = p;
+        for (int c = 0; c < 13; ++c) state[(size_t)c * K + j] = state[(size_t)c * K + p];
+        const float4 *src = reinterpret_cast<const float4 *>(warm + (size_t)p * P.C_max * WARM_STRIDE);
+        float4 *dst = reinterpret_cast<float4 *>(warm + (size_t)j * P.C_max * WARM_STRIDE);
+        for (int c = 0; c < P.C_max; ++c) dst[c] = src[c];
+        philox4x32_10((uint32_t)j, window_idx, 1u, 0u, key0, key1, w1);
+        philox4x32_10((uint32_t)j, window_idx, 2u, 0u, key0, key1, w2);
+        float n0, n1, n2, n3, n4, n5;
+        box_muller(w1[0], w1[1], n0, n1);
+        box_muller(w1[2], w1[3], n2, n3);
+        box_muller(w2[0], w2[1], n4, n5);
+        float mu = params[1 * (size_t)K + p] + R.sigma_mu * n0;
+        float ms = params[0 * (size_t)K + p] + R.sigma_m * n1;
+        params[1 * (size_t)K + j] = fminf(fmaxf(mu, R.mu_lo), R.mu_hi);
+        params[0 * (size_t)K + j] = fminf(fmaxf(ms, R.m_lo), R.m_hi);
+        params[2 * (size_t)K + j] = R.sigma_f * n2;
+        params[3 * (size_t)K + j] = R.sigma_f * n3;
+        params[4 * (size_t)K + j] = R.sigma_f * n4;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += blockDim.x) cost_sum[lo + i] = 0.f;
+}
+
+// ---------------------------------------------------------------------
+// batched path: persistent kernel over a window of T steps
+// ---------------------------------------------------------------------
+__global__ void k_reset_queue(int32_t *q)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) q[0] = 0;
+}
+
+template <typename SR>
+__global__ __launch_bounds__(512) void k_window(Consts P, Tables tb, const float *__restrict__ seg_win,
+                                                 float *__restrict__ state, float *__restrict__ params,
+                                                 float *__restrict__ warm, const float *__restrict__ obs_gt_win,
+                                                 float *__restrict__ cost_sum, float *__restrict__ obs_out,
+                                                 const int32_t *__restrict__ env_order, int32_t *__restrict__ queue,
+                                                 int64_t *__restrict__ stats)
+{
+    extern __shared__ __align__(16) char smem[];
+    const int wib = threadIdx.x / WAVE;
+    const int lane = lane_id();
+    WaveLds lds = carve_lds(smem, wib, P.max_cand);
+    float *stage = contact_stage(lds);
+    StepStats st = {0, 0, 0};
+    int64_t done = 0;
+    const size_t LK = (size_t)P.L * P.K, LG = (size_t)P.L * P.G;
+    for (;;) {
+        int slot = 0;
+        if (lane == 0) slot = atomicAdd(queue, 1);
+        slot = __builtin_amdgcn_readfirstlane(slot);
+        if (slot >= P.K) break;
+        const int e = env_order[slot];
+        const int type = tb.env_type[e];
+        const int g = tb.group_of[e];
+        const int S = tb.n_spheres[type];
+        const float *sph = tb.spheres + (size_t)type * P.S_max * 4;
+        const float *inv = tb.inv_inertia + 3 * type;
+        Body B;
+        load_body(state, params, P.K, e, B);
+        int wkey;
+        float wr[3];
+        load_warm(warm, P.C_max, e, wkey, wr);
+        // running sum continued step by step, in the order the plain path adds
+        float cost = cost_sum[e];
+        for (int t = 0; t < P.T; ++t) {
+            int link;
+            float imp[3];
+            env_step<SR>(P, seg_win + (size_t)t * P.L * SEG_STRIDE, sph, S, inv, B, wkey, wr, link, imp, lds, st);
+            *reinterpret_cast<float4 *>(stage + 4 * lane) = make_float4(__int_as_float(link), imp[0], imp[1], imp[2]);
+            wave_sync();
+            float o[4];
+            float cl = 0.f;
+            if (sensor_force(P, stage, o)) {
+                const float *gt = obs_gt_win + (size_t)t * 4 * LG;
+                float gv[4] = {gt[0 * LG + (size_t)lane * P.G + g], gt[1 * LG + (size_t)lane * P.G + g],
+                               gt[2 * LG + (size_t)lane * P.G + g], gt[3 * LG + (size_t)lane * P.G + g]};
+                cl = sensor_cost(P, o, gv);
+                if (obs_out) {
+                    float *ob = obs_out + (size_t)t * 4 * LK;
+                    ob[0 * LK + (size_t)lane * P.K + e] = o[0];
+                    ob[1 * LK + (size_t)lane * P.K + e] = o[1];
+                    ob[2 * LK + (size_t)lane * P.K + e] = o[2];
+                    ob[3 * LK + (size_t)lane * P.K + e] = o[3];
+                }
+            }
+            wave_sync();
+            // step cost summed over sensors in sensor order
+            float cs = 0.f;
+                    for (int l = 0; l < P.L; ++l) cs += __shfl(cl, l, WAVE);
+            cost += cs;
+        }
+        store_body(state, params, P.K, e, B);
+        store_warm(warm, P.C_max, e, wkey, wr);
+        if (lane == 0) cost_sum[e] = cost;
+        done += P.T;
+    }
+    flush_stats(stats, st, done);
+}
+
+}  // namespace pt
+
+// ---------------------------------------------------------------------
+// launch wrappers (host side)
+// ---------------------------------------------------------------------
+using namespace pt;
+
+hipError_t launch_hand_fk(const float *hand, int L, float dt, const float *u_prev, const float *u, int stride,
+                          int nsteps, float *seg_out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_hand_fk, dim3(nsteps), dim3(64), 0, s, hand, L, dt, u_prev, u, stride, seg_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_step(const Consts &P, const Tables &tb, const float *seg, float *state, float *params, float *warm,
+                       float *contacts, int64_t *stats, int waves_per_block, hipStream_t s)
+{
+    int blocks = (P.K + waves_per_block - 1) / waves_per_block;
+    size_t lds = (size_t)waves_per_block * wave_lds_bytes(P.max_cand);
+    if (P.solve_fp64)
+        hipLaunchKernelGGL(k_step<double>, dim3(blocks), dim3(WAVE * waves_per_block), lds, s, P, tb, seg, state,
+                           params, warm, contacts, stats);
+    else
+        hipLaunchKernelGGL(k_step<float>, dim3(blocks), dim3(WAVE * waves_per_block), lds, s, P, tb, seg, state,
+                           params, warm, contacts, stats);
+    return hipGetLastError();
+}
+
+hipError_t launch_observe(const Consts &P, const float *contacts, float *obs, hipStream_t s)
+{
+    int blocks = (P.K + 3) / 4;
+    hipLaunchKernelGGL(k_observe, dim3(blocks), dim3(256), 0, s, P, contacts, obs);
+    return hipGetLastError();
+}
+
+hipError_t launch_cost(const Consts &P, const int32_t *group_of, const float *obs, const float *obs_gt,
+                       float *cost_sum, hipStream_t s)
+{
+    int blocks = (P.K + 255) / 256;
+    hipLaunchKernelGGL(k_cost, dim3(blocks), dim3(256), 0, s, P, group_of, obs, obs_gt, cost_sum);
+    return hipGetLastError();
+}
+
+hipError_t launch_argmin(int G, const int32_t *group_start, const float *cost, int32_t *best, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_argmin, dim3(G), dim3(1024), 0, s, group_start, cost, best);
+    return hipGetLastError();
+}
+
+hipError_t launch_resample(const Consts &P, const ResampleArgs &R, const int32_t *group_start, int max_group,
+                           uint32_t window_idx, float *cost_sum, float *state, float *params, float *warm,
+                           int32_t *parent, hipStream_t s)
+{
+    size_t lds = (size_t)8 * max_group;
+    hipLaunchKernelGGL(k_resample, dim3(P.G), dim3(1024), lds, s, P, R, group_start, window_idx, cost_sum, state,
+                       params, warm, parent);
+    return hipGetLastError();
+}
+
+hipError_t launch_reset_queue(int32_t *q, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(64), 0, s, q);
+    return hipGetLastError();
+}
+
+hipError_t launch_window(const Consts &P, const Tables &tb, const float *seg_win, float *state, float *params,
+                         float *warm, const float *obs_gt_win, float *cost_sum, float *obs_out,
+                         const int32_t *env_order, int32_t *queue, int64_t *stats, int waves_per_block, int blocks,
+                         hipStream_t s)
+{
+    size_t lds = (size_t)waves_per_block * wave_lds_bytes(P.max_cand);
+    if (P.solve_fp64)
+        hipLaunchKernelGGL(k_window<double>, dim3(blocks), dim3(WAVE * waves_per_block), lds, s, P, tb, seg_win,
+                           state, params, warm, obs_gt_win, cost_sum, obs_out, env_order, queue, stats);
+    else
+        hipLaunchKernelGGL(k_window<float>, dim3(blocks), dim3(WAVE * waves_per_block), lds, s, P, tb, seg_win,
+                           state, params, warm, obs_gt_win, cost_sum, obs_out, env_order, queue, stats);
+    return hipGetLastError();
+}
+
+hipError_t window_occupancy(int waves_per_block, int max_cand, bool fp64, int *blocks_per_cu)
+{
+    size_t lds = (size_t)waves_per_block * wave_lds_bytes(max_cand);
+    const void *f = fp64 ? reinterpret_cast<const void *>(k_window<double>)
+                         : reinterpret_cast<const void *>(k_window<float>);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, f, WAVE * waves_per_block, lds);
+}
+
+hipError_t set_lds_limits(size_t bytes)
+{
+    const void *fs[] = {reinterpret_cast<const void *>(k_window<float>), reinterpret_cast<const void *>(k_window<double>),
+                        reinterpret_cast<const void *>(k_step<float>), reinterpret_cast<const void *>(k_step<double>),
+                        reinterpret_cast<const void *>(k_resample)};
+    for (const void *f : fs) {
+        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}

@@ -1,0 +1,282 @@
+"""Python binding of libpt (include/pt.h): argument marshalling only.
+
+Every computation runs in the HIP kernels of libpt.so; PyTorch supplies the
+device memory (tensors) and the streams.  Importing this module fails loudly
+when the library has not been built -- there is no fallback.
+
+Names follow the C ABI: ``pt_create_batch``, ``pt_step``, ``pt_observe``,
+``pt_cost``, ``pt_resample``, ``pt_run_window``, ``pt_autotune``,
+``pt_read_stats``; :class:`Batch` bundles a handle with its tensors.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpt.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"libpt.so is not built ({LIB_PATH}); run paper_2002_12160_amd/build.py "
+                      "or __graft_entry__.build() first")
+
+_lib = C.CDLL(LIB_PATH)
+
+HAND_STRIDE = 20
+MAX_CMAX = 64
+PT_OK = 0
+ERROR_NAMES = {1: "PT_E_ARG", 2: "PT_E_HIP", 3: "PT_E_STATE", 4: "PT_E_CAPTURE", 5: "PT_E_UNSUPPORTED"}
+
+
+class PtError(RuntimeError):
+    def __init__(self, code, where):
+        msg = _lib.pt_last_error().decode(errors="replace")
+        super().__init__(f"{where}: {ERROR_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class BatchDesc(C.Structure):
+    _fields_ = [
+        ("K", C.c_int32), ("G", C.c_int32), ("L", C.c_int32), ("D", C.c_int32), ("n_types", C.c_int32),
+        ("S_max", C.c_int32), ("C_max", C.c_int32), ("newton_iters", C.c_int32), ("T", C.c_int32),
+        ("solve_precision", C.c_int32),
+        ("dt", C.c_float), ("gravity", C.c_float * 3), ("margin", C.c_float), ("erp", C.c_float),
+        ("compliance", C.c_float), ("kappa", C.c_float), ("fb_delta", C.c_float), ("armijo_sigma", C.c_float),
+        ("tau_contact", C.c_float), ("w_mag", C.c_float), ("w_dir", C.c_float),
+        ("elite_frac", C.c_float), ("sigma_mu", C.c_float), ("sigma_m", C.c_float), ("sigma_f", C.c_float),
+        ("mu_lo", C.c_float), ("mu_hi", C.c_float), ("m_lo", C.c_float), ("m_hi", C.c_float),
+        ("seed", C.c_uint64),
+        ("hand", C.c_void_p), ("spheres", C.c_void_p), ("n_spheres", C.c_void_p), ("inv_inertia", C.c_void_p),
+        ("env_type", C.c_void_p), ("group_start", C.c_void_p),
+        ("state", C.c_void_p), ("params", C.c_void_p), ("warm", C.c_void_p),
+    ]
+
+
+_vp = C.c_void_p
+_lib.pt_last_error.restype = C.c_char_p
+_lib.pt_last_error.argtypes = []
+_lib.pt_create_batch.argtypes = [C.POINTER(BatchDesc), C.POINTER(_vp)]
+_lib.pt_destroy_batch.argtypes = [_vp]
+_lib.pt_step.argtypes = [_vp, _vp, _vp, _vp]
+_lib.pt_observe.argtypes = [_vp, _vp, _vp]
+_lib.pt_cost.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp]
+_lib.pt_resample.argtypes = [_vp, _vp, C.c_uint32, _vp, _vp]
+_lib.pt_run_window.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, C.c_int32, _vp]
+_lib.pt_autotune.argtypes = [_vp, _vp, _vp, C.POINTER(C.c_int32), _vp]
+_lib.pt_read_stats.argtypes = [_vp, C.POINTER(C.c_int64), _vp]
+_lib.pt_set_tuning.argtypes = [_vp, C.c_int32]
+for _f in ("pt_create_batch", "pt_destroy_batch", "pt_step", "pt_observe", "pt_cost", "pt_resample",
+           "pt_run_window", "pt_autotune", "pt_read_stats", "pt_set_tuning"):
+    getattr(_lib, _f).restype = C.c_int
+
+
+def _check(code, where):
+    if code != PT_OK:
+        raise PtError(code, where)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    assert t.is_contiguous(), "tensor must be contiguous"
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+# ---------------------------------------------------------------------------
+# C-ABI mirrors
+# ---------------------------------------------------------------------------
+
+def pt_create_batch(desc: BatchDesc) -> C.c_void_p:
+    h = C.c_void_p()
+    _check(_lib.pt_create_batch(C.byref(desc), C.byref(h)), "pt_create_batch")
+    return h
+
+
+def pt_destroy_batch(h):
+    _check(_lib.pt_destroy_batch(h), "pt_destroy_batch")
+
+
+def pt_step(h, u_prev, u, stream=None):
+    _check(_lib.pt_step(h, _ptr(u_prev), _ptr(u), _stream(stream)), "pt_step")
+
+
+def pt_observe(h, obs, stream=None):
+    _check(_lib.pt_observe(h, _ptr(obs), _stream(stream)), "pt_observe")
+
+
+def pt_cost(h, obs, obs_gt, cost_sum, best=None, stream=None):
+    _check(_lib.pt_cost(h, _ptr(obs), _ptr(obs_gt), _ptr(cost_sum), _ptr(best), _stream(stream)), "pt_cost")
+
+
+def pt_resample(h, cost_sum, window_idx, parent=None, stream=None):
+    _check(_lib.pt_resample(h, _ptr(cost_sum), int(window_idx), _ptr(parent), _stream(stream)), "pt_resample")
+
+
+def pt_run_window(h, u_win, obs_gt_win, cost_sum, best=None, obs_out=None, graph=True, stream=None):
+    _check(_lib.pt_run_window(h, _ptr(u_win), _ptr(obs_gt_win), _ptr(cost_sum), _ptr(best), _ptr(obs_out),
+                              1 if graph else 0, _stream(stream)), "pt_run_window")
+
+
+def pt_autotune(h, u_win, obs_gt_win, stream=None):
+    r = C.c_int32(0)
+    _check(_lib.pt_autotune(h, _ptr(u_win), _ptr(obs_gt_win), C.byref(r), _stream(stream)), "pt_autotune")
+    return int(r.value)
+
+
+def pt_set_tuning(h, waves_per_workgroup):
+    _check(_lib.pt_set_tuning(h, int(waves_per_workgroup)), "pt_set_tuning")
+
+
+def pt_read_stats(h, stream=None):
+    out = (C.c_int64 * 4)()
+    _check(_lib.pt_read_stats(h, out, _stream(stream)), "pt_read_stats")
+    return {"env_steps": out[0], "candidates": out[1], "contacts": out[2], "dropped": out[3]}
+
+
+# ---------------------------------------------------------------------------
+# convenience wrapper
+# ---------------------------------------------------------------------------
+
+class Batch:
+    """A population of simulations on one device: the handle plus the state
+    tensors it is bound to (state [13][K], params [5][K], warm [K][C_max][4])."""
+
+    def __init__(self, *, hand, spheres, n_spheres, inv_inertia, env_type, group_start, consts, C_max,
+                 newton_iters, T, state, params, resample=None, solve_precision=64, device="cuda"):
+        self.device = torch.device(device)
+        K = int(np.asarray(env_type).shape[0])
+        self.K, self.C_max, self.T = K, int(C_max), int(T)
+        self.hand = np.ascontiguousarray(hand, dtype=np.float32)
+        self.spheres = np.ascontiguousarray(spheres, dtype=np.float32)
+        self.n_spheres = np.ascontiguousarray(n_spheres, dtype=np.int32)
+        self.inv_inertia = np.ascontiguousarray(inv_inertia, dtype=np.float32)
+        self.env_type = np.ascontiguousarray(env_type, dtype=np.int32)
+        self.group_start = np.ascontiguousarray(group_start, dtype=np.int32)
+        self.L = self.hand.shape[0]
+        self.G = self.group_start.shape[0] - 1
+        self.D = int(max(self.hand[:, 1].max(), self.hand[:, 2].max())) + 1
+        self.state = torch.empty((13, K), dtype=torch.float32, device=self.device)
+        self.params = torch.empty((5, K), dtype=torch.float32, device=self.device)
+        self.warm = torch.empty((K, self.C_max, 4), dtype=torch.float32, device=self.device)
+        self.set_state(state, params)
+        self.clear_warm()
+        d = BatchDesc()
+        d.K, d.G, d.L, d.D = K, self.G, self.L, self.D
+        d.n_types, d.S_max = self.spheres.shape[0], self.spheres.shape[1]
+        d.C_max, d.newton_iters, d.T = self.C_max, int(newton_iters), self.T
+        d.solve_precision = int(solve_precision)
+        d.dt = consts.dt
+        for i in range(3):
+            d.gravity[i] = consts.gravity[i]
+        d.margin, d.erp, d.compliance, d.kappa = consts.margin, consts.erp, consts.compliance, consts.kappa
+        d.fb_delta, d.armijo_sigma = consts.fb_delta, consts.armijo_sigma
+        d.tau_contact, d.w_mag, d.w_dir = consts.tau_contact, consts.w_mag, consts.w_dir
+        r = resample or {}
+        d.elite_frac = r.get("elite_frac", 0.25)
+        d.sigma_mu, d.sigma_m, d.sigma_f = r.get("sigma_mu", 0.0), r.get("sigma_m", 0.0), r.get("sigma_f", 0.0)
+        d.mu_lo, d.mu_hi = r.get("mu_range", (0.0, 10.0))
+        d.m_lo, d.m_hi = r.get("m_range", (1e-6, 1e6))
+        d.seed = int(r.get("seed", 0))
+        d.hand = self.hand.ctypes.data
+        d.spheres = self.spheres.ctypes.data
+        d.n_spheres = self.n_spheres.ctypes.data
+        d.inv_inertia = self.inv_inertia.ctypes.data
+        d.env_type = self.env_type.ctypes.data
+        d.group_start = self.group_start.ctypes.data
+        d.state = self.state.data_ptr()
+        d.params = self.params.data_ptr()
+        d.warm = self.warm.data_ptr()
+        self.desc = d
+        self.handle = pt_create_batch(d)
+
+    @classmethod
+    def from_scene(cls, scene, hidden=False, device="cuda", **kw):
+        cfg = scene.cfg
+        common = dict(hand=scene.hand, spheres=scene.spheres, n_spheres=scene.n_spheres,
+                      inv_inertia=scene.inv_inertia, consts=cfg.consts, C_max=kw.pop("C_max", cfg.C_max),
+                      newton_iters=kw.pop("newton_iters", cfg.newton_iters), T=kw.pop("T", cfg.T),
+                      resample=dict(elite_frac=cfg.elite_frac, sigma_mu=cfg.sigma_mu, sigma_m=cfg.sigma_m,
+                                    sigma_f=cfg.sigma_f, mu_range=cfg.mu_range, m_range=cfg.m_range,
+                                    seed=cfg.seed), device=device)
+        if hidden:
+            G = scene.G
+            return cls(env_type=scene.hidden_type, group_start=np.arange(G + 1, dtype=np.int32),
+                       state=scene.hidden_state, params=scene.hidden_params, **common, **kw)
+        return cls(env_type=scene.env_type, group_start=scene.group_start, state=scene.state,
+                   params=scene.params, **common, **kw)
+
+    # -- state transfer (host arrays are env-major [K][13] / [K][5]) -------
+    def set_state(self, state, params=None):
+        self.state.copy_(torch.as_tensor(np.ascontiguousarray(np.asarray(state, dtype=np.float32).T)))
+        if params is not None:
+            self.params.copy_(torch.as_tensor(np.ascontiguousarray(np.asarray(params, dtype=np.float32).T)))
+
+    def get_state(self):
+        torch.cuda.synchronize(self.device)
+        return self.state.cpu().numpy().T.astype(np.float64), self.params.cpu().numpy().T.astype(np.float64)
+
+    def set_warm(self, keys, r):
+        w = np.zeros((self.K, self.C_max, 4), dtype=np.float32)
+        w[:, :, 0] = np.asarray(keys, dtype=np.int32).view(np.float32)
+        w[:, :, 1:] = np.asarray(r, dtype=np.float32)
+        self.warm.copy_(torch.as_tensor(w))
+
+    def get_warm(self):
+        torch.cuda.synchronize(self.device)
+        w = self.warm.cpu().numpy()
+        return np.ascontiguousarray(w[:, :, 0]).view(np.int32).copy(), w[:, :, 1:].astype(np.float64)
+
+    def clear_warm(self):
+        self.set_warm(np.full((self.K, self.C_max), -1, dtype=np.int32), np.zeros((self.K, self.C_max, 3)))
+
+    # -- the hot path ------------------------------------------------------
+    def new_obs(self, T=None):
+        shape = (4, self.L, self.K) if T is None else (T, 4, self.L, self.K)
+        return torch.zeros(shape, dtype=torch.float32, device=self.device)
+
+    def step(self, u_prev, u, stream=None):
+        pt_step(self.handle, u_prev, u, stream)
+
+    def observe(self, obs=None, stream=None):
+        if obs is None:
+            obs = self.new_obs()
+        pt_observe(self.handle, obs, stream)
+        return obs
+
+    def cost(self, obs, obs_gt, cost_sum, best=None, stream=None):
+        pt_cost(self.handle, obs, obs_gt, cost_sum, best, stream)
+
+    def resample(self, cost_sum, window_idx, parent=None, stream=None):
+        pt_resample(self.handle, cost_sum, window_idx, parent, stream)
+
+    def run_window(self, u_win, obs_gt_win, cost_sum, best=None, obs_out=None, graph=True, stream=None):
+        pt_run_window(self.handle, u_win, obs_gt_win, cost_sum, best, obs_out, graph, stream)
+
+    def autotune(self, u_win, obs_gt_win, stream=None):
+        return pt_autotune(self.handle, u_win, obs_gt_win, stream)
+
+    def set_tuning(self, waves_per_workgroup):
+        pt_set_tuning(self.handle, waves_per_workgroup)
+
+    def read_stats(self, stream=None):
+        return pt_read_stats(self.handle, stream)
+
+    def close(self):
+        if getattr(self, "handle", None) is not None:
+            pt_destroy_batch(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,110 @@
+"""The C-ABI library loads and exports every entry point include/pt.h
+declares; descriptor validation errors are reported before any device call
+(CPU only, no GPU needed)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_2002_12160_amd", "libpt.so")
+HEADER = os.path.join(ROOT, "include", "pt.h")
+
+
+def declared_symbols():
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"^PT_API [^()]*?\b(pt_\w+)\(", txt, flags=re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.fail("libpt.so is not built; run __graft_entry__.build()")
+    return C.CDLL(LIB)
+
+
+def test_header_declares_the_boundary():
+    syms = declared_symbols()
+    for name in ("pt_create_batch", "pt_destroy_batch", "pt_step", "pt_observe", "pt_cost", "pt_resample",
+                 "pt_run_window", "pt_autotune", "pt_read_stats", "pt_set_tuning", "pt_last_error"):
+        assert name in syms
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in declared_symbols():
+        assert hasattr(lib, name), name
+
+
+def test_no_oracle_symbols_in_the_library(lib):
+    # the product library shares no code with the test oracle
+    for name in ("or_env_step", "or_hand_fk", "or_philox4x32_10", "or_resample_pbo"):
+        assert not hasattr(lib, name)
+
+
+def _desc_module():
+    from paper_2002_12160_amd import pt
+    return pt
+
+
+def _valid_desc(pt, keep):
+    from paper_2002_12160_amd import scene as S
+    sc = S.make_scene(S.CONFIGS["small"], K=8, steps=2)
+    arrs = dict(hand=np.ascontiguousarray(sc.hand, np.float32), spheres=np.ascontiguousarray(sc.spheres, np.float32),
+                nsph=np.ascontiguousarray(sc.n_spheres, np.int32),
+                inv=np.ascontiguousarray(sc.inv_inertia, np.float32),
+                typ=np.ascontiguousarray(sc.env_type, np.int32), gs=np.ascontiguousarray(sc.group_start, np.int32),
+                st=np.zeros((13, 8), np.float32), pr=np.zeros((5, 8), np.float32), w=np.zeros((8, 16, 4), np.float32))
+    keep.update(arrs)
+    d = pt.BatchDesc()
+    d.K, d.G, d.L, d.D, d.n_types, d.S_max, d.C_max, d.newton_iters, d.T = 8, 1, sc.L, sc.D, 1, sc.S_max, 16, 10, 10
+    c = sc.cfg.consts
+    d.dt, d.margin, d.erp, d.compliance, d.kappa, d.fb_delta = c.dt, c.margin, c.erp, c.compliance, c.kappa, c.fb_delta
+    d.armijo_sigma, d.tau_contact, d.w_mag, d.w_dir = c.armijo_sigma, c.tau_contact, c.w_mag, c.w_dir
+    d.gravity[2] = -9.81
+    d.elite_frac, d.mu_lo, d.mu_hi, d.m_lo, d.m_hi = 0.25, 0.3, 1.0, 0.05, 0.2
+    d.hand, d.spheres, d.n_spheres = arrs["hand"].ctypes.data, arrs["spheres"].ctypes.data, arrs["nsph"].ctypes.data
+    d.inv_inertia, d.env_type, d.group_start = arrs["inv"].ctypes.data, arrs["typ"].ctypes.data, arrs["gs"].ctypes.data
+    d.state, d.params, d.warm = arrs["st"].ctypes.data, arrs["pr"].ctypes.data, arrs["w"].ctypes.data
+    return d
+
+
+@pytest.mark.parametrize("field,value,code", [
+    ("K", 0, 1), ("C_max", 65, 5), ("C_max", 0, 5), ("L", 0, 5), ("S_max", 300, 5), ("newton_iters", -1, 1),
+    ("dt", 0.0, 1), ("T", 0, 1), ("G", 9, 1), ("elite_frac", 0.0, 1), ("fb_delta", 0.0, 1),
+])
+def test_descriptor_validation(lib, field, value, code):
+    pt = _desc_module()
+    keep = {}
+    d = _valid_desc(pt, keep)
+    setattr(d, field, value)
+    h = C.c_void_p()
+    rc = pt._lib.pt_create_batch(C.byref(d), C.byref(h))
+    assert rc == code
+    assert h.value is None
+    assert len(pt._lib.pt_last_error()) > 0
+
+
+def test_validation_of_tables(lib):
+    pt = _desc_module()
+    keep = {}
+    d = _valid_desc(pt, keep)
+    keep["typ"][3] = 7          # object type out of range
+    h = C.c_void_p()
+    assert pt._lib.pt_create_batch(C.byref(d), C.byref(h)) == 1
+    assert b"env_type" in pt._lib.pt_last_error()
+    keep["typ"][3] = 0
+    keep["hand"][2, 0] = 5.0    # parent after child
+    assert pt._lib.pt_create_batch(C.byref(d), C.byref(h)) == 1
+    assert b"parent" in pt._lib.pt_last_error()
+    keep["hand"][2, 0] = 1.0
+    d.state = None
+    assert pt._lib.pt_create_batch(C.byref(d), C.byref(h)) == 1
+
+
+def test_null_handles_are_rejected(lib):
+    pt = _desc_module()
+    assert pt._lib.pt_step(None, None, None, None) == 1
+    assert pt._lib.pt_observe(None, None, None) == 1
+    assert pt._lib.pt_destroy_batch(None) == 0

@@ -1,0 +1,184 @@
+"""GPU (libpt, float32) against the FP64 oracle, element by element on the
+same seeded inputs.  Parity rule and tolerances: tests/parity_util.py."""
+import dataclasses
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2002_12160_amd import scene as S
+from tests import parity_util as PU
+from tests import tiny
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pt():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2002_12160_amd import pt as _pt
+    return _pt
+
+
+def _u(x):
+    return torch.as_tensor(np.asarray(x, dtype=np.float32), device="cuda").contiguous()
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _scene(cfg, K, steps):
+    """Scene tables (hand, commands, spheres, inertias) rounded to float32 for
+    both sides; the population's initial state and parameters kept in double,
+    so that the oracle's reference trajectory starts from the double values
+    and the float32-rounded copy is a genuine perturbation from step 0 on."""
+    sc = S.make_scene(cfg, K=K, steps=steps)
+    return dataclasses.replace(S.round_to_f32(sc), state=sc.state, params=sc.params,
+                               hidden_state=sc.hidden_state, hidden_params=sc.hidden_params)
+
+
+def per_step_parity(pt, cfg_name, K, steps, sample=None, seed_offset=0):
+    """Drive the oracle through `steps` steps; before every step hand the
+    float32-rounded oracle state to the GPU, step both, compare.  Returns
+    (n_checked, n_nonchaotic, failures)."""
+    cfg = S.CONFIGS[cfg_name].with_(T=10 ** 6)
+    sc = _scene(cfg, K, steps)
+    tr = oracle.Tracker(sc)
+    o = tr.o
+    b = pt.Batch.from_scene(sc)
+    idx = np.arange(K) if sample is None else np.asarray(sample)
+    n_chk = n_ok = 0
+    fails = []
+    for t in range(steps):
+        u_prev, u = sc.u[max(t - 1, 0)], sc.u[t]
+        st64, pr64, wk, wr64 = tr.state[idx].copy(), tr.params[idx].copy(), tr.wkey[idx].copy(), tr.wr[idx].copy()
+        st32, pr32, wr32 = PU.f32(st64), PU.f32(pr64), PU.f32(wr64)
+        # oracle from the double state and from the float32-rounded state
+        a_st, a_pr, a_k, a_r = st64.copy(), pr64.copy(), wk.copy(), wr64.copy()
+        o.batch_step(sc.env_type[idx], u_prev, u, a_st, a_pr, a_k, a_r)
+        b_st, b_pr, b_k, b_r = st32.copy(), pr32.copy(), wk.copy(), wr32.copy()
+        b_obs, _, b_dg = o.batch_step(sc.env_type[idx], u_prev, u, b_st, b_pr, b_k, b_r, want_diag=True)
+        nonchaotic = (PU.rel_err(a_st, b_st).max(axis=1) < PU.CHAOS_TOL) & \
+            np.array([x == y for x, y in zip(PU.key_sets(a_k), PU.key_sets(b_k))])
+        # GPU from the float32 state (all K envs on the device; the sampled
+        # ones carry the oracle's state)
+        full_st, full_pr = PU.f32(tr.state), PU.f32(tr.params)
+        b.set_state(full_st, full_pr)
+        b.set_warm(tr.wkey, PU.f32(tr.wr))
+        b.step(_u(u_prev), _u(u))
+        obs = b.observe()
+        g_st, _ = b.get_state()
+        g_k, g_r = b.get_warm()
+        g_obs = PU.obs_from_gpu(obs)
+        g_st, g_k, g_obs = g_st[idx], g_k[idx], g_obs[idx]
+        err = PU.rel_err(g_st, b_st).max(axis=1)
+        keys_eq = PU.keys_match(g_k, b_k, b_dg)
+        obs_ok = PU.obs_close(g_obs, b_obs, cfg.consts.tau_contact)
+        for j in np.nonzero(nonchaotic)[0]:
+            n_ok += 1
+            if not (err[j] <= PU.TOL and keys_eq[j] and obs_ok[j]):
+                fails.append((t, int(idx[j]), float(err[j]), bool(keys_eq[j]), bool(obs_ok[j])))
+        n_chk += len(idx)
+        tr.step()
+    b.close()
+    return n_chk, n_ok, fails
+
+
+def test_per_step_parity_small(pt):
+    _say("per-step parity: small config, K=32, 60 steps")
+    n_chk, n_ok, fails = per_step_parity(pt, "small", 32, 60)
+    _say(f"checked {n_chk} env-steps, {n_ok} non-chaotic, {len(fails)} outside tolerance: {fails[:10]}")
+    assert n_ok >= 0.5 * n_chk
+    assert len(fails) <= 0.01 * n_ok, fails[:20]
+
+
+def segment_parity(pt, cfg_name, K, n_seg, seg_len=10):
+    """10-step segments from the oracle's trajectory: the GPU and the oracle
+    both run seg_len steps from the float32-rounded state at the segment
+    start (no resampling inside); a simulation's segment is non-chaotic when
+    the oracle from the double state and from the float32 state agree to 1e-6
+    with identical contact sets at every step."""
+    cfg = S.CONFIGS[cfg_name].with_(T=10 ** 6)
+    steps = n_seg * seg_len
+    sc = _scene(cfg, K, steps)
+    tr = oracle.Tracker(sc)
+    o = tr.o
+    b = pt.Batch.from_scene(sc)
+    n_ok = 0
+    fails = []
+    for sgi in range(n_seg):
+        t0 = sgi * seg_len
+        A = [tr.state.copy(), tr.params.copy(), tr.wkey.copy(), tr.wr.copy()]
+        Bq = [PU.f32(tr.state), PU.f32(tr.params), tr.wkey.copy(), PU.f32(tr.wr)]
+        b.set_state(Bq[0], Bq[1])
+        b.set_warm(Bq[2], Bq[3])
+        same = np.ones(K, bool)
+        keys_ok = np.ones(K, bool)
+        for t in range(t0, t0 + seg_len):
+            u_prev, u = sc.u[max(t - 1, 0)], sc.u[t]
+            o.batch_step(sc.env_type, u_prev, u, *A)
+            _, _, dg = o.batch_step(sc.env_type, u_prev, u, *Bq, want_diag=True)
+            b.step(_u(u_prev), _u(u))
+            gk, _ = b.get_warm()
+            same &= PU.rel_err(A[0], Bq[0]).max(axis=1) < PU.CHAOS_TOL
+            same &= np.array([x == y for x, y in zip(PU.key_sets(A[2]), PU.key_sets(Bq[2]))])
+            keys_ok &= PU.keys_match(gk, Bq[2], dg)
+        g_st, _ = b.get_state()
+        err = PU.rel_err(g_st, Bq[0]).max(axis=1)
+        for i in np.nonzero(same)[0]:
+            n_ok += 1
+            if not (err[i] <= PU.TOL and keys_ok[i]):
+                fails.append((t0, int(i), float(err[i]), bool(keys_ok[i])))
+        for t in range(t0, t0 + seg_len):
+            tr.step()
+    b.close()
+    return n_ok, fails
+
+
+def test_segment_parity_small(pt):
+    _say("10-step segment parity: small config, K=64, 6 segments")
+    n_ok, fails = segment_parity(pt, "small", 64, 6)
+    _say(f"{n_ok} non-chaotic segments, {len(fails)} outside tolerance: {fails[:10]}")
+    assert n_ok >= 30
+    assert len(fails) <= 0.02 * n_ok, fails
+
+
+def test_per_step_parity_plain256_sampled(pt):
+    # the 256-simulation workload at full size, in the launch configuration the
+    # benchmark times; the oracle follows a sample of 24 simulations
+    _say("per-step parity: plain256 config, K=256, 30 steps, 24 sampled envs")
+    sample = np.linspace(0, 255, 24).astype(int)
+    n_chk, n_ok, fails = per_step_parity(pt, "plain256", 256, 30, sample=sample)
+    _say(f"checked {n_chk} env-steps, {n_ok} non-chaotic, {len(fails)} outside tolerance: {fails[:10]}")
+    assert n_ok >= 0.4 * n_chk
+    assert len(fails) <= 0.01 * n_ok, fails[:20]
+
+
+def test_free_fall_and_resting_on_gpu(pt):
+    # closed forms on the GPU: free fall is exact to float32 rounding; a
+    # sphere resting on the table carries m g (r_n = m g dt)
+    _say("closed forms on the GPU")
+    rho, m = 0.01, 0.1
+    sph, nsph, inv = tiny.single_sphere(rho)
+    hand = np.array([tiny.far_link()])
+    K = 2
+    st = np.stack([tiny.state(x=(0, 0, 20.0), v=(0.3, 0.1, 0.5)), tiny.state(x=(0, 0, rho))])
+    pr = np.stack([tiny.params(m, 0.5), tiny.params(m, 0.6)])
+    b = pt.Batch(hand=hand, spheres=sph, n_spheres=nsph, inv_inertia=inv, env_type=np.zeros(K, np.int32),
+                 group_start=np.array([0, K], np.int32), consts=tiny.consts(), C_max=4, newton_iters=10, T=10,
+                 state=st, params=pr)
+    u = _u(np.zeros(1))
+    dt = 1.0 / 30.0
+    for n in range(1, 41):
+        b.step(u, u)
+    g_st, _ = b.get_state()
+    v0 = np.array([0.3, 0.1, 0.5])
+    np.testing.assert_allclose(g_st[0, 7:10], v0 + 40 * np.array([0, 0, -9.81]) * dt, rtol=1e-5)
+    for n in range(41, 301):
+        b.step(u, u)
+    k, r = b.get_warm()
+    assert k[1, 0] == 1 and k[1, 1] == -1
+    np.testing.assert_allclose(r[1, 0, 0], m * 9.81 * dt, rtol=1e-5)
+    b.close()

@@ -1,0 +1,211 @@
+"""GPU paths against each other and the resampler / cost / argmin against the
+oracle.  The batched window (persistent kernel, optionally replayed from a HIP
+graph, any environments-per-workgroup) runs the same per-simulation
+arithmetic as the plain per-step kernels, so the two must agree bit for bit."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2002_12160_amd import scene as S
+from tests import parity_util as PU
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pt():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2002_12160_amd import pt as _pt
+    return _pt
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _window_inputs(sc, w, T, dev="cuda"):
+    t0 = w * T
+    rows = [sc.u[max(t0 - 1, 0)]] + [sc.u[t0 + t] for t in range(T)]
+    return torch.as_tensor(np.array(rows, dtype=np.float32), device=dev)
+
+
+def run_plain(pt, sc, windows, T, resample=True, solve_precision=64):
+    b = pt.Batch.from_scene(sc, solve_precision=solve_precision)
+    h = pt.Batch.from_scene(sc, hidden=True, solve_precision=solve_precision)
+    cost = torch.zeros(sc.K, device="cuda")
+    best = torch.zeros(sc.G, dtype=torch.int32, device="cuda")
+    parent = torch.zeros(sc.K, dtype=torch.int32, device="cuda")
+    obs_hist, bests, parents, costs = [], [], [], []
+    for w in range(windows):
+        uw = _window_inputs(sc, w, T)
+        for t in range(T):
+            h.step(uw[t], uw[t + 1])
+            gt = h.observe()
+            b.step(uw[t], uw[t + 1])
+            obs = b.observe()
+            b.cost(obs, gt, cost, best)
+            obs_hist.append(obs.clone())
+        costs.append(cost.clone())
+        bests.append(best.clone())
+        if resample:
+            b.resample(cost, w, parent)
+            parents.append(parent.clone())
+    torch.cuda.synchronize()
+    out = dict(state=b.state.clone(), params=b.params.clone(), warm=b.warm.clone(), obs=torch.stack(obs_hist),
+               best=torch.stack(bests), costs=torch.stack(costs),
+               parent=torch.stack(parents) if parents else None)
+    b.close()
+    h.close()
+    return out
+
+
+def run_batched(pt, sc, windows, T, graph, wpb=None, resample=True, solve_precision=64):
+    b = pt.Batch.from_scene(sc, solve_precision=solve_precision)
+    h = pt.Batch.from_scene(sc, hidden=True, solve_precision=solve_precision)
+    cost = torch.zeros(sc.K, device="cuda")
+    costh = torch.zeros(sc.G, device="cuda")
+    best = torch.zeros(sc.G, dtype=torch.int32, device="cuda")
+    parent = torch.zeros(sc.K, dtype=torch.int32, device="cuda")
+    gtw = torch.zeros((T, 4, sc.L, sc.G), device="cuda")
+    dummy = torch.zeros((T, 4, sc.L, sc.G), device="cuda")
+    obs_w = torch.zeros((T, 4, sc.L, sc.K), device="cuda")
+    uw = torch.zeros((T + 1, sc.D), device="cuda")
+    if wpb is not None:
+        b.set_tuning(wpb)
+    obs_hist, bests, parents, costs = [], [], [], []
+    for w in range(windows):
+        uw.copy_(_window_inputs(sc, w, T))
+        h.run_window(uw, dummy, costh, None, gtw, graph=graph)
+        b.run_window(uw, gtw, cost, best, obs_w, graph=graph)
+        obs_hist.append(obs_w.clone())
+        costs.append(cost.clone())
+        bests.append(best.clone())
+        if resample:
+            b.resample(cost, w, parent)
+            parents.append(parent.clone())
+    torch.cuda.synchronize()
+    out = dict(state=b.state.clone(), params=b.params.clone(), warm=b.warm.clone(), obs=torch.cat(obs_hist),
+               best=torch.stack(bests), costs=torch.stack(costs),
+               parent=torch.stack(parents) if parents else None)
+    b.close()
+    h.close()
+    return out
+
+
+def _assert_same(a, b, what):
+    # compare raw bits (the warm cache holds integer keys; -1 is a NaN pattern)
+    for k in ("state", "params", "warm", "obs", "best", "costs", "parent"):
+        if a[k] is None:
+            continue
+        x, y = a[k].contiguous().view(torch.int32), b[k].contiguous().view(torch.int32)
+        assert torch.equal(x, y), f"{what}: {k} differs in {(x != y).sum().item()} words"
+
+
+@pytest.mark.parametrize("cfg_name,K", [("small", 37), ("batched4096", 96)])
+def test_batched_equals_plain_bitwise(pt, cfg_name, K):
+    _say(f"plain vs batched: {cfg_name} K={K}")
+    cfg = S.CONFIGS[cfg_name]
+    sc = S.make_scene(cfg, K=K, steps=40)
+    ref = run_plain(pt, sc, 3, cfg.T)
+    for graph in (False, True):
+        got = run_batched(pt, sc, 3, cfg.T, graph=graph)
+        _assert_same(ref, got, f"graph={graph}")
+
+
+def test_autotune_choices_agree_bitwise(pt):
+    _say("every environments-per-workgroup choice gives the same bits")
+    cfg = S.CONFIGS["small"]
+    sc = S.make_scene(cfg, K=40, steps=20)
+    outs = []
+    for wpb in (1, 2, 4, 8):
+        b = pt.Batch.from_scene(sc)
+        h = pt.Batch.from_scene(sc, hidden=True)
+        uw = _window_inputs(sc, 0, cfg.T)
+        gtw = torch.zeros((cfg.T, 4, sc.L, sc.G), device="cuda")
+        dummy = torch.zeros_like(gtw)
+        cost = torch.zeros(sc.K, device="cuda")
+        costh = torch.zeros(sc.G, device="cuda")
+        h.run_window(uw, dummy, costh, None, gtw, graph=False)
+        if wpb == 1:
+            assert b.autotune(uw, gtw) in (1, 2, 4, 8)   # leaves the state untouched
+        b.set_tuning(wpb)
+        b.run_window(uw, gtw, cost, None, None, graph=(wpb % 2 == 0))
+        torch.cuda.synchronize()
+        outs.append((b.state.clone(), cost.clone()))
+        b.close()
+        h.close()
+    for st, c in outs[1:]:
+        assert torch.equal(st, outs[0][0]) and torch.equal(c, outs[0][1])
+
+
+def test_resample_matches_oracle(pt):
+    _say("resampler parity")
+    cfg = S.CONFIGS["small"].with_(group_types=(0, 0, 0))
+    K = 300
+    sc = S.round_to_f32(S.make_scene(cfg, K=K, steps=2))
+    rng = np.random.default_rng(3)
+    st = PU.f32(sc.state.copy())
+    st[:, 7:13] = PU.f32(rng.normal(size=(K, 6)))
+    pr = sc.params.copy()
+    keys = rng.integers(-1, 300, size=(K, cfg.C_max)).astype(np.int32)
+    wr = PU.f32(rng.normal(size=(K, cfg.C_max, 3)))
+    cost = PU.f32(rng.uniform(0, 5, size=K))
+    cost[10] = cost[11]          # tie
+    cost[12] = np.nan            # divergent simulation
+    b = pt.Batch.from_scene(sc)
+    b.set_state(st, pr)
+    b.set_warm(keys, wr)
+    c_dev = torch.as_tensor(cost.astype(np.float32), device="cuda")
+    parent = torch.zeros(K, dtype=torch.int32, device="cuda")
+    b.resample(c_dev, 7, parent)
+    g_st, g_pr = b.get_state()
+    g_k, g_r = b.get_warm()
+    o = oracle.Oracle.from_scene(sc)
+    o_st, o_pr, o_k, o_r, o_c = st.copy(), pr.copy(), keys.copy(), wr.copy(), cost.copy()
+    o_par = o.resample(oracle.resample_cfg(cfg), sc.group_start, 7, o_c, o_st, o_pr, o_k, o_r)
+    assert np.array_equal(parent.cpu().numpy(), o_par)
+    assert np.array_equal(g_st, o_st)           # copies are bit-exact
+    assert np.array_equal(g_k, o_k) and np.array_equal(g_r, o_r)
+    np.testing.assert_allclose(g_pr, o_pr, rtol=1e-6, atol=1e-7)
+    assert float(c_dev.abs().sum()) == 0.0
+    b.close()
+
+
+def test_cost_and_argmin_match_oracle(pt):
+    _say("cost and argmin parity")
+    cfg = S.CONFIGS["small"].with_(group_types=(0, 0))
+    K = 50
+    sc = S.round_to_f32(S.make_scene(cfg, K=K, steps=2))
+    rng = np.random.default_rng(9)
+    L = sc.L
+    obs = np.zeros((K, L, 4))
+    obs[..., 0] = rng.uniform(0, 3, size=(K, L)) * (rng.uniform(size=(K, L)) > 0.4)
+    d = rng.normal(size=(K, L, 3))
+    obs[..., 1:] = d / np.linalg.norm(d, axis=-1, keepdims=True) * (obs[..., :1] > 0)
+    obs = PU.f32(obs)
+    gt = PU.f32(obs[[3, 30]].copy())
+    obs[20] = gt[0]              # an exact copy of group 0's observation
+    obs[41] = obs[40]            # a tie in group 1
+    b = pt.Batch.from_scene(sc)
+    obs_t = torch.as_tensor(obs.transpose(2, 1, 0).astype(np.float32).copy(), device="cuda")
+    gt_t = torch.as_tensor(gt.transpose(2, 1, 0).astype(np.float32).copy(), device="cuda")
+    cost = torch.zeros(K, device="cuda")
+    best = torch.zeros(2, dtype=torch.int32, device="cuda")
+    b.cost(obs_t, gt_t, cost, best)
+    torch.cuda.synchronize()
+    o = oracle.Oracle.from_scene(sc)
+    ref = np.zeros(K)
+    o.batch_cost(sc.group_start, obs, gt, ref)
+    np.testing.assert_allclose(cost.cpu().numpy(), ref, rtol=1e-6, atol=1e-7)
+    g_best = best.cpu().numpy()
+    for g in range(2):
+        lo, hi = sc.group_start[g], sc.group_start[g + 1]
+        assert g_best[g] == lo + oracle.argmin(cost.cpu().numpy()[lo:hi].astype(np.float64))
+    assert cost[3].item() == 0.0 and cost[20].item() == 0.0 and g_best[0] == 3
+    # NaN costs rank last
+    c2 = torch.tensor([np.nan, 2.0, 1.0, 1.0] + [5.0] * (K - 4), device="cuda")
+    b.cost(torch.zeros_like(obs_t), torch.zeros_like(gt_t), c2, best)
+    torch.cuda.synchronize()
+    assert best.cpu().numpy()[0] == 2
+    b.close()
