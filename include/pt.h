@@ -178,14 +178,15 @@ PT_API pt_status pt_run_window(pt_batch b, const float *u_win, const float *obs_
                         int32_t *best, float *obs_out, int32_t graph, pt_stream s);
 
 /* Chooses the persistent kernel's environments per workgroup (waves per
- * workgroup, {1,2,4,8}) by timing windows on scratch copies of the state;
+ * workgroup, {1,2,4,8}; at most 4 with the float64 solve) by timing windows on scratch copies of the state;
  * the batch's own buffers are not modified.  Synchronises the stream.
  * result (host, may be NULL) receives the chosen value. */
 PT_API pt_status pt_autotune(pt_batch b, const float *u_win, const float *obs_gt_win, int32_t *result, pt_stream s);
 
 /* Sets the persistent kernel's environments per workgroup (1, 2, 4 or 8)
  * by hand instead of through pt_autotune.  PT_E_UNSUPPORTED if that many
- * simulations' LDS does not fit in one workgroup. */
+ * simulations' LDS does not fit in one workgroup, or above 4 with the
+ * float64 solve. */
 PT_API pt_status pt_set_tuning(pt_batch b, int32_t waves_per_workgroup);
 
 /* Reads the batch's cumulative counters (host out[4]): environment-steps,

@@ -127,6 +127,9 @@ pt_status validate(const pt_batch_desc *d)
 
 int round_up(int a, int b) { return (a + b - 1) / b * b; }
 
+// largest simulations-per-workgroup the step kernels are compiled for
+int max_wpb(const Consts &P) { return P.solve_fp64 ? 4 : 8; }
+
 }  // namespace
 
 extern "C" {
@@ -217,7 +220,7 @@ pt_status pt_create_batch(const pt_batch_desc *d, pt_batch *out)
     HIP_TRY_C(hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking));
     // environments per workgroup within the LDS budget (autotuned later)
     b->wpb = 4;
-    while (b->wpb > 1 && (size_t)b->wpb * wave_lds > 160 * 1024) b->wpb >>= 1;
+    while (b->wpb > 1 && ((size_t)b->wpb * wave_lds > 160 * 1024 || b->wpb > max_wpb(P))) b->wpb >>= 1;
     b->step_wpb = b->wpb;
 #undef HIP_TRY_C
     *out = b;
@@ -361,7 +364,7 @@ pt_status pt_autotune(pt_batch b, const float *u_win, const float *obs_gt_win, i
     float best_ms = 1e30f;
     pt_status rc = PT_OK;
     for (int wpb : {1, 2, 4, 8}) {
-        if ((size_t)wpb * wave_lds > 160 * 1024) continue;
+        if ((size_t)wpb * wave_lds > 160 * 1024 || wpb > max_wpb(P)) continue;
         float total = 0.f;
         for (int rep = 0; rep < 3 && rc == PT_OK; ++rep) {
             if (hipMemcpyAsync(ts, b->state, sizeof(float) * n_state, hipMemcpyDeviceToDevice, st) != hipSuccess ||
@@ -409,6 +412,8 @@ pt_status pt_set_tuning(pt_batch b, int32_t wpb)
     if (wpb != 1 && wpb != 2 && wpb != 4 && wpb != 8) return fail(PT_E_ARG, "waves per workgroup must be 1, 2, 4 or 8");
     if ((size_t)wpb * pt::wave_lds_bytes(b->P.max_cand) > 160 * 1024)
         return fail(PT_E_UNSUPPORTED, "%d simulations per workgroup exceed the LDS", wpb);
+    if (wpb > max_wpb(b->P))
+        return fail(PT_E_UNSUPPORTED, "at most %d simulations per workgroup with this solve precision", max_wpb(b->P));
     if (wpb != b->wpb && b->has_graph) {
         HIP_TRY(hipDeviceSynchronize());
         HIP_TRY(hipGraphExecDestroy(b->graph_exec));

@@ -65,24 +65,80 @@ __device__ __forceinline__ int mask_rank(uint64_t mask)
     return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
-// butterfly all-reduce over the 64 lanes; every lane gets the same bits
+// Cross-lane sums with DPP (data-parallel primitives: VALU lane moves, no LDS
+// round trip).  Prefix sums inside each 16-lane row (row_shr 1, 2, 4, 8),
+// then row 0's total is added into row 1 and row 2's into row 3
+// (row_bcast:15), then lane 31 into rows 2-3 (row_bcast:31); the total ends in
+// the last lane of the span and is broadcast with readlane, so every lane gets
+// the same bits.  `span` (16, 32 or 64, wave-uniform) is the number of lanes
+// that can hold non-zero values.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_f(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xf, true));
+}
+
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_f(double v)
+{
+    long long b = __double_as_longlong(v);
+    int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, ROW_MASK, 0xf, true);
+    int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROW_MASK, 0xf, true);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// readlane moves 32-bit integers: reinterpret, never convert
+__device__ __forceinline__ float bcast_lane(float v, int lane)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+__device__ __forceinline__ double bcast_lane(double v, int lane)
+{
+    long long b = __double_as_longlong(v);
+    int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), lane);
+    int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 template <typename T, int N>
-__device__ __forceinline__ void wave_sum(T (&v)[N])
+__device__ __forceinline__ void wave_sum(T (&v)[N], int span = 64)
 {
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
+    for (int i = 0; i < N; ++i) v[i] += dpp_f<0x111, 0xf>(v[i]);  // row_shr:1
 #pragma unroll
-        for (int i = 0; i < N; ++i) v[i] += __shfl_xor(v[i], off, WAVE);
+    for (int i = 0; i < N; ++i) v[i] += dpp_f<0x112, 0xf>(v[i]);  // row_shr:2
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] += dpp_f<0x114, 0xf>(v[i]);  // row_shr:4
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] += dpp_f<0x118, 0xf>(v[i]);  // row_shr:8
+    if (span <= 16) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) v[i] = bcast_lane(v[i], 15);
+        return;
     }
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] += dpp_f<0x142, 0xa>(v[i]);  // row_bcast:15 into rows 1, 3
+    if (span <= 32) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) v[i] = bcast_lane(v[i], 31);
+        return;
+    }
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] += dpp_f<0x143, 0xc>(v[i]);  // row_bcast:31 into rows 2, 3
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] = bcast_lane(v[i], 63);
 }
 
 template <typename T>
-__device__ __forceinline__ T wave_sum1(T a)
+__device__ __forceinline__ T wave_sum1(T a, int span = 64)
 {
     T v[1] = {a};
-    wave_sum<T, 1>(v);
+    wave_sum<T, 1>(v, span);
     return v[0];
 }
+
+// span of lanes holding the first n contacts
+__device__ __forceinline__ int lane_span(int n) { return n <= 16 ? 16 : (n <= 32 ? 32 : 64); }
 
 // ---------------------------------------------------------------------
 // small vector helpers
@@ -497,6 +553,7 @@ __device__ __forceinline__ void env_step(const Consts &P, const float *__restric
     SR IinvS[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) IinvS[i] = Iinv[i];
+    const int span = lane_span(C);
     // M^-1 J^T x summed over contacts, for an impulse x of this lane
     auto body_dv = [&](const SR *x, SR *dn) {
         SR f[3] = {F[0] * x[0] + F[3] * x[1] + F[6] * x[2], F[1] * x[0] + F[4] * x[1] + F[7] * x[2],
@@ -504,7 +561,7 @@ __device__ __forceinline__ void env_step(const Consts &P, const float *__restric
         SR tq[3];
         cross3(rho, f, tq);
         SR a6[6] = {f[0], f[1], f[2], tq[0], tq[1], tq[2]};
-        wave_sum<SR, 6>(a6);
+        wave_sum<SR, 6>(a6, span);
         dn[0] = a6[0] * imS; dn[1] = a6[1] * imS; dn[2] = a6[2] * imS;
         dn[3] = IinvS[0] * a6[3] + IinvS[1] * a6[4] + IinvS[2] * a6[5];
         dn[4] = IinvS[3] * a6[3] + IinvS[4] * a6[4] + IinvS[5] * a6[5];
@@ -588,7 +645,7 @@ __device__ __forceinline__ void env_step(const Consts &P, const float *__restric
 #pragma unroll
                 for (int i = 0; i < 43; ++i) acc[i] = SR(0);
             }
-            wave_sum<SR, 43>(acc);
+            wave_sum<SR, 43>(acc, span);
             const SR psi = acc[42];
             // (I + M^-1 A6) dnu = -M^-1 b6
             SR S6[36], rhs[6];
@@ -635,7 +692,7 @@ __device__ __forceinline__ void env_step(const Consts &P, const float *__restric
                 SR rt[3] = {r[0] + a * dr[0], r[1] + a * dr[1], r[2] + a * dr[2]};
                 SR ut[3] = {u[0] + a * du[0], u[1] + a * du[1], u[2] + a * du[2]};
                 SR ptr = act ? fb_merit(mu, kap, del, rt, ut) : SR(0);
-                ptr = wave_sum1(ptr);
+                ptr = wave_sum1(ptr, span);
                 if (ptr <= (SR(1) - SR(2) * SR(P.armijo_sigma) * a) * psi) { alpha = a; break; }
             }
             r[0] += alpha * dr[0]; r[1] += alpha * dr[1]; r[2] += alpha * dr[2];

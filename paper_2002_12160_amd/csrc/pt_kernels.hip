@@ -218,8 +218,14 @@ __device__ __forceinline__ float sensor_cost(const Consts &P, const float *o, co
 // ---------------------------------------------------------------------
 // plain path
 // ---------------------------------------------------------------------
+// float64 solves need more registers than a 512-thread block leaves a wave
 template <typename SR>
-__global__ __launch_bounds__(512) void k_step(Consts P, Tables tb, const float *__restrict__ seg,
+struct StepBounds {
+    static constexpr int threads = sizeof(SR) == 8 ? 256 : 512;
+};
+
+template <typename SR>
+__global__ __launch_bounds__(StepBounds<SR>::threads) void k_step(Consts P, Tables tb, const float *__restrict__ seg,
                                                float *__restrict__ state, float *__restrict__ params,
                                                float *__restrict__ warm, float *__restrict__ contacts,
                                                int64_t *__restrict__ stats)
@@ -274,25 +280,37 @@ __global__ __launch_bounds__(256) void k_observe(Consts P, const float *__restri
     }
 }
 
-// one thread per simulation; obs_gt is [4][L][G] (the observed batch's
-// own observation layout)
-__global__ void k_cost(Consts P, const int32_t *__restrict__ group_of, const float *__restrict__ obs,
-                       const float *__restrict__ obs_gt, float *__restrict__ cost_sum)
+// step cost of one simulation from its sensors' terms held one per lane
+// (lane l < L), summed in sensor order; shared by the plain and batched paths
+__device__ __forceinline__ float step_cost_wave(const Consts &P, float cl)
 {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    float cs = 0.f;
+    for (int l = 0; l < P.L; ++l) cs += bcast_lane(cl, l);
+    return cs;
+}
+
+// one wavefront per simulation, lanes over sensors; obs_gt is [4][L][G]
+// (the observed batch's own observation layout)
+__global__ __launch_bounds__(256) void k_cost(Consts P, const int32_t *__restrict__ group_of,
+                                              const float *__restrict__ obs, const float *__restrict__ obs_gt,
+                                              float *__restrict__ cost_sum)
+{
+    const int e = blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
     if (e >= P.K) return;
+    const int lane = lane_id();
     const int g = group_of[e];
     const size_t LK = (size_t)P.L * P.K, LG = (size_t)P.L * P.G;
-    float c = 0.f;
-    for (int l = 0; l < P.L; ++l) {
+    float cl = 0.f;
+    if (lane < P.L) {
         float o[4], gt[4];
         for (int j = 0; j < 4; ++j) {
-            o[j] = obs[j * LK + (size_t)l * P.K + e];
-            gt[j] = obs_gt[j * LG + (size_t)l * P.G + g];
+            o[j] = obs[j * LK + (size_t)lane * P.K + e];
+            gt[j] = obs_gt[j * LG + (size_t)lane * P.G + g];
         }
-        c += sensor_cost(P, o, gt);
+        cl = sensor_cost(P, o, gt);
     }
-    cost_sum[e] += c;
+    const float cs = step_cost_wave(P, cl);
+    if (lane == 0) cost_sum[e] += cs;
 }
 
 // one block per group: lowest index of the minimum, NaN ranked as +inf
@@ -433,7 +451,7 @@ __global__ void k_reset_queue(int32_t *q)
 }
 
 template <typename SR>
-__global__ __launch_bounds__(512) void k_window(Consts P, Tables tb, const float *__restrict__ seg_win,
+__global__ __launch_bounds__(StepBounds<SR>::threads) void k_window(Consts P, Tables tb, const float *__restrict__ seg_win,
                                                  float *__restrict__ state, float *__restrict__ params,
                                                  float *__restrict__ warm, const float *__restrict__ obs_gt_win,
                                                  float *__restrict__ cost_sum, float *__restrict__ obs_out,
@@ -490,7 +508,7 @@ __global__ __launch_bounds__(512) void k_window(Consts P, Tables tb, const float
             wave_sync();
             // step cost summed over sensors in sensor order
             float cs = 0.f;
-                    for (int l = 0; l < P.L; ++l) cs += __shfl(cl, l, WAVE);
+                    for (int l = 0; l < P.L; ++l) cs += bcast_lane(cl, l);
             cost += cs;
         }
         store_body(state, params, P.K, e, B);
@@ -539,7 +557,7 @@ hipError_t launch_observe(const Consts &P, const float *contacts, float *obs, hi
 hipError_t launch_cost(const Consts &P, const int32_t *group_of, const float *obs, const float *obs_gt,
                        float *cost_sum, hipStream_t s)
 {
-    int blocks = (P.K + 255) / 256;
+    int blocks = (P.K + 3) / 4;
     hipLaunchKernelGGL(k_cost, dim3(blocks), dim3(256), 0, s, P, group_of, obs, obs_gt, cost_sum);
     return hipGetLastError();
 }

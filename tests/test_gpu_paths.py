@@ -113,14 +113,15 @@ def test_batched_equals_plain_bitwise(pt, cfg_name, K):
         _assert_same(ref, got, f"graph={graph}")
 
 
-def test_autotune_choices_agree_bitwise(pt):
-    _say("every environments-per-workgroup choice gives the same bits")
+@pytest.mark.parametrize("prec,choices", [(64, (1, 2, 4)), (32, (1, 2, 4, 8))])
+def test_autotune_choices_agree_bitwise(pt, prec, choices):
+    _say(f"every environments-per-workgroup choice gives the same bits (solve precision {prec})")
     cfg = S.CONFIGS["small"]
     sc = S.make_scene(cfg, K=40, steps=20)
     outs = []
-    for wpb in (1, 2, 4, 8):
-        b = pt.Batch.from_scene(sc)
-        h = pt.Batch.from_scene(sc, hidden=True)
+    for wpb in choices:
+        b = pt.Batch.from_scene(sc, solve_precision=prec)
+        h = pt.Batch.from_scene(sc, hidden=True, solve_precision=prec)
         uw = _window_inputs(sc, 0, cfg.T)
         gtw = torch.zeros((cfg.T, 4, sc.L, sc.G), device="cuda")
         dummy = torch.zeros_like(gtw)
@@ -128,7 +129,7 @@ def test_autotune_choices_agree_bitwise(pt):
         costh = torch.zeros(sc.G, device="cuda")
         h.run_window(uw, dummy, costh, None, gtw, graph=False)
         if wpb == 1:
-            assert b.autotune(uw, gtw) in (1, 2, 4, 8)   # leaves the state untouched
+            assert b.autotune(uw, gtw) in choices   # leaves the state untouched
         b.set_tuning(wpb)
         b.run_window(uw, gtw, cost, None, None, graph=(wpb % 2 == 0))
         torch.cuda.synchronize()
