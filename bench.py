@@ -74,7 +74,7 @@ def main():
     cfg = S.CONFIGS[args.config]
     total_steps = args.warmup + args.steps
     T = cfg.T
-    sc = S.make_scene(cfg, steps=max(total_steps, cfg.steps) + 1)
+    sc = S.make_scene(cfg, steps=max(total_steps, cfg.steps) + 2 * cfg.T + 1)
     K, G, L = sc.K, sc.G, sc.L
     u_all = torch.as_tensor(sc.u.astype(np.float32), device=dev)
 
@@ -83,28 +83,41 @@ def main():
                 pt.Batch.from_scene(sc, hidden=True, solve_precision=args.solve_precision))
 
     # ---------------- plain per-step path ----------------------------------
+    # The observed ("real") simulation runs on its own stream (default
+    # priority): it does not depend on the population, so its step overlaps
+    # the population's; the cost waits for its observation.  Observations are
+    # double-buffered, with events guarding reuse.
     main_b, hid_b = make()
     cost = torch.zeros(K, device=dev)
     best = torch.zeros(G, dtype=torch.int32, device=dev)
     parent = torch.zeros(K, dtype=torch.int32, device=dev)
     obs = main_b.new_obs()
-    gt = hid_b.new_obs()
+    gts = [hid_b.new_obs(), hid_b.new_obs()]
     stream = torch.cuda.current_stream()
+    s_obs = torch.cuda.Stream(device=dev)
+    ev_gt = [torch.cuda.Event(), torch.cuda.Event()]
+    ev_used = [torch.cuda.Event(), torch.cuda.Event()]
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
     window = 0
+    torch.cuda.synchronize()
 
     def plain_step(t, timed_idx=None):
         nonlocal window
         up, u = u_all[max(t - 1, 0)], u_all[t]
-        hid_b.step(up, u)
-        hid_b.observe(gt)
+        k = t % 2
+        s_obs.wait_event(ev_used[k])
+        hid_b.step(up, u, stream=s_obs)
+        hid_b.observe(gts[k], stream=s_obs)
+        ev_gt[k].record(s_obs)
         if timed_idx is not None:
             ev[timed_idx][0].record(stream)
         main_b.step(up, u)
         if timed_idx is not None:
             ev[timed_idx][1].record(stream)
         main_b.observe(obs)
-        main_b.cost(obs, gt, cost, best)
+        stream.wait_event(ev_gt[k])
+        main_b.cost(obs, gts[k], cost, best)
+        ev_used[k].record(stream)
         if (t + 1) % T == 0:
             main_b.resample(cost, window, parent)
             window += 1
@@ -162,34 +175,55 @@ def main():
     result["roofline"]["frac"] = round(result["roofline"]["achieved"] / result["roofline"]["peak"], 6)
 
     # ---------------- batched path (persistent kernel + graph) -------------
+    # The observed simulation runs one window ahead on its own stream, so its
+    # window overlaps the population's; inputs and observations are
+    # double-buffered.
     if not args.no_batched:
         main_b, hid_b = make()
         n_win = max(1, args.steps // T)
         n_warm = max(1, args.warmup // T)
-        u_win = torch.empty((T + 1, sc.D), device=dev)
-        gtw = torch.zeros((T, 4, L, G), device=dev)
+        u_wins = [torch.empty((T + 1, sc.D), device=dev) for _ in range(2)]
+        gtws = [torch.zeros((T, 4, L, G), device=dev) for _ in range(2)]
         costb = torch.zeros(K, device=dev)
         bestb = torch.zeros(G, dtype=torch.int32, device=dev)
         parentb = torch.zeros(K, dtype=torch.int32, device=dev)
         costh = torch.zeros(G, device=dev)
         gt_dummy = torch.zeros((T, 4, L, G), device=dev)
+        s_obs = torch.cuda.Stream(device=dev)
+        ev_ready = [torch.cuda.Event(), torch.cuda.Event()]
+        ev_free = [torch.cuda.Event(), torch.cuda.Event()]
 
-        def window_run(w):
+        def fill_u(w, buf):
             t0_ = w * T
-            u_win.copy_(u_all[max(t0_ - 1, 0): t0_ + T] if t0_ > 0 else
-                        torch.cat([u_all[:1], u_all[:T]], 0))
-            hid_b.run_window(u_win, gt_dummy, costh, None, gtw, graph=True)
-            main_b.run_window(u_win, gtw, costb, bestb, None, graph=True)
-            main_b.resample(costb, w, parentb)
+            buf.copy_(u_all[t0_ - 1: t0_ + T] if t0_ > 0 else torch.cat([u_all[:1], u_all[:T]], 0))
 
-        # the observed batch writes its observations straight into gtw
-        tuned = main_b.autotune(u_win.copy_(torch.cat([u_all[:1], u_all[:T]], 0)), gtw)
+        def observed_window(w):
+            k = w % 2
+            with torch.cuda.stream(s_obs):
+                s_obs.wait_event(ev_free[k])
+                fill_u(w, u_wins[k])
+                hid_b.run_window(u_wins[k], gt_dummy, costh, None, gtws[k], graph=True, stream=s_obs)
+                ev_ready[k].record(s_obs)
+
+        def population_window(w):
+            k = w % 2
+            stream.wait_event(ev_ready[k])
+            main_b.run_window(u_wins[k], gtws[k], costb, bestb, None, graph=True)
+            main_b.resample(costb, w, parentb)
+            ev_free[k].record(stream)
+
+        fill_u(0, u_wins[0])
+        tuned = main_b.autotune(u_wins[0], gtws[0])
+        torch.cuda.synchronize()
+        observed_window(0)
         for w in range(n_warm):
-            window_run(w)
+            observed_window(w + 1)
+            population_window(w)
         torch.cuda.synchronize()
         tb0 = time.perf_counter()
         for w in range(n_warm, n_warm + n_win):
-            window_run(w)
+            observed_window(w + 1)
+            population_window(w)
         torch.cuda.synchronize()
         bwall = time.perf_counter() - tb0
         result["batched"] = {"value": round(K * T * n_win / bwall, 1), "unit": "env-steps/s",

@@ -74,9 +74,21 @@ struct pt_batch_s {
     int wpb = 4;
     int step_wpb = 4;
     hipStream_t capture_stream = nullptr;
-    hipGraphExec_t graph_exec = nullptr;
-    GraphKey graph_key{};
-    bool has_graph = false;
+    // captured windows, keyed by their buffers (a driver that double-buffers
+    // its inputs alternates between a few); least recently used is evicted
+    static constexpr int N_GRAPHS = 4;
+    hipGraphExec_t graph_exec[N_GRAPHS] = {};
+    GraphKey graph_key[N_GRAPHS] = {};
+    uint64_t graph_used[N_GRAPHS] = {};
+    uint64_t graph_clock = 0;
+    void drop_graphs()
+    {
+        for (int i = 0; i < N_GRAPHS; ++i)
+            if (graph_exec[i]) {
+                (void)hipGraphExecDestroy(graph_exec[i]);
+                graph_exec[i] = nullptr;
+            }
+    }
 };
 
 namespace {
@@ -231,7 +243,7 @@ pt_status pt_destroy_batch(pt_batch b)
 {
     if (!b) return PT_OK;
     (void)hipDeviceSynchronize();
-    if (b->has_graph) (void)hipGraphExecDestroy(b->graph_exec);
+    b->drop_graphs();
     if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
     void *ptrs[] = {b->d_hand, b->d_spheres, b->d_inv, b->d_nsph, b->d_type, b->d_group_of, b->d_group_start,
                     b->d_order, b->d_queue, b->d_stats, b->d_seg, b->d_seg_win, b->d_contacts};
@@ -319,11 +331,24 @@ pt_status pt_run_window(pt_batch b, const float *u_win, const float *obs_gt_win,
     if (!graph)
         return enqueue_window(b, u_win, obs_gt_win, cost_sum, best, obs_out, b->wpb, b->state, b->params, b->warm, st);
     GraphKey key{{u_win, obs_gt_win, cost_sum, best, obs_out}, b->wpb};
-    if (!b->has_graph || !(key == b->graph_key)) {
-        if (b->has_graph) {
+    int slot = -1;
+    for (int i = 0; i < pt_batch_s::N_GRAPHS; ++i)
+        if (b->graph_exec[i] && b->graph_key[i] == key) slot = i;
+    if (slot < 0) {
+        // an empty entry, else the least recently used one
+        int victim = -1;
+        for (int i = 0; i < pt_batch_s::N_GRAPHS && victim < 0; ++i)
+            if (!b->graph_exec[i]) victim = i;
+        if (victim < 0) {
+            victim = 0;
+            for (int i = 1; i < pt_batch_s::N_GRAPHS; ++i)
+                if (b->graph_used[i] < b->graph_used[victim]) victim = i;
+        }
+        slot = victim;
+        if (b->graph_exec[slot]) {
             HIP_TRY(hipStreamSynchronize(st));
-            HIP_TRY(hipGraphExecDestroy(b->graph_exec));
-            b->has_graph = false;
+            HIP_TRY(hipGraphExecDestroy(b->graph_exec[slot]));
+            b->graph_exec[slot] = nullptr;
         }
         hipGraph_t g = nullptr;
         HIP_TRY(hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal));
@@ -335,13 +360,16 @@ pt_status pt_run_window(pt_batch b, const float *u_win, const float *obs_gt_win,
             return cs;
         }
         if (ec != hipSuccess) return fail(PT_E_CAPTURE, "hipStreamEndCapture: %s", hipGetErrorString(ec));
-        hipError_t ei = hipGraphInstantiate(&b->graph_exec, g, nullptr, nullptr, 0);
+        hipError_t ei = hipGraphInstantiate(&b->graph_exec[slot], g, nullptr, nullptr, 0);
         (void)hipGraphDestroy(g);
-        if (ei != hipSuccess) return fail(PT_E_CAPTURE, "hipGraphInstantiate: %s", hipGetErrorString(ei));
-        b->graph_key = key;
-        b->has_graph = true;
+        if (ei != hipSuccess) {
+            b->graph_exec[slot] = nullptr;
+            return fail(PT_E_CAPTURE, "hipGraphInstantiate: %s", hipGetErrorString(ei));
+        }
+        b->graph_key[slot] = key;
     }
-    HIP_TRY(hipGraphLaunch(b->graph_exec, st));
+    b->graph_used[slot] = ++b->graph_clock;
+    HIP_TRY(hipGraphLaunch(b->graph_exec[slot], st));
     return PT_OK;
 }
 
@@ -397,10 +425,6 @@ pt_status pt_autotune(pt_batch b, const float *u_win, const float *obs_gt_win, i
     (void)hipEventDestroy(e1);
     (void)hipFree(tmp);
     if (rc != PT_OK) return rc;
-    if (best_wpb != b->wpb && b->has_graph) {
-        (void)hipGraphExecDestroy(b->graph_exec);
-        b->has_graph = false;
-    }
     b->wpb = best_wpb;
     if (result) *result = best_wpb;
     return PT_OK;
@@ -414,11 +438,6 @@ pt_status pt_set_tuning(pt_batch b, int32_t wpb)
         return fail(PT_E_UNSUPPORTED, "%d simulations per workgroup exceed the LDS", wpb);
     if (wpb > max_wpb(b->P))
         return fail(PT_E_UNSUPPORTED, "at most %d simulations per workgroup with this solve precision", max_wpb(b->P));
-    if (wpb != b->wpb && b->has_graph) {
-        HIP_TRY(hipDeviceSynchronize());
-        HIP_TRY(hipGraphExecDestroy(b->graph_exec));
-        b->has_graph = false;
-    }
     b->wpb = wpb;
     return PT_OK;
 }

@@ -36,12 +36,31 @@ __device__ void quat_mul_d(const double *a, const double *b, double *o)
     o[0] = w; o[1] = x; o[2] = y; o[3] = z;
 }
 
-__device__ void fk_one(const float *__restrict__ hand, int L, const float *__restrict__ u, double *tq, double *tp,
-                       double *seg_a, double *seg_b)
+// joint rotation of link l for joint vector u: Rot(axis0, u[j0]) Rot(axis1, u[j1])
+__device__ void fk_joint(const float *__restrict__ h, const float *__restrict__ u, double *qj)
+{
+    int j0 = (int)h[1], j1 = (int)h[2];
+    double q[4] = {1, 0, 0, 0};
+    if (j0 >= 0) {
+        double th = u[j0], s = sin(0.5 * th);
+        q[0] = cos(0.5 * th); q[1] = s * h[3]; q[2] = s * h[4]; q[3] = s * h[5];
+    }
+    if (j1 >= 0) {
+        double th = u[j1], s = sin(0.5 * th);
+        double r[4] = {cos(0.5 * th), s * h[6], s * h[7], s * h[8]}, t[4];
+        quat_mul_d(q, r, t);
+        for (int i = 0; i < 4; ++i) q[i] = t[i];
+    }
+    for (int i = 0; i < 4; ++i) qj[i] = q[i];
+}
+
+// chain composition along the link tree (parents precede children)
+__device__ void fk_chain(const float *__restrict__ hand, int L, const double *qjs, double *tq, double *tp,
+                         double *seg_a, double *seg_b)
 {
     for (int l = 0; l < L; ++l) {
         const float *h = hand + l * HAND_STRIDE;
-        int parent = (int)h[0], j0 = (int)h[1], j1 = (int)h[2];
+        int parent = (int)h[0];
         double pq[4] = {1, 0, 0, 0}, pp[3] = {0, 0, 0};
         if (parent >= 0) {
             for (int i = 0; i < 4; ++i) pq[i] = tq[4 * parent + i];
@@ -54,24 +73,14 @@ __device__ void fk_one(const float *__restrict__ hand, int L, const float *__res
                        pp[1] + Rp[3] * off[0] + Rp[4] * off[1] + Rp[5] * off[2],
                        pp[2] + Rp[6] * off[0] + Rp[7] * off[1] + Rp[8] * off[2]};
         double qo[4] = {h[12], h[13], h[14], h[15]};
-        double q[4];
-        quat_mul_d(pq, qo, q);
-        if (j0 >= 0) {
-            double th = u[j0], s = sin(0.5 * th);
-            double qj[4] = {cos(0.5 * th), s * h[3], s * h[4], s * h[5]}, t[4];
-            quat_mul_d(q, qj, t);
-            for (int i = 0; i < 4; ++i) q[i] = t[i];
-        }
-        if (j1 >= 0) {
-            double th = u[j1], s = sin(0.5 * th);
-            double qj[4] = {cos(0.5 * th), s * h[6], s * h[7], s * h[8]}, t[4];
-            quat_mul_d(q, qj, t);
-            for (int i = 0; i < 4; ++i) q[i] = t[i];
-        }
-        double R[9];
-        quat_to_mat_d(q, R);
+        double q0[4], q[4];
+        quat_mul_d(pq, qo, q0);
+        quat_mul_d(q0, qjs + 4 * l, q);
         double len = h[16];
-        double b[3] = {o[0] + len * R[0], o[1] + len * R[3], o[2] + len * R[6]};
+        // local +x axis of the link frame
+        double xa[3] = {1 - 2 * (q[2] * q[2] + q[3] * q[3]), 2 * (q[1] * q[2] + q[0] * q[3]),
+                        2 * (q[1] * q[3] - q[0] * q[2])};
+        double b[3] = {o[0] + len * xa[0], o[1] + len * xa[1], o[2] + len * xa[2]};
         for (int i = 0; i < 4; ++i) tq[4 * l + i] = q[i];
         for (int i = 0; i < 3; ++i) {
             tp[3 * l + i] = b[i];
@@ -82,15 +91,23 @@ __device__ void fk_one(const float *__restrict__ hand, int L, const float *__res
 }
 
 // grid: one block per step; u_prev/u for step t at u_prev + t*stride.
+// Joint rotations (the transcendental part) are computed by one thread per
+// (configuration, link); two threads then compose the chains.
 __global__ void k_hand_fk(const float *__restrict__ hand, int L, float dt, const float *__restrict__ u_prev,
                           const float *__restrict__ u, int stride, float *__restrict__ seg_out)
 {
-    __shared__ double tq[2][MAX_LINKS * 4], tp[2][MAX_LINKS * 3], sa[2][MAX_LINKS * 3], sb[2][MAX_LINKS * 3];
+    __shared__ double qj[2][MAX_LINKS * 4], tq[2][MAX_LINKS * 4], tp[2][MAX_LINKS * 3], sa[2][MAX_LINKS * 3],
+        sb[2][MAX_LINKS * 3];
     const int t = blockIdx.x;
+    for (int i = threadIdx.x; i < 2 * L; i += blockDim.x) {
+        int w = i / L, l = i - w * L;
+        const float *uu = (w == 0 ? u_prev : u) + (size_t)t * stride;
+        fk_joint(hand + l * HAND_STRIDE, uu, &qj[w][4 * l]);
+    }
+    __syncthreads();
     if (threadIdx.x < 2) {
         int w = threadIdx.x;
-        const float *uu = (w == 0 ? u_prev : u) + (size_t)t * stride;
-        fk_one(hand, L, uu, tq[w], tp[w], sa[w], sb[w]);
+        fk_chain(hand, L, qj[w], tq[w], tp[w], sa[w], sb[w]);
     }
     __syncthreads();
     const double idt = 1.0 / (double)dt;
