@@ -39,22 +39,42 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-steps", type=int, default=300)
     ap.add_argument("--profile", action="store_true", help="short run for the profiler (no CPU baseline)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy 256 MiB on the device three times (reference for the FETCH_SIZE / WRITE_SIZE "
+                         "counters)")
     return ap.parse_args()
 
 
-# algorithmic floating-point operations (an FMA counts 2), counted from the
-# arithmetic the step performs; see the design doc for the derivation
-FLOP_SPHERE = 21            # c_k = x + R s_k
-FLOP_PAIR = 30              # sphere-capsule signed gap (plane: 1)
-FLOP_ENV = 420              # pose, inertia, free velocity, integration, observation
-FLOP_CONTACT_SETUP = 130    # frame, Jacobian, free relative velocity
-FLOP_CONTACT_ITER = 830     # per Newton iteration: FB value+Jacobian, 3x3 solves, 6x6 contribution, dr, W dr, one merit
-FLOP_ENV_ITER = 370         # per Newton iteration: 6x6 assembly and LU, velocity updates
+# HBM bytes per k_step launch of the 256-simulation workload (float64 solve),
+# from FETCH_SIZE / WRITE_SIZE counters scaled by a plain device copy of known
+# size (profiles/k_step_plain256.txt); None for any other configuration
+MEASURED_TRAFFIC = {("plain256", 64): 1091563}
 
 
-def algorithmic_flops(S, L, N, env_steps, contacts, plane_pairs=True):
-    per_env = FLOP_ENV + S * FLOP_SPHERE + S * L * FLOP_PAIR + (S if plane_pairs else 0) + N * FLOP_ENV_ITER
-    return env_steps * per_env + contacts * (FLOP_CONTACT_SETUP + N * FLOP_CONTACT_ITER)
+# algorithmic floating-point operations (an FMA counts 2; a square root,
+# division or reciprocal counts 1), counted from the arithmetic of one step
+FLOP_SPHERE = 19            # sphere centre x + R s_k, and its table gap
+FLOP_PAIR = 23              # sphere-capsule signed gap
+FLOP_ENV = 360              # pose, inverse inertia, free velocity, integration, momentum remap
+FLOP_ENV_PER_LINK = 25      # per sensor: force magnitude/direction and its cost terms
+FLOP_CONTACT = 175          # contact setup (frame, Jacobian, free velocity), body sums, observation
+FLOP_CONTACT_ITER = 860     # per Newton iteration: FB value + Jacobian, 3x3 solves, 6x6 contribution,
+                            # dr, W dr, one merit trial, cross-contact sums
+FLOP_ENV_ITER = 390         # per Newton iteration: 6x6 assembly, LU, velocity updates
+
+
+def algorithmic_flops(S, L, N, env_steps, contacts):
+    per_env = FLOP_ENV + FLOP_ENV_PER_LINK * L + S * FLOP_SPHERE + S * L * FLOP_PAIR + N * FLOP_ENV_ITER
+    return env_steps * per_env + contacts * (FLOP_CONTACT + N * FLOP_CONTACT_ITER)
+
+
+# algorithmic HBM bytes of the plain step kernel per environment-step: state
+# (13 floats) and parameters (5) read, state and the consumed perturbation
+# force written, the warm-start cache read and written and the contact buffer
+# written (C_max x 16 B each); hand segments and sphere tables are shared by
+# every simulation and stay in cache
+def algorithmic_bytes(C_max):
+    return 52 + 20 + 52 + 12 + 3 * 16 * C_max
 
 
 def main():
@@ -66,10 +86,20 @@ def main():
     import numpy as np
     import torch
 
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.copy_calibration:
+        a = torch.ones(64 * 1024 * 1024, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": a.numel() * 4, "copies": 3}), flush=True)
+        return
+
     from paper_2002_12160_amd import pt
     from paper_2002_12160_amd import scene as S
 
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     cfg = S.CONFIGS[args.config]
     total_steps = args.warmup + args.steps
@@ -167,9 +197,12 @@ def main():
         "contacts_per_env_step": round(d_con / max(d_env, 1), 2),
         "candidates_per_env_step": round(d_cand / max(d_env, 1), 2),
         "roofline": {"bound": "alu", "kernel": "k_step (with its hand-kinematics launch)",
-                     "achieved": round(achieved_tflops, 4), "peak": 78.6 if args.solve_precision == 64 else 157.3,
-                     "unit": "TFLOP/s", "frac": None, "traffic": None,
+                     "achieved": round(achieved_tflops, 4), "peak": 78.6,
+                     "unit": "TFLOP/s", "frac": None,
+                     "traffic": MEASURED_TRAFFIC.get((cfg.name, args.solve_precision)),
                      "flop_per_env_step": round(flops / max(d_env, 1), 1),
+                     "hbm_bytes_per_env_step": algorithmic_bytes(cfg.C_max),
+                     "hbm_gbps": round(algorithmic_bytes(cfg.C_max) * d_env / step_kernel_s / 1e9, 3),
                      "avg_launch_us": round(step_kernel_s / args.steps * 1e6, 2)},
     }
     result["roofline"]["frac"] = round(result["roofline"]["achieved"] / result["roofline"]["peak"], 6)

@@ -136,6 +136,17 @@ __global__ void k_hand_fk(const float *__restrict__ hand, int L, float dt, const
 // ---------------------------------------------------------------------
 // helpers shared by the plain and the batched kernels
 // ---------------------------------------------------------------------
+// Workgroups are dealt round-robin over the 8 XCDs, each with its own L2.
+// Renumber them so that consecutive logical workgroups (hence consecutive
+// simulations, whose SoA state shares cache lines) run on the same XCD.
+constexpr int N_XCD = 8;
+__device__ __forceinline__ int xcd_block(int b, int nb)
+{
+    const int xcd = b % N_XCD, idx = b / N_XCD;
+    const int per = nb / N_XCD, rem = nb % N_XCD;
+    return xcd * per + (xcd < rem ? xcd : rem) + idx;
+}
+
 __device__ __forceinline__ WaveLds carve_lds(char *base, int wave_in_block, int max_cand)
 {
     char *p = base + (size_t)wave_in_block * wave_lds_bytes(max_cand);
@@ -249,7 +260,7 @@ __global__ __launch_bounds__(StepBounds<SR>::threads) void k_step(Consts P, Tabl
 {
     extern __shared__ __align__(16) char smem[];
     const int wib = threadIdx.x / WAVE;
-    const int e = blockIdx.x * (blockDim.x / WAVE) + wib;
+    const int e = xcd_block(blockIdx.x, gridDim.x) * (blockDim.x / WAVE) + wib;
     if (e >= P.K) return;
     WaveLds lds = carve_lds(smem, wib, P.max_cand);
     const int type = tb.env_type[e];
@@ -279,7 +290,7 @@ __global__ __launch_bounds__(256) void k_observe(Consts P, const float *__restri
 {
     __shared__ __align__(16) float stage[4][WAVE * 4];
     const int wib = threadIdx.x / WAVE;
-    const int e = blockIdx.x * (blockDim.x / WAVE) + wib;
+    const int e = xcd_block(blockIdx.x, gridDim.x) * (blockDim.x / WAVE) + wib;
     if (e >= P.K) return;
     const int lane = lane_id();
     float *sg = stage[wib];
@@ -312,7 +323,7 @@ __global__ __launch_bounds__(256) void k_cost(Consts P, const int32_t *__restric
                                               const float *__restrict__ obs, const float *__restrict__ obs_gt,
                                               float *__restrict__ cost_sum)
 {
-    const int e = blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
+    const int e = xcd_block(blockIdx.x, gridDim.x) * (blockDim.x / WAVE) + threadIdx.x / WAVE;
     if (e >= P.K) return;
     const int lane = lane_id();
     const int g = group_of[e];
