@@ -305,7 +305,8 @@ __device__ __forceinline__ T fb_merit(T mu, T kap, T del, const T *r, const T *u
 // Jacobian blocks of Phi: dPhi/dr = Dx Sx =: JX, dPhi/du = Dy Sy =: JY with
 // Dx = I - Lw^-1 Lx, Dy = I - Lw^-1 Ly (row-major 3x3)
 template <typename T>
-__device__ __forceinline__ void fb_jacobian(T mu, T kap, const T *u, const FBOut<T> &o, T *JX, T *JY)
+__device__ __forceinline__ void fb_jacobian(T mu, T kap, const T *u, const FBOut<T> &o, T *JX, T *JY,
+                                            T *DXo = nullptr, T *DYo = nullptr)
 {
     T w0 = o.w0, w1 = o.w1, w2 = o.w2, s = o.s;
     T k = T(1) / (w0 * s);
@@ -340,6 +341,13 @@ __device__ __forceinline__ void fb_jacobian(T mu, T kap, const T *u, const FBOut
         JY[3 * i + 0] = Dy[3 * i + 0];
         JY[3 * i + 1] = Dy[3 * i + 0] * th1 + Dy[3 * i + 1] * mu;
         JY[3 * i + 2] = Dy[3 * i + 0] * th2 + Dy[3 * i + 2] * mu;
+    }
+    if (DXo) {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            DXo[i] = Dx[i];
+            DYo[i] = Dy[i];
+        }
     }
 }
 
@@ -409,355 +417,69 @@ __device__ __forceinline__ void solve6(T (&A)[36], T (&b)[6])
     }
 }
 
+// One contact's contribution to the 6x6 Schur system: with the world-frame
+// block Qw (3x3) and vector gw, J_c^T Qw J_c = [[Qw, -Qw rhat], [rhat Qw,
+// -rhat Qw rhat]] (row i of Qw rhat is q_i x rho) into acc[0..35] row-major,
+// and J_c^T gw = (gw, rho x gw) into acc[36..41].
+template <typename SR>
+__device__ __forceinline__ void schur_contribution(const SR *Qw, const SR *gw, const SR *rho, SR *acc)
+{
+    SR X[9];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) cross3(Qw + 3 * i, rho, X + 3 * i);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            acc[6 * i + j] = Qw[3 * i + j];
+            acc[6 * i + 3 + j] = -X[3 * i + j];
+        }
+    // bottom blocks: columns rho x (column j of Qw), -(rho x column j of X)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        SR cq[3] = {Qw[j], Qw[3 + j], Qw[6 + j]}, cx[3] = {X[j], X[3 + j], X[6 + j]};
+        SR a3[3], b3[3];
+        cross3(rho, cq, a3);
+        cross3(rho, cx, b3);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            acc[6 * (3 + i) + j] = a3[i];
+            acc[6 * (3 + i) + 3 + j] = -b3[i];
+        }
+    }
+    SR tg[3];
+    cross3(rho, gw, tg);
+    acc[36] = gw[0]; acc[37] = gw[1]; acc[38] = gw[2];
+    acc[39] = tg[0]; acc[40] = tg[1]; acc[41] = tg[2];
+}
+
+// Solves (I + M^-1 A6) z = -M^-1 b6 for the summed acc (A6 = acc[0..35],
+// b6 = acc[36..41]); M^-1 = diag(im I, Iinv).  Result in z.
+template <typename SR>
+__device__ __forceinline__ void schur_solve(const SR *acc, SR im, const SR *Iinv, SR (&z)[6])
+{
+    SR S6[36];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+        S6[j] = acc[j] * im + (j == 0 ? SR(1) : SR(0));
+        S6[6 + j] = acc[6 + j] * im + (j == 1 ? SR(1) : SR(0));
+        S6[12 + j] = acc[12 + j] * im + (j == 2 ? SR(1) : SR(0));
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+            S6[6 * (3 + i) + j] = Iinv[3 * i] * acc[18 + j] + Iinv[3 * i + 1] * acc[24 + j] +
+                                  Iinv[3 * i + 2] * acc[30 + j] + (j == 3 + i ? SR(1) : SR(0));
+    }
+    z[0] = -acc[36] * im; z[1] = -acc[37] * im; z[2] = -acc[38] * im;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) z[3 + i] = -(Iinv[3 * i] * acc[39] + Iinv[3 * i + 1] * acc[40] + Iinv[3 * i + 2] * acc[41]);
+    solve6(S6, z);
+}
+
 // ---------------------------------------------------------------------
 // per-step statistics kept by each wave
 // ---------------------------------------------------------------------
 struct StepStats {
     int64_t cand, contacts, dropped;
 };
-
-// ---------------------------------------------------------------------
-// one step of one simulation, executed by one wavefront
-// ---------------------------------------------------------------------
-// Inputs: body (uniform, in/out), per-lane warm slot (key, r) in/out.
-// Output per lane c < C: link (or -1 for the table / empty) and the impulse
-// on the object in world coordinates.  Geometry runs in float32; the contact
-// solve runs in SR (float or double).
-template <typename SR>
-__device__ __forceinline__ void env_step(const Consts &P, const float *__restrict__ seg,
-                                         const float *__restrict__ sph, int S, const float *inv_in, Body &B,
-                                         int &wkey, float *wr, int &out_link, float *out_imp, const WaveLds &lds,
-                                         StepStats &stats)
-{
-    const int lane = lane_id();
-    const int L = P.L;
-    const float dt = P.dt;
-
-    // 1. pose, rotation, inverse inertia, free velocity
-    float qn = rsqrtf(B.q[0] * B.q[0] + B.q[1] * B.q[1] + B.q[2] * B.q[2] + B.q[3] * B.q[3]);
-    float q[4] = {B.q[0] * qn, B.q[1] * qn, B.q[2] * qn, B.q[3] * qn};
-    float R[9];
-    quat_to_mat(q, R);
-    const float m = B.m;
-    const float im = 1.f / m;
-    float ii[3] = {inv_in[0] * im, inv_in[1] * im, inv_in[2] * im};
-    float Iinv[9];
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j = 0; j < 3; ++j)
-            Iinv[3 * i + j] = R[3 * i] * ii[0] * R[3 * j] + R[3 * i + 1] * ii[1] * R[3 * j + 1] +
-                              R[3 * i + 2] * ii[2] * R[3 * j + 2];
-    float vs[3] = {B.v[0] + dt * (P.gx + B.f[0] * im), B.v[1] + dt * (P.gy + B.f[1] * im),
-                   B.v[2] + dt * (P.gz + B.f[2] * im)};
-    float ws[3] = {B.w[0], B.w[1], B.w[2]};
-
-    // 2. narrow phase: lanes over spheres, candidates appended to LDS in
-    //    (sphere block, link) order by ballot + prefix count
-    int ncand = 0;
-    for (int kb = 0; kb < S; kb += WAVE) {
-        int k = kb + lane;
-        bool valid = k < S;
-        float s4[4] = {0.f, 0.f, 0.f, 0.f};
-        if (valid) {
-            const float4 t = *reinterpret_cast<const float4 *>(sph + 4 * k);
-            s4[0] = t.x; s4[1] = t.y; s4[2] = t.z; s4[3] = t.w;
-        }
-        float c[3] = {B.x[0] + R[0] * s4[0] + R[1] * s4[1] + R[2] * s4[2],
-                      B.x[1] + R[3] * s4[0] + R[4] * s4[1] + R[5] * s4[2],
-                      B.x[2] + R[6] * s4[0] + R[7] * s4[1] + R[8] * s4[2]};
-        for (int l = 0; l <= L; ++l) {
-            float d = pair_gap(seg, l, L, c, s4[3]);
-            bool cand = valid && (d < P.margin);
-            uint64_t mask = __ballot(cand);
-            if (cand) {
-                int pos = ncand + mask_rank(mask);
-                lds.cand_d[pos] = d;
-                lds.cand_k[pos] = k * (L + 1) + l;
-            }
-            ncand += __popcll(mask);
-        }
-    }
-    wave_sync();
-    const int C = ncand < P.C_max ? ncand : P.C_max;
-
-    // 3. cap: rank of every candidate in (d, key) order; the C_max lowest
-    //    land in sel[rank]
-    for (int i = lane; i < ncand; i += WAVE) {
-        float di = lds.cand_d[i];
-        int ki = lds.cand_k[i];
-        int rank = 0;
-        for (int j = 0; j < ncand; ++j) {
-            float dj = lds.cand_d[j];
-            int kj = lds.cand_k[j];
-            rank += (dj < di || (dj == di && kj < ki)) ? 1 : 0;
-        }
-        if (rank < P.C_max) lds.sel[rank] = ki;
-    }
-    // previous warm cache to LDS for the key lookup
-    lds.wkey[lane] = wkey;
-    lds.wr[3 * lane + 0] = wr[0];
-    lds.wr[3 * lane + 1] = wr[1];
-    lds.wr[3 * lane + 2] = wr[2];
-    wave_sync();
-
-    stats.cand += ncand;
-    stats.contacts += C;
-    stats.dropped += ncand - C;
-
-    // 4. contact setup, one contact per lane
-    const bool act = lane < C;
-    int key = act ? lds.sel[lane] : -1;
-    SR F[9] = {0, 0, 1, 0, 1, 0, 1, 0, 0};  // rows n, t1, t2
-    SR rho[3] = {0, 0, 0};
-    SR ucst[3] = {0, 0, 0};
-    SR r[3] = {0, 0, 0};
-    int link = -1;
-    if (act) {
-        int k = key / (L + 1);
-        int l = key - k * (L + 1);
-        const float4 t = *reinterpret_cast<const float4 *>(sph + 4 * k);
-        float s4[4] = {t.x, t.y, t.z, t.w};
-        float c[3] = {B.x[0] + R[0] * s4[0] + R[1] * s4[1] + R[2] * s4[2],
-                      B.x[1] + R[3] * s4[0] + R[4] * s4[1] + R[5] * s4[2],
-                      B.x[2] + R[6] * s4[0] + R[7] * s4[1] + R[8] * s4[2]};
-        float d, n[3], p[3], vl[3];
-        pair_contact(seg, l, L, c, s4[3], d, n, p, vl);
-        float t1[3], t2[3];
-        tangent_frame(n, t1, t2);
-        F[0] = n[0]; F[1] = n[1]; F[2] = n[2];
-        F[3] = t1[0]; F[4] = t1[1]; F[5] = t1[2];
-        F[6] = t2[0]; F[7] = t2[1]; F[8] = t2[2];
-        rho[0] = p[0] - B.x[0]; rho[1] = p[1] - B.x[1]; rho[2] = p[2] - B.x[2];
-        float bn = d >= 0.f ? d / dt : P.erp * d / dt;
-        ucst[0] = -(n[0] * vl[0] + n[1] * vl[1] + n[2] * vl[2]) + bn;
-        ucst[1] = -(t1[0] * vl[0] + t1[1] * vl[1] + t1[2] * vl[2]);
-        ucst[2] = -(t2[0] * vl[0] + t2[1] * vl[1] + t2[2] * vl[2]);
-        link = l < L ? l : -1;
-        // warm start from the previous step's impulse of the same key
-        for (int j = 0; j < P.C_max; ++j) {
-            if (lds.wkey[j] == key) {
-                r[0] = lds.wr[3 * j]; r[1] = lds.wr[3 * j + 1]; r[2] = lds.wr[3 * j + 2];
-                break;
-            }
-        }
-    }
-
-    // 5. Newton on the smoothed FB system.  The 3C x 3C Newton matrix
-    //    A = blkdiag(JX) + blkdiag(JY) W, W = J M^-1 J^T + eps I, is reduced
-    //    to the 6x6 system (I + M^-1 sum_c J_c^T P_c^-1 B_c J_c) dnu =
-    //    -M^-1 sum_c J_c^T P_c^-1 Phi_c with P_c = JX_c + eps JY_c,
-    //    B_c = JY_c; then dr_c = -P_c^-1 (Phi_c + B_c J_c dnu).
-    const SR eps = P.compliance, kap = P.kappa, del = P.fb_delta, mu = B.mu;
-    const SR imS = SR(1) / SR(m);
-    SR IinvS[9];
-#pragma unroll
-    for (int i = 0; i < 9; ++i) IinvS[i] = Iinv[i];
-    const int span = lane_span(C);
-    // M^-1 J^T x summed over contacts, for an impulse x of this lane
-    auto body_dv = [&](const SR *x, SR *dn) {
-        SR f[3] = {F[0] * x[0] + F[3] * x[1] + F[6] * x[2], F[1] * x[0] + F[4] * x[1] + F[7] * x[2],
-                   F[2] * x[0] + F[5] * x[1] + F[8] * x[2]};
-        SR tq[3];
-        cross3(rho, f, tq);
-        SR a6[6] = {f[0], f[1], f[2], tq[0], tq[1], tq[2]};
-        wave_sum<SR, 6>(a6, span);
-        dn[0] = a6[0] * imS; dn[1] = a6[1] * imS; dn[2] = a6[2] * imS;
-        dn[3] = IinvS[0] * a6[3] + IinvS[1] * a6[4] + IinvS[2] * a6[5];
-        dn[4] = IinvS[3] * a6[3] + IinvS[4] * a6[4] + IinvS[5] * a6[5];
-        dn[5] = IinvS[6] * a6[3] + IinvS[7] * a6[4] + IinvS[8] * a6[5];
-    };
-    // current body velocity nu = nu* + M^-1 J^T r
-    SR nu[6];
-    body_dv(r, nu);
-    nu[0] += vs[0]; nu[1] += vs[1]; nu[2] += vs[2];
-    nu[3] += ws[0]; nu[4] += ws[1]; nu[5] += ws[2];
-    if (C > 0) {
-        for (int it = 0; it < P.newton_iters; ++it) {
-            // relative velocity u = F (v + w x rho) + ucst + eps r
-            SR pv[3];
-            SR nw3[3] = {nu[3], nu[4], nu[5]};
-            cross3(nw3, rho, pv);
-            pv[0] += nu[0]; pv[1] += nu[1]; pv[2] += nu[2];
-            SR u[3] = {dot3(F, pv) + ucst[0] + eps * r[0], dot3(F + 3, pv) + ucst[1] + eps * r[1],
-                       dot3(F + 6, pv) + ucst[2] + eps * r[2]};
-            FBOut<SR> fo;
-            fb_value(mu, kap, del, r, u, fo);
-            SR JX[9], JY[9];
-            fb_jacobian(mu, kap, u, fo, JX, JY);
-            SR Pm[9], Pi[9], Q[9], g[3];
-#pragma unroll
-            for (int i = 0; i < 9; ++i) Pm[i] = JX[i] + eps * JY[i];
-            inv3(Pm, Pi);
-#pragma unroll
-            for (int i = 0; i < 3; ++i) {
-#pragma unroll
-                for (int j = 0; j < 3; ++j)
-                    Q[3 * i + j] = Pi[3 * i] * JY[j] + Pi[3 * i + 1] * JY[3 + j] + Pi[3 * i + 2] * JY[6 + j];
-                g[i] = Pi[3 * i] * fo.phi[0] + Pi[3 * i + 1] * fo.phi[1] + Pi[3 * i + 2] * fo.phi[2];
-            }
-            // world-frame blocks: Qw = F^T Q F, gw = F^T g
-            SR QF[9];
-#pragma unroll
-            for (int i = 0; i < 3; ++i)
-#pragma unroll
-                for (int j = 0; j < 3; ++j)
-                    QF[3 * i + j] = Q[3 * i] * F[j] + Q[3 * i + 1] * F[3 + j] + Q[3 * i + 2] * F[6 + j];
-            SR acc[43];
-            SR Qw[9];
-#pragma unroll
-            for (int i = 0; i < 3; ++i)
-#pragma unroll
-                for (int j = 0; j < 3; ++j)
-                    Qw[3 * i + j] = F[i] * QF[j] + F[3 + i] * QF[3 + j] + F[6 + i] * QF[6 + j];
-            SR gw[3] = {F[0] * g[0] + F[3] * g[1] + F[6] * g[2], F[1] * g[0] + F[4] * g[1] + F[7] * g[2],
-                        F[2] * g[0] + F[5] * g[1] + F[8] * g[2]};
-            // A6 = [[Qw, -Qw rhat], [rhat Qw, -rhat Qw rhat]]; row i of Qw rhat = q_i x rho
-            SR X[9];
-#pragma unroll
-            for (int i = 0; i < 3; ++i) cross3(Qw + 3 * i, rho, X + 3 * i);
-#pragma unroll
-            for (int i = 0; i < 3; ++i)
-#pragma unroll
-                for (int j = 0; j < 3; ++j) {
-                    acc[6 * i + j] = Qw[3 * i + j];
-                    acc[6 * i + 3 + j] = -X[3 * i + j];
-                }
-            // bottom blocks: columns rho x (column j of Qw), -(rho x column j of X)
-#pragma unroll
-            for (int j = 0; j < 3; ++j) {
-                SR cq[3] = {Qw[j], Qw[3 + j], Qw[6 + j]}, cx[3] = {X[j], X[3 + j], X[6 + j]};
-                SR a3[3], b3[3];
-                cross3(rho, cq, a3);
-                cross3(rho, cx, b3);
-#pragma unroll
-                for (int i = 0; i < 3; ++i) {
-                    acc[6 * (3 + i) + j] = a3[i];
-                    acc[6 * (3 + i) + 3 + j] = -b3[i];
-                }
-            }
-            SR tg[3];
-            cross3(rho, gw, tg);
-            acc[36] = gw[0]; acc[37] = gw[1]; acc[38] = gw[2];
-            acc[39] = tg[0]; acc[40] = tg[1]; acc[41] = tg[2];
-            acc[42] = SR(0.5) * (fo.phi[0] * fo.phi[0] + fo.phi[1] * fo.phi[1] + fo.phi[2] * fo.phi[2]);
-            if (!act) {
-#pragma unroll
-                for (int i = 0; i < 43; ++i) acc[i] = SR(0);
-            }
-            wave_sum<SR, 43>(acc, span);
-            const SR psi = acc[42];
-            // (I + M^-1 A6) dnu = -M^-1 b6
-            SR S6[36], rhs[6];
-#pragma unroll
-            for (int j = 0; j < 6; ++j) {
-                S6[j] = acc[j] * imS + (j == 0 ? SR(1) : SR(0));
-                S6[6 + j] = acc[6 + j] * imS + (j == 1 ? SR(1) : SR(0));
-                S6[12 + j] = acc[12 + j] * imS + (j == 2 ? SR(1) : SR(0));
-#pragma unroll
-                for (int i = 0; i < 3; ++i)
-                    S6[6 * (3 + i) + j] = IinvS[3 * i] * acc[18 + j] + IinvS[3 * i + 1] * acc[24 + j] +
-                                          IinvS[3 * i + 2] * acc[30 + j] + (j == 3 + i ? SR(1) : SR(0));
-            }
-            rhs[0] = -acc[36] * imS; rhs[1] = -acc[37] * imS; rhs[2] = -acc[38] * imS;
-#pragma unroll
-            for (int i = 0; i < 3; ++i)
-                rhs[3 + i] = -(IinvS[3 * i] * acc[39] + IinvS[3 * i + 1] * acc[40] + IinvS[3 * i + 2] * acc[41]);
-            solve6(S6, rhs);
-            // dr = -g - Q F (dv + dw x rho)
-            SR dp[3];
-            SR dw3[3] = {rhs[3], rhs[4], rhs[5]};
-            cross3(dw3, rho, dp);
-            dp[0] += rhs[0]; dp[1] += rhs[1]; dp[2] += rhs[2];
-            SR dr[3];
-#pragma unroll
-            for (int i = 0; i < 3; ++i)
-                dr[i] = -g[i] - (QF[3 * i] * dp[0] + QF[3 * i + 1] * dp[1] + QF[3 * i + 2] * dp[2]);
-            if (!act) { dr[0] = dr[1] = dr[2] = SR(0); }
-            // body-velocity change of the step, M^-1 J^T dr, summed afresh so
-            // that the tracked velocity stays consistent with r (the 6x6
-            // solution equals it only up to the Schur system's conditioning)
-            SR dn[6];
-            body_dv(dr, dn);
-            // du = W dr = F (dn_v + dn_w x rho) + eps dr
-            SR dq[3];
-            SR dnw[3] = {dn[3], dn[4], dn[5]};
-            cross3(dnw, rho, dq);
-            dq[0] += dn[0]; dq[1] += dn[1]; dq[2] += dn[2];
-            SR du[3] = {dot3(F, dq) + eps * dr[0], dot3(F + 3, dq) + eps * dr[1], dot3(F + 6, dq) + eps * dr[2]};
-            // Armijo backtracking over alpha = 1, 1/2, 1/4, 1/8 (1/8 if none passes)
-            SR alpha = SR(0.125);
-            SR a = SR(1);
-            for (int t = 0; t < 4; ++t, a *= SR(0.5)) {
-                SR rt[3] = {r[0] + a * dr[0], r[1] + a * dr[1], r[2] + a * dr[2]};
-                SR ut[3] = {u[0] + a * du[0], u[1] + a * du[1], u[2] + a * du[2]};
-                SR ptr = act ? fb_merit(mu, kap, del, rt, ut) : SR(0);
-                ptr = wave_sum1(ptr, span);
-                if (ptr <= (SR(1) - SR(2) * SR(P.armijo_sigma) * a) * psi) { alpha = a; break; }
-            }
-            r[0] += alpha * dr[0]; r[1] += alpha * dr[1]; r[2] += alpha * dr[2];
-#pragma unroll
-            for (int i = 0; i < 6; ++i) nu[i] += alpha * dn[i];
-        }
-    }
-
-    // 6. integrate: nu+ = nu* + M^-1 J^T r (fresh sum), x += dt v+,
-    //    q <- normalize(Exp(dt w+) q), angular-momentum-preserving w remap
-    SR impS[3] = {F[0] * r[0] + F[3] * r[1] + F[6] * r[2], F[1] * r[0] + F[4] * r[1] + F[7] * r[2],
-                  F[2] * r[0] + F[5] * r[1] + F[8] * r[2]};
-    if (!act) { impS[0] = impS[1] = impS[2] = SR(0); }
-    float vp[3], wp[3];
-    {
-        SR dv[6];
-        body_dv(r, dv);
-        vp[0] = (float)(SR(vs[0]) + dv[0]); vp[1] = (float)(SR(vs[1]) + dv[1]); vp[2] = (float)(SR(vs[2]) + dv[2]);
-        wp[0] = (float)(SR(ws[0]) + dv[3]); wp[1] = (float)(SR(ws[1]) + dv[4]); wp[2] = (float)(SR(ws[2]) + dv[5]);
-    }
-    float xn[3] = {B.x[0] + dt * vp[0], B.x[1] + dt * vp[1], B.x[2] + dt * vp[2]};
-    float th[3] = {dt * wp[0], dt * wp[1], dt * wp[2]};
-    float an = sqrtf(th[0] * th[0] + th[1] * th[1] + th[2] * th[2]);
-    float eq[4];
-    if (an < 1e-4f) {
-        float a2 = an * an;
-        float sc = 0.5f - a2 / 48.f;
-        eq[0] = 1.f - a2 / 8.f; eq[1] = sc * th[0]; eq[2] = sc * th[1]; eq[3] = sc * th[2];
-    } else {
-        float sc = sinf(0.5f * an) / an;
-        eq[0] = cosf(0.5f * an); eq[1] = sc * th[0]; eq[2] = sc * th[1]; eq[3] = sc * th[2];
-    }
-    float q2[4];
-    quat_mul(eq, q, q2);
-    float qi = rsqrtf(q2[0] * q2[0] + q2[1] * q2[1] + q2[2] * q2[2] + q2[3] * q2[3]);
-    q2[0] *= qi; q2[1] *= qi; q2[2] *= qi; q2[3] *= qi;
-    // h = I_w(q) w+ in body components, carried to the new orientation
-    float wb[3] = {R[0] * wp[0] + R[3] * wp[1] + R[6] * wp[2], R[1] * wp[0] + R[4] * wp[1] + R[7] * wp[2],
-                   R[2] * wp[0] + R[5] * wp[1] + R[8] * wp[2]};
-    float hb[3];
-#pragma unroll
-    for (int i = 0; i < 3; ++i) hb[i] = inv_in[i] > 0.f ? wb[i] * m / inv_in[i] : 0.f;
-    float h[3] = {R[0] * hb[0] + R[1] * hb[1] + R[2] * hb[2], R[3] * hb[0] + R[4] * hb[1] + R[5] * hb[2],
-                  R[6] * hb[0] + R[7] * hb[1] + R[8] * hb[2]};
-    float Rn[9];
-    quat_to_mat(q2, Rn);
-    float hn[3] = {Rn[0] * h[0] + Rn[3] * h[1] + Rn[6] * h[2], Rn[1] * h[0] + Rn[4] * h[1] + Rn[7] * h[2],
-                   Rn[2] * h[0] + Rn[5] * h[1] + Rn[8] * h[2]};
-#pragma unroll
-    for (int i = 0; i < 3; ++i) hn[i] *= ii[i];
-    B.w[0] = Rn[0] * hn[0] + Rn[1] * hn[1] + Rn[2] * hn[2];
-    B.w[1] = Rn[3] * hn[0] + Rn[4] * hn[1] + Rn[5] * hn[2];
-    B.w[2] = Rn[6] * hn[0] + Rn[7] * hn[1] + Rn[8] * hn[2];
-    B.x[0] = xn[0]; B.x[1] = xn[1]; B.x[2] = xn[2];
-    B.q[0] = q2[0]; B.q[1] = q2[1]; B.q[2] = q2[2]; B.q[3] = q2[3];
-    B.v[0] = vp[0]; B.v[1] = vp[1]; B.v[2] = vp[2];
-    B.f[0] = B.f[1] = B.f[2] = 0.f;
-
-    // 7. new warm cache slot and contact output of this lane
-    wkey = act ? key : -1;
-    wr[0] = act ? (float)r[0] : 0.f;
-    wr[1] = act ? (float)r[1] : 0.f;
-    wr[2] = act ? (float)r[2] : 0.f;
-    out_link = act ? link : -1;
-    out_imp[0] = (float)impS[0]; out_imp[1] = (float)impS[1]; out_imp[2] = (float)impS[2];
-}
 
 }  // namespace pt

@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 #include "pt_device.hpp"
+#include "pt_step.hpp"
 
 namespace pt {
 

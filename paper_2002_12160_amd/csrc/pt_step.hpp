@@ -1,0 +1,412 @@
+// pt_step.hpp -- one simulation step executed by one wavefront, split into
+// phases so that the adjoint can re-run the forward step with the same code:
+//   step_setup   pose, free velocity, narrow phase, cap, contact setup, warm start
+//   step_solve   smoothed Fischer-Burmeister Newton on the 6x6 Schur system
+//   step_finish  integration, warm cache and contact outputs
+// Geometry runs in float32; the contact solve runs in SR (float or double).
+#pragma once
+
+#include "pt_device.hpp"
+
+namespace pt {
+
+template <typename SR>
+struct StepState {
+    // uniform
+    float q[4];        // normalised pre-step orientation
+    float R[9];
+    float ii[3];       // principal inverse inertia / m
+    float Iinv[9];     // world inverse inertia
+    float vs[3], ws[3];// free velocity
+    float m, im;
+    int C, span, ncand;
+    // per lane (contact slot)
+    bool act;
+    int key, link, k, l;
+    float c[3];        // sphere centre
+    float d, n[3], p[3], vl[3], tpar, dist;
+    bool interior;     // closest point strictly inside the segment
+    int e_axis;        // axis used for the tangent frame
+    SR F[9];           // rows n, t1, t2
+    SR rho[3];         // p - x
+    SR ucst[3];        // -F v_link + (b_n, 0, 0)
+    SR r[3];           // impulse
+    SR nu[6];          // body velocity after the solve (fresh sum)
+};
+
+// M^-1 J^T x summed over contacts, for an impulse x held by this lane
+template <typename SR>
+__device__ __forceinline__ void body_dv(const StepState<SR> &st, const SR *x, SR *dn)
+{
+    const SR *F = st.F;
+    SR f[3] = {F[0] * x[0] + F[3] * x[1] + F[6] * x[2], F[1] * x[0] + F[4] * x[1] + F[7] * x[2],
+               F[2] * x[0] + F[5] * x[1] + F[8] * x[2]};
+    SR tq[3];
+    cross3(st.rho, f, tq);
+    SR a6[6] = {f[0], f[1], f[2], tq[0], tq[1], tq[2]};
+    wave_sum<SR, 6>(a6, st.span);
+    const SR imS = SR(1) / SR(st.m);
+    dn[0] = a6[0] * imS; dn[1] = a6[1] * imS; dn[2] = a6[2] * imS;
+    dn[3] = SR(st.Iinv[0]) * a6[3] + SR(st.Iinv[1]) * a6[4] + SR(st.Iinv[2]) * a6[5];
+    dn[4] = SR(st.Iinv[3]) * a6[3] + SR(st.Iinv[4]) * a6[4] + SR(st.Iinv[5]) * a6[5];
+    dn[5] = SR(st.Iinv[6]) * a6[3] + SR(st.Iinv[7]) * a6[4] + SR(st.Iinv[8]) * a6[5];
+}
+
+// relative velocity u = F (v + w x rho) + ucst + eps r for body velocity nu
+template <typename SR>
+__device__ __forceinline__ void rel_velocity(const StepState<SR> &st, const SR *nu, const SR *r, SR eps, SR *u)
+{
+    SR pv[3];
+    SR nw3[3] = {nu[3], nu[4], nu[5]};
+    cross3(nw3, st.rho, pv);
+    pv[0] += nu[0]; pv[1] += nu[1]; pv[2] += nu[2];
+    const SR *F = st.F;
+    u[0] = dot3(F, pv) + st.ucst[0] + eps * r[0];
+    u[1] = dot3(F + 3, pv) + st.ucst[1] + eps * r[1];
+    u[2] = dot3(F + 6, pv) + st.ucst[2] + eps * r[2];
+}
+
+// phases 1-4: pose, free velocity, narrow phase, cap, contact setup, warm start
+template <typename SR>
+__device__ __forceinline__ void step_setup(const Consts &P, const float *__restrict__ seg,
+                                           const float *__restrict__ sph, int S, const float *inv_in, const Body &B,
+                                           int wkey, const float *wr, const WaveLds &lds, StepStats &stats,
+                                           StepState<SR> &st)
+{
+    const int lane = lane_id();
+    const int L = P.L;
+    const float dt = P.dt;
+
+    // 1. pose, rotation, inverse inertia, free velocity
+    float qn = rsqrtf(B.q[0] * B.q[0] + B.q[1] * B.q[1] + B.q[2] * B.q[2] + B.q[3] * B.q[3]);
+    float *q = st.q;
+    q[0] = B.q[0] * qn; q[1] = B.q[1] * qn; q[2] = B.q[2] * qn; q[3] = B.q[3] * qn;
+    float *R = st.R;
+    quat_to_mat(q, R);
+    st.m = B.m;
+    st.im = 1.f / st.m;
+    const float im = st.im;
+    st.ii[0] = inv_in[0] * im; st.ii[1] = inv_in[1] * im; st.ii[2] = inv_in[2] * im;
+    const float *ii = st.ii;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            st.Iinv[3 * i + j] = R[3 * i] * ii[0] * R[3 * j] + R[3 * i + 1] * ii[1] * R[3 * j + 1] +
+                                 R[3 * i + 2] * ii[2] * R[3 * j + 2];
+    st.vs[0] = B.v[0] + dt * (P.gx + B.f[0] * im);
+    st.vs[1] = B.v[1] + dt * (P.gy + B.f[1] * im);
+    st.vs[2] = B.v[2] + dt * (P.gz + B.f[2] * im);
+    st.ws[0] = B.w[0]; st.ws[1] = B.w[1]; st.ws[2] = B.w[2];
+
+    // 2. narrow phase: lanes over spheres, candidates appended to LDS in
+    //    (sphere block, link) order by ballot + prefix count
+    int ncand = 0;
+    for (int kb = 0; kb < S; kb += WAVE) {
+        int k = kb + lane;
+        bool valid = k < S;
+        float s4[4] = {0.f, 0.f, 0.f, 0.f};
+        if (valid) {
+            const float4 t = *reinterpret_cast<const float4 *>(sph + 4 * k);
+            s4[0] = t.x; s4[1] = t.y; s4[2] = t.z; s4[3] = t.w;
+        }
+        float c[3] = {B.x[0] + R[0] * s4[0] + R[1] * s4[1] + R[2] * s4[2],
+                      B.x[1] + R[3] * s4[0] + R[4] * s4[1] + R[5] * s4[2],
+                      B.x[2] + R[6] * s4[0] + R[7] * s4[1] + R[8] * s4[2]};
+        for (int l = 0; l <= L; ++l) {
+            float d = pair_gap(seg, l, L, c, s4[3]);
+            bool cand = valid && (d < P.margin);
+            uint64_t mask = __ballot(cand);
+            if (cand) {
+                int pos = ncand + mask_rank(mask);
+                lds.cand_d[pos] = d;
+                lds.cand_k[pos] = k * (L + 1) + l;
+            }
+            ncand += __popcll(mask);
+        }
+    }
+    wave_sync();
+    const int C = ncand < P.C_max ? ncand : P.C_max;
+    st.C = C;
+    st.ncand = ncand;
+    st.span = lane_span(C);
+
+    // 3. cap: rank of every candidate in (d, key) order; the C_max lowest
+    //    land in sel[rank]
+    for (int i = lane; i < ncand; i += WAVE) {
+        float di = lds.cand_d[i];
+        int ki = lds.cand_k[i];
+        int rank = 0;
+        for (int j = 0; j < ncand; ++j) {
+            float dj = lds.cand_d[j];
+            int kj = lds.cand_k[j];
+            rank += (dj < di || (dj == di && kj < ki)) ? 1 : 0;
+        }
+        if (rank < P.C_max) lds.sel[rank] = ki;
+    }
+    // previous warm cache to LDS for the key lookup
+    lds.wkey[lane] = wkey;
+    lds.wr[3 * lane + 0] = wr[0];
+    lds.wr[3 * lane + 1] = wr[1];
+    lds.wr[3 * lane + 2] = wr[2];
+    wave_sync();
+
+    stats.cand += ncand;
+    stats.contacts += C;
+    stats.dropped += ncand - C;
+
+    // 4. contact setup, one contact per lane
+    st.act = lane < C;
+    st.key = st.act ? lds.sel[lane] : -1;
+    SR *F = st.F;
+    F[0] = 0; F[1] = 0; F[2] = 1; F[3] = 0; F[4] = 1; F[5] = 0; F[6] = 1; F[7] = 0; F[8] = 0;
+    st.rho[0] = st.rho[1] = st.rho[2] = SR(0);
+    st.ucst[0] = st.ucst[1] = st.ucst[2] = SR(0);
+    st.r[0] = st.r[1] = st.r[2] = SR(0);
+    st.link = -1;
+    st.k = 0;
+    st.l = L;
+    st.interior = false;
+    st.e_axis = 0;
+    st.tpar = 0.f;
+    st.dist = 0.f;
+    st.d = 0.f;
+    if (st.act) {
+        int k = st.key / (L + 1);
+        int l = st.key - k * (L + 1);
+        st.k = k;
+        st.l = l;
+        const float4 t = *reinterpret_cast<const float4 *>(sph + 4 * k);
+        float s4[4] = {t.x, t.y, t.z, t.w};
+        float *c = st.c;
+        c[0] = B.x[0] + R[0] * s4[0] + R[1] * s4[1] + R[2] * s4[2];
+        c[1] = B.x[1] + R[3] * s4[0] + R[4] * s4[1] + R[5] * s4[2];
+        c[2] = B.x[2] + R[6] * s4[0] + R[7] * s4[1] + R[8] * s4[2];
+        float d, *n = st.n, *p = st.p, *vl = st.vl;
+        pair_contact(seg, l, L, c, s4[3], d, n, p, vl);
+        st.d = d;
+        if (l < L) {
+            const float *sg = seg + l * SEG_STRIDE;
+            float ca[3] = {c[0] - sg[0], c[1] - sg[1], c[2] - sg[2]};
+            float tr = (ca[0] * sg[4] + ca[1] * sg[5] + ca[2] * sg[6]) * sg[7];
+            st.interior = tr > 0.f && tr < 1.f;
+            st.tpar = fminf(fmaxf(tr, 0.f), 1.f);
+            st.dist = d + s4[3] + sg[3];
+        }
+        float t1[3], t2[3];
+        tangent_frame(n, t1, t2);
+        {
+            float an0 = fabsf(n[0]), an1 = fabsf(n[1]), an2 = fabsf(n[2]);
+            int e = 0;
+            float best = an0;
+            if (an1 < best) { e = 1; best = an1; }
+            if (an2 < best) { e = 2; }
+            st.e_axis = e;
+        }
+        F[0] = n[0]; F[1] = n[1]; F[2] = n[2];
+        F[3] = t1[0]; F[4] = t1[1]; F[5] = t1[2];
+        F[6] = t2[0]; F[7] = t2[1]; F[8] = t2[2];
+        st.rho[0] = p[0] - B.x[0]; st.rho[1] = p[1] - B.x[1]; st.rho[2] = p[2] - B.x[2];
+        float bn = d >= 0.f ? d / dt : P.erp * d / dt;
+        st.ucst[0] = -(n[0] * vl[0] + n[1] * vl[1] + n[2] * vl[2]) + bn;
+        st.ucst[1] = -(t1[0] * vl[0] + t1[1] * vl[1] + t1[2] * vl[2]);
+        st.ucst[2] = -(t2[0] * vl[0] + t2[1] * vl[1] + t2[2] * vl[2]);
+        st.link = l < L ? l : -1;
+        // warm start from the previous step's impulse of the same key
+        for (int j = 0; j < P.C_max; ++j) {
+            if (lds.wkey[j] == st.key) {
+                st.r[0] = lds.wr[3 * j]; st.r[1] = lds.wr[3 * j + 1]; st.r[2] = lds.wr[3 * j + 2];
+                break;
+            }
+        }
+    }
+}
+
+// Newton on the smoothed FB system.  The 3C x 3C Newton matrix
+// A = blkdiag(JX) + blkdiag(JY) W, W = J M^-1 J^T + eps I, is reduced to the
+// 6x6 system (I + M^-1 sum_c J_c^T P_c^-1 B_c J_c) dnu =
+// -M^-1 sum_c J_c^T P_c^-1 Phi_c with P_c = JX_c + eps JY_c, B_c = JY_c; then
+// dr_c = -P_c^-1 (Phi_c + B_c J_c dnu).  Leaves st.r and the fresh st.nu.
+template <typename SR>
+__device__ __forceinline__ void step_solve(const Consts &P, StepState<SR> &st, float mu_f)
+{
+    const SR eps = P.compliance, kap = P.kappa, del = P.fb_delta, mu = mu_f;
+    const SR imS = SR(1) / SR(st.m);
+    SR IinvS[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) IinvS[i] = st.Iinv[i];
+    const bool act = st.act;
+    const int span = st.span;
+    SR *r = st.r;
+    const SR *F = st.F, *rho = st.rho;
+    // current body velocity nu = nu* + M^-1 J^T r
+    SR nu[6];
+    body_dv(st, r, nu);
+    nu[0] += st.vs[0]; nu[1] += st.vs[1]; nu[2] += st.vs[2];
+    nu[3] += st.ws[0]; nu[4] += st.ws[1]; nu[5] += st.ws[2];
+    if (st.C > 0) {
+        for (int it = 0; it < P.newton_iters; ++it) {
+            SR u[3];
+            rel_velocity(st, nu, r, eps, u);
+            FBOut<SR> fo;
+            fb_value(mu, kap, del, r, u, fo);
+            SR JX[9], JY[9];
+            fb_jacobian(mu, kap, u, fo, JX, JY);
+            SR Pm[9], Pi[9], Q[9], g[3];
+#pragma unroll
+            for (int i = 0; i < 9; ++i) Pm[i] = JX[i] + eps * JY[i];
+            inv3(Pm, Pi);
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+#pragma unroll
+                for (int j = 0; j < 3; ++j)
+                    Q[3 * i + j] = Pi[3 * i] * JY[j] + Pi[3 * i + 1] * JY[3 + j] + Pi[3 * i + 2] * JY[6 + j];
+                g[i] = Pi[3 * i] * fo.phi[0] + Pi[3 * i + 1] * fo.phi[1] + Pi[3 * i + 2] * fo.phi[2];
+            }
+            // world-frame blocks: Qw = F^T Q F, gw = F^T g
+            SR QF[9];
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int j = 0; j < 3; ++j)
+                    QF[3 * i + j] = Q[3 * i] * F[j] + Q[3 * i + 1] * F[3 + j] + Q[3 * i + 2] * F[6 + j];
+            SR acc[43];
+            SR Qw[9];
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int j = 0; j < 3; ++j)
+                    Qw[3 * i + j] = F[i] * QF[j] + F[3 + i] * QF[3 + j] + F[6 + i] * QF[6 + j];
+            SR gw[3] = {F[0] * g[0] + F[3] * g[1] + F[6] * g[2], F[1] * g[0] + F[4] * g[1] + F[7] * g[2],
+                        F[2] * g[0] + F[5] * g[1] + F[8] * g[2]};
+            schur_contribution(Qw, gw, rho, acc);
+            acc[42] = SR(0.5) * (fo.phi[0] * fo.phi[0] + fo.phi[1] * fo.phi[1] + fo.phi[2] * fo.phi[2]);
+            if (!act) {
+#pragma unroll
+                for (int i = 0; i < 43; ++i) acc[i] = SR(0);
+            }
+            wave_sum<SR, 43>(acc, span);
+            const SR psi = acc[42];
+            SR rhs[6];
+            schur_solve(acc, imS, IinvS, rhs);
+            // dr = -g - Q F (dv + dw x rho)
+            SR dp[3];
+            SR dw3[3] = {rhs[3], rhs[4], rhs[5]};
+            cross3(dw3, rho, dp);
+            dp[0] += rhs[0]; dp[1] += rhs[1]; dp[2] += rhs[2];
+            SR dr[3];
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+                dr[i] = -g[i] - (QF[3 * i] * dp[0] + QF[3 * i + 1] * dp[1] + QF[3 * i + 2] * dp[2]);
+            if (!act) { dr[0] = dr[1] = dr[2] = SR(0); }
+            // body-velocity change of the step, M^-1 J^T dr, summed afresh so
+            // that the tracked velocity stays consistent with r (the 6x6
+            // solution equals it only up to the Schur system's conditioning)
+            SR dn[6];
+            body_dv(st, dr, dn);
+            // du = W dr = F (dn_v + dn_w x rho) + eps dr
+            SR du[3];
+            {
+                SR dq[3];
+                SR dnw[3] = {dn[3], dn[4], dn[5]};
+                cross3(dnw, rho, dq);
+                dq[0] += dn[0]; dq[1] += dn[1]; dq[2] += dn[2];
+                du[0] = dot3(F, dq) + eps * dr[0];
+                du[1] = dot3(F + 3, dq) + eps * dr[1];
+                du[2] = dot3(F + 6, dq) + eps * dr[2];
+            }
+            // Armijo backtracking over alpha = 1, 1/2, 1/4, 1/8 (1/8 if none passes)
+            SR alpha = SR(0.125);
+            SR a = SR(1);
+            for (int t = 0; t < 4; ++t, a *= SR(0.5)) {
+                SR rt[3] = {r[0] + a * dr[0], r[1] + a * dr[1], r[2] + a * dr[2]};
+                SR ut[3] = {u[0] + a * du[0], u[1] + a * du[1], u[2] + a * du[2]};
+                SR ptr = act ? fb_merit(mu, kap, del, rt, ut) : SR(0);
+                ptr = wave_sum1(ptr, span);
+                if (ptr <= (SR(1) - SR(2) * SR(P.armijo_sigma) * a) * psi) { alpha = a; break; }
+            }
+            r[0] += alpha * dr[0]; r[1] += alpha * dr[1]; r[2] += alpha * dr[2];
+#pragma unroll
+            for (int i = 0; i < 6; ++i) nu[i] += alpha * dn[i];
+        }
+    }
+    // fresh sum of the body velocity for the final impulses
+    body_dv(st, r, st.nu);
+    st.nu[0] += st.vs[0]; st.nu[1] += st.vs[1]; st.nu[2] += st.vs[2];
+    st.nu[3] += st.ws[0]; st.nu[4] += st.ws[1]; st.nu[5] += st.ws[2];
+}
+
+// integrate: x += dt v+, q <- normalize(Exp(dt w+) q), angular-momentum-
+// preserving w remap; new warm cache slot and contact output of this lane
+template <typename SR>
+__device__ __forceinline__ void step_finish(const Consts &P, const StepState<SR> &st, const float *inv_in, Body &B,
+                                            int &wkey, float *wr, int &out_link, float *out_imp)
+{
+    const float dt = P.dt;
+    const SR *F = st.F, *r = st.r;
+    SR impS[3] = {F[0] * r[0] + F[3] * r[1] + F[6] * r[2], F[1] * r[0] + F[4] * r[1] + F[7] * r[2],
+                  F[2] * r[0] + F[5] * r[1] + F[8] * r[2]};
+    if (!st.act) { impS[0] = impS[1] = impS[2] = SR(0); }
+    float vp[3] = {(float)st.nu[0], (float)st.nu[1], (float)st.nu[2]};
+    float wp[3] = {(float)st.nu[3], (float)st.nu[4], (float)st.nu[5]};
+    const float *q = st.q, *R = st.R;
+    float xn[3] = {B.x[0] + dt * vp[0], B.x[1] + dt * vp[1], B.x[2] + dt * vp[2]};
+    float th[3] = {dt * wp[0], dt * wp[1], dt * wp[2]};
+    float an = sqrtf(th[0] * th[0] + th[1] * th[1] + th[2] * th[2]);
+    float eq[4];
+    if (an < 1e-4f) {
+        float a2 = an * an;
+        float sc = 0.5f - a2 / 48.f;
+        eq[0] = 1.f - a2 / 8.f; eq[1] = sc * th[0]; eq[2] = sc * th[1]; eq[3] = sc * th[2];
+    } else {
+        float sc = sinf(0.5f * an) / an;
+        eq[0] = cosf(0.5f * an); eq[1] = sc * th[0]; eq[2] = sc * th[1]; eq[3] = sc * th[2];
+    }
+    float q2[4];
+    quat_mul(eq, q, q2);
+    float qi = rsqrtf(q2[0] * q2[0] + q2[1] * q2[1] + q2[2] * q2[2] + q2[3] * q2[3]);
+    q2[0] *= qi; q2[1] *= qi; q2[2] *= qi; q2[3] *= qi;
+    // h = I_w(q) w+ in body components, carried to the new orientation
+    float wb[3] = {R[0] * wp[0] + R[3] * wp[1] + R[6] * wp[2], R[1] * wp[0] + R[4] * wp[1] + R[7] * wp[2],
+                   R[2] * wp[0] + R[5] * wp[1] + R[8] * wp[2]};
+    float hb[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) hb[i] = inv_in[i] > 0.f ? wb[i] * st.m / inv_in[i] : 0.f;
+    float h[3] = {R[0] * hb[0] + R[1] * hb[1] + R[2] * hb[2], R[3] * hb[0] + R[4] * hb[1] + R[5] * hb[2],
+                  R[6] * hb[0] + R[7] * hb[1] + R[8] * hb[2]};
+    float Rn[9];
+    quat_to_mat(q2, Rn);
+    float hn[3] = {Rn[0] * h[0] + Rn[3] * h[1] + Rn[6] * h[2], Rn[1] * h[0] + Rn[4] * h[1] + Rn[7] * h[2],
+                   Rn[2] * h[0] + Rn[5] * h[1] + Rn[8] * h[2]};
+#pragma unroll
+    for (int i = 0; i < 3; ++i) hn[i] *= st.ii[i];
+    B.w[0] = Rn[0] * hn[0] + Rn[1] * hn[1] + Rn[2] * hn[2];
+    B.w[1] = Rn[3] * hn[0] + Rn[4] * hn[1] + Rn[5] * hn[2];
+    B.w[2] = Rn[6] * hn[0] + Rn[7] * hn[1] + Rn[8] * hn[2];
+    B.x[0] = xn[0]; B.x[1] = xn[1]; B.x[2] = xn[2];
+    B.q[0] = q2[0]; B.q[1] = q2[1]; B.q[2] = q2[2]; B.q[3] = q2[3];
+    B.v[0] = vp[0]; B.v[1] = vp[1]; B.v[2] = vp[2];
+    B.f[0] = B.f[1] = B.f[2] = 0.f;
+
+    wkey = st.act ? st.key : -1;
+    wr[0] = st.act ? (float)r[0] : 0.f;
+    wr[1] = st.act ? (float)r[1] : 0.f;
+    wr[2] = st.act ? (float)r[2] : 0.f;
+    out_link = st.act ? st.link : -1;
+    out_imp[0] = (float)impS[0]; out_imp[1] = (float)impS[1]; out_imp[2] = (float)impS[2];
+}
+
+// one full step of one simulation
+template <typename SR>
+__device__ __forceinline__ void env_step(const Consts &P, const float *__restrict__ seg,
+                                         const float *__restrict__ sph, int S, const float *inv_in, Body &B,
+                                         int &wkey, float *wr, int &out_link, float *out_imp, const WaveLds &lds,
+                                         StepStats &stats)
+{
+    StepState<SR> st;
+    step_setup<SR>(P, seg, sph, S, inv_in, B, wkey, wr, lds, stats, st);
+    step_solve<SR>(P, st, B.mu);
+    step_finish<SR>(P, st, inv_in, B, wkey, wr, out_link, out_imp);
+}
+
+}  // namespace pt
