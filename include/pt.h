@@ -32,8 +32,11 @@
  *     float32/int32 memory (torch tensors) unless stated "host".
  *   - Every call is asynchronous on the given HIP stream; nothing here
  *     synchronises the device except pt_read_stats and pt_autotune.
- *   - Device memory is allocated only by pt_create_batch (scene tables,
- *     internal scratch) and freed by pt_destroy_batch.
+ *   - Device memory is allocated by pt_create_batch (scene tables, internal
+ *     scratch), by pt_autotune (scratch copies, freed before it returns) and
+ *     on first use by pt_window_grad / pt_refine_elites (checkpoints and
+ *     refinement buffers, grown on demand); pt_destroy_batch frees it all.
+ *     Calls that may allocate must not run under stream capture.
  *   - Return value: PT_OK (0) or an error code; pt_last_error() returns a
  *     thread-local message for the last failing call on that thread.
  *     Argument and shape errors are detected before any launch.  Kernel
@@ -188,6 +191,76 @@ PT_API pt_status pt_autotune(pt_batch b, const float *u_win, const float *obs_gt
  * simulations' LDS does not fit in one workgroup, or above 4 with the
  * float64 solve. */
 PT_API pt_status pt_set_tuning(pt_batch b, int32_t waves_per_workgroup);
+
+/* Gradient of the window cost of n listed simulations with respect to their
+ * window start.  The window cost is the sum over the window's T steps of the
+ * step cost of pt_cost (Eq. 3 terms, accumulated as in Eq. 1 and Alg. 1).
+ * The paper's optimisers are derivative-free (Sec. III-D); this gradient
+ * serves pt_refine_elites.  Each simulation runs the window from the given
+ * start exactly as pt_run_window does (the same bits for the same start),
+ * writing a checkpoint of its body and warm cache before every step; the
+ * reverse sweep re-runs each step from its checkpoint and propagates the
+ * adjoint through the cost, the observation, the integration and the
+ * contact solve.  The contact solve is differentiated implicitly: the
+ * computed impulses are taken as the root of the smoothed Fischer-Burmeister
+ * system, and its transposed Newton matrix is solved through the same 6x6
+ * Schur reduction as the forward solve.  The contact set, the cap and the
+ * branch choices of each step (tangent axis, clamps, depenetration) are held
+ * fixed: the result is the gradient of the smooth piece of the window map
+ * that contains the start.
+ *   u_win      [T+1][D]       as in pt_run_window
+ *   obs_gt_win [T][4][L][G]   as in pt_run_window
+ *   n          >= 0 simulations listed
+ *   env        [n] int32      batch index of each (gives its object type and
+ *                             group); an index outside [0, K) yields cost NaN
+ *                             and a zero gradient
+ *   start      [18][n]        x(3) q(4) v(3) omega(3) mass mu f_pert(3)
+ *   warm0      [n][C_max][4]  warm cache at the window start
+ *   cost       [n]            out: window cost
+ *   grad       [18][n]        out: d cost / d start (rows as start), or NULL
+ *                             for the cost alone (no checkpoints, no reverse
+ *                             sweep); the q rows are the gradient through the
+ *                             normalisation of q (orthogonal to q)
+ *   end_state  [13][n]        out: state after the window, or NULL
+ *   end_warm   [n][C_max][4]  out: warm cache after the window, or NULL
+ * The batch's own state, params and warm cache are neither read nor written.
+ * The checkpoints (n * T * (16 + 4 * C_max) floats) live in a buffer the
+ * batch owns and shares between calls: calls on different streams must not
+ * overlap. */
+PT_API pt_status pt_window_grad(pt_batch b, const float *u_win, const float *obs_gt_win, int32_t n,
+                                const int32_t *env, const float *start, const float *warm0, float *cost,
+                                float *grad, float *end_state, float *end_warm, pt_stream s);
+
+/* Elite refinement by the window-cost gradient, run between pt_run_window
+ * and pt_resample.  The elites of each group, ranked from cost_sum as
+ * pt_resample ranks them, take `steps` scaled gradient steps from their
+ * window start: delta = -rho (s o s o g) / |s o g| over (x, q, v, omega,
+ * mass, mu), rho starting at `step`; a trial is kept when its replayed window
+ * cost is lower than the current one, otherwise rho is halved; q is
+ * renormalised, mass and mu are clamped to [m_lo, m_hi] and [mu_lo, mu_hi],
+ * and f_pert is kept.  For each elite whose start changed, the batch's
+ * state, params (f_pert 0) and warm cache become the end of the kept replay
+ * and cost_sum its window cost; costs only decrease, so pt_resample keeps
+ * the same elites.
+ *   cost_sum       [K]   window costs from the pt_run_window just done
+ *   start_state [13][K], start_params [5][K], start_warm [K][C_max][4]:
+ *                        copies of the batch's buffers taken before it
+ *   steps          >= 0 gradient steps; step > 0
+ *   scale          host [15], or NULL for (1 mm x3, 0.01 x4, 1 cm/s x3,
+ *                  0.1 rad/s x3, 5 g, 0.02)
+ *   best           [G] argmin of cost_sum per group afterwards, or NULL
+ *   elite_out      [pt_elite_count(b)] int32 batch index of each elite
+ *                  (groups in order, by rank within a group), or NULL
+ * Buffers for the elites' starts, gradients and checkpoints are allocated on
+ * first use and kept by the batch. */
+PT_API pt_status pt_refine_elites(pt_batch b, const float *u_win, const float *obs_gt_win, float *cost_sum,
+                                  const float *start_state, const float *start_params, const float *start_warm,
+                                  int32_t steps, float step, const float *scale, int32_t *best, int32_t *elite_out,
+                                  pt_stream s);
+
+/* Number of elites over all groups, sum over g of max(1, floor(K_g *
+ * elite_frac)); -1 for a NULL batch. */
+PT_API int32_t pt_elite_count(pt_batch b);
 
 /* Reads the batch's cumulative counters (host out[4]): environment-steps,
  * narrow-phase candidates (d < margin), contacts solved, contacts dropped by

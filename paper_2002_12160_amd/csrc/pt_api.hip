@@ -65,6 +65,13 @@ struct pt_batch_s {
     float *d_seg = nullptr;      // [L][16]
     float *d_seg_win = nullptr;  // [T][L][16]
     float *d_contacts = nullptr; // [K][C_max][4]
+    float *d_seg_grad = nullptr; // [T][L][16] for the gradient and refinement calls
+    // gradient checkpoints and refinement buffers, grown on demand
+    float *d_ckpt = nullptr;
+    size_t ckpt_cap = 0;         // floats
+    int n_elite = 0;
+    int32_t *d_elite = nullptr;  // [n_elite]
+    float *d_ref = nullptr;      // see refine_layout
     // caller-owned state
     float *state, *params, *warm;
     // host copies
@@ -194,6 +201,7 @@ pt_status pt_create_batch(const pt_batch_desc *d, pt_batch *out)
     HIP_TRY_C(hipGetDevice(&b->device));
     HIP_TRY_C(hipDeviceGetAttribute(&b->num_cu, hipDeviceAttributeMultiprocessorCount, b->device));
     HIP_TRY_C(set_lds_limits(160 * 1024));
+    HIP_TRY_C(set_grad_lds_limits(160 * 1024));
 
     const size_t K = d->K;
     std::vector<int32_t> group_of(K), order(K);
@@ -218,6 +226,9 @@ pt_status pt_create_batch(const pt_batch_desc *d, pt_batch *out)
     HIP_TRY_C(hipMalloc(&b->d_seg, sizeof(float) * d->L * pt::SEG_STRIDE));
     HIP_TRY_C(hipMalloc(&b->d_seg_win, sizeof(float) * (size_t)d->T * d->L * pt::SEG_STRIDE));
     HIP_TRY_C(hipMalloc(&b->d_contacts, sizeof(float) * K * d->C_max * 4));
+    HIP_TRY_C(hipMalloc(&b->d_seg_grad, sizeof(float) * (size_t)d->T * d->L * pt::SEG_STRIDE));
+    for (int g = 0; g < d->G; ++g)
+        b->n_elite += pt::elite_count(d->group_start[g + 1] - d->group_start[g], d->elite_frac);
     HIP_TRY_C(hipMemcpy(b->d_hand, d->hand, sizeof(float) * d->L * PT_HAND_STRIDE, hipMemcpyHostToDevice));
     HIP_TRY_C(hipMemcpy(b->d_spheres, d->spheres, sizeof(float) * d->n_types * d->S_max * 4, hipMemcpyHostToDevice));
     HIP_TRY_C(hipMemcpy(b->d_inv, d->inv_inertia, sizeof(float) * d->n_types * 3, hipMemcpyHostToDevice));
@@ -246,7 +257,8 @@ pt_status pt_destroy_batch(pt_batch b)
     b->drop_graphs();
     if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
     void *ptrs[] = {b->d_hand, b->d_spheres, b->d_inv, b->d_nsph, b->d_type, b->d_group_of, b->d_group_start,
-                    b->d_order, b->d_queue, b->d_stats, b->d_seg, b->d_seg_win, b->d_contacts};
+                    b->d_order, b->d_queue, b->d_stats, b->d_seg, b->d_seg_win, b->d_contacts,
+                    b->d_seg_grad, b->d_ckpt, b->d_elite, b->d_ref};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete b;
@@ -441,6 +453,128 @@ pt_status pt_set_tuning(pt_batch b, int32_t wpb)
     b->wpb = wpb;
     return PT_OK;
 }
+
+// checkpoint buffer of at least `floats` floats (the stream is drained
+// before an old buffer is released)
+static pt_status ensure_ckpt(pt_batch b, size_t floats, hipStream_t st)
+{
+    if (b->ckpt_cap >= floats) return PT_OK;
+    if (b->d_ckpt) {
+        HIP_TRY(hipStreamSynchronize(st));
+        HIP_TRY(hipFree(b->d_ckpt));
+        b->d_ckpt = nullptr;
+        b->ckpt_cap = 0;
+    }
+    HIP_TRY(hipMalloc(&b->d_ckpt, sizeof(float) * floats));
+    b->ckpt_cap = floats;
+    return PT_OK;
+}
+
+static size_t ckpt_floats(const Consts &P, int n) { return (size_t)n * P.T * (16 + 4 * (size_t)P.C_max); }
+
+pt_status pt_window_grad(pt_batch b, const float *u_win, const float *obs_gt_win, int32_t n, const int32_t *env,
+                         const float *start, const float *warm0, float *cost, float *grad, float *end_state,
+                         float *end_warm, pt_stream s)
+{
+    if (!b) return fail(PT_E_ARG, "batch is NULL");
+    if (n < 0) return fail(PT_E_ARG, "n must be >= 0 (got %d)", n);
+    if (n == 0) return PT_OK;
+    if (!u_win || !obs_gt_win || !env || !start || !warm0 || !cost)
+        return fail(PT_E_ARG, "u_win/obs_gt_win/env/start/warm0/cost is NULL");
+    hipStream_t st = (hipStream_t)s;
+    const Consts &P = b->P;
+    if (grad) {
+        pt_status rc = ensure_ckpt(b, ckpt_floats(P, n), st);
+        if (rc != PT_OK) return rc;
+    }
+    HIP_TRY(launch_hand_fk(b->d_hand, P.L, P.dt, u_win, u_win + P.D, P.D, P.T, b->d_seg_grad, st));
+    HIP_TRY(launch_window_grad(P, tables_of(b), b->d_seg_grad, n, env, start, warm0, obs_gt_win, cost, grad, end_state,
+                               end_warm, grad ? b->d_ckpt : nullptr, st));
+    return PT_OK;
+}
+
+// refinement buffers of n elites, carved from one allocation
+struct RefineBufs {
+    float *xi, *xi_try, *g, *g_try, *cost, *cost_try, *rho, *end_state, *end_warm, *warm0;
+};
+
+static size_t refine_floats(const Consts &P, int n)
+{
+    const size_t w = (size_t)n * P.C_max * 4;
+    return 4 * (size_t)pt::XI_ROWS * n + 3 * (size_t)n + 13 * (size_t)n + 2 * w;
+}
+
+static RefineBufs refine_layout(float *base, const Consts &P, int n)
+{
+    RefineBufs r;
+    const size_t x = (size_t)pt::XI_ROWS * n, w = (size_t)n * P.C_max * 4;
+    r.xi = base;
+    r.xi_try = r.xi + x;
+    r.g = r.xi_try + x;
+    r.g_try = r.g + x;
+    r.cost = r.g_try + x;
+    r.cost_try = r.cost + n;
+    r.rho = r.cost_try + n;
+    r.end_state = r.rho + n;
+    r.end_warm = r.end_state + 13 * (size_t)n;  // after 88 n floats: 16-byte aligned
+    r.warm0 = r.end_warm + w;
+    return r;
+}
+
+pt_status pt_refine_elites(pt_batch b, const float *u_win, const float *obs_gt_win, float *cost_sum,
+                           const float *start_state, const float *start_params, const float *start_warm,
+                           int32_t steps, float step, const float *scale, int32_t *best, int32_t *elite_out,
+                           pt_stream s)
+{
+    if (!b) return fail(PT_E_ARG, "batch is NULL");
+    if (!u_win || !obs_gt_win || !cost_sum || !start_state || !start_params || !start_warm)
+        return fail(PT_E_ARG, "u_win/obs_gt_win/cost_sum/start_state/start_params/start_warm is NULL");
+    if (steps < 0) return fail(PT_E_ARG, "steps must be >= 0 (got %d)", steps);
+    if (!(step > 0.f) || !std::isfinite(step)) return fail(PT_E_ARG, "step must be positive and finite");
+    pt::RefineArgs A;
+    static const float kScale[15] = {1e-3f, 1e-3f, 1e-3f, 0.01f, 0.01f, 0.01f, 0.01f, 0.01f,
+                                     0.01f, 0.01f, 0.1f,  0.1f,  0.1f,  5e-3f, 0.02f};
+    for (int i = 0; i < 15; ++i) {
+        A.scale[i] = scale ? scale[i] : kScale[i];
+        if (!(A.scale[i] >= 0.f) || !std::isfinite(A.scale[i])) return fail(PT_E_ARG, "scale[%d] must be finite and >= 0", i);
+    }
+    A.m_lo = b->R.m_lo; A.m_hi = b->R.m_hi; A.mu_lo = b->R.mu_lo; A.mu_hi = b->R.mu_hi;
+    hipStream_t st = (hipStream_t)s;
+    const Consts &P = b->P;
+    const int n = b->n_elite;
+    if (!b->d_ref) {
+        HIP_TRY(hipMalloc(&b->d_ref, sizeof(float) * refine_floats(P, n)));
+        HIP_TRY(hipMalloc(&b->d_elite, sizeof(int32_t) * n));
+    }
+    pt_status rc = ensure_ckpt(b, ckpt_floats(P, n), st);
+    if (rc != PT_OK) return rc;
+    RefineBufs r = refine_layout(b->d_ref, P, n);
+    const Tables tb = tables_of(b);
+    HIP_TRY(launch_select_elites(P.G, b->R.elite_frac, b->d_group_start, cost_sum, b->d_elite, st));
+    if (elite_out)
+        HIP_TRY(hipMemcpyAsync(elite_out, b->d_elite, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, st));
+    if (steps > 0) {
+        HIP_TRY(launch_hand_fk(b->d_hand, P.L, P.dt, u_win, u_win + P.D, P.D, P.T, b->d_seg_grad, st));
+        HIP_TRY(launch_refine_gather(n, P.K, P.C_max, b->d_elite, start_state, start_params, start_warm, r.xi,
+                                     r.warm0, r.rho, step, st));
+        HIP_TRY(launch_window_grad(P, tb, b->d_seg_grad, n, b->d_elite, r.xi, r.warm0, obs_gt_win, r.cost, r.g,
+                                   nullptr, nullptr, b->d_ckpt, st));
+        for (int it = 0; it < steps; ++it) {
+            const bool last = it == steps - 1;
+            HIP_TRY(launch_refine_propose(n, A, r.xi, r.g, r.rho, r.xi_try, st));
+            HIP_TRY(launch_window_grad(P, tb, b->d_seg_grad, n, b->d_elite, r.xi_try, r.warm0, obs_gt_win,
+                                       r.cost_try, last ? nullptr : r.g_try, r.end_state, r.end_warm,
+                                       last ? nullptr : b->d_ckpt, st));
+            HIP_TRY(launch_refine_accept(n, P.K, P.C_max, b->d_elite, r.cost, r.cost_try, r.xi, r.xi_try, r.g,
+                                         last ? nullptr : r.g_try, r.rho, r.end_state, r.end_warm, b->state,
+                                         b->params, b->warm, cost_sum, st));
+        }
+    }
+    if (best) HIP_TRY(launch_argmin(P.G, b->d_group_start, cost_sum, best, st));
+    return PT_OK;
+}
+
+int32_t pt_elite_count(pt_batch b) { return b ? b->n_elite : -1; }
 
 pt_status pt_read_stats(pt_batch b, int64_t *out, pt_stream s)
 {

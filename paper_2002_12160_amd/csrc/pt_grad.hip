@@ -1,0 +1,329 @@
+// pt_grad.hip -- gradients of the window cost and the elite refinement built
+// on them.
+//
+//   k_window_grad     one wavefront per listed simulation: runs the window
+//                     from a given start (same step code as the other
+//                     kernels), writing a checkpoint of the body and warm
+//                     cache before every step; then walks the steps backwards,
+//                     re-running each from its checkpoint and applying the
+//                     step adjoint (implicit differentiation of the contact
+//                     solve).  Output: window cost and its gradient with
+//                     respect to the start (x, q, v, w, m, mu, f).
+//   k_select_elites   per group, the simulations of lowest window cost (the
+//                     same ranking the resampler keeps)
+//   k_refine_*        gather / scaled gradient step / accept-or-halve
+#include "pt_adjoint.hpp"
+#include "pt_internal.h"
+#include "pt_io.hpp"
+
+namespace pt {
+
+constexpr int CK_BODY = 16;  // checkpoint body record: x(3) q(4) v(3) w(3) f(3)
+
+__device__ __forceinline__ void save_ckpt(float *__restrict__ ck, int C_max, const Body &B, int wkey, const float *wr)
+{
+    const int lane = lane_id();
+    if (lane == 0) {
+        float4 *b4 = reinterpret_cast<float4 *>(ck);
+        b4[0] = make_float4(B.x[0], B.x[1], B.x[2], B.q[0]);
+        b4[1] = make_float4(B.q[1], B.q[2], B.q[3], B.v[0]);
+        b4[2] = make_float4(B.v[1], B.v[2], B.w[0], B.w[1]);
+        b4[3] = make_float4(B.w[2], B.f[0], B.f[1], B.f[2]);
+    }
+    if (lane < C_max)
+        *reinterpret_cast<float4 *>(ck + CK_BODY + WARM_STRIDE * lane) = make_float4(__int_as_float(wkey), wr[0], wr[1], wr[2]);
+}
+
+__device__ __forceinline__ void load_ckpt(const float *__restrict__ ck, int C_max, Body &B, int &wkey, float *wr)
+{
+    const int lane = lane_id();
+    const float4 *b4 = reinterpret_cast<const float4 *>(ck);
+    float4 a = b4[0], b = b4[1], c = b4[2], d = b4[3];
+    B.x[0] = a.x; B.x[1] = a.y; B.x[2] = a.z; B.q[0] = a.w;
+    B.q[1] = b.x; B.q[2] = b.y; B.q[3] = b.z; B.v[0] = b.w;
+    B.v[1] = c.x; B.v[2] = c.y; B.w[0] = c.z; B.w[1] = c.w;
+    B.w[2] = d.x; B.f[0] = d.y; B.f[1] = d.z; B.f[2] = d.w;
+    wkey = -1;
+    wr[0] = wr[1] = wr[2] = 0.f;
+    if (lane < C_max) {
+        float4 w = *reinterpret_cast<const float4 *>(ck + CK_BODY + WARM_STRIDE * lane);
+        wkey = __float_as_int(w.x);
+        wr[0] = w.y; wr[1] = w.z; wr[2] = w.w;
+    }
+}
+
+// xi is [18][n]: x(3) q(4) v(3) w(3) m mu f(3); warm0 is [n][C_max][4]
+template <typename SR>
+__global__ __launch_bounds__(WAVE) void k_window_grad(Consts P, Tables tb, const float *__restrict__ seg_win, int n,
+                                                      const int32_t *__restrict__ env, const float *__restrict__ xi,
+                                                      const float *__restrict__ warm0,
+                                                      const float *__restrict__ obs_gt_win, float *__restrict__ cost_out,
+                                                      float *__restrict__ grad, float *__restrict__ end_state,
+                                                      float *__restrict__ end_warm, float *__restrict__ ckpt)
+{
+    extern __shared__ __align__(16) char smem[];
+    const int i = blockIdx.x;
+    if (i >= n) return;
+    const int lane = lane_id();
+    const int e = env[i];
+    if (e < 0 || e >= P.K) {
+        // not a simulation of this batch: NaN cost, zero gradient
+        if (lane == 0) {
+            cost_out[i] = __int_as_float(0x7fc00000);
+            if (grad)
+                for (int r = 0; r < XI_ROWS; ++r) grad[(size_t)r * n + i] = 0.f;
+        }
+        return;
+    }
+    WaveLds lds = carve_lds(smem, 0, P.max_cand);
+    float *stage = contact_stage(lds);
+    const int type = tb.env_type[e];
+    const int g = tb.group_of[e];
+    const int S = tb.n_spheres[type];
+    const float *sph = tb.spheres + (size_t)type * P.S_max * 4;
+    const float *inv = tb.inv_inertia + 3 * type;
+    const size_t LG = (size_t)P.L * P.G;
+    const size_t CK = CK_BODY + (size_t)WARM_STRIDE * P.C_max;
+
+    Body B;
+    B.x[0] = xi[0 * (size_t)n + i]; B.x[1] = xi[1 * (size_t)n + i]; B.x[2] = xi[2 * (size_t)n + i];
+    B.q[0] = xi[3 * (size_t)n + i]; B.q[1] = xi[4 * (size_t)n + i]; B.q[2] = xi[5 * (size_t)n + i];
+    B.q[3] = xi[6 * (size_t)n + i];
+    B.v[0] = xi[7 * (size_t)n + i]; B.v[1] = xi[8 * (size_t)n + i]; B.v[2] = xi[9 * (size_t)n + i];
+    B.w[0] = xi[10 * (size_t)n + i]; B.w[1] = xi[11 * (size_t)n + i]; B.w[2] = xi[12 * (size_t)n + i];
+    B.m = xi[13 * (size_t)n + i]; B.mu = xi[14 * (size_t)n + i];
+    B.f[0] = xi[15 * (size_t)n + i]; B.f[1] = xi[16 * (size_t)n + i]; B.f[2] = xi[17 * (size_t)n + i];
+    const float m0 = B.m, mu0 = B.mu;
+    int wkey;
+    float wr[3];
+    load_warm(warm0, P.C_max, i, wkey, wr);
+    StepStats stt = {0, 0, 0};
+
+    // forward sweep (cost summed in the order of the other paths)
+    float cost = 0.f;
+    for (int t = 0; t < P.T; ++t) {
+        if (ckpt) save_ckpt(ckpt + ((size_t)i * P.T + t) * CK, P.C_max, B, wkey, wr);
+        int link;
+        float imp[3];
+        env_step<SR>(P, seg_win + (size_t)t * P.L * SEG_STRIDE, sph, S, inv, B, wkey, wr, link, imp, lds, stt);
+        *reinterpret_cast<float4 *>(stage + 4 * lane) = make_float4(__int_as_float(link), imp[0], imp[1], imp[2]);
+        wave_sync();
+        float o[4];
+        float cl = 0.f;
+        if (sensor_force(P, stage, o)) {
+            const float *gt = obs_gt_win + (size_t)t * 4 * LG;
+            float gv[4] = {gt[0 * LG + (size_t)lane * P.G + g], gt[1 * LG + (size_t)lane * P.G + g],
+                           gt[2 * LG + (size_t)lane * P.G + g], gt[3 * LG + (size_t)lane * P.G + g]};
+            cl = sensor_cost(P, o, gv);
+        }
+        wave_sync();
+        cost += step_cost_wave(P, cl);
+    }
+    if (lane == 0) {
+        cost_out[i] = cost;
+        if (end_state) {
+            const float v13[13] = {B.x[0], B.x[1], B.x[2], B.q[0], B.q[1], B.q[2], B.q[3],
+                                   B.v[0], B.v[1], B.v[2], B.w[0], B.w[1], B.w[2]};
+            for (int r = 0; r < 13; ++r) end_state[(size_t)r * n + i] = v13[r];
+        }
+    }
+    if (end_warm) store_warm(end_warm, P.C_max, i, wkey, wr);
+    if (!grad) return;
+
+    // reverse sweep: re-run each step from its checkpoint, then its adjoint
+    wave_sync();
+    BodyBar<SR> bar;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) bar.x[k] = bar.v[k] = bar.w[k] = SR(0);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) bar.q[k] = SR(0);
+    SR mbar = 0, mubar = 0, fbar[3] = {0, 0, 0};
+    for (int t = P.T - 1; t >= 0; --t) {
+        load_ckpt(ckpt + ((size_t)i * P.T + t) * CK, P.C_max, B, wkey, wr);
+        B.m = m0;
+        B.mu = mu0;
+        const float *seg = seg_win + (size_t)t * P.L * SEG_STRIDE;
+        StepState<SR> st;
+        step_setup<SR>(P, seg, sph, S, inv, B, wkey, wr, lds, stt, st);
+        step_solve<SR>(P, st, B.mu);
+        step_adjoint<SR>(P, seg, sph, inv, B, st, obs_gt_win + (size_t)t * 4 * LG, g, stage, lds.wr, bar, mbar,
+                         mubar, t == 0 ? fbar : nullptr);
+    }
+    if (lane == 0) {
+        const SR gv[XI_ROWS] = {bar.x[0], bar.x[1], bar.x[2], bar.q[0], bar.q[1], bar.q[2], bar.q[3],
+                                bar.v[0], bar.v[1], bar.v[2], bar.w[0], bar.w[1], bar.w[2],
+                                mbar,     mubar,    fbar[0],  fbar[1],  fbar[2]};
+        for (int r = 0; r < XI_ROWS; ++r) grad[(size_t)r * n + i] = (float)gv[r];
+    }
+}
+
+// one workgroup per group: its elites (lowest (cost, index), NaN ranked as
+// +inf; count max(1, floor(n elite_frac))) go to elite_env[offset + rank],
+// offset = number of elites of the lower groups
+__global__ __launch_bounds__(1024) void k_select_elites(int G, float elite_frac, const int32_t *__restrict__ group_start,
+                                                        const float *__restrict__ cost_sum, int32_t *__restrict__ elite_env)
+{
+    const int g = blockIdx.x;
+    if (g >= G) return;
+    int off = 0;
+    for (int h = 0; h < g; ++h) off += elite_count(group_start[h + 1] - group_start[h], elite_frac);
+    const int lo = group_start[g], n = group_start[g + 1] - lo;
+    const int kb = elite_count(n, elite_frac);
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        float ci = cost_sum[lo + i];
+        if (ci != ci) ci = __int_as_float(0x7f800000);
+        int rank = 0;
+        for (int j = 0; j < n; ++j) {
+            float cj = cost_sum[lo + j];
+            if (cj != cj) cj = __int_as_float(0x7f800000);
+            rank += (cj < ci || (cj == ci && j < i)) ? 1 : 0;
+        }
+        if (rank < kb) elite_env[off + rank] = lo + i;
+    }
+}
+
+// start of each listed simulation from the window-start snapshot
+__global__ void k_refine_gather(int n, int K, int C_max, const int32_t *__restrict__ env,
+                                const float *__restrict__ state, const float *__restrict__ params,
+                                const float *__restrict__ warm, float *__restrict__ xi, float *__restrict__ warm0,
+                                float *__restrict__ rho, float rho0)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int e = env[i];
+    if (e < 0 || e >= K) return;
+    for (int r = 0; r < 13; ++r) xi[(size_t)r * n + i] = state[(size_t)r * K + e];
+    for (int r = 0; r < 5; ++r) xi[(size_t)(13 + r) * n + i] = params[(size_t)r * K + e];
+    const float4 *src = reinterpret_cast<const float4 *>(warm + (size_t)e * C_max * WARM_STRIDE);
+    float4 *dst = reinterpret_cast<float4 *>(warm0 + (size_t)i * C_max * WARM_STRIDE);
+    for (int c = 0; c < C_max; ++c) dst[c] = src[c];
+    rho[i] = rho0;
+}
+
+// trial start: xi - rho (s o s o g) / |s o g| over (x, q, v, w, m, mu), then
+// q renormalised and m, mu clamped; the one-step force is kept
+__global__ void k_refine_propose(int n, RefineArgs A, const float *__restrict__ xi, const float *__restrict__ grad,
+                                 const float *__restrict__ rho, float *__restrict__ xi_try)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float x[XI_ROWS];
+    for (int r = 0; r < XI_ROWS; ++r) x[r] = xi[(size_t)r * n + i];
+    float sg2 = 0.f;
+    for (int r = 0; r < 15; ++r) {
+        float v = A.scale[r] * grad[(size_t)r * n + i];
+        sg2 += v * v;
+    }
+    const float nrm = sqrtf(sg2);
+    if (nrm > 0.f && nrm < __int_as_float(0x7f800000)) {
+        const float f = rho[i] / nrm;
+        for (int r = 0; r < 15; ++r) x[r] -= f * A.scale[r] * A.scale[r] * grad[(size_t)r * n + i];
+        const float qn = sqrtf(x[3] * x[3] + x[4] * x[4] + x[5] * x[5] + x[6] * x[6]);
+        if (qn > 0.f)
+            for (int r = 3; r < 7; ++r) x[r] /= qn;
+        x[13] = fminf(fmaxf(x[13], A.m_lo), A.m_hi);
+        x[14] = fminf(fmaxf(x[14], A.mu_lo), A.mu_hi);
+    }
+    for (int r = 0; r < XI_ROWS; ++r) xi_try[(size_t)r * n + i] = x[r];
+}
+
+// keep the trial where its replayed window cost is lower (the batch slot then
+// takes the replay's end-of-window state, mass, friction and warm cache, and
+// its window cost); otherwise halve the step
+__global__ void k_refine_accept(int n, int K, int C_max, const int32_t *__restrict__ env, float *__restrict__ cost_cur,
+                                const float *__restrict__ cost_try, float *__restrict__ xi,
+                                const float *__restrict__ xi_try, float *__restrict__ grad,
+                                const float *__restrict__ grad_try, float *__restrict__ rho,
+                                const float *__restrict__ end_state, const float *__restrict__ end_warm,
+                                float *__restrict__ state, float *__restrict__ params, float *__restrict__ warm,
+                                float *__restrict__ cost_sum)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int e = env[i];
+    if (e < 0 || e >= K) return;
+    const float ct = cost_try[i];
+    if (!(ct < cost_cur[i])) {
+        rho[i] *= 0.5f;
+        return;
+    }
+    cost_cur[i] = ct;
+    for (int r = 0; r < XI_ROWS; ++r) xi[(size_t)r * n + i] = xi_try[(size_t)r * n + i];
+    if (grad_try)
+        for (int r = 0; r < XI_ROWS; ++r) grad[(size_t)r * n + i] = grad_try[(size_t)r * n + i];
+    for (int r = 0; r < 13; ++r) state[(size_t)r * K + e] = end_state[(size_t)r * n + i];
+    params[0 * (size_t)K + e] = xi_try[13 * (size_t)n + i];
+    params[1 * (size_t)K + e] = xi_try[14 * (size_t)n + i];
+    params[2 * (size_t)K + e] = 0.f;
+    params[3 * (size_t)K + e] = 0.f;
+    params[4 * (size_t)K + e] = 0.f;
+    const float4 *src = reinterpret_cast<const float4 *>(end_warm + (size_t)i * C_max * WARM_STRIDE);
+    float4 *dst = reinterpret_cast<float4 *>(warm + (size_t)e * C_max * WARM_STRIDE);
+    for (int c = 0; c < C_max; ++c) dst[c] = src[c];
+    cost_sum[e] = ct;
+}
+
+}  // namespace pt
+
+using namespace pt;
+
+hipError_t launch_window_grad(const Consts &P, const Tables &tb, const float *seg_win, int n, const int32_t *env,
+                              const float *xi, const float *warm0, const float *obs_gt_win, float *cost, float *grad,
+                              float *end_state, float *end_warm, float *ckpt, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    size_t lds = wave_lds_bytes(P.max_cand);
+    if (P.solve_fp64)
+        hipLaunchKernelGGL(k_window_grad<double>, dim3(n), dim3(WAVE), lds, s, P, tb, seg_win, n, env, xi, warm0,
+                           obs_gt_win, cost, grad, end_state, end_warm, ckpt);
+    else
+        hipLaunchKernelGGL(k_window_grad<float>, dim3(n), dim3(WAVE), lds, s, P, tb, seg_win, n, env, xi, warm0,
+                           obs_gt_win, cost, grad, end_state, end_warm, ckpt);
+    return hipGetLastError();
+}
+
+hipError_t launch_select_elites(int G, float elite_frac, const int32_t *group_start, const float *cost_sum,
+                                int32_t *elite_env, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_select_elites, dim3(G), dim3(1024), 0, s, G, elite_frac, group_start, cost_sum, elite_env);
+    return hipGetLastError();
+}
+
+hipError_t launch_refine_gather(int n, int K, int C_max, const int32_t *env, const float *state, const float *params,
+                                const float *warm, float *xi, float *warm0, float *rho, float rho0, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_refine_gather, dim3((n + 63) / 64), dim3(64), 0, s, n, K, C_max, env, state, params, warm,
+                       xi, warm0, rho, rho0);
+    return hipGetLastError();
+}
+
+hipError_t launch_refine_propose(int n, const RefineArgs &A, const float *xi, const float *grad, const float *rho,
+                                 float *xi_try, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_refine_propose, dim3((n + 63) / 64), dim3(64), 0, s, n, A, xi, grad, rho, xi_try);
+    return hipGetLastError();
+}
+
+hipError_t launch_refine_accept(int n, int K, int C_max, const int32_t *env, float *cost_cur, const float *cost_try,
+                                float *xi, const float *xi_try, float *grad, const float *grad_try, float *rho,
+                                const float *end_state, const float *end_warm, float *state, float *params,
+                                float *warm, float *cost_sum, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_refine_accept, dim3((n + 63) / 64), dim3(64), 0, s, n, K, C_max, env, cost_cur, cost_try,
+                       xi, xi_try, grad, grad_try, rho, end_state, end_warm, state, params, warm, cost_sum);
+    return hipGetLastError();
+}
+
+hipError_t set_grad_lds_limits(size_t bytes)
+{
+    const void *fs[] = {reinterpret_cast<const void *>(k_window_grad<float>),
+                        reinterpret_cast<const void *>(k_window_grad<double>)};
+    for (const void *f : fs) {
+        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}

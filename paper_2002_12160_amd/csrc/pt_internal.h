@@ -18,6 +18,23 @@ struct ResampleArgs {
     uint64_t seed;
 };
 
+// refinement step: per-component scales of the gradient step over
+// (x(3), q(4), v(3), w(3), m, mu) and the clamp ranges of m and mu
+struct RefineArgs {
+    float scale[15];
+    float m_lo, m_hi, mu_lo, mu_hi;
+};
+
+// rows of a window start: x(3) q(4) v(3) w(3) m mu f(3)
+constexpr int XI_ROWS = 18;
+
+// elites kept per group of n simulations: max(1, floor(n elite_frac)), at most n
+__host__ __device__ inline int elite_count(int n, float elite_frac)
+{
+    int kb = (int)floorf((float)n * elite_frac);
+    return kb < 1 ? 1 : (kb > n ? n : kb);
+}
+
 // bytes of LDS per wavefront: candidate (d, key) list, selected keys,
 // previous warm keys and impulses, contact staging for the observation
 __host__ __device__ constexpr size_t wave_lds_bytes(int max_cand)
@@ -45,3 +62,17 @@ hipError_t launch_window(const pt::Consts &P, const pt::Tables &tb, const float 
                          hipStream_t s);
 hipError_t window_occupancy(int waves_per_block, int max_cand, bool fp64, int *blocks_per_cu);
 hipError_t set_lds_limits(size_t bytes);
+hipError_t set_grad_lds_limits(size_t bytes);
+hipError_t launch_window_grad(const pt::Consts &P, const pt::Tables &tb, const float *seg_win, int n,
+                              const int32_t *env, const float *xi, const float *warm0, const float *obs_gt_win,
+                              float *cost, float *grad, float *end_state, float *end_warm, float *ckpt, hipStream_t s);
+hipError_t launch_select_elites(int G, float elite_frac, const int32_t *group_start, const float *cost_sum,
+                                int32_t *elite_env, hipStream_t s);
+hipError_t launch_refine_gather(int n, int K, int C_max, const int32_t *env, const float *state, const float *params,
+                                const float *warm, float *xi, float *warm0, float *rho, float rho0, hipStream_t s);
+hipError_t launch_refine_propose(int n, const pt::RefineArgs &A, const float *xi, const float *grad, const float *rho,
+                                 float *xi_try, hipStream_t s);
+hipError_t launch_refine_accept(int n, int K, int C_max, const int32_t *env, float *cost_cur, const float *cost_try,
+                                float *xi, const float *xi_try, float *grad, const float *grad_try, float *rho,
+                                const float *end_state, const float *end_warm, float *state, float *params,
+                                float *warm, float *cost_sum, hipStream_t s);

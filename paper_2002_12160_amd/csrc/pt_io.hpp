@@ -1,0 +1,126 @@
+// pt_io.hpp -- per-simulation helpers shared by the step, window and
+// adjoint kernels: workgroup numbering, LDS carving, state and warm-cache
+// I/O, sensor forces and the step cost.
+#pragma once
+
+#include "pt_internal.h"
+
+namespace pt {
+
+// Workgroups are dealt round-robin over the 8 XCDs, each with its own L2.
+// Renumber them so that consecutive logical workgroups (hence consecutive
+// simulations, whose SoA state shares cache lines) run on the same XCD.
+constexpr int N_XCD = 8;
+__device__ __forceinline__ int xcd_block(int b, int nb)
+{
+    const int xcd = b % N_XCD, idx = b / N_XCD;
+    const int per = nb / N_XCD, rem = nb % N_XCD;
+    return xcd * per + (xcd < rem ? xcd : rem) + idx;
+}
+
+__device__ __forceinline__ WaveLds carve_lds(char *base, int wave_in_block, int max_cand)
+{
+    char *p = base + (size_t)wave_in_block * wave_lds_bytes(max_cand);
+    WaveLds w;
+    w.cand_d = reinterpret_cast<float *>(p);
+    w.cand_k = reinterpret_cast<int *>(p + 4 * (size_t)max_cand);
+    w.sel = reinterpret_cast<int *>(p + 8 * (size_t)max_cand);
+    w.wkey = w.sel + WAVE;
+    w.wr = reinterpret_cast<float *>(w.wkey + WAVE);
+    return w;
+}
+
+__device__ __forceinline__ float *contact_stage(const WaveLds &w) { return w.wr + 3 * WAVE; }  // [64][4]
+
+__device__ __forceinline__ void load_body(const float *__restrict__ state, const float *__restrict__ params, int K,
+                                          int e, Body &B)
+{
+    B.x[0] = state[0 * K + e]; B.x[1] = state[1 * K + e]; B.x[2] = state[2 * K + e];
+    B.q[0] = state[3 * K + e]; B.q[1] = state[4 * K + e]; B.q[2] = state[5 * K + e]; B.q[3] = state[6 * K + e];
+    B.v[0] = state[7 * K + e]; B.v[1] = state[8 * K + e]; B.v[2] = state[9 * K + e];
+    B.w[0] = state[10 * K + e]; B.w[1] = state[11 * K + e]; B.w[2] = state[12 * K + e];
+    B.m = params[0 * K + e]; B.mu = params[1 * K + e];
+    B.f[0] = params[2 * K + e]; B.f[1] = params[3 * K + e]; B.f[2] = params[4 * K + e];
+}
+
+__device__ __forceinline__ void store_body(float *__restrict__ state, float *__restrict__ params, int K, int e,
+                                           const Body &B)
+{
+    if (lane_id() == 0) {
+        state[0 * K + e] = B.x[0]; state[1 * K + e] = B.x[1]; state[2 * K + e] = B.x[2];
+        state[3 * K + e] = B.q[0]; state[4 * K + e] = B.q[1]; state[5 * K + e] = B.q[2]; state[6 * K + e] = B.q[3];
+        state[7 * K + e] = B.v[0]; state[8 * K + e] = B.v[1]; state[9 * K + e] = B.v[2];
+        state[10 * K + e] = B.w[0]; state[11 * K + e] = B.w[1]; state[12 * K + e] = B.w[2];
+        params[2 * K + e] = B.f[0]; params[3 * K + e] = B.f[1]; params[4 * K + e] = B.f[2];
+    }
+}
+
+__device__ __forceinline__ void load_warm(const float *__restrict__ warm, int C_max, int e, int &wkey, float *wr)
+{
+    const int lane = lane_id();
+    wkey = -1;
+    wr[0] = wr[1] = wr[2] = 0.f;
+    if (lane < C_max) {
+        float4 w = *reinterpret_cast<const float4 *>(warm + ((size_t)e * C_max + lane) * WARM_STRIDE);
+        wkey = __float_as_int(w.x);
+        wr[0] = w.y; wr[1] = w.z; wr[2] = w.w;
+    }
+}
+
+__device__ __forceinline__ void store_warm(float *__restrict__ warm, int C_max, int e, int wkey, const float *wr)
+{
+    const int lane = lane_id();
+    if (lane < C_max)
+        *reinterpret_cast<float4 *>(warm + ((size_t)e * C_max + lane) * WARM_STRIDE) =
+            make_float4(__int_as_float(wkey), wr[0], wr[1], wr[2]);
+}
+
+__device__ __forceinline__ void flush_stats(int64_t *stats, const StepStats &st, int64_t steps)
+{
+    if (lane_id() == 0) {
+        atomicAdd((unsigned long long *)&stats[0], (unsigned long long)steps);
+        atomicAdd((unsigned long long *)&stats[1], (unsigned long long)st.cand);
+        atomicAdd((unsigned long long *)&stats[2], (unsigned long long)st.contacts);
+        atomicAdd((unsigned long long *)&stats[3], (unsigned long long)st.dropped);
+    }
+}
+
+// per-sensor force from the contacts staged in LDS ([64][4]: link bits,
+// impulse on the object), summed in contact order; lane l < L gets
+// (|c_l|, c_hat_l).  Returns false on lanes >= L.
+__device__ __forceinline__ bool sensor_force(const Consts &P, const float *stage, float *o)
+{
+    const int lane = lane_id();
+    float f0 = 0.f, f1 = 0.f, f2 = 0.f;
+    for (int c = 0; c < P.C_max; ++c) {
+        const float4 rec = *reinterpret_cast<const float4 *>(stage + 4 * c);
+        if (__float_as_int(rec.x) == lane) {
+            f0 += rec.y; f1 += rec.z; f2 += rec.w;
+        }
+    }
+    float idt = 1.f / P.dt;
+    f0 = -f0 * idt; f1 = -f1 * idt; f2 = -f2 * idt;
+    float mag = sqrtf(f0 * f0 + f1 * f1 + f2 * f2);
+    bool on = mag > P.tau_contact;
+    float im = on ? 1.f / mag : 0.f;
+    o[0] = mag; o[1] = on ? f0 * im : 0.f; o[2] = on ? f1 * im : 0.f; o[3] = on ? f2 * im : 0.f;
+    return lane < P.L;
+}
+
+__device__ __forceinline__ float sensor_cost(const Consts &P, const float *o, const float *gt)
+{
+    float dm = o[0] - gt[0];
+    float d1 = o[1] - gt[1], d2 = o[2] - gt[2], d3 = o[3] - gt[3];
+    return P.w_mag * dm * dm + P.w_dir * (d1 * d1 + d2 * d2 + d3 * d3);
+}
+
+// step cost of one simulation from its sensors' terms held one per lane
+// (lane l < L), summed in sensor order; shared by the plain and batched paths
+__device__ __forceinline__ float step_cost_wave(const Consts &P, float cl)
+{
+    float cs = 0.f;
+    for (int l = 0; l < P.L; ++l) cs += bcast_lane(cl, l);
+    return cs;
+}
+
+}  // namespace pt

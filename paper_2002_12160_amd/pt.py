@@ -6,7 +6,9 @@ when the library has not been built -- there is no fallback.
 
 Names follow the C ABI: ``pt_create_batch``, ``pt_step``, ``pt_observe``,
 ``pt_cost``, ``pt_resample``, ``pt_run_window``, ``pt_autotune``,
-``pt_read_stats``; :class:`Batch` bundles a handle with its tensors.
+``pt_window_grad``, ``pt_refine_elites``, ``pt_read_stats``; :class:`Batch`
+bundles a handle with its tensors and :class:`WindowFn` exposes the window
+cost and its adjoint to ``torch.autograd``.
 """
 from __future__ import annotations
 
@@ -68,8 +70,13 @@ _lib.pt_run_window.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, C.c_int32, _vp]
 _lib.pt_autotune.argtypes = [_vp, _vp, _vp, C.POINTER(C.c_int32), _vp]
 _lib.pt_read_stats.argtypes = [_vp, C.POINTER(C.c_int64), _vp]
 _lib.pt_set_tuning.argtypes = [_vp, C.c_int32]
+_lib.pt_window_grad.argtypes = [_vp, _vp, _vp, C.c_int32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+_lib.pt_refine_elites.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp, C.c_int32, C.c_float, _vp, _vp, _vp, _vp]
+_lib.pt_elite_count.argtypes = [_vp]
+_lib.pt_elite_count.restype = C.c_int32
 for _f in ("pt_create_batch", "pt_destroy_batch", "pt_step", "pt_observe", "pt_cost", "pt_resample",
-           "pt_run_window", "pt_autotune", "pt_read_stats", "pt_set_tuning"):
+           "pt_run_window", "pt_autotune", "pt_read_stats", "pt_set_tuning", "pt_window_grad",
+           "pt_refine_elites"):
     getattr(_lib, _f).restype = C.c_int
 
 
@@ -134,6 +141,29 @@ def pt_autotune(h, u_win, obs_gt_win, stream=None):
 
 def pt_set_tuning(h, waves_per_workgroup):
     _check(_lib.pt_set_tuning(h, int(waves_per_workgroup)), "pt_set_tuning")
+
+
+def pt_window_grad(h, u_win, obs_gt_win, env, start, warm0, cost, grad=None, end_state=None, end_warm=None,
+                   stream=None):
+    n = int(env.shape[0])
+    _check(_lib.pt_window_grad(h, _ptr(u_win), _ptr(obs_gt_win), n, _ptr(env), _ptr(start), _ptr(warm0), _ptr(cost),
+                               _ptr(grad), _ptr(end_state), _ptr(end_warm), _stream(stream)), "pt_window_grad")
+
+
+def pt_refine_elites(h, u_win, obs_gt_win, cost_sum, start_state, start_params, start_warm, steps=3, step=0.5,
+                     scale=None, best=None, elite_out=None, stream=None):
+    sc = None
+    if scale is not None:
+        arr = np.ascontiguousarray(scale, dtype=np.float32)
+        assert arr.shape == (15,)
+        sc = C.c_void_p(arr.ctypes.data)
+    _check(_lib.pt_refine_elites(h, _ptr(u_win), _ptr(obs_gt_win), _ptr(cost_sum), _ptr(start_state),
+                                 _ptr(start_params), _ptr(start_warm), int(steps), float(step), sc, _ptr(best),
+                                 _ptr(elite_out), _stream(stream)), "pt_refine_elites")
+
+
+def pt_elite_count(h):
+    return int(_lib.pt_elite_count(h))
 
 
 def pt_read_stats(h, stream=None):
@@ -267,6 +297,40 @@ class Batch:
     def set_tuning(self, waves_per_workgroup):
         pt_set_tuning(self.handle, waves_per_workgroup)
 
+    # -- gradients and elite refinement -------------------------------------
+    def start_of(self, env, state=None, params=None, warm=None):
+        """Window start [18][n] and warm cache [n][C_max][4] of the listed
+        simulations, gathered from the batch's buffers (or the given copies)."""
+        state = self.state if state is None else state
+        params = self.params if params is None else params
+        warm = self.warm if warm is None else warm
+        idx = env.long()
+        return torch.cat([state[:, idx], params[:, idx]]).contiguous(), warm[idx].contiguous()
+
+    def window_grad(self, u_win, obs_gt_win, env, start, warm0, want_grad=True, want_end=False, stream=None):
+        n = int(env.shape[0])
+        dev = self.device
+        cost = torch.empty(n, dtype=torch.float32, device=dev)
+        grad = torch.empty((18, n), dtype=torch.float32, device=dev) if want_grad else None
+        end_state = torch.empty((13, n), dtype=torch.float32, device=dev) if want_end else None
+        end_warm = torch.empty((n, self.C_max, 4), dtype=torch.float32, device=dev) if want_end else None
+        pt_window_grad(self.handle, u_win, obs_gt_win, env, start, warm0, cost, grad, end_state, end_warm, stream)
+        return cost, grad, end_state, end_warm
+
+    def snapshot(self):
+        """Copies of (state, params, warm) to pass as a window start."""
+        return self.state.clone(), self.params.clone(), self.warm.clone()
+
+    def elite_count(self):
+        return pt_elite_count(self.handle)
+
+    def refine_elites(self, u_win, obs_gt_win, cost_sum, start, steps=3, step=0.5, scale=None, best=None,
+                      stream=None):
+        elites = torch.empty(self.elite_count(), dtype=torch.int32, device=self.device)
+        pt_refine_elites(self.handle, u_win, obs_gt_win, cost_sum, start[0], start[1], start[2], steps, step, scale,
+                         best, elites, stream)
+        return elites
+
     def read_stats(self, stream=None):
         return pt_read_stats(self.handle, stream)
 
@@ -280,3 +344,26 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+class WindowFn(torch.autograd.Function):
+    """Window cost of listed simulations as a differentiable function of their
+    window start: ``cost = WindowFn.apply(start, batch, env, warm0, u_win,
+    obs_gt_win)`` with start [18][n] (x, q, v, omega, mass, mu, f_pert).  The
+    forward pass runs pt_window_grad (forward sweep with checkpoints and the
+    reverse sweep) and keeps d cost / d start; backward scales it by the
+    incoming gradient of each simulation's cost."""
+
+    @staticmethod
+    def forward(ctx, start, batch, env, warm0, u_win, obs_gt_win):
+        cost, grad, _, _ = batch.window_grad(u_win, obs_gt_win, env, start.detach().contiguous(), warm0,
+                                             want_grad=ctx.needs_input_grad[0])
+        ctx.save_for_backward(grad if grad is not None else cost.new_empty(0))
+        return cost
+
+    @staticmethod
+    def backward(ctx, grad_cost):
+        (g,) = ctx.saved_tensors
+        if g.numel() == 0:
+            return (None,) * 6
+        return g * grad_cost.unsqueeze(0), None, None, None, None, None

@@ -28,7 +28,8 @@ def lib():
 def test_header_declares_the_boundary():
     syms = declared_symbols()
     for name in ("pt_create_batch", "pt_destroy_batch", "pt_step", "pt_observe", "pt_cost", "pt_resample",
-                 "pt_run_window", "pt_autotune", "pt_read_stats", "pt_set_tuning", "pt_last_error"):
+                 "pt_run_window", "pt_autotune", "pt_read_stats", "pt_set_tuning", "pt_last_error",
+                 "pt_window_grad", "pt_refine_elites", "pt_elite_count"):
         assert name in syms
 
 
@@ -108,3 +109,15 @@ def test_null_handles_are_rejected(lib):
     assert pt._lib.pt_step(None, None, None, None) == 1
     assert pt._lib.pt_observe(None, None, None) == 1
     assert pt._lib.pt_destroy_batch(None) == 0
+
+
+def test_gradient_calls_reject_a_null_batch(lib):
+    # argument errors come back before any device call
+    lib.pt_window_grad.restype = C.c_int
+    lib.pt_refine_elites.restype = C.c_int
+    lib.pt_elite_count.restype = C.c_int32
+    lib.pt_elite_count.argtypes = [C.c_void_p]
+    assert lib.pt_window_grad(None, None, None, 0, None, None, None, None, None, None, None, None) == 1
+    assert lib.pt_refine_elites(None, None, None, None, None, None, None, 3, C.c_float(0.5), None, None, None,
+                                None) == 1
+    assert lib.pt_elite_count(None) == -1

@@ -1,0 +1,306 @@
+"""Window-cost gradients of the HIP path (pt_window_grad, its reverse sweep
+with implicit differentiation of the contact solve) against central finite
+differences of the FP64 oracle's window cost; the forward sweep against
+pt_run_window; torch.autograd through WindowFn; the elite refinement.
+
+Finite-difference reference: the oracle in converged mode (Newton run to
+|Phi|^2 < 1e-26, so its window cost is the exact function the implicit
+adjoint differentiates), central differences with h = 1e-6 per start
+component (cold warm start on both sides).  A component is compared where
+the window map is smooth across the stencil: the h and 4h differences agree
+to 1e-4 of the environment's largest gradient entry (a contact that appears
+or vanishes inside the stencil breaks this).  Bar: |g - fd| <= 1e-3 |fd| +
+1e-3 max|fd| over the environment's 18 components."""
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2002_12160_amd import scene as S
+from tests import parity_util as PU
+
+pytestmark = pytest.mark.gpu
+
+FD_H = 1e-6
+GRAD_RTOL = 1e-3
+
+
+@pytest.fixture(scope="module")
+def pt():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2002_12160_amd import pt as _pt
+    return _pt
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _cold_warm(n, C_max):
+    w = np.zeros((n, C_max, 4), dtype=np.float32)
+    w[:, :, 0] = np.full((n, C_max), -1, dtype=np.int32).view(np.float32)
+    return torch.as_tensor(w, device="cuda")
+
+
+def window_case(cfg_name, K, W0, T):
+    """Mid-trajectory window starts: the oracle tracker runs W0 steps from the
+    scene's initial population (no resampling), its float32-rounded state is
+    the start; the observed batch's forces over the next T steps are the
+    window's observation."""
+    cfg = S.CONFIGS[cfg_name].with_(T=10 ** 6)
+    sc = S.round_to_f32(S.make_scene(cfg, K=K, steps=W0 + T))
+    tr = oracle.Tracker(sc)
+    for _ in range(W0):
+        tr.step()
+    st0, pr0 = PU.f32(tr.state), PU.f32(tr.params)
+    gts = [tr.step()["obs_gt"] for _ in range(T)]
+    gt = PU.f32(np.stack(gts))                            # [T][G][L][4]
+    u_win = PU.f32(sc.u[W0 - 1:W0 + T])                   # [T+1][D]
+    return sc, st0, pr0, gt, u_win
+
+
+def _gpu_inputs(st0, pr0, gt, u_win, C_max):
+    start = torch.as_tensor(np.concatenate([st0.T, pr0.T]).astype(np.float32), device="cuda").contiguous()
+    gt_t = torch.as_tensor(gt.transpose(0, 3, 2, 1).astype(np.float32).copy(), device="cuda")
+    u_t = torch.as_tensor(u_win.astype(np.float32), device="cuda")
+    return start, _cold_warm(st0.shape[0], C_max), u_t, gt_t
+
+
+def oracle_fd(sc, st0, pr0, gt, u_win, envs, h=FD_H):
+    """Central differences of the converged oracle's window cost: returns the
+    base costs, fd(h) and fd(4h), each [n][18]."""
+    o = oracle.Oracle.from_scene(sc, converged=True)
+    g_of = np.searchsorted(sc.group_start, np.arange(sc.K), side="right") - 1
+
+    def wc(j, x):
+        return o.window_cost(sc.env_type[j], x[:13], x[13:], u_win, gt[:, g_of[j]])
+
+    tasks = []
+    for a, j in enumerate(envs):
+        x0 = np.concatenate([st0[j], pr0[j]])
+        tasks.append((a, -1, 0.0, x0))
+        for c in range(18):
+            for s in (h, -h, 4 * h, -4 * h):
+                x = x0.copy()
+                x[c] += s
+                tasks.append((a, c, s, x))
+    with ThreadPoolExecutor(8) as ex:
+        vals = list(ex.map(lambda tk: wc(envs[tk[0]], tk[3]), tasks))
+    n = len(envs)
+    base = np.zeros(n)
+    fp = {}
+    for (a, c, s, _), v in zip(tasks, vals):
+        if c < 0:
+            base[a] = v
+        else:
+            fp[(a, c, s)] = v
+    fd1 = np.zeros((n, 18))
+    fd4 = np.zeros((n, 18))
+    for a in range(n):
+        for c in range(18):
+            fd1[a, c] = (fp[(a, c, h)] - fp[(a, c, -h)]) / (2 * h)
+            fd4[a, c] = (fp[(a, c, 4 * h)] - fp[(a, c, -4 * h)]) / (8 * h)
+    return base, fd1, fd4
+
+
+def compare_grad(g, fd1, fd4):
+    """Per (env, component): smooth?, within the bar?"""
+    scale = np.maximum(np.abs(fd1).max(axis=1, keepdims=True), 1e-12)
+    smooth = np.abs(fd1 - fd4) <= 1e-4 * scale
+    ok = np.abs(g - fd1) <= GRAD_RTOL * np.abs(fd1) + GRAD_RTOL * scale
+    return smooth, ok
+
+
+@pytest.mark.parametrize("cfg_name,K,W0", [("adjoint1024", 8, 15), ("small", 8, 20)])
+def test_window_grad_matches_oracle_fd(pt, cfg_name, K, W0):
+    T = 10
+    _say(f"window gradient vs oracle finite differences: {cfg_name} K={K} start step {W0} T={T}")
+    sc, st0, pr0, gt, u_win = window_case(cfg_name, K, W0, T)
+    # cold-started solves of a squeezed object can need more than 40
+    # iterations to converge; 100 matches the converged oracle on these cases
+    b = pt.Batch.from_scene(sc, T=T, newton_iters=100)
+    start, warm0, u_t, gt_t = _gpu_inputs(st0, pr0, gt, u_win, sc.cfg.C_max)
+    env = torch.arange(K, dtype=torch.int32, device="cuda")
+    cost, grad, _, _ = b.window_grad(u_t, gt_t, env, start, warm0)
+    torch.cuda.synchronize()
+    g = grad.cpu().numpy().T.astype(np.float64)          # [K][18]
+    c_gpu = cost.cpu().numpy().astype(np.float64)
+    b.close()
+    base, fd1, fd4 = oracle_fd(sc, st0, pr0, gt, u_win, list(range(K)))
+    smooth, ok = compare_grad(g, fd1, fd4)
+    names = ["x0", "x1", "x2", "qw", "qx", "qy", "qz", "v0", "v1", "v2", "w0", "w1", "w2", "m", "mu", "f0", "f1", "f2"]
+    for a in range(K):
+        bad = [f"{names[c]}: gpu {g[a, c]:.6e} fd {fd1[a, c]:.6e} (4h {fd4[a, c]:.6e})"
+               for c in range(18) if smooth[a, c] and not ok[a, c]]
+        _say(f"env {a}: cost gpu {c_gpu[a]:.6e} oracle {base[a]:.6e}; smooth {int(smooth[a].sum())}/18; "
+             f"outside {len(bad)}" + ("; " + "; ".join(bad[:6]) if bad else ""))
+    np.testing.assert_allclose(c_gpu, base, rtol=1e-4, atol=1e-6)
+    assert smooth.sum() >= 0.75 * smooth.size, "too few smooth components to check"
+    assert np.all(ok[smooth]), f"{int((~ok & smooth).sum())} of {int(smooth.sum())} components outside the bar"
+    assert np.abs(fd1).max() > 0, "vacuous: zero gradient everywhere"
+
+
+def test_window_grad_without_contact_is_zero(pt):
+    # an object far above the hand never touches anything: every sensor reads
+    # 0 whatever the start, so the window cost is constant and its gradient 0
+    _say("window gradient of a contact-free window")
+    T = 10
+    sc, st0, pr0, gt, u_win = window_case("small", 4, 5, T)
+    st0 = st0.copy()
+    st0[:, 2] += 5.0
+    b = pt.Batch.from_scene(sc, T=T)
+    start, warm0, u_t, gt_t = _gpu_inputs(st0, pr0, gt, u_win, sc.cfg.C_max)
+    env = torch.arange(4, dtype=torch.int32, device="cuda")
+    cost, grad, _, _ = b.window_grad(u_t, gt_t, env, start, warm0)
+    torch.cuda.synchronize()
+    assert torch.count_nonzero(grad).item() == 0
+    # cost = sum over steps and sensors of w_mag |gt|^2 + w_dir |gt_hat|^2
+    c = sc.cfg.consts
+    g_of = np.searchsorted(sc.group_start, np.arange(4), side="right") - 1
+    ref = [(c.w_mag * gt[:, g, :, 0] ** 2 + c.w_dir * (gt[:, g, :, 1:] ** 2).sum(-1)).sum() for g in g_of]
+    np.testing.assert_allclose(cost.cpu().numpy(), ref, rtol=1e-5)
+    b.close()
+
+
+def _window_setup(pt, cfg_name, K, T, steps_before=0):
+    cfg = S.CONFIGS[cfg_name]
+    sc = S.make_scene(cfg.with_(T=T), K=K, steps=steps_before + 2 * T)
+    b = pt.Batch.from_scene(sc)
+    h = pt.Batch.from_scene(sc, hidden=True)
+    return sc, b, h
+
+
+def test_window_grad_forward_is_run_window(pt):
+    # the forward sweep is the batched window's own step code: same bits for
+    # the cost, the end state and the warm cache, with and without gradient
+    _say("pt_window_grad forward sweep vs pt_run_window, bitwise")
+    T = 10
+    sc, b, h = _window_setup(pt, "small", 37, T)
+    u_t = torch.as_tensor(np.array([sc.u[0]] + [sc.u[t] for t in range(T)], dtype=np.float32), device="cuda")
+    gtw = torch.zeros((T, 4, sc.L, sc.G), device="cuda")
+    costh = torch.zeros(sc.G, device="cuda")
+    h.run_window(u_t, torch.zeros_like(gtw), costh, None, gtw, graph=False)
+    env = torch.arange(sc.K, dtype=torch.int32, device="cuda")
+    start, warm0 = b.start_of(env)
+    cost_sum = torch.zeros(sc.K, device="cuda")
+    b.run_window(u_t, gtw, cost_sum, None, None, graph=False)
+    for want_grad in (False, True):
+        cost, grad, end_state, end_warm = b.window_grad(u_t, gtw, env, start, warm0, want_grad=want_grad,
+                                                        want_end=True)
+        torch.cuda.synchronize()
+        assert torch.equal(cost.view(torch.int32), cost_sum.view(torch.int32))
+        assert torch.equal(end_state.view(torch.int32), b.state.view(torch.int32))
+        assert torch.equal(end_warm.view(torch.int32), b.warm.view(torch.int32))
+        if want_grad:
+            assert bool(torch.isfinite(grad).all())
+    # listed out-of-range simulation: NaN cost, zero gradient, others unaffected
+    env2 = torch.tensor([3, sc.K, -1, 5], dtype=torch.int32, device="cuda")
+    st2, w2 = b.start_of(torch.tensor([3, 0, 0, 5], dtype=torch.int32, device="cuda"), start[:13], start[13:], warm0)
+    cost2, grad2, _, _ = b.window_grad(u_t, gtw, env2, st2, w2)
+    torch.cuda.synchronize()
+    c2 = cost2.cpu().numpy()
+    assert np.isnan(c2[1]) and np.isnan(c2[2])
+    assert c2[0] == cost_sum[3].item() and c2[3] == cost_sum[5].item()
+    assert torch.count_nonzero(grad2[:, 1:3]).item() == 0
+    b.close()
+    h.close()
+
+
+def test_window_fn_autograd(pt):
+    _say("torch.autograd through WindowFn")
+    T = 10
+    sc, st0, pr0, gt, u_win = window_case("adjoint1024", 6, 15, T)
+    b = pt.Batch.from_scene(sc, T=T)
+    start, warm0, u_t, gt_t = _gpu_inputs(st0, pr0, gt, u_win, sc.cfg.C_max)
+    env = torch.arange(6, dtype=torch.int32, device="cuda")
+    _, g_ref, _, _ = b.window_grad(u_t, gt_t, env, start, warm0)
+    x = start.clone().requires_grad_(True)
+    cost = pt.WindowFn.apply(x, b, env, warm0, u_t, gt_t)
+    w = torch.arange(1, 7, dtype=torch.float32, device="cuda")
+    (cost * w).sum().backward()
+    torch.cuda.synchronize()
+    assert torch.allclose(x.grad, g_ref * w.unsqueeze(0), rtol=0, atol=0)
+    with torch.no_grad():
+        c2 = pt.WindowFn.apply(start, b, env, warm0, u_t, gt_t)
+    assert torch.equal(c2, cost.detach())
+    b.close()
+
+
+def test_refine_elites(pt):
+    _say("elite refinement: elites, monotone costs, untouched non-elites")
+    T = 10
+    K = 64
+    cfg = S.CONFIGS["adjoint1024"].with_(T=T)
+    sc = S.make_scene(cfg, K=K, steps=3 * T)
+    b = pt.Batch.from_scene(sc)
+    h = pt.Batch.from_scene(sc, hidden=True)
+    gtw = torch.zeros((T, 4, sc.L, sc.G), device="cuda")
+    costh = torch.zeros(sc.G, device="cuda")
+    cost = torch.zeros(K, device="cuda")
+    best = torch.zeros(sc.G, dtype=torch.int32, device="cuda")
+    parent = torch.zeros(K, dtype=torch.int32, device="cuda")
+    improved_total = 0
+    for w in range(2):
+        rows = [sc.u[max(w * T - 1, 0)]] + [sc.u[w * T + t] for t in range(T)]
+        u_t = torch.as_tensor(np.array(rows, dtype=np.float32), device="cuda")
+        h.run_window(u_t, torch.zeros_like(gtw), costh, None, gtw, graph=False)
+        snap = b.snapshot()
+        b.run_window(u_t, gtw, cost, None, None, graph=False)
+        st_run, pr_run, wm_run = b.snapshot()
+        cost0 = cost.clone()
+        elites = b.refine_elites(u_t, gtw, cost, snap, steps=3, step=0.5, best=best)
+        torch.cuda.synchronize()
+        c0, c1 = cost0.cpu().numpy(), cost.cpu().numpy()
+        el = elites.cpu().numpy()
+        # elites: the resampler's ranking (stable, NaN last)
+        key = np.where(np.isnan(c0), np.inf, c0)
+        kb = max(1, int(np.floor(np.float32(K) * np.float32(cfg.elite_frac))))
+        assert np.array_equal(el, np.argsort(key, kind="stable")[:kb])
+        non = np.setdiff1d(np.arange(K), el)
+        assert np.array_equal(c1[non], c0[non])
+        assert np.all(c1[el] <= c0[el])
+        changed = el[c1[el] < c0[el]]
+        same = np.setdiff1d(np.arange(K), changed)
+        # unchanged simulations keep the window's end state bit for bit
+        # (raw bits: the warm cache's empty keys are NaN patterns)
+        assert torch.equal(b.state[:, same].view(torch.int32), st_run[:, same].view(torch.int32))
+        assert torch.equal(b.warm[same].view(torch.int32), wm_run[same].view(torch.int32))
+        assert torch.equal(b.params[:, same].view(torch.int32), pr_run[:, same].view(torch.int32))
+        # a changed elite's new end state is that of a replay from its refined
+        # start: replaying from the new state is not possible, but its cost is
+        # finite, lower and its f_pert consumed
+        assert np.all(np.isfinite(c1[changed]))
+        assert torch.count_nonzero(b.params[2:, changed]).item() == 0
+        assert best.cpu().numpy()[0] == int(np.argmin(np.where(np.isnan(c1), np.inf, c1)))
+        improved_total += len(changed)
+        b.resample(cost, w, parent)
+        par = parent.cpu().numpy()
+        assert np.array_equal(np.sort(np.nonzero(par == -1)[0]), np.sort(el))
+    _say(f"elites improved over two windows: {improved_total}")
+    assert improved_total > 0
+    b.close()
+    h.close()
+
+
+def test_refine_with_zero_scale_changes_nothing(pt):
+    T = 10
+    K = 32
+    cfg = S.CONFIGS["adjoint1024"].with_(T=T)
+    sc = S.make_scene(cfg, K=K, steps=T)
+    b = pt.Batch.from_scene(sc)
+    h = pt.Batch.from_scene(sc, hidden=True)
+    gtw = torch.zeros((T, 4, sc.L, sc.G), device="cuda")
+    u_t = torch.as_tensor(np.array([sc.u[0]] + [sc.u[t] for t in range(T)], dtype=np.float32), device="cuda")
+    h.run_window(u_t, torch.zeros_like(gtw), torch.zeros(sc.G, device="cuda"), None, gtw, graph=False)
+    snap = b.snapshot()
+    cost = torch.zeros(K, device="cuda")
+    b.run_window(u_t, gtw, cost, None, None, graph=False)
+    ref = (b.state.clone(), b.params.clone(), b.warm.clone(), cost.clone())
+    b.refine_elites(u_t, gtw, cost, snap, steps=3, scale=np.zeros(15))
+    torch.cuda.synchronize()
+    for x, y in zip((b.state, b.params, b.warm, cost), ref):
+        assert torch.equal(x.view(torch.int32), y.view(torch.int32))
+    b.close()
+    h.close()
