@@ -12,8 +12,11 @@ hand on sinusoidal joint commands and a 64-sphere ellipsoid on a table.
 
 Default workload: 256 simulations, 300 steps at 30 Hz, plain per-step
 launches (the "plain256" scene).  The same run also times the batched path
-(one persistent kernel per 10-step window, replayed from a HIP graph) on the
-same workload.  Prints one JSON line.
+(one persistent kernel per 10-step window, replayed from a HIP graph) and
+the batched path with elite refinement (three gradient steps of the window
+cost for the elites before every resampling) on the same workload, and both
+batched variants on the 1024-simulation differentiation workload
+("adjoint1024").  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -27,6 +30,13 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+# The observed simulation runs on a stream of its own beside the population.
+# HIP deals streams to hardware queues round-robin (4 by default); two streams
+# on one queue serialise, which would put the observed window back on the
+# population's critical path.  Sixteen queues give each stream here its own.
+# (Read when the HIP runtime starts, so set before torch is imported.)
+os.environ.setdefault("GPU_MAX_HW_QUEUES", "16")
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -36,6 +46,7 @@ def parse():
     ap.add_argument("--config", default="plain256")
     ap.add_argument("--solve-precision", type=int, default=64, choices=[32, 64])
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the batched + elite-refinement legs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-steps", type=int, default=300)
     ap.add_argument("--profile", action="store_true", help="short run for the profiler (no CPU baseline)")
@@ -75,6 +86,92 @@ def algorithmic_flops(S, L, N, env_steps, contacts):
 # every simulation and stay in cache
 def algorithmic_bytes(C_max):
     return 52 + 20 + 52 + 12 + 3 * 16 * C_max
+
+
+def batched_run(pt, S, sc, dev, solve_precision, n_win, n_warm, adjoint):
+    """Windows of the batched path: the observed simulation runs one window
+    ahead on its own stream (inputs and observations double-buffered); the
+    population's window is one persistent kernel replayed from a HIP graph,
+    then (adjoint) the elites are refined by three gradient steps of the
+    window cost from their window start, then the resampler runs."""
+    import torch
+    cfg = sc.cfg
+    K, G, L, T = sc.K, sc.G, sc.L, cfg.T
+    u_all = torch.as_tensor(sc.u.astype("float32"), device=dev)
+    main_b = pt.Batch.from_scene(sc, solve_precision=solve_precision)
+    hid_b = pt.Batch.from_scene(sc, hidden=True, solve_precision=solve_precision)
+    stream = torch.cuda.current_stream()
+    u_wins = [torch.empty((T + 1, sc.D), device=dev) for _ in range(2)]
+    gtws = [torch.zeros((T, 4, L, G), device=dev) for _ in range(2)]
+    cost = torch.zeros(K, device=dev)
+    best = torch.zeros(G, dtype=torch.int32, device=dev)
+    parent = torch.zeros(K, dtype=torch.int32, device=dev)
+    costh = torch.zeros(G, device=dev)
+    gt_dummy = torch.zeros((T, 4, L, G), device=dev)
+    snap = main_b.snapshot()
+    s_obs = torch.cuda.Stream(device=dev)
+    ev_ready = [torch.cuda.Event(), torch.cuda.Event()]
+    ev_free = [torch.cuda.Event(), torch.cuda.Event()]
+    improved = [0, 0]
+
+    def fill_u(w, buf):
+        t0_ = w * T
+        buf.copy_(u_all[t0_ - 1: t0_ + T] if t0_ > 0 else torch.cat([u_all[:1], u_all[:T]], 0))
+
+    def observed_window(w):
+        k = w % 2
+        with torch.cuda.stream(s_obs):
+            s_obs.wait_event(ev_free[k])
+            fill_u(w, u_wins[k])
+            hid_b.run_window(u_wins[k], gt_dummy, costh, None, gtws[k], graph=True, stream=s_obs)
+            ev_ready[k].record(s_obs)
+
+    def population_window(w, count=False):
+        k = w % 2
+        stream.wait_event(ev_ready[k])
+        if adjoint:
+            snap[0].copy_(main_b.state)
+            snap[1].copy_(main_b.params)
+            snap[2].copy_(main_b.warm)
+        main_b.run_window(u_wins[k], gtws[k], cost, best, None, graph=True)
+        if adjoint:
+            c0 = cost.clone() if count else None
+            elites = main_b.refine_elites(u_wins[k], gtws[k], cost, snap, steps=3, step=0.5, best=best)
+            if count:
+                e = elites.long()
+                improved[0] += int((cost[e] < c0[e]).sum())
+                improved[1] += int(e.numel())
+        main_b.resample(cost, w, parent)
+        ev_free[k].record(stream)
+
+    fill_u(0, u_wins[0])
+    tuned = main_b.autotune(u_wins[0], gtws[0])
+    torch.cuda.synchronize()
+    observed_window(0)
+    for w in range(n_warm):
+        observed_window(w + 1)
+        population_window(w)
+    torch.cuda.synchronize()
+    tb0 = time.perf_counter()
+    for w in range(n_warm, n_warm + n_win):
+        observed_window(w + 1)
+        population_window(w)
+    torch.cuda.synchronize()
+    bwall = time.perf_counter() - tb0
+    out = {"value": round(K * T * n_win / bwall, 1), "unit": "env-steps/s", "windows": n_win,
+           "windows_per_s": round(n_win / bwall, 2), "ms_per_step": round(bwall / (n_win * T) * 1e3, 4),
+           "waves_per_workgroup": tuned}
+    if adjoint:
+        # one more window, untimed, to count the elites the refinement improved
+        w = n_warm + n_win
+        observed_window(w + 1)
+        population_window(w, count=True)
+        torch.cuda.synchronize()
+        out.update({"elites": main_b.elite_count(), "refine_steps": 3,
+                    "elites_improved_frac": round(improved[0] / max(improved[1], 1), 3)})
+    main_b.close()
+    hid_b.close()
+    return out
 
 
 def main():
@@ -208,62 +305,27 @@ def main():
     result["roofline"]["frac"] = round(result["roofline"]["achieved"] / result["roofline"]["peak"], 6)
 
     # ---------------- batched path (persistent kernel + graph) -------------
-    # The observed simulation runs one window ahead on its own stream, so its
-    # window overlaps the population's; inputs and observations are
-    # double-buffered.
     if not args.no_batched:
-        main_b, hid_b = make()
         n_win = max(1, args.steps // T)
         n_warm = max(1, args.warmup // T)
-        u_wins = [torch.empty((T + 1, sc.D), device=dev) for _ in range(2)]
-        gtws = [torch.zeros((T, 4, L, G), device=dev) for _ in range(2)]
-        costb = torch.zeros(K, device=dev)
-        bestb = torch.zeros(G, dtype=torch.int32, device=dev)
-        parentb = torch.zeros(K, dtype=torch.int32, device=dev)
-        costh = torch.zeros(G, device=dev)
-        gt_dummy = torch.zeros((T, 4, L, G), device=dev)
-        s_obs = torch.cuda.Stream(device=dev)
-        ev_ready = [torch.cuda.Event(), torch.cuda.Event()]
-        ev_free = [torch.cuda.Event(), torch.cuda.Event()]
-
-        def fill_u(w, buf):
-            t0_ = w * T
-            buf.copy_(u_all[t0_ - 1: t0_ + T] if t0_ > 0 else torch.cat([u_all[:1], u_all[:T]], 0))
-
-        def observed_window(w):
-            k = w % 2
-            with torch.cuda.stream(s_obs):
-                s_obs.wait_event(ev_free[k])
-                fill_u(w, u_wins[k])
-                hid_b.run_window(u_wins[k], gt_dummy, costh, None, gtws[k], graph=True, stream=s_obs)
-                ev_ready[k].record(s_obs)
-
-        def population_window(w):
-            k = w % 2
-            stream.wait_event(ev_ready[k])
-            main_b.run_window(u_wins[k], gtws[k], costb, bestb, None, graph=True)
-            main_b.resample(costb, w, parentb)
-            ev_free[k].record(stream)
-
-        fill_u(0, u_wins[0])
-        tuned = main_b.autotune(u_wins[0], gtws[0])
-        torch.cuda.synchronize()
-        observed_window(0)
-        for w in range(n_warm):
-            observed_window(w + 1)
-            population_window(w)
-        torch.cuda.synchronize()
-        tb0 = time.perf_counter()
-        for w in range(n_warm, n_warm + n_win):
-            observed_window(w + 1)
-            population_window(w)
-        torch.cuda.synchronize()
-        bwall = time.perf_counter() - tb0
-        result["batched"] = {"value": round(K * T * n_win / bwall, 1), "unit": "env-steps/s",
-                             "windows": n_win, "ms_per_step": round(bwall / (n_win * T) * 1e3, 4),
-                             "waves_per_workgroup": tuned, "speedup_vs_plain": round(K * T * n_win / bwall / plain_value, 3)}
-        main_b.close()
-        hid_b.close()
+        bat = batched_run(pt, S, sc, dev, args.solve_precision, n_win, n_warm, adjoint=False)
+        bat["speedup_vs_plain"] = round(bat["value"] / plain_value, 3)
+        result["batched"] = bat
+        if not args.no_adjoint:
+            adj = batched_run(pt, S, sc, dev, args.solve_precision, n_win, n_warm, adjoint=True)
+            adj["speedup_vs_plain"] = round(adj["value"] / plain_value, 3)
+            result["batched_adjoint"] = adj
+            # the differentiation workload: 1024 simulations, 64-sphere cuboid
+            acfg = S.CONFIGS["adjoint1024"]
+            asc = S.make_scene(acfg, steps=(n_win + n_warm + 2) * acfg.T + 1)
+            a_b = batched_run(pt, S, asc, dev, args.solve_precision, n_win, n_warm, adjoint=False)
+            a_a = batched_run(pt, S, asc, dev, args.solve_precision, n_win, n_warm, adjoint=True)
+            result["adjoint1024"] = {
+                "workload": f"{acfg.name}: {asc.K} simulations + {asc.G} observed, {asc.L} capsule links, "
+                            f"{int(asc.n_spheres[0])}-sphere cuboid, C_max={acfg.C_max}, "
+                            f"{acfg.newton_iters} Newton iterations, {acfg.T}-step windows",
+                "batched": a_b, "batched_adjoint": a_a,
+                "adjoint_cost_ratio": round(a_b["value"] / a_a["value"], 3)}
 
     # ---------------- CPU baseline: the FP64 oracle ----------------------
     if not args.no_cpu_baseline and not args.profile:

@@ -181,9 +181,12 @@ PT_API pt_status pt_run_window(pt_batch b, const float *u_win, const float *obs_
                         int32_t *best, float *obs_out, int32_t graph, pt_stream s);
 
 /* Chooses the persistent kernel's environments per workgroup (waves per
- * workgroup, {1,2,4,8}; at most 4 with the float64 solve) by timing windows on scratch copies of the state;
- * the batch's own buffers are not modified.  Synchronises the stream.
- * result (host, may be NULL) receives the chosen value. */
+ * workgroup, {1,2,4,8}; at most 4 with the float64 solve) by timing windows
+ * on scratch copies of the state; the widest choice is kept unless a
+ * narrower one is at least 2% faster (fuller workgroups leave compute units
+ * free for work on other streams).  The batch's own buffers are not
+ * modified.  Synchronises the stream.  result (host, may be NULL) receives
+ * the chosen value. */
 PT_API pt_status pt_autotune(pt_batch b, const float *u_win, const float *obs_gt_win, int32_t *result, pt_stream s);
 
 /* Sets the persistent kernel's environments per workgroup (1, 2, 4 or 8)

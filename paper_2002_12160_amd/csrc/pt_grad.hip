@@ -1,14 +1,18 @@
 // pt_grad.hip -- gradients of the window cost and the elite refinement built
 // on them.
 //
-//   k_window_grad     one wavefront per listed simulation: runs the window
-//                     from a given start (same step code as the other
-//                     kernels), writing a checkpoint of the body and warm
-//                     cache before every step; then walks the steps backwards,
-//                     re-running each from its checkpoint and applying the
-//                     step adjoint (implicit differentiation of the contact
-//                     solve).  Output: window cost and its gradient with
-//                     respect to the start (x, q, v, w, m, mu, f).
+//   k_window_fwd      one wavefront per listed simulation: runs the window
+//                     from a given start with the step code of the other
+//                     kernels (same bits), the cost and optionally the end
+//                     state; with a checkpoint buffer it records, before every
+//                     step, the body and after the step's solve the kept
+//                     contact keys and their impulses (float64)
+//   k_window_bwd      the reverse sweep over those checkpoints: each step's
+//                     contacts are rebuilt from the recorded keys (no narrow
+//                     phase, no Newton solve), then the step adjoint runs
+//                     (implicit differentiation of the contact solve).
+//                     Output: the gradient of the window cost with respect
+//                     to the start (x, q, v, w, m, mu, f)
 //   k_select_elites   per group, the simulations of lowest window cost (the
 //                     same ranking the resampler keeps)
 //   k_refine_*        gather / scaled gradient step / accept-or-halve
@@ -18,48 +22,74 @@
 
 namespace pt {
 
-constexpr int CK_BODY = 16;  // checkpoint body record: x(3) q(4) v(3) w(3) f(3)
+// checkpoint of one step of one simulation: body record x(3) q(4) v(3) w(3)
+// f(3) (16 floats), then per contact slot r(3) and key as 4 doubles
+constexpr int CK_BODY = 16;
+__host__ __device__ constexpr size_t ckpt_step_floats(int C_max) { return CK_BODY + 8 * (size_t)C_max; }
 
-__device__ __forceinline__ void save_ckpt(float *__restrict__ ck, int C_max, const Body &B, int wkey, const float *wr)
+__device__ __forceinline__ void save_body(float *__restrict__ ck, const Body &B)
 {
-    const int lane = lane_id();
-    if (lane == 0) {
+    if (lane_id() == 0) {
         float4 *b4 = reinterpret_cast<float4 *>(ck);
         b4[0] = make_float4(B.x[0], B.x[1], B.x[2], B.q[0]);
         b4[1] = make_float4(B.q[1], B.q[2], B.q[3], B.v[0]);
         b4[2] = make_float4(B.v[1], B.v[2], B.w[0], B.w[1]);
         b4[3] = make_float4(B.w[2], B.f[0], B.f[1], B.f[2]);
     }
-    if (lane < C_max)
-        *reinterpret_cast<float4 *>(ck + CK_BODY + WARM_STRIDE * lane) = make_float4(__int_as_float(wkey), wr[0], wr[1], wr[2]);
 }
 
-__device__ __forceinline__ void load_ckpt(const float *__restrict__ ck, int C_max, Body &B, int &wkey, float *wr)
+__device__ __forceinline__ void load_body_ckpt(const float *__restrict__ ck, Body &B)
 {
-    const int lane = lane_id();
     const float4 *b4 = reinterpret_cast<const float4 *>(ck);
     float4 a = b4[0], b = b4[1], c = b4[2], d = b4[3];
     B.x[0] = a.x; B.x[1] = a.y; B.x[2] = a.z; B.q[0] = a.w;
     B.q[1] = b.x; B.q[2] = b.y; B.q[3] = b.z; B.v[0] = b.w;
     B.v[1] = c.x; B.v[2] = c.y; B.w[0] = c.z; B.w[1] = c.w;
     B.w[2] = d.x; B.f[0] = d.y; B.f[1] = d.z; B.f[2] = d.w;
-    wkey = -1;
-    wr[0] = wr[1] = wr[2] = 0.f;
+}
+
+template <typename SR>
+__device__ __forceinline__ void save_contact(float *__restrict__ ck, int C_max, const StepState<SR> &st)
+{
+    const int lane = lane_id();
     if (lane < C_max) {
-        float4 w = *reinterpret_cast<const float4 *>(ck + CK_BODY + WARM_STRIDE * lane);
-        wkey = __float_as_int(w.x);
-        wr[0] = w.y; wr[1] = w.z; wr[2] = w.w;
+        double2 *d2 = reinterpret_cast<double2 *>(ck + CK_BODY) + 2 * lane;
+        d2[0] = make_double2((double)st.r[0], (double)st.r[1]);
+        d2[1] = make_double2((double)st.r[2], (double)(st.act ? st.key : -1));
     }
+}
+
+template <typename SR>
+__device__ __forceinline__ int load_contact(const float *__restrict__ ck, int C_max, SR *r)
+{
+    const int lane = lane_id();
+    r[0] = r[1] = r[2] = SR(0);
+    if (lane >= C_max) return -1;
+    const double2 *d2 = reinterpret_cast<const double2 *>(ck + CK_BODY) + 2 * lane;
+    double2 a = d2[0], b = d2[1];
+    r[0] = (SR)a.x; r[1] = (SR)a.y; r[2] = (SR)b.x;
+    return (int)b.y;
+}
+
+__device__ __forceinline__ void load_start(const float *__restrict__ xi, int n, int i, Body &B)
+{
+    B.x[0] = xi[0 * (size_t)n + i]; B.x[1] = xi[1 * (size_t)n + i]; B.x[2] = xi[2 * (size_t)n + i];
+    B.q[0] = xi[3 * (size_t)n + i]; B.q[1] = xi[4 * (size_t)n + i]; B.q[2] = xi[5 * (size_t)n + i];
+    B.q[3] = xi[6 * (size_t)n + i];
+    B.v[0] = xi[7 * (size_t)n + i]; B.v[1] = xi[8 * (size_t)n + i]; B.v[2] = xi[9 * (size_t)n + i];
+    B.w[0] = xi[10 * (size_t)n + i]; B.w[1] = xi[11 * (size_t)n + i]; B.w[2] = xi[12 * (size_t)n + i];
+    B.m = xi[13 * (size_t)n + i]; B.mu = xi[14 * (size_t)n + i];
+    B.f[0] = xi[15 * (size_t)n + i]; B.f[1] = xi[16 * (size_t)n + i]; B.f[2] = xi[17 * (size_t)n + i];
 }
 
 // xi is [18][n]: x(3) q(4) v(3) w(3) m mu f(3); warm0 is [n][C_max][4]
 template <typename SR>
-__global__ __launch_bounds__(WAVE) void k_window_grad(Consts P, Tables tb, const float *__restrict__ seg_win, int n,
-                                                      const int32_t *__restrict__ env, const float *__restrict__ xi,
-                                                      const float *__restrict__ warm0,
-                                                      const float *__restrict__ obs_gt_win, float *__restrict__ cost_out,
-                                                      float *__restrict__ grad, float *__restrict__ end_state,
-                                                      float *__restrict__ end_warm, float *__restrict__ ckpt)
+__global__ __launch_bounds__(WAVE) void k_window_fwd(Consts P, Tables tb, const float *__restrict__ seg_win, int n,
+                                                     const int32_t *__restrict__ env, const float *__restrict__ xi,
+                                                     const float *__restrict__ warm0,
+                                                     const float *__restrict__ obs_gt_win, float *__restrict__ cost_out,
+                                                     float *__restrict__ end_state, float *__restrict__ end_warm,
+                                                     float *__restrict__ ckpt)
 {
     extern __shared__ __align__(16) char smem[];
     const int i = blockIdx.x;
@@ -67,12 +97,8 @@ __global__ __launch_bounds__(WAVE) void k_window_grad(Consts P, Tables tb, const
     const int lane = lane_id();
     const int e = env[i];
     if (e < 0 || e >= P.K) {
-        // not a simulation of this batch: NaN cost, zero gradient
-        if (lane == 0) {
-            cost_out[i] = __int_as_float(0x7fc00000);
-            if (grad)
-                for (int r = 0; r < XI_ROWS; ++r) grad[(size_t)r * n + i] = 0.f;
-        }
+        // not a simulation of this batch
+        if (lane == 0) cost_out[i] = __int_as_float(0x7fc00000);
         return;
     }
     WaveLds lds = carve_lds(smem, 0, P.max_cand);
@@ -83,29 +109,28 @@ __global__ __launch_bounds__(WAVE) void k_window_grad(Consts P, Tables tb, const
     const float *sph = tb.spheres + (size_t)type * P.S_max * 4;
     const float *inv = tb.inv_inertia + 3 * type;
     const size_t LG = (size_t)P.L * P.G;
-    const size_t CK = CK_BODY + (size_t)WARM_STRIDE * P.C_max;
+    const size_t CK = ckpt_step_floats(P.C_max);
 
     Body B;
-    B.x[0] = xi[0 * (size_t)n + i]; B.x[1] = xi[1 * (size_t)n + i]; B.x[2] = xi[2 * (size_t)n + i];
-    B.q[0] = xi[3 * (size_t)n + i]; B.q[1] = xi[4 * (size_t)n + i]; B.q[2] = xi[5 * (size_t)n + i];
-    B.q[3] = xi[6 * (size_t)n + i];
-    B.v[0] = xi[7 * (size_t)n + i]; B.v[1] = xi[8 * (size_t)n + i]; B.v[2] = xi[9 * (size_t)n + i];
-    B.w[0] = xi[10 * (size_t)n + i]; B.w[1] = xi[11 * (size_t)n + i]; B.w[2] = xi[12 * (size_t)n + i];
-    B.m = xi[13 * (size_t)n + i]; B.mu = xi[14 * (size_t)n + i];
-    B.f[0] = xi[15 * (size_t)n + i]; B.f[1] = xi[16 * (size_t)n + i]; B.f[2] = xi[17 * (size_t)n + i];
-    const float m0 = B.m, mu0 = B.mu;
+    load_start(xi, n, i, B);
     int wkey;
     float wr[3];
     load_warm(warm0, P.C_max, i, wkey, wr);
     StepStats stt = {0, 0, 0};
 
-    // forward sweep (cost summed in the order of the other paths)
+    // cost summed in the order of the other paths
     float cost = 0.f;
     for (int t = 0; t < P.T; ++t) {
-        if (ckpt) save_ckpt(ckpt + ((size_t)i * P.T + t) * CK, P.C_max, B, wkey, wr);
+        float *ck = ckpt ? ckpt + ((size_t)i * P.T + t) * CK : nullptr;
+        if (ck) save_body(ck, B);
+        const float *seg = seg_win + (size_t)t * P.L * SEG_STRIDE;
+        StepState<SR> st;
+        step_setup<SR>(P, seg, sph, S, inv, B, wkey, wr, lds, stt, st);
+        step_solve<SR>(P, st, B.mu);
+        if (ck) save_contact<SR>(ck, P.C_max, st);
         int link;
         float imp[3];
-        env_step<SR>(P, seg_win + (size_t)t * P.L * SEG_STRIDE, sph, S, inv, B, wkey, wr, link, imp, lds, stt);
+        step_finish<SR>(P, st, inv, B, wkey, wr, link, imp);
         *reinterpret_cast<float4 *>(stage + 4 * lane) = make_float4(__int_as_float(link), imp[0], imp[1], imp[2]);
         wave_sync();
         float o[4];
@@ -128,10 +153,38 @@ __global__ __launch_bounds__(WAVE) void k_window_grad(Consts P, Tables tb, const
         }
     }
     if (end_warm) store_warm(end_warm, P.C_max, i, wkey, wr);
-    if (!grad) return;
+}
 
-    // reverse sweep: re-run each step from its checkpoint, then its adjoint
-    wave_sync();
+// reverse sweep over the checkpoints k_window_fwd wrote for the same n, env
+// and xi; simulations with flag[i] == 0 are skipped (flag may be NULL)
+template <typename SR>
+__global__ __launch_bounds__(WAVE) void k_window_bwd(Consts P, Tables tb, const float *__restrict__ seg_win, int n,
+                                                     const int32_t *__restrict__ env, const float *__restrict__ xi,
+                                                     const float *__restrict__ obs_gt_win,
+                                                     const float *__restrict__ ckpt, const int32_t *__restrict__ flag,
+                                                     float *__restrict__ grad)
+{
+    extern __shared__ __align__(16) char smem[];
+    const int i = blockIdx.x;
+    if (i >= n) return;
+    if (flag && flag[i] == 0) return;
+    const int lane = lane_id();
+    const int e = env[i];
+    if (e < 0 || e >= P.K) {
+        if (lane == 0)
+            for (int r = 0; r < XI_ROWS; ++r) grad[(size_t)r * n + i] = 0.f;
+        return;
+    }
+    WaveLds lds = carve_lds(smem, 0, P.max_cand);
+    float *stage = contact_stage(lds);
+    const int type = tb.env_type[e];
+    const int g = tb.group_of[e];
+    const float *sph = tb.spheres + (size_t)type * P.S_max * 4;
+    const float *inv = tb.inv_inertia + 3 * type;
+    const size_t LG = (size_t)P.L * P.G;
+    const size_t CK = ckpt_step_floats(P.C_max);
+    const float m0 = xi[13 * (size_t)n + i], mu0 = xi[14 * (size_t)n + i];
+
     BodyBar<SR> bar;
 #pragma unroll
     for (int k = 0; k < 3; ++k) bar.x[k] = bar.v[k] = bar.w[k] = SR(0);
@@ -139,13 +192,26 @@ __global__ __launch_bounds__(WAVE) void k_window_grad(Consts P, Tables tb, const
     for (int k = 0; k < 4; ++k) bar.q[k] = SR(0);
     SR mbar = 0, mubar = 0, fbar[3] = {0, 0, 0};
     for (int t = P.T - 1; t >= 0; --t) {
-        load_ckpt(ckpt + ((size_t)i * P.T + t) * CK, P.C_max, B, wkey, wr);
+        const float *ck = ckpt + ((size_t)i * P.T + t) * CK;
+        Body B;
+        load_body_ckpt(ck, B);
         B.m = m0;
         B.mu = mu0;
+        SR r[3];
+        const int key = load_contact<SR>(ck, P.C_max, r);
         const float *seg = seg_win + (size_t)t * P.L * SEG_STRIDE;
+        // the step as the forward sweep left it: same contacts, same impulses
         StepState<SR> st;
-        step_setup<SR>(P, seg, sph, S, inv, B, wkey, wr, lds, stt, st);
-        step_solve<SR>(P, st, B.mu);
+        step_pose<SR>(P, inv, B, st);
+        contact_setup<SR>(P, seg, sph, B, key, st);
+        const int C = __popcll(__ballot(st.act));
+        st.C = C;
+        st.ncand = C;
+        st.span = lane_span(C);
+        st.r[0] = r[0]; st.r[1] = r[1]; st.r[2] = r[2];
+        body_dv(st, st.r, st.nu);
+        st.nu[0] += st.vs[0]; st.nu[1] += st.vs[1]; st.nu[2] += st.vs[2];
+        st.nu[3] += st.ws[0]; st.nu[4] += st.ws[1]; st.nu[5] += st.ws[2];
         step_adjoint<SR>(P, seg, sph, inv, B, st, obs_gt_win + (size_t)t * 4 * LG, g, stage, lds.wr, bar, mbar,
                          mubar, t == 0 ? fbar : nullptr);
     }
@@ -229,17 +295,18 @@ __global__ void k_refine_propose(int n, RefineArgs A, const float *__restrict__ 
 
 // keep the trial where its replayed window cost is lower (the batch slot then
 // takes the replay's end-of-window state, mass, friction and warm cache, and
-// its window cost); otherwise halve the step
+// its window cost; flag[i] = 1 asks for the gradient at the new start);
+// otherwise halve the step (flag[i] = 0)
 __global__ void k_refine_accept(int n, int K, int C_max, const int32_t *__restrict__ env, float *__restrict__ cost_cur,
                                 const float *__restrict__ cost_try, float *__restrict__ xi,
-                                const float *__restrict__ xi_try, float *__restrict__ grad,
-                                const float *__restrict__ grad_try, float *__restrict__ rho,
+                                const float *__restrict__ xi_try, float *__restrict__ rho, int32_t *__restrict__ flag,
                                 const float *__restrict__ end_state, const float *__restrict__ end_warm,
                                 float *__restrict__ state, float *__restrict__ params, float *__restrict__ warm,
                                 float *__restrict__ cost_sum)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    flag[i] = 0;
     const int e = env[i];
     if (e < 0 || e >= K) return;
     const float ct = cost_try[i];
@@ -247,10 +314,9 @@ __global__ void k_refine_accept(int n, int K, int C_max, const int32_t *__restri
         rho[i] *= 0.5f;
         return;
     }
+    flag[i] = 1;
     cost_cur[i] = ct;
     for (int r = 0; r < XI_ROWS; ++r) xi[(size_t)r * n + i] = xi_try[(size_t)r * n + i];
-    if (grad_try)
-        for (int r = 0; r < XI_ROWS; ++r) grad[(size_t)r * n + i] = grad_try[(size_t)r * n + i];
     for (int r = 0; r < 13; ++r) state[(size_t)r * K + e] = end_state[(size_t)r * n + i];
     params[0 * (size_t)K + e] = xi_try[13 * (size_t)n + i];
     params[1 * (size_t)K + e] = xi_try[14 * (size_t)n + i];
@@ -267,18 +333,35 @@ __global__ void k_refine_accept(int n, int K, int C_max, const int32_t *__restri
 
 using namespace pt;
 
-hipError_t launch_window_grad(const Consts &P, const Tables &tb, const float *seg_win, int n, const int32_t *env,
-                              const float *xi, const float *warm0, const float *obs_gt_win, float *cost, float *grad,
-                              float *end_state, float *end_warm, float *ckpt, hipStream_t s)
+size_t ckpt_floats(const Consts &P, int n) { return (size_t)n * P.T * ckpt_step_floats(P.C_max); }
+
+hipError_t launch_window_fwd(const Consts &P, const Tables &tb, const float *seg_win, int n, const int32_t *env,
+                             const float *xi, const float *warm0, const float *obs_gt_win, float *cost,
+                             float *end_state, float *end_warm, float *ckpt, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
     size_t lds = wave_lds_bytes(P.max_cand);
     if (P.solve_fp64)
-        hipLaunchKernelGGL(k_window_grad<double>, dim3(n), dim3(WAVE), lds, s, P, tb, seg_win, n, env, xi, warm0,
-                           obs_gt_win, cost, grad, end_state, end_warm, ckpt);
+        hipLaunchKernelGGL(k_window_fwd<double>, dim3(n), dim3(WAVE), lds, s, P, tb, seg_win, n, env, xi, warm0,
+                           obs_gt_win, cost, end_state, end_warm, ckpt);
     else
-        hipLaunchKernelGGL(k_window_grad<float>, dim3(n), dim3(WAVE), lds, s, P, tb, seg_win, n, env, xi, warm0,
-                           obs_gt_win, cost, grad, end_state, end_warm, ckpt);
+        hipLaunchKernelGGL(k_window_fwd<float>, dim3(n), dim3(WAVE), lds, s, P, tb, seg_win, n, env, xi, warm0,
+                           obs_gt_win, cost, end_state, end_warm, ckpt);
+    return hipGetLastError();
+}
+
+hipError_t launch_window_bwd(const Consts &P, const Tables &tb, const float *seg_win, int n, const int32_t *env,
+                             const float *xi, const float *obs_gt_win, const float *ckpt, const int32_t *flag,
+                             float *grad, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    size_t lds = wave_lds_bytes(P.max_cand);
+    if (P.solve_fp64)
+        hipLaunchKernelGGL(k_window_bwd<double>, dim3(n), dim3(WAVE), lds, s, P, tb, seg_win, n, env, xi, obs_gt_win,
+                           ckpt, flag, grad);
+    else
+        hipLaunchKernelGGL(k_window_bwd<float>, dim3(n), dim3(WAVE), lds, s, P, tb, seg_win, n, env, xi, obs_gt_win,
+                           ckpt, flag, grad);
     return hipGetLastError();
 }
 
@@ -307,20 +390,22 @@ hipError_t launch_refine_propose(int n, const RefineArgs &A, const float *xi, co
 }
 
 hipError_t launch_refine_accept(int n, int K, int C_max, const int32_t *env, float *cost_cur, const float *cost_try,
-                                float *xi, const float *xi_try, float *grad, const float *grad_try, float *rho,
-                                const float *end_state, const float *end_warm, float *state, float *params,
-                                float *warm, float *cost_sum, hipStream_t s)
+                                float *xi, const float *xi_try, float *rho, int32_t *flag, const float *end_state,
+                                const float *end_warm, float *state, float *params, float *warm, float *cost_sum,
+                                hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_refine_accept, dim3((n + 63) / 64), dim3(64), 0, s, n, K, C_max, env, cost_cur, cost_try,
-                       xi, xi_try, grad, grad_try, rho, end_state, end_warm, state, params, warm, cost_sum);
+                       xi, xi_try, rho, flag, end_state, end_warm, state, params, warm, cost_sum);
     return hipGetLastError();
 }
 
 hipError_t set_grad_lds_limits(size_t bytes)
 {
-    const void *fs[] = {reinterpret_cast<const void *>(k_window_grad<float>),
-                        reinterpret_cast<const void *>(k_window_grad<double>)};
+    const void *fs[] = {reinterpret_cast<const void *>(k_window_fwd<float>),
+                        reinterpret_cast<const void *>(k_window_fwd<double>),
+                        reinterpret_cast<const void *>(k_window_bwd<float>),
+                        reinterpret_cast<const void *>(k_window_bwd<double>)};
     for (const void *f : fs) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
         if (e != hipSuccess) return e;

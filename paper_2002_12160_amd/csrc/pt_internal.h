@@ -63,9 +63,13 @@ hipError_t launch_window(const pt::Consts &P, const pt::Tables &tb, const float 
 hipError_t window_occupancy(int waves_per_block, int max_cand, bool fp64, int *blocks_per_cu);
 hipError_t set_lds_limits(size_t bytes);
 hipError_t set_grad_lds_limits(size_t bytes);
-hipError_t launch_window_grad(const pt::Consts &P, const pt::Tables &tb, const float *seg_win, int n,
-                              const int32_t *env, const float *xi, const float *warm0, const float *obs_gt_win,
-                              float *cost, float *grad, float *end_state, float *end_warm, float *ckpt, hipStream_t s);
+size_t ckpt_floats(const pt::Consts &P, int n);
+hipError_t launch_window_fwd(const pt::Consts &P, const pt::Tables &tb, const float *seg_win, int n,
+                             const int32_t *env, const float *xi, const float *warm0, const float *obs_gt_win,
+                             float *cost, float *end_state, float *end_warm, float *ckpt, hipStream_t s);
+hipError_t launch_window_bwd(const pt::Consts &P, const pt::Tables &tb, const float *seg_win, int n,
+                             const int32_t *env, const float *xi, const float *obs_gt_win, const float *ckpt,
+                             const int32_t *flag, float *grad, hipStream_t s);
 hipError_t launch_select_elites(int G, float elite_frac, const int32_t *group_start, const float *cost_sum,
                                 int32_t *elite_env, hipStream_t s);
 hipError_t launch_refine_gather(int n, int K, int C_max, const int32_t *env, const float *state, const float *params,
@@ -73,6 +77,6 @@ hipError_t launch_refine_gather(int n, int K, int C_max, const int32_t *env, con
 hipError_t launch_refine_propose(int n, const pt::RefineArgs &A, const float *xi, const float *grad, const float *rho,
                                  float *xi_try, hipStream_t s);
 hipError_t launch_refine_accept(int n, int K, int C_max, const int32_t *env, float *cost_cur, const float *cost_try,
-                                float *xi, const float *xi_try, float *grad, const float *grad_try, float *rho,
-                                const float *end_state, const float *end_warm, float *state, float *params,
-                                float *warm, float *cost_sum, hipStream_t s);
+                                float *xi, const float *xi_try, float *rho, int32_t *flag, const float *end_state,
+                                const float *end_warm, float *state, float *params, float *warm, float *cost_sum,
+                                hipStream_t s);

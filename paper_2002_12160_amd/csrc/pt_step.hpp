@@ -66,18 +66,11 @@ __device__ __forceinline__ void rel_velocity(const StepState<SR> &st, const SR *
     u[2] = dot3(F + 6, pv) + st.ucst[2] + eps * r[2];
 }
 
-// phases 1-4: pose, free velocity, narrow phase, cap, contact setup, warm start
+// phase 1: pose, rotation, inverse inertia, free velocity (wave-uniform)
 template <typename SR>
-__device__ __forceinline__ void step_setup(const Consts &P, const float *__restrict__ seg,
-                                           const float *__restrict__ sph, int S, const float *inv_in, const Body &B,
-                                           int wkey, const float *wr, const WaveLds &lds, StepStats &stats,
-                                           StepState<SR> &st)
+__device__ __forceinline__ void step_pose(const Consts &P, const float *inv_in, const Body &B, StepState<SR> &st)
 {
-    const int lane = lane_id();
-    const int L = P.L;
     const float dt = P.dt;
-
-    // 1. pose, rotation, inverse inertia, free velocity
     float qn = rsqrtf(B.q[0] * B.q[0] + B.q[1] * B.q[1] + B.q[2] * B.q[2] + B.q[3] * B.q[3]);
     float *q = st.q;
     q[0] = B.q[0] * qn; q[1] = B.q[1] * qn; q[2] = B.q[2] * qn; q[3] = B.q[3] * qn;
@@ -98,6 +91,88 @@ __device__ __forceinline__ void step_setup(const Consts &P, const float *__restr
     st.vs[1] = B.v[1] + dt * (P.gy + B.f[1] * im);
     st.vs[2] = B.v[2] + dt * (P.gz + B.f[2] * im);
     st.ws[0] = B.w[0]; st.ws[1] = B.w[1]; st.ws[2] = B.w[2];
+}
+
+// phase 4: geometry of the contact with key `key` held by this lane (key < 0:
+// an empty slot), impulse reset to 0
+template <typename SR>
+__device__ __forceinline__ void contact_setup(const Consts &P, const float *__restrict__ seg,
+                                              const float *__restrict__ sph, const Body &B, int key,
+                                              StepState<SR> &st)
+{
+    const int L = P.L;
+    const float dt = P.dt;
+    const float *R = st.R;
+    st.act = key >= 0;
+    st.key = key;
+    SR *F = st.F;
+    F[0] = 0; F[1] = 0; F[2] = 1; F[3] = 0; F[4] = 1; F[5] = 0; F[6] = 1; F[7] = 0; F[8] = 0;
+    st.rho[0] = st.rho[1] = st.rho[2] = SR(0);
+    st.ucst[0] = st.ucst[1] = st.ucst[2] = SR(0);
+    st.r[0] = st.r[1] = st.r[2] = SR(0);
+    st.link = -1;
+    st.k = 0;
+    st.l = L;
+    st.interior = false;
+    st.e_axis = 0;
+    st.tpar = 0.f;
+    st.dist = 0.f;
+    st.d = 0.f;
+    if (st.act) {
+        int k = st.key / (L + 1);
+        int l = st.key - k * (L + 1);
+        st.k = k;
+        st.l = l;
+        const float4 t = *reinterpret_cast<const float4 *>(sph + 4 * k);
+        float s4[4] = {t.x, t.y, t.z, t.w};
+        float *c = st.c;
+        c[0] = B.x[0] + R[0] * s4[0] + R[1] * s4[1] + R[2] * s4[2];
+        c[1] = B.x[1] + R[3] * s4[0] + R[4] * s4[1] + R[5] * s4[2];
+        c[2] = B.x[2] + R[6] * s4[0] + R[7] * s4[1] + R[8] * s4[2];
+        float d, *n = st.n, *p = st.p, *vl = st.vl;
+        pair_contact(seg, l, L, c, s4[3], d, n, p, vl);
+        st.d = d;
+        if (l < L) {
+            const float *sg = seg + l * SEG_STRIDE;
+            float ca[3] = {c[0] - sg[0], c[1] - sg[1], c[2] - sg[2]};
+            float tr = (ca[0] * sg[4] + ca[1] * sg[5] + ca[2] * sg[6]) * sg[7];
+            st.interior = tr > 0.f && tr < 1.f;
+            st.tpar = fminf(fmaxf(tr, 0.f), 1.f);
+            st.dist = d + s4[3] + sg[3];
+        }
+        float t1[3], t2[3];
+        tangent_frame(n, t1, t2);
+        {
+            float an0 = fabsf(n[0]), an1 = fabsf(n[1]), an2 = fabsf(n[2]);
+            int e = 0;
+            float best = an0;
+            if (an1 < best) { e = 1; best = an1; }
+            if (an2 < best) { e = 2; }
+            st.e_axis = e;
+        }
+        F[0] = n[0]; F[1] = n[1]; F[2] = n[2];
+        F[3] = t1[0]; F[4] = t1[1]; F[5] = t1[2];
+        F[6] = t2[0]; F[7] = t2[1]; F[8] = t2[2];
+        st.rho[0] = p[0] - B.x[0]; st.rho[1] = p[1] - B.x[1]; st.rho[2] = p[2] - B.x[2];
+        float bn = d >= 0.f ? d / dt : P.erp * d / dt;
+        st.ucst[0] = -(n[0] * vl[0] + n[1] * vl[1] + n[2] * vl[2]) + bn;
+        st.ucst[1] = -(t1[0] * vl[0] + t1[1] * vl[1] + t1[2] * vl[2]);
+        st.ucst[2] = -(t2[0] * vl[0] + t2[1] * vl[1] + t2[2] * vl[2]);
+        st.link = l < L ? l : -1;
+    }
+}
+
+// phases 1-4: pose, free velocity, narrow phase, cap, contact setup, warm start
+template <typename SR>
+__device__ __forceinline__ void step_setup(const Consts &P, const float *__restrict__ seg,
+                                           const float *__restrict__ sph, int S, const float *inv_in, const Body &B,
+                                           int wkey, const float *wr, const WaveLds &lds, StepStats &stats,
+                                           StepState<SR> &st)
+{
+    const int lane = lane_id();
+    const int L = P.L;
+    step_pose<SR>(P, inv_in, B, st);
+    const float *R = st.R;
 
     // 2. narrow phase: lanes over spheres, candidates appended to LDS in
     //    (sphere block, link) order by ballot + prefix count
@@ -155,64 +230,10 @@ __device__ __forceinline__ void step_setup(const Consts &P, const float *__restr
     stats.contacts += C;
     stats.dropped += ncand - C;
 
-    // 4. contact setup, one contact per lane
-    st.act = lane < C;
-    st.key = st.act ? lds.sel[lane] : -1;
-    SR *F = st.F;
-    F[0] = 0; F[1] = 0; F[2] = 1; F[3] = 0; F[4] = 1; F[5] = 0; F[6] = 1; F[7] = 0; F[8] = 0;
-    st.rho[0] = st.rho[1] = st.rho[2] = SR(0);
-    st.ucst[0] = st.ucst[1] = st.ucst[2] = SR(0);
-    st.r[0] = st.r[1] = st.r[2] = SR(0);
-    st.link = -1;
-    st.k = 0;
-    st.l = L;
-    st.interior = false;
-    st.e_axis = 0;
-    st.tpar = 0.f;
-    st.dist = 0.f;
-    st.d = 0.f;
+    // 4. contact setup, one contact per lane, and the warm start from the
+    //    previous step's impulse of the same key
+    contact_setup<SR>(P, seg, sph, B, lane < C ? lds.sel[lane] : -1, st);
     if (st.act) {
-        int k = st.key / (L + 1);
-        int l = st.key - k * (L + 1);
-        st.k = k;
-        st.l = l;
-        const float4 t = *reinterpret_cast<const float4 *>(sph + 4 * k);
-        float s4[4] = {t.x, t.y, t.z, t.w};
-        float *c = st.c;
-        c[0] = B.x[0] + R[0] * s4[0] + R[1] * s4[1] + R[2] * s4[2];
-        c[1] = B.x[1] + R[3] * s4[0] + R[4] * s4[1] + R[5] * s4[2];
-        c[2] = B.x[2] + R[6] * s4[0] + R[7] * s4[1] + R[8] * s4[2];
-        float d, *n = st.n, *p = st.p, *vl = st.vl;
-        pair_contact(seg, l, L, c, s4[3], d, n, p, vl);
-        st.d = d;
-        if (l < L) {
-            const float *sg = seg + l * SEG_STRIDE;
-            float ca[3] = {c[0] - sg[0], c[1] - sg[1], c[2] - sg[2]};
-            float tr = (ca[0] * sg[4] + ca[1] * sg[5] + ca[2] * sg[6]) * sg[7];
-            st.interior = tr > 0.f && tr < 1.f;
-            st.tpar = fminf(fmaxf(tr, 0.f), 1.f);
-            st.dist = d + s4[3] + sg[3];
-        }
-        float t1[3], t2[3];
-        tangent_frame(n, t1, t2);
-        {
-            float an0 = fabsf(n[0]), an1 = fabsf(n[1]), an2 = fabsf(n[2]);
-            int e = 0;
-            float best = an0;
-            if (an1 < best) { e = 1; best = an1; }
-            if (an2 < best) { e = 2; }
-            st.e_axis = e;
-        }
-        F[0] = n[0]; F[1] = n[1]; F[2] = n[2];
-        F[3] = t1[0]; F[4] = t1[1]; F[5] = t1[2];
-        F[6] = t2[0]; F[7] = t2[1]; F[8] = t2[2];
-        st.rho[0] = p[0] - B.x[0]; st.rho[1] = p[1] - B.x[1]; st.rho[2] = p[2] - B.x[2];
-        float bn = d >= 0.f ? d / dt : P.erp * d / dt;
-        st.ucst[0] = -(n[0] * vl[0] + n[1] * vl[1] + n[2] * vl[2]) + bn;
-        st.ucst[1] = -(t1[0] * vl[0] + t1[1] * vl[1] + t1[2] * vl[2]);
-        st.ucst[2] = -(t2[0] * vl[0] + t2[1] * vl[1] + t2[2] * vl[2]);
-        st.link = l < L ? l : -1;
-        // warm start from the previous step's impulse of the same key
         for (int j = 0; j < P.C_max; ++j) {
             if (lds.wkey[j] == st.key) {
                 st.r[0] = lds.wr[3 * j]; st.r[1] = lds.wr[3 * j + 1]; st.r[2] = lds.wr[3 * j + 2];
