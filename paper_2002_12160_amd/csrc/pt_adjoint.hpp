@@ -98,15 +98,15 @@ __device__ __forceinline__ void rdr_adj(const SR *R, const SR *dg, const SR *Mb,
 // Adjoint of one step.  `st` holds the recomputed forward step (after
 // step_setup and step_solve) for pre-step body B; gt is this step's observed
 // sensor record ([4][L][G], group g); stage and stage2 are LDS scratch of
-// 64 x 4 and 64 x 3 floats.  bar: in = adjoint of the post-step state, out =
+// 64 x 4 and 64 x 3 floats, red the LDS of the cross-contact sums.  bar: in = adjoint of the post-step state, out =
 // adjoint of the pre-step state (x, q as stored, v, w); mbar and mubar
 // accumulate; fbar (optional) receives the adjoint of the one-step external
 // force.
 template <typename SR>
 __device__ void step_adjoint(const Consts &P, const float *__restrict__ seg, const float *__restrict__ sph,
                              const float *inv_in, const Body &B, const StepState<SR> &st,
-                             const float *__restrict__ gt, int g, float *stage, float *stage2, BodyBar<SR> &bar,
-                             SR &mbar, SR &mubar, SR *fbar)
+                             const float *__restrict__ gt, int g, float *stage, float *stage2, SR *red,
+                             BodyBar<SR> &bar, SR &mbar, SR &mubar, SR *fbar)
 {
     const int lane = lane_id();
     const int L = P.L;
@@ -323,7 +323,7 @@ __device__ void step_adjoint(const Consts &P, const float *__restrict__ seg, con
 #pragma unroll
             for (int i = 0; i < 42; ++i) acc[i] = SR(0);
         }
-        if (st.C > 0) wave_sum<SR, 42>(acc, span);
+        if (st.C > 0) lds_sum<SR, 42>(acc, st.C, red);
         SR z[6];
         schur_solve(acc, im, Iinv, z);
 #pragma unroll

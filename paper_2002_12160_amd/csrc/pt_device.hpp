@@ -371,50 +371,134 @@ __device__ __forceinline__ void inv3(const T *a, T *o)
     o[8] = (a[0] * a[4] - a[1] * a[3]) * id;
 }
 
-// in-register 6x6 LU with partial pivoting; solves A z = b (A, b destroyed)
+// 6x6 solve S z = b by 3x3 blocks S = [[A, B], [Cb, D]]:
+// z2 = (D - Cb A^-1 B)^-1 (b2 - Cb A^-1 b1), z1 = A^-1 (b1 - B z2), both 3x3
+// inverses by the adjugate.  A = I + (1/m) sum of the contacts' world blocks
+// (the translational part of I + M^-1 sum J^T Q J) and its Schur complement
+// (the rotational part) stay well away from singular, so no pivoting is done:
+// every lane runs the same straight-line code in registers.
 template <typename T>
-__device__ __forceinline__ void solve6(T (&A)[36], T (&b)[6])
+__device__ __forceinline__ void solve6(const T (&S)[36], T (&b)[6])
 {
+    T A[9], Bm[9], Cb[9], Dm[9];
 #pragma unroll
-    for (int k = 0; k < 6; ++k) {
-        // pivot search (values are wave-uniform, so is the branch)
-        int piv = k;
-        T best = fabs(A[6 * k + k]);
+    for (int i = 0; i < 3; ++i)
 #pragma unroll
-        for (int i = k + 1; i < 6; ++i) {
-            T v = fabs(A[6 * i + k]);
-            if (v > best) { best = v; piv = i; }
+        for (int j = 0; j < 3; ++j) {
+            A[3 * i + j] = S[6 * i + j];
+            Bm[3 * i + j] = S[6 * i + 3 + j];
+            Cb[3 * i + j] = S[6 * (3 + i) + j];
+            Dm[3 * i + j] = S[6 * (3 + i) + 3 + j];
         }
-        // swap rows k and piv with selects (keeps everything in registers)
+    T Ai[9];
+    inv3(A, Ai);
+    T X[9];   // A^-1 B
 #pragma unroll
-        for (int i = k + 1; i < 6; ++i) {
-            bool sw = (piv == i);
+    for (int i = 0; i < 3; ++i)
 #pragma unroll
-            for (int j = 0; j < 6; ++j) {
-                T a = A[6 * k + j], c = A[6 * i + j];
-                A[6 * k + j] = sw ? c : a;
-                A[6 * i + j] = sw ? a : c;
+        for (int j = 0; j < 3; ++j) X[3 * i + j] = Ai[3 * i] * Bm[j] + Ai[3 * i + 1] * Bm[3 + j] + Ai[3 * i + 2] * Bm[6 + j];
+    T y1[3] = {Ai[0] * b[0] + Ai[1] * b[1] + Ai[2] * b[2], Ai[3] * b[0] + Ai[4] * b[1] + Ai[5] * b[2],
+               Ai[6] * b[0] + Ai[7] * b[1] + Ai[8] * b[2]};
+    T Sc[9], r2[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            Sc[3 * i + j] = Dm[3 * i + j] - (Cb[3 * i] * X[j] + Cb[3 * i + 1] * X[3 + j] + Cb[3 * i + 2] * X[6 + j]);
+        r2[i] = b[3 + i] - (Cb[3 * i] * y1[0] + Cb[3 * i + 1] * y1[1] + Cb[3 * i + 2] * y1[2]);
+    }
+    T Si[9];
+    inv3(Sc, Si);
+    T z2[3] = {Si[0] * r2[0] + Si[1] * r2[1] + Si[2] * r2[2], Si[3] * r2[0] + Si[4] * r2[1] + Si[5] * r2[2],
+               Si[6] * r2[0] + Si[7] * r2[1] + Si[8] * r2[2]};
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        b[i] = y1[i] - (X[3 * i] * z2[0] + X[3 * i + 1] * z2[1] + X[3 * i + 2] * z2[2]);
+        b[3 + i] = z2[i];
+    }
+}
+
+// Row stride (elements) of the LDS reduction buffer: rows start 16-byte
+// aligned and 4 banks apart, so the row writes of a wavefront spread over
+// all banks.
+template <typename T>
+struct RedStride {
+    static constexpr int value = sizeof(T) == 8 ? 50 : 68;
+};
+
+template <typename T>
+__device__ __forceinline__ void store16(T *p, const T *v);
+template <>
+__device__ __forceinline__ void store16<double>(double *p, const double *v)
+{
+    *reinterpret_cast<double2 *>(p) = make_double2(v[0], v[1]);
+}
+template <>
+__device__ __forceinline__ void store16<float>(float *p, const float *v)
+{
+    *reinterpret_cast<float4 *>(p) = make_float4(v[0], v[1], v[2], v[3]);
+}
+template <typename T>
+__device__ __forceinline__ void load16(const T *p, T *v);
+template <>
+__device__ __forceinline__ void load16<double>(const double *p, double *v)
+{
+    double2 a = *reinterpret_cast<const double2 *>(p);
+    v[0] = a.x; v[1] = a.y;
+}
+template <>
+__device__ __forceinline__ void load16<float>(const float *p, float *v)
+{
+    float4 a = *reinterpret_cast<const float4 *>(p);
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+}
+
+// Sum of v[0..N) over lanes [0, n) through LDS, for wide vectors where DPP
+// rounds would cost N instructions each: the lanes below n write their
+// values as rows, lane j < N adds column j over the rows (four interleaved
+// partial sums in a fixed order), the N sums go back to LDS and every lane reads
+// all of them -- the same bits in every lane.  Lanes >= n do not take part
+// (their values must be zero for the sum to mean the whole wave's).
+// buf: 16-byte aligned, max(n, 1) rows of RedStride<T> elements.
+template <typename T, int N>
+__device__ __forceinline__ void lds_sum(T (&v)[N], int n, T *buf)
+{
+    constexpr int RS = RedStride<T>::value;
+    constexpr int PER = 16 / (int)sizeof(T);
+    static_assert(N <= RS && N <= 64, "vector too long for the reduction buffer");
+    const int lane = lane_id();
+    if (lane < n) {
+        T *row = buf + lane * RS;
+#pragma unroll
+        for (int j = 0; j + PER <= N; j += PER) store16<T>(row + j, v + j);
+#pragma unroll
+        for (int j = N - N % PER; j < N; ++j) row[j] = v[j];
+    }
+    wave_sync();
+    // eight rows in flight per round (rows past n read row n-1 and add 0),
+    // four interleaved partial sums
+    T s4[4] = {T(0), T(0), T(0), T(0)};
+    if (lane < N) {
+        for (int r0 = 0; r0 < n; r0 += 8) {
+            T x[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const int r = r0 + k < n ? r0 + k : n - 1;
+                x[k] = buf[r * RS + lane];
             }
-            T a = b[k], c = b[i];
-            b[k] = sw ? c : a;
-            b[i] = sw ? a : c;
-        }
-        T ip = T(1) / A[6 * k + k];
 #pragma unroll
-        for (int i = k + 1; i < 6; ++i) {
-            T f = A[6 * i + k] * ip;
-#pragma unroll
-            for (int j = k + 1; j < 6; ++j) A[6 * i + j] -= f * A[6 * k + j];
-            b[i] -= f * b[k];
+            for (int k = 0; k < 8; ++k) s4[k & 3] += r0 + k < n ? x[k] : T(0);
         }
     }
+    const T s = (s4[0] + s4[1]) + (s4[2] + s4[3]);
+    wave_sync();
+    if (lane < N) buf[lane] = s;
+    wave_sync();
 #pragma unroll
-    for (int k = 5; k >= 0; --k) {
-        T s = b[k];
+    for (int j = 0; j + PER <= N; j += PER) load16<T>(buf + j, v + j);
 #pragma unroll
-        for (int j = k + 1; j < 6; ++j) s -= A[6 * k + j] * b[j];
-        b[k] = s / A[6 * k + k];
-    }
+    for (int j = N - N % PER; j < N; ++j) v[j] = buf[j];
+    wave_sync();
 }
 
 // One contact's contribution to the 6x6 Schur system: with the world-frame

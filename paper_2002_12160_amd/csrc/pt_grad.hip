@@ -126,7 +126,7 @@ __global__ __launch_bounds__(WAVE) void k_window_fwd(Consts P, Tables tb, const 
         const float *seg = seg_win + (size_t)t * P.L * SEG_STRIDE;
         StepState<SR> st;
         step_setup<SR>(P, seg, sph, S, inv, B, wkey, wr, lds, stt, st);
-        step_solve<SR>(P, st, B.mu);
+        step_solve<SR>(P, st, B.mu, reinterpret_cast<SR *>(lds.cand_d));
         if (ck) save_contact<SR>(ck, P.C_max, st);
         int link;
         float imp[3];
@@ -212,8 +212,8 @@ __global__ __launch_bounds__(WAVE) void k_window_bwd(Consts P, Tables tb, const 
         body_dv(st, st.r, st.nu);
         st.nu[0] += st.vs[0]; st.nu[1] += st.vs[1]; st.nu[2] += st.vs[2];
         st.nu[3] += st.ws[0]; st.nu[4] += st.ws[1]; st.nu[5] += st.ws[2];
-        step_adjoint<SR>(P, seg, sph, inv, B, st, obs_gt_win + (size_t)t * 4 * LG, g, stage, lds.wr, bar, mbar,
-                         mubar, t == 0 ? fbar : nullptr);
+        step_adjoint<SR>(P, seg, sph, inv, B, st, obs_gt_win + (size_t)t * 4 * LG, g, stage, lds.wr,
+                         reinterpret_cast<SR *>(lds.cand_d), bar, mbar, mubar, t == 0 ? fbar : nullptr);
     }
     if (lane == 0) {
         const SR gv[XI_ROWS] = {bar.x[0], bar.x[1], bar.x[2], bar.q[0], bar.q[1], bar.q[2], bar.q[3],

@@ -208,14 +208,24 @@ __device__ __forceinline__ void step_setup(const Consts &P, const float *__restr
 
     // 3. cap: rank of every candidate in (d, key) order; the C_max lowest
     //    land in sel[rank]
+    //    (all lanes read the same four candidates per 16-byte LDS read;
+    //    entries past ncand are padded with (+inf, INT_MAX), never below)
+    if (lane < 4) {
+        lds.cand_d[ncand + lane] = __int_as_float(0x7f800000);
+        lds.cand_k[ncand + lane] = 0x7fffffff;
+    }
+    wave_sync();
     for (int i = lane; i < ncand; i += WAVE) {
         float di = lds.cand_d[i];
         int ki = lds.cand_k[i];
         int rank = 0;
-        for (int j = 0; j < ncand; ++j) {
-            float dj = lds.cand_d[j];
-            int kj = lds.cand_k[j];
-            rank += (dj < di || (dj == di && kj < ki)) ? 1 : 0;
+        for (int j = 0; j < ncand; j += 4) {
+            const float4 d4 = *reinterpret_cast<const float4 *>(lds.cand_d + j);
+            const int4 k4 = *reinterpret_cast<const int4 *>(lds.cand_k + j);
+            rank += (d4.x < di || (d4.x == di && k4.x < ki)) ? 1 : 0;
+            rank += (d4.y < di || (d4.y == di && k4.y < ki)) ? 1 : 0;
+            rank += (d4.z < di || (d4.z == di && k4.z < ki)) ? 1 : 0;
+            rank += (d4.w < di || (d4.w == di && k4.w < ki)) ? 1 : 0;
         }
         if (rank < P.C_max) lds.sel[rank] = ki;
     }
@@ -248,8 +258,10 @@ __device__ __forceinline__ void step_setup(const Consts &P, const float *__restr
 // 6x6 system (I + M^-1 sum_c J_c^T P_c^-1 B_c J_c) dnu =
 // -M^-1 sum_c J_c^T P_c^-1 Phi_c with P_c = JX_c + eps JY_c, B_c = JY_c; then
 // dr_c = -P_c^-1 (Phi_c + B_c J_c dnu).  Leaves st.r and the fresh st.nu.
+// red: LDS for the cross-contact sum of the 6x6 system (the wave's candidate
+// list, free once the cap has run).
 template <typename SR>
-__device__ __forceinline__ void step_solve(const Consts &P, StepState<SR> &st, float mu_f)
+__device__ __forceinline__ void step_solve(const Consts &P, StepState<SR> &st, float mu_f, SR *red)
 {
     const SR eps = P.compliance, kap = P.kappa, del = P.fb_delta, mu = mu_f;
     const SR imS = SR(1) / SR(st.m);
@@ -306,7 +318,7 @@ __device__ __forceinline__ void step_solve(const Consts &P, StepState<SR> &st, f
 #pragma unroll
                 for (int i = 0; i < 43; ++i) acc[i] = SR(0);
             }
-            wave_sum<SR, 43>(acc, span);
+            lds_sum<SR, 43>(acc, st.C, red);
             const SR psi = acc[42];
             SR rhs[6];
             schur_solve(acc, imS, IinvS, rhs);
@@ -320,11 +332,17 @@ __device__ __forceinline__ void step_solve(const Consts &P, StepState<SR> &st, f
             for (int i = 0; i < 3; ++i)
                 dr[i] = -g[i] - (QF[3 * i] * dp[0] + QF[3 * i + 1] * dp[1] + QF[3 * i + 2] * dp[2]);
             if (!act) { dr[0] = dr[1] = dr[2] = SR(0); }
-            // body-velocity change of the step, M^-1 J^T dr, summed afresh so
-            // that the tracked velocity stays consistent with r (the 6x6
-            // solution equals it only up to the Schur system's conditioning)
+            // body-velocity change of the step, M^-1 J^T dr: in float64 the
+            // 6x6 solution itself; in float32 summed afresh from dr, so that
+            // the tracked velocity stays consistent with r (the 6x6 solution
+            // equals it only up to the Schur system's conditioning)
             SR dn[6];
-            body_dv(st, dr, dn);
+            if (sizeof(SR) == 8) {
+#pragma unroll
+                for (int i = 0; i < 6; ++i) dn[i] = rhs[i];
+            } else {
+                body_dv(st, dr, dn);
+            }
             // du = W dr = F (dn_v + dn_w x rho) + eps dr
             SR du[3];
             {
@@ -426,7 +444,7 @@ __device__ __forceinline__ void env_step(const Consts &P, const float *__restric
 {
     StepState<SR> st;
     step_setup<SR>(P, seg, sph, S, inv_in, B, wkey, wr, lds, stats, st);
-    step_solve<SR>(P, st, B.mu);
+    step_solve<SR>(P, st, B.mu, reinterpret_cast<SR *>(lds.cand_d));
     step_finish<SR>(P, st, inv_in, B, wkey, wr, out_link, out_imp);
 }
 
