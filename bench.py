@@ -55,7 +55,7 @@ def parse():
 # HBM bytes per k_step launch of the 256-simulation workload (float64 solve),
 # from FETCH_SIZE / WRITE_SIZE counters scaled by a plain device copy of known
 # size (profiles/k_step_plain256.txt); None for any other configuration
-MEASURED_TRAFFIC = {("plain256", 64): 1091563}
+MEASURED_TRAFFIC = {("plain256", 64): 852957}
 
 
 # algorithmic floating-point operations (an FMA counts 2; a square root,
