@@ -55,62 +55,80 @@ __device__ void fk_joint(const float *__restrict__ h, const float *__restrict__ 
     for (int i = 0; i < 4; ++i) qj[i] = q[i];
 }
 
-// chain composition along the link tree (parents precede children)
-__device__ void fk_chain(const float *__restrict__ hand, int L, const double *qjs, double *tq, double *tp,
-                         double *seg_a, double *seg_b)
+// pose of link l in configuration w from its parent's (already computed):
+// origin, orientation and the segment [a, b] along the link's local +x axis
+__device__ void fk_link(const float *__restrict__ h, int parent, const double *qj, double *tq, double *tp,
+                        double *seg_a, double *seg_b, int l)
 {
-    for (int l = 0; l < L; ++l) {
-        const float *h = hand + l * HAND_STRIDE;
-        int parent = (int)h[0];
-        double pq[4] = {1, 0, 0, 0}, pp[3] = {0, 0, 0};
-        if (parent >= 0) {
-            for (int i = 0; i < 4; ++i) pq[i] = tq[4 * parent + i];
-            for (int i = 0; i < 3; ++i) pp[i] = tp[3 * parent + i];
-        }
-        double Rp[9];
-        quat_to_mat_d(pq, Rp);
-        double off[3] = {h[9], h[10], h[11]};
-        double o[3] = {pp[0] + Rp[0] * off[0] + Rp[1] * off[1] + Rp[2] * off[2],
-                       pp[1] + Rp[3] * off[0] + Rp[4] * off[1] + Rp[5] * off[2],
-                       pp[2] + Rp[6] * off[0] + Rp[7] * off[1] + Rp[8] * off[2]};
-        double qo[4] = {h[12], h[13], h[14], h[15]};
-        double q0[4], q[4];
-        quat_mul_d(pq, qo, q0);
-        quat_mul_d(q0, qjs + 4 * l, q);
-        double len = h[16];
-        // local +x axis of the link frame
-        double xa[3] = {1 - 2 * (q[2] * q[2] + q[3] * q[3]), 2 * (q[1] * q[2] + q[0] * q[3]),
-                        2 * (q[1] * q[3] - q[0] * q[2])};
-        double b[3] = {o[0] + len * xa[0], o[1] + len * xa[1], o[2] + len * xa[2]};
-        for (int i = 0; i < 4; ++i) tq[4 * l + i] = q[i];
-        for (int i = 0; i < 3; ++i) {
-            tp[3 * l + i] = b[i];
-            seg_a[3 * l + i] = o[i];
-            seg_b[3 * l + i] = b[i];
-        }
+    double pq[4] = {1, 0, 0, 0}, pp[3] = {0, 0, 0};
+    if (parent >= 0) {
+        for (int i = 0; i < 4; ++i) pq[i] = tq[4 * parent + i];
+        for (int i = 0; i < 3; ++i) pp[i] = tp[3 * parent + i];
+    }
+    double Rp[9];
+    quat_to_mat_d(pq, Rp);
+    double off[3] = {h[9], h[10], h[11]};
+    double o[3] = {pp[0] + Rp[0] * off[0] + Rp[1] * off[1] + Rp[2] * off[2],
+                   pp[1] + Rp[3] * off[0] + Rp[4] * off[1] + Rp[5] * off[2],
+                   pp[2] + Rp[6] * off[0] + Rp[7] * off[1] + Rp[8] * off[2]};
+    double qo[4] = {h[12], h[13], h[14], h[15]};
+    double q0[4], q[4];
+    quat_mul_d(pq, qo, q0);
+    quat_mul_d(q0, qj + 4 * l, q);
+    double len = h[16];
+    // local +x axis of the link frame
+    double xa[3] = {1 - 2 * (q[2] * q[2] + q[3] * q[3]), 2 * (q[1] * q[2] + q[0] * q[3]),
+                    2 * (q[1] * q[3] - q[0] * q[2])};
+    double b[3] = {o[0] + len * xa[0], o[1] + len * xa[1], o[2] + len * xa[2]};
+    for (int i = 0; i < 4; ++i) tq[4 * l + i] = q[i];
+    for (int i = 0; i < 3; ++i) {
+        tp[3 * l + i] = b[i];
+        seg_a[3 * l + i] = o[i];
+        seg_b[3 * l + i] = b[i];
     }
 }
 
-// grid: one block per step; u_prev/u for step t at u_prev + t*stride.
-// Joint rotations (the transcendental part) are computed by one thread per
-// (configuration, link); two threads then compose the chains.
-__global__ void k_hand_fk(const float *__restrict__ hand, int L, float dt, const float *__restrict__ u_prev,
-                          const float *__restrict__ u, int stride, float *__restrict__ seg_out)
+// grid: one block per step; u_prev/u for step t at u_prev + t*stride.  The
+// hand table is staged in LDS; joint rotations (the transcendental part) run
+// one thread per (configuration, link); the chains are composed level by
+// level of the link tree (links at one depth in parallel, both
+// configurations at once), so the serial depth is the longest chain.
+__global__ __launch_bounds__(128) void k_hand_fk(const float *__restrict__ hand, int L, float dt,
+                                                 const float *__restrict__ u_prev, const float *__restrict__ u,
+                                                 int stride, float *__restrict__ seg_out)
 {
+    __shared__ float hs[MAX_LINKS * HAND_STRIDE];
+    __shared__ int depth[MAX_LINKS];
     __shared__ double qj[2][MAX_LINKS * 4], tq[2][MAX_LINKS * 4], tp[2][MAX_LINKS * 3], sa[2][MAX_LINKS * 3],
         sb[2][MAX_LINKS * 3];
     const int t = blockIdx.x;
+    for (int i = threadIdx.x; i < L * HAND_STRIDE; i += blockDim.x) hs[i] = hand[i];
+    __syncthreads();
+    for (int l = threadIdx.x; l < L; l += blockDim.x) {
+        // parents precede children (checked at batch creation), so the walk ends
+        int d = 0, p = (int)hs[l * HAND_STRIDE];
+        while (p >= 0) {
+            ++d;
+            p = (int)hs[p * HAND_STRIDE];
+        }
+        depth[l] = d;
+    }
     for (int i = threadIdx.x; i < 2 * L; i += blockDim.x) {
         int w = i / L, l = i - w * L;
         const float *uu = (w == 0 ? u_prev : u) + (size_t)t * stride;
-        fk_joint(hand + l * HAND_STRIDE, uu, &qj[w][4 * l]);
+        fk_joint(hs + l * HAND_STRIDE, uu, &qj[w][4 * l]);
     }
     __syncthreads();
-    if (threadIdx.x < 2) {
-        int w = threadIdx.x;
-        fk_chain(hand, L, qj[w], tq[w], tp[w], sa[w], sb[w]);
+    int dmax = 0;
+    for (int l = 0; l < L; ++l) dmax = max(dmax, depth[l]);
+    for (int d = 0; d <= dmax; ++d) {
+        for (int i = threadIdx.x; i < 2 * L; i += blockDim.x) {
+            int w = i / L, l = i - w * L;
+            if (depth[l] == d)
+                fk_link(hs + l * HAND_STRIDE, (int)hs[l * HAND_STRIDE], qj[w], tq[w], tp[w], sa[w], sb[w], l);
+        }
+        __syncthreads();
     }
-    __syncthreads();
     const double idt = 1.0 / (double)dt;
     for (int l = threadIdx.x; l < L; l += blockDim.x) {
         float *s = seg_out + ((size_t)t * L + l) * SEG_STRIDE;
@@ -127,7 +145,7 @@ __global__ void k_hand_fk(const float *__restrict__ hand, int L, float dt, const
             s[8 + i] = (float)((sa[1][3 * l + i] - sa[0][3 * l + i]) * idt);
             s[12 + i] = (float)((sb[1][3 * l + i] - sb[0][3 * l + i]) * idt);
         }
-        s[3] = hand[l * HAND_STRIDE + 17];
+        s[3] = hs[l * HAND_STRIDE + 17];
         s[7] = inv;
         s[11] = 0.f;
         s[15] = 0.f;
@@ -438,7 +456,7 @@ using namespace pt;
 hipError_t launch_hand_fk(const float *hand, int L, float dt, const float *u_prev, const float *u, int stride,
                           int nsteps, float *seg_out, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_hand_fk, dim3(nsteps), dim3(64), 0, s, hand, L, dt, u_prev, u, stride, seg_out);
+    hipLaunchKernelGGL(k_hand_fk, dim3(nsteps), dim3(128), 0, s, hand, L, dt, u_prev, u, stride, seg_out);
     return hipGetLastError();
 }
 
