@@ -32,11 +32,10 @@
  *     float32/int32 memory (torch tensors) unless stated "host".
  *   - Every call is asynchronous on the given HIP stream; nothing here
  *     synchronises the device except pt_read_stats and pt_autotune.
- *   - Device memory is allocated by pt_create_batch (scene tables, internal
- *     scratch), by pt_autotune (scratch copies, freed before it returns) and
- *     on first use by pt_window_grad / pt_refine_elites (checkpoints and
- *     refinement buffers, grown on demand); pt_destroy_batch frees it all.
- *     Calls that may allocate must not run under stream capture.
+ *   - Device memory is allocated only by pt_create_batch (scene tables and
+ *     the library's scratch: hand segments, contact buffer, counters, the
+ *     autotuner's copies, gradient checkpoints for the elites, refinement
+ *     buffers) and freed by pt_destroy_batch; no other call allocates.
  *   - Return value: PT_OK (0) or an error code; pt_last_error() returns a
  *     thread-local message for the last failing call on that thread.
  *     Argument and shape errors are detected before any launch.  Kernel
@@ -227,9 +226,11 @@ PT_API pt_status pt_set_tuning(pt_batch b, int32_t waves_per_workgroup);
  *   end_state  [13][n]        out: state after the window, or NULL
  *   end_warm   [n][C_max][4]  out: warm cache after the window, or NULL
  * The batch's own state, params and warm cache are neither read nor written.
- * The checkpoints (n * T * (16 + 4 * C_max) floats) live in a buffer the
- * batch owns and shares between calls: calls on different streams must not
- * overlap. */
+ * The checkpoints (per simulation and step the body and the contacts' keys
+ * and float64 impulses, 64 + 32 C_max bytes) live in a buffer the batch owns,
+ * sized for pt_elite_count(b) simulations; longer lists run in chunks of that
+ * many.  The buffer is shared between calls: calls on different streams must
+ * not overlap. */
 PT_API pt_status pt_window_grad(pt_batch b, const float *u_win, const float *obs_gt_win, int32_t n,
                                 const int32_t *env, const float *start, const float *warm0, float *cost,
                                 float *grad, float *end_state, float *end_warm, pt_stream s);
@@ -254,8 +255,8 @@ PT_API pt_status pt_window_grad(pt_batch b, const float *u_win, const float *obs
  *   best           [G] argmin of cost_sum per group afterwards, or NULL
  *   elite_out      [pt_elite_count(b)] int32 batch index of each elite
  *                  (groups in order, by rank within a group), or NULL
- * Buffers for the elites' starts, gradients and checkpoints are allocated on
- * first use and kept by the batch. */
+ * The elites' starts, gradients and checkpoints use buffers the batch holds
+ * from pt_create_batch on; calls on different streams must not overlap. */
 PT_API pt_status pt_refine_elites(pt_batch b, const float *u_win, const float *obs_gt_win, float *cost_sum,
                                   const float *start_state, const float *start_params, const float *start_warm,
                                   int32_t steps, float step, const float *scale, int32_t *best, int32_t *elite_out,

@@ -66,9 +66,9 @@ struct pt_batch_s {
     float *d_seg_win = nullptr;  // [T][L][16]
     float *d_contacts = nullptr; // [K][C_max][4]
     float *d_seg_grad = nullptr; // [T][L][16] for the gradient and refinement calls
-    // gradient checkpoints and refinement buffers, grown on demand
+    float *d_tune = nullptr;     // autotuner's copies of state, params, warm cache and costs
+    // gradient checkpoints (for n_elite simulations at a time) and refinement buffers
     float *d_ckpt = nullptr;
-    size_t ckpt_cap = 0;         // floats
     int n_elite = 0;
     int32_t *d_elite = nullptr;  // [n_elite]
     float *d_ref = nullptr;      // see refine_layout
@@ -151,6 +151,46 @@ int max_wpb(const Consts &P) { return P.solve_fp64 ? 4 : 8; }
 
 }  // namespace
 
+// refinement buffers of n elites, carved from one allocation (every block a
+// multiple of 4 floats, so the warm caches stay 16-byte aligned)
+struct RefineBufs {
+    float *xi, *xi_try, *g, *cost, *cost_try, *rho, *end_state, *end_warm, *warm0;
+    int32_t *flag;
+};
+
+static size_t pad4(size_t x) { return (x + 3) / 4 * 4; }
+
+static size_t refine_floats(const Consts &P, int n)
+{
+    const size_t w = (size_t)n * P.C_max * 4;
+    return 3 * pad4((size_t)pt::XI_ROWS * n) + 4 * pad4(n) + pad4(13 * (size_t)n) + 2 * w;
+}
+
+static RefineBufs refine_layout(float *base, const Consts &P, int n)
+{
+    RefineBufs r;
+    const size_t x = pad4((size_t)pt::XI_ROWS * n), v = pad4(n), w = (size_t)n * P.C_max * 4;
+    r.xi = base;
+    r.xi_try = r.xi + x;
+    r.g = r.xi_try + x;
+    r.cost = r.g + x;
+    r.cost_try = r.cost + v;
+    r.rho = r.cost_try + v;
+    r.flag = reinterpret_cast<int32_t *>(r.rho + v);
+    r.end_state = r.rho + 2 * v;
+    r.end_warm = r.end_state + pad4(13 * (size_t)n);
+    r.warm0 = r.end_warm + w;
+    return r;
+}
+
+// autotuner scratch: copies of state [13][K], params [5][K], warm cache
+// [K][C_max][4] and costs [K]
+static size_t tune_floats(const Consts &P)
+{
+    const size_t K = P.K;
+    return 13 * K + 5 * K + K * P.C_max * 4 + K;
+}
+
 extern "C" {
 
 const char *pt_last_error(void) { return g_err.c_str(); }
@@ -232,8 +272,12 @@ pt_status pt_create_batch(const pt_batch_desc *d, pt_batch *out)
     HIP_TRY_C(hipMalloc(&b->d_seg_win, sizeof(float) * (size_t)d->T * d->L * pt::SEG_STRIDE));
     HIP_TRY_C(hipMalloc(&b->d_contacts, sizeof(float) * K * d->C_max * 4));
     HIP_TRY_C(hipMalloc(&b->d_seg_grad, sizeof(float) * (size_t)d->T * d->L * pt::SEG_STRIDE));
+    HIP_TRY_C(hipMalloc(&b->d_tune, sizeof(float) * tune_floats(P)));
     for (int g = 0; g < d->G; ++g)
         b->n_elite += pt::elite_count(d->group_start[g + 1] - d->group_start[g], d->elite_frac);
+    HIP_TRY_C(hipMalloc(&b->d_ckpt, sizeof(float) * ckpt_floats(P, b->n_elite)));
+    HIP_TRY_C(hipMalloc(&b->d_ref, sizeof(float) * refine_floats(P, b->n_elite)));
+    HIP_TRY_C(hipMalloc(&b->d_elite, sizeof(int32_t) * b->n_elite));
     HIP_TRY_C(hipMemcpy(b->d_hand, d->hand, sizeof(float) * d->L * PT_HAND_STRIDE, hipMemcpyHostToDevice));
     HIP_TRY_C(hipMemcpy(b->d_spheres, d->spheres, sizeof(float) * d->n_types * d->S_max * 4, hipMemcpyHostToDevice));
     HIP_TRY_C(hipMemcpy(b->d_inv, d->inv_inertia, sizeof(float) * d->n_types * 3, hipMemcpyHostToDevice));
@@ -263,7 +307,7 @@ pt_status pt_destroy_batch(pt_batch b)
     if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
     void *ptrs[] = {b->d_hand, b->d_spheres, b->d_inv, b->d_nsph, b->d_type, b->d_group_of, b->d_group_start,
                     b->d_order, b->d_queue, b->d_stats, b->d_seg, b->d_seg_win, b->d_contacts,
-                    b->d_seg_grad, b->d_ckpt, b->d_elite, b->d_ref};
+                    b->d_seg_grad, b->d_tune, b->d_ckpt, b->d_elite, b->d_ref};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete b;
@@ -398,9 +442,7 @@ pt_status pt_autotune(pt_batch b, const float *u_win, const float *obs_gt_win, i
     const Consts &P = b->P;
     const size_t K = P.K;
     const size_t n_state = 13 * K, n_params = 5 * K, n_warm = K * P.C_max * 4;
-    float *tmp = nullptr;
-    HIP_TRY(hipMalloc(&tmp, sizeof(float) * (n_state + n_params + n_warm + K)));
-    float *ts = tmp, *tp = ts + n_state, *tw = tp + n_params, *tc = tw + n_warm;
+    float *ts = b->d_tune, *tp = ts + n_state, *tw = tp + n_params, *tc = tw + n_warm;
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
@@ -442,7 +484,6 @@ pt_status pt_autotune(pt_batch b, const float *u_win, const float *obs_gt_win, i
     (void)hipStreamSynchronize(st);
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    (void)hipFree(tmp);
     if (rc != PT_OK) return rc;
     b->wpb = best_wpb;
     if (result) *result = best_wpb;
@@ -461,22 +502,6 @@ pt_status pt_set_tuning(pt_batch b, int32_t wpb)
     return PT_OK;
 }
 
-// checkpoint buffer of at least `floats` floats (the stream is drained
-// before an old buffer is released)
-static pt_status ensure_ckpt(pt_batch b, size_t floats, hipStream_t st)
-{
-    if (b->ckpt_cap >= floats) return PT_OK;
-    if (b->d_ckpt) {
-        HIP_TRY(hipStreamSynchronize(st));
-        HIP_TRY(hipFree(b->d_ckpt));
-        b->d_ckpt = nullptr;
-        b->ckpt_cap = 0;
-    }
-    HIP_TRY(hipMalloc(&b->d_ckpt, sizeof(float) * floats));
-    b->ckpt_cap = floats;
-    return PT_OK;
-}
-
 pt_status pt_window_grad(pt_batch b, const float *u_win, const float *obs_gt_win, int32_t n, const int32_t *env,
                          const float *start, const float *warm0, float *cost, float *grad, float *end_state,
                          float *end_warm, pt_stream s)
@@ -488,49 +513,23 @@ pt_status pt_window_grad(pt_batch b, const float *u_win, const float *obs_gt_win
         return fail(PT_E_ARG, "u_win/obs_gt_win/env/start/warm0/cost is NULL");
     hipStream_t st = (hipStream_t)s;
     const Consts &P = b->P;
-    if (grad) {
-        pt_status rc = ensure_ckpt(b, ckpt_floats(P, n), st);
-        if (rc != PT_OK) return rc;
-    }
     const Tables tb = tables_of(b);
     HIP_TRY(launch_hand_fk(b->d_hand, P.L, P.dt, u_win, u_win + P.D, P.D, P.T, b->d_seg_grad, st));
-    HIP_TRY(launch_window_fwd(P, tb, b->d_seg_grad, n, env, start, warm0, obs_gt_win, cost, end_state, end_warm,
-                              grad ? b->d_ckpt : nullptr, st));
-    if (grad)
-        HIP_TRY(launch_window_bwd(P, tb, b->d_seg_grad, n, env, start, obs_gt_win, b->d_ckpt, nullptr, grad, st));
+    if (!grad) {
+        HIP_TRY(launch_window_fwd(P, tb, b->d_seg_grad, n, 0, n, env, start, warm0, obs_gt_win, cost, end_state,
+                                  end_warm, nullptr, st));
+        return PT_OK;
+    }
+    // the checkpoint buffer holds n_elite simulations: forward and reverse
+    // sweeps run in chunks of that many
+    for (int i0 = 0; i0 < n; i0 += b->n_elite) {
+        const int cnt = std::min(b->n_elite, n - i0);
+        HIP_TRY(launch_window_fwd(P, tb, b->d_seg_grad, n, i0, cnt, env, start, warm0, obs_gt_win, cost, end_state,
+                                  end_warm, b->d_ckpt, st));
+        HIP_TRY(launch_window_bwd(P, tb, b->d_seg_grad, n, i0, cnt, env, start, obs_gt_win, b->d_ckpt, nullptr, grad,
+                                  st));
+    }
     return PT_OK;
-}
-
-// refinement buffers of n elites, carved from one allocation (every block a
-// multiple of 4 floats, so the warm caches stay 16-byte aligned)
-struct RefineBufs {
-    float *xi, *xi_try, *g, *cost, *cost_try, *rho, *end_state, *end_warm, *warm0;
-    int32_t *flag;
-};
-
-static size_t pad4(size_t x) { return (x + 3) / 4 * 4; }
-
-static size_t refine_floats(const Consts &P, int n)
-{
-    const size_t w = (size_t)n * P.C_max * 4;
-    return 3 * pad4((size_t)pt::XI_ROWS * n) + 4 * pad4(n) + pad4(13 * (size_t)n) + 2 * w;
-}
-
-static RefineBufs refine_layout(float *base, const Consts &P, int n)
-{
-    RefineBufs r;
-    const size_t x = pad4((size_t)pt::XI_ROWS * n), v = pad4(n), w = (size_t)n * P.C_max * 4;
-    r.xi = base;
-    r.xi_try = r.xi + x;
-    r.g = r.xi_try + x;
-    r.cost = r.g + x;
-    r.cost_try = r.cost + v;
-    r.rho = r.cost_try + v;
-    r.flag = reinterpret_cast<int32_t *>(r.rho + v);
-    r.end_state = r.rho + 2 * v;
-    r.end_warm = r.end_state + pad4(13 * (size_t)n);
-    r.warm0 = r.end_warm + w;
-    return r;
 }
 
 pt_status pt_refine_elites(pt_batch b, const float *u_win, const float *obs_gt_win, float *cost_sum,
@@ -554,12 +553,6 @@ pt_status pt_refine_elites(pt_batch b, const float *u_win, const float *obs_gt_w
     hipStream_t st = (hipStream_t)s;
     const Consts &P = b->P;
     const int n = b->n_elite;
-    if (!b->d_ref) {
-        HIP_TRY(hipMalloc(&b->d_ref, sizeof(float) * refine_floats(P, n)));
-        HIP_TRY(hipMalloc(&b->d_elite, sizeof(int32_t) * n));
-    }
-    pt_status rc = ensure_ckpt(b, ckpt_floats(P, n), st);
-    if (rc != PT_OK) return rc;
     RefineBufs r = refine_layout(b->d_ref, P, n);
     const Tables tb = tables_of(b);
     HIP_TRY(launch_select_elites(P.G, b->R.elite_frac, b->d_group_start, cost_sum, b->d_elite, st));
@@ -569,23 +562,23 @@ pt_status pt_refine_elites(pt_batch b, const float *u_win, const float *obs_gt_w
         HIP_TRY(launch_hand_fk(b->d_hand, P.L, P.dt, u_win, u_win + P.D, P.D, P.T, b->d_seg_grad, st));
         HIP_TRY(launch_refine_gather(n, P.K, P.C_max, b->d_elite, start_state, start_params, start_warm, r.xi,
                                      r.warm0, r.rho, step, st));
-        HIP_TRY(launch_window_fwd(P, tb, b->d_seg_grad, n, b->d_elite, r.xi, r.warm0, obs_gt_win, r.cost, nullptr,
-                                  nullptr, b->d_ckpt, st));
-        HIP_TRY(launch_window_bwd(P, tb, b->d_seg_grad, n, b->d_elite, r.xi, obs_gt_win, b->d_ckpt, nullptr, r.g,
-                                  st));
+        HIP_TRY(launch_window_fwd(P, tb, b->d_seg_grad, n, 0, n, b->d_elite, r.xi, r.warm0, obs_gt_win, r.cost,
+                                  nullptr, nullptr, b->d_ckpt, st));
+        HIP_TRY(launch_window_bwd(P, tb, b->d_seg_grad, n, 0, n, b->d_elite, r.xi, obs_gt_win, b->d_ckpt, nullptr,
+                                  r.g, st));
         for (int it = 0; it < steps; ++it) {
             // trial, its replay (checkpointed unless it is the last), keep or
             // halve, then the gradient at the kept trials only
             const bool last = it == steps - 1;
             HIP_TRY(launch_refine_propose(n, A, r.xi, r.g, r.rho, r.xi_try, st));
-            HIP_TRY(launch_window_fwd(P, tb, b->d_seg_grad, n, b->d_elite, r.xi_try, r.warm0, obs_gt_win, r.cost_try,
-                                      r.end_state, r.end_warm, last ? nullptr : b->d_ckpt, st));
+            HIP_TRY(launch_window_fwd(P, tb, b->d_seg_grad, n, 0, n, b->d_elite, r.xi_try, r.warm0, obs_gt_win,
+                                      r.cost_try, r.end_state, r.end_warm, last ? nullptr : b->d_ckpt, st));
             HIP_TRY(launch_refine_accept(n, P.K, P.C_max, b->d_elite, r.cost, r.cost_try, r.xi, r.xi_try, r.rho,
                                          r.flag, r.end_state, r.end_warm, b->state, b->params, b->warm, cost_sum,
                                          st));
             if (!last)
-                HIP_TRY(launch_window_bwd(P, tb, b->d_seg_grad, n, b->d_elite, r.xi, obs_gt_win, b->d_ckpt, r.flag,
-                                          r.g, st));
+                HIP_TRY(launch_window_bwd(P, tb, b->d_seg_grad, n, 0, n, b->d_elite, r.xi, obs_gt_win, b->d_ckpt,
+                                          r.flag, r.g, st));
         }
     }
     if (best) HIP_TRY(launch_argmin(P.G, b->d_group_start, cost_sum, best, st));

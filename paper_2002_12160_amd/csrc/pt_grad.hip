@@ -83,8 +83,11 @@ __device__ __forceinline__ void load_start(const float *__restrict__ xi, int n, 
 }
 
 // xi is [18][n]: x(3) q(4) v(3) w(3) m mu f(3); warm0 is [n][C_max][4]
+// One launch covers `count` listed simulations i0 .. i0+count-1 of arrays
+// with row stride n; the checkpoint buffer holds `count` simulations.
 template <typename SR>
 __global__ __launch_bounds__(WAVE) void k_window_fwd(Consts P, Tables tb, const float *__restrict__ seg_win, int n,
+                                                     int i0, int count,
                                                      const int32_t *__restrict__ env, const float *__restrict__ xi,
                                                      const float *__restrict__ warm0,
                                                      const float *__restrict__ obs_gt_win, float *__restrict__ cost_out,
@@ -92,8 +95,9 @@ __global__ __launch_bounds__(WAVE) void k_window_fwd(Consts P, Tables tb, const 
                                                      float *__restrict__ ckpt)
 {
     extern __shared__ __align__(16) char smem[];
-    const int i = blockIdx.x;
-    if (i >= n) return;
+    const int c = blockIdx.x;
+    if (c >= count) return;
+    const int i = i0 + c;
     const int lane = lane_id();
     const int e = env[i];
     if (e < 0 || e >= P.K) {
@@ -121,7 +125,7 @@ __global__ __launch_bounds__(WAVE) void k_window_fwd(Consts P, Tables tb, const 
     // cost summed in the order of the other paths
     float cost = 0.f;
     for (int t = 0; t < P.T; ++t) {
-        float *ck = ckpt ? ckpt + ((size_t)i * P.T + t) * CK : nullptr;
+        float *ck = ckpt ? ckpt + ((size_t)c * P.T + t) * CK : nullptr;
         if (ck) save_body(ck, B);
         const float *seg = seg_win + (size_t)t * P.L * SEG_STRIDE;
         StepState<SR> st;
@@ -159,14 +163,16 @@ __global__ __launch_bounds__(WAVE) void k_window_fwd(Consts P, Tables tb, const 
 // and xi; simulations with flag[i] == 0 are skipped (flag may be NULL)
 template <typename SR>
 __global__ __launch_bounds__(WAVE) void k_window_bwd(Consts P, Tables tb, const float *__restrict__ seg_win, int n,
+                                                     int i0, int count,
                                                      const int32_t *__restrict__ env, const float *__restrict__ xi,
                                                      const float *__restrict__ obs_gt_win,
                                                      const float *__restrict__ ckpt, const int32_t *__restrict__ flag,
                                                      float *__restrict__ grad)
 {
     extern __shared__ __align__(16) char smem[];
-    const int i = blockIdx.x;
-    if (i >= n) return;
+    const int c = blockIdx.x;
+    if (c >= count) return;
+    const int i = i0 + c;
     if (flag && flag[i] == 0) return;
     const int lane = lane_id();
     const int e = env[i];
@@ -192,7 +198,7 @@ __global__ __launch_bounds__(WAVE) void k_window_bwd(Consts P, Tables tb, const 
     for (int k = 0; k < 4; ++k) bar.q[k] = SR(0);
     SR mbar = 0, mubar = 0, fbar[3] = {0, 0, 0};
     for (int t = P.T - 1; t >= 0; --t) {
-        const float *ck = ckpt + ((size_t)i * P.T + t) * CK;
+        const float *ck = ckpt + ((size_t)c * P.T + t) * CK;
         Body B;
         load_body_ckpt(ck, B);
         B.m = m0;
@@ -335,33 +341,33 @@ using namespace pt;
 
 size_t ckpt_floats(const Consts &P, int n) { return (size_t)n * P.T * ckpt_step_floats(P.C_max); }
 
-hipError_t launch_window_fwd(const Consts &P, const Tables &tb, const float *seg_win, int n, const int32_t *env,
-                             const float *xi, const float *warm0, const float *obs_gt_win, float *cost,
-                             float *end_state, float *end_warm, float *ckpt, hipStream_t s)
+hipError_t launch_window_fwd(const Consts &P, const Tables &tb, const float *seg_win, int n, int i0, int count,
+                             const int32_t *env, const float *xi, const float *warm0, const float *obs_gt_win,
+                             float *cost, float *end_state, float *end_warm, float *ckpt, hipStream_t s)
 {
-    if (n <= 0) return hipSuccess;
+    if (count <= 0) return hipSuccess;
     size_t lds = wave_lds_bytes(P.max_cand);
     if (P.solve_fp64)
-        hipLaunchKernelGGL(k_window_fwd<double>, dim3(n), dim3(WAVE), lds, s, P, tb, seg_win, n, env, xi, warm0,
-                           obs_gt_win, cost, end_state, end_warm, ckpt);
+        hipLaunchKernelGGL(k_window_fwd<double>, dim3(count), dim3(WAVE), lds, s, P, tb, seg_win, n, i0, count, env,
+                           xi, warm0, obs_gt_win, cost, end_state, end_warm, ckpt);
     else
-        hipLaunchKernelGGL(k_window_fwd<float>, dim3(n), dim3(WAVE), lds, s, P, tb, seg_win, n, env, xi, warm0,
-                           obs_gt_win, cost, end_state, end_warm, ckpt);
+        hipLaunchKernelGGL(k_window_fwd<float>, dim3(count), dim3(WAVE), lds, s, P, tb, seg_win, n, i0, count, env,
+                           xi, warm0, obs_gt_win, cost, end_state, end_warm, ckpt);
     return hipGetLastError();
 }
 
-hipError_t launch_window_bwd(const Consts &P, const Tables &tb, const float *seg_win, int n, const int32_t *env,
-                             const float *xi, const float *obs_gt_win, const float *ckpt, const int32_t *flag,
-                             float *grad, hipStream_t s)
+hipError_t launch_window_bwd(const Consts &P, const Tables &tb, const float *seg_win, int n, int i0, int count,
+                             const int32_t *env, const float *xi, const float *obs_gt_win, const float *ckpt,
+                             const int32_t *flag, float *grad, hipStream_t s)
 {
-    if (n <= 0) return hipSuccess;
+    if (count <= 0) return hipSuccess;
     size_t lds = wave_lds_bytes(P.max_cand);
     if (P.solve_fp64)
-        hipLaunchKernelGGL(k_window_bwd<double>, dim3(n), dim3(WAVE), lds, s, P, tb, seg_win, n, env, xi, obs_gt_win,
-                           ckpt, flag, grad);
+        hipLaunchKernelGGL(k_window_bwd<double>, dim3(count), dim3(WAVE), lds, s, P, tb, seg_win, n, i0, count, env,
+                           xi, obs_gt_win, ckpt, flag, grad);
     else
-        hipLaunchKernelGGL(k_window_bwd<float>, dim3(n), dim3(WAVE), lds, s, P, tb, seg_win, n, env, xi, obs_gt_win,
-                           ckpt, flag, grad);
+        hipLaunchKernelGGL(k_window_bwd<float>, dim3(count), dim3(WAVE), lds, s, P, tb, seg_win, n, i0, count, env,
+                           xi, obs_gt_win, ckpt, flag, grad);
     return hipGetLastError();
 }
 

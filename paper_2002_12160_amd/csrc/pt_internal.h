@@ -64,12 +64,13 @@ hipError_t window_occupancy(int waves_per_block, int max_cand, bool fp64, int *b
 hipError_t set_lds_limits(size_t bytes);
 hipError_t set_grad_lds_limits(size_t bytes);
 size_t ckpt_floats(const pt::Consts &P, int n);
-hipError_t launch_window_fwd(const pt::Consts &P, const pt::Tables &tb, const float *seg_win, int n,
-                             const int32_t *env, const float *xi, const float *warm0, const float *obs_gt_win,
-                             float *cost, float *end_state, float *end_warm, float *ckpt, hipStream_t s);
-hipError_t launch_window_bwd(const pt::Consts &P, const pt::Tables &tb, const float *seg_win, int n,
-                             const int32_t *env, const float *xi, const float *obs_gt_win, const float *ckpt,
-                             const int32_t *flag, float *grad, hipStream_t s);
+hipError_t launch_window_fwd(const pt::Consts &P, const pt::Tables &tb, const float *seg_win, int n, int i0,
+                             int count, const int32_t *env, const float *xi, const float *warm0,
+                             const float *obs_gt_win, float *cost, float *end_state, float *end_warm, float *ckpt,
+                             hipStream_t s);
+hipError_t launch_window_bwd(const pt::Consts &P, const pt::Tables &tb, const float *seg_win, int n, int i0,
+                             int count, const int32_t *env, const float *xi, const float *obs_gt_win,
+                             const float *ckpt, const int32_t *flag, float *grad, hipStream_t s);
 hipError_t launch_select_elites(int G, float elite_frac, const int32_t *group_start, const float *cost_sum,
                                 int32_t *elite_env, hipStream_t s);
 hipError_t launch_refine_gather(int n, int K, int C_max, const int32_t *env, const float *state, const float *params,

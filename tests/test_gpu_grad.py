@@ -304,3 +304,25 @@ def test_refine_with_zero_scale_changes_nothing(pt):
         assert torch.equal(x.view(torch.int32), y.view(torch.int32))
     b.close()
     h.close()
+
+
+def test_window_grad_chunks_agree(pt):
+    # the checkpoint buffer holds the batch's elite count of simulations;
+    # longer lists run in chunks and give the same bits as one at a time
+    _say("pt_window_grad: chunked list vs single simulations, bitwise")
+    T = 10
+    sc, st0, pr0, gt, u_win = window_case("small", 8, 10, T)
+    b = pt.Batch.from_scene(sc, T=T)
+    assert b.elite_count() == 2
+    start, warm0, u_t, gt_t = _gpu_inputs(st0, pr0, gt, u_win, sc.cfg.C_max)
+    env = torch.arange(8, dtype=torch.int32, device="cuda")
+    c_all, g_all, e_all, w_all = b.window_grad(u_t, gt_t, env, start, warm0, want_end=True)
+    for j in range(8):
+        c1, g1, e1, w1 = b.window_grad(u_t, gt_t, env[j:j + 1].contiguous(), start[:, j:j + 1].contiguous(),
+                                       warm0[j:j + 1].contiguous(), want_end=True)
+        torch.cuda.synchronize()
+        assert torch.equal(c1.view(torch.int32), c_all[j:j + 1].view(torch.int32))
+        assert torch.equal(g1.view(torch.int32), g_all[:, j:j + 1].contiguous().view(torch.int32))
+        assert torch.equal(e1.view(torch.int32), e_all[:, j:j + 1].contiguous().view(torch.int32))
+        assert torch.equal(w1.view(torch.int32), w_all[j:j + 1].view(torch.int32))
+    b.close()
