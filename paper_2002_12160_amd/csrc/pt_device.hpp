@@ -294,14 +294,6 @@ __device__ __forceinline__ void fb_value(T mu, T kap, T del, const T *r, const T
     o.phi[2] = x2 + y2 - o.w2;
 }
 
-template <typename T>
-__device__ __forceinline__ T fb_merit(T mu, T kap, T del, const T *r, const T *u)
-{
-    FBOut<T> o;
-    fb_value(mu, kap, del, r, u, o);
-    return T(0.5) * (o.phi[0] * o.phi[0] + o.phi[1] * o.phi[1] + o.phi[2] * o.phi[2]);
-}
-
 // Jacobian blocks of Phi: dPhi/dr = Dx Sx =: JX, dPhi/du = Dy Sy =: JY with
 // Dx = I - Lw^-1 Lx, Dy = I - Lw^-1 Ly (row-major 3x3)
 template <typename T>

@@ -278,11 +278,13 @@ __device__ __forceinline__ void step_solve(const Consts &P, StepState<SR> &st, f
     nu[0] += st.vs[0]; nu[1] += st.vs[1]; nu[2] += st.vs[2];
     nu[3] += st.ws[0]; nu[4] += st.ws[1]; nu[5] += st.ws[2];
     if (st.C > 0) {
+        // relative velocity and FB value at the current impulses; after the
+        // first iteration they are those of the line search's accepted trial
+        SR u[3];
+        rel_velocity(st, nu, r, eps, u);
+        FBOut<SR> fo;
+        fb_value(mu, kap, del, r, u, fo);
         for (int it = 0; it < P.newton_iters; ++it) {
-            SR u[3];
-            rel_velocity(st, nu, r, eps, u);
-            FBOut<SR> fo;
-            fb_value(mu, kap, del, r, u, fo);
             SR JX[9], JY[9];
             fb_jacobian(mu, kap, u, fo, JX, JY);
             SR Pm[9], Pi[9], Q[9], g[3];
@@ -354,17 +356,32 @@ __device__ __forceinline__ void step_solve(const Consts &P, StepState<SR> &st, f
                 du[1] = dot3(F + 3, dq) + eps * dr[1];
                 du[2] = dot3(F + 6, dq) + eps * dr[2];
             }
-            // Armijo backtracking over alpha = 1, 1/2, 1/4, 1/8 (1/8 if none passes)
+            // Armijo backtracking over alpha = 1, 1/2, 1/4, 1/8 (1/8 if none
+            // passes); the last trial evaluated is the accepted one, and its
+            // impulses, relative velocity (u + alpha W dr) and FB value carry
+            // into the next iteration
             SR alpha = SR(0.125);
             SR a = SR(1);
+            SR rt[3], ut[3];
+            FBOut<SR> ft;
             for (int t = 0; t < 4; ++t, a *= SR(0.5)) {
-                SR rt[3] = {r[0] + a * dr[0], r[1] + a * dr[1], r[2] + a * dr[2]};
-                SR ut[3] = {u[0] + a * du[0], u[1] + a * du[1], u[2] + a * du[2]};
-                SR ptr = act ? fb_merit(mu, kap, del, rt, ut) : SR(0);
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    rt[i] = r[i] + a * dr[i];
+                    ut[i] = u[i] + a * du[i];
+                }
+                fb_value(mu, kap, del, rt, ut, ft);
+                SR ptr = act ? SR(0.5) * (ft.phi[0] * ft.phi[0] + ft.phi[1] * ft.phi[1] + ft.phi[2] * ft.phi[2])
+                             : SR(0);
                 ptr = wave_sum1(ptr, span);
                 if (ptr <= (SR(1) - SR(2) * SR(P.armijo_sigma) * a) * psi) { alpha = a; break; }
             }
-            r[0] += alpha * dr[0]; r[1] += alpha * dr[1]; r[2] += alpha * dr[2];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                r[i] = rt[i];
+                u[i] = ut[i];
+            }
+            fo = ft;
 #pragma unroll
             for (int i = 0; i < 6; ++i) nu[i] += alpha * dn[i];
         }
