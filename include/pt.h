@@ -112,7 +112,8 @@ typedef struct {
     const float *hand;             /* [L][20]                                    */
     const float *spheres;          /* [n_types][S_max][4] body-frame centre, radius */
     const int32_t *n_spheres;      /* [n_types], each 1..S_max                   */
-    const float *inv_inertia;      /* [n_types][3] principal 1/I per unit mass   */
+    const float *inv_inertia;      /* [n_types][3] principal 1/I per unit mass, >= 0
+                                      (0: the body does not turn about that axis) */
     const int32_t *env_type;       /* [K] in [0, n_types)                        */
     const int32_t *group_start;    /* [G+1], 0 = g0 < ... < gG = K               */
     /* simulation state: DEVICE pointers, caller-owned, bound for the batch's life */

@@ -325,7 +325,9 @@ __device__ void step_adjoint(const Consts &P, const float *__restrict__ seg, con
         }
         if (st.C > 0) lds_sum<SR, 42>(acc, st.C, red);
         SR z[6];
-        schur_solve(acc, im, Iinv, z);
+        BodyMass<SR> Mb;
+        body_mass<SR>(st.m, st.Iinv, inv_in, Mb);
+        schur_solve(acc, Mb, z);
 #pragma unroll
         for (int i = 0; i < 6; ++i) zeta[i] = st.C > 0 ? -z[i] : SR(0);
     }

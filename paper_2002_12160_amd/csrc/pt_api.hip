@@ -135,6 +135,12 @@ pt_status validate(const pt_batch_desc *d)
     for (int t = 0; t < d->n_types; ++t)
         if (d->n_spheres[t] < 1 || d->n_spheres[t] > d->S_max)
             return fail(PT_E_ARG, "n_spheres[%d] = %d must be in [1, S_max]", t, d->n_spheres[t]);
+    for (int t = 0; t < d->n_types; ++t)
+        for (int a = 0; a < 3; ++a) {
+            const float v = d->inv_inertia[3 * t + a];
+            if (!(v >= 0.f) || !std::isfinite(v))
+                return fail(PT_E_ARG, "inv_inertia[%d][%d] must be finite and >= 0", t, a);
+        }
     for (int i = 0; i < d->K; ++i)
         if (d->env_type[i] < 0 || d->env_type[i] >= d->n_types) return fail(PT_E_ARG, "env_type[%d] out of range", i);
     if (d->group_start[0] != 0 || d->group_start[d->G] != d->K)

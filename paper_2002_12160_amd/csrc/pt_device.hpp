@@ -365,10 +365,11 @@ __device__ __forceinline__ void inv3(const T *a, T *o)
 
 // 6x6 solve S z = b by 3x3 blocks S = [[A, B], [Cb, D]]:
 // z2 = (D - Cb A^-1 B)^-1 (b2 - Cb A^-1 b1), z1 = A^-1 (b1 - B z2), both 3x3
-// inverses by the adjugate.  A = I + (1/m) sum of the contacts' world blocks
-// (the translational part of I + M^-1 sum J^T Q J) and its Schur complement
-// (the rotational part) stay well away from singular, so no pivoting is done:
-// every lane runs the same straight-line code in registers.
+// inverses by the adjugate.  A = m I + the sum of the contacts' world blocks
+// (the translational part of M + sum J^T Q J; I + M^-1 sum J^T Q J in the
+// inverse-mass form) and its Schur complement (the rotational part) stay
+// well away from singular, so no pivoting is done: every lane runs the same
+// straight-line code in registers.
 template <typename T>
 __device__ __forceinline__ void solve6(const T (&S)[36], T (&b)[6])
 {
@@ -446,12 +447,12 @@ __device__ __forceinline__ void load16<float>(const float *p, float *v)
 }
 
 // Sum of v[0..N) over lanes [0, n) through LDS, for wide vectors where DPP
-// rounds would cost N instructions each: the lanes below n write their
-// values as rows, lane j < N adds column j over the rows (four interleaved
-// partial sums in a fixed order), the N sums go back to LDS and every lane reads
-// all of them -- the same bits in every lane.  Lanes >= n do not take part
-// (their values must be zero for the sum to mean the whole wave's).
-// buf: 16-byte aligned, max(n, 1) rows of RedStride<T> elements.
+// rounds would cost N instructions each: the lanes below n8 = n rounded up to
+// 8 write their values as rows (lanes n .. n8-1 must hold zeros), lane j < N
+// adds column j over the rows, eight at a time into four interleaved partial
+// sums in a fixed order, the N sums go back to LDS and every lane reads all
+// of them -- the same bits in every lane.  Lanes >= n8 do not take part.
+// buf: 16-byte aligned, n8 rows of RedStride<T> elements.
 template <typename T, int N>
 __device__ __forceinline__ void lds_sum(T (&v)[N], int n, T *buf)
 {
@@ -459,7 +460,8 @@ __device__ __forceinline__ void lds_sum(T (&v)[N], int n, T *buf)
     constexpr int PER = 16 / (int)sizeof(T);
     static_assert(N <= RS && N <= 64, "vector too long for the reduction buffer");
     const int lane = lane_id();
-    if (lane < n) {
+    const int n8 = (n + 7) & ~7;
+    if (lane < n8) {
         T *row = buf + lane * RS;
 #pragma unroll
         for (int j = 0; j + PER <= N; j += PER) store16<T>(row + j, v + j);
@@ -467,19 +469,15 @@ __device__ __forceinline__ void lds_sum(T (&v)[N], int n, T *buf)
         for (int j = N - N % PER; j < N; ++j) row[j] = v[j];
     }
     wave_sync();
-    // eight rows in flight per round (rows past n read row n-1 and add 0),
-    // four interleaved partial sums
     T s4[4] = {T(0), T(0), T(0), T(0)};
     if (lane < N) {
-        for (int r0 = 0; r0 < n; r0 += 8) {
+        const T *col = buf + lane;
+        for (int r0 = 0; r0 < n8; r0 += 8, col += 8 * RS) {
             T x[8];
 #pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                const int r = r0 + k < n ? r0 + k : n - 1;
-                x[k] = buf[r * RS + lane];
-            }
+            for (int k = 0; k < 8; ++k) x[k] = col[k * RS];
 #pragma unroll
-            for (int k = 0; k < 8; ++k) s4[k & 3] += r0 + k < n ? x[k] : T(0);
+            for (int k = 0; k < 8; ++k) s4[k & 3] += x[k];
         }
     }
     const T s = (s4[0] + s4[1]) + (s4[2] + s4[3]);
@@ -529,25 +527,62 @@ __device__ __forceinline__ void schur_contribution(const SR *Qw, const SR *gw, c
     acc[39] = tg[0]; acc[40] = tg[1]; acc[41] = tg[2];
 }
 
-// Solves (I + M^-1 A6) z = -M^-1 b6 for the summed acc (A6 = acc[0..35],
-// b6 = acc[36..41]); M^-1 = diag(im I, Iinv).  Result in z.
+// Mass matrix of one body for the 6x6 solve: M = diag(m I, Iw) when every
+// principal inertia is finite (Iw = Iinv^-1, inverted in SR so that the two
+// agree to SR rounding), else only M^-1 = diag(im I, Iinv) (a body that
+// cannot turn about some axis).
 template <typename SR>
-__device__ __forceinline__ void schur_solve(const SR *acc, SR im, const SR *Iinv, SR (&z)[6])
+struct BodyMass {
+    bool inertia_form;
+    SR m, im, Iw[9], Iinv[9];
+};
+
+template <typename SR>
+__device__ __forceinline__ void body_mass(float m, const float *Iinv, const float *inv_in, BodyMass<SR> &M)
+{
+    M.inertia_form = inv_in[0] > 0.f && inv_in[1] > 0.f && inv_in[2] > 0.f;
+    M.m = m;
+    M.im = SR(1) / SR(m);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) M.Iinv[i] = Iinv[i];
+    if (M.inertia_form) inv3(M.Iinv, M.Iw);
+}
+
+// Solves (I + M^-1 A6) z = -M^-1 b6 for the summed acc (A6 = acc[0..35],
+// b6 = acc[36..41]); with finite inertias as (M + A6) z = -b6, the same z
+// without forming M^-1 A6.  Result in z.
+template <typename SR>
+__device__ __forceinline__ void schur_solve(const SR *acc, const BodyMass<SR> &M, SR (&z)[6])
 {
     SR S6[36];
+    if (M.inertia_form) {
 #pragma unroll
-    for (int j = 0; j < 6; ++j) {
-        S6[j] = acc[j] * im + (j == 0 ? SR(1) : SR(0));
-        S6[6 + j] = acc[6 + j] * im + (j == 1 ? SR(1) : SR(0));
-        S6[12 + j] = acc[12 + j] * im + (j == 2 ? SR(1) : SR(0));
+        for (int i = 0; i < 36; ++i) S6[i] = acc[i];
+        S6[0] += M.m; S6[7] += M.m; S6[14] += M.m;
 #pragma unroll
         for (int i = 0; i < 3; ++i)
-            S6[6 * (3 + i) + j] = Iinv[3 * i] * acc[18 + j] + Iinv[3 * i + 1] * acc[24 + j] +
-                                  Iinv[3 * i + 2] * acc[30 + j] + (j == 3 + i ? SR(1) : SR(0));
-    }
-    z[0] = -acc[36] * im; z[1] = -acc[37] * im; z[2] = -acc[38] * im;
 #pragma unroll
-    for (int i = 0; i < 3; ++i) z[3 + i] = -(Iinv[3 * i] * acc[39] + Iinv[3 * i + 1] * acc[40] + Iinv[3 * i + 2] * acc[41]);
+            for (int j = 0; j < 3; ++j) S6[6 * (3 + i) + 3 + j] += M.Iw[3 * i + j];
+#pragma unroll
+        for (int i = 0; i < 6; ++i) z[i] = -acc[36 + i];
+    } else {
+        const SR im = M.im;
+        const SR *Iinv = M.Iinv;
+#pragma unroll
+        for (int j = 0; j < 6; ++j) {
+            S6[j] = acc[j] * im + (j == 0 ? SR(1) : SR(0));
+            S6[6 + j] = acc[6 + j] * im + (j == 1 ? SR(1) : SR(0));
+            S6[12 + j] = acc[12 + j] * im + (j == 2 ? SR(1) : SR(0));
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+                S6[6 * (3 + i) + j] = Iinv[3 * i] * acc[18 + j] + Iinv[3 * i + 1] * acc[24 + j] +
+                                      Iinv[3 * i + 2] * acc[30 + j] + (j == 3 + i ? SR(1) : SR(0));
+        }
+        z[0] = -acc[36] * im; z[1] = -acc[37] * im; z[2] = -acc[38] * im;
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+            z[3 + i] = -(Iinv[3 * i] * acc[39] + Iinv[3 * i + 1] * acc[40] + Iinv[3 * i + 2] * acc[41]);
+    }
     solve6(S6, z);
 }
 

@@ -261,13 +261,12 @@ __device__ __forceinline__ void step_setup(const Consts &P, const float *__restr
 // red: LDS for the cross-contact sum of the 6x6 system (the wave's candidate
 // list, free once the cap has run).
 template <typename SR>
-__device__ __forceinline__ void step_solve(const Consts &P, StepState<SR> &st, float mu_f, SR *red)
+__device__ __forceinline__ void step_solve(const Consts &P, StepState<SR> &st, float mu_f, const float *inv_in,
+                                           SR *red)
 {
     const SR eps = P.compliance, kap = P.kappa, del = P.fb_delta, mu = mu_f;
-    const SR imS = SR(1) / SR(st.m);
-    SR IinvS[9];
-#pragma unroll
-    for (int i = 0; i < 9; ++i) IinvS[i] = st.Iinv[i];
+    BodyMass<SR> Mb;
+    body_mass<SR>(st.m, st.Iinv, inv_in, Mb);
     const bool act = st.act;
     const int span = st.span;
     SR *r = st.r;
@@ -323,7 +322,7 @@ __device__ __forceinline__ void step_solve(const Consts &P, StepState<SR> &st, f
             lds_sum<SR, 43>(acc, st.C, red);
             const SR psi = acc[42];
             SR rhs[6];
-            schur_solve(acc, imS, IinvS, rhs);
+            schur_solve(acc, Mb, rhs);
             // dr = -g - Q F (dv + dw x rho)
             SR dp[3];
             SR dw3[3] = {rhs[3], rhs[4], rhs[5]};
@@ -461,7 +460,7 @@ __device__ __forceinline__ void env_step(const Consts &P, const float *__restric
 {
     StepState<SR> st;
     step_setup<SR>(P, seg, sph, S, inv_in, B, wkey, wr, lds, stats, st);
-    step_solve<SR>(P, st, B.mu, reinterpret_cast<SR *>(lds.cand_d));
+    step_solve<SR>(P, st, B.mu, inv_in, reinterpret_cast<SR *>(lds.cand_d));
     step_finish<SR>(P, st, inv_in, B, wkey, wr, out_link, out_imp);
 }
 
