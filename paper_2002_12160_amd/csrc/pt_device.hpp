@@ -248,10 +248,13 @@ __device__ __forceinline__ void tangent_frame(const float *n, float *t1, float *
 // smoothed Fischer-Burmeister function of one contact on the Lorentz cone
 // ---------------------------------------------------------------------
 // x = kappa (mu r_n, r_t), y = (u_n + mu sqrt(|u_t|^2 + delta^2), mu u_t),
-// w = sqrt(x o x + y o y + 2 delta^2 e), Phi = x + y - w.  The small
-// spectral value lambda1 of z = x o x + y o y + 2 delta^2 e is obtained as
-// det(z) / lambda2 with det(z) written as a sum of squares, which keeps it
-// accurate in float32 when x and y sit on the cone boundary (sliding).
+// w = sqrt(x o x + y o y + 2 delta^2 e), Phi = x + y - w.  With the spectral
+// values l1,2 = z0 -/+ |zb| of z = x o x + y o y + 2 delta^2 e,
+// w0 = (sqrt l1 + sqrt l2) / 2 and wb = zb / (sqrt l1 + sqrt l2), where
+// sqrt l1 + sqrt l2 = sqrt(2 z0 + 2 sqrt(det z)) and det z = l1 l2 is written
+// as a sum of squares: no difference of nearly equal terms, so the small
+// spectral value stays accurate when x and y sit on the cone boundary
+// (sliding), and |zb| itself is never needed.
 template <typename T>
 struct FBOut {
     T phi[3];
@@ -270,8 +273,6 @@ __device__ __forceinline__ void fb_value(T mu, T kap, T del, const T *r, const T
     T d2 = del * del;
     T z0 = A + B + T(2) * d2;
     T zb1 = T(2) * (x0 * x1 + y0 * y1), zb2 = T(2) * (x0 * x2 + y0 * y2);
-    T nz = sqrt(zb1 * zb1 + zb2 * zb2);
-    T l2 = z0 + nz;
     T dx = x0 * x0 - (x1 * x1 + x2 * x2);
     T dy = y0 * y0 - (y1 * y1 + y2 * y2);
     T c1 = x0 * y1 - y0 * x1, c2 = x0 * y2 - y0 * x2;
@@ -279,13 +280,13 @@ __device__ __forceinline__ void fb_value(T mu, T kap, T del, const T *r, const T
     T cr = x1 * y2 - x2 * y1;
     T detz = dx * dx + dy * dy + T(2) * (c1 * c1 + c2 * c2) + T(2) * e * e + T(2) * cr * cr +
                  T(4) * d2 * (A + B) + T(4) * d2 * d2;
-    T l1 = detz / l2;
-    T s1 = sqrt(l1), s2 = sqrt(l2);
-    T inv = T(1) / (s1 + s2);
-    o.w0 = T(0.5) * (s1 + s2);
+    T sd = sqrt(detz);                       // sqrt(l1) sqrt(l2)
+    T sum = sqrt(T(2) * (z0 + sd));          // sqrt(l1) + sqrt(l2)
+    T inv = T(1) / sum;
+    o.w0 = T(0.5) * sum;
     o.w1 = zb1 * inv;
     o.w2 = zb2 * inv;
-    o.s = s1 * s2;
+    o.s = sd;
     o.st = st;
     o.x[0] = x0; o.x[1] = x1; o.x[2] = x2;
     o.y[0] = y0; o.y[1] = y1; o.y[2] = y2;
