@@ -43,6 +43,8 @@ def parse():
     ap.add_argument("--solve-precision", type=int, default=64, choices=[32, 64])
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the batched + elite-refinement legs")
+    ap.add_argument("--realtime-windows", type=int, default=30,
+                    help="timed windows of the 16384-simulation real-time workload (0 skips it)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-steps", type=int, default=300)
     ap.add_argument("--profile", action="store_true", help="short run for the profiler (no CPU baseline)")
@@ -84,21 +86,26 @@ def algorithmic_bytes(C_max):
     return 52 + 20 + 52 + 12 + 3 * 16 * C_max
 
 
-def observed_forces(pt, sc, dev, solve_precision, n_steps):
+def observed_forces(pt, sc, dev, solve_precision, n_steps, pose_every=None):
     """The observed ("real") simulation's sensor forces for steps
     0..n_steps-1, [n_steps][4][L][G].  They are the tracker's input stream
     (the robot's contact sensors), so they are produced before any timed
-    region and stay resident in HBM."""
+    region and stay resident in HBM.  With pose_every = T also the observed
+    object's state after every T steps ([n_steps / T][13][G], for the
+    tracking error)."""
     import torch
     u_all = torch.as_tensor(sc.u.astype("float32"), device=dev)
     h = pt.Batch.from_scene(sc, hidden=True, solve_precision=solve_precision)
     out = torch.empty((n_steps, 4, sc.L, sc.G), device=dev)
+    poses = []
     for t in range(n_steps):
         h.step(u_all[max(t - 1, 0)], u_all[t])
         h.observe(out[t])
+        if pose_every and (t + 1) % pose_every == 0:
+            poses.append(h.state.clone())
     torch.cuda.synchronize()
     h.close()
-    return out
+    return (out, torch.stack(poses)) if pose_every else out
 
 
 def batched_run(pt, S, sc, dev, solve_precision, n_win, n_warm, adjoint):
@@ -163,6 +170,94 @@ def batched_run(pt, S, sc, dev, solve_precision, n_win, n_warm, adjoint):
                     "elites_improved_frac": round(improved[0] / max(improved[1], 1), 3)})
     main_b.close()
     return out
+
+
+def add_distance(points, pa, pb):
+    """Mean distance between the object's points placed at poses pa and pb
+    (x(3), q(4)): the tracking error of a pose estimate."""
+    import numpy as np
+
+    def rot(q):
+        w, x, y, z = q / np.linalg.norm(q)
+        return np.array([[1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)],
+                         [2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)],
+                         [2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)]])
+    a = points @ rot(pa[3:7]).T + pa[:3]
+    b = points @ rot(pb[3:7]).T + pb[:3]
+    return float(np.linalg.norm(a - b, axis=1).mean())
+
+
+def realtime_run(pt, S, dev, solve_precision, n_win, n_warm=2):
+    """The real-time workload: 16384 simulations in 16 groups (one
+    superquadric object each), batched windows with elite refinement before
+    every resampling.  Reports env-steps/s, the per-step latency (window time
+    / T) against the 33 ms budget of 30 Hz, and the tracking error: the mean
+    distance between the object's points at the best simulation's pose and
+    at the observed object's pose, after every window, over all groups."""
+    import numpy as np
+    import torch
+    cfg = S.CONFIGS["realtime16384"]
+    T = cfg.T
+    n_total = n_warm + n_win
+    sc = S.make_scene(cfg, steps=(n_total + 1) * T + 1)
+    K, G, L = sc.K, sc.G, sc.L
+    gts, hposes = observed_forces(pt, sc, dev, solve_precision, n_total * T, pose_every=T)
+    u_all = torch.as_tensor(sc.u.astype("float32"), device=dev)
+    b = pt.Batch.from_scene(sc, solve_precision=solve_precision)
+    u_win = torch.empty((T + 1, sc.D), device=dev)
+    gt_win = torch.empty((T, 4, L, G), device=dev)
+    cost = torch.zeros(K, device=dev)
+    best = torch.zeros(G, dtype=torch.int32, device=dev)
+    parent = torch.zeros(K, dtype=torch.int32, device=dev)
+    snap = b.snapshot()
+    est = torch.empty((n_total, 13, G), device=dev)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n_total)]
+
+    def window(w):
+        t0_ = w * T
+        ev[w][0].record()
+        u_win.copy_(u_all[t0_ - 1: t0_ + T] if t0_ > 0 else torch.cat([u_all[:1], u_all[:T]], 0))
+        gt_win.copy_(gts[t0_: t0_ + T])
+        snap[0].copy_(b.state)
+        snap[1].copy_(b.params)
+        snap[2].copy_(b.warm)
+        b.run_window(u_win, gt_win, cost, best, None, graph=True)
+        b.refine_elites(u_win, gt_win, cost, snap, steps=3, step=0.5, best=best)
+        torch.index_select(b.state, 1, best, out=est[w])
+        b.resample(cost, w, parent)
+        ev[w][1].record()
+
+    u_win.copy_(torch.cat([u_all[:1], u_all[:T]], 0))
+    gt_win.copy_(gts[:T])
+    tuned = b.autotune(u_win, gt_win)
+    torch.cuda.synchronize()
+    for w in range(n_warm):
+        window(w)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for w in range(n_warm, n_total):
+        window(w)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    step_ms = np.array([ev[w][0].elapsed_time(ev[w][1]) / T for w in range(n_warm, n_total)])
+    est_h, hp = est.cpu().numpy(), hposes.cpu().numpy()
+    errs = []
+    for w in range(n_warm, n_total):
+        for g in range(G):
+            pts = sc.spheres[sc.hidden_type[g], :sc.n_spheres[sc.hidden_type[g]], :3]
+            errs.append(add_distance(pts, est_h[w, :7, g], hp[w, :7, g]))
+    b.close()
+    return {"workload": f"{cfg.name}: {K} simulations in {G} groups (one {int(sc.n_spheres[0])}-sphere superquadric "
+                        f"object each) + {G} observed, {L} capsule links, C_max={cfg.C_max}, "
+                        f"{cfg.newton_iters} Newton iterations, {T}-step windows, elite refinement (3 steps) and "
+                        f"resampling after every window, {n_win} timed windows",
+            "value": round(K * T * n_win / wall, 1), "unit": "env-steps/s",
+            "per_step_ms": {"p50": round(float(np.median(step_ms)), 3),
+                            "p99": round(float(np.quantile(step_ms, 0.99)), 3)},
+            "budget_30hz_met": bool(np.quantile(step_ms, 0.99) < 1000.0 / 30.0),
+            "tracking_error_mm": {"mean": round(1e3 * float(np.mean(errs)), 3),
+                                  "p90": round(1e3 * float(np.quantile(errs, 0.9)), 3)},
+            "waves_per_workgroup": tuned}
 
 
 def main():
@@ -301,6 +396,11 @@ def main():
                             f"{acfg.newton_iters} Newton iterations, {acfg.T}-step windows",
                 "batched": a_b, "batched_adjoint": a_a,
                 "adjoint_cost_ratio": round(a_b["value"] / a_a["value"], 3)}
+
+    # ---------------- real-time workload (16384 simulations) -------------
+    if not args.no_batched and not args.no_adjoint and args.realtime_windows > 0:
+        result["realtime16384"] = realtime_run(pt, S, dev, args.solve_precision,
+                                               args.realtime_windows if not args.profile else 3)
 
     # ---------------- CPU baseline: the FP64 oracle ----------------------
     if not args.no_cpu_baseline and not args.profile:
