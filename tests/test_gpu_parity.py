@@ -171,6 +171,18 @@ def test_per_step_parity_plain256_sampled(pt):
     assert len(fails) <= 0.01 * n_ok, fails[:20]
 
 
+@pytest.mark.parametrize("cfg_name,K", [("batched4096", 96), ("adjoint1024", 64), ("realtime16384", 64)])
+def test_per_step_parity_other_workloads(pt, cfg_name, K):
+    # the other scenes at reduced K: mixed object types, 64-contact caps (a
+    # full wave of contact lanes), the 9-link hand and the 20-link hand with
+    # superquadric objects in 16 groups
+    _say(f"per-step parity: {cfg_name} config, K={K}, 30 steps")
+    n_chk, n_ok, fails = per_step_parity(pt, cfg_name, K, 30)
+    _say(f"checked {n_chk} env-steps, {n_ok} non-chaotic, {len(fails)} outside tolerance: {fails[:10]}")
+    assert n_ok >= 0.4 * n_chk
+    assert len(fails) <= 0.01 * n_ok, fails[:20]
+
+
 def test_free_fall_and_resting_on_gpu(pt):
     # closed forms on the GPU: free fall is exact to float32 rounding; a
     # sphere resting on the table carries m g (r_n = m g dt)
