@@ -57,7 +57,7 @@ def parse():
 # HBM bytes per k_step launch of the 256-simulation workload (float64 solve),
 # from FETCH_SIZE / WRITE_SIZE counters scaled by a plain device copy of known
 # size (profiles/k_step_plain256.txt); None for any other configuration
-MEASURED_TRAFFIC = {("plain256", 64): 852957}
+MEASURED_TRAFFIC = {("plain256", 64): 839651}
 
 
 # algorithmic floating-point operations (an FMA counts 2; a square root,
