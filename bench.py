@@ -120,7 +120,7 @@ def batched_run(pt, S, sc, dev, solve_precision, n_win, n_warm, adjoint):
     n_total = n_warm + n_win + (1 if adjoint else 0)
     gts = observed_forces(pt, sc, dev, solve_precision, n_total * T)
     u_all = torch.as_tensor(sc.u.astype("float32"), device=dev)
-    main_b = pt.Batch.from_scene(sc, solve_precision=solve_precision)
+    main_b = pt.Batch.from_scene(sc, solve_precision=solve_precision, window_checkpoints=adjoint)
     u_win = torch.empty((T + 1, sc.D), device=dev)
     gt_win = torch.empty((T, 4, L, G), device=dev)
     cost = torch.zeros(K, device=dev)
@@ -203,7 +203,7 @@ def realtime_run(pt, S, dev, solve_precision, n_win, n_warm=2):
     K, G, L = sc.K, sc.G, sc.L
     gts, hposes = observed_forces(pt, sc, dev, solve_precision, n_total * T, pose_every=T)
     u_all = torch.as_tensor(sc.u.astype("float32"), device=dev)
-    b = pt.Batch.from_scene(sc, solve_precision=solve_precision)
+    b = pt.Batch.from_scene(sc, solve_precision=solve_precision, window_checkpoints=True)
     u_win = torch.empty((T + 1, sc.D), device=dev)
     gt_win = torch.empty((T, 4, L, G), device=dev)
     cost = torch.zeros(K, device=dev)

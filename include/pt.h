@@ -120,6 +120,12 @@ typedef struct {
     float *state;                  /* [13][K]                                    */
     float *params;                 /* [5][K]                                     */
     float *warm;                   /* [K][C_max][4]                              */
+    /* nonzero: pt_run_window records a checkpoint of every simulation before
+       every step (body, kept contacts' keys and float64 impulses; K * T *
+       (64 + 32 C_max) bytes, allocated by pt_create_batch), from which
+       pt_refine_elites takes the elites' first gradient instead of replaying
+       their window */
+    int32_t window_checkpoints;
 } pt_batch_desc;
 
 /* Creates a batch: validates the descriptor (PT_E_ARG / PT_E_UNSUPPORTED),

@@ -69,6 +69,7 @@ struct pt_batch_s {
     float *d_tune = nullptr;     // autotuner's copies of state, params, warm cache and costs
     // gradient checkpoints (for n_elite simulations at a time) and refinement buffers
     float *d_ckpt = nullptr;
+    float *d_wckpt = nullptr;    // per-step checkpoints of every simulation's window (window_checkpoints)
     int n_elite = 0;
     int32_t *d_elite = nullptr;  // [n_elite]
     float *d_ref = nullptr;      // see refine_layout
@@ -284,6 +285,7 @@ pt_status pt_create_batch(const pt_batch_desc *d, pt_batch *out)
     HIP_TRY_C(hipMalloc(&b->d_ckpt, sizeof(float) * ckpt_floats(P, b->n_elite)));
     HIP_TRY_C(hipMalloc(&b->d_ref, sizeof(float) * refine_floats(P, b->n_elite)));
     HIP_TRY_C(hipMalloc(&b->d_elite, sizeof(int32_t) * b->n_elite));
+    if (d->window_checkpoints) HIP_TRY_C(hipMalloc(&b->d_wckpt, sizeof(float) * ckpt_floats(P, (int)K)));
     HIP_TRY_C(hipMemcpy(b->d_hand, d->hand, sizeof(float) * d->L * PT_HAND_STRIDE, hipMemcpyHostToDevice));
     HIP_TRY_C(hipMemcpy(b->d_spheres, d->spheres, sizeof(float) * d->n_types * d->S_max * 4, hipMemcpyHostToDevice));
     HIP_TRY_C(hipMemcpy(b->d_inv, d->inv_inertia, sizeof(float) * d->n_types * 3, hipMemcpyHostToDevice));
@@ -313,7 +315,7 @@ pt_status pt_destroy_batch(pt_batch b)
     if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
     void *ptrs[] = {b->d_hand, b->d_spheres, b->d_inv, b->d_nsph, b->d_type, b->d_group_of, b->d_group_start,
                     b->d_order, b->d_queue, b->d_stats, b->d_seg, b->d_seg_win, b->d_contacts,
-                    b->d_seg_grad, b->d_tune, b->d_ckpt, b->d_elite, b->d_ref};
+                    b->d_seg_grad, b->d_tune, b->d_ckpt, b->d_wckpt, b->d_elite, b->d_ref};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete b;
@@ -373,7 +375,7 @@ pt_status pt_resample(pt_batch b, float *cost_sum, uint32_t window_idx, int32_t 
 // the launches of one window, in stream order
 static pt_status enqueue_window(pt_batch b, const float *u_win, const float *obs_gt_win, float *cost_sum,
                                 int32_t *best, float *obs_out, int wpb, float *state, float *params, float *warm,
-                                hipStream_t st)
+                                float *ckpt, hipStream_t st)
 {
     const Consts &P = b->P;
     int bpc = 0;
@@ -384,7 +386,7 @@ static pt_status enqueue_window(pt_batch b, const float *u_win, const float *obs
     HIP_TRY(launch_hand_fk(b->d_hand, P.L, P.dt, u_win, u_win + P.D, P.D, P.T, b->d_seg_win, st));
     HIP_TRY(launch_reset_queue(b->d_queue, st));
     HIP_TRY(launch_window(P, tables_of(b), b->d_seg_win, state, params, warm, obs_gt_win, cost_sum, obs_out,
-                          b->d_order, b->d_queue, b->d_stats, wpb, blocks, st));
+                          b->d_order, b->d_queue, b->d_stats, wpb, blocks, ckpt, st));
     if (best) HIP_TRY(launch_argmin(P.G, b->d_group_start, cost_sum, best, st));
     return PT_OK;
 }
@@ -396,7 +398,8 @@ pt_status pt_run_window(pt_batch b, const float *u_win, const float *obs_gt_win,
     if (!u_win || !obs_gt_win || !cost_sum) return fail(PT_E_ARG, "u_win/obs_gt_win/cost_sum is NULL");
     hipStream_t st = (hipStream_t)s;
     if (!graph)
-        return enqueue_window(b, u_win, obs_gt_win, cost_sum, best, obs_out, b->wpb, b->state, b->params, b->warm, st);
+        return enqueue_window(b, u_win, obs_gt_win, cost_sum, best, obs_out, b->wpb, b->state, b->params, b->warm,
+                              b->d_wckpt, st);
     GraphKey key{{u_win, obs_gt_win, cost_sum, best, obs_out}, b->wpb};
     int slot = -1;
     for (int i = 0; i < pt_batch_s::N_GRAPHS; ++i)
@@ -420,7 +423,7 @@ pt_status pt_run_window(pt_batch b, const float *u_win, const float *obs_gt_win,
         hipGraph_t g = nullptr;
         HIP_TRY(hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal));
         pt_status cs = enqueue_window(b, u_win, obs_gt_win, cost_sum, best, obs_out, b->wpb, b->state, b->params,
-                                      b->warm, b->capture_stream);
+                                      b->warm, b->d_wckpt, b->capture_stream);
         hipError_t ec = hipStreamEndCapture(b->capture_stream, &g);
         if (cs != PT_OK) {
             if (g) (void)hipGraphDestroy(g);
@@ -470,7 +473,7 @@ pt_status pt_autotune(pt_batch b, const float *u_win, const float *obs_gt_win, i
                 break;
             }
             (void)hipEventRecord(e0, st);
-            rc = enqueue_window(b, u_win, obs_gt_win, tc, nullptr, nullptr, wpb, ts, tp, tw, st);
+            rc = enqueue_window(b, u_win, obs_gt_win, tc, nullptr, nullptr, wpb, ts, tp, tw, nullptr, st);
             (void)hipEventRecord(e1, st);
             if (rc != PT_OK) break;
             if (hipEventSynchronize(e1) != hipSuccess) {
@@ -532,8 +535,8 @@ pt_status pt_window_grad(pt_batch b, const float *u_win, const float *obs_gt_win
         const int cnt = std::min(b->n_elite, n - i0);
         HIP_TRY(launch_window_fwd(P, tb, b->d_seg_grad, n, i0, cnt, env, start, warm0, obs_gt_win, cost, end_state,
                                   end_warm, b->d_ckpt, st));
-        HIP_TRY(launch_window_bwd(P, tb, b->d_seg_grad, n, i0, cnt, env, start, obs_gt_win, b->d_ckpt, nullptr, grad,
-                                  st));
+        HIP_TRY(launch_window_bwd(P, tb, b->d_seg_grad, n, i0, cnt, env, start, obs_gt_win, b->d_ckpt, false, nullptr,
+                                  grad, st));
     }
     return PT_OK;
 }
@@ -566,12 +569,16 @@ pt_status pt_refine_elites(pt_batch b, const float *u_win, const float *obs_gt_w
         HIP_TRY(hipMemcpyAsync(elite_out, b->d_elite, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, st));
     if (steps > 0) {
         HIP_TRY(launch_hand_fk(b->d_hand, P.L, P.dt, u_win, u_win + P.D, P.D, P.T, b->d_seg_grad, st));
-        HIP_TRY(launch_refine_gather(n, P.K, P.C_max, b->d_elite, start_state, start_params, start_warm, r.xi,
-                                     r.warm0, r.rho, step, st));
-        HIP_TRY(launch_window_fwd(P, tb, b->d_seg_grad, n, 0, n, b->d_elite, r.xi, r.warm0, obs_gt_win, r.cost,
-                                  nullptr, nullptr, b->d_ckpt, st));
-        HIP_TRY(launch_window_bwd(P, tb, b->d_seg_grad, n, 0, n, b->d_elite, r.xi, obs_gt_win, b->d_ckpt, nullptr,
-                                  r.g, st));
+        // the first gradient: from the checkpoints the population's window
+        // recorded (window_checkpoints) or from a replay of the window
+        const bool from_window = b->d_wckpt != nullptr;
+        HIP_TRY(launch_refine_gather(n, P.K, P.C_max, b->d_elite, start_state, start_params, start_warm,
+                                     from_window ? cost_sum : nullptr, r.xi, r.warm0, r.cost, r.rho, step, st));
+        if (!from_window)
+            HIP_TRY(launch_window_fwd(P, tb, b->d_seg_grad, n, 0, n, b->d_elite, r.xi, r.warm0, obs_gt_win, r.cost,
+                                      nullptr, nullptr, b->d_ckpt, st));
+        HIP_TRY(launch_window_bwd(P, tb, b->d_seg_grad, n, 0, n, b->d_elite, r.xi, obs_gt_win,
+                                  from_window ? b->d_wckpt : b->d_ckpt, from_window, nullptr, r.g, st));
         for (int it = 0; it < steps; ++it) {
             // trial, its replay (checkpointed unless it is the last), keep or
             // halve, then the gradient at the kept trials only
@@ -584,7 +591,7 @@ pt_status pt_refine_elites(pt_batch b, const float *u_win, const float *obs_gt_w
                                          st));
             if (!last)
                 HIP_TRY(launch_window_bwd(P, tb, b->d_seg_grad, n, 0, n, b->d_elite, r.xi, obs_gt_win, b->d_ckpt,
-                                          r.flag, r.g, st));
+                                          false, r.flag, r.g, st));
         }
     }
     if (best) HIP_TRY(launch_argmin(P.G, b->d_group_start, cost_sum, best, st));

@@ -22,55 +22,6 @@
 
 namespace pt {
 
-// checkpoint of one step of one simulation: body record x(3) q(4) v(3) w(3)
-// f(3) (16 floats), then per contact slot r(3) and key as 4 doubles
-constexpr int CK_BODY = 16;
-__host__ __device__ constexpr size_t ckpt_step_floats(int C_max) { return CK_BODY + 8 * (size_t)C_max; }
-
-__device__ __forceinline__ void save_body(float *__restrict__ ck, const Body &B)
-{
-    if (lane_id() == 0) {
-        float4 *b4 = reinterpret_cast<float4 *>(ck);
-        b4[0] = make_float4(B.x[0], B.x[1], B.x[2], B.q[0]);
-        b4[1] = make_float4(B.q[1], B.q[2], B.q[3], B.v[0]);
-        b4[2] = make_float4(B.v[1], B.v[2], B.w[0], B.w[1]);
-        b4[3] = make_float4(B.w[2], B.f[0], B.f[1], B.f[2]);
-    }
-}
-
-__device__ __forceinline__ void load_body_ckpt(const float *__restrict__ ck, Body &B)
-{
-    const float4 *b4 = reinterpret_cast<const float4 *>(ck);
-    float4 a = b4[0], b = b4[1], c = b4[2], d = b4[3];
-    B.x[0] = a.x; B.x[1] = a.y; B.x[2] = a.z; B.q[0] = a.w;
-    B.q[1] = b.x; B.q[2] = b.y; B.q[3] = b.z; B.v[0] = b.w;
-    B.v[1] = c.x; B.v[2] = c.y; B.w[0] = c.z; B.w[1] = c.w;
-    B.w[2] = d.x; B.f[0] = d.y; B.f[1] = d.z; B.f[2] = d.w;
-}
-
-template <typename SR>
-__device__ __forceinline__ void save_contact(float *__restrict__ ck, int C_max, const StepState<SR> &st)
-{
-    const int lane = lane_id();
-    if (lane < C_max) {
-        double2 *d2 = reinterpret_cast<double2 *>(ck + CK_BODY) + 2 * lane;
-        d2[0] = make_double2((double)st.r[0], (double)st.r[1]);
-        d2[1] = make_double2((double)st.r[2], (double)(st.act ? st.key : -1));
-    }
-}
-
-template <typename SR>
-__device__ __forceinline__ int load_contact(const float *__restrict__ ck, int C_max, SR *r)
-{
-    const int lane = lane_id();
-    r[0] = r[1] = r[2] = SR(0);
-    if (lane >= C_max) return -1;
-    const double2 *d2 = reinterpret_cast<const double2 *>(ck + CK_BODY) + 2 * lane;
-    double2 a = d2[0], b = d2[1];
-    r[0] = (SR)a.x; r[1] = (SR)a.y; r[2] = (SR)b.x;
-    return (int)b.y;
-}
-
 __device__ __forceinline__ void load_start(const float *__restrict__ xi, int n, int i, Body &B)
 {
     B.x[0] = xi[0 * (size_t)n + i]; B.x[1] = xi[1 * (size_t)n + i]; B.x[2] = xi[2 * (size_t)n + i];
@@ -160,14 +111,16 @@ __global__ __launch_bounds__(WAVE) void k_window_fwd(Consts P, Tables tb, const 
 }
 
 // reverse sweep over the checkpoints k_window_fwd wrote for the same n, env
-// and xi; simulations with flag[i] == 0 are skipped (flag may be NULL)
+// and xi (ckpt_by_env = 0: slot c of the launch), or that the population's
+// window wrote (ckpt_by_env = 1: slot env[i]); simulations with flag[i] == 0
+// are skipped (flag may be NULL)
 template <typename SR>
 __global__ __launch_bounds__(WAVE) void k_window_bwd(Consts P, Tables tb, const float *__restrict__ seg_win, int n,
                                                      int i0, int count,
                                                      const int32_t *__restrict__ env, const float *__restrict__ xi,
                                                      const float *__restrict__ obs_gt_win,
-                                                     const float *__restrict__ ckpt, const int32_t *__restrict__ flag,
-                                                     float *__restrict__ grad)
+                                                     const float *__restrict__ ckpt, int ckpt_by_env,
+                                                     const int32_t *__restrict__ flag, float *__restrict__ grad)
 {
     extern __shared__ __align__(16) char smem[];
     const int c = blockIdx.x;
@@ -198,7 +151,7 @@ __global__ __launch_bounds__(WAVE) void k_window_bwd(Consts P, Tables tb, const 
     for (int k = 0; k < 4; ++k) bar.q[k] = SR(0);
     SR mbar = 0, mubar = 0, fbar[3] = {0, 0, 0};
     for (int t = P.T - 1; t >= 0; --t) {
-        const float *ck = ckpt + ((size_t)c * P.T + t) * CK;
+        const float *ck = ckpt + ((size_t)(ckpt_by_env ? e : c) * P.T + t) * CK;
         Body B;
         load_body_ckpt(ck, B);
         B.m = m0;
@@ -254,10 +207,12 @@ __global__ __launch_bounds__(1024) void k_select_elites(int G, float elite_frac,
     }
 }
 
-// start of each listed simulation from the window-start snapshot
+// start of each listed simulation from the window-start snapshot (and, if
+// cost_sum is given, its window cost)
 __global__ void k_refine_gather(int n, int K, int C_max, const int32_t *__restrict__ env,
                                 const float *__restrict__ state, const float *__restrict__ params,
-                                const float *__restrict__ warm, float *__restrict__ xi, float *__restrict__ warm0,
+                                const float *__restrict__ warm, const float *__restrict__ cost_sum,
+                                float *__restrict__ xi, float *__restrict__ warm0, float *__restrict__ cost,
                                 float *__restrict__ rho, float rho0)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -270,6 +225,7 @@ __global__ void k_refine_gather(int n, int K, int C_max, const int32_t *__restri
     float4 *dst = reinterpret_cast<float4 *>(warm0 + (size_t)i * C_max * WARM_STRIDE);
     for (int c = 0; c < C_max; ++c) dst[c] = src[c];
     rho[i] = rho0;
+    if (cost_sum) cost[i] = cost_sum[e];
 }
 
 // trial start: xi - rho (s o s o g) / |s o g| over (x, q, v, w, m, mu), then
@@ -358,16 +314,17 @@ hipError_t launch_window_fwd(const Consts &P, const Tables &tb, const float *seg
 
 hipError_t launch_window_bwd(const Consts &P, const Tables &tb, const float *seg_win, int n, int i0, int count,
                              const int32_t *env, const float *xi, const float *obs_gt_win, const float *ckpt,
-                             const int32_t *flag, float *grad, hipStream_t s)
+                             bool ckpt_by_env, const int32_t *flag, float *grad, hipStream_t s)
 {
     if (count <= 0) return hipSuccess;
     size_t lds = wave_lds_bytes(P.max_cand);
+    const int by_env = ckpt_by_env ? 1 : 0;
     if (P.solve_fp64)
         hipLaunchKernelGGL(k_window_bwd<double>, dim3(count), dim3(WAVE), lds, s, P, tb, seg_win, n, i0, count, env,
-                           xi, obs_gt_win, ckpt, flag, grad);
+                           xi, obs_gt_win, ckpt, by_env, flag, grad);
     else
         hipLaunchKernelGGL(k_window_bwd<float>, dim3(count), dim3(WAVE), lds, s, P, tb, seg_win, n, i0, count, env,
-                           xi, obs_gt_win, ckpt, flag, grad);
+                           xi, obs_gt_win, ckpt, by_env, flag, grad);
     return hipGetLastError();
 }
 
@@ -379,11 +336,12 @@ hipError_t launch_select_elites(int G, float elite_frac, const int32_t *group_st
 }
 
 hipError_t launch_refine_gather(int n, int K, int C_max, const int32_t *env, const float *state, const float *params,
-                                const float *warm, float *xi, float *warm0, float *rho, float rho0, hipStream_t s)
+                                const float *warm, const float *cost_sum, float *xi, float *warm0, float *cost,
+                                float *rho, float rho0, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_refine_gather, dim3((n + 63) / 64), dim3(64), 0, s, n, K, C_max, env, state, params, warm,
-                       xi, warm0, rho, rho0);
+                       cost_sum, xi, warm0, cost, rho, rho0);
     return hipGetLastError();
 }
 

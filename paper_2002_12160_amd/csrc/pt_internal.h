@@ -59,7 +59,7 @@ hipError_t launch_reset_queue(int32_t *q, hipStream_t s);
 hipError_t launch_window(const pt::Consts &P, const pt::Tables &tb, const float *seg_win, float *state, float *params,
                          float *warm, const float *obs_gt_win, float *cost_sum, float *obs_out,
                          const int32_t *env_order, int32_t *queue, int64_t *stats, int waves_per_block, int blocks,
-                         hipStream_t s);
+                         float *ckpt, hipStream_t s);
 hipError_t window_occupancy(int waves_per_block, int max_cand, bool fp64, int *blocks_per_cu);
 hipError_t set_lds_limits(size_t bytes);
 hipError_t set_grad_lds_limits(size_t bytes);
@@ -70,11 +70,13 @@ hipError_t launch_window_fwd(const pt::Consts &P, const pt::Tables &tb, const fl
                              hipStream_t s);
 hipError_t launch_window_bwd(const pt::Consts &P, const pt::Tables &tb, const float *seg_win, int n, int i0,
                              int count, const int32_t *env, const float *xi, const float *obs_gt_win,
-                             const float *ckpt, const int32_t *flag, float *grad, hipStream_t s);
+                             const float *ckpt, bool ckpt_by_env, const int32_t *flag, float *grad,
+                             hipStream_t s);
 hipError_t launch_select_elites(int G, float elite_frac, const int32_t *group_start, const float *cost_sum,
                                 int32_t *elite_env, hipStream_t s);
 hipError_t launch_refine_gather(int n, int K, int C_max, const int32_t *env, const float *state, const float *params,
-                                const float *warm, float *xi, float *warm0, float *rho, float rho0, hipStream_t s);
+                                const float *warm, const float *cost_sum, float *xi, float *warm0, float *cost,
+                                float *rho, float rho0, hipStream_t s);
 hipError_t launch_refine_propose(int n, const pt::RefineArgs &A, const float *xi, const float *grad, const float *rho,
                                  float *xi_try, hipStream_t s);
 hipError_t launch_refine_accept(int n, int K, int C_max, const int32_t *env, float *cost_cur, const float *cost_try,

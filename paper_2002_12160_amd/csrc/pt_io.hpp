@@ -4,6 +4,7 @@
 #pragma once
 
 #include "pt_internal.h"
+#include "pt_step.hpp"
 
 namespace pt {
 
@@ -121,6 +122,55 @@ __device__ __forceinline__ float step_cost_wave(const Consts &P, float cl)
     float cs = 0.f;
     for (int l = 0; l < P.L; ++l) cs += bcast_lane(cl, l);
     return cs;
+}
+
+// checkpoint of one step of one simulation: body record x(3) q(4) v(3) w(3)
+// f(3) (16 floats), then per contact slot r(3) and key as 4 doubles
+constexpr int CK_BODY = 16;
+__host__ __device__ constexpr size_t ckpt_step_floats(int C_max) { return CK_BODY + 8 * (size_t)C_max; }
+
+__device__ __forceinline__ void save_body(float *__restrict__ ck, const Body &B)
+{
+    if (lane_id() == 0) {
+        float4 *b4 = reinterpret_cast<float4 *>(ck);
+        b4[0] = make_float4(B.x[0], B.x[1], B.x[2], B.q[0]);
+        b4[1] = make_float4(B.q[1], B.q[2], B.q[3], B.v[0]);
+        b4[2] = make_float4(B.v[1], B.v[2], B.w[0], B.w[1]);
+        b4[3] = make_float4(B.w[2], B.f[0], B.f[1], B.f[2]);
+    }
+}
+
+__device__ __forceinline__ void load_body_ckpt(const float *__restrict__ ck, Body &B)
+{
+    const float4 *b4 = reinterpret_cast<const float4 *>(ck);
+    float4 a = b4[0], b = b4[1], c = b4[2], d = b4[3];
+    B.x[0] = a.x; B.x[1] = a.y; B.x[2] = a.z; B.q[0] = a.w;
+    B.q[1] = b.x; B.q[2] = b.y; B.q[3] = b.z; B.v[0] = b.w;
+    B.v[1] = c.x; B.v[2] = c.y; B.w[0] = c.z; B.w[1] = c.w;
+    B.w[2] = d.x; B.f[0] = d.y; B.f[1] = d.z; B.f[2] = d.w;
+}
+
+template <typename SR>
+__device__ __forceinline__ void save_contact(float *__restrict__ ck, int C_max, const StepState<SR> &st)
+{
+    const int lane = lane_id();
+    if (lane < C_max) {
+        double2 *d2 = reinterpret_cast<double2 *>(ck + CK_BODY) + 2 * lane;
+        d2[0] = make_double2((double)st.r[0], (double)st.r[1]);
+        d2[1] = make_double2((double)st.r[2], (double)(st.act ? st.key : -1));
+    }
+}
+
+template <typename SR>
+__device__ __forceinline__ int load_contact(const float *__restrict__ ck, int C_max, SR *r)
+{
+    const int lane = lane_id();
+    r[0] = r[1] = r[2] = SR(0);
+    if (lane >= C_max) return -1;
+    const double2 *d2 = reinterpret_cast<const double2 *>(ck + CK_BODY) + 2 * lane;
+    double2 a = d2[0], b = d2[1];
+    r[0] = (SR)a.x; r[1] = (SR)a.y; r[2] = (SR)b.x;
+    return (int)b.y;
 }
 
 }  // namespace pt

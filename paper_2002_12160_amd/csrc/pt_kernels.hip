@@ -385,7 +385,7 @@ __global__ __launch_bounds__(StepBounds<SR>::threads) void k_window(Consts P, Ta
                                                  float *__restrict__ warm, const float *__restrict__ obs_gt_win,
                                                  float *__restrict__ cost_sum, float *__restrict__ obs_out,
                                                  const int32_t *__restrict__ env_order, int32_t *__restrict__ queue,
-                                                 int64_t *__restrict__ stats)
+                                                 int64_t *__restrict__ stats, float *__restrict__ ckpt)
 {
     extern __shared__ __align__(16) char smem[];
     const int wib = threadIdx.x / WAVE;
@@ -416,7 +416,16 @@ __global__ __launch_bounds__(StepBounds<SR>::threads) void k_window(Consts P, Ta
         for (int t = 0; t < P.T; ++t) {
             int link;
             float imp[3];
-            env_step<SR>(P, seg_win + (size_t)t * P.L * SEG_STRIDE, sph, S, inv, B, wkey, wr, link, imp, lds, st);
+            // with a checkpoint buffer: the body before the step and the kept
+            // contacts' keys and impulses after its solve, per simulation
+            const float *seg = seg_win + (size_t)t * P.L * SEG_STRIDE;
+            float *ck = ckpt ? ckpt + ((size_t)e * P.T + t) * ckpt_step_floats(P.C_max) : nullptr;
+            if (ck) save_body(ck, B);
+            StepState<SR> sst;
+            step_setup<SR>(P, seg, sph, S, inv, B, wkey, wr, lds, st, sst);
+            step_solve<SR>(P, sst, B.mu, inv, reinterpret_cast<SR *>(lds.cand_d));
+            if (ck) save_contact<SR>(ck, P.C_max, sst);
+            step_finish<SR>(P, sst, inv, B, wkey, wr, link, imp);
             *reinterpret_cast<float4 *>(stage + 4 * lane) = make_float4(__int_as_float(link), imp[0], imp[1], imp[2]);
             wave_sync();
             float o[4];
@@ -514,15 +523,15 @@ hipError_t launch_reset_queue(int32_t *q, hipStream_t s)
 hipError_t launch_window(const Consts &P, const Tables &tb, const float *seg_win, float *state, float *params,
                          float *warm, const float *obs_gt_win, float *cost_sum, float *obs_out,
                          const int32_t *env_order, int32_t *queue, int64_t *stats, int waves_per_block, int blocks,
-                         hipStream_t s)
+                         float *ckpt, hipStream_t s)
 {
     size_t lds = (size_t)waves_per_block * wave_lds_bytes(P.max_cand);
     if (P.solve_fp64)
         hipLaunchKernelGGL(k_window<double>, dim3(blocks), dim3(WAVE * waves_per_block), lds, s, P, tb, seg_win,
-                           state, params, warm, obs_gt_win, cost_sum, obs_out, env_order, queue, stats);
+                           state, params, warm, obs_gt_win, cost_sum, obs_out, env_order, queue, stats, ckpt);
     else
         hipLaunchKernelGGL(k_window<float>, dim3(blocks), dim3(WAVE * waves_per_block), lds, s, P, tb, seg_win,
-                           state, params, warm, obs_gt_win, cost_sum, obs_out, env_order, queue, stats);
+                           state, params, warm, obs_gt_win, cost_sum, obs_out, env_order, queue, stats, ckpt);
     return hipGetLastError();
 }
 

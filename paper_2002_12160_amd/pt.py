@@ -54,6 +54,7 @@ class BatchDesc(C.Structure):
         ("hand", C.c_void_p), ("spheres", C.c_void_p), ("n_spheres", C.c_void_p), ("inv_inertia", C.c_void_p),
         ("env_type", C.c_void_p), ("group_start", C.c_void_p),
         ("state", C.c_void_p), ("params", C.c_void_p), ("warm", C.c_void_p),
+        ("window_checkpoints", C.c_int32),
     ]
 
 
@@ -181,7 +182,8 @@ class Batch:
     tensors it is bound to (state [13][K], params [5][K], warm [K][C_max][4])."""
 
     def __init__(self, *, hand, spheres, n_spheres, inv_inertia, env_type, group_start, consts, C_max,
-                 newton_iters, T, state, params, resample=None, solve_precision=64, device="cuda"):
+                 newton_iters, T, state, params, resample=None, solve_precision=64, window_checkpoints=False,
+                 device="cuda"):
         self.device = torch.device(device)
         K = int(np.asarray(env_type).shape[0])
         self.K, self.C_max, self.T = K, int(C_max), int(T)
@@ -225,6 +227,7 @@ class Batch:
         d.state = self.state.data_ptr()
         d.params = self.params.data_ptr()
         d.warm = self.warm.data_ptr()
+        d.window_checkpoints = 1 if window_checkpoints else 0
         self.desc = d
         self.handle = pt_create_batch(d)
 

@@ -326,3 +326,37 @@ def test_window_grad_chunks_agree(pt):
         assert torch.equal(e1.view(torch.int32), e_all[:, j:j + 1].contiguous().view(torch.int32))
         assert torch.equal(w1.view(torch.int32), w_all[j:j + 1].view(torch.int32))
     b.close()
+
+
+def test_refine_from_window_checkpoints_is_identical(pt):
+    # the first gradient from the checkpoints the population's window recorded
+    # equals the one from a replay of the window, bit for bit
+    _say("elite refinement with and without window checkpoints, bitwise")
+    T = 10
+    K = 64
+    cfg = S.CONFIGS["adjoint1024"].with_(T=T)
+    sc = S.make_scene(cfg, K=K, steps=3 * T)
+    outs = []
+    for wc in (False, True):
+        b = pt.Batch.from_scene(sc, window_checkpoints=wc)
+        h = pt.Batch.from_scene(sc, hidden=True)
+        gtw = torch.zeros((T, 4, sc.L, sc.G), device="cuda")
+        cost = torch.zeros(K, device="cuda")
+        best = torch.zeros(sc.G, dtype=torch.int32, device="cuda")
+        parent = torch.zeros(K, dtype=torch.int32, device="cuda")
+        rec = []
+        for w in range(2):
+            rows = [sc.u[max(w * T - 1, 0)]] + [sc.u[w * T + t] for t in range(T)]
+            u_t = torch.as_tensor(np.array(rows, dtype=np.float32), device="cuda")
+            h.run_window(u_t, torch.zeros_like(gtw), torch.zeros(sc.G, device="cuda"), None, gtw, graph=False)
+            snap = b.snapshot()
+            b.run_window(u_t, gtw, cost, None, None, graph=(w == 1))
+            b.refine_elites(u_t, gtw, cost, snap, steps=3, step=0.5, best=best)
+            rec.append(cost.clone())
+            b.resample(cost, w, parent)
+        torch.cuda.synchronize()
+        outs.append([x.view(torch.int32).clone() for x in (b.state, b.params, b.warm, *rec)])
+        b.close()
+        h.close()
+    for x, y in zip(*outs):
+        assert torch.equal(x, y)
