@@ -360,3 +360,54 @@ def test_refine_from_window_checkpoints_is_identical(pt):
         h.close()
     for x, y in zip(*outs):
         assert torch.equal(x, y)
+
+
+def test_window_grad_resting_sphere_analytic(pt):
+    # One step of a sphere at rest on a horizontal sensor link, penetrating it
+    # by `pen`: the single contact is closed, u_n = 0, so
+    # r_n (1/m + eps) = g dt - v_z - b_n with b_n = erp d / dt (d = -pen), the
+    # sensor reads |c| = r_n / dt straight down, and a one-step window cost
+    # w_mag (|c| - g0)^2 (observed direction also straight down) has the
+    # closed-form derivatives below.  The smoothing delta shifts u_n by about
+    # mu delta, 1e-4 of g dt, far inside the 1e-3 bar.
+    from tests import tiny
+    _say("window gradient of a sphere resting on a sensor link: closed form")
+    rho, R, m, mu, pen = 0.01, 0.008, 0.1, 0.5, 1e-4
+    z_link = 0.5
+    c = tiny.consts()
+    dt, g, eps, erp = c.dt, -c.gravity[2], c.compliance, c.erp
+    hand = np.array([tiny.link_row((-0.05, 0.0, z_link), (0.05, 0.0, z_link), R)])
+    sph, nsph, inv = tiny.single_sphere(rho, inv_inertia=(2.5 / rho ** 2,) * 3)
+    st = tiny.state(x=(0.0, 0.0, z_link + R + rho - pen))
+    pr = tiny.params(m, mu)
+    b = pt.Batch(hand=hand, spheres=sph, n_spheres=nsph, inv_inertia=inv, env_type=np.zeros(1, np.int32),
+                 group_start=np.array([0, 1], np.int32), consts=c, C_max=4, newton_iters=100, T=1,
+                 state=st[None], params=pr[None])
+    bn = erp * (-pen) / dt
+    rn = m * (g * dt - bn) / (1.0 + eps * m)
+    cmag = rn / dt
+    g0 = 0.5 * cmag
+    gt = np.zeros((1, 4, 1, 1), dtype=np.float32)
+    gt[0, :, 0, 0] = (g0, 0.0, 0.0, -1.0)
+    gt_t = torch.as_tensor(gt, device="cuda")
+    u_t = torch.zeros((2, 1), device="cuda")          # the hand has no joints
+    start = torch.as_tensor(np.concatenate([st, pr]).astype(np.float32)[:, None].copy(), device="cuda")
+    env = torch.zeros(1, dtype=torch.int32, device="cuda")
+    cost, grad, _, _ = b.window_grad(u_t, gt_t, env, start, _cold_warm(1, 4))
+    torch.cuda.synchronize()
+    gr = grad.cpu().numpy()[:, 0].astype(np.float64)
+    dC = 2.0 * c.w_mag * (cmag - g0)
+    want = {
+        13: dC * (g * dt - bn) / (1.0 + eps * m) ** 2 / dt,     # d/dm
+        2: dC * (-m * (erp / dt) / (1.0 + eps * m)) / dt,       # d/dz
+        9: dC * (-m / (1.0 + eps * m)) / dt,                    # d/dv_z
+    }
+    _say(f"cost gpu {cost.item():.6e} closed form {c.w_mag * (cmag - g0) ** 2:.6e}; grad m, z, v_z gpu "
+         f"{gr[13]:.6e} {gr[2]:.6e} {gr[9]:.6e} closed form {want[13]:.6e} {want[2]:.6e} {want[9]:.6e}")
+    np.testing.assert_allclose(cost.item(), c.w_mag * (cmag - g0) ** 2, rtol=1e-3)
+    for k, v in want.items():
+        np.testing.assert_allclose(gr[k], v, rtol=1e-3)
+    # sliding the sphere along the link axis, or off it sideways (at first
+    # order), does not change the gap
+    assert abs(gr[0]) <= 1e-4 * abs(want[2]) and abs(gr[1]) <= 1e-4 * abs(want[2])
+    b.close()
