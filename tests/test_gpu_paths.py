@@ -210,3 +210,50 @@ def test_cost_and_argmin_match_oracle(pt):
     torch.cuda.synchronize()
     assert best.cpu().numpy()[0] == 2
     b.close()
+
+
+def test_divergent_simulations(pt):
+    # A simulation whose state is not finite (a divergent sample) gets a NaN
+    # window cost, ranks last, is never the estimate nor an elite, and the
+    # resampler overwrites it with a copy of an elite.  A group whose
+    # simulations have all diverged keeps its lowest indices as elites (NaN
+    # ranks as +inf, ties by index) and stays divergent: the caller has to
+    # re-initialise it.
+    _say("divergent simulations: NaN cost, never elite, replaced at resampling")
+    cfg = S.CONFIGS["small"]
+    K = 32
+    sc = S.make_scene(cfg, K=K, steps=2 * cfg.T)
+    b = pt.Batch.from_scene(sc)
+    h = pt.Batch.from_scene(sc, hidden=True)
+    T = cfg.T
+    uw = _window_inputs(sc, 0, T)
+    gtw = torch.zeros((T, 4, sc.L, sc.G), device="cuda")
+    h.run_window(uw, torch.zeros_like(gtw), torch.zeros(sc.G, device="cuda"), None, gtw, graph=False)
+    b.state[7:10, 5] = float("nan")
+    b.state[7, 9] = 1e30
+    cost = torch.zeros(K, device="cuda")
+    best = torch.zeros(sc.G, dtype=torch.int32, device="cuda")
+    parent = torch.zeros(K, dtype=torch.int32, device="cuda")
+    b.run_window(uw, gtw, cost, best, None, graph=False)
+    torch.cuda.synchronize()
+    c = cost.cpu().numpy()
+    assert np.isnan(c[5]) and not np.isfinite(c[9])
+    assert best.item() not in (5, 9)
+    b.resample(cost, 0, parent)
+    torch.cuda.synchronize()
+    par = parent.cpu().numpy()
+    assert par[5] >= 0 and par[9] >= 0                      # replaced, not kept
+    st = b.state.cpu().numpy()
+    assert np.all(np.isfinite(st[:, 5])) and np.all(np.isfinite(st[:, 9]))
+    assert np.array_equal(st[:, 5], st[:, par[5]])           # a copy of its elite
+    # every simulation divergent
+    b.state[7:10, :] = float("nan")
+    cost.zero_()
+    b.run_window(uw, gtw, cost, best, None, graph=False)
+    b.resample(cost, 1, parent)
+    torch.cuda.synchronize()
+    kb = max(1, int(np.floor(np.float32(K) * np.float32(cfg.elite_frac))))
+    assert best.item() == 0
+    assert np.array_equal(np.nonzero(parent.cpu().numpy() == -1)[0], np.arange(kb))
+    b.close()
+    h.close()
