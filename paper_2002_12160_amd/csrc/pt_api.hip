@@ -208,12 +208,12 @@ pt_status pt_create_batch(const pt_batch_desc *d, pt_batch *out)
     *out = nullptr;
     pt_status st = validate(d);
     if (st != PT_OK) return st;
-    // candidate list (every sphere-link pair, plus 4 entries of padding for
+    // candidate list (every sphere-link pair, plus 8 entries of padding for
     // the cap's 16-byte reads); the same LDS holds, once the cap has run, the
     // rows of the solve's cross-contact sums (lane_span(C_max) rows of 50
     // doubles)
     const int red_rows = d->C_max <= 16 ? 16 : (d->C_max <= 32 ? 32 : 64);
-    const int max_cand = std::max(round_up(d->S_max * (d->L + 1) + 4, 64), round_up(red_rows * 50, 64));
+    const int max_cand = std::max(round_up(d->S_max * (d->L + 1) + 8, 64), round_up(red_rows * 50, 64));
     const size_t wave_lds = pt::wave_lds_bytes(max_cand);
     if (wave_lds > 160 * 1024)
         return fail(PT_E_UNSUPPORTED, "S_max*(L+1) = %d candidates need %zu B of LDS per simulation (> 160 KiB)",

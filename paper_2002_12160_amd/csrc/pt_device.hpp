@@ -177,15 +177,20 @@ __device__ __forceinline__ void quat_mul(const float *a, const float *b, float *
 // hand segment record (16 floats): a(3), radius, ab(3), 1/|ab|^2 (0 if
 // degenerate), va(3), 0, vb(3), 0  -- positions at the start of the step,
 // endpoint velocities over the step.
-__device__ __forceinline__ float pair_gap(const float *__restrict__ seg, int l, int L, const float *c, float rho)
+// gap of sphere (c, rho) to the capsule whose record starts at s
+__device__ __forceinline__ float segment_gap(const float *s, const float *c, float rho)
 {
-    if (l == L) return c[2] - rho;
-    const float *s = seg + l * SEG_STRIDE;
     float ca0 = c[0] - s[0], ca1 = c[1] - s[1], ca2 = c[2] - s[2];
     float t = (ca0 * s[4] + ca1 * s[5] + ca2 * s[6]) * s[7];
     t = fminf(fmaxf(t, 0.f), 1.f);
     float d0 = ca0 - t * s[4], d1 = ca1 - t * s[5], d2 = ca2 - t * s[6];
     return sqrtf(d0 * d0 + d1 * d1 + d2 * d2) - rho - s[3];
+}
+
+__device__ __forceinline__ float pair_gap(const float *__restrict__ seg, int l, int L, const float *c, float rho)
+{
+    if (l == L) return c[2] - rho;
+    return segment_gap(seg + l * SEG_STRIDE, c, rho);
 }
 
 // full contact geometry of a kept pair: gap, normal (link -> object),

@@ -175,7 +175,16 @@ __device__ __forceinline__ void step_setup(const Consts &P, const float *__restr
     const float *R = st.R;
 
     // 2. narrow phase: lanes over spheres, candidates appended to LDS in
-    //    (sphere block, link) order by ballot + prefix count
+    //    (sphere block, link) order by ballot + prefix count.  The links'
+    //    segment records (first 8 floats) sit in registers, one link per
+    //    lane, and are broadcast link by link.
+    float sgr[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    if (lane < L) {
+        const float4 a = *reinterpret_cast<const float4 *>(seg + lane * SEG_STRIDE);
+        const float4 b = *reinterpret_cast<const float4 *>(seg + lane * SEG_STRIDE + 4);
+        sgr[0] = a.x; sgr[1] = a.y; sgr[2] = a.z; sgr[3] = a.w;
+        sgr[4] = b.x; sgr[5] = b.y; sgr[6] = b.z; sgr[7] = b.w;
+    }
     int ncand = 0;
     for (int kb = 0; kb < S; kb += WAVE) {
         int k = kb + lane;
@@ -189,7 +198,15 @@ __device__ __forceinline__ void step_setup(const Consts &P, const float *__restr
                       B.x[1] + R[3] * s4[0] + R[4] * s4[1] + R[5] * s4[2],
                       B.x[2] + R[6] * s4[0] + R[7] * s4[1] + R[8] * s4[2]};
         for (int l = 0; l <= L; ++l) {
-            float d = pair_gap(seg, l, L, c, s4[3]);
+            float d;
+            if (l == L) {
+                d = c[2] - s4[3];
+            } else {
+                float sl[8];
+#pragma unroll
+                for (int i = 0; i < 8; ++i) sl[i] = bcast_lane(sgr[i], l);
+                d = segment_gap(sl, c, s4[3]);
+            }
             bool cand = valid && (d < P.margin);
             uint64_t mask = __ballot(cand);
             if (cand) {
@@ -208,9 +225,10 @@ __device__ __forceinline__ void step_setup(const Consts &P, const float *__restr
 
     // 3. cap: rank of every candidate in (d, key) order; the C_max lowest
     //    land in sel[rank]
-    //    (all lanes read the same four candidates per 16-byte LDS read;
-    //    entries past ncand are padded with (+inf, INT_MAX), never below)
-    if (lane < 4) {
+    //    (all lanes read the same eight candidates per pair of 16-byte LDS
+    //    reads; entries past ncand are padded with (+inf, INT_MAX), never
+    //    below)
+    if (lane < 8) {
         lds.cand_d[ncand + lane] = __int_as_float(0x7f800000);
         lds.cand_k[ncand + lane] = 0x7fffffff;
     }
@@ -219,13 +237,19 @@ __device__ __forceinline__ void step_setup(const Consts &P, const float *__restr
         float di = lds.cand_d[i];
         int ki = lds.cand_k[i];
         int rank = 0;
-        for (int j = 0; j < ncand; j += 4) {
+        for (int j = 0; j < ncand; j += 8) {
             const float4 d4 = *reinterpret_cast<const float4 *>(lds.cand_d + j);
+            const float4 e4 = *reinterpret_cast<const float4 *>(lds.cand_d + j + 4);
             const int4 k4 = *reinterpret_cast<const int4 *>(lds.cand_k + j);
+            const int4 m4 = *reinterpret_cast<const int4 *>(lds.cand_k + j + 4);
             rank += (d4.x < di || (d4.x == di && k4.x < ki)) ? 1 : 0;
             rank += (d4.y < di || (d4.y == di && k4.y < ki)) ? 1 : 0;
             rank += (d4.z < di || (d4.z == di && k4.z < ki)) ? 1 : 0;
             rank += (d4.w < di || (d4.w == di && k4.w < ki)) ? 1 : 0;
+            rank += (e4.x < di || (e4.x == di && m4.x < ki)) ? 1 : 0;
+            rank += (e4.y < di || (e4.y == di && m4.y < ki)) ? 1 : 0;
+            rank += (e4.z < di || (e4.z == di && m4.z < ki)) ? 1 : 0;
+            rank += (e4.w < di || (e4.w == di && m4.w < ki)) ? 1 : 0;
         }
         if (rank < P.C_max) lds.sel[rank] = ki;
     }
@@ -242,13 +266,24 @@ __device__ __forceinline__ void step_setup(const Consts &P, const float *__restr
 
     // 4. contact setup, one contact per lane, and the warm start from the
     //    previous step's impulse of the same key
+    //    (keys of the previous cache are unique; eight compared per round)
     contact_setup<SR>(P, seg, sph, B, lane < C ? lds.sel[lane] : -1, st);
     if (st.act) {
-        for (int j = 0; j < P.C_max; ++j) {
-            if (lds.wkey[j] == st.key) {
-                st.r[0] = lds.wr[3 * j]; st.r[1] = lds.wr[3 * j + 1]; st.r[2] = lds.wr[3 * j + 2];
-                break;
-            }
+        int hit = -1;
+        for (int j = 0; j < P.C_max; j += 8) {
+            const int4 a = *reinterpret_cast<const int4 *>(lds.wkey + j);
+            const int4 b = *reinterpret_cast<const int4 *>(lds.wkey + j + 4);
+            hit = a.x == st.key ? j : hit;
+            hit = a.y == st.key ? j + 1 : hit;
+            hit = a.z == st.key ? j + 2 : hit;
+            hit = a.w == st.key ? j + 3 : hit;
+            hit = b.x == st.key ? j + 4 : hit;
+            hit = b.y == st.key ? j + 5 : hit;
+            hit = b.z == st.key ? j + 6 : hit;
+            hit = b.w == st.key ? j + 7 : hit;
+        }
+        if (hit >= 0) {
+            st.r[0] = lds.wr[3 * hit]; st.r[1] = lds.wr[3 * hit + 1]; st.r[2] = lds.wr[3 * hit + 2];
         }
     }
 }
