@@ -235,9 +235,9 @@ pt_status pt_create_batch(const pt_batch_desc *d, pt_batch *out)
     b->warm = d->warm;
     b->group_start.assign(d->group_start, d->group_start + d->G + 1);
     for (int g = 0; g < d->G; ++g) b->max_group = std::max(b->max_group, b->group_start[g + 1] - b->group_start[g]);
-    if ((size_t)8 * b->max_group > 160 * 1024) {
+    if (pt::resample_lds_bytes(b->max_group) > 160 * 1024) {
         delete b;
-        return fail(PT_E_UNSUPPORTED, "group of %d simulations exceeds the resampler's LDS (max 20480)", b->max_group);
+        return fail(PT_E_UNSUPPORTED, "group of %d simulations exceeds the resampler's LDS (max 16384)", b->max_group);
     }
 
     auto cleanup = [&](pt_status code) {
@@ -564,7 +564,7 @@ pt_status pt_refine_elites(pt_batch b, const float *u_win, const float *obs_gt_w
     const int n = b->n_elite;
     RefineBufs r = refine_layout(b->d_ref, P, n);
     const Tables tb = tables_of(b);
-    HIP_TRY(launch_select_elites(P.G, b->R.elite_frac, b->d_group_start, cost_sum, b->d_elite, st));
+    HIP_TRY(launch_select_elites(P.G, b->max_group, b->R.elite_frac, b->d_group_start, cost_sum, b->d_elite, st));
     if (elite_out)
         HIP_TRY(hipMemcpyAsync(elite_out, b->d_elite, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, st));
     if (steps > 0) {

@@ -188,23 +188,18 @@ __global__ __launch_bounds__(WAVE) void k_window_bwd(Consts P, Tables tb, const 
 __global__ __launch_bounds__(1024) void k_select_elites(int G, float elite_frac, const int32_t *__restrict__ group_start,
                                                         const float *__restrict__ cost_sum, int32_t *__restrict__ elite_env)
 {
+    extern __shared__ __align__(16) char smem[];
     const int g = blockIdx.x;
     if (g >= G) return;
     int off = 0;
     for (int h = 0; h < g; ++h) off += elite_count(group_start[h + 1] - group_start[h], elite_frac);
     const int lo = group_start[g], n = group_start[g + 1] - lo;
+    const int np2 = sort_slots(n);
     const int kb = elite_count(n, elite_frac);
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        float ci = cost_sum[lo + i];
-        if (ci != ci) ci = __int_as_float(0x7f800000);
-        int rank = 0;
-        for (int j = 0; j < n; ++j) {
-            float cj = cost_sum[lo + j];
-            if (cj != cj) cj = __int_as_float(0x7f800000);
-            rank += (cj < ci || (cj == ci && j < i)) ? 1 : 0;
-        }
-        if (rank < kb) elite_env[off + rank] = lo + i;
-    }
+    float *cs = reinterpret_cast<float *>(smem);
+    int *order = reinterpret_cast<int *>(smem + 4 * (size_t)np2);
+    sort_group(cost_sum + lo, n, np2, cs, order);
+    for (int t = threadIdx.x; t < kb; t += blockDim.x) elite_env[off + t] = lo + order[t];
 }
 
 // start of each listed simulation from the window-start snapshot (and, if
@@ -328,10 +323,11 @@ hipError_t launch_window_bwd(const Consts &P, const Tables &tb, const float *seg
     return hipGetLastError();
 }
 
-hipError_t launch_select_elites(int G, float elite_frac, const int32_t *group_start, const float *cost_sum,
-                                int32_t *elite_env, hipStream_t s)
+hipError_t launch_select_elites(int G, int max_group, float elite_frac, const int32_t *group_start,
+                                const float *cost_sum, int32_t *elite_env, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_select_elites, dim3(G), dim3(1024), 0, s, G, elite_frac, group_start, cost_sum, elite_env);
+    hipLaunchKernelGGL(k_select_elites, dim3(G), dim3(1024), resample_lds_bytes(max_group), s, G, elite_frac,
+                       group_start, cost_sum, elite_env);
     return hipGetLastError();
 }
 
@@ -366,7 +362,8 @@ hipError_t launch_refine_accept(int n, int K, int C_max, const int32_t *env, flo
 
 hipError_t set_grad_lds_limits(size_t bytes)
 {
-    const void *fs[] = {reinterpret_cast<const void *>(k_window_fwd<float>),
+    const void *fs[] = {reinterpret_cast<const void *>(k_select_elites),
+                        reinterpret_cast<const void *>(k_window_fwd<float>),
                         reinterpret_cast<const void *>(k_window_fwd<double>),
                         reinterpret_cast<const void *>(k_window_bwd<float>),
                         reinterpret_cast<const void *>(k_window_bwd<double>)};

@@ -35,6 +35,20 @@ __host__ __device__ inline int elite_count(int n, float elite_frac)
     return kb < 1 ? 1 : (kb > n ? n : kb);
 }
 
+// slots of one group's sort: the next power of two
+__host__ __device__ constexpr int sort_slots(int n)
+{
+    int p = 1;
+    while (p < n) p <<= 1;
+    return p;
+}
+
+// LDS of one group's sort: costs and indices over sort_slots(max_group)
+__host__ __device__ constexpr size_t resample_lds_bytes(int max_group)
+{
+    return (size_t)8 * (size_t)sort_slots(max_group);
+}
+
 // bytes of LDS per wavefront: candidate (d, key) list, selected keys,
 // previous warm keys and impulses, contact staging for the observation
 __host__ __device__ constexpr size_t wave_lds_bytes(int max_cand)
@@ -72,8 +86,8 @@ hipError_t launch_window_bwd(const pt::Consts &P, const pt::Tables &tb, const fl
                              int count, const int32_t *env, const float *xi, const float *obs_gt_win,
                              const float *ckpt, bool ckpt_by_env, const int32_t *flag, float *grad,
                              hipStream_t s);
-hipError_t launch_select_elites(int G, float elite_frac, const int32_t *group_start, const float *cost_sum,
-                                int32_t *elite_env, hipStream_t s);
+hipError_t launch_select_elites(int G, int max_group, float elite_frac, const int32_t *group_start,
+                                const float *cost_sum, int32_t *elite_env, hipStream_t s);
 hipError_t launch_refine_gather(int n, int K, int C_max, const int32_t *env, const float *state, const float *params,
                                 const float *warm, const float *cost_sum, float *xi, float *warm0, float *cost,
                                 float *rho, float rho0, hipStream_t s);

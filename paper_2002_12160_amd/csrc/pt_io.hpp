@@ -173,4 +173,35 @@ __device__ __forceinline__ int load_contact(const float *__restrict__ ck, int C_
     return (int)b.y;
 }
 
+// One group's simulations in (cost, index) order, NaN ranked as +inf: a
+// bitonic sort in LDS over np2 slots (a power of two >= n, padding (+inf,
+// index >= n) sorts after every real entry).  All threads of the block take
+// part; afterwards ix[0..n) holds the group's local indices in order.
+__device__ __forceinline__ void sort_group(const float *__restrict__ cost, int n, int np2, float *cs, int *ix)
+{
+    for (int i = threadIdx.x; i < np2; i += blockDim.x) {
+        const float v = i < n ? cost[i] : __int_as_float(0x7f800000);
+        cs[i] = (v != v) ? __int_as_float(0x7f800000) : v;
+        ix[i] = i;
+    }
+    __syncthreads();
+    for (int k = 2; k <= np2; k <<= 1)
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = threadIdx.x; i < np2; i += blockDim.x) {
+                const int p = i ^ j;
+                if (p > i) {
+                    const float ci = cs[i], cp = cs[p];
+                    const int xi = ix[i], xp = ix[p];
+                    // entries are distinct (indices are), so "after" is strict
+                    const bool after = ci > cp || (ci == cp && xi > xp);
+                    if (after == ((i & k) == 0)) {
+                        cs[i] = cp; cs[p] = ci;
+                        ix[i] = xp; ix[p] = xi;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+}
+
 }  // namespace pt

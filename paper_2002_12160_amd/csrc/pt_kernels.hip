@@ -308,7 +308,7 @@ __device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, float &n0, fl
     n1 = rad * sinf(ang);
 }
 
-// one block per group; ranks by counting, then copies and perturbs
+// one block per group; sorts by (cost, index), then copies and perturbs
 __global__ __launch_bounds__(1024) void k_resample(Consts P, ResampleArgs R, const int32_t *__restrict__ group_start,
                                                    uint32_t window_idx, float *__restrict__ cost_sum,
                                                    float *__restrict__ state, float *__restrict__ params,
@@ -318,23 +318,10 @@ __global__ __launch_bounds__(1024) void k_resample(Consts P, ResampleArgs R, con
     const int g = blockIdx.x;
     const int lo = group_start[g], hi = group_start[g + 1];
     const int n = hi - lo;
+    const int np2 = sort_slots(n);
     float *cs = reinterpret_cast<float *>(smem);
-    int *order = reinterpret_cast<int *>(smem + 4 * (size_t)n);
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        float v = cost_sum[lo + i];
-        cs[i] = (v != v) ? __int_as_float(0x7f800000) : v;
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        float ci = cs[i];
-        int rank = 0;
-        for (int j = 0; j < n; ++j) {
-            float cj = cs[j];
-            rank += (cj < ci || (cj == ci && j < i)) ? 1 : 0;
-        }
-        order[rank] = i;
-    }
-    __syncthreads();
+    int *order = reinterpret_cast<int *>(smem + 4 * (size_t)np2);
+    sort_group(cost_sum + lo, n, np2, cs, order);
     const int kb = elite_count(n, R.elite_frac);
     const uint32_t key0 = (uint32_t)(R.seed & 0xffffffffu), key1 = (uint32_t)(R.seed >> 32);
     const int K = P.K;
@@ -508,7 +495,7 @@ hipError_t launch_resample(const Consts &P, const ResampleArgs &R, const int32_t
                            uint32_t window_idx, float *cost_sum, float *state, float *params, float *warm,
                            int32_t *parent, hipStream_t s)
 {
-    size_t lds = (size_t)8 * max_group;
+    size_t lds = resample_lds_bytes(max_group);
     hipLaunchKernelGGL(k_resample, dim3(P.G), dim3(1024), lds, s, P, R, group_start, window_idx, cost_sum, state,
                        params, warm, parent);
     return hipGetLastError();
