@@ -56,8 +56,9 @@ def parse():
 
 # HBM bytes per k_step launch of the 256-simulation workload (float64 solve),
 # from FETCH_SIZE / WRITE_SIZE counters scaled by a plain device copy of known
-# size (profiles/k_step_plain256.txt); None for any other configuration
-MEASURED_TRAFFIC = {("plain256", 64): 839651}
+# size (profiles/k_step_plain256.txt); None where the kernel changed since
+# the counters were taken, and for any other configuration
+MEASURED_TRAFFIC = {}
 
 
 # algorithmic floating-point operations (an FMA counts 2; a square root,

@@ -358,8 +358,13 @@ pt_status pt_cost(pt_batch b, const float *obs, const float *obs_gt, float *cost
     if (!b) return fail(PT_E_ARG, "batch is NULL");
     if (!obs || !obs_gt || !cost_sum) return fail(PT_E_ARG, "obs/obs_gt/cost_sum is NULL");
     hipStream_t st = (hipStream_t)s;
-    HIP_TRY(launch_cost(b->P, b->d_group_of, obs, obs_gt, cost_sum, st));
-    if (best) HIP_TRY(launch_argmin(b->P.G, b->d_group_start, cost_sum, best, st));
+    // up to FUSED_ARGMIN_MAX simulations the cost kernel's last workgroup ranks
+    // the groups itself; past that one workgroup's pass over the population
+    // takes longer than a launch of the per-group argmin kernel
+    const bool fused = best && b->P.K <= pt::FUSED_ARGMIN_MAX;
+    HIP_TRY(launch_cost(b->P, b->d_group_of, b->d_group_start, obs, obs_gt, cost_sum, fused ? best : nullptr,
+                        b->d_queue + 2, st));
+    if (best && !fused) HIP_TRY(launch_argmin(b->P.G, b->d_group_start, cost_sum, best, st));
     return PT_OK;
 }
 
@@ -384,10 +389,13 @@ static pt_status enqueue_window(pt_batch b, const float *u_win, const float *obs
     int want = (P.K + wpb - 1) / wpb;
     int blocks = std::min(want, bpc * b->num_cu);
     HIP_TRY(launch_hand_fk(b->d_hand, P.L, P.dt, u_win, u_win + P.D, P.D, P.T, b->d_seg_win, st));
-    HIP_TRY(launch_reset_queue(b->d_queue, st));
+    // the window kernel's last workgroup puts the work queue back to 0 and,
+    // for populations up to FUSED_ARGMIN_MAX, ranks the groups
+    const bool fused = best && P.K <= pt::FUSED_ARGMIN_MAX;
     HIP_TRY(launch_window(P, tables_of(b), b->d_seg_win, state, params, warm, obs_gt_win, cost_sum, obs_out,
-                          b->d_order, b->d_queue, b->d_stats, wpb, blocks, ckpt, st));
-    if (best) HIP_TRY(launch_argmin(P.G, b->d_group_start, cost_sum, best, st));
+                          b->d_order, b->d_queue, b->d_stats, wpb, blocks, ckpt, b->d_group_start,
+                          fused ? best : nullptr, st));
+    if (best && !fused) HIP_TRY(launch_argmin(P.G, b->d_group_start, cost_sum, best, st));
     return PT_OK;
 }
 

@@ -100,6 +100,23 @@ __device__ __forceinline__ double bcast_lane(double v, int lane)
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+__device__ __forceinline__ uint64_t bcast_lane(uint64_t v, int lane)
+{
+    uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, lane);
+    uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), lane);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// A candidate contact (gap d, key k >= 0) as one 64-bit word whose unsigned
+// order is the (d, k) order: d's bits made monotone (sign set: all bits
+// flipped, else the sign bit set; -0 taken as +0 first) above the key.
+__device__ __forceinline__ uint64_t pack_gap_key(float d, int k)
+{
+    uint32_t u = __float_as_uint(d + 0.f);
+    u = (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+    return ((uint64_t)u << 32) | (uint32_t)k;
+}
+
 template <typename T, int N>
 __device__ __forceinline__ void wave_sum(T (&v)[N], int span = 64)
 {
@@ -264,14 +281,35 @@ template <typename T>
 struct FBOut {
     T phi[3];
     T w0, w1, w2, s, st;   // sqrt(z), det(sqrt z), smoothed |u_t|
+    T rw, rs, rst;         // 1 / (2 w0), 1 / s, 1 / st
     T x[3], y[3];
 };
+
+// 1/sqrt(x) for x > 0 (the math library's, to about an ulp)
+__device__ __forceinline__ double rsqrt_t(double x) { return rsqrt(x); }
+__device__ __forceinline__ float rsqrt_t(float x) { return rsqrtf(x); }
+
+// 1/x for a finite, normal, nonzero x: the hardware estimate refined by two
+// Newton-Raphson steps y <- y + y (1 - x y), each of which squares the
+// relative error, to about an ulp in float64
+__device__ __forceinline__ double recip(double x)
+{
+    double y = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, y, 1.0);
+    y = fma(y, e, y);
+    e = fma(-x, y, 1.0);
+    return fma(y, e, y);
+}
+__device__ __forceinline__ float recip(float x) { return 1.f / x; }
 
 template <typename T>
 __device__ __forceinline__ void fb_value(T mu, T kap, T del, const T *r, const T *u, FBOut<T> &o)
 {
     T x0 = kap * mu * r[0], x1 = kap * r[1], x2 = kap * r[2];
-    T st = sqrt(u[1] * u[1] + u[2] * u[2] + del * del);
+    // square roots as x * (1/sqrt(x)): the reciprocals serve the Jacobian
+    T q2 = u[1] * u[1] + u[2] * u[2] + del * del;
+    T rst = rsqrt_t(q2);
+    T st = q2 * rst;
     T y0 = u[0] + mu * st, y1 = mu * u[1], y2 = mu * u[2];
     T A = x0 * x0 + x1 * x1 + x2 * x2;
     T B = y0 * y0 + y1 * y1 + y2 * y2;
@@ -285,10 +323,15 @@ __device__ __forceinline__ void fb_value(T mu, T kap, T del, const T *r, const T
     T cr = x1 * y2 - x2 * y1;
     T detz = dx * dx + dy * dy + T(2) * (c1 * c1 + c2 * c2) + T(2) * e * e + T(2) * cr * cr +
                  T(4) * d2 * (A + B) + T(4) * d2 * d2;
-    T sd = sqrt(detz);                       // sqrt(l1) sqrt(l2)
-    T sum = sqrt(T(2) * (z0 + sd));          // sqrt(l1) + sqrt(l2)
-    T inv = T(1) / sum;
+    T rs = rsqrt_t(detz);
+    T sd = detz * rs;                        // sqrt(l1) sqrt(l2)
+    T s2 = T(2) * (z0 + sd);
+    T inv = rsqrt_t(s2);
+    T sum = s2 * inv;                        // sqrt(l1) + sqrt(l2)
     o.w0 = T(0.5) * sum;
+    o.rw = inv;
+    o.rs = rs;
+    o.rst = rst;
     o.w1 = zb1 * inv;
     o.w2 = zb2 * inv;
     o.s = sd;
@@ -307,7 +350,7 @@ __device__ __forceinline__ void fb_jacobian(T mu, T kap, const T *u, const FBOut
                                             T *DXo = nullptr, T *DYo = nullptr)
 {
     T w0 = o.w0, w1 = o.w1, w2 = o.w2, s = o.s;
-    T k = T(1) / (w0 * s);
+    T k = T(2) * o.rw * o.rs;                // 1 / (w0 s)
     T Li[9] = {k * w0 * w0, -k * w0 * w1, -k * w0 * w2,
                    -k * w0 * w1, k * (s + w1 * w1), k * w1 * w2,
                    -k * w0 * w2, k * w1 * w2, k * (s + w2 * w2)};
@@ -330,7 +373,7 @@ __device__ __forceinline__ void fb_jacobian(T mu, T kap, const T *u, const FBOut
         Dy[3 * i + 1] = (i == 1 ? T(1) : T(0)) - py1;
         Dy[3 * i + 2] = (i == 2 ? T(1) : T(0)) - py2;
     }
-    T th1 = mu * u[1] / o.st, th2 = mu * u[2] / o.st;
+    T th1 = mu * u[1] * o.rst, th2 = mu * u[2] * o.rst;
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
         JX[3 * i + 0] = Dx[3 * i + 0] * (kap * mu);
@@ -357,7 +400,7 @@ __device__ __forceinline__ void inv3(const T *a, T *o)
     T c01 = a[5] * a[6] - a[3] * a[8];
     T c02 = a[3] * a[7] - a[4] * a[6];
     T det = a[0] * c00 + a[1] * c01 + a[2] * c02;
-    T id = T(1) / det;
+    T id = recip(det);
     o[0] = c00 * id;
     o[1] = (a[2] * a[7] - a[1] * a[8]) * id;
     o[2] = (a[1] * a[5] - a[2] * a[4]) * id;
@@ -453,12 +496,13 @@ __device__ __forceinline__ void load16<float>(const float *p, float *v)
 }
 
 // Sum of v[0..N) over lanes [0, n) through LDS, for wide vectors where DPP
-// rounds would cost N instructions each: the lanes below n8 = n rounded up to
-// 8 write their values as rows (lanes n .. n8-1 must hold zeros), lane j < N
-// adds column j over the rows, eight at a time into four interleaved partial
-// sums in a fixed order, the N sums go back to LDS and every lane reads all
-// of them -- the same bits in every lane.  Lanes >= n8 do not take part.
-// buf: 16-byte aligned, n8 rows of RedStride<T> elements.
+// rounds would cost N instructions each: the lanes below n16 = n rounded up
+// to 16 write their values as rows (lanes n .. n16-1 must hold zeros), lane
+// j < N adds column j over the rows, sixteen reads in flight at a time into
+// four interleaved partial sums in a fixed order, the N sums go back to LDS
+// and every lane reads all of them -- the same bits in every lane.  Lanes >=
+// n16 do not take part.  buf: 16-byte aligned, n16 rows of RedStride<T>
+// elements.
 template <typename T, int N>
 __device__ __forceinline__ void lds_sum(T (&v)[N], int n, T *buf)
 {
@@ -466,8 +510,8 @@ __device__ __forceinline__ void lds_sum(T (&v)[N], int n, T *buf)
     constexpr int PER = 16 / (int)sizeof(T);
     static_assert(N <= RS && N <= 64, "vector too long for the reduction buffer");
     const int lane = lane_id();
-    const int n8 = (n + 7) & ~7;
-    if (lane < n8) {
+    const int n16 = (n + 15) & ~15;
+    if (lane < n16) {
         T *row = buf + lane * RS;
 #pragma unroll
         for (int j = 0; j + PER <= N; j += PER) store16<T>(row + j, v + j);
@@ -478,12 +522,12 @@ __device__ __forceinline__ void lds_sum(T (&v)[N], int n, T *buf)
     T s4[4] = {T(0), T(0), T(0), T(0)};
     if (lane < N) {
         const T *col = buf + lane;
-        for (int r0 = 0; r0 < n8; r0 += 8, col += 8 * RS) {
-            T x[8];
+        for (int r0 = 0; r0 < n16; r0 += 16, col += 16 * RS) {
+            T x[16];
 #pragma unroll
-            for (int k = 0; k < 8; ++k) x[k] = col[k * RS];
+            for (int k = 0; k < 16; ++k) x[k] = col[k * RS];
 #pragma unroll
-            for (int k = 0; k < 8; ++k) s4[k & 3] += x[k];
+            for (int k = 0; k < 16; ++k) s4[k & 3] += x[k];
         }
     }
     const T s = (s4[0] + s4[1]) + (s4[2] + s4[3]);
@@ -504,27 +548,28 @@ __device__ __forceinline__ void lds_sum(T (&v)[N], int n, T *buf)
 template <typename SR>
 __device__ __forceinline__ void schur_contribution(const SR *Qw, const SR *gw, const SR *rho, SR *acc)
 {
-    SR X[9];
+    // Y = -Qw rhat: row i is rho x q_i, so no block needs a negation
+    SR Y[9];
 #pragma unroll
-    for (int i = 0; i < 3; ++i) cross3(Qw + 3 * i, rho, X + 3 * i);
+    for (int i = 0; i < 3; ++i) cross3(rho, Qw + 3 * i, Y + 3 * i);
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
             acc[6 * i + j] = Qw[3 * i + j];
-            acc[6 * i + 3 + j] = -X[3 * i + j];
+            acc[6 * i + 3 + j] = Y[3 * i + j];
         }
-    // bottom blocks: columns rho x (column j of Qw), -(rho x column j of X)
+    // bottom blocks: columns rho x (column j of Qw), rho x (column j of Y)
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-        SR cq[3] = {Qw[j], Qw[3 + j], Qw[6 + j]}, cx[3] = {X[j], X[3 + j], X[6 + j]};
+        SR cq[3] = {Qw[j], Qw[3 + j], Qw[6 + j]}, cy[3] = {Y[j], Y[3 + j], Y[6 + j]};
         SR a3[3], b3[3];
         cross3(rho, cq, a3);
-        cross3(rho, cx, b3);
+        cross3(rho, cy, b3);
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
             acc[6 * (3 + i) + j] = a3[i];
-            acc[6 * (3 + i) + 3 + j] = -b3[i];
+            acc[6 * (3 + i) + 3 + j] = b3[i];
         }
     }
     SR tg[3];
@@ -537,21 +582,29 @@ __device__ __forceinline__ void schur_contribution(const SR *Qw, const SR *gw, c
 // principal inertia is finite (Iw = Iinv^-1, inverted in SR so that the two
 // agree to SR rounding), else only M^-1 = diag(im I, Iinv) (a body that
 // cannot turn about some axis).
+// Only the form's own block and scalar are kept: (m, Iw) in the inertia
+// form, (1/m, Iinv) otherwise.
 template <typename SR>
 struct BodyMass {
     bool inertia_form;
-    SR m, im, Iw[9], Iinv[9];
+    SR sc, blk[9];
 };
 
 template <typename SR>
 __device__ __forceinline__ void body_mass(float m, const float *Iinv, const float *inv_in, BodyMass<SR> &M)
 {
     M.inertia_form = inv_in[0] > 0.f && inv_in[1] > 0.f && inv_in[2] > 0.f;
-    M.m = m;
-    M.im = SR(1) / SR(m);
+    SR I9[9];
 #pragma unroll
-    for (int i = 0; i < 9; ++i) M.Iinv[i] = Iinv[i];
-    if (M.inertia_form) inv3(M.Iinv, M.Iw);
+    for (int i = 0; i < 9; ++i) I9[i] = Iinv[i];
+    if (M.inertia_form) {
+        M.sc = m;
+        inv3(I9, M.blk);
+    } else {
+        M.sc = SR(1) / SR(m);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) M.blk[i] = I9[i];
+    }
 }
 
 // Solves (I + M^-1 A6) z = -M^-1 b6 for the summed acc (A6 = acc[0..35],
@@ -564,16 +617,16 @@ __device__ __forceinline__ void schur_solve(const SR *acc, const BodyMass<SR> &M
     if (M.inertia_form) {
 #pragma unroll
         for (int i = 0; i < 36; ++i) S6[i] = acc[i];
-        S6[0] += M.m; S6[7] += M.m; S6[14] += M.m;
+        S6[0] += M.sc; S6[7] += M.sc; S6[14] += M.sc;
 #pragma unroll
         for (int i = 0; i < 3; ++i)
 #pragma unroll
-            for (int j = 0; j < 3; ++j) S6[6 * (3 + i) + 3 + j] += M.Iw[3 * i + j];
+            for (int j = 0; j < 3; ++j) S6[6 * (3 + i) + 3 + j] += M.blk[3 * i + j];
 #pragma unroll
         for (int i = 0; i < 6; ++i) z[i] = -acc[36 + i];
     } else {
-        const SR im = M.im;
-        const SR *Iinv = M.Iinv;
+        const SR im = M.sc;
+        const SR *Iinv = M.blk;
 #pragma unroll
         for (int j = 0; j < 6; ++j) {
             S6[j] = acc[j] * im + (j == 0 ? SR(1) : SR(0));

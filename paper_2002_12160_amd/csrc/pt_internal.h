@@ -25,6 +25,10 @@ struct RefineArgs {
     float m_lo, m_hi, mu_lo, mu_hi;
 };
 
+// populations up to this size rank their groups in the last workgroup of the
+// cost or window kernel instead of a launch of their own
+constexpr int FUSED_ARGMIN_MAX = 4096;
+
 // rows of a window start: x(3) q(4) v(3) w(3) m mu f(3)
 constexpr int XI_ROWS = 18;
 
@@ -63,17 +67,16 @@ hipError_t launch_hand_fk(const float *hand, int L, float dt, const float *u_pre
 hipError_t launch_step(const pt::Consts &P, const pt::Tables &tb, const float *seg, float *state, float *params,
                        float *warm, float *contacts, int64_t *stats, int waves_per_block, hipStream_t s);
 hipError_t launch_observe(const pt::Consts &P, const float *contacts, float *obs, hipStream_t s);
-hipError_t launch_cost(const pt::Consts &P, const int32_t *group_of, const float *obs, const float *obs_gt,
-                       float *cost_sum, hipStream_t s);
+hipError_t launch_cost(const pt::Consts &P, const int32_t *group_of, const int32_t *group_start, const float *obs,
+                       const float *obs_gt, float *cost_sum, int32_t *best, int32_t *done, hipStream_t s);
 hipError_t launch_argmin(int G, const int32_t *group_start, const float *cost, int32_t *best, hipStream_t s);
 hipError_t launch_resample(const pt::Consts &P, const pt::ResampleArgs &R, const int32_t *group_start, int max_group,
                            uint32_t window_idx, float *cost_sum, float *state, float *params, float *warm,
                            int32_t *parent, hipStream_t s);
-hipError_t launch_reset_queue(int32_t *q, hipStream_t s);
 hipError_t launch_window(const pt::Consts &P, const pt::Tables &tb, const float *seg_win, float *state, float *params,
                          float *warm, const float *obs_gt_win, float *cost_sum, float *obs_out,
                          const int32_t *env_order, int32_t *queue, int64_t *stats, int waves_per_block, int blocks,
-                         float *ckpt, hipStream_t s);
+                         float *ckpt, const int32_t *group_start, int32_t *best, hipStream_t s);
 hipError_t window_occupancy(int waves_per_block, int max_cand, bool fp64, int *blocks_per_cu);
 hipError_t set_lds_limits(size_t bytes);
 hipError_t set_grad_lds_limits(size_t bytes);

@@ -204,4 +204,62 @@ __device__ __forceinline__ void sort_group(const float *__restrict__ cost, int n
         }
 }
 
+// True in every thread of the workgroup that arrives last among the grid's
+// workgroups, counted on *done (0 before the launch); that workgroup sees the
+// global writes every other one made before its call.  The caller's last
+// workgroup puts *done back to 0 for the next launch.  Every thread of every
+// workgroup calls it once.  flag: one int of LDS, free for the call.
+__device__ __forceinline__ bool last_block(int32_t *done, int *flag)
+{
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) *flag = atomicAdd(done, 1) == (int)gridDim.x - 1;
+    __syncthreads();
+    const bool l = *flag != 0;
+    if (l) __threadfence();
+    return l;
+}
+
+// Per-group argmin of cost over [group_start[g], group_start[g + 1]) by one
+// workgroup (at most 1024 threads): the lowest index of the minimum with NaN
+// ranked as +inf, the group's start for an empty group.  (cost, index) pairs
+// are totally ordered, so the result does not depend on the order in which
+// the threads combine.  sv, si: 16 entries each of LDS, free for the call.
+__device__ __forceinline__ void block_argmin(int G, const int32_t *__restrict__ group_start, const float *cost,
+                                             int32_t *__restrict__ best, float *sv, int *si)
+{
+    const int lane = lane_id(), w = threadIdx.x / WAVE, nw = blockDim.x / WAVE;
+    const int nt = blockDim.x;
+    for (int g = 0; g < G; ++g) {
+        const int lo = group_start[g], hi = group_start[g + 1];
+        float bv = __int_as_float(0x7f800000);
+        int bi = 0x7fffffff;
+        for (int i0 = lo + threadIdx.x; i0 < hi; i0 += 4 * nt) {
+            float v[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) v[k] = i0 + k * nt < hi ? cost[i0 + k * nt] : 0.f;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int i = i0 + k * nt;
+                const float x = v[k] != v[k] ? __int_as_float(0x7f800000) : v[k];
+                if (i < hi && (x < bv || (x == bv && i < bi))) { bv = x; bi = i; }
+            }
+        }
+#pragma unroll
+        for (int off = WAVE / 2; off > 0; off >>= 1) {
+            const float x = __shfl_xor(bv, off);
+            const int i = __shfl_xor(bi, off);
+            if (x < bv || (x == bv && i < bi)) { bv = x; bi = i; }
+        }
+        if (lane == 0) { sv[w] = bv; si[w] = bi; }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            for (int k = 1; k < nw; ++k)
+                if (sv[k] < bv || (sv[k] == bv && si[k] < bi)) { bv = sv[k]; bi = si[k]; }
+            best[g] = bi == 0x7fffffff ? lo : bi;
+        }
+        __syncthreads();
+    }
+}
+
 }  // namespace pt

@@ -222,57 +222,43 @@ __global__ __launch_bounds__(256) void k_observe(Consts P, const float *__restri
 // one wavefront per simulation, lanes over sensors; obs_gt is [4][L][G]
 // (the observed batch's own observation layout)
 __global__ __launch_bounds__(256) void k_cost(Consts P, const int32_t *__restrict__ group_of,
+                                              const int32_t *__restrict__ group_start,
                                               const float *__restrict__ obs, const float *__restrict__ obs_gt,
-                                              float *__restrict__ cost_sum)
+                                              float *cost_sum, int32_t *__restrict__ best, int32_t *done)
 {
     const int e = xcd_block(blockIdx.x, gridDim.x) * (blockDim.x / WAVE) + threadIdx.x / WAVE;
-    if (e >= P.K) return;
     const int lane = lane_id();
-    const int g = group_of[e];
-    const size_t LK = (size_t)P.L * P.K, LG = (size_t)P.L * P.G;
-    float cl = 0.f;
-    if (lane < P.L) {
-        float o[4], gt[4];
-        for (int j = 0; j < 4; ++j) {
-            o[j] = obs[j * LK + (size_t)lane * P.K + e];
-            gt[j] = obs_gt[j * LG + (size_t)lane * P.G + g];
+    if (e < P.K) {
+        const int g = group_of[e];
+        const size_t LK = (size_t)P.L * P.K, LG = (size_t)P.L * P.G;
+        float cl = 0.f;
+        if (lane < P.L) {
+            float o[4], gt[4];
+            for (int j = 0; j < 4; ++j) {
+                o[j] = obs[j * LK + (size_t)lane * P.K + e];
+                gt[j] = obs_gt[j * LG + (size_t)lane * P.G + g];
+            }
+            cl = sensor_cost(P, o, gt);
         }
-        cl = sensor_cost(P, o, gt);
+        const float cs = step_cost_wave(P, cl);
+        if (lane == 0) cost_sum[e] += cs;
     }
-    const float cs = step_cost_wave(P, cl);
-    if (lane == 0) cost_sum[e] += cs;
+    // with `best`: the workgroup that finishes last ranks every group (Eq. 2)
+    __shared__ float sv[16];
+    __shared__ int si[17];
+    if (best && last_block(done, si + 16)) {
+        block_argmin(P.G, group_start, cost_sum, best, sv, si);
+        if (threadIdx.x == 0) *done = 0;
+    }
 }
 
 // one block per group: lowest index of the minimum, NaN ranked as +inf
 __global__ void k_argmin(const int32_t *__restrict__ group_start, const float *__restrict__ cost,
                          int32_t *__restrict__ best)
 {
-    __shared__ float sv[1024];
-    __shared__ int si[1024];
-    const int g = blockIdx.x;
-    const int lo = group_start[g], hi = group_start[g + 1];
-    float bv = __int_as_float(0x7f800000);
-    int bi = 0x7fffffff;
-    for (int i = lo + threadIdx.x; i < hi; i += blockDim.x) {
-        float v = cost[i];
-        if (v != v) v = __int_as_float(0x7f800000);
-        if (v < bv || (v == bv && i < bi)) { bv = v; bi = i; }
-    }
-    sv[threadIdx.x] = bv;
-    si[threadIdx.x] = bi;
-    __syncthreads();
-    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-        if (threadIdx.x < s) {
-            float v = sv[threadIdx.x + s];
-            int i = si[threadIdx.x + s];
-            if (v < sv[threadIdx.x] || (v == sv[threadIdx.x] && i < si[threadIdx.x])) {
-                sv[threadIdx.x] = v;
-                si[threadIdx.x] = i;
-            }
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) best[g] = si[0] == 0x7fffffff ? lo : si[0];
+    __shared__ float sv[16];
+    __shared__ int si[16];
+    block_argmin(1, group_start + blockIdx.x, cost, best + blockIdx.x, sv, si);
 }
 
 // ---------------------------------------------------------------------
@@ -361,18 +347,14 @@ __global__ __launch_bounds__(1024) void k_resample(Consts P, ResampleArgs R, con
 // ---------------------------------------------------------------------
 // batched path: persistent kernel over a window of T steps
 // ---------------------------------------------------------------------
-__global__ void k_reset_queue(int32_t *q)
-{
-    if (threadIdx.x == 0 && blockIdx.x == 0) q[0] = 0;
-}
-
 template <typename SR>
 __global__ __launch_bounds__(StepBounds<SR>::threads) void k_window(Consts P, Tables tb, const float *__restrict__ seg_win,
                                                  float *__restrict__ state, float *__restrict__ params,
                                                  float *__restrict__ warm, const float *__restrict__ obs_gt_win,
                                                  float *__restrict__ cost_sum, float *__restrict__ obs_out,
-                                                 const int32_t *__restrict__ env_order, int32_t *__restrict__ queue,
-                                                 int64_t *__restrict__ stats, float *__restrict__ ckpt)
+                                                 const int32_t *__restrict__ env_order, int32_t *queue,
+                                                 int64_t *__restrict__ stats, float *__restrict__ ckpt,
+                                                 const int32_t *__restrict__ group_start, int32_t *__restrict__ best)
 {
     extern __shared__ __align__(16) char smem[];
     const int wib = threadIdx.x / WAVE;
@@ -440,6 +422,15 @@ __global__ __launch_bounds__(StepBounds<SR>::threads) void k_window(Consts P, Ta
         done += P.T;
     }
     flush_stats(stats, st, done);
+    // the workgroup that finishes last ranks every group (Eq. 2) and puts the
+    // work queue back to 0 for the next window
+    // (the block's dynamic LDS is free once every wave has left the loop)
+    float *sv = reinterpret_cast<float *>(smem);
+    int *si = reinterpret_cast<int *>(smem) + 16;
+    if (last_block(queue + 1, si + 16)) {
+        if (best) block_argmin(P.G, group_start, cost_sum, best, sv, si);
+        if (threadIdx.x == 0) { queue[0] = 0; queue[1] = 0; }
+    }
 }
 
 }  // namespace pt
@@ -477,11 +468,12 @@ hipError_t launch_observe(const Consts &P, const float *contacts, float *obs, hi
     return hipGetLastError();
 }
 
-hipError_t launch_cost(const Consts &P, const int32_t *group_of, const float *obs, const float *obs_gt,
-                       float *cost_sum, hipStream_t s)
+hipError_t launch_cost(const Consts &P, const int32_t *group_of, const int32_t *group_start, const float *obs,
+                       const float *obs_gt, float *cost_sum, int32_t *best, int32_t *done, hipStream_t s)
 {
     int blocks = (P.K + 3) / 4;
-    hipLaunchKernelGGL(k_cost, dim3(blocks), dim3(256), 0, s, P, group_of, obs, obs_gt, cost_sum);
+    hipLaunchKernelGGL(k_cost, dim3(blocks), dim3(256), 0, s, P, group_of, group_start, obs, obs_gt, cost_sum, best,
+                       done);
     return hipGetLastError();
 }
 
@@ -501,24 +493,20 @@ hipError_t launch_resample(const Consts &P, const ResampleArgs &R, const int32_t
     return hipGetLastError();
 }
 
-hipError_t launch_reset_queue(int32_t *q, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(64), 0, s, q);
-    return hipGetLastError();
-}
-
 hipError_t launch_window(const Consts &P, const Tables &tb, const float *seg_win, float *state, float *params,
                          float *warm, const float *obs_gt_win, float *cost_sum, float *obs_out,
                          const int32_t *env_order, int32_t *queue, int64_t *stats, int waves_per_block, int blocks,
-                         float *ckpt, hipStream_t s)
+                         float *ckpt, const int32_t *group_start, int32_t *best, hipStream_t s)
 {
     size_t lds = (size_t)waves_per_block * wave_lds_bytes(P.max_cand);
     if (P.solve_fp64)
         hipLaunchKernelGGL(k_window<double>, dim3(blocks), dim3(WAVE * waves_per_block), lds, s, P, tb, seg_win,
-                           state, params, warm, obs_gt_win, cost_sum, obs_out, env_order, queue, stats, ckpt);
+                           state, params, warm, obs_gt_win, cost_sum, obs_out, env_order, queue, stats, ckpt,
+                           group_start, best);
     else
         hipLaunchKernelGGL(k_window<float>, dim3(blocks), dim3(WAVE * waves_per_block), lds, s, P, tb, seg_win,
-                           state, params, warm, obs_gt_win, cost_sum, obs_out, env_order, queue, stats, ckpt);
+                           state, params, warm, obs_gt_win, cost_sum, obs_out, env_order, queue, stats, ckpt,
+                           group_start, best);
     return hipGetLastError();
 }
 

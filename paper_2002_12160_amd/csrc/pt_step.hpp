@@ -218,40 +218,60 @@ __device__ __forceinline__ void step_setup(const Consts &P, const float *__restr
         }
     }
     wave_sync();
+    ncand = __builtin_amdgcn_readfirstlane(ncand);   // wave-uniform: loops on it stay scalar
     const int C = ncand < P.C_max ? ncand : P.C_max;
     st.C = C;
     st.ncand = ncand;
     st.span = lane_span(C);
 
     // 3. cap: rank of every candidate in (d, key) order; the C_max lowest
-    //    land in sel[rank]
-    //    (all lanes read the same eight candidates per pair of 16-byte LDS
-    //    reads; entries past ncand are padded with (+inf, INT_MAX), never
-    //    below)
-    if (lane < 8) {
-        lds.cand_d[ncand + lane] = __int_as_float(0x7f800000);
-        lds.cand_k[ncand + lane] = 0x7fffffff;
-    }
-    wave_sync();
-    for (int i = lane; i < ncand; i += WAVE) {
-        float di = lds.cand_d[i];
-        int ki = lds.cand_k[i];
-        int rank = 0;
-        for (int j = 0; j < ncand; j += 8) {
-            const float4 d4 = *reinterpret_cast<const float4 *>(lds.cand_d + j);
-            const float4 e4 = *reinterpret_cast<const float4 *>(lds.cand_d + j + 4);
-            const int4 k4 = *reinterpret_cast<const int4 *>(lds.cand_k + j);
-            const int4 m4 = *reinterpret_cast<const int4 *>(lds.cand_k + j + 4);
-            rank += (d4.x < di || (d4.x == di && k4.x < ki)) ? 1 : 0;
-            rank += (d4.y < di || (d4.y == di && k4.y < ki)) ? 1 : 0;
-            rank += (d4.z < di || (d4.z == di && k4.z < ki)) ? 1 : 0;
-            rank += (d4.w < di || (d4.w == di && k4.w < ki)) ? 1 : 0;
-            rank += (e4.x < di || (e4.x == di && m4.x < ki)) ? 1 : 0;
-            rank += (e4.y < di || (e4.y == di && m4.y < ki)) ? 1 : 0;
-            rank += (e4.z < di || (e4.z == di && m4.z < ki)) ? 1 : 0;
-            rank += (e4.w < di || (e4.w == di && m4.w < ki)) ? 1 : 0;
+    //    land in sel[rank].  Up to a wave of candidates each lane holds one
+    //    as a packed (d, key) word and counts the lower words, broadcast
+    //    lane by lane; beyond, every lane ranks its candidates against the
+    //    LDS list, eight per pair of 16-byte reads (entries past ncand padded
+    //    with (+inf, INT_MAX), never below).
+    if (ncand <= WAVE) {
+        uint64_t w = ~0ull;
+        int ki = 0;
+        if (lane < ncand) {
+            ki = lds.cand_k[lane];
+            w = pack_gap_key(lds.cand_d[lane], ki);
         }
-        if (rank < P.C_max) lds.sel[rank] = ki;
+        // lanes past ncand hold the largest word, never below a candidate's,
+        // so the count runs over whole groups of four lanes
+        int rank = 0;
+        for (int j = 0; j < ncand; j += 4) {
+            const uint64_t a = bcast_lane(w, j), b = bcast_lane(w, j + 1);
+            const uint64_t c = bcast_lane(w, j + 2), d = bcast_lane(w, j + 3);
+            rank += (a < w ? 1 : 0) + (b < w ? 1 : 0) + (c < w ? 1 : 0) + (d < w ? 1 : 0);
+        }
+        if (lane < ncand && rank < P.C_max) lds.sel[rank] = ki;
+    } else {
+        if (lane < 8) {
+            lds.cand_d[ncand + lane] = __int_as_float(0x7f800000);
+            lds.cand_k[ncand + lane] = 0x7fffffff;
+        }
+        wave_sync();
+        for (int i = lane; i < ncand; i += WAVE) {
+            float di = lds.cand_d[i];
+            int ki = lds.cand_k[i];
+            int rank = 0;
+            for (int j = 0; j < ncand; j += 8) {
+                const float4 d4 = *reinterpret_cast<const float4 *>(lds.cand_d + j);
+                const float4 e4 = *reinterpret_cast<const float4 *>(lds.cand_d + j + 4);
+                const int4 k4 = *reinterpret_cast<const int4 *>(lds.cand_k + j);
+                const int4 m4 = *reinterpret_cast<const int4 *>(lds.cand_k + j + 4);
+                rank += (d4.x < di || (d4.x == di && k4.x < ki)) ? 1 : 0;
+                rank += (d4.y < di || (d4.y == di && k4.y < ki)) ? 1 : 0;
+                rank += (d4.z < di || (d4.z == di && k4.z < ki)) ? 1 : 0;
+                rank += (d4.w < di || (d4.w == di && k4.w < ki)) ? 1 : 0;
+                rank += (e4.x < di || (e4.x == di && m4.x < ki)) ? 1 : 0;
+                rank += (e4.y < di || (e4.y == di && m4.y < ki)) ? 1 : 0;
+                rank += (e4.z < di || (e4.z == di && m4.z < ki)) ? 1 : 0;
+                rank += (e4.w < di || (e4.w == di && m4.w < ki)) ? 1 : 0;
+            }
+            if (rank < P.C_max) lds.sel[rank] = ki;
+        }
     }
     // previous warm cache to LDS for the key lookup
     lds.wkey[lane] = wkey;

@@ -212,6 +212,38 @@ def test_cost_and_argmin_match_oracle(pt):
     b.close()
 
 
+@pytest.mark.parametrize("K", [64, 4096, 4097, 9000])
+def test_group_argmin_sizes(pt, K):
+    # the cost kernel ranks the groups in its last workgroup up to 4096
+    # simulations and leaves it to a kernel of its own beyond; both give the
+    # lowest index of the minimum with NaN last, on repeated calls (the
+    # last-workgroup counter is put back after each launch)
+    _say(f"group argmin, K={K}")
+    cfg = S.CONFIGS["small"].with_(group_types=(0, 0, 0))
+    sc = S.make_scene(cfg, K=K, steps=2)
+    b = pt.Batch.from_scene(sc)
+    G, L = sc.G, sc.L
+    zo = torch.zeros((4, L, K), device="cuda")
+    zg = torch.zeros((4, L, G), device="cuda")
+    best = torch.full((G,), -7, dtype=torch.int32, device="cuda")
+    rng = np.random.default_rng(K)
+    for rep in range(3):
+        c = rng.integers(0, 40, size=K).astype(np.float32)   # many ties
+        c[rng.uniform(size=K) < 0.1] = np.nan
+        if rep == 2:
+            lo, hi = sc.group_start[1], sc.group_start[2]
+            c[lo:hi] = np.nan                                 # a group with no finite cost
+        cost = torch.as_tensor(c, device="cuda")
+        b.cost(zo, zg, cost, best)
+        torch.cuda.synchronize()
+        got = best.cpu().numpy()
+        for g in range(G):
+            lo, hi = sc.group_start[g], sc.group_start[g + 1]
+            want = lo + oracle.argmin(c[lo:hi].astype(np.float64))
+            assert got[g] == want, (rep, g, got[g], want)
+    b.close()
+
+
 def test_divergent_simulations(pt):
     # A simulation whose state is not finite (a divergent sample) gets a NaN
     # window cost, ranks last, is never the estimate nor an elite, and the
