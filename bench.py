@@ -58,7 +58,28 @@ def parse():
 # from FETCH_SIZE / WRITE_SIZE counters scaled by a plain device copy of known
 # size (profiles/k_step_plain256.txt); None where the kernel changed since
 # the counters were taken, and for any other configuration
-MEASURED_TRAFFIC = {}
+MEASURED_TRAFFIC = {("plain256", 64): 843744}
+
+# VALU counters per k_step launch of the same workload (profiles/
+# k_step_plain256.txt): SQ_INSTS_VALU, SQ_ACTIVE_INST_VALU (quad-cycles) and
+# SQ_THREAD_CYCLES_VALU summed over the chip; the same staleness rule
+MEASURED_VALU = {("plain256", 64): (4072613, 4241541, 247078103)}
+SIMDS, CLOCK_HZ = 1024, 2.4e9     # MI355X: 256 CUs x 4 SIMDs at 2.4 GHz; a VALU instruction issues in 4 cycles
+
+
+def valu_figures(key, launch_s, waves):
+    """VALU issue and busy fractions of the chip's peak over one launch of
+    launch_s seconds, the active-lane fraction, from MEASURED_VALU; with one
+    wavefront per simulation a launch of `waves` wavefronts occupies at most
+    waves / SIMDS of the SIMDs (its ceiling)."""
+    m = MEASURED_VALU.get(key)
+    if m is None:
+        return None
+    insts, active_q, thread_cyc = m
+    slots = SIMDS * CLOCK_HZ * launch_s
+    return {"issue_frac": round(insts * 4 / slots, 4), "busy_frac": round(active_q * 4 / slots, 4),
+            "lane_frac": round(thread_cyc / (active_q * 64), 3), "insts_per_launch": insts,
+            "ceiling": round(min(1.0, waves / SIMDS), 4)}
 
 
 # algorithmic floating-point operations (an FMA counts 2; a square root,
@@ -371,7 +392,8 @@ def main():
                      "flop_per_env_step": round(flops / max(d_env, 1), 1),
                      "hbm_bytes_per_env_step": algorithmic_bytes(cfg.C_max),
                      "hbm_gbps": round(algorithmic_bytes(cfg.C_max) * d_env / step_kernel_s / 1e9, 3),
-                     "avg_launch_us": round(step_kernel_s / args.steps * 1e6, 2)},
+                     "avg_launch_us": round(step_kernel_s / args.steps * 1e6, 2),
+                     "valu": valu_figures((cfg.name, args.solve_precision), step_kernel_s / args.steps, K)},
     }
     result["roofline"]["frac"] = round(result["roofline"]["achieved"] / result["roofline"]["peak"], 6)
 
