@@ -101,6 +101,7 @@ def lib():
         L.or_philox4x32_10.argtypes = [C.POINTER(C.c_uint32), C.POINTER(C.c_uint32), C.POINTER(C.c_uint32)]
         L.or_resample_pbo.argtypes = [mp, C.POINTER(ResampleCfg), C.c_int, C.c_int, ip, C.c_uint32,
                                       dp, dp, dp, ip, dp, ip]
+        L.or_resample_apply.argtypes = [mp, C.POINTER(ResampleCfg), C.c_int, ip, C.c_uint32, dp, dp, dp, ip, dp]
         L.or_add.argtypes = [mp, C.c_int, dp, dp]
         L.or_add.restype = C.c_double
         L.or_window_cost.argtypes = [mp, C.c_int, dp, dp, C.c_void_p, C.c_void_p, C.c_int, dp, dp]
@@ -231,6 +232,18 @@ class Oracle:
         lib().or_resample_pbo(C.byref(self.m), C.byref(rcfg), K, G, _ip(group_start), window_idx, _dp(cost_sum),
                               _dp(state), _dp(params), _ip(wkey), _dp(wr), _ip(parent))
         return parent
+
+    def resample_weighted(self, kind, hyper, rcfg, group_start, window_idx, n_steps, cost_sum, state, params,
+                          wkey, wr):
+        """WRS or REPS resampling (Sec. III-D.1/2) in place; returns
+        (parent, pmf, eta, cdf, target) -- see oracle.resamplers."""
+        from . import resamplers as RS
+        pmf, eta = RS.group_pmf(kind, hyper, cost_sum, n_steps, group_start)
+        parent, cdf, target = RS.draw_parents(pmf, group_start, window_idx, int(rcfg.seed))
+        K = state.shape[0]
+        lib().or_resample_apply(C.byref(self.m), C.byref(rcfg), K, _ip(parent), window_idx, _dp(cost_sum),
+                                _dp(state), _dp(params), _ip(wkey), _dp(wr))
+        return parent, pmf, eta, cdf, target
 
     def add(self, typ, pose_a, pose_b):
         return lib().or_add(C.byref(self.m), int(typ), _dp(np.ascontiguousarray(pose_a[:7], dtype=np.float64)),

@@ -853,6 +853,48 @@ void or_resample_pbo(const or_model *m, const or_resample_cfg *rc, int K, int G,
     }
 }
 
+/* Resampling with replacement: copies from a snapshot of the envs before
+ * the call (a parent may itself be overwritten), then explores every env. */
+void or_resample_apply(const or_model *m, const or_resample_cfg *rc, int K, const int32_t *parent,
+                       uint32_t window_idx, double *cost_sum, double *state, double *params,
+                       int32_t *wkey, double *wr)
+{
+    int Cmax = m->C_max;
+    uint32_t key[2] = {(uint32_t)(rc->seed & 0xffffffffu), (uint32_t)(rc->seed >> 32)};
+    double *st0 = (double *)malloc(sizeof(double) * 13 * (size_t)K);
+    double *pr0 = (double *)malloc(sizeof(double) * 5 * (size_t)K);
+    int32_t *wk0 = (int32_t *)malloc(sizeof(int32_t) * (size_t)K * Cmax);
+    double *wr0 = (double *)malloc(sizeof(double) * (size_t)K * Cmax * 3);
+    memcpy(st0, state, sizeof(double) * 13 * (size_t)K);
+    memcpy(pr0, params, sizeof(double) * 5 * (size_t)K);
+    memcpy(wk0, wkey, sizeof(int32_t) * (size_t)K * Cmax);
+    memcpy(wr0, wr, sizeof(double) * (size_t)K * Cmax * 3);
+    for (int j = 0; j < K; ++j) {
+        int p = parent[j];
+        memcpy(state + 13 * (size_t)j, st0 + 13 * (size_t)p, 13 * sizeof(double));
+        memcpy(wkey + (size_t)j * Cmax, wk0 + (size_t)p * Cmax, (size_t)Cmax * sizeof(int32_t));
+        memcpy(wr + (size_t)j * Cmax * 3, wr0 + (size_t)p * Cmax * 3, (size_t)Cmax * 3 * sizeof(double));
+        double nrm[6];
+        uint32_t c1[4] = {(uint32_t)j, window_idx, 1u, 0u}, c2[4] = {(uint32_t)j, window_idx, 2u, 0u}, w1[4], w2[4];
+        or_philox4x32_10(c1, key, w1);
+        or_philox4x32_10(c2, key, w2);
+        box_muller(w1[0], w1[1], &nrm[0], &nrm[1]);
+        box_muller(w1[2], w1[3], &nrm[2], &nrm[3]);
+        box_muller(w2[0], w2[1], &nrm[4], &nrm[5]);
+        const double *pp0 = pr0 + 5 * (size_t)p;
+        double *pp = params + 5 * (size_t)j;
+        double mu = pp0[1] + rc->sigma_mu * nrm[0];
+        double ms = pp0[0] + rc->sigma_m * nrm[1];
+        pp[1] = mu < rc->mu_lo ? rc->mu_lo : (mu > rc->mu_hi ? rc->mu_hi : mu);
+        pp[0] = ms < rc->m_lo ? rc->m_lo : (ms > rc->m_hi ? rc->m_hi : ms);
+        pp[2] = rc->sigma_f * nrm[2];
+        pp[3] = rc->sigma_f * nrm[3];
+        pp[4] = rc->sigma_f * nrm[4];
+        cost_sum[j] = 0.0;
+    }
+    free(st0); free(pr0); free(wk0); free(wr0);
+}
+
 /* ------------------------------------------------------------------ */
 /* ADD metric                                                          */
 /* ------------------------------------------------------------------ */

@@ -136,6 +136,16 @@ void or_resample_pbo(const or_model *m, const or_resample_cfg *rc, int K, int G,
                      double *cost_sum, double *state, double *params,
                      int32_t *wkey, double *wr, int32_t *parent);
 
+/* Resampling with replacement (Sec. III-D.1, III-D.2): env j becomes a copy
+ * of env parent[j] as it was before the call (state, params, warm-start
+ * cache), then every env is explored: mu and m get N(0, sigma^2) noise
+ * around the copied values (clamped to their ranges) and the perturbation
+ * force is drawn from N(0, sigma_f^2 I), with the same Philox counters as the
+ * population-based resampler.  cost_sum is zeroed. */
+void or_resample_apply(const or_model *m, const or_resample_cfg *rc, int K, const int32_t *parent,
+                       uint32_t window_idx, double *cost_sum, double *state, double *params,
+                       int32_t *wkey, double *wr);
+
 /* ADD (Sec. IV): mean distance of the object's sphere centres between pose a
  * and pose b (each x(3), q(4)). */
 double or_add(const or_model *m, int type, const double *pose_a, const double *pose_b);
