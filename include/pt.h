@@ -173,6 +173,37 @@ PT_API pt_status pt_cost(pt_batch b, const float *obs, const float *obs_gt, floa
  * (j, window_idx, 2, 0).  cost_sum is zeroed.  parent [K] may be NULL. */
 PT_API pt_status pt_resample(pt_batch b, float *cost_sum, uint32_t window_idx, int32_t *parent, pt_stream s);
 
+/* Weighted resampling, WRS (Sec. III-D.1, Eq. 4), per group: with the
+ * window-mean costs C_i = cost_sum[i] / n_steps, P(i) is proportional to
+ * exp(-lambda (C_i - min_j C_j)) over the finite costs (a NaN or infinite
+ * cost gets P = 0; a group without a finite cost draws uniformly).  Every
+ * simulation j then draws its parent with replacement: the first index of
+ * the group whose running sum of P exceeds u = (w0 + 1/2) 2^-32 of the
+ * total, w = Philox4x32-10(key = seed, counter = (j, window_idx, 3, 0)), and
+ * becomes a copy of that parent as it was before the call (state, params,
+ * warm cache); every simulation is then explored as pt_resample explores a
+ * copy (same counters).  cost_sum is zeroed.  parent [K] (required)
+ * receives the drawn index; weights [K] (may be NULL) the group's P.
+ * lambda: finite, >= 0 (0 draws uniformly); n_steps >= 1.  The copies go
+ * through a snapshot buffer owned by the batch: no allocation. */
+PT_API pt_status pt_resample_wrs(pt_batch b, float *cost_sum, int32_t n_steps, uint32_t window_idx, float lambda,
+                                 int32_t *parent, float *weights, pt_stream s);
+
+/* Relative Entropy Policy Search, REPS (Sec. III-D.2, Eqs. 5-6), per group:
+ * rewards R_i = max_j C_j + min_j C_j - C_i over the finite window-mean
+ * costs, eta* = argmin over eta > 0 of eta epsilon + eta log((1/K_f) sum_i
+ * exp(R_i / eta)) (K_f finite costs), P(i) = softmax(R_i / eta*); then the
+ * draw, copies and exploration of pt_resample_wrs.  eta* is found where the
+ * dual's slope epsilon - KL(P_eta || uniform) vanishes, by bisection on
+ * log(eta) to ~1e-13; when all finite costs are equal P is uniform over
+ * them, and with no finite cost uniform over the group (eta* reported as
+ * +inf in both cases); when epsilon >= log(K_f / #argmin) the
+ * dual has no interior minimum and P is the eta -> 0+ limit, uniform over
+ * the lowest costs (eta* reported as 0).  eta [G] and weights [K] may be
+ * NULL.  epsilon: finite, > 0. */
+PT_API pt_status pt_resample_reps(pt_batch b, float *cost_sum, int32_t n_steps, uint32_t window_idx, float epsilon,
+                                  int32_t *parent, float *weights, float *eta, pt_stream s);
+
 /* Batched execution of one optimiser window: T steps of every simulation
  * with the per-step observation and cost fused, in one persistent kernel
  * (environments pulled from a work queue, state kept on chip for all T

@@ -75,7 +75,7 @@ def reps_rewards(cost_mean):
 def reps_pmf(cost_mean, eps):
     """Eqs. 5-6: (P, eta*).  eta* is found by a bounded scalar minimisation of
     g over log(eta); eta* is returned as 0 for the eta -> 0+ limit and +inf
-    when every finite cost is equal."""
+    when every finite cost is equal or none is finite."""
     c, ok = _finite(cost_mean)
     n = c.shape[0]
     if not ok.any():

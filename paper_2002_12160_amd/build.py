@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libpt.so")
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("pt_kernels.hip", "pt_grad.hip", "pt_api.hip")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("pt_kernels.hip", "pt_grad.hip", "pt_resample.hip", "pt_api.hip")]
 ARCH = os.environ.get("PT_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

@@ -73,6 +73,7 @@ struct pt_batch_s {
     int n_elite = 0;
     int32_t *d_elite = nullptr;  // [n_elite]
     float *d_ref = nullptr;      // see refine_layout
+    float *d_snap = nullptr;     // [18][K] + [K][C_max][4]: parents' copies for the weighted resamplers
     // caller-owned state
     float *state, *params, *warm;
     // host copies
@@ -254,6 +255,7 @@ pt_status pt_create_batch(const pt_batch_desc *d, pt_batch *out)
     HIP_TRY_C(hipDeviceGetAttribute(&b->num_cu, hipDeviceAttributeMultiprocessorCount, b->device));
     HIP_TRY_C(set_lds_limits(160 * 1024));
     HIP_TRY_C(set_grad_lds_limits(160 * 1024));
+    HIP_TRY_C(set_draw_lds_limits(160 * 1024));
 
     const size_t K = d->K;
     std::vector<int32_t> group_of(K), order(K);
@@ -285,6 +287,7 @@ pt_status pt_create_batch(const pt_batch_desc *d, pt_batch *out)
     HIP_TRY_C(hipMalloc(&b->d_ckpt, sizeof(float) * ckpt_floats(P, b->n_elite)));
     HIP_TRY_C(hipMalloc(&b->d_ref, sizeof(float) * refine_floats(P, b->n_elite)));
     HIP_TRY_C(hipMalloc(&b->d_elite, sizeof(int32_t) * b->n_elite));
+    HIP_TRY_C(hipMalloc(&b->d_snap, sizeof(float) * K * (18 + (size_t)4 * d->C_max)));
     if (d->window_checkpoints) HIP_TRY_C(hipMalloc(&b->d_wckpt, sizeof(float) * ckpt_floats(P, (int)K)));
     HIP_TRY_C(hipMemcpy(b->d_hand, d->hand, sizeof(float) * d->L * PT_HAND_STRIDE, hipMemcpyHostToDevice));
     HIP_TRY_C(hipMemcpy(b->d_spheres, d->spheres, sizeof(float) * d->n_types * d->S_max * 4, hipMemcpyHostToDevice));
@@ -315,7 +318,7 @@ pt_status pt_destroy_batch(pt_batch b)
     if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
     void *ptrs[] = {b->d_hand, b->d_spheres, b->d_inv, b->d_nsph, b->d_type, b->d_group_of, b->d_group_start,
                     b->d_order, b->d_queue, b->d_stats, b->d_seg, b->d_seg_win, b->d_contacts,
-                    b->d_seg_grad, b->d_tune, b->d_ckpt, b->d_wckpt, b->d_elite, b->d_ref};
+                    b->d_seg_grad, b->d_tune, b->d_ckpt, b->d_wckpt, b->d_elite, b->d_ref, b->d_snap};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete b;
@@ -375,6 +378,32 @@ pt_status pt_resample(pt_batch b, float *cost_sum, uint32_t window_idx, int32_t 
     HIP_TRY(launch_resample(b->P, b->R, b->d_group_start, b->max_group, window_idx, cost_sum, b->state, b->params,
                             b->warm, parent, (hipStream_t)s));
     return PT_OK;
+}
+
+static pt_status weighted_resample(pt_batch b, int kind, float hyper, float *cost_sum, int32_t n_steps,
+                                   uint32_t window_idx, int32_t *parent, float *weights, float *eta, pt_stream s)
+{
+    if (!b) return fail(PT_E_ARG, "batch is NULL");
+    if (!cost_sum || !parent) return fail(PT_E_ARG, "cost_sum/parent is NULL");
+    if (n_steps < 1) return fail(PT_E_ARG, "n_steps must be >= 1 (got %d)", n_steps);
+    if (!std::isfinite(hyper) || (kind == 0 ? hyper < 0.f : hyper <= 0.f))
+        return fail(PT_E_ARG, kind == 0 ? "lambda must be finite and >= 0" : "epsilon must be finite and > 0");
+    HIP_TRY(launch_weighted_resample(b->P, b->R, kind, hyper, b->d_group_start, b->max_group, n_steps, window_idx,
+                                     cost_sum, b->state, b->params, b->warm, b->d_snap, parent, weights, eta,
+                                     (hipStream_t)s));
+    return PT_OK;
+}
+
+pt_status pt_resample_wrs(pt_batch b, float *cost_sum, int32_t n_steps, uint32_t window_idx, float lambda,
+                          int32_t *parent, float *weights, pt_stream s)
+{
+    return weighted_resample(b, 0, lambda, cost_sum, n_steps, window_idx, parent, weights, nullptr, s);
+}
+
+pt_status pt_resample_reps(pt_batch b, float *cost_sum, int32_t n_steps, uint32_t window_idx, float epsilon,
+                           int32_t *parent, float *weights, float *eta, pt_stream s)
+{
+    return weighted_resample(b, 1, epsilon, cost_sum, n_steps, window_idx, parent, weights, eta, s);
 }
 
 // the launches of one window, in stream order

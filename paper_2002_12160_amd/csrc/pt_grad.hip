@@ -368,7 +368,7 @@ hipError_t set_grad_lds_limits(size_t bytes)
                         reinterpret_cast<const void *>(k_window_bwd<float>),
                         reinterpret_cast<const void *>(k_window_bwd<double>)};
     for (const void *f : fs) {
-        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+        hipError_t e = set_dynamic_lds_limit(f, bytes);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

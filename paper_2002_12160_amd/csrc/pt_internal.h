@@ -62,6 +62,16 @@ __host__ __device__ constexpr size_t wave_lds_bytes(int max_cand)
 
 }  // namespace pt
 
+// Lets kernel f take dynamic LDS up to `bytes` of workgroup LDS less its own
+// static LDS.
+inline hipError_t set_dynamic_lds_limit(const void *f, size_t bytes)
+{
+    hipFuncAttributes a;
+    hipError_t e = hipFuncGetAttributes(&a, f);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(bytes - a.sharedSizeBytes));
+}
+
 hipError_t launch_hand_fk(const float *hand, int L, float dt, const float *u_prev, const float *u, int stride,
                           int nsteps, float *seg_out, hipStream_t s);
 hipError_t launch_step(const pt::Consts &P, const pt::Tables &tb, const float *seg, float *state, float *params,
@@ -100,3 +110,8 @@ hipError_t launch_refine_accept(int n, int K, int C_max, const int32_t *env, flo
                                 float *xi, const float *xi_try, float *rho, int32_t *flag, const float *end_state,
                                 const float *end_warm, float *state, float *params, float *warm, float *cost_sum,
                                 hipStream_t s);
+hipError_t launch_weighted_resample(const pt::Consts &P, const pt::ResampleArgs &R, int kind, float hyper,
+                                    const int32_t *group_start, int max_group, int n_steps, uint32_t window_idx,
+                                    float *cost_sum, float *state, float *params, float *warm, float *snap,
+                                    int32_t *parent, float *weights, float *eta, hipStream_t s);
+hipError_t set_draw_lds_limits(size_t bytes);

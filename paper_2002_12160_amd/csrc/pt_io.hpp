@@ -262,4 +262,58 @@ __device__ __forceinline__ void block_argmin(int G, const int32_t *__restrict__ 
     }
 }
 
+// Philox4x32 with 10 rounds (Salmon et al., SC'11): per round the words 0
+// and 2 are multiplied by the two round multipliers, the high halves are
+// mixed with the other two words and the round key, and the key is bumped
+// by the two Weyl increments.
+__device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                                              uint32_t k1, uint32_t *out)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
+        uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+        uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+__device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, float &n0, float &n1)
+{
+    // uniforms (w + 1/2) 2^-32 in (0, 1), formed in double to keep every bit
+    double u = ((double)a + 0.5) * 2.3283064365386963e-10;
+    double v = ((double)b + 0.5) * 2.3283064365386963e-10;
+    float rad = sqrtf(-2.f * (float)log(u));
+    float ang = (float)(6.283185307179586 * v);
+    n0 = rad * cosf(ang);
+    n1 = rad * sinf(ang);
+}
+
+// Exploration of simulation j after a copy (Sec. III-D): mu and m get
+// Gaussian noise around the source values (clamped to their ranges) and the
+// perturbation force is drawn afresh, the normals by Box-Muller from the
+// Philox counters (j, window, 1, 0) and (j, window, 2, 0).  out: m, mu, f(3).
+__device__ __forceinline__ void explore(const ResampleArgs &R, uint32_t j, uint32_t window_idx, float m_src,
+                                        float mu_src, float *out)
+{
+    const uint32_t key0 = (uint32_t)(R.seed & 0xffffffffu), key1 = (uint32_t)(R.seed >> 32);
+    uint32_t w1[4], w2[4];
+    philox4x32_10(j, window_idx, 1u, 0u, key0, key1, w1);
+    philox4x32_10(j, window_idx, 2u, 0u, key0, key1, w2);
+    float n0, n1, n2, n3, n4, n5;
+    box_muller(w1[0], w1[1], n0, n1);
+    box_muller(w1[2], w1[3], n2, n3);
+    box_muller(w2[0], w2[1], n4, n5);
+    float mu = mu_src + R.sigma_mu * n0;
+    float ms = m_src + R.sigma_m * n1;
+    out[1] = fminf(fmaxf(mu, R.mu_lo), R.mu_hi);
+    out[0] = fminf(fmaxf(ms, R.m_lo), R.m_hi);
+    out[2] = R.sigma_f * n2;
+    out[3] = R.sigma_f * n3;
+    out[4] = R.sigma_f * n4;
+}
+
 }  // namespace pt

@@ -264,36 +264,6 @@ __global__ void k_argmin(const int32_t *__restrict__ group_start, const float *_
 // ---------------------------------------------------------------------
 // population-based resampling
 // ---------------------------------------------------------------------
-// Philox4x32 with 10 rounds (Salmon et al., SC'11): per round the words 0
-// and 2 are multiplied by the two round multipliers, the high halves are
-// mixed with the other two words and the round key, and the key is bumped
-// by the two Weyl increments.
-__device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
-                                              uint32_t k1, uint32_t *out)
-{
-#pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
-        uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
-        uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
-        c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
-        k0 += 0x9E3779B9u;
-        k1 += 0xBB67AE85u;
-    }
-    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
-}
-
-__device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, float &n0, float &n1)
-{
-    // uniforms (w + 1/2) 2^-32 in (0, 1), formed in double to keep every bit
-    double u = ((double)a + 0.5) * 2.3283064365386963e-10;
-    double v = ((double)b + 0.5) * 2.3283064365386963e-10;
-    float rad = sqrtf(-2.f * (float)log(u));
-    float ang = (float)(6.283185307179586 * v);
-    n0 = rad * cosf(ang);
-    n1 = rad * sinf(ang);
-}
-
 // one block per group; sorts by (cost, index), then copies and perturbs
 __global__ __launch_bounds__(1024) void k_resample(Consts P, ResampleArgs R, const int32_t *__restrict__ group_start,
                                                    uint32_t window_idx, float *__restrict__ cost_sum,
@@ -317,7 +287,7 @@ __global__ __launch_bounds__(1024) void k_resample(Consts P, ResampleArgs R, con
             if (parent) parent[j] = -1;
             continue;
         }
-        uint32_t w[4], w1[4], w2[4];
+        uint32_t w[4];
         philox4x32_10((uint32_t)j, window_idx, 0u, 0u, key0, key1, w);
         const int prank = (int)(((uint64_t)w[0] * (uint64_t)kb) >> 32);
         const int p = lo + order[prank];
@@ -326,19 +296,9 @@ __global__ __launch_bounds__(1024) void k_resample(Consts P, ResampleArgs R, con
         const float4 *src = reinterpret_cast<const float4 *>(warm + (size_t)p * P.C_max * WARM_STRIDE);
         float4 *dst = reinterpret_cast<float4 *>(warm + (size_t)j * P.C_max * WARM_STRIDE);
         for (int c = 0; c < P.C_max; ++c) dst[c] = src[c];
-        philox4x32_10((uint32_t)j, window_idx, 1u, 0u, key0, key1, w1);
-        philox4x32_10((uint32_t)j, window_idx, 2u, 0u, key0, key1, w2);
-        float n0, n1, n2, n3, n4, n5;
-        box_muller(w1[0], w1[1], n0, n1);
-        box_muller(w1[2], w1[3], n2, n3);
-        box_muller(w2[0], w2[1], n4, n5);
-        float mu = params[1 * (size_t)K + p] + R.sigma_mu * n0;
-        float ms = params[0 * (size_t)K + p] + R.sigma_m * n1;
-        params[1 * (size_t)K + j] = fminf(fmaxf(mu, R.mu_lo), R.mu_hi);
-        params[0 * (size_t)K + j] = fminf(fmaxf(ms, R.m_lo), R.m_hi);
-        params[2 * (size_t)K + j] = R.sigma_f * n2;
-        params[3 * (size_t)K + j] = R.sigma_f * n3;
-        params[4 * (size_t)K + j] = R.sigma_f * n4;
+        float e[5];
+        explore(R, (uint32_t)j, window_idx, params[0 * (size_t)K + p], params[1 * (size_t)K + p], e);
+        for (int c = 0; c < 5; ++c) params[(size_t)c * K + j] = e[c];
     }
     __syncthreads();
     for (int i = threadIdx.x; i < n; i += blockDim.x) cost_sum[lo + i] = 0.f;
@@ -524,7 +484,7 @@ hipError_t set_lds_limits(size_t bytes)
                         reinterpret_cast<const void *>(k_step<float>), reinterpret_cast<const void *>(k_step<double>),
                         reinterpret_cast<const void *>(k_resample)};
     for (const void *f : fs) {
-        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+        hipError_t e = set_dynamic_lds_limit(f, bytes);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

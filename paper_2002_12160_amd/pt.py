@@ -5,7 +5,8 @@ device memory (tensors) and the streams.  Importing this module fails loudly
 when the library has not been built -- there is no fallback.
 
 Names follow the C ABI: ``pt_create_batch``, ``pt_step``, ``pt_observe``,
-``pt_cost``, ``pt_resample``, ``pt_run_window``, ``pt_autotune``,
+``pt_cost``, ``pt_resample`` (and its weighted variants ``pt_resample_wrs``,
+``pt_resample_reps``), ``pt_run_window``, ``pt_autotune``,
 ``pt_window_grad``, ``pt_refine_elites``, ``pt_read_stats``; :class:`Batch`
 bundles a handle with its tensors and :class:`WindowFn` exposes the window
 cost and its adjoint to ``torch.autograd``.
@@ -67,6 +68,8 @@ _lib.pt_step.argtypes = [_vp, _vp, _vp, _vp]
 _lib.pt_observe.argtypes = [_vp, _vp, _vp]
 _lib.pt_cost.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp]
 _lib.pt_resample.argtypes = [_vp, _vp, C.c_uint32, _vp, _vp]
+_lib.pt_resample_wrs.argtypes = [_vp, _vp, C.c_int32, C.c_uint32, C.c_float, _vp, _vp, _vp]
+_lib.pt_resample_reps.argtypes = [_vp, _vp, C.c_int32, C.c_uint32, C.c_float, _vp, _vp, _vp, _vp]
 _lib.pt_run_window.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, C.c_int32, _vp]
 _lib.pt_autotune.argtypes = [_vp, _vp, _vp, C.POINTER(C.c_int32), _vp]
 _lib.pt_read_stats.argtypes = [_vp, C.POINTER(C.c_int64), _vp]
@@ -76,7 +79,7 @@ _lib.pt_refine_elites.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp, C.c_int32, 
 _lib.pt_elite_count.argtypes = [_vp]
 _lib.pt_elite_count.restype = C.c_int32
 for _f in ("pt_create_batch", "pt_destroy_batch", "pt_step", "pt_observe", "pt_cost", "pt_resample",
-           "pt_run_window", "pt_autotune", "pt_read_stats", "pt_set_tuning", "pt_window_grad",
+           "pt_resample_wrs", "pt_resample_reps", "pt_run_window", "pt_autotune", "pt_read_stats", "pt_set_tuning", "pt_window_grad",
            "pt_refine_elites"):
     getattr(_lib, _f).restype = C.c_int
 
@@ -127,6 +130,16 @@ def pt_cost(h, obs, obs_gt, cost_sum, best=None, stream=None):
 
 def pt_resample(h, cost_sum, window_idx, parent=None, stream=None):
     _check(_lib.pt_resample(h, _ptr(cost_sum), int(window_idx), _ptr(parent), _stream(stream)), "pt_resample")
+
+
+def pt_resample_wrs(h, cost_sum, n_steps, window_idx, lam, parent, weights=None, stream=None):
+    _check(_lib.pt_resample_wrs(h, _ptr(cost_sum), int(n_steps), int(window_idx), float(lam), _ptr(parent),
+                                _ptr(weights), _stream(stream)), "pt_resample_wrs")
+
+
+def pt_resample_reps(h, cost_sum, n_steps, window_idx, eps, parent, weights=None, eta=None, stream=None):
+    _check(_lib.pt_resample_reps(h, _ptr(cost_sum), int(n_steps), int(window_idx), float(eps), _ptr(parent),
+                                 _ptr(weights), _ptr(eta), _stream(stream)), "pt_resample_reps")
 
 
 def pt_run_window(h, u_win, obs_gt_win, cost_sum, best=None, obs_out=None, graph=True, stream=None):
@@ -290,6 +303,12 @@ class Batch:
 
     def resample(self, cost_sum, window_idx, parent=None, stream=None):
         pt_resample(self.handle, cost_sum, window_idx, parent, stream)
+
+    def resample_wrs(self, cost_sum, n_steps, window_idx, lam, parent, weights=None, stream=None):
+        pt_resample_wrs(self.handle, cost_sum, n_steps, window_idx, lam, parent, weights, stream)
+
+    def resample_reps(self, cost_sum, n_steps, window_idx, eps, parent, weights=None, eta=None, stream=None):
+        pt_resample_reps(self.handle, cost_sum, n_steps, window_idx, eps, parent, weights, eta, stream)
 
     def run_window(self, u_win, obs_gt_win, cost_sum, best=None, obs_out=None, graph=True, stream=None):
         pt_run_window(self.handle, u_win, obs_gt_win, cost_sum, best, obs_out, graph, stream)

@@ -29,7 +29,7 @@ def test_header_declares_the_boundary():
     syms = declared_symbols()
     for name in ("pt_create_batch", "pt_destroy_batch", "pt_step", "pt_observe", "pt_cost", "pt_resample",
                  "pt_run_window", "pt_autotune", "pt_read_stats", "pt_set_tuning", "pt_last_error",
-                 "pt_window_grad", "pt_refine_elites", "pt_elite_count"):
+                 "pt_window_grad", "pt_refine_elites", "pt_elite_count", "pt_resample_wrs", "pt_resample_reps"):
         assert name in syms
 
 
@@ -40,7 +40,7 @@ def test_library_exports_every_declared_symbol(lib):
 
 def test_no_oracle_symbols_in_the_library(lib):
     # the product library shares no code with the test oracle
-    for name in ("or_env_step", "or_hand_fk", "or_philox4x32_10", "or_resample_pbo"):
+    for name in ("or_env_step", "or_hand_fk", "or_philox4x32_10", "or_resample_pbo", "or_resample_apply"):
         assert not hasattr(lib, name)
 
 
@@ -121,3 +121,11 @@ def test_gradient_calls_reject_a_null_batch(lib):
     assert lib.pt_refine_elites(None, None, None, None, None, None, None, 3, C.c_float(0.5), None, None, None,
                                 None) == 1
     assert lib.pt_elite_count(None) == -1
+
+
+def test_weighted_resamplers_reject_bad_arguments(lib):
+    # a NULL batch is rejected before any device call
+    pt = _desc_module()
+    f, g = pt._lib.pt_resample_wrs, pt._lib.pt_resample_reps
+    assert f(None, None, 10, 0, C.c_float(1.0), None, None, None) == 1
+    assert g(None, None, 10, 0, C.c_float(0.5), None, None, None, None) == 1
