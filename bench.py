@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--realtime-windows", type=int, default=30,
                     help="timed windows of the 16384-simulation real-time workload (0 skips it)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-optimizers", action="store_true",
+                    help="skip the WRS / REPS / identity comparison on the real-time workload")
     ap.add_argument("--cpu-sample-steps", type=int, default=300)
     ap.add_argument("--profile", action="store_true", help="short run for the profiler (no CPU baseline)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -209,44 +211,83 @@ def add_distance(points, pa, pb):
     return float(np.linalg.norm(a - b, axis=1).mean())
 
 
-def realtime_run(pt, S, dev, solve_precision, n_win, n_warm=2):
-    """The real-time workload: 16384 simulations in 16 groups (one
-    superquadric object each), batched windows with elite refinement before
-    every resampling.  Reports env-steps/s, the per-step latency (window time
-    / T) against the 33 ms budget of 30 Hz, and the tracking error: the mean
-    distance between the object's points at the best simulation's pose and
-    at the observed object's pose, after every window, over all groups."""
-    import numpy as np
+# optimiser hyperparameters of the comparison leg (the paper gives no values):
+# WRS temperature per unit of window-mean cost, REPS KL bound
+WRS_LAMBDA = 1.0
+REPS_EPS = 1.0
+
+
+def realtime_setup(pt, S, dev, solve_precision, n_total):
+    """Scene, observed forces and observed poses of the real-time workload,
+    shared by the optimisers compared on it."""
     import torch
     cfg = S.CONFIGS["realtime16384"]
     T = cfg.T
-    n_total = n_warm + n_win
     sc = S.make_scene(cfg, steps=(n_total + 1) * T + 1)
-    K, G, L = sc.K, sc.G, sc.L
     gts, hposes = observed_forces(pt, sc, dev, solve_precision, n_total * T, pose_every=T)
     u_all = torch.as_tensor(sc.u.astype("float32"), device=dev)
-    b = pt.Batch.from_scene(sc, solve_precision=solve_precision, window_checkpoints=True)
+    return {"cfg": cfg, "sc": sc, "gts": gts, "hposes": hposes, "u_all": u_all}
+
+
+def realtime_run(pt, S, dev, solve_precision, n_win, n_warm=2, optimizer="pbo", setup=None):
+    """The real-time workload: 16384 simulations in 16 groups (one
+    superquadric object each), batched windows; with optimizer "pbo", "wrs"
+    or "reps" the elites are refined before every resampling by that
+    optimiser, with "eye" the population is never refined nor resampled.
+    Reports env-steps/s, the per-step latency (window time / T) against the
+    33 ms budget of 30 Hz, the resampler's time per window and the tracking
+    error: the mean distance between the object's points at the estimated
+    pose and at the observed object's pose, after every window, over all
+    groups -- the estimate being the lowest-cost simulation (for "eye" also
+    the first simulation of each group alone, which is the open-loop
+    baseline: without resampling each simulation evolves on its own)."""
+    import numpy as np
+    import torch
+    n_total = n_warm + n_win
+    if setup is None:
+        setup = realtime_setup(pt, S, dev, solve_precision, n_total)
+    cfg, sc, gts, hposes, u_all = setup["cfg"], setup["sc"], setup["gts"], setup["hposes"], setup["u_all"]
+    T = cfg.T
+    K, G, L = sc.K, sc.G, sc.L
+    adapt = optimizer != "eye"
+    b = pt.Batch.from_scene(sc, solve_precision=solve_precision, window_checkpoints=adapt)
     u_win = torch.empty((T + 1, sc.D), device=dev)
     gt_win = torch.empty((T, 4, L, G), device=dev)
     cost = torch.zeros(K, device=dev)
     best = torch.zeros(G, dtype=torch.int32, device=dev)
     parent = torch.zeros(K, dtype=torch.int32, device=dev)
+    first = torch.as_tensor(np.asarray(sc.group_start[:-1], dtype=np.int64), device=dev)
     snap = b.snapshot()
     est = torch.empty((n_total, 13, G), device=dev)
+    est_olp = torch.empty((n_total, 13, G), device=dev)
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n_total)]
+    ev_rs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n_total)]
 
     def window(w):
         t0_ = w * T
         ev[w][0].record()
         u_win.copy_(u_all[t0_ - 1: t0_ + T] if t0_ > 0 else torch.cat([u_all[:1], u_all[:T]], 0))
         gt_win.copy_(gts[t0_: t0_ + T])
-        snap[0].copy_(b.state)
-        snap[1].copy_(b.params)
-        snap[2].copy_(b.warm)
+        if adapt:
+            snap[0].copy_(b.state)
+            snap[1].copy_(b.params)
+            snap[2].copy_(b.warm)
         b.run_window(u_win, gt_win, cost, best, None, graph=True)
-        b.refine_elites(u_win, gt_win, cost, snap, steps=3, step=0.5, best=best)
+        if adapt:
+            b.refine_elites(u_win, gt_win, cost, snap, steps=3, step=0.5, best=best)
         torch.index_select(b.state, 1, best, out=est[w])
-        b.resample(cost, w, parent)
+        if not adapt:
+            torch.index_select(b.state, 1, first, out=est_olp[w])
+        ev_rs[w][0].record()
+        if optimizer == "pbo":
+            b.resample(cost, w, parent)
+        elif optimizer == "wrs":
+            b.resample_wrs(cost, T, w, WRS_LAMBDA, parent)
+        elif optimizer == "reps":
+            b.resample_reps(cost, T, w, REPS_EPS, parent)
+        else:
+            cost.zero_()
+        ev_rs[w][1].record()
         ev[w][1].record()
 
     u_win.copy_(torch.cat([u_all[:1], u_all[:T]], 0))
@@ -262,24 +303,33 @@ def realtime_run(pt, S, dev, solve_precision, n_win, n_warm=2):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     step_ms = np.array([ev[w][0].elapsed_time(ev[w][1]) / T for w in range(n_warm, n_total)])
-    est_h, hp = est.cpu().numpy(), hposes.cpu().numpy()
-    errs = []
-    for w in range(n_warm, n_total):
-        for g in range(G):
-            pts = sc.spheres[sc.hidden_type[g], :sc.n_spheres[sc.hidden_type[g]], :3]
-            errs.append(add_distance(pts, est_h[w, :7, g], hp[w, :7, g]))
+    rs_ms = np.array([ev_rs[w][0].elapsed_time(ev_rs[w][1]) for w in range(n_warm, n_total)])
+    hp = setup["hposes"].cpu().numpy()
+
+    def tracking(e):
+        errs = []
+        for w in range(n_warm, n_total):
+            for g in range(G):
+                pts = sc.spheres[sc.hidden_type[g], :sc.n_spheres[sc.hidden_type[g]], :3]
+                errs.append(add_distance(pts, e[w, :7, g], hp[w, :7, g]))
+        return {"mean": round(1e3 * float(np.mean(errs)), 3), "p90": round(1e3 * float(np.quantile(errs, 0.9)), 3)}
+
     b.close()
-    return {"workload": f"{cfg.name}: {K} simulations in {G} groups (one {int(sc.n_spheres[0])}-sphere superquadric "
-                        f"object each) + {G} observed, {L} capsule links, C_max={cfg.C_max}, "
-                        f"{cfg.newton_iters} Newton iterations, {T}-step windows, elite refinement (3 steps) and "
-                        f"resampling after every window, {n_win} timed windows",
-            "value": round(K * T * n_win / wall, 1), "unit": "env-steps/s",
-            "per_step_ms": {"p50": round(float(np.median(step_ms)), 3),
-                            "p99": round(float(np.quantile(step_ms, 0.99)), 3)},
-            "budget_30hz_met": bool(np.quantile(step_ms, 0.99) < 1000.0 / 30.0),
-            "tracking_error_mm": {"mean": round(1e3 * float(np.mean(errs)), 3),
-                                  "p90": round(1e3 * float(np.quantile(errs, 0.9)), 3)},
-            "waves_per_workgroup": tuned}
+    out = {"value": round(K * T * n_win / wall, 1), "unit": "env-steps/s",
+           "per_step_ms": {"p50": round(float(np.median(step_ms)), 3),
+                           "p99": round(float(np.quantile(step_ms, 0.99)), 3)},
+           "budget_30hz_met": bool(np.quantile(step_ms, 0.99) < 1000.0 / 30.0),
+           "resample_ms_per_window": round(float(np.median(rs_ms)), 4),
+           "tracking_error_mm": tracking(est.cpu().numpy()),
+           "waves_per_workgroup": tuned}
+    if not adapt:
+        out["open_loop_tracking_error_mm"] = tracking(est_olp.cpu().numpy())
+    if optimizer == "pbo":
+        out = {"workload": f"{cfg.name}: {K} simulations in {G} groups (one {int(sc.n_spheres[0])}-sphere "
+                           f"superquadric object each) + {G} observed, {L} capsule links, C_max={cfg.C_max}, "
+                           f"{cfg.newton_iters} Newton iterations, {T}-step windows, elite refinement (3 steps) and "
+                           f"resampling after every window, {n_win} timed windows", **out}
+    return out
 
 
 def main():
@@ -422,8 +472,18 @@ def main():
 
     # ---------------- real-time workload (16384 simulations) -------------
     if not args.no_batched and not args.no_adjoint and args.realtime_windows > 0:
-        result["realtime16384"] = realtime_run(pt, S, dev, args.solve_precision,
-                                               args.realtime_windows if not args.profile else 3)
+        n_rt = args.realtime_windows if not args.profile else 3
+        rt_setup = realtime_setup(pt, S, dev, args.solve_precision, n_rt + 2)
+        result["realtime16384"] = realtime_run(pt, S, dev, args.solve_precision, n_rt, setup=rt_setup)
+        if not args.no_optimizers:
+            # the paper's other optimisers and its identity baseline on the
+            # same workload (Sec. III-D, Sec. IV), same windows and refinement
+            result["realtime16384"]["optimizers"] = {
+                "wrs": {"lambda": WRS_LAMBDA,
+                        **realtime_run(pt, S, dev, args.solve_precision, n_rt, optimizer="wrs", setup=rt_setup)},
+                "reps": {"epsilon": REPS_EPS,
+                         **realtime_run(pt, S, dev, args.solve_precision, n_rt, optimizer="reps", setup=rt_setup)},
+                "eye": realtime_run(pt, S, dev, args.solve_precision, n_rt, optimizer="eye", setup=rt_setup)}
 
     # ---------------- CPU baseline: the FP64 oracle ----------------------
     if not args.no_cpu_baseline and not args.profile:
