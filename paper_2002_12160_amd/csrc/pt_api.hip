@@ -62,7 +62,6 @@ struct pt_batch_s {
     int32_t *d_order = nullptr, *d_queue = nullptr;
     int64_t *d_stats = nullptr;
     // scratch
-    float *d_seg = nullptr;      // [L][16]
     float *d_seg_win = nullptr;  // [T][L][16]
     float *d_contacts = nullptr; // [K][C_max][4]
     float *d_seg_grad = nullptr; // [T][L][16] for the gradient and refinement calls
@@ -214,8 +213,10 @@ pt_status pt_create_batch(const pt_batch_desc *d, pt_batch *out)
     // rows of the solve's cross-contact sums (lane_span(C_max) rows of 50
     // doubles)
     const int red_rows = d->C_max <= 16 ? 16 : (d->C_max <= 32 ? 32 : 64);
-    const int max_cand = std::max(round_up(d->S_max * (d->L + 1) + 8, 64), round_up(red_rows * 50, 64));
-    const size_t wave_lds = pt::wave_lds_bytes(max_cand);
+    // ... and the step's hand kinematics, which use the same LDS first
+    const int max_cand = std::max({round_up(d->S_max * (d->L + 1) + 8, 64), round_up(red_rows * 50, 64),
+                                   round_up((int)((hand_fk_lds_bytes(d->L, d->D) + 7) / 8), 64)});
+    const size_t wave_lds = pt::wave_lds_bytes(max_cand, d->L);
     if (wave_lds > 160 * 1024)
         return fail(PT_E_UNSUPPORTED, "S_max*(L+1) = %d candidates need %zu B of LDS per simulation (> 160 KiB)",
                     d->S_max * (d->L + 1), wave_lds);
@@ -277,7 +278,6 @@ pt_status pt_create_batch(const pt_batch_desc *d, pt_batch *out)
     HIP_TRY_C(hipMalloc(&b->d_order, sizeof(int32_t) * K));
     HIP_TRY_C(hipMalloc(&b->d_queue, sizeof(int32_t) * 4));
     HIP_TRY_C(hipMalloc(&b->d_stats, sizeof(int64_t) * 4));
-    HIP_TRY_C(hipMalloc(&b->d_seg, sizeof(float) * d->L * pt::SEG_STRIDE));
     HIP_TRY_C(hipMalloc(&b->d_seg_win, sizeof(float) * (size_t)d->T * d->L * pt::SEG_STRIDE));
     HIP_TRY_C(hipMalloc(&b->d_contacts, sizeof(float) * K * d->C_max * 4));
     HIP_TRY_C(hipMalloc(&b->d_seg_grad, sizeof(float) * (size_t)d->T * d->L * pt::SEG_STRIDE));
@@ -317,7 +317,7 @@ pt_status pt_destroy_batch(pt_batch b)
     b->drop_graphs();
     if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
     void *ptrs[] = {b->d_hand, b->d_spheres, b->d_inv, b->d_nsph, b->d_type, b->d_group_of, b->d_group_start,
-                    b->d_order, b->d_queue, b->d_stats, b->d_seg, b->d_seg_win, b->d_contacts,
+                    b->d_order, b->d_queue, b->d_stats, b->d_seg_win, b->d_contacts,
                     b->d_seg_grad, b->d_tune, b->d_ckpt, b->d_wckpt, b->d_elite, b->d_ref, b->d_snap};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -342,8 +342,7 @@ pt_status pt_step(pt_batch b, const float *u_prev, const float *u, pt_stream s)
     if (!b) return fail(PT_E_ARG, "batch is NULL");
     if (b->P.D > 0 && (!u_prev || !u)) return fail(PT_E_ARG, "u_prev/u is NULL");
     hipStream_t st = (hipStream_t)s;
-    HIP_TRY(launch_hand_fk(b->d_hand, b->P.L, b->P.dt, u_prev, u, 0, 1, b->d_seg, st));
-    HIP_TRY(launch_step(b->P, tables_of(b), b->d_seg, b->state, b->params, b->warm, b->d_contacts, b->d_stats,
+    HIP_TRY(launch_step(b->P, tables_of(b), u_prev, u, b->state, b->params, b->warm, b->d_contacts, b->d_stats,
                         b->step_wpb, st));
     return PT_OK;
 }
@@ -413,11 +412,11 @@ static pt_status enqueue_window(pt_batch b, const float *u_win, const float *obs
 {
     const Consts &P = b->P;
     int bpc = 0;
-    HIP_TRY(window_occupancy(wpb, P.max_cand, P.solve_fp64 != 0, &bpc));
+    HIP_TRY(window_occupancy(wpb, P.max_cand, P.L, P.solve_fp64 != 0, &bpc));
     if (bpc < 1) return fail(PT_E_UNSUPPORTED, "persistent kernel does not fit with %d waves per workgroup", wpb);
     int want = (P.K + wpb - 1) / wpb;
     int blocks = std::min(want, bpc * b->num_cu);
-    HIP_TRY(launch_hand_fk(b->d_hand, P.L, P.dt, u_win, u_win + P.D, P.D, P.T, b->d_seg_win, st));
+    HIP_TRY(launch_hand_fk(b->d_hand, P.L, P.D, P.dt, u_win, u_win + P.D, P.D, P.T, b->d_seg_win, st));
     // the window kernel's last workgroup puts the work queue back to 0 and,
     // for populations up to FUSED_ARGMIN_MAX, ranks the groups
     const bool fused = best && P.K <= pt::FUSED_ARGMIN_MAX;
@@ -492,7 +491,7 @@ pt_status pt_autotune(pt_batch b, const float *u_win, const float *obs_gt_win, i
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
-    const size_t wave_lds = pt::wave_lds_bytes(P.max_cand);
+    const size_t wave_lds = pt::wave_lds_bytes(P.max_cand, P.L);
     int best_wpb = b->wpb;
     float best_ms = 1e30f;
     pt_status rc = PT_OK;
@@ -540,7 +539,7 @@ pt_status pt_set_tuning(pt_batch b, int32_t wpb)
 {
     if (!b) return fail(PT_E_ARG, "batch is NULL");
     if (wpb != 1 && wpb != 2 && wpb != 4 && wpb != 8) return fail(PT_E_ARG, "waves per workgroup must be 1, 2, 4 or 8");
-    if ((size_t)wpb * pt::wave_lds_bytes(b->P.max_cand) > 160 * 1024)
+    if ((size_t)wpb * pt::wave_lds_bytes(b->P.max_cand, b->P.L) > 160 * 1024)
         return fail(PT_E_UNSUPPORTED, "%d simulations per workgroup exceed the LDS", wpb);
     if (wpb > max_wpb(b->P))
         return fail(PT_E_UNSUPPORTED, "at most %d simulations per workgroup with this solve precision", max_wpb(b->P));
@@ -560,7 +559,7 @@ pt_status pt_window_grad(pt_batch b, const float *u_win, const float *obs_gt_win
     hipStream_t st = (hipStream_t)s;
     const Consts &P = b->P;
     const Tables tb = tables_of(b);
-    HIP_TRY(launch_hand_fk(b->d_hand, P.L, P.dt, u_win, u_win + P.D, P.D, P.T, b->d_seg_grad, st));
+    HIP_TRY(launch_hand_fk(b->d_hand, P.L, P.D, P.dt, u_win, u_win + P.D, P.D, P.T, b->d_seg_grad, st));
     if (!grad) {
         HIP_TRY(launch_window_fwd(P, tb, b->d_seg_grad, n, 0, n, env, start, warm0, obs_gt_win, cost, end_state,
                                   end_warm, nullptr, st));
@@ -605,7 +604,7 @@ pt_status pt_refine_elites(pt_batch b, const float *u_win, const float *obs_gt_w
     if (elite_out)
         HIP_TRY(hipMemcpyAsync(elite_out, b->d_elite, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, st));
     if (steps > 0) {
-        HIP_TRY(launch_hand_fk(b->d_hand, P.L, P.dt, u_win, u_win + P.D, P.D, P.T, b->d_seg_grad, st));
+        HIP_TRY(launch_hand_fk(b->d_hand, P.L, P.D, P.dt, u_win, u_win + P.D, P.D, P.T, b->d_seg_grad, st));
         // the first gradient: from the checkpoints the population's window
         // recorded (window_checkpoints) or from a replay of the window
         const bool from_window = b->d_wckpt != nullptr;

@@ -49,6 +49,7 @@ struct WaveLds {
     int *sel;        // [64]
     int *wkey;       // [64]
     float *wr;       // [64*3]
+    float *seg;      // [L][16] hand segment records of the step (after the [64][4] contact stage)
 };
 
 __device__ __forceinline__ int lane_id() { return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u)); }

@@ -56,7 +56,7 @@ __global__ __launch_bounds__(WAVE) void k_window_fwd(Consts P, Tables tb, const 
         if (lane == 0) cost_out[i] = __int_as_float(0x7fc00000);
         return;
     }
-    WaveLds lds = carve_lds(smem, 0, P.max_cand);
+    WaveLds lds = carve_lds(smem, 0, P.max_cand, P.L);
     float *stage = contact_stage(lds);
     const int type = tb.env_type[e];
     const int g = tb.group_of[e];
@@ -134,7 +134,7 @@ __global__ __launch_bounds__(WAVE) void k_window_bwd(Consts P, Tables tb, const 
             for (int r = 0; r < XI_ROWS; ++r) grad[(size_t)r * n + i] = 0.f;
         return;
     }
-    WaveLds lds = carve_lds(smem, 0, P.max_cand);
+    WaveLds lds = carve_lds(smem, 0, P.max_cand, P.L);
     float *stage = contact_stage(lds);
     const int type = tb.env_type[e];
     const int g = tb.group_of[e];
@@ -297,7 +297,7 @@ hipError_t launch_window_fwd(const Consts &P, const Tables &tb, const float *seg
                              float *cost, float *end_state, float *end_warm, float *ckpt, hipStream_t s)
 {
     if (count <= 0) return hipSuccess;
-    size_t lds = wave_lds_bytes(P.max_cand);
+    size_t lds = wave_lds_bytes(P.max_cand, P.L);
     if (P.solve_fp64)
         hipLaunchKernelGGL(k_window_fwd<double>, dim3(count), dim3(WAVE), lds, s, P, tb, seg_win, n, i0, count, env,
                            xi, warm0, obs_gt_win, cost, end_state, end_warm, ckpt);
@@ -312,7 +312,7 @@ hipError_t launch_window_bwd(const Consts &P, const Tables &tb, const float *seg
                              bool ckpt_by_env, const int32_t *flag, float *grad, hipStream_t s)
 {
     if (count <= 0) return hipSuccess;
-    size_t lds = wave_lds_bytes(P.max_cand);
+    size_t lds = wave_lds_bytes(P.max_cand, P.L);
     const int by_env = ckpt_by_env ? 1 : 0;
     if (P.solve_fp64)
         hipLaunchKernelGGL(k_window_bwd<double>, dim3(count), dim3(WAVE), lds, s, P, tb, seg_win, n, i0, count, env,

@@ -54,10 +54,11 @@ __host__ __device__ constexpr size_t resample_lds_bytes(int max_group)
 }
 
 // bytes of LDS per wavefront: candidate (d, key) list, selected keys,
-// previous warm keys and impulses, contact staging for the observation
-__host__ __device__ constexpr size_t wave_lds_bytes(int max_cand)
+// previous warm keys and impulses, contact staging for the observation, the
+// step's L hand segment records
+__host__ __device__ constexpr size_t wave_lds_bytes(int max_cand, int L)
 {
-    return (size_t)8 * max_cand + 4 * 64 + 4 * 64 + 12 * 64 + 16 * 64;
+    return (size_t)8 * max_cand + 4 * 64 + 4 * 64 + 12 * 64 + 16 * 64 + (size_t)64 * L;
 }
 
 }  // namespace pt
@@ -72,10 +73,12 @@ inline hipError_t set_dynamic_lds_limit(const void *f, size_t bytes)
     return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(bytes - a.sharedSizeBytes));
 }
 
-hipError_t launch_hand_fk(const float *hand, int L, float dt, const float *u_prev, const float *u, int stride,
-                          int nsteps, float *seg_out, hipStream_t s);
-hipError_t launch_step(const pt::Consts &P, const pt::Tables &tb, const float *seg, float *state, float *params,
-                       float *warm, float *contacts, int64_t *stats, int waves_per_block, hipStream_t s);
+hipError_t launch_hand_fk(const float *hand, int L, int D, float dt, const float *u_prev, const float *u,
+                          int stride, int nsteps, float *seg_out, hipStream_t s);
+hipError_t launch_step(const pt::Consts &P, const pt::Tables &tb, const float *u_prev, const float *u, float *state,
+                       float *params, float *warm, float *contacts, int64_t *stats, int waves_per_block,
+                       hipStream_t s);
+size_t hand_fk_lds_bytes(int L, int D);
 hipError_t launch_observe(const pt::Consts &P, const float *contacts, float *obs, hipStream_t s);
 hipError_t launch_cost(const pt::Consts &P, const int32_t *group_of, const int32_t *group_start, const float *obs,
                        const float *obs_gt, float *cost_sum, int32_t *best, int32_t *done, hipStream_t s);
@@ -87,7 +90,7 @@ hipError_t launch_window(const pt::Consts &P, const pt::Tables &tb, const float 
                          float *warm, const float *obs_gt_win, float *cost_sum, float *obs_out,
                          const int32_t *env_order, int32_t *queue, int64_t *stats, int waves_per_block, int blocks,
                          float *ckpt, const int32_t *group_start, int32_t *best, hipStream_t s);
-hipError_t window_occupancy(int waves_per_block, int max_cand, bool fp64, int *blocks_per_cu);
+hipError_t window_occupancy(int waves_per_block, int max_cand, int L, bool fp64, int *blocks_per_cu);
 hipError_t set_lds_limits(size_t bytes);
 hipError_t set_grad_lds_limits(size_t bytes);
 size_t ckpt_floats(const pt::Consts &P, int n);

@@ -19,15 +19,16 @@ __device__ __forceinline__ int xcd_block(int b, int nb)
     return xcd * per + (xcd < rem ? xcd : rem) + idx;
 }
 
-__device__ __forceinline__ WaveLds carve_lds(char *base, int wave_in_block, int max_cand)
+__device__ __forceinline__ WaveLds carve_lds(char *base, int wave_in_block, int max_cand, int L)
 {
-    char *p = base + (size_t)wave_in_block * wave_lds_bytes(max_cand);
+    char *p = base + (size_t)wave_in_block * wave_lds_bytes(max_cand, L);
     WaveLds w;
     w.cand_d = reinterpret_cast<float *>(p);
     w.cand_k = reinterpret_cast<int *>(p + 4 * (size_t)max_cand);
     w.sel = reinterpret_cast<int *>(p + 8 * (size_t)max_cand);
     w.wkey = w.sel + WAVE;
     w.wr = reinterpret_cast<float *>(w.wkey + WAVE);
+    w.seg = w.wr + 3 * WAVE + 4 * WAVE;
     return w;
 }
 

@@ -20,7 +20,7 @@ namespace pt {
 // hand kinematics (double precision: it runs once per step for the whole
 // population, and the link velocities are differences of positions)
 // ---------------------------------------------------------------------
-__device__ void quat_to_mat_d(const double *q, double *R)
+__device__ __forceinline__ void quat_to_mat_d(const double *q, double *R)
 {
     double w = q[0], x = q[1], y = q[2], z = q[3];
     R[0] = 1 - 2 * (y * y + z * z); R[1] = 2 * (x * y - w * z);     R[2] = 2 * (x * z + w * y);
@@ -28,7 +28,7 @@ __device__ void quat_to_mat_d(const double *q, double *R)
     R[6] = 2 * (x * z - w * y);     R[7] = 2 * (y * z + w * x);     R[8] = 1 - 2 * (x * x + y * y);
 }
 
-__device__ void quat_mul_d(const double *a, const double *b, double *o)
+__device__ __forceinline__ void quat_mul_d(const double *a, const double *b, double *o)
 {
     double w = a[0] * b[0] - a[1] * b[1] - a[2] * b[2] - a[3] * b[3];
     double x = a[0] * b[1] + a[1] * b[0] + a[2] * b[3] - a[3] * b[2];
@@ -38,17 +38,19 @@ __device__ void quat_mul_d(const double *a, const double *b, double *o)
 }
 
 // joint rotation of link l for joint vector u: Rot(axis0, u[j0]) Rot(axis1, u[j1])
-__device__ void fk_joint(const float *__restrict__ h, const float *__restrict__ u, double *qj)
+__device__ __forceinline__ void fk_joint(const float *__restrict__ h, const float *__restrict__ u, double *qj)
 {
     int j0 = (int)h[1], j1 = (int)h[2];
     double q[4] = {1, 0, 0, 0};
     if (j0 >= 0) {
-        double th = u[j0], s = sin(0.5 * th);
-        q[0] = cos(0.5 * th); q[1] = s * h[3]; q[2] = s * h[4]; q[3] = s * h[5];
+        double s, c;
+        sincos(0.5 * (double)u[j0], &s, &c);
+        q[0] = c; q[1] = s * h[3]; q[2] = s * h[4]; q[3] = s * h[5];
     }
     if (j1 >= 0) {
-        double th = u[j1], s = sin(0.5 * th);
-        double r[4] = {cos(0.5 * th), s * h[6], s * h[7], s * h[8]}, t[4];
+        double s, c;
+        sincos(0.5 * (double)u[j1], &s, &c);
+        double r[4] = {c, s * h[6], s * h[7], s * h[8]}, t[4];
         quat_mul_d(q, r, t);
         for (int i = 0; i < 4; ++i) q[i] = t[i];
     }
@@ -57,7 +59,7 @@ __device__ void fk_joint(const float *__restrict__ h, const float *__restrict__ 
 
 // pose of link l in configuration w from its parent's (already computed):
 // origin, orientation and the segment [a, b] along the link's local +x axis
-__device__ void fk_link(const float *__restrict__ h, int parent, const double *qj, double *tq, double *tp,
+__device__ __forceinline__ void fk_link(const float *__restrict__ h, int parent, const double *qj, double *tq, double *tp,
                         double *seg_a, double *seg_b, int l)
 {
     double pq[4] = {1, 0, 0, 0}, pp[3] = {0, 0, 0};
@@ -88,68 +90,126 @@ __device__ void fk_link(const float *__restrict__ h, int parent, const double *q
     }
 }
 
-// grid: one block per step; u_prev/u for step t at u_prev + t*stride.  The
-// hand table is staged in LDS; joint rotations (the transcendental part) run
-// one thread per (configuration, link); the chains are composed level by
-// level of the link tree (links at one depth in parallel, both
-// configurations at once), so the serial depth is the longest chain.
-__global__ __launch_bounds__(128) void k_hand_fk(const float *__restrict__ hand, int L, float dt,
-                                                 const float *__restrict__ u_prev, const float *__restrict__ u,
-                                                 int stride, float *__restrict__ seg_out)
+// LDS of one evaluation of the hand kinematics: the link table, the link
+// depths, and for both configurations the joint rotations, link frames and
+// segment ends (double)
+struct FkLds {
+    float *hs;
+    int *depth;
+    float *su;       // [2][Ds] staged joint commands (u_prev, u), Ds = fk_staged_joints(D)
+    double *cf;      // per configuration w: cf + 17 L w = [qj 4L | tq 4L | tp 3L | sa 3L | sb 3L]
+    int L;
+    __device__ double *qj(int w) const { return cf + (size_t)17 * L * w; }
+    __device__ double *tq(int w) const { return cf + (size_t)17 * L * w + 4 * L; }
+    __device__ double *tp(int w) const { return cf + (size_t)17 * L * w + 8 * L; }
+    __device__ double *sa(int w) const { return cf + (size_t)17 * L * w + 11 * L; }
+    __device__ double *sb(int w) const { return cf + (size_t)17 * L * w + 14 * L; }
+};
+
+// joint commands staged in LDS (every command, read before the link table
+// says which ones are used); past 2 MAX_LINKS of them they are read from
+// global memory where needed
+__host__ __device__ constexpr int fk_staged_joints(int D) { return D <= 2 * MAX_LINKS ? D : 0; }
+
+__host__ __device__ constexpr size_t fk_head_bytes(int L, int D)
 {
-    __shared__ float hs[MAX_LINKS * HAND_STRIDE];
-    __shared__ int depth[MAX_LINKS];
-    __shared__ double qj[2][MAX_LINKS * 4], tq[2][MAX_LINKS * 4], tp[2][MAX_LINKS * 3], sa[2][MAX_LINKS * 3],
-        sb[2][MAX_LINKS * 3];
-    const int t = blockIdx.x;
-    for (int i = threadIdx.x; i < L * HAND_STRIDE; i += blockDim.x) hs[i] = hand[i];
-    __syncthreads();
-    for (int l = threadIdx.x; l < L; l += blockDim.x) {
+    return ((size_t)L * (4 * HAND_STRIDE + 4) + (size_t)8 * fk_staged_joints(D) + 7) & ~(size_t)7;
+}
+
+__host__ __device__ constexpr size_t fk_lds_bytes(int L, int D) { return fk_head_bytes(L, D) + (size_t)L * 2 * 17 * 8; }
+
+__device__ __forceinline__ FkLds carve_fk(char *p, int L, int D)
+{
+    FkLds s;
+    s.hs = reinterpret_cast<float *>(p);
+    s.depth = reinterpret_cast<int *>(s.hs + (size_t)L * HAND_STRIDE);
+    s.su = reinterpret_cast<float *>(s.depth + L);
+    s.cf = reinterpret_cast<double *>(p + fk_head_bytes(L, D));
+    s.L = L;
+    return s;
+}
+
+// Hand kinematics of one step by nt cooperating threads (tid in [0, nt)):
+// the link table staged in LDS, the joint rotations (the transcendental
+// part) one thread per (configuration, link), the chains composed level by
+// level of the link tree (links at one depth in parallel, both
+// configurations at once), then the segment record of every link: a,
+// b - a, the radius, 1/|b - a|^2 and the end-point velocities
+// (FK(u) - FK(u_prev)) / dt.  sync() orders the LDS between the stages.
+// Every value is computed by the same code whichever threads run it, so a
+// workgroup and a wavefront produce the same bits.
+template <typename Sync>
+__device__ __forceinline__ void hand_kinematics(const float *__restrict__ hand, int L, int D, float dt,
+                                                const float *__restrict__ u_prev, const float *__restrict__ u,
+                                                const FkLds &s, float *seg_out, int tid, int nt, Sync sync)
+{
+    const int Ds = fk_staged_joints(D);
+    for (int i = tid; i < L * HAND_STRIDE; i += nt) s.hs[i] = hand[i];
+    for (int i = tid; i < Ds; i += nt) {
+        s.su[i] = u_prev[i];
+        s.su[Ds + i] = u[i];
+    }
+    sync();
+    for (int l = tid; l < L; l += nt) {
         // parents precede children (checked at batch creation), so the walk ends
-        int d = 0, p = (int)hs[l * HAND_STRIDE];
+        int d = 0, p = (int)s.hs[l * HAND_STRIDE];
         while (p >= 0) {
             ++d;
-            p = (int)hs[p * HAND_STRIDE];
+            p = (int)s.hs[p * HAND_STRIDE];
         }
-        depth[l] = d;
+        s.depth[l] = d;
     }
-    for (int i = threadIdx.x; i < 2 * L; i += blockDim.x) {
+    for (int i = tid; i < 2 * L; i += nt) {
         int w = i / L, l = i - w * L;
-        const float *uu = (w == 0 ? u_prev : u) + (size_t)t * stride;
-        fk_joint(hs + l * HAND_STRIDE, uu, &qj[w][4 * l]);
+        const float *uw = Ds > 0 ? s.su + w * Ds : (w == 0 ? u_prev : u);
+        fk_joint(s.hs + l * HAND_STRIDE, uw, s.qj(w) + 4 * l);
     }
-    __syncthreads();
+    sync();
     int dmax = 0;
-    for (int l = 0; l < L; ++l) dmax = max(dmax, depth[l]);
+    for (int l = 0; l < L; ++l) dmax = max(dmax, s.depth[l]);
     for (int d = 0; d <= dmax; ++d) {
-        for (int i = threadIdx.x; i < 2 * L; i += blockDim.x) {
+        for (int i = tid; i < 2 * L; i += nt) {
             int w = i / L, l = i - w * L;
-            if (depth[l] == d)
-                fk_link(hs + l * HAND_STRIDE, (int)hs[l * HAND_STRIDE], qj[w], tq[w], tp[w], sa[w], sb[w], l);
+            if (s.depth[l] == d)
+                fk_link(s.hs + l * HAND_STRIDE, (int)s.hs[l * HAND_STRIDE], s.qj(w), s.tq(w), s.tp(w), s.sa(w),
+                        s.sb(w), l);
         }
-        __syncthreads();
+        sync();
     }
     const double idt = 1.0 / (double)dt;
-    for (int l = threadIdx.x; l < L; l += blockDim.x) {
-        float *s = seg_out + ((size_t)t * L + l) * SEG_STRIDE;
+    for (int l = tid; l < L; l += nt) {
+        float *o = seg_out + (size_t)l * SEG_STRIDE;
         float a0[3], ab[3];
+        const double *sa0 = s.sa(0), *sb0 = s.sb(0), *sa1 = s.sa(1), *sb1 = s.sb(1);
         for (int i = 0; i < 3; ++i) {
-            a0[i] = (float)sa[0][3 * l + i];
-            ab[i] = (float)(sb[0][3 * l + i] - sa[0][3 * l + i]);
+            a0[i] = (float)sa0[3 * l + i];
+            ab[i] = (float)(sb0[3 * l + i] - sa0[3 * l + i]);
         }
         float L2 = ab[0] * ab[0] + ab[1] * ab[1] + ab[2] * ab[2];
         float inv = sqrtf(L2) >= 1e-9f ? 1.f / L2 : 0.f;
         for (int i = 0; i < 3; ++i) {
-            s[i] = a0[i];
-            s[4 + i] = ab[i];
-            s[8 + i] = (float)((sa[1][3 * l + i] - sa[0][3 * l + i]) * idt);
-            s[12 + i] = (float)((sb[1][3 * l + i] - sb[0][3 * l + i]) * idt);
+            o[i] = a0[i];
+            o[4 + i] = ab[i];
+            o[8 + i] = (float)((sa1[3 * l + i] - sa0[3 * l + i]) * idt);
+            o[12 + i] = (float)((sb1[3 * l + i] - sb0[3 * l + i]) * idt);
         }
-        s[3] = hs[l * HAND_STRIDE + 17];
-        s[7] = inv;
-        s[11] = 0.f;
-        s[15] = 0.f;
+        o[3] = s.hs[l * HAND_STRIDE + 17];
+        o[7] = inv;
+        o[11] = 0.f;
+        o[15] = 0.f;
     }
+}
+
+// grid: one block per step; u_prev/u for step t at u_prev + t*stride
+__global__ __launch_bounds__(128) void k_hand_fk(const float *__restrict__ hand, int L, int D, float dt,
+                                                 const float *__restrict__ u_prev, const float *__restrict__ u,
+                                                 int stride, float *__restrict__ seg_out)
+{
+    __shared__ __align__(16) char fk[fk_lds_bytes(MAX_LINKS, 2 * MAX_LINKS)];
+    const int t = blockIdx.x;
+    const FkLds s = carve_fk(fk, L, D);
+    hand_kinematics(hand, L, D, dt, u_prev + (size_t)t * stride, u + (size_t)t * stride, s,
+                    seg_out + (size_t)t * L * SEG_STRIDE, threadIdx.x, blockDim.x, [] { __syncthreads(); });
 }
 
 
@@ -163,7 +223,8 @@ struct StepBounds {
 };
 
 template <typename SR>
-__global__ __launch_bounds__(StepBounds<SR>::threads) void k_step(Consts P, Tables tb, const float *__restrict__ seg,
+__global__ __launch_bounds__(StepBounds<SR>::threads) void k_step(Consts P, Tables tb,
+                                               const float *__restrict__ u_prev, const float *__restrict__ u,
                                                float *__restrict__ state, float *__restrict__ params,
                                                float *__restrict__ warm, float *__restrict__ contacts,
                                                int64_t *__restrict__ stats)
@@ -172,7 +233,7 @@ __global__ __launch_bounds__(StepBounds<SR>::threads) void k_step(Consts P, Tabl
     const int wib = threadIdx.x / WAVE;
     const int e = xcd_block(blockIdx.x, gridDim.x) * (blockDim.x / WAVE) + wib;
     if (e >= P.K) return;
-    WaveLds lds = carve_lds(smem, wib, P.max_cand);
+    WaveLds lds = carve_lds(smem, wib, P.max_cand, P.L);
     const int type = tb.env_type[e];
     const int S = tb.n_spheres[type];
     const float *sph = tb.spheres + (size_t)type * P.S_max * 4;
@@ -182,6 +243,14 @@ __global__ __launch_bounds__(StepBounds<SR>::threads) void k_step(Consts P, Tabl
     int wkey;
     float wr[3];
     load_warm(warm, P.C_max, e, wkey, wr);
+    // every wavefront evaluates the step's hand kinematics itself (the
+    // candidate list's LDS as scratch), while its state loads are in flight:
+    // no launch of its own on the per-step path, and the same bits as
+    // k_hand_fk
+    hand_kinematics(tb.hand, P.L, P.D, P.dt, u_prev, u, carve_fk(reinterpret_cast<char *>(lds.cand_d), P.L, P.D),
+                    lds.seg,
+                    lane_id(), WAVE, [] { wave_sync(); });
+    const float *seg = lds.seg;
     StepStats st = {0, 0, 0};
     int link;
     float imp[3];
@@ -319,7 +388,7 @@ __global__ __launch_bounds__(StepBounds<SR>::threads) void k_window(Consts P, Ta
     extern __shared__ __align__(16) char smem[];
     const int wib = threadIdx.x / WAVE;
     const int lane = lane_id();
-    WaveLds lds = carve_lds(smem, wib, P.max_cand);
+    WaveLds lds = carve_lds(smem, wib, P.max_cand, P.L);
     float *stage = contact_stage(lds);
     StepStats st = {0, 0, 0};
     int64_t done = 0;
@@ -400,24 +469,27 @@ __global__ __launch_bounds__(StepBounds<SR>::threads) void k_window(Consts P, Ta
 // ---------------------------------------------------------------------
 using namespace pt;
 
-hipError_t launch_hand_fk(const float *hand, int L, float dt, const float *u_prev, const float *u, int stride,
-                          int nsteps, float *seg_out, hipStream_t s)
+size_t hand_fk_lds_bytes(int L, int D) { return fk_lds_bytes(L, D); }
+
+hipError_t launch_hand_fk(const float *hand, int L, int D, float dt, const float *u_prev, const float *u,
+                          int stride, int nsteps, float *seg_out, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_hand_fk, dim3(nsteps), dim3(128), 0, s, hand, L, dt, u_prev, u, stride, seg_out);
+    hipLaunchKernelGGL(k_hand_fk, dim3(nsteps), dim3(128), 0, s, hand, L, D, dt, u_prev, u, stride, seg_out);
     return hipGetLastError();
 }
 
-hipError_t launch_step(const Consts &P, const Tables &tb, const float *seg, float *state, float *params, float *warm,
-                       float *contacts, int64_t *stats, int waves_per_block, hipStream_t s)
+hipError_t launch_step(const Consts &P, const Tables &tb, const float *u_prev, const float *u, float *state,
+                       float *params, float *warm, float *contacts, int64_t *stats, int waves_per_block,
+                       hipStream_t s)
 {
     int blocks = (P.K + waves_per_block - 1) / waves_per_block;
-    size_t lds = (size_t)waves_per_block * wave_lds_bytes(P.max_cand);
+    size_t lds = (size_t)waves_per_block * wave_lds_bytes(P.max_cand, P.L);
     if (P.solve_fp64)
-        hipLaunchKernelGGL(k_step<double>, dim3(blocks), dim3(WAVE * waves_per_block), lds, s, P, tb, seg, state,
-                           params, warm, contacts, stats);
+        hipLaunchKernelGGL(k_step<double>, dim3(blocks), dim3(WAVE * waves_per_block), lds, s, P, tb, u_prev, u,
+                           state, params, warm, contacts, stats);
     else
-        hipLaunchKernelGGL(k_step<float>, dim3(blocks), dim3(WAVE * waves_per_block), lds, s, P, tb, seg, state,
-                           params, warm, contacts, stats);
+        hipLaunchKernelGGL(k_step<float>, dim3(blocks), dim3(WAVE * waves_per_block), lds, s, P, tb, u_prev, u,
+                           state, params, warm, contacts, stats);
     return hipGetLastError();
 }
 
@@ -458,7 +530,7 @@ hipError_t launch_window(const Consts &P, const Tables &tb, const float *seg_win
                          const int32_t *env_order, int32_t *queue, int64_t *stats, int waves_per_block, int blocks,
                          float *ckpt, const int32_t *group_start, int32_t *best, hipStream_t s)
 {
-    size_t lds = (size_t)waves_per_block * wave_lds_bytes(P.max_cand);
+    size_t lds = (size_t)waves_per_block * wave_lds_bytes(P.max_cand, P.L);
     if (P.solve_fp64)
         hipLaunchKernelGGL(k_window<double>, dim3(blocks), dim3(WAVE * waves_per_block), lds, s, P, tb, seg_win,
                            state, params, warm, obs_gt_win, cost_sum, obs_out, env_order, queue, stats, ckpt,
@@ -470,9 +542,9 @@ hipError_t launch_window(const Consts &P, const Tables &tb, const float *seg_win
     return hipGetLastError();
 }
 
-hipError_t window_occupancy(int waves_per_block, int max_cand, bool fp64, int *blocks_per_cu)
+hipError_t window_occupancy(int waves_per_block, int max_cand, int L, bool fp64, int *blocks_per_cu)
 {
-    size_t lds = (size_t)waves_per_block * wave_lds_bytes(max_cand);
+    size_t lds = (size_t)waves_per_block * wave_lds_bytes(max_cand, L);
     const void *f = fp64 ? reinterpret_cast<const void *>(k_window<double>)
                          : reinterpret_cast<const void *>(k_window<float>);
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, f, WAVE * waves_per_block, lds);
