@@ -44,6 +44,7 @@ class Model(C.Structure):
         ("tau_contact", C.c_double), ("w_mag", C.c_double), ("w_dir", C.c_double),
         ("hand", C.POINTER(C.c_double)), ("spheres", C.POINTER(C.c_double)),
         ("n_spheres", C.POINTER(C.c_int32)), ("inv_inertia", C.POINTER(C.c_double)),
+        ("cost_mode", C.c_int32), ("tau_slip", C.c_double), ("tau_spin", C.c_double), ("w_eq3", C.c_double * 7),
     ]
 
 
@@ -94,6 +95,9 @@ def lib():
         L.or_observe.argtypes = [mp, C.c_int, C.c_void_p, dp]
         L.or_step_cost.argtypes = [mp, dp, dp]
         L.or_step_cost.restype = C.c_double
+        L.or_observe_eq3.argtypes = [mp, C.c_int, C.c_void_p, dp, dp, dp, dp]
+        L.or_step_cost_eq3.argtypes = [mp, dp, dp]
+        L.or_step_cost_eq3.restype = C.c_double
         L.or_batch_step.argtypes = [mp, C.c_int, ip, dp, dp, dp, dp, ip, dp, C.c_void_p, C.c_void_p, C.c_void_p]
         L.or_batch_cost.argtypes = [mp, C.c_int, C.c_int, ip, dp, dp, dp]
         L.or_argmin.argtypes = [C.c_int, dp]
@@ -152,6 +156,10 @@ class Oracle:
         m.margin, m.erp, m.compliance = consts.margin, consts.erp, consts.compliance
         m.kappa, m.fb_delta, m.armijo_sigma = consts.kappa, consts.fb_delta, consts.armijo_sigma
         m.tau_contact, m.w_mag, m.w_dir = consts.tau_contact, consts.w_mag, consts.w_dir
+        m.cost_mode = int(getattr(consts, "cost_mode", 0))
+        m.tau_slip, m.tau_spin = getattr(consts, "tau_slip", 0.005), getattr(consts, "tau_spin", 0.1)
+        for i, wv in enumerate(getattr(consts, "w_eq3", (1.0,) * 7)):
+            m.w_eq3[i] = wv
         m.hand = _dp(self.hand)
         m.spheres = _dp(self.spheres)
         m.n_spheres = _ip(self.n_spheres)
@@ -159,6 +167,7 @@ class Oracle:
         self.m = m
         self.consts = consts
         self.L, self.D, self.C_max = L, D, C_max
+        self.R = 7 if m.cost_mode == 1 else 4     # observation rows per sensor
 
     @classmethod
     def from_scene(cls, scene, **kw):
@@ -201,9 +210,20 @@ class Oracle:
         lib().or_observe(C.byref(self.m), len(cont), _vp(cont), _dp(obs))
         return obs
 
+    def observe_eq3(self, cont, seg0, seg1, omega_obj):
+        """Eq. 3's observation [L][7] of one env's contacts (see oracle.h)."""
+        cont = np.ascontiguousarray(cont, dtype=CONTACT_DTYPE)
+        obs = np.zeros((self.L, 7))
+        lib().or_observe_eq3(C.byref(self.m), len(cont), _vp(cont),
+                             _dp(np.ascontiguousarray(seg0, dtype=np.float64)),
+                             _dp(np.ascontiguousarray(seg1, dtype=np.float64)),
+                             _dp(np.ascontiguousarray(omega_obj, dtype=np.float64)), _dp(obs))
+        return obs
+
     def step_cost(self, obs, obs_gt):
-        return lib().or_step_cost(C.byref(self.m), _dp(np.ascontiguousarray(obs, dtype=np.float64)),
-                                  _dp(np.ascontiguousarray(obs_gt, dtype=np.float64)))
+        f = lib().or_step_cost_eq3 if self.R == 7 else lib().or_step_cost
+        return f(C.byref(self.m), _dp(np.ascontiguousarray(obs, dtype=np.float64)),
+                 _dp(np.ascontiguousarray(obs_gt, dtype=np.float64)))
 
     # -- batch -----------------------------------------------------------
     def new_warm(self, K):
@@ -212,7 +232,7 @@ class Oracle:
     def batch_step(self, env_type, u_prev, u, state, params, wkey, wr, want_contacts=False, want_diag=False):
         """In-place step of K envs; returns (obs [K][L][4], contacts, diag)."""
         K = state.shape[0]
-        obs = np.zeros((K, self.L, 4))
+        obs = np.zeros((K, self.L, self.R))
         cont = np.zeros((K, self.C_max), dtype=CONTACT_DTYPE) if want_contacts else None
         dg = np.zeros(K, dtype=DIAG_DTYPE) if want_diag else None
         lib().or_batch_step(C.byref(self.m), K, _ip(env_type), _dp(np.ascontiguousarray(u_prev, dtype=np.float64)),

@@ -697,6 +697,117 @@ double or_step_cost(const or_model *m, const double *obs, const double *obs_gt)
     return s;
 }
 
+/* Observation of Eq. 3 (see oracle.h): contact force, slip direction in the
+ * sensor's surface frame, spin direction about the mean contact normal. */
+void or_observe_eq3(const or_model *m, int nc, const or_contact *cont, const double *seg0, const double *seg1,
+                    const double *omega_obj, double *obs)
+{
+    int L = m->L;
+    double eps = m->compliance;
+    double *f = (double *)calloc((size_t)L * 3, sizeof(double));
+    double *N = (double *)calloc((size_t)L * 3, sizeof(double));
+    double *S = (double *)calloc((size_t)L * 3, sizeof(double));
+    double *W = (double *)calloc((size_t)L, sizeof(double));
+    for (int c = 0; c < nc; ++c) {
+        int l = cont[c].link;
+        if (l >= L) continue;
+        const or_contact *k = &cont[c];
+        double rn = k->r[0];
+        /* relative tangential velocity of the object's point against the
+         * link's: the constraint velocity less the compliance term */
+        double v1 = k->u[1] - eps * k->r[1], v2 = k->u[2] - eps * k->r[2];
+        for (int i = 0; i < 3; ++i) {
+            f[3 * l + i] -= (k->r[0] * k->n[i] + k->r[1] * k->t1[i] + k->r[2] * k->t2[i]) / m->dt;
+            N[3 * l + i] += rn * k->n[i];
+            S[3 * l + i] += rn * (v1 * k->t1[i] + v2 * k->t2[i]);
+        }
+        W[l] += rn;
+    }
+    for (int l = 0; l < L; ++l) {
+        double *o = obs + 7 * l;
+        double mag = norm3(f + 3 * l);
+        o[0] = mag;
+        for (int i = 0; i < 3; ++i) o[1 + i] = mag > m->tau_contact ? f[3 * l + i] / mag : 0.0;
+        o[4] = o[5] = o[6] = 0.0;
+        double nn = norm3(N + 3 * l);
+        if (W[l] <= 0.0 || nn <= 0.0) continue;
+        double nb[3] = {N[3 * l] / nn, N[3 * l + 1] / nn, N[3 * l + 2] / nn};
+        const double *a0 = seg0 + 6 * l, *b0 = seg0 + 6 * l + 3, *a1 = seg1 + 6 * l, *b1 = seg1 + 6 * l + 3;
+        double ab[3], va[3], vb[3], dv[3];
+        for (int i = 0; i < 3; ++i) {
+            ab[i] = b0[i] - a0[i];
+            va[i] = (a1[i] - a0[i]) / m->dt;
+            vb[i] = (b1[i] - b0[i]) / m->dt;
+            dv[i] = vb[i] - va[i];
+        }
+        double sl[3] = {S[3 * l] / W[l], S[3 * l + 1] / W[l], S[3 * l + 2] / W[l]};
+        if (norm3(sl) > m->tau_slip) {
+            /* surface frame: the link axis projected on the tangent plane
+             * (if the normal runs along the axis, the contact-frame rule) */
+            double la = norm3(ab);
+            double ea[3] = {ab[0] / la, ab[1] / la, ab[2] / la};
+            double an = dot3(ea, nb);
+            double e1[3] = {ea[0] - an * nb[0], ea[1] - an * nb[1], ea[2] - an * nb[2]};
+            double n1 = norm3(e1);
+            double e2[3];
+            if (n1 < 1e-6) {
+                tangent_frame(nb, e1, e2);
+            } else {
+                for (int i = 0; i < 3; ++i) e1[i] /= n1;
+                cross3(nb, e1, e2);
+            }
+            double d1 = dot3(sl, e1), d2 = dot3(sl, e2);
+            double dn = sqrt(d1 * d1 + d2 * d2);
+            if (dn > 0.0) { o[4] = d1 / dn; o[5] = d2 / dn; }
+        }
+        double wl[3];
+        cross3(ab, dv, wl);
+        double l2 = dot3(ab, ab);
+        double spin = 0.0;
+        for (int i = 0; i < 3; ++i) spin += (omega_obj[i] - wl[i] / l2) * nb[i];
+        o[6] = spin > m->tau_spin ? 1.0 : (spin < -m->tau_spin ? -1.0 : 0.0);
+    }
+    free(f); free(N); free(S); free(W);
+}
+
+/* the angle between two unit vectors (or 0 if either is 0) */
+static double unit_angle(const double *a, const double *b, int n)
+{
+    double d = 0.0;
+    for (int i = 0; i < n; ++i) d += a[i] * b[i];
+    d = d > 1.0 ? 1.0 : (d < -1.0 ? -1.0 : d);
+    return acos(d);
+}
+
+double or_step_cost_eq3(const or_model *m, const double *obs, const double *obs_gt)
+{
+    const double *w = m->w_eq3;   /* w4 .. w10 */
+    double s = 0;
+    for (int l = 0; l < m->L; ++l) {
+        const double *a = obs + 7 * l, *b = obs_gt + 7 * l;
+        int in_a = a[0] > m->tau_contact, in_b = b[0] > m->tau_contact;
+        int sl_a = a[4] != 0.0 || a[5] != 0.0, sl_b = b[4] != 0.0 || b[5] != 0.0;
+        int ro_a = a[6] != 0.0, ro_b = b[6] != 0.0;
+        if (in_a == in_b) {
+            s += w[1] * fabs(a[0] - b[0]);
+            if (in_a) s += w[2] * unit_angle(a + 1, b + 1, 3);
+        } else {
+            s += w[0];
+        }
+        if (sl_a == sl_b) {
+            if (sl_a) s += w[4] * unit_angle(a + 4, b + 4, 2);
+        } else {
+            s += w[3];
+        }
+        if (ro_a == ro_b) {
+            if (ro_a) s += w[6] * fabs((a[6] > 0.0 ? 1.0 : 0.0) - (b[6] > 0.0 ? 1.0 : 0.0));
+        } else {
+            s += w[5];
+        }
+    }
+    return s;
+}
+
 void or_batch_step(const or_model *m, int K, const int32_t *env_type,
                    const double *u_prev, const double *u,
                    double *state, double *params, int32_t *wkey, double *wr,
@@ -715,7 +826,12 @@ void or_batch_step(const or_model *m, int K, const int32_t *env_type,
                              wkey + (size_t)i * Cmax, wr + (size_t)i * Cmax * 3, cp, diag ? diag + i : NULL);
         if (cont)
             for (int c = nc; c < Cmax; ++c) { memset(cp + c, 0, sizeof(or_contact)); cp[c].key = -1; }
-        if (obs) or_observe(m, nc, cp, obs + (size_t)i * L * 4);
+        if (obs) {
+            if (m->cost_mode == 1)
+                or_observe_eq3(m, nc, cp, seg0, seg1, state + 13 * (size_t)i + 10, obs + (size_t)i * L * 7);
+            else
+                or_observe(m, nc, cp, obs + (size_t)i * L * 4);
+        }
     }
     free(seg0);
     free(seg1);
@@ -727,7 +843,9 @@ void or_batch_cost(const or_model *m, int K, int G, const int32_t *group_start,
     int L = m->L;
     for (int g = 0; g < G; ++g)
         for (int i = group_start[g]; i < group_start[g + 1] && i < K; ++i)
-            cost_sum[i] += or_step_cost(m, obs + (size_t)i * L * 4, obs_gt + (size_t)g * L * 4);
+            cost_sum[i] += m->cost_mode == 1
+                               ? or_step_cost_eq3(m, obs + (size_t)i * L * 7, obs_gt + (size_t)g * L * 7)
+                               : or_step_cost(m, obs + (size_t)i * L * 4, obs_gt + (size_t)g * L * 4);
 }
 
 int or_argmin(int n, const double *v)

@@ -57,6 +57,10 @@ typedef struct {
     const double *spheres;     /* [n_types][S_max][4] body-frame centre, radius */
     const int32_t *n_spheres;  /* [n_types]                                     */
     const double *inv_inertia; /* [n_types][3] principal inverse inertia per unit mass (0 = locked axis) */
+    int32_t cost_mode;         /* 0: force magnitude / direction cost, obs [L][4];
+                                * 1: Eq. 3 with contact-state, slip and spin terms, obs [L][7] */
+    double tau_slip, tau_spin; /* slip thresholds: m/s, rad/s                    */
+    double w_eq3[7];           /* w4 .. w10 of Eq. 3                             */
 } or_model;
 
 typedef struct {
@@ -105,6 +109,28 @@ void or_observe(const or_model *m, int nc, const or_contact *cont, double *obs);
 /* Step cost of one simulation's observation against the observed one. */
 double or_step_cost(const or_model *m, const double *obs, const double *obs_gt);
 
+/* Observation of Eq. 3 (cost_mode 1), per sensor l, obs[l][7]:
+ * |c|, c/|c| (0 when |c| <= tau_contact), d (2), rot, where, over the
+ * link's contacts with normal impulses r_n (weights W = sum r_n):
+ * n_bar = normalised sum r_n n, the slip velocity s = sum r_n (relative
+ * tangential velocity of the object's contact point against the link's,
+ * u - eps r in (t1, t2)) / W; when |s| > tau_slip, d = s in the sensor's
+ * surface frame (e1 = the link axis projected on the plane normal to n_bar,
+ * e2 = n_bar x e1), normalised, else 0; rot = sign of
+ * (omega_obj - omega_link) . n_bar when its size exceeds tau_spin, else 0.
+ * omega_link = ((b - a) x (vb - va)) / |b - a|^2 from the segment's end
+ * velocities; omega_obj is the object's angular velocity after the step.
+ * seg0 / seg1: the step's segments at u_prev and u ([L][6]). */
+void or_observe_eq3(const or_model *m, int nc, const or_contact *cont, const double *seg0, const double *seg1,
+                    const double *omega_obj, double *obs);
+
+/* Step cost of Eq. 3 (cost_mode 1), obs [L][7] each: per sensor
+ * w4 (1 - a) + a (w5 |dM| + w6 angle(c, c_gt)) + w7 (1 - b) + b w8 angle(d, d_gt)
+ * + w9 (1 - g) + g w10 |r - r_gt|, a / b / g = agreement of the contact,
+ * slip and spin states, the angles and |r - r_gt| counted where both sides
+ * are in that state (r = 1 for a positive spin). */
+double or_step_cost_eq3(const or_model *m, const double *obs, const double *obs_gt);
+
 /* Batched step over K environments (OpenMP over environments).
  * u_prev/u: [D].  cont [K][C_max], diag [K], obs [K][L][4] may be NULL. */
 void or_batch_step(const or_model *m, int K, const int32_t *env_type,
@@ -150,7 +176,8 @@ void or_resample_apply(const or_model *m, const or_resample_cfg *rc, int K, cons
  * and pose b (each x(3), q(4)). */
 double or_add(const or_model *m, int type, const double *pose_a, const double *pose_b);
 
-/* Window cost of a single environment over T steps: sum of step costs
+/* Window cost of a single environment over T steps (force cost, cost_mode
+ * 0, the one the adjoint differentiates): sum of step costs
  * against obs_gt[T][L][4]; u_seq[T+1][D] with u_seq[0] the command before
  * the window.  Inputs are not modified. */
 double or_window_cost(const or_model *m, int type, const double *st0, const double *pr0,

@@ -49,6 +49,11 @@ class ModelConsts:
     tau_contact: float = 0.01    # sensor contact threshold [N]
     w_mag: float = 1.0           # cost weight on the force magnitude
     w_dir: float = 0.1           # cost weight on the force direction
+    # the full cost of Eq. 3 (cost_mode 1): contact-state, slip and spin terms
+    cost_mode: int = 0           # 0: force magnitude / direction terms; 1: Eq. 3
+    tau_slip: float = 0.005      # translational slip threshold [m/s]
+    tau_spin: float = 0.1        # rotational slip threshold [rad/s]
+    w_eq3: tuple = (1.0, 1.0, 0.6366197723675814, 1.0, 0.6366197723675814, 1.0, 1.0)  # w4..w10
 
 
 @dataclass(frozen=True)
