@@ -126,6 +126,18 @@ typedef struct {
        pt_refine_elites takes the elites' first gradient instead of replaying
        their window */
     int32_t window_checkpoints;
+    /* observation and cost: 0 = contact-force terms, obs [4][L][K] rows |c|,
+       c/|c|; 1 = the full cost of Eq. 3 (Sec. III-C) with the terms a
+       kinematic hand does not make identically zero: contact-state
+       agreement, force magnitude and angle, translational slip (agreement
+       and direction in the sensor's surface frame) and rotational slip
+       (agreement and direction), obs [7][L][K] rows |c|, c/|c|, d (2), rot.
+       Mode 1 has no gradient: pt_window_grad and pt_refine_elites return
+       PT_E_UNSUPPORTED. */
+    int32_t cost_mode;
+    float tau_slip;       /* translational slip threshold [m/s], mode 1       */
+    float tau_spin;       /* rotational slip threshold [rad/s], mode 1        */
+    float w_eq3[7];       /* w4 .. w10 of Eq. 3, mode 1                       */
 } pt_batch_desc;
 
 /* Creates a batch: validates the descriptor (PT_E_ARG / PT_E_UNSUPPORTED),

@@ -770,13 +770,21 @@ void or_observe_eq3(const or_model *m, int nc, const or_contact *cont, const dou
     free(f); free(N); free(S); free(W);
 }
 
-/* the angle between two unit vectors (or 0 if either is 0) */
+/* the angle between two vectors of n = 2 or 3 components:
+ * atan2(|a x b|, a . b), exact also when the inputs are unit vectors only up
+ * to their rounding (where acos of the dot product is off by ~sqrt(2 ulp)) */
 static double unit_angle(const double *a, const double *b, int n)
 {
-    double d = 0.0;
+    double d = 0.0, c;
     for (int i = 0; i < n; ++i) d += a[i] * b[i];
-    d = d > 1.0 ? 1.0 : (d < -1.0 ? -1.0 : d);
-    return acos(d);
+    if (n == 2) {
+        c = fabs(a[0] * b[1] - a[1] * b[0]);
+    } else {
+        double x[3];
+        cross3(a, b, x);
+        c = norm3(x);
+    }
+    return atan2(c, d);
 }
 
 double or_step_cost_eq3(const or_model *m, const double *obs, const double *obs_gt)

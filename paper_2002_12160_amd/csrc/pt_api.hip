@@ -69,6 +69,8 @@ struct pt_batch_s {
     // gradient checkpoints (for n_elite simulations at a time) and refinement buffers
     float *d_ckpt = nullptr;
     float *d_wckpt = nullptr;    // per-step checkpoints of every simulation's window (window_checkpoints)
+    float *d_cslip = nullptr;    // [K][C_max][8] per-contact slip data of the last step (cost_mode 1)
+    float *d_seg = nullptr;      // [L][16] the last step's hand segments (cost_mode 1)
     int n_elite = 0;
     int32_t *d_elite = nullptr;  // [n_elite]
     float *d_ref = nullptr;      // see refine_layout
@@ -119,6 +121,14 @@ pt_status validate(const pt_batch_desc *d)
         return fail(PT_E_ARG, "solve_precision must be 32 or 64 (or 0 for the default, 64)");
     if (!(d->dt > 0.f) || !std::isfinite(d->dt)) return fail(PT_E_ARG, "dt must be positive and finite");
     if (!(d->kappa > 0.f) || !(d->fb_delta > 0.f)) return fail(PT_E_ARG, "kappa and fb_delta must be positive");
+    if (d->cost_mode != 0 && d->cost_mode != 1) return fail(PT_E_ARG, "cost_mode must be 0 or 1 (got %d)", d->cost_mode);
+    if (d->cost_mode == 1) {
+        if (!(d->tau_slip >= 0.f) || !std::isfinite(d->tau_slip) || !(d->tau_spin >= 0.f) ||
+            !std::isfinite(d->tau_spin))
+            return fail(PT_E_ARG, "tau_slip and tau_spin must be finite and >= 0");
+        for (int i = 0; i < 7; ++i)
+            if (!std::isfinite(d->w_eq3[i])) return fail(PT_E_ARG, "w_eq3[%d] is not finite", i);
+    }
     if (!(d->compliance >= 0.f)) return fail(PT_E_ARG, "compliance must be >= 0");
     if (!(d->elite_frac > 0.f && d->elite_frac <= 1.f)) return fail(PT_E_ARG, "elite_frac must be in (0, 1]");
     if (!(d->mu_lo <= d->mu_hi) || !(d->m_lo <= d->m_hi) || !(d->m_lo > 0.f))
@@ -230,6 +240,9 @@ pt_status pt_create_batch(const pt_batch_desc *d, pt_batch *out)
     P.margin = d->margin; P.erp = d->erp; P.compliance = d->compliance; P.kappa = d->kappa;
     P.fb_delta = d->fb_delta; P.armijo_sigma = d->armijo_sigma;
     P.tau_contact = d->tau_contact; P.w_mag = d->w_mag; P.w_dir = d->w_dir;
+    P.cost_mode = d->cost_mode;
+    P.tau_slip = d->tau_slip; P.tau_spin = d->tau_spin;
+    for (int i = 0; i < 7; ++i) P.w_eq3[i] = d->cost_mode == 1 ? d->w_eq3[i] : 0.f;
     b->R = {d->elite_frac, d->sigma_mu, d->sigma_m, d->sigma_f, d->mu_lo, d->mu_hi, d->m_lo, d->m_hi, d->seed};
     b->n_types = d->n_types;
     b->state = d->state;
@@ -289,6 +302,11 @@ pt_status pt_create_batch(const pt_batch_desc *d, pt_batch *out)
     HIP_TRY_C(hipMalloc(&b->d_elite, sizeof(int32_t) * b->n_elite));
     HIP_TRY_C(hipMalloc(&b->d_snap, sizeof(float) * K * (18 + (size_t)4 * d->C_max)));
     if (d->window_checkpoints) HIP_TRY_C(hipMalloc(&b->d_wckpt, sizeof(float) * ckpt_floats(P, (int)K)));
+    if (d->cost_mode == 1) {
+        HIP_TRY_C(hipMalloc(&b->d_cslip, sizeof(float) * K * d->C_max * 8));
+        HIP_TRY_C(hipMalloc(&b->d_seg, sizeof(float) * d->L * pt::SEG_STRIDE));
+        HIP_TRY_C(hipMemset(b->d_cslip, 0, sizeof(float) * K * d->C_max * 8));
+    }
     HIP_TRY_C(hipMemcpy(b->d_hand, d->hand, sizeof(float) * d->L * PT_HAND_STRIDE, hipMemcpyHostToDevice));
     HIP_TRY_C(hipMemcpy(b->d_spheres, d->spheres, sizeof(float) * d->n_types * d->S_max * 4, hipMemcpyHostToDevice));
     HIP_TRY_C(hipMemcpy(b->d_inv, d->inv_inertia, sizeof(float) * d->n_types * 3, hipMemcpyHostToDevice));
@@ -318,7 +336,8 @@ pt_status pt_destroy_batch(pt_batch b)
     if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
     void *ptrs[] = {b->d_hand, b->d_spheres, b->d_inv, b->d_nsph, b->d_type, b->d_group_of, b->d_group_start,
                     b->d_order, b->d_queue, b->d_stats, b->d_seg_win, b->d_contacts,
-                    b->d_seg_grad, b->d_tune, b->d_ckpt, b->d_wckpt, b->d_elite, b->d_ref, b->d_snap};
+                    b->d_seg_grad, b->d_tune, b->d_ckpt, b->d_wckpt, b->d_elite, b->d_ref, b->d_snap,
+                    b->d_cslip, b->d_seg};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete b;
@@ -342,8 +361,8 @@ pt_status pt_step(pt_batch b, const float *u_prev, const float *u, pt_stream s)
     if (!b) return fail(PT_E_ARG, "batch is NULL");
     if (b->P.D > 0 && (!u_prev || !u)) return fail(PT_E_ARG, "u_prev/u is NULL");
     hipStream_t st = (hipStream_t)s;
-    HIP_TRY(launch_step(b->P, tables_of(b), u_prev, u, b->state, b->params, b->warm, b->d_contacts, b->d_stats,
-                        b->step_wpb, st));
+    HIP_TRY(launch_step(b->P, tables_of(b), u_prev, u, b->state, b->params, b->warm, b->d_contacts, b->d_cslip,
+                        b->d_seg, b->d_stats, b->step_wpb, st));
     return PT_OK;
 }
 
@@ -351,7 +370,7 @@ pt_status pt_observe(pt_batch b, float *obs, pt_stream s)
 {
     if (!b) return fail(PT_E_ARG, "batch is NULL");
     if (!obs) return fail(PT_E_ARG, "obs is NULL");
-    HIP_TRY(launch_observe(b->P, b->d_contacts, obs, (hipStream_t)s));
+    HIP_TRY(launch_observe(b->P, b->d_contacts, b->d_cslip, b->d_seg, obs, (hipStream_t)s));
     return PT_OK;
 }
 
@@ -412,7 +431,7 @@ static pt_status enqueue_window(pt_batch b, const float *u_win, const float *obs
 {
     const Consts &P = b->P;
     int bpc = 0;
-    HIP_TRY(window_occupancy(wpb, P.max_cand, P.L, P.solve_fp64 != 0, &bpc));
+    HIP_TRY(window_occupancy(wpb, P.max_cand, P.L, P.solve_fp64 != 0, P.cost_mode == 1, &bpc));
     if (bpc < 1) return fail(PT_E_UNSUPPORTED, "persistent kernel does not fit with %d waves per workgroup", wpb);
     int want = (P.K + wpb - 1) / wpb;
     int blocks = std::min(want, bpc * b->num_cu);
@@ -552,6 +571,7 @@ pt_status pt_window_grad(pt_batch b, const float *u_win, const float *obs_gt_win
                          float *end_warm, pt_stream s)
 {
     if (!b) return fail(PT_E_ARG, "batch is NULL");
+    if (b->P.cost_mode != 0) return fail(PT_E_UNSUPPORTED, "the window gradient is defined for cost_mode 0 only");
     if (n < 0) return fail(PT_E_ARG, "n must be >= 0 (got %d)", n);
     if (n == 0) return PT_OK;
     if (!u_win || !obs_gt_win || !env || !start || !warm0 || !cost)
@@ -582,6 +602,8 @@ pt_status pt_refine_elites(pt_batch b, const float *u_win, const float *obs_gt_w
                            int32_t steps, float step, const float *scale, int32_t *best, int32_t *elite_out,
                            pt_stream s)
 {
+    if (b && b->P.cost_mode != 0)
+        return fail(PT_E_UNSUPPORTED, "elite refinement needs the window gradient, defined for cost_mode 0 only");
     if (!b) return fail(PT_E_ARG, "batch is NULL");
     if (!u_win || !obs_gt_win || !cost_sum || !start_state || !start_params || !start_warm)
         return fail(PT_E_ARG, "u_win/obs_gt_win/cost_sum/start_state/start_params/start_warm is NULL");

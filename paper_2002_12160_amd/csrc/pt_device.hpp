@@ -25,6 +25,8 @@ struct Consts {
     int K, G, L, D, S_max, C_max, newton_iters, T, max_cand, solve_fp64;
     float dt, gx, gy, gz, margin, erp, compliance, kappa, fb_delta, armijo_sigma;
     float tau_contact, w_mag, w_dir;
+    int cost_mode;             // 0: force terms, obs rows 4; 1: Eq. 3, obs rows 7
+    float tau_slip, tau_spin, w_eq3[7];
 };
 
 struct Tables {

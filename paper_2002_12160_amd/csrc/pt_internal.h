@@ -76,10 +76,11 @@ inline hipError_t set_dynamic_lds_limit(const void *f, size_t bytes)
 hipError_t launch_hand_fk(const float *hand, int L, int D, float dt, const float *u_prev, const float *u,
                           int stride, int nsteps, float *seg_out, hipStream_t s);
 hipError_t launch_step(const pt::Consts &P, const pt::Tables &tb, const float *u_prev, const float *u, float *state,
-                       float *params, float *warm, float *contacts, int64_t *stats, int waves_per_block,
-                       hipStream_t s);
+                       float *params, float *warm, float *contacts, float *cslip, float *seg_out, int64_t *stats,
+                       int waves_per_block, hipStream_t s);
 size_t hand_fk_lds_bytes(int L, int D);
-hipError_t launch_observe(const pt::Consts &P, const float *contacts, float *obs, hipStream_t s);
+hipError_t launch_observe(const pt::Consts &P, const float *contacts, const float *cslip, const float *seg, float *obs,
+                          hipStream_t s);
 hipError_t launch_cost(const pt::Consts &P, const int32_t *group_of, const int32_t *group_start, const float *obs,
                        const float *obs_gt, float *cost_sum, int32_t *best, int32_t *done, hipStream_t s);
 hipError_t launch_argmin(int G, const int32_t *group_start, const float *cost, int32_t *best, hipStream_t s);
@@ -90,7 +91,7 @@ hipError_t launch_window(const pt::Consts &P, const pt::Tables &tb, const float 
                          float *warm, const float *obs_gt_win, float *cost_sum, float *obs_out,
                          const int32_t *env_order, int32_t *queue, int64_t *stats, int waves_per_block, int blocks,
                          float *ckpt, const int32_t *group_start, int32_t *best, hipStream_t s);
-hipError_t window_occupancy(int waves_per_block, int max_cand, int L, bool fp64, int *blocks_per_cu);
+hipError_t window_occupancy(int waves_per_block, int max_cand, int L, bool fp64, bool eq3, int *blocks_per_cu);
 hipError_t set_lds_limits(size_t bytes);
 hipError_t set_grad_lds_limits(size_t bytes);
 size_t ckpt_floats(const pt::Consts &P, int n);

@@ -116,6 +116,136 @@ __device__ __forceinline__ float sensor_cost(const Consts &P, const float *o, co
     return P.w_mag * dm * dm + P.w_dir * (d1 * d1 + d2 * d2 + d3 * d3);
 }
 
+// ---------------------------------------------------------------------
+// the full cost of Eq. 3 (cost_mode 1): contact state, slip and spin
+// ---------------------------------------------------------------------
+constexpr int SLIP_STRIDE = 8;   // per-contact slip record, floats
+
+// Slip record of this lane's contact after the step: r_n n (3), r_n,
+// r_n s (3), q, with s the relative tangential velocity of the object's
+// contact point against the link's (the constraint velocity without the
+// compliance term, in world axes) and q = r_n (w_obj - w_link) . n, w_link
+// = (b - a) x (vb - va) / |b - a|^2 from the link's segment record and
+// w_obj the object's angular velocity after the step.  Zeros for an empty
+// slot and for a table contact (not a sensor).
+template <typename SR>
+__device__ __forceinline__ void slip_record(const StepState<SR> &st, const float *seg, const float *w_obj,
+                                            float *out)
+{
+#pragma unroll
+    for (int i = 0; i < SLIP_STRIDE; ++i) out[i] = 0.f;
+    if (!st.act || st.link < 0) return;
+    SR u[3];
+    rel_velocity(st, st.nu, st.r, SR(0), u);
+    const SR *F = st.F;
+    const float rn = (float)st.r[0];
+    const float n[3] = {(float)F[0], (float)F[1], (float)F[2]};
+    const float sv[3] = {(float)(u[1] * F[3] + u[2] * F[6]), (float)(u[1] * F[4] + u[2] * F[7]),
+                         (float)(u[1] * F[5] + u[2] * F[8])};
+    const float *sg = seg + st.link * SEG_STRIDE;
+    const float ab[3] = {sg[4], sg[5], sg[6]};
+    const float dv[3] = {sg[12] - sg[8], sg[13] - sg[9], sg[14] - sg[10]};
+    float wl[3];
+    cross3(ab, dv, wl);
+    const float il2 = sg[7];
+    const float q = rn * ((w_obj[0] - wl[0] * il2) * n[0] + (w_obj[1] - wl[1] * il2) * n[1] +
+                          (w_obj[2] - wl[2] * il2) * n[2]);
+    out[0] = rn * n[0]; out[1] = rn * n[1]; out[2] = rn * n[2]; out[3] = rn;
+    out[4] = rn * sv[0]; out[5] = rn * sv[1]; out[6] = rn * sv[2]; out[7] = q;
+}
+
+// Eq. 3 observation of sensor `lane` (lanes < L) from the step's staged
+// contacts -- stage [C_max][4] (link, impulse), slip [C_max][8] -- and the
+// step's segment records: |c|, c/|c| as sensor_force; with n_bar the
+// normalised sum r_n n and s = sum r_n s / sum r_n, d = s in the sensor's
+// surface frame (e1 = the link axis projected normal to n_bar, or the
+// contact-frame rule if the normal runs along the axis; e2 = n_bar x e1),
+// normalised, when |s| > tau_slip, else 0; rot = the sign of
+// sum q / |sum r_n n| beyond tau_spin, else 0.  o[7].
+__device__ __forceinline__ bool sensor_obs_eq3(const Consts &P, const float *stage, const float *slip,
+                                               const float *seg, float *o)
+{
+    const int lane = lane_id();
+    const bool sensor = sensor_force(P, stage, o);
+    o[4] = o[5] = o[6] = 0.f;
+    if (!sensor) return false;
+    float N[3] = {0.f, 0.f, 0.f}, S[3] = {0.f, 0.f, 0.f}, W = 0.f, Q = 0.f;
+    for (int c = 0; c < P.C_max; ++c) {
+        if (__float_as_int(stage[4 * c]) != lane) continue;
+        const float4 a = *reinterpret_cast<const float4 *>(slip + SLIP_STRIDE * c);
+        const float4 b = *reinterpret_cast<const float4 *>(slip + SLIP_STRIDE * c + 4);
+        N[0] += a.x; N[1] += a.y; N[2] += a.z; W += a.w;
+        S[0] += b.x; S[1] += b.y; S[2] += b.z; Q += b.w;
+    }
+    const float nn = sqrtf(dot3(N, N));
+    if (!(W > 0.f) || !(nn > 0.f)) return true;
+    const float nb[3] = {N[0] / nn, N[1] / nn, N[2] / nn};
+    const float sl[3] = {S[0] / W, S[1] / W, S[2] / W};
+    if (sqrtf(dot3(sl, sl)) > P.tau_slip) {
+        const float *sg = seg + lane * SEG_STRIDE;
+        const float la = sqrtf(sg[4] * sg[4] + sg[5] * sg[5] + sg[6] * sg[6]);
+        const float ea[3] = {sg[4] / la, sg[5] / la, sg[6] / la};
+        const float an = dot3(ea, nb);
+        float e1[3] = {ea[0] - an * nb[0], ea[1] - an * nb[1], ea[2] - an * nb[2]}, e2[3];
+        const float n1 = sqrtf(dot3(e1, e1));
+        if (n1 < 1e-6f) {
+            tangent_frame(nb, e1, e2);
+        } else {
+            e1[0] /= n1; e1[1] /= n1; e1[2] /= n1;
+            cross3(nb, e1, e2);
+        }
+        const float d1 = dot3(sl, e1), d2 = dot3(sl, e2);
+        const float dn = sqrtf(d1 * d1 + d2 * d2);
+        if (dn > 0.f) { o[4] = d1 / dn; o[5] = d2 / dn; }
+    }
+    const float spin = Q / nn;
+    o[6] = spin > P.tau_spin ? 1.f : (spin < -P.tau_spin ? -1.f : 0.f);
+    return true;
+}
+
+// angle between two unit vectors of n components, 2 atan2(|a - b|, |a + b|)
+// (no loss of accuracy near 0 or pi)
+__device__ __forceinline__ float unit_angle(const float *a, const float *b, int n)
+{
+    float dm = 0.f, dp = 0.f;
+    for (int i = 0; i < n; ++i) {
+        dm += (a[i] - b[i]) * (a[i] - b[i]);
+        dp += (a[i] + b[i]) * (a[i] + b[i]);
+    }
+    return 2.f * atan2f(sqrtf(dm), sqrtf(dp));
+}
+
+// Eq. 3 cost of one sensor: w4 (1 - alpha) + alpha (w5 |dM| + w6 angle of
+// the forces when in contact) + w7 (1 - beta) + beta w8 angle of the slip
+// directions when slipping + w9 (1 - gamma) + gamma w10 |r - r_gt| when
+// spinning (r = 1 for a positive spin); alpha, beta, gamma the agreement of
+// the contact, slip and spin states
+__device__ __forceinline__ float sensor_cost_eq3(const Consts &P, const float *o, const float *gt)
+{
+    const float *w = P.w_eq3;
+    const bool in_a = o[0] > P.tau_contact, in_b = gt[0] > P.tau_contact;
+    const bool sl_a = o[4] != 0.f || o[5] != 0.f, sl_b = gt[4] != 0.f || gt[5] != 0.f;
+    const bool ro_a = o[6] != 0.f, ro_b = gt[6] != 0.f;
+    float c = 0.f;
+    if (in_a == in_b) {
+        c += w[1] * fabsf(o[0] - gt[0]);
+        if (in_a) c += w[2] * unit_angle(o + 1, gt + 1, 3);
+    } else {
+        c += w[0];
+    }
+    if (sl_a == sl_b) {
+        if (sl_a) c += w[4] * unit_angle(o + 4, gt + 4, 2);
+    } else {
+        c += w[3];
+    }
+    if (ro_a == ro_b) {
+        if (ro_a) c += w[6] * fabsf((o[6] > 0.f ? 1.f : 0.f) - (gt[6] > 0.f ? 1.f : 0.f));
+    } else {
+        c += w[5];
+    }
+    return c;
+}
+
 // step cost of one simulation from its sensors' terms held one per lane
 // (lane l < L), summed in sensor order; shared by the plain and batched paths
 __device__ __forceinline__ float step_cost_wave(const Consts &P, float cl)

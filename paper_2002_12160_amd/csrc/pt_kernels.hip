@@ -222,11 +222,14 @@ struct StepBounds {
     static constexpr int threads = sizeof(SR) == 8 ? 256 : 512;
 };
 
-template <typename SR>
+// EQ3: the observation of Eq. 3 (cost_mode 1) compiled in; the default
+// force-only kernels carry none of its registers
+template <typename SR, bool EQ3>
 __global__ __launch_bounds__(StepBounds<SR>::threads) void k_step(Consts P, Tables tb,
                                                const float *__restrict__ u_prev, const float *__restrict__ u,
                                                float *__restrict__ state, float *__restrict__ params,
                                                float *__restrict__ warm, float *__restrict__ contacts,
+                                               float *__restrict__ cslip, float *__restrict__ seg_out,
                                                int64_t *__restrict__ stats)
 {
     extern __shared__ __align__(16) char smem[];
@@ -254,10 +257,26 @@ __global__ __launch_bounds__(StepBounds<SR>::threads) void k_step(Consts P, Tabl
     StepStats st = {0, 0, 0};
     int link;
     float imp[3];
-    env_step<SR>(P, seg, sph, S, inv, B, wkey, wr, link, imp, lds, st);
+    StepState<SR> sst;
+    step_setup<SR>(P, seg, sph, S, inv, B, wkey, wr, lds, st, sst);
+    step_solve<SR>(P, sst, B.mu, inv, reinterpret_cast<SR *>(lds.cand_d));
+    step_finish<SR>(P, sst, inv, B, wkey, wr, link, imp);
+    const int lane = lane_id();
+    if (EQ3) {
+        // Eq. 3's slip data of every contact, and the step's segments (one
+        // wavefront) for the observation kernel
+        float rec[SLIP_STRIDE];
+        slip_record<SR>(sst, seg, B.w, rec);
+        if (lane < P.C_max) {
+            float4 *o = reinterpret_cast<float4 *>(cslip + ((size_t)e * P.C_max + lane) * SLIP_STRIDE);
+            o[0] = make_float4(rec[0], rec[1], rec[2], rec[3]);
+            o[1] = make_float4(rec[4], rec[5], rec[6], rec[7]);
+        }
+        if (e == 0)
+            for (int i = lane; i < P.L * SEG_STRIDE; i += WAVE) seg_out[i] = seg[i];
+    }
     store_body(state, params, P.K, e, B);
     store_warm(warm, P.C_max, e, wkey, wr);
-    const int lane = lane_id();
     if (lane < P.C_max)
         *reinterpret_cast<float4 *>(contacts + ((size_t)e * P.C_max + lane) * 4) =
             make_float4(__int_as_float(link), imp[0], imp[1], imp[2]);
@@ -265,25 +284,39 @@ __global__ __launch_bounds__(StepBounds<SR>::threads) void k_step(Consts P, Tabl
 }
 
 // one wavefront per simulation, lanes over sensors
-__global__ __launch_bounds__(256) void k_observe(Consts P, const float *__restrict__ contacts, float *__restrict__ obs)
+// (cost_mode 1: the seven rows of Eq. 3's observation, from the contacts'
+// slip records and the step's segments)
+__global__ __launch_bounds__(256) void k_observe(Consts P, const float *__restrict__ contacts,
+                                                 const float *__restrict__ cslip, const float *__restrict__ seg,
+                                                 float *__restrict__ obs)
 {
     __shared__ __align__(16) float stage[4][WAVE * 4];
+    __shared__ __align__(16) float slip[4][WAVE * SLIP_STRIDE];
     const int wib = threadIdx.x / WAVE;
     const int e = xcd_block(blockIdx.x, gridDim.x) * (blockDim.x / WAVE) + wib;
     if (e >= P.K) return;
     const int lane = lane_id();
     float *sg = stage[wib];
-    if (lane < P.C_max)
+    float *sl = slip[wib];
+    const bool eq3 = P.cost_mode == 1;
+    if (lane < P.C_max) {
         *reinterpret_cast<float4 *>(sg + 4 * lane) =
             *reinterpret_cast<const float4 *>(contacts + ((size_t)e * P.C_max + lane) * 4);
+        if (eq3) {
+            const float4 *src = reinterpret_cast<const float4 *>(cslip + ((size_t)e * P.C_max + lane) * SLIP_STRIDE);
+            *reinterpret_cast<float4 *>(sl + SLIP_STRIDE * lane) = src[0];
+            *reinterpret_cast<float4 *>(sl + SLIP_STRIDE * lane + 4) = src[1];
+        }
+    }
     wave_sync();
-    float o[4];
-    if (sensor_force(P, sg, o)) {
-        const size_t LK = (size_t)P.L * P.K;
-        obs[0 * LK + (size_t)lane * P.K + e] = o[0];
-        obs[1 * LK + (size_t)lane * P.K + e] = o[1];
-        obs[2 * LK + (size_t)lane * P.K + e] = o[2];
-        obs[3 * LK + (size_t)lane * P.K + e] = o[3];
+    const size_t LK = (size_t)P.L * P.K;
+    float o[7];
+    const bool sensor = eq3 ? sensor_obs_eq3(P, sg, sl, seg, o) : sensor_force(P, sg, o);
+    if (sensor) {
+        const int R = eq3 ? 7 : 4;
+#pragma unroll
+        for (int j = 0; j < 7; ++j)
+            if (j < R) obs[j * LK + (size_t)lane * P.K + e] = o[j];
     }
 }
 
@@ -300,14 +333,17 @@ __global__ __launch_bounds__(256) void k_cost(Consts P, const int32_t *__restric
     if (e < P.K) {
         const int g = group_of[e];
         const size_t LK = (size_t)P.L * P.K, LG = (size_t)P.L * P.G;
+        const bool eq3 = P.cost_mode == 1;
         float cl = 0.f;
         if (lane < P.L) {
-            float o[4], gt[4];
-            for (int j = 0; j < 4; ++j) {
-                o[j] = obs[j * LK + (size_t)lane * P.K + e];
-                gt[j] = obs_gt[j * LG + (size_t)lane * P.G + g];
+            float o[7], gt[7];
+            const int R = eq3 ? 7 : 4;
+#pragma unroll
+            for (int j = 0; j < 7; ++j) {
+                o[j] = j < R ? obs[j * LK + (size_t)lane * P.K + e] : 0.f;
+                gt[j] = j < R ? obs_gt[j * LG + (size_t)lane * P.G + g] : 0.f;
             }
-            cl = sensor_cost(P, o, gt);
+            cl = eq3 ? sensor_cost_eq3(P, o, gt) : sensor_cost(P, o, gt);
         }
         const float cs = step_cost_wave(P, cl);
         if (lane == 0) cost_sum[e] += cs;
@@ -376,7 +412,7 @@ __global__ __launch_bounds__(1024) void k_resample(Consts P, ResampleArgs R, con
 // ---------------------------------------------------------------------
 // batched path: persistent kernel over a window of T steps
 // ---------------------------------------------------------------------
-template <typename SR>
+template <typename SR, bool EQ3>
 __global__ __launch_bounds__(StepBounds<SR>::threads) void k_window(Consts P, Tables tb, const float *__restrict__ seg_win,
                                                  float *__restrict__ state, float *__restrict__ params,
                                                  float *__restrict__ warm, const float *__restrict__ obs_gt_win,
@@ -425,20 +461,46 @@ __global__ __launch_bounds__(StepBounds<SR>::threads) void k_window(Consts P, Ta
             if (ck) save_contact<SR>(ck, P.C_max, sst);
             step_finish<SR>(P, sst, inv, B, wkey, wr, link, imp);
             *reinterpret_cast<float4 *>(stage + 4 * lane) = make_float4(__int_as_float(link), imp[0], imp[1], imp[2]);
+            // Eq. 3 (cost_mode 1): the contacts' slip records staged in the
+            // candidate list's LDS, free between the solve and the next
+            // step's narrow phase
+            float *slip = lds.cand_d;
+            if constexpr (EQ3) {
+                float rec[SLIP_STRIDE];
+                slip_record<SR>(sst, seg, B.w, rec);
+                *reinterpret_cast<float4 *>(slip + SLIP_STRIDE * lane) = make_float4(rec[0], rec[1], rec[2], rec[3]);
+                *reinterpret_cast<float4 *>(slip + SLIP_STRIDE * lane + 4) = make_float4(rec[4], rec[5], rec[6], rec[7]);
+            }
             wave_sync();
-            float o[4];
             float cl = 0.f;
-            if (sensor_force(P, stage, o)) {
-                const float *gt = obs_gt_win + (size_t)t * 4 * LG;
-                float gv[4] = {gt[0 * LG + (size_t)lane * P.G + g], gt[1 * LG + (size_t)lane * P.G + g],
-                               gt[2 * LG + (size_t)lane * P.G + g], gt[3 * LG + (size_t)lane * P.G + g]};
-                cl = sensor_cost(P, o, gv);
-                if (obs_out) {
-                    float *ob = obs_out + (size_t)t * 4 * LK;
-                    ob[0 * LK + (size_t)lane * P.K + e] = o[0];
-                    ob[1 * LK + (size_t)lane * P.K + e] = o[1];
-                    ob[2 * LK + (size_t)lane * P.K + e] = o[2];
-                    ob[3 * LK + (size_t)lane * P.K + e] = o[3];
+            if constexpr (EQ3) {
+                float o[7];
+                if (sensor_obs_eq3(P, stage, slip, seg, o)) {
+                    const float *gt = obs_gt_win + (size_t)t * 7 * LG;
+                    float gv[7];
+#pragma unroll
+                    for (int j = 0; j < 7; ++j) gv[j] = gt[j * LG + (size_t)lane * P.G + g];
+                    cl = sensor_cost_eq3(P, o, gv);
+                    if (obs_out) {
+                        float *ob = obs_out + (size_t)t * 7 * LK;
+#pragma unroll
+                        for (int j = 0; j < 7; ++j) ob[j * LK + (size_t)lane * P.K + e] = o[j];
+                    }
+                }
+            } else {
+                float o[4];
+                if (sensor_force(P, stage, o)) {
+                    const float *gt = obs_gt_win + (size_t)t * 4 * LG;
+                    float gv[4] = {gt[0 * LG + (size_t)lane * P.G + g], gt[1 * LG + (size_t)lane * P.G + g],
+                                   gt[2 * LG + (size_t)lane * P.G + g], gt[3 * LG + (size_t)lane * P.G + g]};
+                    cl = sensor_cost(P, o, gv);
+                    if (obs_out) {
+                        float *ob = obs_out + (size_t)t * 4 * LK;
+                        ob[0 * LK + (size_t)lane * P.K + e] = o[0];
+                        ob[1 * LK + (size_t)lane * P.K + e] = o[1];
+                        ob[2 * LK + (size_t)lane * P.K + e] = o[2];
+                        ob[3 * LK + (size_t)lane * P.K + e] = o[3];
+                    }
                 }
             }
             wave_sync();
@@ -479,24 +541,33 @@ hipError_t launch_hand_fk(const float *hand, int L, int D, float dt, const float
 }
 
 hipError_t launch_step(const Consts &P, const Tables &tb, const float *u_prev, const float *u, float *state,
-                       float *params, float *warm, float *contacts, int64_t *stats, int waves_per_block,
-                       hipStream_t s)
+                       float *params, float *warm, float *contacts, float *cslip, float *seg_out, int64_t *stats,
+                       int waves_per_block, hipStream_t s)
 {
     int blocks = (P.K + waves_per_block - 1) / waves_per_block;
     size_t lds = (size_t)waves_per_block * wave_lds_bytes(P.max_cand, P.L);
-    if (P.solve_fp64)
-        hipLaunchKernelGGL(k_step<double>, dim3(blocks), dim3(WAVE * waves_per_block), lds, s, P, tb, u_prev, u,
-                           state, params, warm, contacts, stats);
+    const dim3 grid(blocks), block(WAVE * waves_per_block);
+    const bool eq3 = P.cost_mode == 1;
+    if (P.solve_fp64 && !eq3)
+        hipLaunchKernelGGL((k_step<double, false>), grid, block, lds, s, P, tb, u_prev, u, state, params, warm,
+                           contacts, cslip, seg_out, stats);
+    else if (P.solve_fp64)
+        hipLaunchKernelGGL((k_step<double, true>), grid, block, lds, s, P, tb, u_prev, u, state, params, warm,
+                           contacts, cslip, seg_out, stats);
+    else if (!eq3)
+        hipLaunchKernelGGL((k_step<float, false>), grid, block, lds, s, P, tb, u_prev, u, state, params, warm,
+                           contacts, cslip, seg_out, stats);
     else
-        hipLaunchKernelGGL(k_step<float>, dim3(blocks), dim3(WAVE * waves_per_block), lds, s, P, tb, u_prev, u,
-                           state, params, warm, contacts, stats);
+        hipLaunchKernelGGL((k_step<float, true>), grid, block, lds, s, P, tb, u_prev, u, state, params, warm,
+                           contacts, cslip, seg_out, stats);
     return hipGetLastError();
 }
 
-hipError_t launch_observe(const Consts &P, const float *contacts, float *obs, hipStream_t s)
+hipError_t launch_observe(const Consts &P, const float *contacts, const float *cslip, const float *seg, float *obs,
+                          hipStream_t s)
 {
     int blocks = (P.K + 3) / 4;
-    hipLaunchKernelGGL(k_observe, dim3(blocks), dim3(256), 0, s, P, contacts, obs);
+    hipLaunchKernelGGL(k_observe, dim3(blocks), dim3(256), 0, s, P, contacts, cslip, seg, obs);
     return hipGetLastError();
 }
 
@@ -531,29 +602,43 @@ hipError_t launch_window(const Consts &P, const Tables &tb, const float *seg_win
                          float *ckpt, const int32_t *group_start, int32_t *best, hipStream_t s)
 {
     size_t lds = (size_t)waves_per_block * wave_lds_bytes(P.max_cand, P.L);
-    if (P.solve_fp64)
-        hipLaunchKernelGGL(k_window<double>, dim3(blocks), dim3(WAVE * waves_per_block), lds, s, P, tb, seg_win,
-                           state, params, warm, obs_gt_win, cost_sum, obs_out, env_order, queue, stats, ckpt,
-                           group_start, best);
+    const dim3 grid(blocks), block(WAVE * waves_per_block);
+    const bool eq3 = P.cost_mode == 1;
+    if (P.solve_fp64 && !eq3)
+        hipLaunchKernelGGL((k_window<double, false>), grid, block, lds, s, P, tb, seg_win, state, params, warm,
+                           obs_gt_win, cost_sum, obs_out, env_order, queue, stats, ckpt, group_start, best);
+    else if (P.solve_fp64)
+        hipLaunchKernelGGL((k_window<double, true>), grid, block, lds, s, P, tb, seg_win, state, params, warm,
+                           obs_gt_win, cost_sum, obs_out, env_order, queue, stats, ckpt, group_start, best);
+    else if (!eq3)
+        hipLaunchKernelGGL((k_window<float, false>), grid, block, lds, s, P, tb, seg_win, state, params, warm,
+                           obs_gt_win, cost_sum, obs_out, env_order, queue, stats, ckpt, group_start, best);
     else
-        hipLaunchKernelGGL(k_window<float>, dim3(blocks), dim3(WAVE * waves_per_block), lds, s, P, tb, seg_win,
-                           state, params, warm, obs_gt_win, cost_sum, obs_out, env_order, queue, stats, ckpt,
-                           group_start, best);
+        hipLaunchKernelGGL((k_window<float, true>), grid, block, lds, s, P, tb, seg_win, state, params, warm,
+                           obs_gt_win, cost_sum, obs_out, env_order, queue, stats, ckpt, group_start, best);
     return hipGetLastError();
 }
 
-hipError_t window_occupancy(int waves_per_block, int max_cand, int L, bool fp64, int *blocks_per_cu)
+hipError_t window_occupancy(int waves_per_block, int max_cand, int L, bool fp64, bool eq3, int *blocks_per_cu)
 {
     size_t lds = (size_t)waves_per_block * wave_lds_bytes(max_cand, L);
-    const void *f = fp64 ? reinterpret_cast<const void *>(k_window<double>)
-                         : reinterpret_cast<const void *>(k_window<float>);
+    const void *f = fp64 ? (eq3 ? reinterpret_cast<const void *>(k_window<double, true>)
+                                : reinterpret_cast<const void *>(k_window<double, false>))
+                         : (eq3 ? reinterpret_cast<const void *>(k_window<float, true>)
+                                : reinterpret_cast<const void *>(k_window<float, false>));
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, f, WAVE * waves_per_block, lds);
 }
 
 hipError_t set_lds_limits(size_t bytes)
 {
-    const void *fs[] = {reinterpret_cast<const void *>(k_window<float>), reinterpret_cast<const void *>(k_window<double>),
-                        reinterpret_cast<const void *>(k_step<float>), reinterpret_cast<const void *>(k_step<double>),
+    const void *fs[] = {reinterpret_cast<const void *>(k_window<float, false>),
+                        reinterpret_cast<const void *>(k_window<double, false>),
+                        reinterpret_cast<const void *>(k_window<float, true>),
+                        reinterpret_cast<const void *>(k_window<double, true>),
+                        reinterpret_cast<const void *>(k_step<float, false>),
+                        reinterpret_cast<const void *>(k_step<double, false>),
+                        reinterpret_cast<const void *>(k_step<float, true>),
+                        reinterpret_cast<const void *>(k_step<double, true>),
                         reinterpret_cast<const void *>(k_resample)};
     for (const void *f : fs) {
         hipError_t e = set_dynamic_lds_limit(f, bytes);

@@ -56,6 +56,7 @@ class BatchDesc(C.Structure):
         ("env_type", C.c_void_p), ("group_start", C.c_void_p),
         ("state", C.c_void_p), ("params", C.c_void_p), ("warm", C.c_void_p),
         ("window_checkpoints", C.c_int32),
+        ("cost_mode", C.c_int32), ("tau_slip", C.c_float), ("tau_spin", C.c_float), ("w_eq3", C.c_float * 7),
     ]
 
 
@@ -241,6 +242,11 @@ class Batch:
         d.params = self.params.data_ptr()
         d.warm = self.warm.data_ptr()
         d.window_checkpoints = 1 if window_checkpoints else 0
+        d.cost_mode = int(getattr(consts, "cost_mode", 0))
+        d.tau_slip, d.tau_spin = getattr(consts, "tau_slip", 0.005), getattr(consts, "tau_spin", 0.1)
+        for i, wv in enumerate(getattr(consts, "w_eq3", (1.0,) * 7)):
+            d.w_eq3[i] = wv
+        self.obs_rows = 7 if d.cost_mode == 1 else 4
         self.desc = d
         self.handle = pt_create_batch(d)
 
@@ -286,7 +292,7 @@ class Batch:
 
     # -- the hot path ------------------------------------------------------
     def new_obs(self, T=None):
-        shape = (4, self.L, self.K) if T is None else (T, 4, self.L, self.K)
+        shape = (self.obs_rows, self.L, self.K) if T is None else (T, self.obs_rows, self.L, self.K)
         return torch.zeros(shape, dtype=torch.float32, device=self.device)
 
     def step(self, u_prev, u, stream=None):

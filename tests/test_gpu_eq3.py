@@ -1,0 +1,187 @@
+"""The full cost of Eq. 3 (cost_mode 1) on the GPU against the oracle: the
+step cost on identical observations, the per-step observation (force,
+slip direction, spin direction) on non-chaotic steps, and the batched
+window against the plain path bit for bit."""
+import dataclasses
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2002_12160_amd import scene as S
+from tests import parity_util as PU
+from tests.test_gpu_paths import _assert_same, run_batched, run_plain
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pt():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2002_12160_amd import pt as _pt
+    return _pt
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _eq3(cfg):
+    return cfg.with_(consts=dataclasses.replace(cfg.consts, cost_mode=1))
+
+
+def _u(x):
+    return torch.as_tensor(np.asarray(x, dtype=np.float32), device="cuda").contiguous()
+
+
+def test_eq3_cost_matches_oracle(pt):
+    # every gate combination: in / out of contact, slipping or not, spinning
+    # either way or not, on both sides, over 3 groups
+    _say("Eq. 3 cost parity")
+    cfg = _eq3(S.CONFIGS["small"].with_(group_types=(0, 0, 0)))
+    K = 60
+    sc = S.round_to_f32(S.make_scene(cfg, K=K, steps=2))
+    L, G = sc.L, sc.G
+    rng = np.random.default_rng(21)
+
+    def rand_obs(n):
+        o = np.zeros((n, L, 7))
+        on = rng.uniform(size=(n, L)) < 0.6
+        mag = np.where(on, rng.uniform(0.02, 3.0, size=(n, L)), rng.uniform(0, 0.009, size=(n, L)))
+        o[..., 0] = mag
+        dvec = rng.normal(size=(n, L, 3))
+        o[..., 1:4] = dvec / np.linalg.norm(dvec, axis=-1, keepdims=True) * on[..., None]
+        sl = rng.uniform(size=(n, L)) < 0.5
+        ang = rng.uniform(-math.pi, math.pi, size=(n, L))
+        o[..., 4] = np.cos(ang) * sl
+        o[..., 5] = np.sin(ang) * sl
+        o[..., 6] = rng.integers(-1, 2, size=(n, L))
+        return PU.f32(o)
+
+    obs, gt = rand_obs(K), rand_obs(G)
+    obs[5] = gt[0]                                   # an exact copy: zero cost
+    b = pt.Batch.from_scene(sc)
+    assert b.obs_rows == 7
+    obs_t = torch.as_tensor(obs.transpose(2, 1, 0).astype(np.float32).copy(), device="cuda")
+    gt_t = torch.as_tensor(gt.transpose(2, 1, 0).astype(np.float32).copy(), device="cuda")
+    cost = torch.zeros(K, device="cuda")
+    best = torch.zeros(G, dtype=torch.int32, device="cuda")
+    b.cost(obs_t, gt_t, cost, best)
+    torch.cuda.synchronize()
+    o = oracle.Oracle.from_scene(sc)
+    ref = np.zeros(K)
+    o.batch_cost(sc.group_start, obs, gt, ref)
+    np.testing.assert_allclose(cost.cpu().numpy(), ref, rtol=1e-5, atol=1e-5)
+    assert cost[5].item() == 0.0
+    b.close()
+
+
+def _slip_and_spin(o, cont, seg0, seg1, omega, dt, eps):
+    """The oracle's per-link slip speed and spin (for the threshold bands)."""
+    L = o.L
+    N, S_, W, Q = np.zeros((L, 3)), np.zeros((L, 3)), np.zeros(L), np.zeros(L)
+    for c in cont:
+        if c["key"] < 0 or c["link"] >= L:
+            continue
+        l = c["link"]
+        rn = c["r"][0]
+        v1, v2 = c["u"][1] - eps * c["r"][1], c["u"][2] - eps * c["r"][2]
+        N[l] += rn * c["n"]
+        S_[l] += rn * (v1 * c["t1"] + v2 * c["t2"])
+        W[l] += rn
+    speed, spin = np.zeros(L), np.zeros(L)
+    for l in range(L):
+        nn = np.linalg.norm(N[l])
+        if W[l] <= 0 or nn <= 0:
+            continue
+        nb = N[l] / nn
+        speed[l] = np.linalg.norm(S_[l] / W[l])
+        a0, b0, a1, b1 = seg0[l, :3], seg0[l, 3:], seg1[l, :3], seg1[l, 3:]
+        ab = b0 - a0
+        wl = np.cross(ab, ((b1 - b0) - (a1 - a0)) / dt) / ab.dot(ab)
+        spin[l] = (omega - wl).dot(nb)
+    return speed, spin
+
+
+def test_eq3_observation_matches_oracle(pt):
+    # per step, from the oracle's float32-rounded state: force rows to the
+    # usual tolerance; the slip and spin states equal wherever the oracle's
+    # slip speed / spin is clear of its threshold, the slip direction within
+    # 2e-3 (or the speed's relative error) when both slip
+    _say("Eq. 3 observation parity: small config, K=32, 40 steps")
+    cfg = _eq3(S.CONFIGS["small"]).with_(T=10 ** 6)
+    c = cfg.consts
+    K, steps = 32, 40
+    sc0 = S.make_scene(cfg, K=K, steps=steps)
+    sc = dataclasses.replace(S.round_to_f32(sc0), state=sc0.state, params=sc0.params)
+    tr = oracle.Tracker(sc)
+    o = tr.o
+    b = pt.Batch.from_scene(sc)
+    n_ok = n_slip = n_spin = 0
+    fails = []
+    for t in range(steps):
+        u_prev, u = sc.u[max(t - 1, 0)], sc.u[t]
+        st64, pr64, wk, wr64 = tr.state.copy(), tr.params.copy(), tr.wkey.copy(), tr.wr.copy()
+        a_st, a_pr, a_k, a_r = st64.copy(), pr64.copy(), wk.copy(), wr64.copy()
+        o.batch_step(sc.env_type, u_prev, u, a_st, a_pr, a_k, a_r)
+        b_st, b_pr, b_k, b_r = PU.f32(st64), PU.f32(pr64), wk.copy(), PU.f32(wr64)
+        b_obs, b_cont, b_dg = o.batch_step(sc.env_type, u_prev, u, b_st, b_pr, b_k, b_r, want_contacts=True,
+                                           want_diag=True)
+        nonchaotic = (PU.rel_err(a_st, b_st).max(axis=1) < PU.CHAOS_TOL) & \
+            np.array([x == y for x, y in zip(PU.key_sets(a_k), PU.key_sets(b_k))])
+        b.set_state(PU.f32(st64), PU.f32(pr64))
+        b.set_warm(wk, PU.f32(wr64))
+        b.step(_u(u_prev), _u(u))
+        g = PU.obs_from_gpu(b.observe())                       # [K][L][7]
+        seg0, seg1 = o.hand_fk(u_prev), o.hand_fk(u)
+        force_ok = PU.obs_close(g[..., :4], b_obs[..., :4], c.tau_contact)
+        for j in np.nonzero(nonchaotic)[0]:
+            n_ok += 1
+            speed, spin = _slip_and_spin(o, b_cont[j], seg0, seg1, b_st[j, 10:13], c.dt, c.compliance)
+            ok = bool(force_ok[j])
+            for l in range(sc.L):
+                gs, os_ = g[j, l, 4:6], b_obs[j, l, 4:6]
+                if abs(speed[l] - c.tau_slip) > 1e-4 + 1e-3 * speed[l]:
+                    g_sl, o_sl = bool(np.any(gs != 0)), bool(np.any(os_ != 0))
+                    ok &= g_sl == o_sl
+                    if g_sl and o_sl:
+                        n_slip += 1
+                        ok &= np.abs(gs - os_).max() <= max(2e-3, 4e-5 / speed[l])
+                if abs(abs(spin[l]) - c.tau_spin) > 1e-3:
+                    ok &= g[j, l, 6] == b_obs[j, l, 6]
+                    n_spin += int(b_obs[j, l, 6] != 0)
+            if not ok:
+                fails.append((t, int(j)))
+        tr.step()
+    b.close()
+    _say(f"{n_ok} non-chaotic env-steps, {n_slip} slipping and {n_spin} spinning sensor-steps compared, "
+         f"{len(fails)} outside: {fails[:10]}")
+    assert n_ok >= 0.5 * K * steps
+    assert n_slip > 0 and n_spin > 0
+    assert len(fails) <= 0.01 * n_ok, fails[:20]
+
+
+def test_eq3_batched_equals_plain_bitwise(pt):
+    _say("Eq. 3: plain vs batched, small K=37")
+    cfg = _eq3(S.CONFIGS["small"])
+    sc = S.make_scene(cfg, K=37, steps=40)
+    ref = run_plain(pt, sc, 3, cfg.T)
+    assert ref["obs"].shape[1] == 7
+    for graph in (False, True):
+        got = run_batched(pt, sc, 3, cfg.T, graph=graph)
+        _assert_same(ref, got, f"graph={graph}")
+
+
+def test_eq3_has_no_gradient(pt):
+    cfg = _eq3(S.CONFIGS["small"])
+    sc = S.make_scene(cfg, K=8, steps=20)
+    b = pt.Batch.from_scene(sc)
+    u = torch.zeros((cfg.T + 1, sc.D), device="cuda")
+    gt = torch.zeros((cfg.T, 7, sc.L, sc.G), device="cuda")
+    env = torch.arange(2, dtype=torch.int32, device="cuda")
+    start, warm0 = b.start_of(env)
+    with pytest.raises(pt.PtError):
+        b.window_grad(u, gt, env, start, warm0)
+    b.close()

@@ -67,9 +67,10 @@ def run_batched(pt, sc, windows, T, graph, wpb=None, resample=True, solve_precis
     costh = torch.zeros(sc.G, device="cuda")
     best = torch.zeros(sc.G, dtype=torch.int32, device="cuda")
     parent = torch.zeros(sc.K, dtype=torch.int32, device="cuda")
-    gtw = torch.zeros((T, 4, sc.L, sc.G), device="cuda")
-    dummy = torch.zeros((T, 4, sc.L, sc.G), device="cuda")
-    obs_w = torch.zeros((T, 4, sc.L, sc.K), device="cuda")
+    R = b.obs_rows
+    gtw = torch.zeros((T, R, sc.L, sc.G), device="cuda")
+    dummy = torch.zeros((T, R, sc.L, sc.G), device="cuda")
+    obs_w = torch.zeros((T, R, sc.L, sc.K), device="cuda")
     uw = torch.zeros((T + 1, sc.D), device="cuda")
     if wpb is not None:
         b.set_tuning(wpb)
