@@ -23,6 +23,7 @@ batched variants on the 1024-simulation differentiation workload
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import math
 import os
@@ -112,7 +113,8 @@ def algorithmic_bytes(C_max):
 
 def observed_forces(pt, sc, dev, solve_precision, n_steps, pose_every=None):
     """The observed ("real") simulation's sensor forces for steps
-    0..n_steps-1, [n_steps][4][L][G].  They are the tracker's input stream
+    0..n_steps-1, [n_steps][R][L][G] (R = 4, or 7 under the full cost of
+    Eq. 3).  They are the tracker's input stream
     (the robot's contact sensors), so they are produced before any timed
     region and stay resident in HBM.  With pose_every = T also the observed
     object's state after every T steps ([n_steps / T][13][G], for the
@@ -120,7 +122,7 @@ def observed_forces(pt, sc, dev, solve_precision, n_steps, pose_every=None):
     import torch
     u_all = torch.as_tensor(sc.u.astype("float32"), device=dev)
     h = pt.Batch.from_scene(sc, hidden=True, solve_precision=solve_precision)
-    out = torch.empty((n_steps, 4, sc.L, sc.G), device=dev)
+    out = torch.empty((n_steps, h.obs_rows, sc.L, sc.G), device=dev)
     poses = []
     for t in range(n_steps):
         h.step(u_all[max(t - 1, 0)], u_all[t])
@@ -146,7 +148,7 @@ def batched_run(pt, S, sc, dev, solve_precision, n_win, n_warm, adjoint):
     u_all = torch.as_tensor(sc.u.astype("float32"), device=dev)
     main_b = pt.Batch.from_scene(sc, solve_precision=solve_precision, window_checkpoints=adjoint)
     u_win = torch.empty((T + 1, sc.D), device=dev)
-    gt_win = torch.empty((T, 4, L, G), device=dev)
+    gt_win = torch.empty((T, main_b.obs_rows, L, G), device=dev)
     cost = torch.zeros(K, device=dev)
     best = torch.zeros(G, dtype=torch.int32, device=dev)
     parent = torch.zeros(K, dtype=torch.int32, device=dev)
@@ -217,11 +219,15 @@ WRS_LAMBDA = 1.0
 REPS_EPS = 1.0
 
 
-def realtime_setup(pt, S, dev, solve_precision, n_total):
+def realtime_setup(pt, S, dev, solve_precision, n_total, cost_mode=0):
     """Scene, observed forces and observed poses of the real-time workload,
-    shared by the optimisers compared on it."""
+    shared by the optimisers compared on it (cost_mode 1: the full cost of
+    Eq. 3 and its seven-row observation)."""
+    import dataclasses
     import torch
     cfg = S.CONFIGS["realtime16384"]
+    if cost_mode:
+        cfg = cfg.with_(consts=dataclasses.replace(cfg.consts, cost_mode=cost_mode))
     T = cfg.T
     sc = S.make_scene(cfg, steps=(n_total + 1) * T + 1)
     gts, hposes = observed_forces(pt, sc, dev, solve_precision, n_total * T, pose_every=T)
@@ -229,7 +235,46 @@ def realtime_setup(pt, S, dev, solve_precision, n_total):
     return {"cfg": cfg, "sc": sc, "gts": gts, "hposes": hposes, "u_all": u_all}
 
 
-def realtime_run(pt, S, dev, solve_precision, n_win, n_warm=2, optimizer="pbo", setup=None):
+def eq3_weights(pt, setup, dev, solve_precision):
+    """Weights w4..w10 of Eq. 3 such that every term's mean magnitude over
+    the population's first window is 1 (Sec. III-C): one window without
+    resampling, its observations against the observed ones, the mean of each
+    gated term over simulations, sensors and steps."""
+    import numpy as np
+    import torch
+    cfg, sc, gts, u_all = setup["cfg"], setup["sc"], setup["gts"], setup["u_all"]
+    T, K, G, L = cfg.T, sc.K, sc.G, sc.L
+    c = cfg.consts
+    b = pt.Batch.from_scene(sc, solve_precision=solve_precision)
+    obs_w = torch.zeros((T, 7, L, K), device=dev)
+    b.run_window(torch.cat([u_all[:1], u_all[:T]], 0), gts[:T].contiguous(), torch.zeros(K, device=dev), None,
+                 obs_w, graph=False)
+    torch.cuda.synchronize()
+    b.close()
+    o = obs_w.cpu().numpy().astype(np.float64)
+    group = np.repeat(np.arange(G), np.diff(np.asarray(sc.group_start)))
+    g = gts[:T].cpu().numpy().astype(np.float64)[:, :, :, group]
+
+    def angle(a, b):       # rows on axis 1
+        if a.shape[1] == 2:
+            cr = np.abs(a[:, 0] * b[:, 1] - a[:, 1] * b[:, 0])
+        else:
+            cr = np.linalg.norm(np.cross(a, b, axis=1), axis=1)
+        return np.arctan2(cr, (a * b).sum(axis=1))
+
+    ina, inb = o[:, 0] > c.tau_contact, g[:, 0] > c.tau_contact
+    sla, slb = (o[:, 4] != 0) | (o[:, 5] != 0), (g[:, 4] != 0) | (g[:, 5] != 0)
+    roa, rob = o[:, 6] != 0, g[:, 6] != 0
+    alpha, beta, gamma = ina == inb, sla == slb, roa == rob
+    terms = [~alpha, alpha * np.abs(o[:, 0] - g[:, 0]), alpha * ina * angle(o[:, 1:4], g[:, 1:4]),
+             ~beta, beta * sla * angle(o[:, 4:6], g[:, 4:6]),
+             ~gamma, gamma * roa * np.abs((o[:, 6] > 0).astype(float) - (g[:, 6] > 0))]
+    means = [float(np.mean(t)) for t in terms]
+    return tuple(1.0 / m if m > 0 else 1.0 for m in means)
+
+
+def realtime_run(pt, S, dev, solve_precision, n_win, n_warm=2, optimizer="pbo", setup=None, refine=True,
+                 describe=False):
     """The real-time workload: 16384 simulations in 16 groups (one
     superquadric object each), batched windows; with optimizer "pbo", "wrs"
     or "reps" the elites are refined before every resampling by that
@@ -250,9 +295,10 @@ def realtime_run(pt, S, dev, solve_precision, n_win, n_warm=2, optimizer="pbo", 
     T = cfg.T
     K, G, L = sc.K, sc.G, sc.L
     adapt = optimizer != "eye"
-    b = pt.Batch.from_scene(sc, solve_precision=solve_precision, window_checkpoints=adapt)
+    refine = refine and adapt
+    b = pt.Batch.from_scene(sc, solve_precision=solve_precision, window_checkpoints=refine)
     u_win = torch.empty((T + 1, sc.D), device=dev)
-    gt_win = torch.empty((T, 4, L, G), device=dev)
+    gt_win = torch.empty((T, b.obs_rows, L, G), device=dev)
     cost = torch.zeros(K, device=dev)
     best = torch.zeros(G, dtype=torch.int32, device=dev)
     parent = torch.zeros(K, dtype=torch.int32, device=dev)
@@ -268,12 +314,12 @@ def realtime_run(pt, S, dev, solve_precision, n_win, n_warm=2, optimizer="pbo", 
         ev[w][0].record()
         u_win.copy_(u_all[t0_ - 1: t0_ + T] if t0_ > 0 else torch.cat([u_all[:1], u_all[:T]], 0))
         gt_win.copy_(gts[t0_: t0_ + T])
-        if adapt:
+        if refine:
             snap[0].copy_(b.state)
             snap[1].copy_(b.params)
             snap[2].copy_(b.warm)
         b.run_window(u_win, gt_win, cost, best, None, graph=True)
-        if adapt:
+        if refine:
             b.refine_elites(u_win, gt_win, cost, snap, steps=3, step=0.5, best=best)
         torch.index_select(b.state, 1, best, out=est[w])
         if not adapt:
@@ -324,7 +370,7 @@ def realtime_run(pt, S, dev, solve_precision, n_win, n_warm=2, optimizer="pbo", 
            "waves_per_workgroup": tuned}
     if not adapt:
         out["open_loop_tracking_error_mm"] = tracking(est_olp.cpu().numpy())
-    if optimizer == "pbo":
+    if describe:
         out = {"workload": f"{cfg.name}: {K} simulations in {G} groups (one {int(sc.n_spheres[0])}-sphere "
                            f"superquadric object each) + {G} observed, {L} capsule links, C_max={cfg.C_max}, "
                            f"{cfg.newton_iters} Newton iterations, {T}-step windows, elite refinement (3 steps) and "
@@ -474,7 +520,8 @@ def main():
     if not args.no_batched and not args.no_adjoint and args.realtime_windows > 0:
         n_rt = args.realtime_windows if not args.profile else 3
         rt_setup = realtime_setup(pt, S, dev, args.solve_precision, n_rt + 2)
-        result["realtime16384"] = realtime_run(pt, S, dev, args.solve_precision, n_rt, setup=rt_setup)
+        result["realtime16384"] = realtime_run(pt, S, dev, args.solve_precision, n_rt, setup=rt_setup,
+                                               describe=True)
         if not args.no_optimizers:
             # the paper's other optimisers and its identity baseline on the
             # same workload (Sec. III-D, Sec. IV), same windows and refinement
@@ -483,7 +530,19 @@ def main():
                         **realtime_run(pt, S, dev, args.solve_precision, n_rt, optimizer="wrs", setup=rt_setup)},
                 "reps": {"epsilon": REPS_EPS,
                          **realtime_run(pt, S, dev, args.solve_precision, n_rt, optimizer="reps", setup=rt_setup)},
-                "eye": realtime_run(pt, S, dev, args.solve_precision, n_rt, optimizer="eye", setup=rt_setup)}
+                "eye": realtime_run(pt, S, dev, args.solve_precision, n_rt, optimizer="eye", setup=rt_setup),
+                # the cost itself: PBO without refinement (the full cost has no
+                # gradient) on the force terms and on the full Eq. 3
+                "pbo_no_refinement": realtime_run(pt, S, dev, args.solve_precision, n_rt, setup=rt_setup,
+                                                  refine=False)}
+            eq3_setup = realtime_setup(pt, S, dev, args.solve_precision, n_rt + 2, cost_mode=1)
+            w_eq3 = eq3_weights(pt, eq3_setup, dev, args.solve_precision)
+            sc3 = eq3_setup["sc"]
+            cfg3 = sc3.cfg.with_(consts=dataclasses.replace(sc3.cfg.consts, w_eq3=w_eq3))
+            eq3_setup.update(cfg=cfg3, sc=dataclasses.replace(sc3, cfg=cfg3))
+            result["realtime16384"]["optimizers"]["pbo_eq3_cost"] = {
+                "w4_w10": [round(x, 4) for x in w_eq3],
+                **realtime_run(pt, S, dev, args.solve_precision, n_rt, setup=eq3_setup, refine=False)}
 
     # ---------------- CPU baseline: the FP64 oracle ----------------------
     if not args.no_cpu_baseline and not args.profile:
