@@ -90,6 +90,20 @@ __device__ __forceinline__ double dpp_f(double v)
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// A wave-uniform value (the same bits in every lane) moved to scalar
+// registers, where it costs no vector register while it stays live
+__device__ __forceinline__ float uniform(float x)
+{
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
+}
+__device__ __forceinline__ double uniform(double x)
+{
+    long long b = __double_as_longlong(x);
+    int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffffll));
+    int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 // readlane moves 32-bit integers: reinterpret, never convert
 __device__ __forceinline__ float bcast_lane(float v, int lane)
 {
@@ -608,6 +622,10 @@ __device__ __forceinline__ void body_mass(float m, const float *Iinv, const floa
 #pragma unroll
         for (int i = 0; i < 9; ++i) M.blk[i] = I9[i];
     }
+    // wave-uniform: held in scalar registers through the Newton loop
+    M.sc = uniform(M.sc);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) M.blk[i] = uniform(M.blk[i]);
 }
 
 // Solves (I + M^-1 A6) z = -M^-1 b6 for the summed acc (A6 = acc[0..35],

@@ -91,6 +91,23 @@ __device__ __forceinline__ void step_pose(const Consts &P, const float *inv_in, 
     st.vs[1] = B.v[1] + dt * (P.gy + B.f[1] * im);
     st.vs[2] = B.v[2] + dt * (P.gz + B.f[2] * im);
     st.ws[0] = B.w[0]; st.ws[1] = B.w[1]; st.ws[2] = B.w[2];
+    // wave-uniform values to scalar registers (they stay live through the
+    // whole step)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) st.q[i] = uniform(st.q[i]);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        st.R[i] = uniform(st.R[i]);
+        st.Iinv[i] = uniform(st.Iinv[i]);
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        st.ii[i] = uniform(st.ii[i]);
+        st.vs[i] = uniform(st.vs[i]);
+        st.ws[i] = uniform(st.ws[i]);
+    }
+    st.m = uniform(st.m);
+    st.im = uniform(st.im);
 }
 
 // phase 4: geometry of the contact with key `key` held by this lane (key < 0:
