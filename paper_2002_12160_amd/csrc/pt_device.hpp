@@ -104,6 +104,19 @@ __device__ __forceinline__ double uniform(double x)
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// the body after a step is the same in every lane: keep it in scalar registers
+__device__ __forceinline__ void uniform_body(Body &B)
+{
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        B.x[i] = uniform(B.x[i]); B.v[i] = uniform(B.v[i]);
+        B.w[i] = uniform(B.w[i]); B.f[i] = uniform(B.f[i]);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) B.q[i] = uniform(B.q[i]);
+    B.m = uniform(B.m); B.mu = uniform(B.mu);
+}
+
 // readlane moves 32-bit integers: reinterpret, never convert
 __device__ __forceinline__ float bcast_lane(float v, int lane)
 {
@@ -516,12 +529,12 @@ __device__ __forceinline__ void load16<float>(const float *p, float *v)
 // rounds would cost N instructions each: the lanes below n16 = n rounded up
 // to 16 write their values as rows (lanes n .. n16-1 must hold zeros), lane
 // j < N adds column j over the rows, sixteen reads in flight at a time into
-// four interleaved partial sums in a fixed order, the N sums go back to LDS
-// and every lane reads all of them -- the same bits in every lane.  Lanes >=
-// n16 do not take part.  buf: 16-byte aligned, n16 rows of RedStride<T>
-// elements.
+// four interleaved partial sums in a fixed order, and the N sums land in
+// buf[0..N), where every lane can read them (the same bits for every lane).
+// Lanes >= n16 do not take part.  buf: 16-byte aligned, n16 rows of
+// RedStride<T> elements.  The sums stay valid until the next write to buf.
 template <typename T, int N>
-__device__ __forceinline__ void lds_sum(T (&v)[N], int n, T *buf)
+__device__ __forceinline__ void lds_colsum(const T (&v)[N], int n, T *buf)
 {
     constexpr int RS = RedStride<T>::value;
     constexpr int PER = 16 / (int)sizeof(T);
@@ -551,6 +564,14 @@ __device__ __forceinline__ void lds_sum(T (&v)[N], int n, T *buf)
     wave_sync();
     if (lane < N) buf[lane] = s;
     wave_sync();
+}
+
+// lds_colsum with the N sums read back into v in every lane
+template <typename T, int N>
+__device__ __forceinline__ void lds_sum(T (&v)[N], int n, T *buf)
+{
+    constexpr int PER = 16 / (int)sizeof(T);
+    lds_colsum<T, N>(v, n, buf);
 #pragma unroll
     for (int j = 0; j + PER <= N; j += PER) load16<T>(buf + j, v + j);
 #pragma unroll

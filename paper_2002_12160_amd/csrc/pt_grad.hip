@@ -81,11 +81,12 @@ __global__ __launch_bounds__(WAVE) void k_window_fwd(Consts P, Tables tb, const 
         const float *seg = seg_win + (size_t)t * P.L * SEG_STRIDE;
         StepState<SR> st;
         step_setup<SR>(P, seg, sph, S, inv, B, wkey, wr, lds, stt, st);
-        step_solve<SR>(P, st, B.mu, inv, reinterpret_cast<SR *>(lds.cand_d));
+        step_solve<SR, true>(P, st, B.mu, inv, reinterpret_cast<SR *>(lds.cand_d));
         if (ck) save_contact<SR>(ck, P.C_max, st);
         int link;
         float imp[3];
         step_finish<SR>(P, st, inv, B, wkey, wr, link, imp);
+        uniform_body(B);
         *reinterpret_cast<float4 *>(stage + 4 * lane) = make_float4(__int_as_float(link), imp[0], imp[1], imp[2]);
         wave_sync();
         float o[4];

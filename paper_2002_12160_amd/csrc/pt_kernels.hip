@@ -457,9 +457,10 @@ __global__ __launch_bounds__(StepBounds<SR>::threads) void k_window(Consts P, Ta
             if (ck) save_body(ck, B);
             StepState<SR> sst;
             step_setup<SR>(P, seg, sph, S, inv, B, wkey, wr, lds, st, sst);
-            step_solve<SR>(P, sst, B.mu, inv, reinterpret_cast<SR *>(lds.cand_d));
+            step_solve<SR, true>(P, sst, B.mu, inv, reinterpret_cast<SR *>(lds.cand_d));
             if (ck) save_contact<SR>(ck, P.C_max, sst);
             step_finish<SR>(P, sst, inv, B, wkey, wr, link, imp);
+            uniform_body(B);
             *reinterpret_cast<float4 *>(stage + 4 * lane) = make_float4(__int_as_float(link), imp[0], imp[1], imp[2]);
             // Eq. 3 (cost_mode 1): the contacts' slip records staged in the
             // candidate list's LDS, free between the solve and the next

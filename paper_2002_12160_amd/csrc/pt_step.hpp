@@ -331,8 +331,11 @@ __device__ __forceinline__ void step_setup(const Consts &P, const float *__restr
 // -M^-1 sum_c J_c^T P_c^-1 Phi_c with P_c = JX_c + eps JY_c, B_c = JY_c; then
 // dr_c = -P_c^-1 (Phi_c + B_c J_c dnu).  Leaves st.r and the fresh st.nu.
 // red: LDS for the cross-contact sum of the 6x6 system (the wave's candidate
-// list, free once the cap has run).
-template <typename SR>
+// list, free once the cap has run).  SumsInLds: the 6x6 solve reads the
+// summed system from LDS as it goes instead of from registers loaded all at
+// once (fewer live registers, so two wavefronts fit on a SIMD; a little more
+// latency per iteration).
+template <typename SR, bool SumsInLds = false>
 __device__ __forceinline__ void step_solve(const Consts &P, StepState<SR> &st, float mu_f, const float *inv_in,
                                            SR *red)
 {
@@ -391,10 +394,17 @@ __device__ __forceinline__ void step_solve(const Consts &P, StepState<SR> &st, f
 #pragma unroll
                 for (int i = 0; i < 43; ++i) acc[i] = SR(0);
             }
-            lds_sum<SR, 43>(acc, st.C, red);
-            const SR psi = acc[42];
-            SR rhs[6];
-            schur_solve(acc, Mb, rhs);
+            SR psi, rhs[6];
+            if constexpr (SumsInLds) {
+                // the sums stay valid in LDS until the next iteration's rows
+                lds_colsum<SR, 43>(acc, st.C, red);
+                psi = red[42];
+                schur_solve(red, Mb, rhs);
+            } else {
+                lds_sum<SR, 43>(acc, st.C, red);
+                psi = acc[42];
+                schur_solve(acc, Mb, rhs);
+            }
             // dr = -g - Q F (dv + dw x rho)
             SR dp[3];
             SR dw3[3] = {rhs[3], rhs[4], rhs[5]};
