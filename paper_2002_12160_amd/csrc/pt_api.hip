@@ -290,7 +290,7 @@ pt_status pt_create_batch(const pt_batch_desc *d, pt_batch *out)
     HIP_TRY_C(hipMalloc(&b->d_group_start, sizeof(int32_t) * (d->G + 1)));
     HIP_TRY_C(hipMalloc(&b->d_order, sizeof(int32_t) * K));
     HIP_TRY_C(hipMalloc(&b->d_queue, sizeof(int32_t) * 4));
-    HIP_TRY_C(hipMalloc(&b->d_stats, sizeof(int64_t) * 4));
+    HIP_TRY_C(hipMalloc(&b->d_stats, sizeof(int64_t) * pt::STATS_SLOTS * pt::STATS_STRIDE));
     HIP_TRY_C(hipMalloc(&b->d_seg_win, sizeof(float) * (size_t)d->T * d->L * pt::SEG_STRIDE));
     HIP_TRY_C(hipMalloc(&b->d_contacts, sizeof(float) * K * d->C_max * 4));
     HIP_TRY_C(hipMalloc(&b->d_seg_grad, sizeof(float) * (size_t)d->T * d->L * pt::SEG_STRIDE));
@@ -316,13 +316,16 @@ pt_status pt_create_batch(const pt_batch_desc *d, pt_batch *out)
     HIP_TRY_C(hipMemcpy(b->d_group_start, d->group_start, sizeof(int32_t) * (d->G + 1), hipMemcpyHostToDevice));
     HIP_TRY_C(hipMemcpy(b->d_order, order.data(), sizeof(int32_t) * K, hipMemcpyHostToDevice));
     HIP_TRY_C(hipMemset(b->d_queue, 0, sizeof(int32_t) * 4));
-    HIP_TRY_C(hipMemset(b->d_stats, 0, sizeof(int64_t) * 4));
+    HIP_TRY_C(hipMemset(b->d_stats, 0, sizeof(int64_t) * pt::STATS_SLOTS * pt::STATS_STRIDE));
     HIP_TRY_C(hipMemset(b->d_contacts, 0, sizeof(float) * K * d->C_max * 4));
     HIP_TRY_C(hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking));
     // environments per workgroup within the LDS budget (autotuned later)
     b->wpb = 4;
     while (b->wpb > 1 && ((size_t)b->wpb * wave_lds > 160 * 1024 || b->wpb > max_wpb(P))) b->wpb >>= 1;
-    b->step_wpb = b->wpb;
+    // the per-step launch: one simulation per workgroup, so that up to one
+    // wavefront per compute unit has its LDS, caches and issue to itself
+    // (measured faster than four per workgroup at 256 simulations)
+    b->step_wpb = 1;
 #undef HIP_TRY_C
     *out = b;
     return PT_OK;
@@ -662,7 +665,13 @@ pt_status pt_read_stats(pt_batch b, int64_t *out, pt_stream s)
 {
     if (!b || !out) return fail(PT_E_ARG, "batch/out is NULL");
     HIP_TRY(hipStreamSynchronize((hipStream_t)s));
-    HIP_TRY(hipMemcpy(out, b->d_stats, sizeof(int64_t) * 4, hipMemcpyDeviceToHost));
+    std::vector<int64_t> slots((size_t)pt::STATS_SLOTS * pt::STATS_STRIDE);
+    HIP_TRY(hipMemcpy(slots.data(), b->d_stats, sizeof(int64_t) * slots.size(), hipMemcpyDeviceToHost));
+    for (int j = 0; j < 4; ++j) {
+        int64_t t = 0;
+        for (int k = 0; k < pt::STATS_SLOTS; ++k) t += slots[(size_t)k * pt::STATS_STRIDE + j];
+        out[j] = t;
+    }
     return PT_OK;
 }
 

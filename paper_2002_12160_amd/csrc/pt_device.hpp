@@ -528,8 +528,8 @@ __device__ __forceinline__ void load16<float>(const float *p, float *v)
 // Sum of v[0..N) over lanes [0, n) through LDS, for wide vectors where DPP
 // rounds would cost N instructions each: the lanes below n16 = n rounded up
 // to 16 write their values as rows (lanes n .. n16-1 must hold zeros), lane
-// j < N adds column j over the rows, sixteen reads in flight at a time into
-// four interleaved partial sums in a fixed order, and the N sums land in
+// j < N adds column j over the rows, 32 reads in flight at a time (16 for a
+// last odd block) into four interleaved partial sums in a fixed order, and the N sums land in
 // buf[0..N), where every lane can read them (the same bits for every lane).
 // Lanes >= n16 do not take part.  buf: 16-byte aligned, n16 rows of
 // RedStride<T> elements.  The sums stay valid until the next write to buf.
@@ -552,7 +552,15 @@ __device__ __forceinline__ void lds_colsum(const T (&v)[N], int n, T *buf)
     T s4[4] = {T(0), T(0), T(0), T(0)};
     if (lane < N) {
         const T *col = buf + lane;
-        for (int r0 = 0; r0 < n16; r0 += 16, col += 16 * RS) {
+        int r0 = 0;
+        for (; r0 + 32 <= n16; r0 += 32, col += 32 * RS) {
+            T x[32];
+#pragma unroll
+            for (int k = 0; k < 32; ++k) x[k] = col[k * RS];
+#pragma unroll
+            for (int k = 0; k < 32; ++k) s4[k & 3] += x[k];
+        }
+        if (r0 < n16) {
             T x[16];
 #pragma unroll
             for (int k = 0; k < 16; ++k) x[k] = col[k * RS];

@@ -62,7 +62,7 @@ __global__ __launch_bounds__(WAVE) void k_window_fwd(Consts P, Tables tb, const 
     const int g = tb.group_of[e];
     const int S = tb.n_spheres[type];
     const float *sph = tb.spheres + (size_t)type * P.S_max * 4;
-    const float *inv = tb.inv_inertia + 3 * type;
+    const float inv[3] = {tb.inv_inertia[3 * type], tb.inv_inertia[3 * type + 1], tb.inv_inertia[3 * type + 2]};
     const size_t LG = (size_t)P.L * P.G;
     const size_t CK = ckpt_step_floats(P.C_max);
 
@@ -140,7 +140,7 @@ __global__ __launch_bounds__(WAVE) void k_window_bwd(Consts P, Tables tb, const 
     const int type = tb.env_type[e];
     const int g = tb.group_of[e];
     const float *sph = tb.spheres + (size_t)type * P.S_max * 4;
-    const float *inv = tb.inv_inertia + 3 * type;
+    const float inv[3] = {tb.inv_inertia[3 * type], tb.inv_inertia[3 * type + 1], tb.inv_inertia[3 * type + 2]};
     const size_t LG = (size_t)P.L * P.G;
     const size_t CK = ckpt_step_floats(P.C_max);
     const float m0 = xi[13 * (size_t)n + i], mu0 = xi[14 * (size_t)n + i];

@@ -29,6 +29,13 @@ struct RefineArgs {
 // cost or window kernel instead of a launch of their own
 constexpr int FUSED_ARGMIN_MAX = 4096;
 
+// step statistics (steps, candidates, contacts, dropped) are accumulated in
+// STATS_SLOTS slots one 128-byte line apart, a wavefront adding to slot
+// (its index mod STATS_SLOTS): the atomics of a launch spread over many
+// lines instead of queueing on one; the totals are the slots' sums
+constexpr int STATS_SLOTS = 256;
+constexpr int STATS_STRIDE = 16;   // int64 per slot
+
 // rows of a window start: x(3) q(4) v(3) w(3) m mu f(3)
 constexpr int XI_ROWS = 18;
 

@@ -77,13 +77,15 @@ __device__ __forceinline__ void store_warm(float *__restrict__ warm, int C_max, 
             make_float4(__int_as_float(wkey), wr[0], wr[1], wr[2]);
 }
 
-__device__ __forceinline__ void flush_stats(int64_t *stats, const StepStats &st, int64_t steps)
+__device__ __forceinline__ void flush_stats(int64_t *stats, const StepStats &st, int64_t steps, int slot)
 {
     if (lane_id() == 0) {
-        atomicAdd((unsigned long long *)&stats[0], (unsigned long long)steps);
-        atomicAdd((unsigned long long *)&stats[1], (unsigned long long)st.cand);
-        atomicAdd((unsigned long long *)&stats[2], (unsigned long long)st.contacts);
-        atomicAdd((unsigned long long *)&stats[3], (unsigned long long)st.dropped);
+        unsigned long long *p =
+            reinterpret_cast<unsigned long long *>(stats + (size_t)(slot & (STATS_SLOTS - 1)) * STATS_STRIDE);
+        atomicAdd(p + 0, (unsigned long long)steps);
+        atomicAdd(p + 1, (unsigned long long)st.cand);
+        atomicAdd(p + 2, (unsigned long long)st.contacts);
+        atomicAdd(p + 3, (unsigned long long)st.dropped);
     }
 }
 

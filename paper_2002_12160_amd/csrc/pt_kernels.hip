@@ -233,14 +233,16 @@ __global__ __launch_bounds__(StepBounds<SR>::threads) void k_step(Consts P, Tabl
                                                int64_t *__restrict__ stats)
 {
     extern __shared__ __align__(16) char smem[];
-    const int wib = threadIdx.x / WAVE;
+    // the simulation index is wave-uniform: its per-simulation loads go
+    // through scalar registers
+    const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
     const int e = xcd_block(blockIdx.x, gridDim.x) * (blockDim.x / WAVE) + wib;
     if (e >= P.K) return;
     WaveLds lds = carve_lds(smem, wib, P.max_cand, P.L);
     const int type = tb.env_type[e];
     const int S = tb.n_spheres[type];
     const float *sph = tb.spheres + (size_t)type * P.S_max * 4;
-    const float *inv = tb.inv_inertia + 3 * type;
+    const float inv[3] = {tb.inv_inertia[3 * type], tb.inv_inertia[3 * type + 1], tb.inv_inertia[3 * type + 2]};
     Body B;
     load_body(state, params, P.K, e, B);
     int wkey;
@@ -280,7 +282,7 @@ __global__ __launch_bounds__(StepBounds<SR>::threads) void k_step(Consts P, Tabl
     if (lane < P.C_max)
         *reinterpret_cast<float4 *>(contacts + ((size_t)e * P.C_max + lane) * 4) =
             make_float4(__int_as_float(link), imp[0], imp[1], imp[2]);
-    flush_stats(stats, st, 1);
+    flush_stats(stats, st, 1, e);
 }
 
 // one wavefront per simulation, lanes over sensors
@@ -439,7 +441,7 @@ __global__ __launch_bounds__(StepBounds<SR>::threads) void k_window(Consts P, Ta
         const int g = tb.group_of[e];
         const int S = tb.n_spheres[type];
         const float *sph = tb.spheres + (size_t)type * P.S_max * 4;
-        const float *inv = tb.inv_inertia + 3 * type;
+        const float inv[3] = {tb.inv_inertia[3 * type], tb.inv_inertia[3 * type + 1], tb.inv_inertia[3 * type + 2]};
         Body B;
         load_body(state, params, P.K, e, B);
         int wkey;
@@ -513,7 +515,7 @@ __global__ __launch_bounds__(StepBounds<SR>::threads) void k_window(Consts P, Ta
         if (lane == 0) cost_sum[e] = cost;
         done += P.T;
     }
-    flush_stats(stats, st, done);
+    flush_stats(stats, st, done, blockIdx.x * (blockDim.x / WAVE) + wib);
     // the workgroup that finishes last ranks every group (Eq. 2) and puts the
     // work queue back to 0 for the next window
     // (the block's dynamic LDS is free once every wave has left the loop)
