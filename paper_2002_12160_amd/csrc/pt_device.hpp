@@ -147,6 +147,45 @@ __device__ __forceinline__ uint64_t pack_gap_key(float d, int k)
     return ((uint64_t)u << 32) | (uint32_t)k;
 }
 
+// One half-wave's values in both halves: lanes i and i + 32 both end with
+// what lane i held (from_upper false) or what lane i + 32 held (true).  One
+// ds_bpermute per 32-bit word (the LDS crossbar, no LDS memory).
+__device__ __forceinline__ uint32_t half_bcast(uint32_t x, bool from_upper)
+{
+    const int src = from_upper ? (lane_id() | 32) : (lane_id() & 31);
+    return (uint32_t)__builtin_amdgcn_ds_bpermute(src << 2, (int)x);
+}
+__device__ __forceinline__ float half_bcast(float x, bool from_upper)
+{
+    return __uint_as_float(half_bcast(__float_as_uint(x), from_upper));
+}
+__device__ __forceinline__ double half_bcast(double x, bool from_upper)
+{
+    const uint64_t b = (uint64_t)__double_as_longlong(x);
+    const uint32_t lo = half_bcast((uint32_t)b, from_upper), hi = half_bcast((uint32_t)(b >> 32), from_upper);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+// Sums of one value over the first span <= 32 lanes of each half-wave, by the
+// same DPP tree as wave_sum (so each half's sum has the bits wave_sum gives
+// for the lower half alone): lo over lanes [0, span), hi over [32, 32 + span)
+template <typename T>
+__device__ __forceinline__ void half_sums(T v, int span, T &lo, T &hi)
+{
+    v += dpp_f<0x111, 0xf>(v);  // row_shr:1
+    v += dpp_f<0x112, 0xf>(v);  // row_shr:2
+    v += dpp_f<0x114, 0xf>(v);  // row_shr:4
+    v += dpp_f<0x118, 0xf>(v);  // row_shr:8
+    if (span <= 16) {
+        lo = bcast_lane(v, 15);
+        hi = bcast_lane(v, 47);
+        return;
+    }
+    v += dpp_f<0x142, 0xa>(v);  // row_bcast:15 into rows 1, 3
+    lo = bcast_lane(v, 31);
+    hi = bcast_lane(v, 63);
+}
+
 template <typename T, int N>
 __device__ __forceinline__ void wave_sum(T (&v)[N], int span = 64)
 {

@@ -261,7 +261,7 @@ __global__ __launch_bounds__(StepBounds<SR>::threads) void k_step(Consts P, Tabl
     float imp[3];
     StepState<SR> sst;
     step_setup<SR>(P, seg, sph, S, inv, B, wkey, wr, lds, st, sst);
-    step_solve<SR>(P, sst, B.mu, inv, reinterpret_cast<SR *>(lds.cand_d));
+    step_solve<SR, false, true>(P, sst, B.mu, inv, reinterpret_cast<SR *>(lds.cand_d));
     step_finish<SR>(P, sst, inv, B, wkey, wr, link, imp);
     const int lane = lane_id();
     if (EQ3) {

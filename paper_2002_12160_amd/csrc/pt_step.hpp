@@ -179,6 +179,45 @@ __device__ __forceinline__ void contact_setup(const Consts &P, const float *__re
     }
 }
 
+// The cap's ranking for ncand <= 64 H candidates: lane i holds candidates
+// i, i + 64, ... as packed (d, key) words (lanes past ncand the largest
+// word, never below a candidate's, so the counts run over whole groups of
+// four lanes); every word is broadcast once and each lane counts the lower
+// ones for each word it holds.  Keys are unique, so the ranks are a
+// permutation; the C_max lowest candidates' keys land in sel[rank].
+template <int H>
+__device__ __forceinline__ void cap_rank(const WaveLds &lds, int ncand, int C_max)
+{
+    const int lane = lane_id();
+    uint64_t w[H];
+    int ki[H], rank[H];
+#pragma unroll
+    for (int h = 0; h < H; ++h) {
+        const int i = lane + WAVE * h;
+        w[h] = ~0ull;
+        ki[h] = 0;
+        rank[h] = 0;
+        if (i < ncand) {
+            ki[h] = lds.cand_k[i];
+            w[h] = pack_gap_key(lds.cand_d[i], ki[h]);
+        }
+    }
+#pragma unroll
+    for (int hb = 0; hb < H; ++hb) {
+        const int n = min(WAVE, ncand - WAVE * hb);
+        for (int j = 0; j < n; j += 4) {
+            const uint64_t a = bcast_lane(w[hb], j), b = bcast_lane(w[hb], j + 1);
+            const uint64_t c = bcast_lane(w[hb], j + 2), d = bcast_lane(w[hb], j + 3);
+#pragma unroll
+            for (int h = 0; h < H; ++h)
+                rank[h] += (a < w[h] ? 1 : 0) + (b < w[h] ? 1 : 0) + (c < w[h] ? 1 : 0) + (d < w[h] ? 1 : 0);
+        }
+    }
+#pragma unroll
+    for (int h = 0; h < H; ++h)
+        if (lane + WAVE * h < ncand && rank[h] < C_max) lds.sel[rank[h]] = ki[h];
+}
+
 // phases 1-4: pose, free velocity, narrow phase, cap, contact setup, warm start
 template <typename SR>
 __device__ __forceinline__ void step_setup(const Consts &P, const float *__restrict__ seg,
@@ -242,27 +281,17 @@ __device__ __forceinline__ void step_setup(const Consts &P, const float *__restr
     st.span = lane_span(C);
 
     // 3. cap: rank of every candidate in (d, key) order; the C_max lowest
-    //    land in sel[rank].  Up to a wave of candidates each lane holds one
-    //    as a packed (d, key) word and counts the lower words, broadcast
-    //    lane by lane; beyond, every lane ranks its candidates against the
-    //    LDS list, eight per pair of 16-byte reads (entries past ncand padded
-    //    with (+inf, INT_MAX), never below).
+    //    land in sel[rank].  Up to four waves of candidates each lane holds
+    //    one to four of them as packed (d, key) words and counts the lower
+    //    words, broadcast lane by lane; beyond, every lane ranks its
+    //    candidates against the LDS list, eight per pair of 16-byte reads
+    //    (entries past ncand padded with (+inf, INT_MAX), never below).
     if (ncand <= WAVE) {
-        uint64_t w = ~0ull;
-        int ki = 0;
-        if (lane < ncand) {
-            ki = lds.cand_k[lane];
-            w = pack_gap_key(lds.cand_d[lane], ki);
-        }
-        // lanes past ncand hold the largest word, never below a candidate's,
-        // so the count runs over whole groups of four lanes
-        int rank = 0;
-        for (int j = 0; j < ncand; j += 4) {
-            const uint64_t a = bcast_lane(w, j), b = bcast_lane(w, j + 1);
-            const uint64_t c = bcast_lane(w, j + 2), d = bcast_lane(w, j + 3);
-            rank += (a < w ? 1 : 0) + (b < w ? 1 : 0) + (c < w ? 1 : 0) + (d < w ? 1 : 0);
-        }
-        if (lane < ncand && rank < P.C_max) lds.sel[rank] = ki;
+        cap_rank<1>(lds, ncand, P.C_max);
+    } else if (ncand <= 2 * WAVE) {
+        cap_rank<2>(lds, ncand, P.C_max);
+    } else if (ncand <= 4 * WAVE) {
+        cap_rank<4>(lds, ncand, P.C_max);
     } else {
         if (lane < 8) {
             lds.cand_d[ncand + lane] = __int_as_float(0x7f800000);
@@ -334,8 +363,10 @@ __device__ __forceinline__ void step_setup(const Consts &P, const float *__restr
 // list, free once the cap has run).  SumsInLds: the 6x6 solve reads the
 // summed system from LDS as it goes instead of from registers loaded all at
 // once (fewer live registers, so two wavefronts fit on a SIMD; a little more
-// latency per iteration).
-template <typename SR, bool SumsInLds = false>
+// latency per iteration).  PairTrials: with at most 32 contacts the line
+// search runs its trials two at a time, one per half-wave (the same trials,
+// sums and choice; the worst case of four trials costs two).
+template <typename SR, bool SumsInLds = false, bool PairTrials = false>
 __device__ __forceinline__ void step_solve(const Consts &P, StepState<SR> &st, float mu_f, const float *inv_in,
                                            SR *red)
 {
@@ -442,20 +473,74 @@ __device__ __forceinline__ void step_solve(const Consts &P, StepState<SR> &st, f
             // impulses, relative velocity (u + alpha W dr) and FB value carry
             // into the next iteration
             SR alpha = SR(0.125);
-            SR a = SR(1);
             SR rt[3], ut[3];
             FBOut<SR> ft;
-            for (int t = 0; t < 4; ++t, a *= SR(0.5)) {
+            if (PairTrials && span <= 32) {
+                // the same four trials two at a time: the lower half-wave
+                // at alpha = 1 (then 1/4), the upper half at 1/2 (then 1/8)
+                // on a copy of the lower half's contacts, each half summed
+                // by the tree wave_sum uses, accepted in the same order
+                SR r2[3], dr2[3], u2[3], du2[3];
 #pragma unroll
                 for (int i = 0; i < 3; ++i) {
-                    rt[i] = r[i] + a * dr[i];
-                    ut[i] = u[i] + a * du[i];
+                    r2[i] = half_bcast(r[i], false);
+                    dr2[i] = half_bcast(dr[i], false);
+                    u2[i] = half_bcast(u[i], false);
+                    du2[i] = half_bcast(du[i], false);
                 }
-                fb_value(mu, kap, del, rt, ut, ft);
-                SR ptr = act ? SR(0.5) * (ft.phi[0] * ft.phi[0] + ft.phi[1] * ft.phi[1] + ft.phi[2] * ft.phi[2])
-                             : SR(0);
-                ptr = wave_sum1(ptr, span);
-                if (ptr <= (SR(1) - SR(2) * SR(P.armijo_sigma) * a) * psi) { alpha = a; break; }
+                const bool act2 = half_bcast((uint32_t)act, false) != 0u;
+                const bool up = lane_id() >= 32;
+                bool from_upper = true;   // 1/8, the fallback, is the upper half's last trial
+                for (int t = 0; t < 2; ++t) {
+                    const SR alo = t == 0 ? SR(1) : SR(0.25), ahi = SR(0.5) * alo;
+                    const SR a = up ? ahi : alo;
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) {
+                        rt[i] = r2[i] + a * dr2[i];
+                        ut[i] = u2[i] + a * du2[i];
+                    }
+                    fb_value(mu, kap, del, rt, ut, ft);
+                    const SR ptr = act2 ? SR(0.5) * (ft.phi[0] * ft.phi[0] + ft.phi[1] * ft.phi[1] +
+                                                     ft.phi[2] * ft.phi[2])
+                                        : SR(0);
+                    SR slo, shi;
+                    half_sums(ptr, span, slo, shi);
+                    if (slo <= (SR(1) - SR(2) * SR(P.armijo_sigma) * alo) * psi) {
+                        alpha = alo;
+                        from_upper = false;
+                        break;
+                    }
+                    if (shi <= (SR(1) - SR(2) * SR(P.armijo_sigma) * ahi) * psi) { alpha = ahi; break; }
+                }
+                if (from_upper) {
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) {
+                        rt[i] = half_bcast(rt[i], true);
+                        ut[i] = half_bcast(ut[i], true);
+                        ft.phi[i] = half_bcast(ft.phi[i], true);
+                        ft.x[i] = half_bcast(ft.x[i], true);
+                        ft.y[i] = half_bcast(ft.y[i], true);
+                    }
+                    ft.w0 = half_bcast(ft.w0, true); ft.w1 = half_bcast(ft.w1, true);
+                    ft.w2 = half_bcast(ft.w2, true); ft.s = half_bcast(ft.s, true);
+                    ft.st = half_bcast(ft.st, true); ft.rw = half_bcast(ft.rw, true);
+                    ft.rs = half_bcast(ft.rs, true); ft.rst = half_bcast(ft.rst, true);
+                }
+            } else {
+                SR a = SR(1);
+                for (int t = 0; t < 4; ++t, a *= SR(0.5)) {
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) {
+                        rt[i] = r[i] + a * dr[i];
+                        ut[i] = u[i] + a * du[i];
+                    }
+                    fb_value(mu, kap, del, rt, ut, ft);
+                    SR ptr = act ? SR(0.5) * (ft.phi[0] * ft.phi[0] + ft.phi[1] * ft.phi[1] +
+                                              ft.phi[2] * ft.phi[2])
+                                 : SR(0);
+                    ptr = wave_sum1(ptr, span);
+                    if (ptr <= (SR(1) - SR(2) * SR(P.armijo_sigma) * a) * psi) { alpha = a; break; }
+                }
             }
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
