@@ -323,37 +323,44 @@ __global__ __launch_bounds__(256) void k_observe(Consts P, const float *__restri
 }
 
 
-// one wavefront per simulation, lanes over sensors; obs_gt is [4][L][G]
-// (the observed batch's own observation layout)
-__global__ __launch_bounds__(256) void k_cost(Consts P, const int32_t *__restrict__ group_of,
-                                              const int32_t *__restrict__ group_start,
-                                              const float *__restrict__ obs, const float *__restrict__ obs_gt,
-                                              float *cost_sum, int32_t *__restrict__ best, int32_t *done)
+// one thread per simulation, its sensors' terms summed in sensor order (the
+// order of step_cost_wave, so the plain and batched paths add the same
+// bits); obs_gt is [R][L][G] (the observed batch's own observation layout)
+constexpr int COST_THREADS = 256;
+__global__ __launch_bounds__(COST_THREADS) void k_cost(Consts P, const int32_t *__restrict__ group_of,
+                                                       const int32_t *__restrict__ group_start,
+                                                       const float *__restrict__ obs,
+                                                       const float *__restrict__ obs_gt, float *cost_sum,
+                                                       int32_t *__restrict__ best, int32_t *done)
 {
-    const int e = xcd_block(blockIdx.x, gridDim.x) * (blockDim.x / WAVE) + threadIdx.x / WAVE;
-    const int lane = lane_id();
+    const int e = blockIdx.x * COST_THREADS + threadIdx.x;
     if (e < P.K) {
         const int g = group_of[e];
         const size_t LK = (size_t)P.L * P.K, LG = (size_t)P.L * P.G;
         const bool eq3 = P.cost_mode == 1;
-        float cl = 0.f;
-        if (lane < P.L) {
+        const int R = eq3 ? 7 : 4;
+        const float prev = cost_sum[e];
+        float cs = 0.f;
+        for (int l = 0; l < P.L; ++l) {
             float o[7], gt[7];
-            const int R = eq3 ? 7 : 4;
 #pragma unroll
             for (int j = 0; j < 7; ++j) {
-                o[j] = j < R ? obs[j * LK + (size_t)lane * P.K + e] : 0.f;
-                gt[j] = j < R ? obs_gt[j * LG + (size_t)lane * P.G + g] : 0.f;
+                o[j] = j < R ? obs[j * LK + (size_t)l * P.K + e] : 0.f;
+                gt[j] = j < R ? obs_gt[j * LG + (size_t)l * P.G + g] : 0.f;
             }
-            cl = eq3 ? sensor_cost_eq3(P, o, gt) : sensor_cost(P, o, gt);
+            cs += eq3 ? sensor_cost_eq3(P, o, gt) : sensor_cost(P, o, gt);
         }
-        const float cs = step_cost_wave(P, cl);
-        if (lane == 0) cost_sum[e] += cs;
+        cost_sum[e] = prev + cs;
     }
-    // with `best`: the workgroup that finishes last ranks every group (Eq. 2)
+    // with `best`: the workgroup that finishes last ranks every group (Eq. 2);
+    // a single workgroup needs no counter
     __shared__ float sv[16];
     __shared__ int si[17];
-    if (best && last_block(done, si + 16)) {
+    if (!best) return;
+    if (gridDim.x == 1) {
+        __syncthreads();
+        block_argmin(P.G, group_start, cost_sum, best, sv, si);
+    } else if (last_block(done, si + 16)) {
         block_argmin(P.G, group_start, cost_sum, best, sv, si);
         if (threadIdx.x == 0) *done = 0;
     }
@@ -388,6 +395,10 @@ __global__ __launch_bounds__(1024) void k_resample(Consts P, ResampleArgs R, con
     const int kb = elite_count(n, R.elite_frac);
     const uint32_t key0 = (uint32_t)(R.seed & 0xffffffffu), key1 = (uint32_t)(R.seed >> 32);
     const int K = P.K;
+    // parents by rank (the sorted costs' LDS is free after the sort); the
+    // parents are elites, never overwritten, so every copy below is
+    // independent of the others
+    int *par = reinterpret_cast<int *>(cs);
     for (int t = threadIdx.x; t < n; t += blockDim.x) {
         const int j = lo + order[t];
         if (t < kb) {
@@ -398,16 +409,26 @@ __global__ __launch_bounds__(1024) void k_resample(Consts P, ResampleArgs R, con
         philox4x32_10((uint32_t)j, window_idx, 0u, 0u, key0, key1, w);
         const int prank = (int)(((uint64_t)w[0] * (uint64_t)kb) >> 32);
         const int p = lo + order[prank];
+        par[t] = p;
         if (parent) parent[j] = p;
-        for (int c = 0; c < 13; ++c) state[(size_t)c * K + j] = state[(size_t)c * K + p];
-        const float4 *src = reinterpret_cast<const float4 *>(warm + (size_t)p * P.C_max * WARM_STRIDE);
-        float4 *dst = reinterpret_cast<float4 *>(warm + (size_t)j * P.C_max * WARM_STRIDE);
-        for (int c = 0; c < P.C_max; ++c) dst[c] = src[c];
         float e[5];
         explore(R, (uint32_t)j, window_idx, params[0 * (size_t)K + p], params[1 * (size_t)K + p], e);
         for (int c = 0; c < 5; ++c) params[(size_t)c * K + j] = e[c];
     }
     __syncthreads();
+    // state rows and warm-cache slots, one (simulation, row or slot) per thread
+    const int nr = n - kb;
+    for (int i = threadIdx.x; i < nr * 13; i += blockDim.x) {
+        const int t = kb + i / 13, c = i - (i / 13) * 13;
+        const int j = lo + order[t], p = par[t];
+        state[(size_t)c * K + j] = state[(size_t)c * K + p];
+    }
+    for (int i = threadIdx.x; i < nr * P.C_max; i += blockDim.x) {
+        const int t = kb + i / P.C_max, c = i - (i / P.C_max) * P.C_max;
+        const int j = lo + order[t], p = par[t];
+        reinterpret_cast<float4 *>(warm)[(size_t)j * P.C_max + c] =
+            reinterpret_cast<const float4 *>(warm)[(size_t)p * P.C_max + c];
+    }
     for (int i = threadIdx.x; i < n; i += blockDim.x) cost_sum[lo + i] = 0.f;
 }
 
@@ -577,9 +598,9 @@ hipError_t launch_observe(const Consts &P, const float *contacts, const float *c
 hipError_t launch_cost(const Consts &P, const int32_t *group_of, const int32_t *group_start, const float *obs,
                        const float *obs_gt, float *cost_sum, int32_t *best, int32_t *done, hipStream_t s)
 {
-    int blocks = (P.K + 3) / 4;
-    hipLaunchKernelGGL(k_cost, dim3(blocks), dim3(256), 0, s, P, group_of, group_start, obs, obs_gt, cost_sum, best,
-                       done);
+    int blocks = (P.K + COST_THREADS - 1) / COST_THREADS;
+    hipLaunchKernelGGL(k_cost, dim3(blocks), dim3(COST_THREADS), 0, s, P, group_of, group_start, obs, obs_gt,
+                       cost_sum, best, done);
     return hipGetLastError();
 }
 
