@@ -327,7 +327,8 @@ hipError_t launch_window_bwd(const Consts &P, const Tables &tb, const float *seg
 hipError_t launch_select_elites(int G, int max_group, float elite_frac, const int32_t *group_start,
                                 const float *cost_sum, int32_t *elite_env, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_select_elites, dim3(G), dim3(1024), resample_lds_bytes(max_group), s, G, elite_frac,
+    hipLaunchKernelGGL(k_select_elites, dim3(G), dim3(group_threads(max_group)), resample_lds_bytes(max_group), s,
+                       G, elite_frac,
                        group_start, cost_sum, elite_env);
     return hipGetLastError();
 }

@@ -54,6 +54,13 @@ __host__ __device__ constexpr int sort_slots(int n)
     return p;
 }
 
+// threads of a per-group workgroup (sort, resample, elites): one per
+// simulation of the largest group, in whole wavefronts, 64 to 1024
+constexpr int group_threads(int max_group)
+{
+    return max_group >= 1024 ? 1024 : (max_group <= 64 ? 64 : (max_group + 63) / 64 * 64);
+}
+
 // LDS of one group's sort: costs and indices over sort_slots(max_group)
 __host__ __device__ constexpr size_t resample_lds_bytes(int max_group)
 {

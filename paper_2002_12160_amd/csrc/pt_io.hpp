@@ -333,8 +333,15 @@ __device__ __forceinline__ void sort_group(const float *__restrict__ cost, int n
                     }
                 }
             }
-            __syncthreads();
+            // a stage with j < WAVE stays inside each wavefront's 64-index
+            // blocks (blockDim is a multiple of WAVE, so one wavefront owns
+            // a block), where the wavefront's own LDS order suffices; a
+            // workgroup barrier only around the stages that cross them
+            const int jn = j > 1 ? j >> 1 : k;   // the next stage's j
+            if (j >= WAVE || (jn >= WAVE && k < np2)) __syncthreads();
+            else wave_sync();
         }
+    __syncthreads();
 }
 
 // True in every thread of the workgroup that arrives last among the grid's

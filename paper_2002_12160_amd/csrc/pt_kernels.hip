@@ -326,7 +326,9 @@ __global__ __launch_bounds__(256) void k_observe(Consts P, const float *__restri
 // one thread per simulation, its sensors' terms summed in sensor order (the
 // order of step_cost_wave, so the plain and batched paths add the same
 // bits); obs_gt is [R][L][G] (the observed batch's own observation layout)
+// (R = 4: force rows; R = 7: the rows of Eq. 3)
 constexpr int COST_THREADS = 256;
+template <int R>
 __global__ __launch_bounds__(COST_THREADS) void k_cost(Consts P, const int32_t *__restrict__ group_of,
                                                        const int32_t *__restrict__ group_start,
                                                        const float *__restrict__ obs,
@@ -334,32 +336,46 @@ __global__ __launch_bounds__(COST_THREADS) void k_cost(Consts P, const int32_t *
                                                        int32_t *__restrict__ best, int32_t *done)
 {
     const int e = blockIdx.x * COST_THREADS + threadIdx.x;
+    __shared__ float csum[COST_THREADS];
     if (e < P.K) {
-        const int g = group_of[e];
+        const int g = P.G == 1 ? 0 : group_of[e];
         const size_t LK = (size_t)P.L * P.K, LG = (size_t)P.L * P.G;
-        const bool eq3 = P.cost_mode == 1;
-        const int R = eq3 ? 7 : 4;
+        constexpr bool eq3 = R == 7;
         const float prev = cost_sum[e];
         float cs = 0.f;
-        for (int l = 0; l < P.L; ++l) {
-            float o[7], gt[7];
+        // CH sensors' loads in flight at a time, then their terms in order
+        constexpr int CH = eq3 ? 8 : 16;
+        for (int l0 = 0; l0 < P.L; l0 += CH) {
+            float o[CH][R], gt[CH][R];
+            // the simulation's own rows first: they do not wait for g
 #pragma unroll
-            for (int j = 0; j < 7; ++j) {
-                o[j] = j < R ? obs[j * LK + (size_t)l * P.K + e] : 0.f;
-                gt[j] = j < R ? obs_gt[j * LG + (size_t)l * P.G + g] : 0.f;
-            }
-            cs += eq3 ? sensor_cost_eq3(P, o, gt) : sensor_cost(P, o, gt);
+            for (int c = 0; c < CH; ++c)
+#pragma unroll
+                for (int j = 0; j < R; ++j)
+                    o[c][j] = l0 + c < P.L ? obs[j * LK + (size_t)(l0 + c) * P.K + e] : 0.f;
+#pragma unroll
+            for (int c = 0; c < CH; ++c)
+#pragma unroll
+                for (int j = 0; j < R; ++j)
+                    gt[c][j] = l0 + c < P.L ? obs_gt[j * LG + (size_t)(l0 + c) * P.G + g] : 0.f;
+#pragma unroll
+            for (int c = 0; c < CH; ++c)
+                if (l0 + c < P.L) {
+                    if constexpr (eq3) cs += sensor_cost_eq3(P, o[c], gt[c]);
+                    else cs += sensor_cost(P, o[c], gt[c]);
+                }
         }
         cost_sum[e] = prev + cs;
+        csum[threadIdx.x] = prev + cs;
     }
     // with `best`: the workgroup that finishes last ranks every group (Eq. 2);
-    // a single workgroup needs no counter
+    // a single workgroup ranks its own sums from LDS, with no counter
     __shared__ float sv[16];
     __shared__ int si[17];
     if (!best) return;
     if (gridDim.x == 1) {
         __syncthreads();
-        block_argmin(P.G, group_start, cost_sum, best, sv, si);
+        block_argmin(P.G, group_start, csum, best, sv, si);
     } else if (last_block(done, si + 16)) {
         block_argmin(P.G, group_start, cost_sum, best, sv, si);
         if (threadIdx.x == 0) *done = 0;
@@ -378,6 +394,36 @@ __global__ void k_argmin(const int32_t *__restrict__ group_start, const float *_
 // ---------------------------------------------------------------------
 // population-based resampling
 // ---------------------------------------------------------------------
+// copy item i of a resample (i < nr: simulation kb + i / rows of the sorted
+// group, row or slot i % rows) read from its parent / written to the child
+__device__ __forceinline__ float state_row_src(const float *state, int K, int lo, int kb, const int *order,
+                                               const int *par, int nr, int i)
+{
+    if (i >= nr * 13) return 0.f;
+    const int t = kb + i / 13, c = i - (i / 13) * 13;
+    return state[(size_t)c * K + par[t]];
+}
+__device__ __forceinline__ void state_row_dst(float *state, int K, int lo, int kb, const int *order, int nr, int i,
+                                              float v)
+{
+    if (i >= nr * 13) return;
+    const int t = kb + i / 13, c = i - (i / 13) * 13;
+    state[(size_t)c * K + lo + order[t]] = v;
+}
+__device__ __forceinline__ float4 warm_slot_src(const float4 *w4, int C, int kb, const int *par, int nr, int i)
+{
+    if (i >= nr * C) return make_float4(0.f, 0.f, 0.f, 0.f);
+    const int t = kb + i / C, c = i - (i / C) * C;
+    return w4[(size_t)par[t] * C + c];
+}
+__device__ __forceinline__ void warm_slot_dst(float4 *w4, int C, int lo, int kb, const int *order, int nr, int i,
+                                              float4 v)
+{
+    if (i >= nr * C) return;
+    const int t = kb + i / C, c = i - (i / C) * C;
+    w4[(size_t)(lo + order[t]) * C + c] = v;
+}
+
 // one block per group; sorts by (cost, index), then copies and perturbs
 __global__ __launch_bounds__(1024) void k_resample(Consts P, ResampleArgs R, const int32_t *__restrict__ group_start,
                                                    uint32_t window_idx, float *__restrict__ cost_sum,
@@ -416,18 +462,34 @@ __global__ __launch_bounds__(1024) void k_resample(Consts P, ResampleArgs R, con
         for (int c = 0; c < 5; ++c) params[(size_t)c * K + j] = e[c];
     }
     __syncthreads();
-    // state rows and warm-cache slots, one (simulation, row or slot) per thread
+    // state rows and warm-cache slots, one (simulation, row or slot) per
+    // thread, four of them loaded before any is stored (the copies read only
+    // elites, which nothing here writes)
     const int nr = n - kb;
-    for (int i = threadIdx.x; i < nr * 13; i += blockDim.x) {
-        const int t = kb + i / 13, c = i - (i / 13) * 13;
-        const int j = lo + order[t], p = par[t];
-        state[(size_t)c * K + j] = state[(size_t)c * K + p];
+    const int nt = blockDim.x;
+    for (int i0 = threadIdx.x; i0 < nr * 13; i0 += 4 * nt) {
+        const int i1 = i0 + nt, i2 = i0 + 2 * nt, i3 = i0 + 3 * nt;
+        const float v0 = state_row_src(state, K, lo, kb, order, par, nr, i0);
+        const float v1 = state_row_src(state, K, lo, kb, order, par, nr, i1);
+        const float v2 = state_row_src(state, K, lo, kb, order, par, nr, i2);
+        const float v3 = state_row_src(state, K, lo, kb, order, par, nr, i3);
+        state_row_dst(state, K, lo, kb, order, nr, i0, v0);
+        state_row_dst(state, K, lo, kb, order, nr, i1, v1);
+        state_row_dst(state, K, lo, kb, order, nr, i2, v2);
+        state_row_dst(state, K, lo, kb, order, nr, i3, v3);
     }
-    for (int i = threadIdx.x; i < nr * P.C_max; i += blockDim.x) {
-        const int t = kb + i / P.C_max, c = i - (i / P.C_max) * P.C_max;
-        const int j = lo + order[t], p = par[t];
-        reinterpret_cast<float4 *>(warm)[(size_t)j * P.C_max + c] =
-            reinterpret_cast<const float4 *>(warm)[(size_t)p * P.C_max + c];
+    float4 *w4 = reinterpret_cast<float4 *>(warm);
+    const int C = P.C_max;
+    for (int i0 = threadIdx.x; i0 < nr * C; i0 += 4 * nt) {
+        const int i1 = i0 + nt, i2 = i0 + 2 * nt, i3 = i0 + 3 * nt;
+        const float4 v0 = warm_slot_src(w4, C, kb, par, nr, i0);
+        const float4 v1 = warm_slot_src(w4, C, kb, par, nr, i1);
+        const float4 v2 = warm_slot_src(w4, C, kb, par, nr, i2);
+        const float4 v3 = warm_slot_src(w4, C, kb, par, nr, i3);
+        warm_slot_dst(w4, C, lo, kb, order, nr, i0, v0);
+        warm_slot_dst(w4, C, lo, kb, order, nr, i1, v1);
+        warm_slot_dst(w4, C, lo, kb, order, nr, i2, v2);
+        warm_slot_dst(w4, C, lo, kb, order, nr, i3, v3);
     }
     for (int i = threadIdx.x; i < n; i += blockDim.x) cost_sum[lo + i] = 0.f;
 }
@@ -599,8 +661,12 @@ hipError_t launch_cost(const Consts &P, const int32_t *group_of, const int32_t *
                        const float *obs_gt, float *cost_sum, int32_t *best, int32_t *done, hipStream_t s)
 {
     int blocks = (P.K + COST_THREADS - 1) / COST_THREADS;
-    hipLaunchKernelGGL(k_cost, dim3(blocks), dim3(COST_THREADS), 0, s, P, group_of, group_start, obs, obs_gt,
-                       cost_sum, best, done);
+    if (P.cost_mode == 1)
+        hipLaunchKernelGGL(k_cost<7>, dim3(blocks), dim3(COST_THREADS), 0, s, P, group_of, group_start, obs, obs_gt,
+                           cost_sum, best, done);
+    else
+        hipLaunchKernelGGL(k_cost<4>, dim3(blocks), dim3(COST_THREADS), 0, s, P, group_of, group_start, obs, obs_gt,
+                           cost_sum, best, done);
     return hipGetLastError();
 }
 
@@ -615,8 +681,8 @@ hipError_t launch_resample(const Consts &P, const ResampleArgs &R, const int32_t
                            int32_t *parent, hipStream_t s)
 {
     size_t lds = resample_lds_bytes(max_group);
-    hipLaunchKernelGGL(k_resample, dim3(P.G), dim3(1024), lds, s, P, R, group_start, window_idx, cost_sum, state,
-                       params, warm, parent);
+    hipLaunchKernelGGL(k_resample, dim3(P.G), dim3(group_threads(max_group)), lds, s, P, R, group_start, window_idx,
+                       cost_sum, state, params, warm, parent);
     return hipGetLastError();
 }
 
