@@ -434,7 +434,7 @@ static pt_status enqueue_window(pt_batch b, const float *u_win, const float *obs
 {
     const Consts &P = b->P;
     int bpc = 0;
-    HIP_TRY(window_occupancy(wpb, P.max_cand, P.L, P.solve_fp64 != 0, P.cost_mode == 1, &bpc));
+    HIP_TRY(window_occupancy(P, wpb, &bpc));
     if (bpc < 1) return fail(PT_E_UNSUPPORTED, "persistent kernel does not fit with %d waves per workgroup", wpb);
     int want = (P.K + wpb - 1) / wpb;
     int blocks = std::min(want, bpc * b->num_cu);

@@ -105,7 +105,7 @@ hipError_t launch_window(const pt::Consts &P, const pt::Tables &tb, const float 
                          float *warm, const float *obs_gt_win, float *cost_sum, float *obs_out,
                          const int32_t *env_order, int32_t *queue, int64_t *stats, int waves_per_block, int blocks,
                          float *ckpt, const int32_t *group_start, int32_t *best, hipStream_t s);
-hipError_t window_occupancy(int waves_per_block, int max_cand, int L, bool fp64, bool eq3, int *blocks_per_cu);
+hipError_t window_occupancy(const pt::Consts &P, int waves_per_block, int *blocks_per_cu);
 hipError_t set_lds_limits(size_t bytes);
 hipError_t set_grad_lds_limits(size_t bytes);
 size_t ckpt_floats(const pt::Consts &P, int n);

@@ -497,7 +497,7 @@ __global__ __launch_bounds__(1024) void k_resample(Consts P, ResampleArgs R, con
 // ---------------------------------------------------------------------
 // batched path: persistent kernel over a window of T steps
 // ---------------------------------------------------------------------
-template <typename SR, bool EQ3>
+template <typename SR, bool EQ3, bool PT>
 __global__ __launch_bounds__(StepBounds<SR>::threads) void k_window(Consts P, Tables tb, const float *__restrict__ seg_win,
                                                  float *__restrict__ state, float *__restrict__ params,
                                                  float *__restrict__ warm, const float *__restrict__ obs_gt_win,
@@ -542,7 +542,7 @@ __global__ __launch_bounds__(StepBounds<SR>::threads) void k_window(Consts P, Ta
             if (ck) save_body(ck, B);
             StepState<SR> sst;
             step_setup<SR>(P, seg, sph, S, inv, B, wkey, wr, lds, st, sst);
-            step_solve<SR, true>(P, sst, B.mu, inv, reinterpret_cast<SR *>(lds.cand_d));
+            step_solve<SR, true, PT>(P, sst, B.mu, inv, reinterpret_cast<SR *>(lds.cand_d));
             if (ck) save_contact<SR>(ck, P.C_max, sst);
             step_finish<SR>(P, sst, inv, B, wkey, wr, link, imp);
             uniform_body(B);
@@ -686,6 +686,21 @@ hipError_t launch_resample(const Consts &P, const ResampleArgs &R, const int32_t
     return hipGetLastError();
 }
 
+// the window kernel for a batch: solve precision, cost mode, and the paired
+// line-search trials when no step can hold more than 32 contacts (C_max <=
+// 32: latency-bound populations, where the extra registers cost nothing)
+template <typename F>
+static hipError_t with_window_kernel(const Consts &P, F f)
+{
+    const bool eq3 = P.cost_mode == 1, pt = P.C_max <= 32;
+    if (P.solve_fp64) {
+        if (eq3) return pt ? f(k_window<double, true, true>) : f(k_window<double, true, false>);
+        return pt ? f(k_window<double, false, true>) : f(k_window<double, false, false>);
+    }
+    if (eq3) return pt ? f(k_window<float, true, true>) : f(k_window<float, true, false>);
+    return pt ? f(k_window<float, false, true>) : f(k_window<float, false, false>);
+}
+
 hipError_t launch_window(const Consts &P, const Tables &tb, const float *seg_win, float *state, float *params,
                          float *warm, const float *obs_gt_win, float *cost_sum, float *obs_out,
                          const int32_t *env_order, int32_t *queue, int64_t *stats, int waves_per_block, int blocks,
@@ -693,38 +708,32 @@ hipError_t launch_window(const Consts &P, const Tables &tb, const float *seg_win
 {
     size_t lds = (size_t)waves_per_block * wave_lds_bytes(P.max_cand, P.L);
     const dim3 grid(blocks), block(WAVE * waves_per_block);
-    const bool eq3 = P.cost_mode == 1;
-    if (P.solve_fp64 && !eq3)
-        hipLaunchKernelGGL((k_window<double, false>), grid, block, lds, s, P, tb, seg_win, state, params, warm,
-                           obs_gt_win, cost_sum, obs_out, env_order, queue, stats, ckpt, group_start, best);
-    else if (P.solve_fp64)
-        hipLaunchKernelGGL((k_window<double, true>), grid, block, lds, s, P, tb, seg_win, state, params, warm,
-                           obs_gt_win, cost_sum, obs_out, env_order, queue, stats, ckpt, group_start, best);
-    else if (!eq3)
-        hipLaunchKernelGGL((k_window<float, false>), grid, block, lds, s, P, tb, seg_win, state, params, warm,
-                           obs_gt_win, cost_sum, obs_out, env_order, queue, stats, ckpt, group_start, best);
-    else
-        hipLaunchKernelGGL((k_window<float, true>), grid, block, lds, s, P, tb, seg_win, state, params, warm,
-                           obs_gt_win, cost_sum, obs_out, env_order, queue, stats, ckpt, group_start, best);
-    return hipGetLastError();
+    return with_window_kernel(P, [&](auto kern) {
+        hipLaunchKernelGGL(kern, grid, block, lds, s, P, tb, seg_win, state, params, warm, obs_gt_win, cost_sum,
+                           obs_out, env_order, queue, stats, ckpt, group_start, best);
+        return hipGetLastError();
+    });
 }
 
-hipError_t window_occupancy(int waves_per_block, int max_cand, int L, bool fp64, bool eq3, int *blocks_per_cu)
+hipError_t window_occupancy(const Consts &P, int waves_per_block, int *blocks_per_cu)
 {
-    size_t lds = (size_t)waves_per_block * wave_lds_bytes(max_cand, L);
-    const void *f = fp64 ? (eq3 ? reinterpret_cast<const void *>(k_window<double, true>)
-                                : reinterpret_cast<const void *>(k_window<double, false>))
-                         : (eq3 ? reinterpret_cast<const void *>(k_window<float, true>)
-                                : reinterpret_cast<const void *>(k_window<float, false>));
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, f, WAVE * waves_per_block, lds);
+    size_t lds = (size_t)waves_per_block * wave_lds_bytes(P.max_cand, P.L);
+    return with_window_kernel(P, [&](auto kern) {
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, reinterpret_cast<const void *>(kern),
+                                                            WAVE * waves_per_block, lds);
+    });
 }
 
 hipError_t set_lds_limits(size_t bytes)
 {
-    const void *fs[] = {reinterpret_cast<const void *>(k_window<float, false>),
-                        reinterpret_cast<const void *>(k_window<double, false>),
-                        reinterpret_cast<const void *>(k_window<float, true>),
-                        reinterpret_cast<const void *>(k_window<double, true>),
+    const void *fs[] = {reinterpret_cast<const void *>(k_window<float, false, false>),
+                        reinterpret_cast<const void *>(k_window<double, false, false>),
+                        reinterpret_cast<const void *>(k_window<float, true, false>),
+                        reinterpret_cast<const void *>(k_window<double, true, false>),
+                        reinterpret_cast<const void *>(k_window<float, false, true>),
+                        reinterpret_cast<const void *>(k_window<double, false, true>),
+                        reinterpret_cast<const void *>(k_window<float, true, true>),
+                        reinterpret_cast<const void *>(k_window<double, true, true>),
                         reinterpret_cast<const void *>(k_step<float, false>),
                         reinterpret_cast<const void *>(k_step<double, false>),
                         reinterpret_cast<const void *>(k_step<float, true>),
