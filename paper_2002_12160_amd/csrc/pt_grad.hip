@@ -36,7 +36,7 @@ __device__ __forceinline__ void load_start(const float *__restrict__ xi, int n, 
 // xi is [18][n]: x(3) q(4) v(3) w(3) m mu f(3); warm0 is [n][C_max][4]
 // One launch covers `count` listed simulations i0 .. i0+count-1 of arrays
 // with row stride n; the checkpoint buffer holds `count` simulations.
-template <typename SR>
+template <typename SR, bool PT>
 __global__ __launch_bounds__(WAVE) void k_window_fwd(Consts P, Tables tb, const float *__restrict__ seg_win, int n,
                                                      int i0, int count,
                                                      const int32_t *__restrict__ env, const float *__restrict__ xi,
@@ -81,7 +81,7 @@ __global__ __launch_bounds__(WAVE) void k_window_fwd(Consts P, Tables tb, const 
         const float *seg = seg_win + (size_t)t * P.L * SEG_STRIDE;
         StepState<SR> st;
         step_setup<SR>(P, seg, sph, S, inv, B, wkey, wr, lds, stt, st);
-        step_solve<SR, true>(P, st, B.mu, inv, reinterpret_cast<SR *>(lds.cand_d));
+        step_solve<SR, true, PT>(P, st, B.mu, inv, reinterpret_cast<SR *>(lds.cand_d));
         if (ck) save_contact<SR>(ck, P.C_max, st);
         int link;
         float imp[3];
@@ -299,13 +299,15 @@ hipError_t launch_window_fwd(const Consts &P, const Tables &tb, const float *seg
 {
     if (count <= 0) return hipSuccess;
     size_t lds = wave_lds_bytes(P.max_cand, P.L);
-    if (P.solve_fp64)
-        hipLaunchKernelGGL(k_window_fwd<double>, dim3(count), dim3(WAVE), lds, s, P, tb, seg_win, n, i0, count, env,
-                           xi, warm0, obs_gt_win, cost, end_state, end_warm, ckpt);
-    else
-        hipLaunchKernelGGL(k_window_fwd<float>, dim3(count), dim3(WAVE), lds, s, P, tb, seg_win, n, i0, count, env,
-                           xi, warm0, obs_gt_win, cost, end_state, end_warm, ckpt);
-    return hipGetLastError();
+    // paired line-search trials when no step can hold more than 32 contacts
+    auto go = [&](auto kern) {
+        hipLaunchKernelGGL(kern, dim3(count), dim3(WAVE), lds, s, P, tb, seg_win, n, i0, count, env, xi, warm0,
+                           obs_gt_win, cost, end_state, end_warm, ckpt);
+        return hipGetLastError();
+    };
+    const bool pt = P.C_max <= 32;
+    if (P.solve_fp64) return pt ? go(k_window_fwd<double, true>) : go(k_window_fwd<double, false>);
+    return pt ? go(k_window_fwd<float, true>) : go(k_window_fwd<float, false>);
 }
 
 hipError_t launch_window_bwd(const Consts &P, const Tables &tb, const float *seg_win, int n, int i0, int count,
@@ -365,8 +367,10 @@ hipError_t launch_refine_accept(int n, int K, int C_max, const int32_t *env, flo
 hipError_t set_grad_lds_limits(size_t bytes)
 {
     const void *fs[] = {reinterpret_cast<const void *>(k_select_elites),
-                        reinterpret_cast<const void *>(k_window_fwd<float>),
-                        reinterpret_cast<const void *>(k_window_fwd<double>),
+                        reinterpret_cast<const void *>(k_window_fwd<float, false>),
+                        reinterpret_cast<const void *>(k_window_fwd<double, false>),
+                        reinterpret_cast<const void *>(k_window_fwd<float, true>),
+                        reinterpret_cast<const void *>(k_window_fwd<double, true>),
                         reinterpret_cast<const void *>(k_window_bwd<float>),
                         reinterpret_cast<const void *>(k_window_bwd<double>)};
     for (const void *f : fs) {
