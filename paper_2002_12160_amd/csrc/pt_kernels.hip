@@ -144,8 +144,28 @@ __device__ __forceinline__ void hand_kinematics(const float *__restrict__ hand, 
                                                 const FkLds &s, float *seg_out, int tid, int nt, Sync sync)
 {
     const int Ds = fk_staged_joints(D);
-    for (int i = tid; i < L * HAND_STRIDE; i += nt) s.hs[i] = hand[i];
-    for (int i = tid; i < Ds; i += nt) {
+    // the loads in flight together before their LDS writes: the commands,
+    // then the link table eight per thread at a time (one round trip to
+    // memory for a table of up to 8 nt floats, not one per element)
+    float up0 = 0.f, uu0 = 0.f;
+    if (tid < Ds) {
+        up0 = u_prev[tid];
+        uu0 = u[tid];
+    }
+    const int nh = L * HAND_STRIDE;
+    for (int i0 = tid; i0 < nh; i0 += 8 * nt) {
+        float v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = hand[min(i0 + k * nt, nh - 1)];   // in bounds, no branch
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            if (i0 + k * nt < nh) s.hs[i0 + k * nt] = v[k];
+    }
+    if (tid < Ds) {
+        s.su[tid] = up0;
+        s.su[Ds + tid] = uu0;
+    }
+    for (int i = tid + nt; i < Ds; i += nt) {
         s.su[i] = u_prev[i];
         s.su[Ds + i] = u[i];
     }
