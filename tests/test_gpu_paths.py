@@ -213,10 +213,11 @@ def test_cost_and_argmin_match_oracle(pt):
     b.close()
 
 
-@pytest.mark.parametrize("K", [64, 4096, 4097, 9000])
+@pytest.mark.parametrize("K", [64, 256, 257, 4096, 4097, 9000])
 def test_group_argmin_sizes(pt, K):
-    # the cost kernel ranks the groups in its last workgroup up to 4096
-    # simulations and leaves it to a kernel of its own beyond; both give the
+    # the cost kernel ranks the groups in its only workgroup up to 256
+    # simulations, in its last workgroup up to 4096 and leaves it to a kernel
+    # of its own beyond; all give the
     # lowest index of the minimum with NaN last, on repeated calls (the
     # last-workgroup counter is put back after each launch)
     _say(f"group argmin, K={K}")
