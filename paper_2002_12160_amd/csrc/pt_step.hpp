@@ -253,25 +253,31 @@ __device__ __forceinline__ void step_setup(const Consts &P, const float *__restr
         float c[3] = {B.x[0] + R[0] * s4[0] + R[1] * s4[1] + R[2] * s4[2],
                       B.x[1] + R[3] * s4[0] + R[4] * s4[1] + R[5] * s4[2],
                       B.x[2] + R[6] * s4[0] + R[7] * s4[1] + R[8] * s4[2]};
-        for (int l = 0; l <= L; ++l) {
-            float d;
-            if (l == L) {
-                d = c[2] - s4[3];
-            } else {
-                float sl[8];
-#pragma unroll
-                for (int i = 0; i < 8; ++i) sl[i] = bcast_lane(sgr[i], l);
-                d = segment_gap(sl, c, s4[3]);
-            }
-            bool cand = valid && (d < P.margin);
-            uint64_t mask = __ballot(cand);
+        // appended in link order, the table (l == L) last; two links' gaps
+        // at a time so that their arithmetic interleaves
+        auto append = [&](float d, int l) {
+            const bool cand = valid && (d < P.margin);
+            const uint64_t mask = __ballot(cand);
             if (cand) {
-                int pos = ncand + mask_rank(mask);
+                const int pos = ncand + mask_rank(mask);
                 lds.cand_d[pos] = d;
                 lds.cand_k[pos] = k * (L + 1) + l;
             }
             ncand += __popcll(mask);
+        };
+        for (int l = 0; l < L; l += 2) {
+            const int l1 = l + 1 < L ? l + 1 : l;
+            float sa[8], sb[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                sa[i] = bcast_lane(sgr[i], l);
+                sb[i] = bcast_lane(sgr[i], l1);
+            }
+            const float da = segment_gap(sa, c, s4[3]), db = segment_gap(sb, c, s4[3]);
+            append(da, l);
+            if (l + 1 < L) append(db, l + 1);
         }
+        append(c[2] - s4[3], L);
     }
     wave_sync();
     ncand = __builtin_amdgcn_readfirstlane(ncand);   // wave-uniform: loops on it stay scalar
