@@ -29,6 +29,12 @@ struct RefineArgs {
 // cost or window kernel instead of a launch of their own
 constexpr int FUSED_ARGMIN_MAX = 4096;
 
+// capacity of a simulation's LDS candidate list (entries of gap + key): a
+// step that finds more cuts its list to the C_max lowest when it fills up
+// and keeps only candidates below the last kept one, so the LDS per
+// simulation stays within ~16-29 KiB whatever S_max and L are
+constexpr int CAND_CAP = 1536;
+
 // step statistics (steps, candidates, contacts, dropped) are accumulated in
 // STATS_SLOTS slots one 128-byte line apart, a wavefront adding to slot
 // (its index mod STATS_SLOTS): the atomics of a launch spread over many

@@ -218,6 +218,134 @@ __device__ __forceinline__ void cap_rank(const WaveLds &lds, int ncand, int C_ma
         if (lane + WAVE * h < ncand && rank[h] < C_max) lds.sel[rank[h]] = ki[h];
 }
 
+// The cap's ranking for any n: every lane ranks its candidates against the
+// LDS list, eight per pair of 16-byte reads (entries past n padded with
+// (+inf, INT_MAX), never below); the keys of the C_max lowest go to
+// sel[rank] and, with dsel, their gaps to dsel[rank].
+__device__ __forceinline__ void cap_rank_lds(const WaveLds &lds, int n, int C_max, float *dsel)
+{
+    const int lane = lane_id();
+    if (lane < 8) {
+        lds.cand_d[n + lane] = __int_as_float(0x7f800000);
+        lds.cand_k[n + lane] = 0x7fffffff;
+    }
+    wave_sync();
+    for (int i = lane; i < n; i += WAVE) {
+        const float di = lds.cand_d[i];
+        const int ki = lds.cand_k[i];
+        int rank = 0;
+        for (int j = 0; j < n; j += 8) {
+            const float4 d4 = *reinterpret_cast<const float4 *>(lds.cand_d + j);
+            const float4 e4 = *reinterpret_cast<const float4 *>(lds.cand_d + j + 4);
+            const int4 k4 = *reinterpret_cast<const int4 *>(lds.cand_k + j);
+            const int4 m4 = *reinterpret_cast<const int4 *>(lds.cand_k + j + 4);
+            rank += (d4.x < di || (d4.x == di && k4.x < ki)) ? 1 : 0;
+            rank += (d4.y < di || (d4.y == di && k4.y < ki)) ? 1 : 0;
+            rank += (d4.z < di || (d4.z == di && k4.z < ki)) ? 1 : 0;
+            rank += (d4.w < di || (d4.w == di && k4.w < ki)) ? 1 : 0;
+            rank += (e4.x < di || (e4.x == di && m4.x < ki)) ? 1 : 0;
+            rank += (e4.y < di || (e4.y == di && m4.y < ki)) ? 1 : 0;
+            rank += (e4.z < di || (e4.z == di && m4.z < ki)) ? 1 : 0;
+            rank += (e4.w < di || (e4.w == di && m4.w < ki)) ? 1 : 0;
+        }
+        if (rank < C_max) {
+            lds.sel[rank] = ki;
+            if (dsel) dsel[rank] = di;
+        }
+    }
+}
+
+// A full candidate list cut to its C_max lowest (d, key) entries, in that
+// order at its head: every candidate dropped has C_max lower ones, so the
+// cap over everything seen is unchanged.  Returns the new length; thr gets
+// the packed word of the last kept entry (the bar for later candidates).
+// The warm cache's LDS (written after the narrow phase) holds the kept gaps.
+__device__ __forceinline__ int compact_candidates(const WaveLds &lds, int n, int C_max, uint64_t &thr)
+{
+    const int lane = lane_id();
+    wave_sync();
+    cap_rank_lds(lds, n, C_max, lds.wr);
+    wave_sync();
+    const int m = min(n, C_max);
+    if (lane < m) {
+        lds.cand_d[lane] = lds.wr[lane];
+        lds.cand_k[lane] = lds.sel[lane];
+    }
+    wave_sync();
+    thr = pack_gap_key(lds.cand_d[m - 1], lds.cand_k[m - 1]);
+    return m;
+}
+
+// Narrow phase: lanes over spheres, candidates appended to LDS in (sphere
+// block, link) order by ballot + prefix count, the table (l == L) after the
+// links, two links' gaps at a time so that their arithmetic interleaves.
+// Bounded: the list may fill up; a batch that would overflow it first cuts
+// the list to its C_max lowest, and from then on only candidates below the
+// last kept one are appended (removed counts the others).
+template <bool Bounded>
+__device__ __forceinline__ void narrow_phase(const Consts &P, const WaveLds &lds, const float (&sgr)[8],
+                                             const float *__restrict__ sph, int S, const float *x, const float *R,
+                                             int cap, int &ncand, int &removed)
+{
+    const int lane = lane_id();
+    const int L = P.L;
+    bool bar = false;
+    uint64_t thr = 0;
+    for (int kb = 0; kb < S; kb += WAVE) {
+        const int k = kb + lane;
+        const bool valid = k < S;
+        float s4[4] = {0.f, 0.f, 0.f, 0.f};
+        if (valid) {
+            const float4 t = *reinterpret_cast<const float4 *>(sph + 4 * k);
+            s4[0] = t.x; s4[1] = t.y; s4[2] = t.z; s4[3] = t.w;
+        }
+        const float c[3] = {x[0] + R[0] * s4[0] + R[1] * s4[1] + R[2] * s4[2],
+                            x[1] + R[3] * s4[0] + R[4] * s4[1] + R[5] * s4[2],
+                            x[2] + R[6] * s4[0] + R[7] * s4[1] + R[8] * s4[2]};
+        auto append = [&](float d, int l) {
+            bool cand = valid && (d < P.margin);
+            uint64_t mask = __ballot(cand);
+            if constexpr (Bounded) {
+                if (bar) {
+                    removed += __popcll(mask);
+                    cand = cand && pack_gap_key(d, k * (L + 1) + l) < thr;
+                    mask = __ballot(cand);
+                    removed -= __popcll(mask);
+                }
+                if (ncand + __popcll(mask) > cap) {
+                    removed += ncand;
+                    ncand = compact_candidates(lds, ncand, P.C_max, thr);
+                    removed -= ncand;
+                    bar = true;
+                    cand = cand && pack_gap_key(d, k * (L + 1) + l) < thr;
+                    const uint64_t m2 = __ballot(cand);
+                    removed += __popcll(mask) - __popcll(m2);
+                    mask = m2;
+                }
+            }
+            if (cand) {
+                const int pos = ncand + mask_rank(mask);
+                lds.cand_d[pos] = d;
+                lds.cand_k[pos] = k * (L + 1) + l;
+            }
+            ncand += __popcll(mask);
+        };
+        for (int l = 0; l < L; l += 2) {
+            const int l1 = l + 1 < L ? l + 1 : l;
+            float sa[8], sb[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                sa[i] = bcast_lane(sgr[i], l);
+                sb[i] = bcast_lane(sgr[i], l1);
+            }
+            const float da = segment_gap(sa, c, s4[3]), db = segment_gap(sb, c, s4[3]);
+            append(da, l);
+            if (l + 1 < L) append(db, l + 1);
+        }
+        append(c[2] - s4[3], L);
+    }
+}
+
 // phases 1-4: pose, free velocity, narrow phase, cap, contact setup, warm start
 template <typename SR>
 __device__ __forceinline__ void step_setup(const Consts &P, const float *__restrict__ seg,
@@ -241,44 +369,14 @@ __device__ __forceinline__ void step_setup(const Consts &P, const float *__restr
         sgr[0] = a.x; sgr[1] = a.y; sgr[2] = a.z; sgr[3] = a.w;
         sgr[4] = b.x; sgr[5] = b.y; sgr[6] = b.z; sgr[7] = b.w;
     }
-    int ncand = 0;
-    for (int kb = 0; kb < S; kb += WAVE) {
-        int k = kb + lane;
-        bool valid = k < S;
-        float s4[4] = {0.f, 0.f, 0.f, 0.f};
-        if (valid) {
-            const float4 t = *reinterpret_cast<const float4 *>(sph + 4 * k);
-            s4[0] = t.x; s4[1] = t.y; s4[2] = t.z; s4[3] = t.w;
-        }
-        float c[3] = {B.x[0] + R[0] * s4[0] + R[1] * s4[1] + R[2] * s4[2],
-                      B.x[1] + R[3] * s4[0] + R[4] * s4[1] + R[5] * s4[2],
-                      B.x[2] + R[6] * s4[0] + R[7] * s4[1] + R[8] * s4[2]};
-        // appended in link order, the table (l == L) last; two links' gaps
-        // at a time so that their arithmetic interleaves
-        auto append = [&](float d, int l) {
-            const bool cand = valid && (d < P.margin);
-            const uint64_t mask = __ballot(cand);
-            if (cand) {
-                const int pos = ncand + mask_rank(mask);
-                lds.cand_d[pos] = d;
-                lds.cand_k[pos] = k * (L + 1) + l;
-            }
-            ncand += __popcll(mask);
-        };
-        for (int l = 0; l < L; l += 2) {
-            const int l1 = l + 1 < L ? l + 1 : l;
-            float sa[8], sb[8];
-#pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                sa[i] = bcast_lane(sgr[i], l);
-                sb[i] = bcast_lane(sgr[i], l1);
-            }
-            const float da = segment_gap(sa, c, s4[3]), db = segment_gap(sb, c, s4[3]);
-            append(da, l);
-            if (l + 1 < L) append(db, l + 1);
-        }
-        append(c[2] - s4[3], L);
-    }
+    // list capacity (entries; 8 more are the cap's padding); a step that
+    // can find more candidates than that runs the bounded form
+    const int cap = P.max_cand - 8;
+    int ncand = 0, removed = 0;
+    if (S * (L + 1) <= cap)
+        narrow_phase<false>(P, lds, sgr, sph, S, B.x, R, cap, ncand, removed);
+    else
+        narrow_phase<true>(P, lds, sgr, sph, S, B.x, R, cap, ncand, removed);
     wave_sync();
     ncand = __builtin_amdgcn_readfirstlane(ncand);   // wave-uniform: loops on it stay scalar
     const int C = ncand < P.C_max ? ncand : P.C_max;
@@ -299,31 +397,7 @@ __device__ __forceinline__ void step_setup(const Consts &P, const float *__restr
     } else if (ncand <= 4 * WAVE) {
         cap_rank<4>(lds, ncand, P.C_max);
     } else {
-        if (lane < 8) {
-            lds.cand_d[ncand + lane] = __int_as_float(0x7f800000);
-            lds.cand_k[ncand + lane] = 0x7fffffff;
-        }
-        wave_sync();
-        for (int i = lane; i < ncand; i += WAVE) {
-            float di = lds.cand_d[i];
-            int ki = lds.cand_k[i];
-            int rank = 0;
-            for (int j = 0; j < ncand; j += 8) {
-                const float4 d4 = *reinterpret_cast<const float4 *>(lds.cand_d + j);
-                const float4 e4 = *reinterpret_cast<const float4 *>(lds.cand_d + j + 4);
-                const int4 k4 = *reinterpret_cast<const int4 *>(lds.cand_k + j);
-                const int4 m4 = *reinterpret_cast<const int4 *>(lds.cand_k + j + 4);
-                rank += (d4.x < di || (d4.x == di && k4.x < ki)) ? 1 : 0;
-                rank += (d4.y < di || (d4.y == di && k4.y < ki)) ? 1 : 0;
-                rank += (d4.z < di || (d4.z == di && k4.z < ki)) ? 1 : 0;
-                rank += (d4.w < di || (d4.w == di && k4.w < ki)) ? 1 : 0;
-                rank += (e4.x < di || (e4.x == di && m4.x < ki)) ? 1 : 0;
-                rank += (e4.y < di || (e4.y == di && m4.y < ki)) ? 1 : 0;
-                rank += (e4.z < di || (e4.z == di && m4.z < ki)) ? 1 : 0;
-                rank += (e4.w < di || (e4.w == di && m4.w < ki)) ? 1 : 0;
-            }
-            if (rank < P.C_max) lds.sel[rank] = ki;
-        }
+        cap_rank_lds(lds, ncand, P.C_max, nullptr);
     }
     // previous warm cache to LDS for the key lookup
     lds.wkey[lane] = wkey;
@@ -332,9 +406,9 @@ __device__ __forceinline__ void step_setup(const Consts &P, const float *__restr
     lds.wr[3 * lane + 2] = wr[2];
     wave_sync();
 
-    stats.cand += ncand;
+    stats.cand += ncand + removed;
     stats.contacts += C;
-    stats.dropped += ncand - C;
+    stats.dropped += ncand + removed - C;
 
     // 4. contact setup, one contact per lane, and the warm start from the
     //    previous step's impulse of the same key
