@@ -72,7 +72,8 @@ def _valid_desc(pt, keep):
 
 
 @pytest.mark.parametrize("field,value,code", [
-    ("K", 0, 1), ("C_max", 65, 5), ("C_max", 0, 5), ("L", 0, 5), ("S_max", 300, 5), ("newton_iters", -1, 1),
+    ("K", 0, 1), ("C_max", 65, 5), ("C_max", 0, 5), ("L", 0, 5), ("L", 63, 5), ("S_max", 257, 5),
+    ("S_max", 300, 5), ("newton_iters", -1, 1),
     ("dt", 0.0, 1), ("T", 0, 1), ("G", 9, 1), ("elite_frac", 0.0, 1), ("fb_delta", 0.0, 1),
 ])
 def test_descriptor_validation(lib, field, value, code):
@@ -100,6 +101,12 @@ def test_validation_of_tables(lib):
     assert pt._lib.pt_create_batch(C.byref(d), C.byref(h)) == 1
     assert b"parent" in pt._lib.pt_last_error()
     keep["hand"][2, 0] = 1.0
+    gs = np.array([0, 0, 8], np.int32)   # an empty group
+    keep["gs2"] = gs
+    d.G, d.group_start = 2, gs.ctypes.data
+    assert pt._lib.pt_create_batch(C.byref(d), C.byref(h)) == 1
+    assert b"non-empty" in pt._lib.pt_last_error()
+    d.G, d.group_start = 1, keep["gs"].ctypes.data
     d.state = None
     assert pt._lib.pt_create_batch(C.byref(d), C.byref(h)) == 1
 
