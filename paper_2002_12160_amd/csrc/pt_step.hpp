@@ -179,7 +179,7 @@ __device__ __forceinline__ void contact_setup(const Consts &P, const float *__re
     }
 }
 
-// The cap's ranking for ncand <= 64 H candidates: lane i holds candidates
+// The cap's ranking for ncand <= 64 H candidates (H = 1 .. 4): lane i holds candidates
 // i, i + 64, ... as packed (d, key) words (lanes past ncand the largest
 // word, never below a candidate's, so the counts run over whole groups of
 // four lanes); every word is broadcast once and each lane counts the lower
@@ -394,6 +394,8 @@ __device__ __forceinline__ void step_setup(const Consts &P, const float *__restr
         cap_rank<1>(lds, ncand, P.C_max);
     } else if (ncand <= 2 * WAVE) {
         cap_rank<2>(lds, ncand, P.C_max);
+    } else if (ncand <= 3 * WAVE) {
+        cap_rank<3>(lds, ncand, P.C_max);
     } else if (ncand <= 4 * WAVE) {
         cap_rank<4>(lds, ncand, P.C_max);
     } else {

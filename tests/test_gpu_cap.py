@@ -1,6 +1,6 @@
 """The contact cap on the GPU at every candidate count the kernel ranks
-differently (up to 64, 128 and 256 candidates held in registers, beyond that
-ranked through LDS) against the oracle: a row of spheres squeezed between the
+differently (up to 64, 128, 192 and 256 candidates held in registers,
+beyond that ranked through LDS) against the oracle: a row of spheres squeezed between the
 table and one long capsule link, every sphere a candidate of both, with
 well-separated seeded gaps, so the C_max kept keys are exact integers."""
 import numpy as np
@@ -36,7 +36,7 @@ def _row(S, seed):
     return sph.astype(np.float32).astype(np.float64)
 
 
-@pytest.mark.parametrize("S,C_max", [(24, 16), (50, 32), (100, 32), (128, 64), (200, 16)])
+@pytest.mark.parametrize("S,C_max", [(24, 16), (50, 32), (80, 32), (100, 32), (128, 64), (200, 16)])
 def test_cap_keeps_the_oracles_keys(pt, S, C_max):
     ncand = 2 * S
     print(f"cap: {S} spheres, {ncand} candidates, C_max {C_max}", flush=True)
