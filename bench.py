@@ -381,8 +381,8 @@ def realtime_run(pt, S, dev, solve_precision, n_win, n_warm=2, optimizer="pbo", 
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (the population would shard "
-                                   "across GPUs by simulation, see DESIGN.md)"}))
+        print(json.dumps({"error": "one GPU only: --gpus must be 1 (the population shards across GPUs by "
+                                   "simulation; only the one-GPU part is implemented)"}))
         sys.exit(2)
     import numpy as np
     import torch
