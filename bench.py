@@ -308,6 +308,7 @@ def realtime_run(pt, S, dev, solve_precision, n_win, n_warm=2, optimizer="pbo", 
     est_olp = torch.empty((n_total, 13, G), device=dev)
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n_total)]
     ev_rs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n_total)]
+    ev_win = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n_total)]
 
     def window(w):
         t0_ = w * T
@@ -318,7 +319,9 @@ def realtime_run(pt, S, dev, solve_precision, n_win, n_warm=2, optimizer="pbo", 
             snap[0].copy_(b.state)
             snap[1].copy_(b.params)
             snap[2].copy_(b.warm)
+        ev_win[w][0].record()
         b.run_window(u_win, gt_win, cost, best, None, graph=True)
+        ev_win[w][1].record()
         if refine:
             b.refine_elites(u_win, gt_win, cost, snap, steps=3, step=0.5, best=best)
         torch.index_select(b.state, 1, best, out=est[w])
@@ -343,12 +346,21 @@ def realtime_run(pt, S, dev, solve_precision, n_win, n_warm=2, optimizer="pbo", 
     for w in range(n_warm):
         window(w)
     torch.cuda.synchronize()
+    stats0 = b.read_stats()
     t0 = time.perf_counter()
     for w in range(n_warm, n_total):
         window(w)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    stats1 = b.read_stats()
     step_ms = np.array([ev[w][0].elapsed_time(ev[w][1]) / T for w in range(n_warm, n_total)])
+    win_s = sum(ev_win[w][0].elapsed_time(ev_win[w][1]) for w in range(n_warm, n_total)) / 1e3
+    # the population's window kernel alone (the graph replay of the
+    # persistent k_window; the refinement's forward passes do not count
+    # their steps): algorithmic flop of its steps / its HIP-event time
+    d_env = stats1["env_steps"] - stats0["env_steps"]
+    w_flops = algorithmic_flops(int(sc.n_spheres[0]), L, cfg.newton_iters, d_env,
+                                stats1["contacts"] - stats0["contacts"])
     rs_ms = np.array([ev_rs[w][0].elapsed_time(ev_rs[w][1]) for w in range(n_warm, n_total)])
     hp = setup["hposes"].cpu().numpy()
 
@@ -367,7 +379,11 @@ def realtime_run(pt, S, dev, solve_precision, n_win, n_warm=2, optimizer="pbo", 
            "budget_30hz_met": bool(np.quantile(step_ms, 0.99) < 1000.0 / 30.0),
            "resample_ms_per_window": round(float(np.median(rs_ms)), 4),
            "tracking_error_mm": tracking(est.cpu().numpy()),
-           "waves_per_workgroup": tuned}
+           "waves_per_workgroup": tuned,
+           "window_kernel": {"bound": "alu", "achieved": round(w_flops / win_s / 1e12, 4), "peak": 78.6,
+                             "unit": "TFLOP/s", "frac": round(w_flops / win_s / 1e12 / 78.6, 5),
+                             "avg_window_ms": round(win_s / n_win * 1e3, 3),
+                             "flop_per_env_step": round(w_flops / max(d_env, 1), 1)}}
     if not adapt:
         out["open_loop_tracking_error_mm"] = tracking(est_olp.cpu().numpy())
     if describe:
