@@ -36,7 +36,7 @@ def _row(S, seed):
     return sph.astype(np.float32).astype(np.float64)
 
 
-@pytest.mark.parametrize("S,C_max", [(24, 16), (50, 32), (80, 32), (100, 32), (128, 64), (200, 16)])
+@pytest.mark.parametrize("S,C_max", [(24, 1), (24, 16), (20, 64), (50, 32), (80, 32), (100, 32), (128, 64), (200, 16)])
 def test_cap_keeps_the_oracles_keys(pt, S, C_max):
     ncand = 2 * S
     print(f"cap: {S} spheres, {ncand} candidates, C_max {C_max}", flush=True)
@@ -62,7 +62,10 @@ def test_cap_keeps_the_oracles_keys(pt, S, C_max):
     stats = b.read_stats()
     b.close()
     assert stats["candidates"] == ncand
-    assert np.all(gk[0] >= 0) and np.all(wk[0] >= 0)
+    kept = min(ncand, C_max)
+    assert stats["contacts"] == kept
+    assert (gk[0] >= 0).sum() == kept and (wk[0] >= 0).sum() == kept
     # every candidate is both sphere-table and sphere-link: the kept keys are
-    # the C_max smallest gaps, the same set on both sides
-    assert sorted(gk[0].tolist()) == sorted(wk[0].tolist())
+    # the C_max smallest gaps (all of them below the cap), the same set on
+    # both sides
+    assert sorted(gk[0][gk[0] >= 0].tolist()) == sorted(wk[0][wk[0] >= 0].tolist())
