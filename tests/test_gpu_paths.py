@@ -103,21 +103,22 @@ def _assert_same(a, b, what):
         assert torch.equal(x, y), f"{what}: {k} differs in {(x != y).sum().item()} words"
 
 
-@pytest.mark.parametrize("cfg_name,K", [("small", 37), ("batched4096", 96), ("small/C_max=64", 37)])
-def test_batched_equals_plain_bitwise(pt, cfg_name, K):
+@pytest.mark.parametrize("cfg_name,K,prec", [("small", 37, 64), ("batched4096", 96, 64), ("small/C_max=64", 37, 64),
+                                           ("small/C_max=64", 37, 32)])
+def test_batched_equals_plain_bitwise(pt, cfg_name, K, prec):
     # "small/C_max=64": a cap above 32 makes the window kernel try the line
     # search's step sizes one at a time while the per-step kernel still
     # pairs them on the two half-waves in every step with at most 32
     # contacts (16- and 32-lane sums): the two forms must give the same bits
-    _say(f"plain vs batched: {cfg_name} K={K}")
+    _say(f"plain vs batched: {cfg_name} K={K}, solve precision {prec}")
     name, _, cap = cfg_name.partition("/C_max=")
     cfg = S.CONFIGS[name]
     if cap:
         cfg = cfg.with_(C_max=int(cap))
     sc = S.make_scene(cfg, K=K, steps=40)
-    ref = run_plain(pt, sc, 3, cfg.T)
+    ref = run_plain(pt, sc, 3, cfg.T, solve_precision=prec)
     for graph in (False, True):
-        got = run_batched(pt, sc, 3, cfg.T, graph=graph)
+        got = run_batched(pt, sc, 3, cfg.T, graph=graph, solve_precision=prec)
         _assert_same(ref, got, f"graph={graph}")
 
 
