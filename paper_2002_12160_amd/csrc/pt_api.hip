@@ -222,11 +222,11 @@ pt_status pt_create_batch(const pt_batch_desc *d, pt_batch *out)
     // step with more cuts its list to the C_max lowest and goes on -- plus 8
     // entries of padding for the cap's 16-byte reads); the same LDS holds,
     // once the cap has run, the rows of the solve's cross-contact sums
-    // (lane_span(C_max) rows of 50 doubles)
+    // (lane_span(C_max) rows of RedStride<double> = 44 doubles)
     const int red_rows = d->C_max <= 16 ? 16 : (d->C_max <= 32 ? 32 : 64);
     // ... and the step's hand kinematics, which use the same LDS first
     const int max_cand = std::max({round_up(std::min(d->S_max * (d->L + 1), pt::CAND_CAP) + 8, 64),
-                                   round_up(red_rows * 50, 64),
+                                   round_up(red_rows * pt::RedStride<double>::value, 64),
                                    round_up((int)((hand_fk_lds_bytes(d->L, d->D) + 7) / 8), 64)});
     const size_t wave_lds = pt::wave_lds_bytes(max_cand, d->L);
     if (wave_lds > 160 * 1024)

@@ -529,12 +529,14 @@ __device__ __forceinline__ void solve6(const T (&S)[36], T (&b)[6])
     }
 }
 
-// Row stride (elements) of the LDS reduction buffer: rows start 16-byte
-// aligned and 4 banks apart, so the row writes of a wavefront spread over
-// all banks.
+// Row stride (elements) of the LDS reduction buffer: rows 16-byte aligned,
+// and the 16-byte row writes of eight consecutive lanes on distinct banks
+// (44 doubles = 88 dwords, rows 24 banks apart); for doubles the narrowest
+// stride that holds the 43 sums, since with caps above 32 its 64 rows set
+// a simulation's LDS and with it how many wavefronts a compute unit holds
 template <typename T>
 struct RedStride {
-    static constexpr int value = sizeof(T) == 8 ? 50 : 68;
+    static constexpr int value = sizeof(T) == 8 ? 44 : 68;
 };
 
 template <typename T>
