@@ -416,8 +416,7 @@ __global__ void k_argmin(const int32_t *__restrict__ group_start, const float *_
 // ---------------------------------------------------------------------
 // copy item i of a resample (i < nr: simulation kb + i / rows of the sorted
 // group, row or slot i % rows) read from its parent / written to the child
-__device__ __forceinline__ float state_row_src(const float *state, int K, int lo, int kb, const int *order,
-                                               const int *par, int nr, int i)
+__device__ __forceinline__ float state_row_src(const float *state, int K, int kb, const int *par, int nr, int i)
 {
     if (i >= nr * 13) return 0.f;
     const int t = kb + i / 13, c = i - (i / 13) * 13;
@@ -489,10 +488,10 @@ __global__ __launch_bounds__(1024) void k_resample(Consts P, ResampleArgs R, con
     const int nt = blockDim.x;
     for (int i0 = threadIdx.x; i0 < nr * 13; i0 += 4 * nt) {
         const int i1 = i0 + nt, i2 = i0 + 2 * nt, i3 = i0 + 3 * nt;
-        const float v0 = state_row_src(state, K, lo, kb, order, par, nr, i0);
-        const float v1 = state_row_src(state, K, lo, kb, order, par, nr, i1);
-        const float v2 = state_row_src(state, K, lo, kb, order, par, nr, i2);
-        const float v3 = state_row_src(state, K, lo, kb, order, par, nr, i3);
+        const float v0 = state_row_src(state, K, kb, par, nr, i0);
+        const float v1 = state_row_src(state, K, kb, par, nr, i1);
+        const float v2 = state_row_src(state, K, kb, par, nr, i2);
+        const float v3 = state_row_src(state, K, kb, par, nr, i3);
         state_row_dst(state, K, lo, kb, order, nr, i0, v0);
         state_row_dst(state, K, lo, kb, order, nr, i1, v1);
         state_row_dst(state, K, lo, kb, order, nr, i2, v2);

@@ -179,11 +179,11 @@ __device__ __forceinline__ void contact_setup(const Consts &P, const float *__re
     }
 }
 
-// The cap's ranking for ncand <= 64 H candidates (H = 1 .. 4): lane i holds candidates
-// i, i + 64, ... as packed (d, key) words (lanes past ncand the largest
-// word, never below a candidate's, so the counts run over whole groups of
-// four lanes); every word is broadcast once and each lane counts the lower
-// ones for each word it holds.  Keys are unique, so the ranks are a
+// The cap's ranking for ncand <= 64 H candidates (H = 1 .. 4): lane i
+// holds candidates i, i + 64, ... as packed (d, key) words (lanes past
+// ncand the largest word, never below a candidate's, so the counts run over
+// whole groups of four lanes); every word is broadcast once and each lane
+// counts the lower ones for each word it holds.  Keys are unique, so the ranks are a
 // permutation; the C_max lowest candidates' keys land in sel[rank].
 template <int H>
 __device__ __forceinline__ void cap_rank(const WaveLds &lds, int ncand, int C_max)
