@@ -44,8 +44,9 @@ def parse():
     ap.add_argument("--solve-precision", type=int, default=64, choices=[32, 64])
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the batched + elite-refinement legs")
-    ap.add_argument("--realtime-windows", type=int, default=30,
-                    help="timed windows of the 16384-simulation real-time workload (0 skips it)")
+    ap.add_argument("--realtime-windows", type=int, default=180,
+                    help="timed windows of the 16384-simulation real-time workload: 180 x 10 steps is the "
+                         "workload's 60 s at 30 Hz (0 skips it)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-optimizers", action="store_true",
                     help="skip the WRS / REPS / identity comparison on the real-time workload")
