@@ -395,6 +395,39 @@ def realtime_run(pt, S, dev, solve_precision, n_win, n_warm=2, optimizer="pbo", 
     return out
 
 
+def plain_run(pt, sc, dev, solve_precision, steps, warmup):
+    """The plain per-step path on a scene (step, observe, cost with the
+    argmin, the resampler every T steps): env-steps/s over `steps` timed
+    steps after `warmup`."""
+    import torch
+    K, G, T = sc.K, sc.G, sc.cfg.T
+    gts = observed_forces(pt, sc, dev, solve_precision, warmup + steps)
+    u_all = torch.as_tensor(sc.u.astype("float32"), device=dev)
+    b = pt.Batch.from_scene(sc, solve_precision=solve_precision)
+    cost = torch.zeros(K, device=dev)
+    best = torch.zeros(G, dtype=torch.int32, device=dev)
+    parent = torch.zeros(K, dtype=torch.int32, device=dev)
+    obs = b.new_obs()
+
+    def one(t):
+        b.step(u_all[max(t - 1, 0)], u_all[t])
+        b.observe(obs)
+        b.cost(obs, gts[t], cost, best)
+        if (t + 1) % T == 0:
+            b.resample(cost, (t + 1) // T - 1, parent)
+
+    for t in range(warmup):
+        one(t)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for t in range(warmup, warmup + steps):
+        one(t)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    b.close()
+    return {"value": round(K * steps / wall, 1), "unit": "env-steps/s", "ms_per_step": round(wall / steps * 1e3, 4)}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -532,6 +565,18 @@ def main():
                             f"{acfg.newton_iters} Newton iterations, {acfg.T}-step windows",
                 "batched": a_b, "batched_adjoint": a_a,
                 "adjoint_cost_ratio": round(a_b["value"] / a_a["value"], 3)}
+            # the batching workload: 4096 simulations of three object
+            # types (32-, 64- and 128-sphere), 64-contact cap, plain
+            # per-step launches against the persistent kernel + graph
+            bcfg = S.CONFIGS["batched4096"]
+            bsc = S.make_scene(bcfg, steps=max(total_steps, (n_win + n_warm + 2) * bcfg.T) + 1)
+            b_p = plain_run(pt, bsc, dev, args.solve_precision, args.steps, args.warmup)
+            b_b = batched_run(pt, S, bsc, dev, args.solve_precision, n_win, n_warm, adjoint=False)
+            result["batched4096"] = {
+                "workload": f"{bcfg.name}: {bsc.K} simulations + {bsc.G} observed, {bsc.L} capsule links, "
+                            f"objects of {sorted(set(int(x) for x in bsc.n_spheres))} spheres, "
+                            f"C_max={bcfg.C_max}, {bcfg.newton_iters} Newton iterations, {bcfg.T}-step windows",
+                "plain": b_p, "batched": b_b, "speedup_vs_plain": round(b_b["value"] / b_p["value"], 3)}
 
     # ---------------- real-time workload (16384 simulations) -------------
     if not args.no_batched and not args.no_adjoint and args.realtime_windows > 0:
