@@ -510,7 +510,7 @@ def main():
     main_b.close()
 
     result = {
-        "metric": "env-steps/sec (step+observe+cost)",
+        "metric": "env-steps/sec (step+observe+cost) plain vs batched vs +adjoint, 30Hz budget met",
         "value": round(plain_value, 1),
         "unit": "env-steps/s",
         "n_gpus": 1,
