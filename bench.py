@@ -62,7 +62,7 @@ def parse():
 # from FETCH_SIZE / WRITE_SIZE counters scaled by a plain device copy of known
 # size (profiles/k_step_plain256.txt); None where the kernel changed since
 # the counters were taken, and for any other configuration
-MEASURED_TRAFFIC = {("plain256", 64): 1097840}
+MEASURED_TRAFFIC = {("plain256", 64): 1097835}
 
 # VALU counters per k_step launch of the same workload (profiles/
 # k_step_plain256.txt): SQ_INSTS_VALU, SQ_ACTIVE_INST_VALU (quad-cycles) and
