@@ -52,9 +52,10 @@ def run_plain(pt, sc, windows, T, resample=True, solve_precision=64):
             b.resample(cost, w, parent)
             parents.append(parent.clone())
     torch.cuda.synchronize()
+    stats = b.read_stats()
     out = dict(state=b.state.clone(), params=b.params.clone(), warm=b.warm.clone(), obs=torch.stack(obs_hist),
                best=torch.stack(bests), costs=torch.stack(costs),
-               parent=torch.stack(parents) if parents else None)
+               parent=torch.stack(parents) if parents else None, stats=stats)
     b.close()
     h.close()
     return out
@@ -86,9 +87,10 @@ def run_batched(pt, sc, windows, T, graph, wpb=None, resample=True, solve_precis
             b.resample(cost, w, parent)
             parents.append(parent.clone())
     torch.cuda.synchronize()
+    stats = b.read_stats()
     out = dict(state=b.state.clone(), params=b.params.clone(), warm=b.warm.clone(), obs=torch.cat(obs_hist),
                best=torch.stack(bests), costs=torch.stack(costs),
-               parent=torch.stack(parents) if parents else None)
+               parent=torch.stack(parents) if parents else None, stats=stats)
     b.close()
     h.close()
     return out
@@ -101,6 +103,9 @@ def _assert_same(a, b, what):
             continue
         x, y = a[k].contiguous().view(torch.int32), b[k].contiguous().view(torch.int32)
         assert torch.equal(x, y), f"{what}: {k} differs in {(x != y).sum().item()} words"
+    # the step statistics (summed over their atomic slots) count the same
+    # steps, candidates, contacts and drops on both paths
+    assert a["stats"] == b["stats"], f"{what}: {a['stats']} != {b['stats']}"
 
 
 @pytest.mark.parametrize("cfg_name,K,prec", [("small", 37, 64), ("batched4096", 96, 64), ("small/C_max=64", 37, 64),
