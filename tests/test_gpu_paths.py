@@ -109,8 +109,9 @@ def _assert_same(a, b, what):
 
 
 @pytest.mark.parametrize("cfg_name,K,prec", [("small", 37, 64), ("batched4096", 96, 64), ("small/C_max=64", 37, 64),
-                                           ("small/C_max=64", 37, 32)])
+                                           ("small/C_max=64", 37, 32), ("small", 300, 64)])
 def test_batched_equals_plain_bitwise(pt, cfg_name, K, prec):
+    # K = 300: more simulations than statistics slots (they wrap around)
     # "small/C_max=64": a cap above 32 makes the window kernel try the line
     # search's step sizes one at a time while the per-step kernel still
     # pairs them on the two half-waves in every step with at most 32
