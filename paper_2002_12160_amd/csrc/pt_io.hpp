@@ -45,6 +45,37 @@ __device__ __forceinline__ void load_body(const float *__restrict__ state, const
     B.f[0] = params[2 * K + e]; B.f[1] = params[3 * K + e]; B.f[2] = params[4 * K + e];
 }
 
+// The body of simulation e spread over the lanes of a wavefront: lane r < 18
+// holds row r of the load_body order (13 state rows, then the 5 parameter
+// rows).  One vector load covers the whole body, so it is in flight with the
+// step's other first loads instead of 18 scalar loads that register
+// pressure would wait for a few at a time; body_from_rows reads it out
+// (readlane) where the values are needed.
+__device__ __forceinline__ float load_body_rows(const float *__restrict__ state, const float *__restrict__ params,
+                                                int K, int e)
+{
+    const int lane = lane_id();
+    float v = 0.f;
+    if (lane < 13)
+        v = state[(size_t)lane * K + e];
+    else if (lane < 18)
+        v = params[(size_t)(lane - 13) * K + e];
+    return v;
+}
+
+__device__ __forceinline__ void body_from_rows(float v, Body &B)
+{
+    float r[18];
+#pragma unroll
+    for (int i = 0; i < 18; ++i) r[i] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), i));
+    B.x[0] = r[0]; B.x[1] = r[1]; B.x[2] = r[2];
+    B.q[0] = r[3]; B.q[1] = r[4]; B.q[2] = r[5]; B.q[3] = r[6];
+    B.v[0] = r[7]; B.v[1] = r[8]; B.v[2] = r[9];
+    B.w[0] = r[10]; B.w[1] = r[11]; B.w[2] = r[12];
+    B.m = r[13]; B.mu = r[14];
+    B.f[0] = r[15]; B.f[1] = r[16]; B.f[2] = r[17];
+}
+
 __device__ __forceinline__ void store_body(float *__restrict__ state, float *__restrict__ params, int K, int e,
                                            const Body &B)
 {

@@ -263,8 +263,7 @@ __global__ __launch_bounds__(StepBounds<SR>::threads) void k_step(Consts P, Tabl
     const int S = tb.n_spheres[type];
     const float *sph = tb.spheres + (size_t)type * P.S_max * 4;
     const float inv[3] = {tb.inv_inertia[3 * type], tb.inv_inertia[3 * type + 1], tb.inv_inertia[3 * type + 2]};
-    Body B;
-    load_body(state, params, P.K, e, B);
+    const float rows = load_body_rows(state, params, P.K, e);
     int wkey;
     float wr[3];
     load_warm(warm, P.C_max, e, wkey, wr);
@@ -275,6 +274,8 @@ __global__ __launch_bounds__(StepBounds<SR>::threads) void k_step(Consts P, Tabl
     hand_kinematics(tb.hand, P.L, P.D, P.dt, u_prev, u, carve_fk(reinterpret_cast<char *>(lds.cand_d), P.L, P.D),
                     lds.seg,
                     lane_id(), WAVE, [] { wave_sync(); });
+    Body B;
+    body_from_rows(rows, B);
     const float *seg = lds.seg;
     StepStats st = {0, 0, 0};
     int link;
