@@ -37,24 +37,33 @@ __device__ __forceinline__ void quat_mul_d(const double *a, const double *b, dou
     o[0] = w; o[1] = x; o[2] = y; o[3] = z;
 }
 
-// joint rotation of link l for joint vector u: Rot(axis0, u[j0]) Rot(axis1, u[j1])
-__device__ __forceinline__ void fk_joint(const float *__restrict__ h, const float *__restrict__ u, double *qj)
+// Joint rotation of a link for joint vector u, Rot(axis0, u[j0]) Rot(axis1,
+// u[j1]) (identity for a joint index < 0), by a pair of adjacent lanes: lane
+// j of the pair (j = 0, 1) evaluates the half-angle rotation of joint j, the
+// odd lane's moves to the even one (DPP, quad_perm [1,0,3,2]), which composes
+// the two and writes them to qj.  Both lanes of the pair must be active.
+__device__ __forceinline__ void fk_joint_pair(const float *__restrict__ h, const float *__restrict__ u, int j,
+                                              double *qj)
 {
-    int j0 = (int)h[1], j1 = (int)h[2];
+    const int jx = (int)h[1 + j];
+    const float *ax = h + 3 + 3 * j;
     double q[4] = {1, 0, 0, 0};
-    if (j0 >= 0) {
+    if (jx >= 0) {
         double s, c;
-        sincos(0.5 * (double)u[j0], &s, &c);
-        q[0] = c; q[1] = s * h[3]; q[2] = s * h[4]; q[3] = s * h[5];
+        sincos(0.5 * (double)u[jx], &s, &c);
+        q[0] = c; q[1] = s * ax[0]; q[2] = s * ax[1]; q[3] = s * ax[2];
     }
-    if (j1 >= 0) {
-        double s, c;
-        sincos(0.5 * (double)u[j1], &s, &c);
-        double r[4] = {c, s * h[6], s * h[7], s * h[8]}, t[4];
-        quat_mul_d(q, r, t);
-        for (int i = 0; i < 4; ++i) q[i] = t[i];
+    double r[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) r[i] = dpp_f<0xb1, 0xf>(q[i]);
+    if (j == 0) {
+        if ((int)h[2] >= 0) {
+            double t[4];
+            quat_mul_d(q, r, t);
+            for (int i = 0; i < 4; ++i) q[i] = t[i];
+        }
+        for (int i = 0; i < 4; ++i) qj[i] = q[i];
     }
-    for (int i = 0; i < 4; ++i) qj[i] = q[i];
 }
 
 // pose of link l in configuration w from its parent's (already computed):
@@ -129,9 +138,10 @@ __device__ __forceinline__ FkLds carve_fk(char *p, int L, int D)
     return s;
 }
 
-// Hand kinematics of one step by nt cooperating threads (tid in [0, nt)):
-// the link table staged in LDS, the joint rotations (the transcendental
-// part) one thread per (configuration, link), the chains composed level by
+// Hand kinematics of one step by nt cooperating threads (tid in [0, nt), nt
+// even, a wavefront's lanes in order): the link table staged in LDS, the joint
+// rotations (the transcendental part) one thread per (configuration, link,
+// joint), the chains composed level by
 // level of the link tree (links at one depth in parallel, both
 // configurations at once), then the segment record of every link: a,
 // b - a, the radius, 1/|b - a|^2 and the end-point velocities
@@ -179,10 +189,11 @@ __device__ __forceinline__ void hand_kinematics(const float *__restrict__ hand, 
         }
         s.depth[l] = d;
     }
-    for (int i = tid; i < 2 * L; i += nt) {
-        int w = i / L, l = i - w * L;
+    // thread pairs (2m, 2m + 1) share an iteration (4 L and nt are even)
+    for (int i = tid; i < 4 * L; i += nt) {
+        const int w = i / (2 * L), r = i - w * 2 * L, l = r >> 1;
         const float *uw = Ds > 0 ? s.su + w * Ds : (w == 0 ? u_prev : u);
-        fk_joint(s.hs + l * HAND_STRIDE, uw, s.qj(w) + 4 * l);
+        fk_joint_pair(s.hs + l * HAND_STRIDE, uw, r & 1, s.qj(w) + 4 * l);
     }
     sync();
     int dmax = 0;
