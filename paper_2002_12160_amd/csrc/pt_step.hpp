@@ -218,6 +218,78 @@ __device__ __forceinline__ void cap_rank(const WaveLds &lds, int ncand, int C_ma
         if (lane + WAVE * h < ncand && rank[h] < C_max) lds.sel[rank[h]] = ki[h];
 }
 
+// The cap for C_max < ncand <= 64 H (H = 2..4), with the same sel[] as
+// cap_rank<H>: the C_max-th lowest packed (d, key) word is found bit by bit
+// (radix select: a bit of the boundary stays set while fewer than C_max
+// words lie below the trial value, counted by ballots), first over the 32
+// gap bits and, only when several words share the boundary gap, over their
+// key bits; the C_max words up to the boundary move to the front of the
+// list and cap_rank<1> ranks them among themselves, which is their rank
+// among all candidates (every lower word is kept too).  32 rounds of H
+// compares instead of ncand broadcasts against H words per lane.
+template <int H>
+__device__ __forceinline__ void cap_select(const WaveLds &lds, int ncand, int C_max)
+{
+    const int lane = lane_id();
+    uint32_t hi[H], lo[H];
+    float d[H];
+#pragma unroll
+    for (int h = 0; h < H; ++h) {
+        const int i = lane + WAVE * h;
+        hi[h] = lo[h] = ~0u;   // above every candidate: gaps are finite
+        d[h] = 0.f;
+        if (i < ncand) {
+            d[h] = lds.cand_d[i];
+            const uint64_t w = pack_gap_key(d[h], lds.cand_k[i]);
+            hi[h] = (uint32_t)(w >> 32);
+            lo[h] = (uint32_t)w;
+        }
+    }
+    uint32_t ph = 0;
+    for (int b = 31; b >= 0; --b) {
+        const uint32_t t = ph | (1u << b);
+        int cnt = 0;
+#pragma unroll
+        for (int h = 0; h < H; ++h) cnt += __popcll(__ballot(hi[h] < t));
+        if (cnt < C_max) ph = t;
+    }
+    // ph: the boundary gap word (fewer than C_max words below it, at least
+    // C_max up to it)
+    int below = 0, at = 0;
+#pragma unroll
+    for (int h = 0; h < H; ++h) {
+        below += __popcll(__ballot(hi[h] < ph));
+        at += __popcll(__ballot(hi[h] == ph));
+    }
+    uint32_t pl = ~0u;
+    if (below + at > C_max) {
+        const int need = C_max - below;
+        pl = 0;
+        for (int b = 31; b >= 0; --b) {
+            const uint32_t t = pl | (1u << b);
+            int cnt = 0;
+#pragma unroll
+            for (int h = 0; h < H; ++h) cnt += __popcll(__ballot(hi[h] == ph && lo[h] < t));
+            if (cnt < need) pl = t;
+        }
+    }
+    wave_sync();   // every lane has read its entries before the list is rewritten
+    int base = 0;
+#pragma unroll
+    for (int h = 0; h < H; ++h) {
+        const bool keep = hi[h] < ph || (hi[h] == ph && lo[h] <= pl);
+        const uint64_t m = __ballot(keep);
+        if (keep) {
+            const int at2 = base + mask_rank(m);
+            lds.cand_d[at2] = d[h];
+            lds.cand_k[at2] = (int)lo[h];
+        }
+        base += __popcll(m);
+    }
+    wave_sync();
+    cap_rank<1>(lds, C_max, C_max);
+}
+
 // The cap's ranking for any n: every lane ranks its candidates against the
 // LDS list, eight per pair of 16-byte reads (entries past n padded with
 // (+inf, INT_MAX), never below); the keys of the C_max lowest go to
@@ -385,19 +457,21 @@ __device__ __forceinline__ void step_setup(const Consts &P, const float *__restr
     st.span = lane_span(C);
 
     // 3. cap: rank of every candidate in (d, key) order; the C_max lowest
-    //    land in sel[rank].  Up to four waves of candidates each lane holds
-    //    one to four of them as packed (d, key) words and counts the lower
-    //    words, broadcast lane by lane; beyond, every lane ranks its
-    //    candidates against the LDS list, eight per pair of 16-byte reads
-    //    (entries past ncand padded with (+inf, INT_MAX), never below).
+    //    land in sel[rank].  Up to one wave of candidates each lane holds
+    //    one as a packed (d, key) word and counts the lower words,
+    //    broadcast lane by lane; up to four, a radix select finds the
+    //    C_max lowest first and only they are ranked; beyond, every lane
+    //    ranks its candidates against the LDS list, eight per pair of
+    //    16-byte reads (entries past ncand padded with (+inf, INT_MAX),
+    //    never below).
     if (ncand <= WAVE) {
         cap_rank<1>(lds, ncand, P.C_max);
     } else if (ncand <= 2 * WAVE) {
-        cap_rank<2>(lds, ncand, P.C_max);
+        cap_select<2>(lds, ncand, P.C_max);
     } else if (ncand <= 3 * WAVE) {
-        cap_rank<3>(lds, ncand, P.C_max);
+        cap_select<3>(lds, ncand, P.C_max);
     } else if (ncand <= 4 * WAVE) {
-        cap_rank<4>(lds, ncand, P.C_max);
+        cap_select<4>(lds, ncand, P.C_max);
     } else {
         cap_rank_lds(lds, ncand, P.C_max, nullptr);
     }
