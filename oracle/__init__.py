@@ -45,6 +45,7 @@ class Model(C.Structure):
         ("hand", C.POINTER(C.c_double)), ("spheres", C.POINTER(C.c_double)),
         ("n_spheres", C.POINTER(C.c_int32)), ("inv_inertia", C.POINTER(C.c_double)),
         ("cost_mode", C.c_int32), ("tau_slip", C.c_double), ("tau_spin", C.c_double), ("w_eq3", C.c_double * 7),
+        ("geom_f32", C.c_int32),
     ]
 
 
@@ -58,7 +59,9 @@ class Contact(C.Structure):
 class Diag(C.Structure):
     _fields_ = [("n_candidates", C.c_int32), ("n_contacts", C.c_int32), ("iters", C.c_int32),
                 ("n_full_steps", C.c_int32), ("psi_first", C.c_double), ("psi_final", C.c_double),
-                ("d_last_kept", C.c_double), ("d_first_dropped", C.c_double)]
+                ("d_last_kept", C.c_double), ("d_first_dropped", C.c_double),
+                ("armijo_margin", C.c_double), ("tangent_tie", C.c_double), ("margin_gap", C.c_double),
+                ("n_fallback", C.c_int32), ("reserved", C.c_int32)]
 
 
 class ResampleCfg(C.Structure):
@@ -73,7 +76,9 @@ CONTACT_DTYPE = np.dtype([("key", np.int32), ("link", np.int32), ("d", np.float6
                           ("u", np.float64, 3)])
 DIAG_DTYPE = np.dtype([("n_candidates", np.int32), ("n_contacts", np.int32), ("iters", np.int32),
                        ("n_full_steps", np.int32), ("psi_first", np.float64), ("psi_final", np.float64),
-                       ("d_last_kept", np.float64), ("d_first_dropped", np.float64)])
+                       ("d_last_kept", np.float64), ("d_first_dropped", np.float64),
+                       ("armijo_margin", np.float64), ("tangent_tie", np.float64), ("margin_gap", np.float64),
+                       ("n_fallback", np.int32), ("reserved", np.int32)])
 assert CONTACT_DTYPE.itemsize == C.sizeof(Contact)
 assert DIAG_DTYPE.itemsize == C.sizeof(Diag)
 
@@ -132,7 +137,7 @@ class Oracle:
     """Holds one scene description (hand, objects, constants) for the C oracle."""
 
     def __init__(self, hand, spheres, n_spheres, inv_inertia, consts, C_max, newton_iters,
-                 D=None, converged=False, conv_tol=1e-26, conv_max_iters=100):
+                 D=None, converged=False, conv_tol=1e-26, conv_max_iters=100, geom_f32=False):
         self.hand = np.ascontiguousarray(hand, dtype=np.float64)
         self.spheres = np.ascontiguousarray(spheres, dtype=np.float64)
         self.n_spheres = np.ascontiguousarray(n_spheres, dtype=np.int32)
@@ -160,6 +165,8 @@ class Oracle:
         m.tau_slip, m.tau_spin = getattr(consts, "tau_slip", 0.005), getattr(consts, "tau_spin", 0.1)
         for i, wv in enumerate(getattr(consts, "w_eq3", (1.0,) * 7)):
             m.w_eq3[i] = wv
+        # diagnostic: geometry rounded to float32 (see oracle.h)
+        m.geom_f32 = int(geom_f32)
         m.hand = _dp(self.hand)
         m.spheres = _dp(self.spheres)
         m.n_spheres = _ip(self.n_spheres)

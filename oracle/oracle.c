@@ -87,6 +87,25 @@ static void qnormalize(double *q)
     q[0] /= n; q[1] /= n; q[2] /= n; q[3] /= n;
 }
 
+/* Diagnostic rounding of n geometric values to float32 (model flag
+ * geom_f32): 1 rounds to the nearest float32; 2 also moves each rounded
+ * value one float32 step up or down, the direction taken from a hash of its
+ * bits (a second probe of the size of float32 arithmetic error). */
+static void geom_round(const or_model *m, double *v, int n)
+{
+    if (!m->geom_f32) return;
+    for (int i = 0; i < n; ++i) {
+        float f = (float)v[i];
+        if (m->geom_f32 == 2 && f != 0.0f && isfinite(f)) {
+            uint32_t bits;
+            memcpy(&bits, &f, sizeof bits);
+            uint32_t h = bits * 0x9E3779B1u;
+            f = nextafterf(f, (h >> 31) ? INFINITY : -INFINITY);
+        }
+        v[i] = (double)f;
+    }
+}
+
 /* ------------------------------------------------------------------ */
 /* hand forward kinematics                                             */
 /* ------------------------------------------------------------------ */
@@ -373,6 +392,7 @@ typedef struct {
     double mass, mu;
     int ncand, C;
     double d_last_kept, d_first_dropped;
+    double margin_gap, tangent_tie;
     or_contact *cc; /* [C] */
     double *J;      /* [3C][6] */
     double *uf;     /* [3C]    */
@@ -405,6 +425,8 @@ static void build_system(const or_model *m, const double *seg0, const double *se
     q[0] = st[3]; q[1] = st[4]; q[2] = st[5]; q[3] = st[6];
     qnormalize(q);
     qmat(q, R);
+    geom_round(m, q, 4);
+    geom_round(m, R, 9);
     double v[3] = {st[7], st[8], st[9]}, w[3] = {st[10], st[11], st[12]};
     /* I_w^{-1} = R diag(inv/m) R^T */
     double *Iinv = y->Iinv;
@@ -414,6 +436,7 @@ static void build_system(const or_model *m, const double *seg0, const double *se
             for (int k = 0; k < 3; ++k) s += R[3 * i + k] * (inv[k] / mass) * R[3 * j + k];
             Iinv[3 * i + j] = s;
         }
+    geom_round(m, Iinv, 9);
 
     /* 2. free velocity */
     double *vs = y->vs, *ws = y->ws;
@@ -421,19 +444,24 @@ static void build_system(const or_model *m, const double *seg0, const double *se
         vs[i] = v[i] + dt * (m->gravity[i] + fp[i] / mass);
         ws[i] = w[i];
     }
+    geom_round(m, vs, 3);
 
     /* 3-5. candidates */
     int npair = S * (L + 1);
     cand_t *cand = (cand_t *)malloc(sizeof(cand_t) * (size_t)(npair > 0 ? npair : 1));
     int ncand = 0;
+    y->margin_gap = INFINITY;
     for (int k = 0; k < S; ++k) {
         double c[3];
         matvec(R, sph + 4 * k, c);
         c[0] += x[0]; c[1] += x[1]; c[2] += x[2];
+        geom_round(m, c, 3);
         double rho = sph[4 * k + 3];
         for (int l = 0; l <= L; ++l) {
             double d, n[3], p[3], vl[3];
             pair_geometry(m, seg0, seg1, l, c, rho, &d, n, p, vl);
+            geom_round(m, &d, 1);
+            if (fabs(d - m->margin) < y->margin_gap) y->margin_gap = fabs(d - m->margin);
             if (d < m->margin) {
                 cand[ncand].d = d;
                 cand[ncand].key = k * (L + 1) + l;
@@ -454,18 +482,36 @@ static void build_system(const or_model *m, const double *seg0, const double *se
     int n3 = 3 * C;
     double *J = (double *)calloc((size_t)(n3 > 0 ? n3 : 1) * 6, sizeof(double));
     double *uf = (double *)calloc((size_t)(n3 > 0 ? n3 : 1), sizeof(double));
+    y->tangent_tie = INFINITY;
     for (int c = 0; c < C; ++c) {
         int key = cand[c].key;
         int k = key / (L + 1), l = key % (L + 1);
         double ctr[3];
         matvec(R, sph + 4 * k, ctr);
         ctr[0] += x[0]; ctr[1] += x[1]; ctr[2] += x[2];
+        geom_round(m, ctr, 3);
         or_contact *o = cc + c;
         o->key = key;
         o->link = l;
         pair_geometry(m, seg0, seg1, l, ctr, sph[4 * k + 3], &o->d, o->n, o->p, o->vlink);
+        geom_round(m, &o->d, 1);
+        geom_round(m, o->n, 3);
+        geom_round(m, o->p, 3);
+        geom_round(m, o->vlink, 3);
         tangent_frame(o->n, o->t1, o->t2);
+        geom_round(m, o->t1, 3);
+        geom_round(m, o->t2, 3);
+        if (l < L) {
+            /* distance of the tangent-axis rule from a tie: the two smallest
+             * |n_i| (a table contact's normal is exactly e_z on any
+             * implementation, so its tie of x and y is exact, not near) */
+            double a0 = fabs(o->n[0]), a1 = fabs(o->n[1]), a2 = fabs(o->n[2]);
+            double lo = fmin(a0, fmin(a1, a2)), hi = fmax(a0, fmax(a1, a2));
+            double mid = a0 + a1 + a2 - lo - hi;
+            if (mid - lo < y->tangent_tie) y->tangent_tie = mid - lo;
+        }
         double rho[3] = {o->p[0] - x[0], o->p[1] - x[1], o->p[2] - x[2]};
+        geom_round(m, rho, 3);
         const double *dirs[3] = {o->n, o->t1, o->t2};
         /* velocity of the object's material point at p under (vs, ws) */
         double wr_[3];
@@ -546,8 +592,9 @@ int or_env_step(const or_model *m, const double *seg0, const double *seg1, int t
     double *Phi = (double *)calloc((size_t)(n3 > 0 ? n3 : 1), sizeof(double));
     double *dr = (double *)calloc((size_t)(n3 > 0 ? n3 : 1), sizeof(double));
     double *rt = (double *)calloc((size_t)(n3 > 0 ? n3 : 1), sizeof(double));
-    int iters = 0, nfull = 0;
+    int iters = 0, nfull = 0, nfall = 0;
     double psi_first = 0, psi = 0;
+    double armijo_margin = INFINITY;
     if (C > 0) {
         int maxit = m->converged ? m->conv_max_iters : m->newton_iters;
         for (int it = 0; it < maxit; ++it) {
@@ -576,11 +623,25 @@ int or_env_step(const or_model *m, const double *seg0, const double *seg1, int t
             /* Armijo backtracking on Psi = 1/2 |Phi|^2 */
             double alpha = 0.125;
             double a = 1.0;
+            double drmax = 0, rmax = 0;
+            for (int i = 0; i < n3; ++i) {
+                if (fabs(dr[i]) > drmax) drmax = fabs(dr[i]);
+                if (fabs(r[i]) > rmax) rmax = fabs(r[i]);
+            }
+            double rscale = fmax(mass * norm3(m->gravity) * dt, rmax);
+            int passed = 0;
             for (int t = 0; t < 4; ++t, a *= 0.5) {
                 for (int i = 0; i < n3; ++i) rt[i] = r[i] + a * dr[i];
                 double pt = merit(m, C, mu, W, uf, rt, u);
-                if (pt <= (1.0 - 2.0 * m->armijo_sigma * a) * psi) { alpha = a; break; }
+                double bound = (1.0 - 2.0 * m->armijo_sigma * a) * psi;
+                /* diagnostics: how close this trial's decision is to flipping */
+                if (t < 3 && psi > 0 && 0.5 * a * drmax > OR_ARMIJO_IMPACT * rscale) {
+                    double rel = fabs(pt - bound) / psi;
+                    if (rel < armijo_margin) armijo_margin = rel;
+                }
+                if (pt <= bound) { alpha = a; passed = 1; break; }
             }
+            if (!passed) ++nfall;
             if (alpha == 1.0) ++nfull;
             for (int i = 0; i < n3; ++i) r[i] += alpha * dr[i];
             ++iters;
@@ -652,6 +713,11 @@ int or_env_step(const or_model *m, const double *seg0, const double *seg1, int t
         dg->psi_final = psi;
         dg->d_last_kept = y.d_last_kept;
         dg->d_first_dropped = y.d_first_dropped;
+        dg->armijo_margin = armijo_margin;
+        dg->tangent_tie = y.tangent_tie;
+        dg->margin_gap = y.margin_gap;
+        dg->n_fallback = nfall;
+        dg->reserved = 0;
     }
     free(r); free(u); free(A); free(Phi); free(dr); free(rt);
     sys_free(&y);
@@ -826,6 +892,8 @@ void or_batch_step(const or_model *m, int K, const int32_t *env_type,
     double *seg1 = (double *)malloc(sizeof(double) * 6 * (size_t)L);
     or_hand_fk(m, u_prev, seg0);
     or_hand_fk(m, u, seg1);
+    geom_round(m, seg0, 6 * L);
+    geom_round(m, seg1, 6 * L);
 #pragma omp parallel for schedule(dynamic, 1)
     for (int i = 0; i < K; ++i) {
         or_contact local[OR_MAX_CMAX];
@@ -1072,6 +1140,8 @@ double or_window_cost(const or_model *m, int type, const double *st0, const doub
     for (int t = 0; t < T; ++t) {
         or_hand_fk(m, u_seq + (size_t)t * D, seg0);
         or_hand_fk(m, u_seq + (size_t)(t + 1) * D, seg1);
+        geom_round(m, seg0, 6 * L);
+        geom_round(m, seg1, 6 * L);
         int nc = or_env_step(m, seg0, seg1, type, st, pr, wkey, wr, cont, NULL);
         or_observe(m, nc, cont, obs);
         total += or_step_cost(m, obs, obs_gt + (size_t)t * L * 4);

@@ -61,6 +61,14 @@ typedef struct {
                                 * 1: Eq. 3 with contact-state, slip and spin terms, obs [L][7] */
     double tau_slip, tau_spin; /* slip thresholds: m/s, rad/s                    */
     double w_eq3[7];           /* w4 .. w10 of Eq. 3                             */
+    int32_t geom_f32;          /* diagnostic only (0 = off): round to float32 every
+                                * geometric quantity a float32 implementation holds
+                                * (hand segments, rotation, inverse inertia, free
+                                * velocity, sphere centres, contact gap, normal,
+                                * frame, point and link velocity), to measure how
+                                * far a step's result moves under such rounding;
+                                * 2: also move each rounded value one float32
+                                * step, up or down by a hash of its bits */
 } or_model;
 
 typedef struct {
@@ -82,7 +90,30 @@ typedef struct {
     double psi_final;          /* merit at the returned impulses                */
     double d_last_kept;        /* gap of the last contact kept by the cap       */
     double d_first_dropped;    /* gap of the first candidate the cap drops (+inf if none) */
+    /* Distances of the step's discrete decisions from their thresholds (the
+     * places where a rounding-level change of the inputs can change the
+     * result by more than rounding):
+     * armijo_margin: smallest |Psi(r + a dr) - (1 - 2 sigma a) Psi(r)| / Psi(r)
+     *   over the line-search trials whose outcome decides the step taken
+     *   (every trial evaluated except a = 1/8, which is taken either way)
+     *   and whose flip would move the impulses by more than ARMIJO_IMPACT of
+     *   the impulse scale max(m |g| dt, max |r|): a flip changes the step by
+     *   at least a/2 |dr|_inf; +inf if there is no such trial;
+     * tangent_tie: smallest difference between the two smallest |n_i| of a
+     *   kept sphere-link contact's normal (the tangent-axis rule; a table
+     *   contact's normal is exactly e_z); +inf without such contacts;
+     * margin_gap: smallest |d - margin| over all pairs (whether a pair is a
+     *   candidate at all). */
+    double armijo_margin;
+    double tangent_tie;
+    double margin_gap;
+    int32_t n_fallback;        /* iterations where no trial passed (a = 1/8)    */
+    int32_t reserved;
 } or_diag;
+
+/* Flips of an Armijo decision that move the impulses by less than this
+ * fraction of the impulse scale are not counted in armijo_margin. */
+#define OR_ARMIJO_IMPACT 1e-6
 
 /* Forward kinematics of the kinematic hand at joint vector u[D]:
  * seg[L][6] = segment endpoints a(3), b(3) in the world frame. */

@@ -35,8 +35,9 @@ ERROR_NAMES = {1: "PT_E_ARG", 2: "PT_E_HIP", 3: "PT_E_STATE", 4: "PT_E_CAPTURE",
 
 
 class PtError(RuntimeError):
-    def __init__(self, code, where):
-        msg = _lib.pt_last_error().decode(errors="replace")
+    def __init__(self, code, where, msg=None):
+        if msg is None:
+            msg = _lib.pt_last_error().decode(errors="replace")
         super().__init__(f"{where}: {ERROR_NAMES.get(code, code)}: {msg}")
         self.code = code
 
@@ -290,36 +291,75 @@ class Batch:
     def clear_warm(self):
         self.set_warm(np.full((self.K, self.C_max), -1, dtype=np.int32), np.zeros((self.K, self.C_max, 3)))
 
+    # -- argument checks (the C ABI takes raw device pointers and cannot see
+    #    a buffer's extent: a buffer shorter than the batch's sizes would be
+    #    read or written past its end) -----------------------------------
+    def _need(self, t, shape, name, dtype=torch.float32):
+        if t is None:
+            return
+        if not isinstance(t, torch.Tensor):
+            raise PtError(1, name, "expected a torch tensor")
+        if t.device != self.device and not (t.device.type == self.device.type and self.device.index is None):
+            raise PtError(1, name, f"on {t.device}, the batch is on {self.device}")
+        if t.dtype != dtype or tuple(t.shape) != tuple(shape) or not t.is_contiguous():
+            raise PtError(1, name, f"expected a contiguous {dtype} tensor of shape {tuple(shape)}, "
+                                   f"got {t.dtype} {tuple(t.shape)}{'' if t.is_contiguous() else ' (not contiguous)'}")
+
+    def _need_window(self, u_win, obs_gt_win):
+        self._need(u_win, (self.T + 1, self.D), "u_win")
+        self._need(obs_gt_win, (self.T, self.obs_rows, self.L, self.G), "obs_gt_win")
+
     # -- the hot path ------------------------------------------------------
     def new_obs(self, T=None):
         shape = (self.obs_rows, self.L, self.K) if T is None else (T, self.obs_rows, self.L, self.K)
         return torch.zeros(shape, dtype=torch.float32, device=self.device)
 
     def step(self, u_prev, u, stream=None):
+        self._need(u_prev, (self.D,), "u_prev")
+        self._need(u, (self.D,), "u")
         pt_step(self.handle, u_prev, u, stream)
 
     def observe(self, obs=None, stream=None):
         if obs is None:
             obs = self.new_obs()
+        self._need(obs, (self.obs_rows, self.L, self.K), "obs")
         pt_observe(self.handle, obs, stream)
         return obs
 
     def cost(self, obs, obs_gt, cost_sum, best=None, stream=None):
+        self._need(obs, (self.obs_rows, self.L, self.K), "obs")
+        self._need(obs_gt, (self.obs_rows, self.L, self.G), "obs_gt")
+        self._need(cost_sum, (self.K,), "cost_sum")
+        self._need(best, (self.G,), "best", torch.int32)
         pt_cost(self.handle, obs, obs_gt, cost_sum, best, stream)
 
     def resample(self, cost_sum, window_idx, parent=None, stream=None):
+        self._need(cost_sum, (self.K,), "cost_sum")
+        self._need(parent, (self.K,), "parent", torch.int32)
         pt_resample(self.handle, cost_sum, window_idx, parent, stream)
 
     def resample_wrs(self, cost_sum, n_steps, window_idx, lam, parent, weights=None, stream=None):
+        self._need(cost_sum, (self.K,), "cost_sum")
+        self._need(parent, (self.K,), "parent", torch.int32)
+        self._need(weights, (self.K,), "weights")
         pt_resample_wrs(self.handle, cost_sum, n_steps, window_idx, lam, parent, weights, stream)
 
     def resample_reps(self, cost_sum, n_steps, window_idx, eps, parent, weights=None, eta=None, stream=None):
+        self._need(cost_sum, (self.K,), "cost_sum")
+        self._need(parent, (self.K,), "parent", torch.int32)
+        self._need(weights, (self.K,), "weights")
+        self._need(eta, (self.G,), "eta")
         pt_resample_reps(self.handle, cost_sum, n_steps, window_idx, eps, parent, weights, eta, stream)
 
     def run_window(self, u_win, obs_gt_win, cost_sum, best=None, obs_out=None, graph=True, stream=None):
+        self._need_window(u_win, obs_gt_win)
+        self._need(cost_sum, (self.K,), "cost_sum")
+        self._need(best, (self.G,), "best", torch.int32)
+        self._need(obs_out, (self.T, self.obs_rows, self.L, self.K), "obs_out")
         pt_run_window(self.handle, u_win, obs_gt_win, cost_sum, best, obs_out, graph, stream)
 
     def autotune(self, u_win, obs_gt_win, stream=None):
+        self._need_window(u_win, obs_gt_win)
         return pt_autotune(self.handle, u_win, obs_gt_win, stream)
 
     def set_tuning(self, waves_per_workgroup):
@@ -337,6 +377,10 @@ class Batch:
 
     def window_grad(self, u_win, obs_gt_win, env, start, warm0, want_grad=True, want_end=False, stream=None):
         n = int(env.shape[0])
+        self._need_window(u_win, obs_gt_win)
+        self._need(env, (n,), "env", torch.int32)
+        self._need(start, (18, n), "start")
+        self._need(warm0, (n, self.C_max, 4), "warm0")
         dev = self.device
         cost = torch.empty(n, dtype=torch.float32, device=dev)
         grad = torch.empty((18, n), dtype=torch.float32, device=dev) if want_grad else None
@@ -354,6 +398,12 @@ class Batch:
 
     def refine_elites(self, u_win, obs_gt_win, cost_sum, start, steps=3, step=0.5, scale=None, best=None,
                       stream=None):
+        self._need_window(u_win, obs_gt_win)
+        self._need(cost_sum, (self.K,), "cost_sum")
+        self._need(start[0], (13, self.K), "start state")
+        self._need(start[1], (5, self.K), "start params")
+        self._need(start[2], (self.K, self.C_max, 4), "start warm")
+        self._need(best, (self.G,), "best", torch.int32)
         elites = torch.empty(self.elite_count(), dtype=torch.int32, device=self.device)
         pt_refine_elites(self.handle, u_win, obs_gt_win, cost_sum, start[0], start[1], start[2], steps, step, scale,
                          best, elites, stream)

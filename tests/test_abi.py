@@ -136,3 +136,28 @@ def test_weighted_resamplers_reject_bad_arguments(lib):
     f, g = pt._lib.pt_resample_wrs, pt._lib.pt_resample_reps
     assert f(None, None, 10, 0, C.c_float(1.0), None, None, None) == 1
     assert g(None, None, 10, 0, C.c_float(0.5), None, None, None, None) == 1
+
+
+def test_binding_checks_buffer_shapes_before_the_call():
+    # the binding rejects a buffer whose shape, type or layout does not match
+    # the batch (the C ABI receives only its address) before anything runs
+    import torch
+    from paper_2002_12160_amd import pt
+
+    b = pt.Batch.__new__(pt.Batch)
+    b.device = torch.device("cpu")
+    b.K, b.G, b.L, b.D, b.T, b.C_max, b.obs_rows = 8, 2, 3, 4, 10, 16, 4
+    ok_u = torch.zeros((11, 4))
+    ok_gt = torch.zeros((10, 4, 3, 2))
+    b._need_window(ok_u, ok_gt)
+    for bad_u, bad_gt in ((torch.zeros((2, 4)), ok_gt),                 # fewer command rows than T + 1
+                          (ok_u, torch.zeros((10, 4, 3, 1))),            # observed forces of too few groups
+                          (ok_u.double(), ok_gt),                        # wrong type
+                          (torch.zeros((4, 11)).t(), ok_gt)):           # not contiguous
+        with pytest.raises(pt.PtError):
+            b._need_window(bad_u, bad_gt)
+    with pytest.raises(pt.PtError):
+        b._need(torch.zeros(8, dtype=torch.float32), (8,), "best", torch.int32)
+    with pytest.raises(pt.PtError):
+        b._need(np.zeros(8, np.float32), (8,), "cost_sum")
+    b._need(None, (8,), "optional")

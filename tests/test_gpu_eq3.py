@@ -2,6 +2,7 @@
 step cost on identical observations, the per-step observation (force,
 slip direction, spin direction) on non-chaotic steps, and the batched
 window against the plain path bit for bit."""
+import collections
 import dataclasses
 import math
 
@@ -106,10 +107,11 @@ def _slip_and_spin(o, cont, seg0, seg1, omega, dt, eps):
 
 
 def test_eq3_observation_matches_oracle(pt):
-    # per step, from the oracle's float32-rounded state: force rows to the
-    # usual tolerance; the slip and spin states equal wherever the oracle's
-    # slip speed / spin is clear of its threshold, the slip direction within
-    # 2e-3 (or the speed's relative error) when both slip
+    # per step, from the oracle's float32-rounded state, on the clear steps
+    # (tests/parity_util.py): force rows to the usual tolerance; the slip and
+    # spin states equal wherever the oracle's slip speed / spin is clear of
+    # its threshold, the slip direction within 2e-3 (or the speed's relative
+    # error) when both slip
     _say("Eq. 3 observation parity: small config, K=32, 40 steps")
     cfg = _eq3(S.CONFIGS["small"]).with_(T=10 ** 6)
     c = cfg.consts
@@ -118,26 +120,24 @@ def test_eq3_observation_matches_oracle(pt):
     sc = dataclasses.replace(S.round_to_f32(sc0), state=sc0.state, params=sc0.params)
     tr = oracle.Tracker(sc)
     o = tr.o
-    b = pt.Batch.from_scene(sc)
+    probes = PU.Probes(o)
+    b = pt.Batch.from_scene(sc, T=10)
     n_ok = n_slip = n_spin = 0
     fails = []
+    reasons = collections.Counter()
     for t in range(steps):
         u_prev, u = sc.u[max(t - 1, 0)], sc.u[t]
         st64, pr64, wk, wr64 = tr.state.copy(), tr.params.copy(), tr.wkey.copy(), tr.wr.copy()
-        a_st, a_pr, a_k, a_r = st64.copy(), pr64.copy(), wk.copy(), wr64.copy()
-        o.batch_step(sc.env_type, u_prev, u, a_st, a_pr, a_k, a_r)
-        b_st, b_pr, b_k, b_r = PU.f32(st64), PU.f32(pr64), wk.copy(), PU.f32(wr64)
-        b_obs, b_cont, b_dg = o.batch_step(sc.env_type, u_prev, u, b_st, b_pr, b_k, b_r, want_contacts=True,
-                                           want_diag=True)
-        nonchaotic = (PU.rel_err(a_st, b_st).max(axis=1) < PU.CHAOS_TOL) & \
-            np.array([x == y for x, y in zip(PU.key_sets(a_k), PU.key_sets(b_k))])
+        ref = probes.step(sc.env_type, u_prev, u, st64, pr64, wk, wr64, want_contacts=True)
+        reasons.update(ref["reason"])
+        b_obs, b_cont, b_st = ref["obs"], ref["cont"], ref["st"]
         b.set_state(PU.f32(st64), PU.f32(pr64))
         b.set_warm(wk, PU.f32(wr64))
         b.step(_u(u_prev), _u(u))
         g = PU.obs_from_gpu(b.observe())                       # [K][L][7]
         seg0, seg1 = o.hand_fk(u_prev), o.hand_fk(u)
-        force_ok = PU.obs_close(g[..., :4], b_obs[..., :4], c.tau_contact)
-        for j in np.nonzero(nonchaotic)[0]:
+        force_ok = PU.obs_close(g[..., :4], b_obs[..., :4], ref["pr"][:, 0], c.tau_contact)
+        for j in np.nonzero(ref["clear"])[0]:
             n_ok += 1
             speed, spin = _slip_and_spin(o, b_cont[j], seg0, seg1, b_st[j, 10:13], c.dt, c.compliance)
             ok = bool(force_ok[j])
@@ -153,14 +153,14 @@ def test_eq3_observation_matches_oracle(pt):
                     ok &= g[j, l, 6] == b_obs[j, l, 6]
                     n_spin += int(b_obs[j, l, 6] != 0)
             if not ok:
-                fails.append((t, int(j)))
+                fails.append((t, int(j), PU.describe(ref, j)))
         tr.step()
     b.close()
-    _say(f"{n_ok} non-chaotic env-steps, {n_slip} slipping and {n_spin} spinning sensor-steps compared, "
-         f"{len(fails)} outside: {fails[:10]}")
-    assert n_ok >= 0.5 * K * steps
+    _say(f"{n_ok} clear env-steps ({dict(reasons)}), {n_slip} slipping and {n_spin} spinning sensor-steps "
+         f"compared, {len(fails)} outside: {fails[:10]}")
+    assert n_ok >= 0.4 * K * steps
     assert n_slip > 0 and n_spin > 0
-    assert len(fails) <= 0.01 * n_ok, fails[:20]
+    assert not fails, fails[:20]
 
 
 def test_eq3_batched_equals_plain_bitwise(pt):

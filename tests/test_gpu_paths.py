@@ -128,6 +128,42 @@ def test_batched_equals_plain_bitwise(pt, cfg_name, K, prec):
         _assert_same(ref, got, f"graph={graph}")
 
 
+def test_deep_work_queue_bitwise_and_oracle(pt):
+    # 65536 simulations (4 groups of 16384): far more than the chip holds at
+    # once (at most 32 wavefronts per compute unit), so every wavefront of
+    # the persistent kernel takes several simulations from the work queue
+    # one after another, reusing its LDS and registers.  Bit for bit equal
+    # to the plain path over two windows with resampling (graph and no
+    # graph), and the first window of 64 sampled simulations against the
+    # oracle on the clear ones.
+    cfg = S.CONFIGS["small"].with_(group_types=(0, 0, 0, 0))
+    K, T = 65536, cfg.T
+    _say(f"deep work queue: small scene, K={K}, 2 windows")
+    sc = S.round_to_f32(S.make_scene(cfg, K=K, steps=2 * T))
+    ref = run_plain(pt, sc, 2, T)
+    for graph in (False, True):
+        got = run_batched(pt, sc, 2, T, graph=graph)
+        _assert_same(ref, got, f"K={K} graph={graph}")
+        del got
+    # the sampled simulations' first window against the oracle
+    idx = np.linspace(0, K - 1, 64).astype(int)
+    o = oracle.Oracle.from_scene(sc)
+    probes = PU.Probes(o)
+    wk, wr = o.new_warm(len(idx))
+    u_rows = [sc.u[0]] + [sc.u[t] for t in range(T)]
+    seg = PU.segment_reference(probes, sc.env_type[idx], u_rows, sc.state[idx], sc.params[idx], wk, wr)
+    g_obs = ref["obs"][:T].cpu().numpy()[:, :, :, idx].transpose(0, 3, 2, 1).astype(np.float64)  # [T][n][L][4]
+    n_ok = 0
+    for j in np.nonzero(seg["clear"])[0]:
+        n_ok += 1
+        for t in range(T):
+            assert PU.obs_close(g_obs[t, j:j + 1], seg["obs"][t, j:j + 1], seg["pr"][j:j + 1, 0],
+                                cfg.consts.tau_contact)[0], (t, idx[j])
+    _say(f"{n_ok} of {len(idx)} sampled windows clear; their observations match the oracle at every step")
+    assert n_ok >= 4
+    del ref
+
+
 @pytest.mark.parametrize("prec,choices", [(64, (1, 2, 4)), (32, (1, 2, 4, 8))])
 def test_autotune_choices_agree_bitwise(pt, prec, choices):
     _say(f"every environments-per-workgroup choice gives the same bits (solve precision {prec})")

@@ -644,3 +644,268 @@ def test_window_cost_matches_stepping():
             tot[i] += o.step_cost(obs[i], gts[t])
     for i in range(4):
         assert o.window_cost(0, sc.state[i], sc.params[i], u_seq, gts) == tot[i]
+
+
+# -------------------------------------------------------------------------
+# orientation update (world-frame exponential, applied on the left)
+# -------------------------------------------------------------------------
+
+def _rot(axis, th):
+    """Rotation matrix about a coordinate axis (0, 1, 2) by th."""
+    c, s = math.cos(th), math.sin(th)
+    if axis == 0:
+        return np.array([[1, 0, 0], [0, c, -s], [0, s, c]])
+    if axis == 1:
+        return np.array([[c, 0, s], [0, 1, 0], [-s, 0, c]])
+    return np.array([[c, -s, 0], [s, c, 0], [0, 0, 1]])
+
+
+def _quat_to_R(q):
+    w, x, y, z = q / np.linalg.norm(q)
+    return np.array([[1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)],
+                     [2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)],
+                     [2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)]])
+
+
+def _rodrigues(axis, th):
+    k = np.asarray(axis, dtype=np.float64) / np.linalg.norm(axis)
+    Kx = np.array([[0, -k[2], k[1]], [k[2], 0, -k[0]], [-k[1], k[0], 0]])
+    return np.eye(3) + math.sin(th) * Kx + (1 - math.cos(th)) * Kx @ Kx
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_torque_free_spin_about_a_principal_axis_of_a_rotated_body(axis):
+    # A body with three distinct principal inertias, turned away from the
+    # world axes by q0, spins about its principal axis R0 e_axis with no
+    # contact: the spin is steady, omega stays the same world vector, and
+    # after n steps R_n = Rot(R0 e_axis, n dt |omega|) R0 (a rotation about a
+    # world axis composed on the left).  A body-frame update would turn about
+    # R0^T applied to omega instead and leave this closed form.
+    inv = (1 / 3e-4, 1 / 7e-4, 1 / 9e-4)
+    sph, nsph, invv = tiny.single_sphere(0.01, inv_inertia=inv)
+    o = _oracle([tiny.far_link()], sph, nsph, invv, gravity=(0.0, 0.0, 0.0))
+    dt = o.consts.dt
+    q0 = np.array([0.8, 0.3, -0.4, 0.33])
+    q0 /= np.linalg.norm(q0)
+    R0 = _quat_to_R(q0)
+    spin = 4.0
+    w = spin * R0[:, axis]
+    st = tiny.state(x=(0, 0, 20.0), q=q0, w=w)
+    pr = tiny.params(0.12, 0.5)
+    hist = _run(o, st, pr, 25)
+    for n, (s, cont, dg) in enumerate(hist, start=1):
+        np.testing.assert_allclose(s[10:13], w, rtol=0, atol=1e-12)
+        Rn = _rodrigues(R0[:, axis], n * dt * spin) @ R0
+        np.testing.assert_allclose(_quat_to_R(s[3:7]), Rn, rtol=0, atol=1e-12)
+    # the body-frame reading differs visibly here
+    R_body = R0 @ _rodrigues(w, 25 * dt * spin)
+    assert np.abs(R_body - _quat_to_R(hist[-1][0][3:7])).max() > 0.1
+
+
+# -------------------------------------------------------------------------
+# kinematics: two joints on one link, offset rotations, a child link
+# -------------------------------------------------------------------------
+
+def test_fk_two_joints_and_offsets_closed_form():
+    # link 0: origin o0, offset rotation Rz(yaw0), joint 0 about its local z
+    # by a, then joint 1 about its (once turned) local y by b -- the
+    # abduction-then-flexion order of the generated hands; link 1 hangs off
+    # link 0's tip, moved by p1 in link 0's tip frame and turned by Rx(roll1),
+    # with one joint about its local y by c; link 2 is a fixed palm capsule
+    # (offset rotation only).  Frames compose as parent tip frame x offset x
+    # joint0 x joint1, so R0 = Rz(yaw0) Rz(a) Ry(b): swapping the joints
+    # gives Rz(yaw0) Ry(b) Rz(a), which moves the tip.
+    yaw0, roll1, yaw2 = 0.7, -0.4, 2.1
+    o0, p1, o2 = np.array([0.01, -0.02, 0.1]), np.array([0.004, 0.003, -0.002]), np.array([-0.03, 0.02, 0.09])
+    len0, len1, len2 = 0.04, 0.035, 0.05
+    rows = []
+    r0 = np.zeros(20)
+    r0[0], r0[1], r0[2] = -1, 0, 1
+    r0[3:6], r0[6:9] = (0, 0, 1), (0, 1, 0)
+    r0[9:12] = o0
+    r0[12:16] = (math.cos(yaw0 / 2), 0, 0, math.sin(yaw0 / 2))
+    r0[16], r0[17] = len0, 0.008
+    rows.append(r0)
+    r1 = np.zeros(20)
+    r1[0], r1[1], r1[2] = 0, 2, -1
+    r1[3:6] = (0, 1, 0)
+    r1[9:12] = p1
+    r1[12:16] = (math.cos(roll1 / 2), math.sin(roll1 / 2), 0, 0)
+    r1[16], r1[17] = len1, 0.008
+    rows.append(r1)
+    r2 = np.zeros(20)
+    r2[0], r2[1], r2[2] = -1, -1, -1
+    r2[9:12] = o2
+    r2[12:16] = (math.cos(yaw2 / 2), 0, 0, math.sin(yaw2 / 2))
+    r2[16], r2[17] = len2, 0.008
+    rows.append(r2)
+    sph, nsph, inv = tiny.single_sphere(0.01)
+    o = oracle.Oracle(np.array(rows), sph, nsph, inv, tiny.consts(), C_max=2, newton_iters=1, D=3)
+    ex = np.array([1.0, 0.0, 0.0])
+    rng = np.random.default_rng(21)
+    for _ in range(6):
+        a, b, c = rng.uniform(-1.2, 1.2, size=3)
+        seg = o.hand_fk(np.array([a, b, c]))
+        Rl0 = _rot(2, yaw0) @ _rot(2, a) @ _rot(1, b)
+        tip0 = o0 + len0 * Rl0 @ ex
+        np.testing.assert_allclose(seg[0, :3], o0, atol=1e-15)
+        np.testing.assert_allclose(seg[0, 3:], tip0, atol=1e-15)
+        base1 = tip0 + Rl0 @ p1
+        Rl1 = Rl0 @ _rot(0, roll1) @ _rot(1, c)
+        np.testing.assert_allclose(seg[1, :3], base1, atol=1e-15)
+        np.testing.assert_allclose(seg[1, 3:], base1 + len1 * Rl1 @ ex, atol=1e-15)
+        np.testing.assert_allclose(seg[2, :3], o2, atol=1e-15)
+        np.testing.assert_allclose(seg[2, 3:], o2 + len2 * _rot(2, yaw2) @ ex, atol=1e-15)
+        swapped = o0 + len0 * _rot(2, yaw0) @ _rot(1, b) @ _rot(2, a) @ ex
+        assert np.abs(swapped - seg[0, 3:]).max() > 1e-4
+
+
+# -------------------------------------------------------------------------
+# the fixed-N Newton iteration and its Armijo schedule
+# -------------------------------------------------------------------------
+
+def _fb_spectral(x, y, delta):
+    """Smoothed Fischer-Burmeister function of the second-order cone in R^3,
+    from the spectral decomposition of the Jordan algebra: with
+    z = x o x + y o y + 2 delta^2 e (a o a = (|a|^2, 2 a0 abar)),
+    z = l1 c1 + l2 c2, l = z0 -/+ |zbar|, c = (1, -/+ zbar/|zbar|)/2 and
+    sqrt(z) = sqrt(l1) c1 + sqrt(l2) c2; Phi = x + y - sqrt(z).  Written
+    with sums of squares and principal square roots only, so that it also
+    evaluates at complex arguments (for complex-step derivatives)."""
+    z0 = np.sum(x * x) + np.sum(y * y) + 2 * delta * delta
+    zb = 2 * (x[0] * x[1:] + y[0] * y[1:])
+    nz = np.sqrt(np.sum(zb * zb))
+    d = zb / nz if nz.real > 0 else np.array([1.0, 0.0])
+    c1 = 0.5 * np.concatenate([[1.0], -d])
+    c2 = 0.5 * np.concatenate([[1.0], d])
+    root = np.sqrt(z0 - nz) * c1 + np.sqrt(z0 + nz) * c2
+    return x + y - root
+
+
+def _phi_all(r, W, uf, mu, c):
+    """Phi of every contact at impulses r (3C): x = kappa (mu r_n, r_t),
+    y = (u_n + mu sqrt(|u_t|^2 + delta^2), mu u_t), u = W r + uf."""
+    u = W @ r + uf
+    out = []
+    for k in range(len(r) // 3):
+        rk, uk = r[3 * k:3 * k + 3], u[3 * k:3 * k + 3]
+        x = c.kappa * np.array([mu * rk[0], rk[1], rk[2]])
+        y = np.array([uk[0] + mu * np.sqrt(uk[1] * uk[1] + uk[2] * uk[2] + c.fb_delta ** 2), mu * uk[1], mu * uk[2]])
+        out.append(_fb_spectral(x, y, c.fb_delta))
+    return np.concatenate(out)
+
+
+def _newton_replay(r, W, uf, mu, c, N):
+    """N iterations of Newton on Phi(r) = 0 with the Jacobian by complex-step
+    differentiation (Im Phi(r + i h e_j) / h), each followed by the Armijo
+    rule: the first a of 1, 1/2, 1/4, 1/8 with Psi(r + a dr) <=
+    (1 - 2 sigma a) Psi(r), Psi = |Phi|^2/2, else 1/8.  Returns the
+    iterates, the chosen step sizes, the smallest relative distance of a
+    trial from its bound and the smallest merit met (below ~1e-18 the trials
+    compare round-off, not the rule)."""
+    alphas, margin, psi_min = [], np.inf, np.inf
+    for _ in range(N):
+        phi = _phi_all(r, W, uf, mu, c)
+        psi = 0.5 * phi @ phi
+        psi_min = min(psi_min, psi)
+        n = len(r)
+        A = np.zeros((n, n))
+        for j in range(n):
+            rc = r.astype(np.complex128)
+            rc[j] += 1e-30j
+            A[:, j] = _phi_all(rc, W, uf, mu, c).imag / 1e-30
+        dr = np.linalg.solve(A, -phi)
+        chosen = 0.125
+        for a in (1.0, 0.5, 0.25, 0.125):
+            pt = 0.5 * np.sum(_phi_all(r + a * dr, W, uf, mu, c) ** 2)
+            bound = (1 - 2 * c.armijo_sigma * a) * psi
+            margin = min(margin, abs(pt - bound) / psi)
+            if pt <= bound:
+                chosen = a
+                break
+        alphas.append(chosen)
+        r = r + chosen * dr
+    return r, alphas, margin, psi_min
+
+
+def _replay_case(o, seg0, seg1, typ, st, pr, wkey, wr, N):
+    """Oracle step with N fixed iterations against the replay from the same
+    contact system and warm start.  Returns the replay's step sizes, or None
+    when a trial lies too close to its bound (or the merit at round-off) for
+    the replay's finite differences to decide it."""
+    cont, W, uf = o.env_system(seg0, seg1, typ, st, pr)
+    C = len(cont)
+    if C == 0:
+        return None
+    r0 = np.zeros((C, 3))
+    for k, key in enumerate(cont["key"]):
+        hit = np.nonzero(wkey == key)[0]
+        if len(hit):
+            r0[k] = wr[hit[0]]
+    r_rep, alphas, margin, psi_min = _newton_replay(r0.reshape(-1).copy(), W, uf, pr[1], o.consts, N)
+    if margin < 1e-9 or psi_min < 1e-24:
+        return None
+    got, dg = o.env_step(seg0, seg1, typ, st.copy(), pr.copy(), wkey.copy(), wr.copy())
+    r_or = np.concatenate([g["r"] for g in got])
+    np.testing.assert_allclose(r_or, r_rep, rtol=0, atol=1e-8 * max(np.abs(r_rep).max(), 1e-4))
+    assert dg["iters"] == N
+    assert dg["n_full_steps"] == sum(a == 1.0 for a in alphas)
+    assert dg["n_fallback"] <= sum(a == 0.125 for a in alphas)
+    return alphas
+
+
+def test_fixed_n_newton_and_armijo_schedule():
+    # The oracle's impulses after N fixed iterations equal an independent
+    # replay (spectral FB function, finite-difference Newton matrix, the
+    # Armijo rule written out), on (a) one or two spheres of a body touching
+    # the table with random velocities and warm starts (Armijo parameter
+    # 1e-4, and 0.3 where the bound's sign decides many trials), and (b) steps of the
+    # small tracking scene (hand contacts squeezing the object), for N = 1 to
+    # 4.  The cases cover a full step (a = 1), a rejected full step with
+    # a = 1/2 or 1/4 accepted, and the fallback a = 1/8 when no trial passes.
+    rng = np.random.default_rng(17)
+    seen = []
+    for trial in range(120):
+        rho = 0.01
+        two = trial % 2 == 1
+        offs = np.array([[0.0, 0.0, 0.0], [0.03, 0.0, 0.0]]) if two else np.zeros((1, 3))
+        sph = np.zeros((1, len(offs), 4))
+        sph[0, :, :3] = offs - offs.mean(axis=0)
+        sph[0, :, 3] = rho
+        inv = 1.0 / rng.uniform(2e-4, 9e-4, size=3)
+        N = 1 if trial % 4 < 2 else 3
+        # sigma = 0.3 on every other pair of cases: the same rule with a
+        # sufficient-decrease band wide enough that its sign decides trials
+        sigma = 0.3 if trial % 8 >= 4 else 1e-4
+        o = oracle.Oracle(np.array([tiny.far_link()]), sph, np.array([len(offs)], np.int32), inv[None],
+                          tiny.consts(armijo_sigma=sigma), C_max=4, newton_iters=N, D=1)
+        st = tiny.state(x=(0, 0, rho + rng.uniform(-0.001, 0.0005)), v=rng.normal(scale=0.3, size=3),
+                        w=rng.normal(scale=2.0, size=3))
+        pr = tiny.params(rng.uniform(0.05, 0.3), rng.uniform(0.2, 1.2))
+        seg = o.hand_fk(np.zeros(1))
+        cont, _, _ = o.env_system(seg, seg, 0, st, pr)
+        wkey, wr = o.new_warm(1)
+        C = len(cont)
+        wkey[0, :C] = cont["key"]
+        wr[0, :C] = rng.normal(scale=0.01, size=(C, 3)) * (rng.uniform() < 0.8)
+        a = _replay_case(o, seg, seg, 0, st, pr, wkey[0], wr[0], N)
+        if a is not None:
+            seen.append(a)
+    n_table = len(seen)
+    cfg = S.CONFIGS["small"].with_(T=10 ** 6)
+    sc = S.make_scene(cfg, K=4, steps=16)
+    tr = oracle.Tracker(sc)
+    for t in range(16):
+        if t >= 4:
+            seg0, seg1 = tr.o.hand_fk(sc.u[t - 1]), tr.o.hand_fk(sc.u[t])
+            for i in range(sc.K):
+                for N in (1, 2, 4):
+                    o = oracle.Oracle.from_scene(sc, newton_iters=N)
+                    a = _replay_case(o, seg0, seg1, sc.env_type[i], tr.state[i], tr.params[i], tr.wkey[i],
+                                     tr.wr[i], N)
+                    if a is not None:
+                        seen.append(a)
+        tr.step()
+    flat = [x for a in seen for x in a]
+    assert n_table >= 80 and len(seen) - n_table >= 60
+    assert {1.0, 0.5, 0.125} <= set(flat), set(flat)
