@@ -1,89 +1,98 @@
 """Benchmark of the data-parallel hot path of sample-based in-hand pose
 tracking on one MI355X.
 
-A "step" is one world step of the whole population with the observation and
-the cost (Alg. 1: step every simulation with the same command, observe, add
-the step cost against the observed contact forces, update the argmin), plus
-the population-based resampling every T steps.  The observed forces are the
-tracker's input (the robot's contact sensors); here they come from a
-separate batch holding the unperturbed ("real") simulation stepped with the
-same commands, run before the timed region so that, like every other input,
-they are resident in HBM when timing starts.  Inputs are seeded and synthetic (the paper's YCB objects
-and teleoperation trajectories are not available): a 4-finger + palm capsule
-hand on sinusoidal joint commands and a 64-sphere ellipsoid on a table.
+A "step" is one world step of the whole population with its observation
+and cost (Alg. 1: step every simulation with the same command, observe, add
+the step cost against the observed contact forces, update the argmin); the
+optimiser runs every T = 10 steps.  The observed forces are the tracker's
+input (the robot's contact sensors); here they come from a separate batch
+holding the unperturbed ("real") simulation of each group stepped with the
+same commands, run before any timed region so that, like every other input,
+they are resident in HBM when timing starts.  Inputs are seeded and
+synthetic (the paper's YCB objects, teleoperation trajectories and hand are
+not available).
 
-Default workload: 256 simulations, 300 steps at 30 Hz, plain per-step
-launches (the "plain256" scene).  The same run also times the batched path
-(one persistent kernel per 10-step window, replayed from a HIP graph) and
-the batched path with elite refinement (three gradient steps of the window
-cost for the elites before every resampling) on the same workload, and both
-batched variants on the 1024-simulation differentiation workload
-("adjoint1024").  Prints one JSON line.
+Headline (`value`): the real-time workload -- 16384 simulations in 16
+groups, each group tracking one seeded 128-sphere superquadric held by a
+5-finger, 20-link capsule hand, 64-contact cap, 10 Newton iterations -- on
+the batched path with adjoint elite refinement: every 10-step window is one
+persistent kernel replayed from a captured HIP graph, then the elites of
+each group take three gradient steps of their window cost, then the
+population-based optimiser resamples.  Timed over the workload's 1800 steps
+(60 s at 30 Hz) five times from the same start; `value` is the median.
+The same workload also runs the plain per-step launch path and the batched
+path without refinement; the other workloads (16, 256, 1024 and 4096
+simulations) run the paths their definitions name.  Prints one JSON line.
 """
 from __future__ import annotations
 
 import argparse
+import ctypes
 import dataclasses
+import hashlib
 import json
-import math
 import os
+import platform
 import sys
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+METRIC = "env-steps/sec (step+observe+cost) plain vs batched vs +adjoint, 30Hz budget met"
+RUNS = 5
+MIN_WINDOWS = 10
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=300, help="timed world steps")
-    ap.add_argument("--warmup", type=int, default=30, help="untimed world steps first")
-    ap.add_argument("--config", default="plain256")
+    ap.add_argument("--steps", type=int, default=1800,
+                    help="timed world steps per run of the headline workload (at least 10 windows are timed)")
+    ap.add_argument("--warmup", type=int, default=20, help="untimed world steps before each run")
+    ap.add_argument("--runs", type=int, default=RUNS, help="timed runs per leg; the median is reported")
     ap.add_argument("--solve-precision", type=int, default=64, choices=[32, 64])
-    ap.add_argument("--no-batched", action="store_true")
-    ap.add_argument("--no-adjoint", action="store_true", help="skip the batched + elite-refinement legs")
-    ap.add_argument("--realtime-windows", type=int, default=180,
-                    help="timed windows of the 16384-simulation real-time workload: 180 x 10 steps is the "
-                         "workload's 60 s at 30 Hz (0 skips it)")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-workloads", action="store_true", help="skip the 16/256/1024/4096-simulation workloads")
     ap.add_argument("--no-optimizers", action="store_true",
-                    help="skip the WRS / REPS / identity comparison on the real-time workload")
-    ap.add_argument("--cpu-sample-steps", type=int, default=300)
-    ap.add_argument("--profile", action="store_true", help="short run for the profiler (no CPU baseline)")
+                    help="skip the WRS / REPS / identity / full-Eq. 3 comparison on the real-time workload")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-steps", type=int, default=30)
+    ap.add_argument("--profile", action="store_true",
+                    help="short run for the profiler: the headline workload's batched + refinement path only")
     ap.add_argument("--copy-calibration", action="store_true",
-                    help="only copy 256 MiB on the device three times (reference for the FETCH_SIZE / WRITE_SIZE "
-                         "counters)")
+                    help="only copy 256 MiB on the device three times with the ceiling library's copy kernel "
+                         "(reference for the FETCH_SIZE / WRITE_SIZE counters)")
     return ap.parse_args()
 
 
-# HBM bytes per k_step launch of the 256-simulation workload (float64 solve),
-# from FETCH_SIZE / WRITE_SIZE counters scaled by a plain device copy of known
-# size (profiles/k_step_plain256.txt); None where the kernel changed since
-# the counters were taken, and for any other configuration
-MEASURED_TRAFFIC = {("plain256", 64): 1032426}
-
-# VALU counters per k_step launch of the same workload (profiles/
-# k_step_plain256.txt): SQ_INSTS_VALU, SQ_ACTIVE_INST_VALU (quad-cycles) and
-# SQ_THREAD_CYCLES_VALU summed over the chip; the same staleness rule
-MEASURED_VALU = {("plain256", 64): (4030907, 4181518, 233401129)}
+# --------------------------------------------------------------------------
+# counters from the profiler (profiles/k_window_realtime16384.txt): HBM bytes
+# per launch of the headline workload's window kernel (FETCH_SIZE and
+# WRITE_SIZE scaled by a plain device copy of known size) and its VALU
+# counters.  Keyed by a hash of the kernel's sources: a figure taken before
+# the kernel last changed is reported as null.
+# --------------------------------------------------------------------------
+KERNEL_SOURCES = ("pt_kernels.hip", "pt_step.hpp", "pt_device.hpp", "pt_io.hpp", "pt_internal.h")
+MEASURED = {
+    # "src": sha256 (first 16 hex digits) of KERNEL_SOURCES, in order
+    "k_window_realtime16384": None,
+}
 SIMDS, CLOCK_HZ = 1024, 2.4e9     # MI355X: 256 CUs x 4 SIMDs at 2.4 GHz; a VALU instruction issues in 4 cycles
+PEAK_F64_TFLOPS = 78.6            # MI355X published float64 vector peak (= non-packed float32)
+PEAK_HBM_GBPS = 8000.0
 
 
-def valu_figures(key, launch_s, waves):
-    """VALU issue and busy fractions of the chip's peak over one launch of
-    launch_s seconds, the active-lane fraction, from MEASURED_VALU; with one
-    wavefront per simulation a launch of `waves` wavefronts occupies at most
-    waves / SIMDS of the SIMDs (its ceiling)."""
-    m = MEASURED_VALU.get(key)
-    if m is None:
-        return None
-    insts, active_q, thread_cyc = m
-    slots = SIMDS * CLOCK_HZ * launch_s
-    return {"issue_frac": round(insts * 4 / slots, 4), "busy_frac": round(active_q * 4 / slots, 4),
-            "lane_frac": round(thread_cyc / (active_q * 64), 3), "insts_per_launch": insts,
-            "ceiling": round(min(1.0, waves / SIMDS), 4)}
+def kernel_src_sha():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2002_12160_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured(key):
+    m = MEASURED.get(key)
+    return m if m is not None and m.get("src") == kernel_src_sha() else None
 
 
 # algorithmic floating-point operations (an FMA counts 2; a square root,
@@ -103,23 +112,33 @@ def algorithmic_flops(S, L, N, env_steps, contacts):
     return env_steps * per_env + contacts * (FLOP_CONTACT + N * FLOP_CONTACT_ITER)
 
 
-# algorithmic HBM bytes of the plain step kernel per environment-step: state
-# (13 floats) and parameters (5) read, state and the consumed perturbation
-# force written, the warm-start cache read and written and the contact buffer
-# written (C_max x 16 B each); hand segments and sphere tables are shared by
-# every simulation and stay in cache
-def algorithmic_bytes(C_max):
-    return 52 + 20 + 52 + 12 + 3 * 16 * C_max
+def window_bytes(C_max, T, L, obs=False):
+    """Algorithmic HBM bytes of the window kernel per environment-step: the
+    state (13 floats), parameters (5) and warm-start cache (C_max x 16 B)
+    read once and written once per window, the observed forces of the group
+    (shared, cache resident) and the cost read and written once; with obs,
+    the observation rows written every step."""
+    return (2 * (13 + 5) * 4 + 2 * 16 * C_max + 8) / T + (16 * L if obs else 0)
 
+
+def median_run(runs):
+    """The run with the median value (odd counts) and the list of values."""
+    vals = sorted(r["value"] for r in runs)
+    mid = vals[len(vals) // 2]
+    pick = next(r for r in runs if r["value"] == mid)
+    return dict(pick, runs=[round(r["value"], 1) for r in runs])
+
+
+# --------------------------------------------------------------------------
+# inputs
+# --------------------------------------------------------------------------
 
 def observed_forces(pt, sc, dev, solve_precision, n_steps, pose_every=None):
     """The observed ("real") simulation's sensor forces for steps
     0..n_steps-1, [n_steps][R][L][G] (R = 4, or 7 under the full cost of
-    Eq. 3).  They are the tracker's input stream
-    (the robot's contact sensors), so they are produced before any timed
-    region and stay resident in HBM.  With pose_every = T also the observed
-    object's state after every T steps ([n_steps / T][13][G], for the
-    tracking error)."""
+    Eq. 3): the tracker's input stream, produced before any timed region and
+    resident in HBM.  With pose_every = T also the observed object's state
+    after every T steps ([n_steps / T][13][G], for the tracking error)."""
     import torch
     u_all = torch.as_tensor(sc.u.astype("float32"), device=dev)
     h = pt.Batch.from_scene(sc, hidden=True, solve_precision=solve_precision)
@@ -135,73 +154,20 @@ def observed_forces(pt, sc, dev, solve_precision, n_steps, pose_every=None):
     return (out, torch.stack(poses)) if pose_every else out
 
 
-def batched_run(pt, S, sc, dev, solve_precision, n_win, n_warm, adjoint):
-    """Windows of the batched path: each window's commands and observed
-    forces are copied into the two buffers a captured HIP graph reads, the
-    population's window is one persistent kernel replayed from that graph,
-    then (adjoint) the elites are refined by three gradient steps of the
-    window cost from their window start, then the resampler runs."""
+def make_setup(pt, S, dev, solve_precision, cfg, n_windows):
+    """Scene, observed forces, observed poses and commands for n_windows
+    windows of a workload (plus one window of slack)."""
     import torch
-    cfg = sc.cfg
-    K, G, L, T = sc.K, sc.G, sc.L, cfg.T
-    n_total = n_warm + n_win + (1 if adjoint else 0)
-    gts = observed_forces(pt, sc, dev, solve_precision, n_total * T)
+    T = cfg.T
+    sc = S.make_scene(cfg, steps=(n_windows + 1) * T + 1)
+    gts, hposes = observed_forces(pt, sc, dev, solve_precision, n_windows * T, pose_every=T)
     u_all = torch.as_tensor(sc.u.astype("float32"), device=dev)
-    main_b = pt.Batch.from_scene(sc, solve_precision=solve_precision, window_checkpoints=adjoint)
-    u_win = torch.empty((T + 1, sc.D), device=dev)
-    gt_win = torch.empty((T, main_b.obs_rows, L, G), device=dev)
-    cost = torch.zeros(K, device=dev)
-    best = torch.zeros(G, dtype=torch.int32, device=dev)
-    parent = torch.zeros(K, dtype=torch.int32, device=dev)
-    snap = main_b.snapshot()
-    improved = [0, 0]
-
-    def window(w, count=False):
-        t0_ = w * T
-        u_win.copy_(u_all[t0_ - 1: t0_ + T] if t0_ > 0 else torch.cat([u_all[:1], u_all[:T]], 0))
-        gt_win.copy_(gts[t0_: t0_ + T])
-        if adjoint:
-            snap[0].copy_(main_b.state)
-            snap[1].copy_(main_b.params)
-            snap[2].copy_(main_b.warm)
-        main_b.run_window(u_win, gt_win, cost, best, None, graph=True)
-        if adjoint:
-            c0 = cost.clone() if count else None
-            elites = main_b.refine_elites(u_win, gt_win, cost, snap, steps=3, step=0.5, best=best)
-            if count:
-                e = elites.long()
-                improved[0] += int((cost[e] < c0[e]).sum())
-                improved[1] += int(e.numel())
-        main_b.resample(cost, w, parent)
-
-    u_win.copy_(torch.cat([u_all[:1], u_all[:T]], 0))
-    gt_win.copy_(gts[:T])
-    tuned = main_b.autotune(u_win, gt_win)
-    torch.cuda.synchronize()
-    for w in range(n_warm):
-        window(w)
-    torch.cuda.synchronize()
-    tb0 = time.perf_counter()
-    for w in range(n_warm, n_warm + n_win):
-        window(w)
-    torch.cuda.synchronize()
-    bwall = time.perf_counter() - tb0
-    out = {"value": round(K * T * n_win / bwall, 1), "unit": "env-steps/s", "windows": n_win,
-           "windows_per_s": round(n_win / bwall, 2), "ms_per_step": round(bwall / (n_win * T) * 1e3, 4),
-           "waves_per_workgroup": tuned}
-    if adjoint:
-        # one more window, untimed, to count the elites the refinement improved
-        window(n_warm + n_win, count=True)
-        torch.cuda.synchronize()
-        out.update({"elites": main_b.elite_count(), "refine_steps": 3,
-                    "elites_improved_frac": round(improved[0] / max(improved[1], 1), 3)})
-    main_b.close()
-    return out
+    return {"cfg": cfg, "sc": sc, "gts": gts, "hposes": hposes, "u_all": u_all}
 
 
 def add_distance(points, pa, pb):
     """Mean distance between the object's points placed at poses pa and pb
-    (x(3), q(4)): the tracking error of a pose estimate."""
+    (x(3), q(4)): the tracking error of a pose estimate (ADD, Sec. IV)."""
     import numpy as np
 
     def rot(q):
@@ -220,21 +186,290 @@ WRS_LAMBDA = 1.0
 REPS_EPS = 1.0
 
 
-def realtime_setup(pt, S, dev, solve_precision, n_total, cost_mode=0):
-    """Scene, observed forces and observed poses of the real-time workload,
-    shared by the optimisers compared on it (cost_mode 1: the full cost of
-    Eq. 3 and its seven-row observation)."""
-    import dataclasses
-    import torch
-    cfg = S.CONFIGS["realtime16384"]
-    if cost_mode:
-        cfg = cfg.with_(consts=dataclasses.replace(cfg.consts, cost_mode=cost_mode))
-    T = cfg.T
-    sc = S.make_scene(cfg, steps=(n_total + 1) * T + 1)
-    gts, hposes = observed_forces(pt, sc, dev, solve_precision, n_total * T, pose_every=T)
-    u_all = torch.as_tensor(sc.u.astype("float32"), device=dev)
-    return {"cfg": cfg, "sc": sc, "gts": gts, "hposes": hposes, "u_all": u_all}
+# --------------------------------------------------------------------------
+# the paths
+# --------------------------------------------------------------------------
 
+def windows_run(pt, setup, dev, solve_precision, n_win, n_warm, optimizer="pbo", refine=True):
+    """Batched windows of a workload: each window's commands and observed
+    forces are copied into the two buffers a captured HIP graph reads, the
+    population's window is one persistent kernel replayed from that graph,
+    then (refine) the elites are refined by three gradient steps of the
+    window cost from their window start, then the optimiser resamples
+    ("pbo", "wrs", "reps"; "eye" neither refines nor resamples).  Reports
+    env-steps/s over the timed windows, the per-step latency (window time /
+    T), the resampler's time, the window kernel's HIP-event time and
+    algorithmic flop, and the tracking error after every window."""
+    import numpy as np
+    import torch
+    cfg, sc, gts, u_all = setup["cfg"], setup["sc"], setup["gts"], setup["u_all"]
+    T = cfg.T
+    K, G, L = sc.K, sc.G, sc.L
+    adapt = optimizer != "eye"
+    refine = refine and adapt
+    n_total = n_warm + n_win
+    assert n_total * T <= gts.shape[0]
+    b = pt.Batch.from_scene(sc, solve_precision=solve_precision, window_checkpoints=refine)
+    u_win = torch.empty((T + 1, sc.D), device=dev)
+    gt_win = torch.empty((T, b.obs_rows, L, G), device=dev)
+    cost = torch.zeros(K, device=dev)
+    best = torch.zeros(G, dtype=torch.int32, device=dev)
+    parent = torch.zeros(K, dtype=torch.int32, device=dev)
+    first = torch.as_tensor(np.asarray(sc.group_start[:-1], dtype=np.int64), device=dev)
+    snap = b.snapshot()
+    est = torch.empty((n_total, 13, G), device=dev)
+    est_olp = torch.empty((n_total, 13, G), device=dev)
+    mk = lambda: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))  # noqa: E731
+    ev, ev_rs, ev_win = [mk() for _ in range(n_total)], [mk() for _ in range(n_total)], [mk() for _ in range(n_total)]
+    improved = [0, 0]
+
+    def window(w, count=False):
+        t0_ = w * T
+        ev[w][0].record()
+        u_win.copy_(u_all[t0_ - 1: t0_ + T] if t0_ > 0 else torch.cat([u_all[:1], u_all[:T]], 0))
+        gt_win.copy_(gts[t0_: t0_ + T])
+        if refine:
+            snap[0].copy_(b.state)
+            snap[1].copy_(b.params)
+            snap[2].copy_(b.warm)
+        ev_win[w][0].record()
+        b.run_window(u_win, gt_win, cost, best, None, graph=True)
+        ev_win[w][1].record()
+        if refine:
+            c0 = cost.clone() if count else None
+            elites = b.refine_elites(u_win, gt_win, cost, snap, steps=3, step=0.5, best=best)
+            if count:
+                e = elites.long()
+                improved[0] += int((cost[e] < c0[e]).sum())
+                improved[1] += int(e.numel())
+        torch.index_select(b.state, 1, best, out=est[w])
+        if not adapt:
+            torch.index_select(b.state, 1, first, out=est_olp[w])
+        ev_rs[w][0].record()
+        if optimizer == "pbo":
+            b.resample(cost, w, parent)
+        elif optimizer == "wrs":
+            b.resample_wrs(cost, T, w, WRS_LAMBDA, parent)
+        elif optimizer == "reps":
+            b.resample_reps(cost, T, w, REPS_EPS, parent)
+        else:
+            cost.zero_()
+        ev_rs[w][1].record()
+        ev[w][1].record()
+
+    u_win.copy_(torch.cat([u_all[:1], u_all[:T]], 0))
+    gt_win.copy_(gts[:T])
+    tuned = b.autotune(u_win, gt_win)
+    torch.cuda.synchronize()
+    for w in range(n_warm):
+        window(w, count=refine and w == n_warm - 1)
+    torch.cuda.synchronize()
+    stats0 = b.read_stats()
+    t0 = time.perf_counter()
+    for w in range(n_warm, n_total):
+        window(w)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    stats1 = b.read_stats()
+    step_ms = np.array([ev[w][0].elapsed_time(ev[w][1]) / T for w in range(n_warm, n_total)])
+    win_ms = np.array([ev_win[w][0].elapsed_time(ev_win[w][1]) for w in range(n_warm, n_total)])
+    rs_ms = np.array([ev_rs[w][0].elapsed_time(ev_rs[w][1]) for w in range(n_warm, n_total)])
+    # the population's window (graph replay of the persistent k_window; the
+    # refinement's own replays do not count their steps in the statistics)
+    d_env = stats1["env_steps"] - stats0["env_steps"]
+    d_con = stats1["contacts"] - stats0["contacts"]
+    flops = algorithmic_flops(int(sc.n_spheres.max()), L, cfg.newton_iters, d_env, d_con)
+    hp = setup["hposes"].cpu().numpy()
+
+    def tracking(e):
+        errs = []
+        for w in range(n_warm, n_total):
+            for g in range(G):
+                pts = sc.spheres[sc.hidden_type[g], :sc.n_spheres[sc.hidden_type[g]], :3]
+                errs.append(add_distance(pts, e[w, :7, g], hp[w, :7, g]))
+        return {"mean": round(1e3 * float(np.mean(errs)), 3), "p90": round(1e3 * float(np.quantile(errs, 0.9)), 3)}
+
+    n_elite = b.elite_count()
+    b.close()
+    out = {"value": K * T * n_win / wall, "unit": "env-steps/s", "windows": n_win,
+           "ms_per_step": round(wall / (n_win * T) * 1e3, 4),
+           "per_step_ms": {"p50": round(float(np.median(step_ms)), 4),
+                           "p99": round(float(np.quantile(step_ms, 0.99)), 4)},
+           "budget_30hz_met": bool(np.quantile(step_ms, 0.99) < 1000.0 / 30.0),
+           "resample_ms_per_window": round(float(np.median(rs_ms)), 4),
+           "tracking_error_mm": tracking(est.cpu().numpy()),
+           "waves_per_workgroup": tuned,
+           "window_kernel": {"avg_launch_us": round(float(win_ms.mean()) * 1e3, 2),
+                             "flop_per_launch": flops / n_win, "env_steps_per_launch": d_env / n_win,
+                             "contacts_per_env_step": round(d_con / max(d_env, 1), 2)}}
+    if refine:
+        out.update({"elites": n_elite, "refine_steps": 3,
+                    "elites_improved_frac": round(improved[0] / max(improved[1], 1), 3)})
+    if not adapt:
+        out["open_loop_tracking_error_mm"] = tracking(est_olp.cpu().numpy())
+    return out
+
+
+def plain_run(pt, setup, dev, solve_precision, steps, warmup):
+    """The plain per-step launch path: step, observe, cost with the argmin,
+    the resampler every T steps; env-steps/s over `steps` timed steps after
+    `warmup`, and the per-step latency of step + observe + cost (HIP events
+    on the stream)."""
+    import numpy as np
+    import torch
+    cfg, sc, gts, u_all = setup["cfg"], setup["sc"], setup["gts"], setup["u_all"]
+    K, G, T = sc.K, sc.G, cfg.T
+    assert warmup + steps <= gts.shape[0]
+    b = pt.Batch.from_scene(sc, solve_precision=solve_precision)
+    cost = torch.zeros(K, device=dev)
+    best = torch.zeros(G, dtype=torch.int32, device=dev)
+    parent = torch.zeros(K, dtype=torch.int32, device=dev)
+    obs = b.new_obs()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+
+    def one(t, i=None):
+        if i is not None:
+            ev[i][0].record()
+        b.step(u_all[max(t - 1, 0)], u_all[t])
+        b.observe(obs)
+        b.cost(obs, gts[t], cost, best)
+        if i is not None:
+            ev[i][1].record()
+        if (t + 1) % T == 0:
+            b.resample(cost, (t + 1) // T - 1, parent)
+
+    for t in range(warmup):
+        one(t)
+    torch.cuda.synchronize()
+    stats0 = b.read_stats()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        one(warmup + i, i)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    stats1 = b.read_stats()
+    b.close()
+    step_ms = np.array([a.elapsed_time(c) for a, c in ev])
+    d_env = stats1["env_steps"] - stats0["env_steps"]
+    d_con = stats1["contacts"] - stats0["contacts"]
+    return {"value": K * steps / wall, "unit": "env-steps/s", "steps": steps,
+            "ms_per_step": round(wall / steps * 1e3, 4),
+            "per_step_ms": {"p50": round(float(np.median(step_ms)), 4),
+                            "p99": round(float(np.quantile(step_ms, 0.99)), 4)},
+            "budget_30hz_met": bool(np.quantile(step_ms, 0.99) < 1000.0 / 30.0),
+            "contacts_per_env_step": round(d_con / max(d_env, 1), 2)}
+
+
+def repeat(fn, runs):
+    return median_run([fn() for _ in range(runs)])
+
+
+def rounded(d):
+    d = dict(d)
+    d["value"] = round(d["value"], 1)
+    return d
+
+
+# --------------------------------------------------------------------------
+# ceilings, CPU baseline
+# --------------------------------------------------------------------------
+
+def ceilings(dev):
+    """Measured float64 FMA rate and HBM copy bandwidth of this device (the
+    ceiling library's microbenchmarks), best of five."""
+    import torch
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_2002_12160_amd", "libptceil.so"))
+    lib.ptc_fma_f64.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p]
+    lib.ptc_copy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, ctypes.c_void_p]
+    n_cu = torch.cuda.get_device_properties(dev).multi_processor_count
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    blocks, iters = n_cu * 16, 8192
+    out = torch.empty(blocks * 256, dtype=torch.float64, device=dev)
+    flop = 2.0 * lib.ptc_fma_chains() * iters * blocks * 256
+    best_fma = 0.0
+    for _ in range(6):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        assert lib.ptc_fma_f64(ctypes.c_void_p(out.data_ptr()), blocks, iters, stream) == 0
+        b.record()
+        torch.cuda.synchronize()
+        best_fma = max(best_fma, flop / (a.elapsed_time(b) * 1e-3) / 1e12)
+    nbytes = 1 << 30
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    best_copy = 0.0
+    for _ in range(6):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        assert lib.ptc_copy(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()), nbytes, n_cu * 8,
+                            stream) == 0
+        b.record()
+        torch.cuda.synchronize()
+        best_copy = max(best_copy, 2.0 * nbytes / (a.elapsed_time(b) * 1e-3) / 1e9)
+    del src, dst, out
+    return {"fma_f64_tflops": round(best_fma, 2), "fma_f64_nominal_tflops": PEAK_F64_TFLOPS,
+            "copy_gbps": round(best_copy, 1), "copy_gbps_nominal": PEAK_HBM_GBPS,
+            "how": "float64 FMA loop (8 independent chains per thread, 16 workgroups of 256 threads per compute "
+                   "unit) and a 1 GiB device-to-device copy (read + write bytes), best of 6"}
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(S, cfg, steps):
+    """The FP64 oracle on a stratified sample of the headline workload:
+    sims_per_group simulations of every group (every object) from the start,
+    stepped with the observation and the cost against the observed
+    simulations; env-steps/s counts the sampled simulations only.  The
+    oracle's cost per simulation does not depend on the population size, so
+    the rate applies to the full population (a linear extrapolation in K).
+    Timed on all the host threads OpenMP uses, then on one thread."""
+    import numpy as np
+    import oracle
+    sims_per_group = 16
+    full = S.make_scene(cfg, steps=steps + 1)
+    idx = np.concatenate([np.arange(full.group_start[g], full.group_start[g] + sims_per_group)
+                          for g in range(full.G)])
+    gs = np.arange(0, len(idx) + 1, sims_per_group, dtype=np.int32)
+    sub = dataclasses.replace(full, env_type=np.ascontiguousarray(full.env_type[idx]), group_start=gs,
+                              state=np.ascontiguousarray(full.state[idx]), params=np.ascontiguousarray(full.params[idx]))
+    res = {}
+    threads_all = oracle.max_threads()
+    for label, threads, n_steps, n_sim in (("all", threads_all, steps, len(idx)), ("one", 1, max(steps // 5, 4), 32)):
+        oracle.set_threads(threads)
+        pick = np.arange(0, len(idx), len(idx) // n_sim)[:n_sim]
+        s2 = sub if n_sim == len(idx) else dataclasses.replace(
+            sub, env_type=np.ascontiguousarray(sub.env_type[pick]), state=np.ascontiguousarray(sub.state[pick]),
+            params=np.ascontiguousarray(sub.params[pick]),
+            group_start=np.arange(0, n_sim + 1, n_sim // full.G, dtype=np.int32))
+        tr = oracle.Tracker(s2)
+        c0 = time.perf_counter()
+        for _ in range(n_steps):
+            tr.step()
+        sec = time.perf_counter() - c0
+        res[label] = (s2.K * n_steps / sec, threads, s2.K, n_steps, sec)
+    oracle.set_threads(threads_all)
+    v, thr, k, n, sec = res["all"]
+    v1, _, k1, n1, sec1 = res["one"]
+    return {"value": round(v, 1), "unit": "env-steps/s", "cores": thr, "kind": "oracle",
+            "sample": f"{k} simulations ({sims_per_group} of each of the {full.G} groups) of {cfg.name} for {n} steps "
+                      f"from the start, with the {full.G} observed simulations, observation, cost and the resampler "
+                      f"every {cfg.T} steps; FP64 dense-Newton oracle, {sec:.1f} s on {thr} threads; the rate per "
+                      f"simulation does not depend on K (linear extrapolation to {full.K})",
+            "cpu_model": cpu_model(), "one_thread": {"value": round(v1, 1), "simulations": k1, "steps": n1,
+                                                     "seconds": round(sec1, 1)}}
+
+
+# --------------------------------------------------------------------------
+# Eq. 3 weights (full-cost comparison leg)
+# --------------------------------------------------------------------------
 
 def eq3_weights(pt, setup, dev, solve_precision):
     """Weights w4..w10 of Eq. 3 such that every term's mean magnitude over
@@ -248,8 +483,8 @@ def eq3_weights(pt, setup, dev, solve_precision):
     c = cfg.consts
     b = pt.Batch.from_scene(sc, solve_precision=solve_precision)
     obs_w = torch.zeros((T, 7, L, K), device=dev)
-    b.run_window(torch.cat([u_all[:1], u_all[:T]], 0), gts[:T].contiguous(), torch.zeros(K, device=dev), None,
-                 obs_w, graph=False)
+    b.run_window(torch.cat([u_all[:1], u_all[:T]], 0).contiguous(), gts[:T].contiguous(), torch.zeros(K, device=dev),
+                 None, obs_w, graph=False)
     torch.cuda.synchronize()
     b.close()
     o = obs_w.cpu().numpy().astype(np.float64)
@@ -274,158 +509,14 @@ def eq3_weights(pt, setup, dev, solve_precision):
     return tuple(1.0 / m if m > 0 else 1.0 for m in means)
 
 
-def realtime_run(pt, S, dev, solve_precision, n_win, n_warm=2, optimizer="pbo", setup=None, refine=True,
-                 describe=False):
-    """The real-time workload: 16384 simulations in 16 groups (one
-    superquadric object each), batched windows; with optimizer "pbo", "wrs"
-    or "reps" the elites are refined before every resampling by that
-    optimiser, with "eye" the population is never refined nor resampled.
-    Reports env-steps/s, the per-step latency (window time / T) against the
-    33 ms budget of 30 Hz, the resampler's time per window and the tracking
-    error: the mean distance between the object's points at the estimated
-    pose and at the observed object's pose, after every window, over all
-    groups -- the estimate being the lowest-cost simulation (for "eye" also
-    the first simulation of each group alone, which is the open-loop
-    baseline: without resampling each simulation evolves on its own)."""
-    import numpy as np
-    import torch
-    n_total = n_warm + n_win
-    if setup is None:
-        setup = realtime_setup(pt, S, dev, solve_precision, n_total)
-    cfg, sc, gts, hposes, u_all = setup["cfg"], setup["sc"], setup["gts"], setup["hposes"], setup["u_all"]
-    T = cfg.T
-    K, G, L = sc.K, sc.G, sc.L
-    adapt = optimizer != "eye"
-    refine = refine and adapt
-    b = pt.Batch.from_scene(sc, solve_precision=solve_precision, window_checkpoints=refine)
-    u_win = torch.empty((T + 1, sc.D), device=dev)
-    gt_win = torch.empty((T, b.obs_rows, L, G), device=dev)
-    cost = torch.zeros(K, device=dev)
-    best = torch.zeros(G, dtype=torch.int32, device=dev)
-    parent = torch.zeros(K, dtype=torch.int32, device=dev)
-    first = torch.as_tensor(np.asarray(sc.group_start[:-1], dtype=np.int64), device=dev)
-    snap = b.snapshot()
-    est = torch.empty((n_total, 13, G), device=dev)
-    est_olp = torch.empty((n_total, 13, G), device=dev)
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n_total)]
-    ev_rs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n_total)]
-    ev_win = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n_total)]
+# --------------------------------------------------------------------------
 
-    def window(w):
-        t0_ = w * T
-        ev[w][0].record()
-        u_win.copy_(u_all[t0_ - 1: t0_ + T] if t0_ > 0 else torch.cat([u_all[:1], u_all[:T]], 0))
-        gt_win.copy_(gts[t0_: t0_ + T])
-        if refine:
-            snap[0].copy_(b.state)
-            snap[1].copy_(b.params)
-            snap[2].copy_(b.warm)
-        ev_win[w][0].record()
-        b.run_window(u_win, gt_win, cost, best, None, graph=True)
-        ev_win[w][1].record()
-        if refine:
-            b.refine_elites(u_win, gt_win, cost, snap, steps=3, step=0.5, best=best)
-        torch.index_select(b.state, 1, best, out=est[w])
-        if not adapt:
-            torch.index_select(b.state, 1, first, out=est_olp[w])
-        ev_rs[w][0].record()
-        if optimizer == "pbo":
-            b.resample(cost, w, parent)
-        elif optimizer == "wrs":
-            b.resample_wrs(cost, T, w, WRS_LAMBDA, parent)
-        elif optimizer == "reps":
-            b.resample_reps(cost, T, w, REPS_EPS, parent)
-        else:
-            cost.zero_()
-        ev_rs[w][1].record()
-        ev[w][1].record()
-
-    u_win.copy_(torch.cat([u_all[:1], u_all[:T]], 0))
-    gt_win.copy_(gts[:T])
-    tuned = b.autotune(u_win, gt_win)
-    torch.cuda.synchronize()
-    for w in range(n_warm):
-        window(w)
-    torch.cuda.synchronize()
-    stats0 = b.read_stats()
-    t0 = time.perf_counter()
-    for w in range(n_warm, n_total):
-        window(w)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    stats1 = b.read_stats()
-    step_ms = np.array([ev[w][0].elapsed_time(ev[w][1]) / T for w in range(n_warm, n_total)])
-    win_s = sum(ev_win[w][0].elapsed_time(ev_win[w][1]) for w in range(n_warm, n_total)) / 1e3
-    # the population's window kernel alone (the graph replay of the
-    # persistent k_window; the refinement's forward passes do not count
-    # their steps): algorithmic flop of its steps / its HIP-event time
-    d_env = stats1["env_steps"] - stats0["env_steps"]
-    w_flops = algorithmic_flops(int(sc.n_spheres[0]), L, cfg.newton_iters, d_env,
-                                stats1["contacts"] - stats0["contacts"])
-    rs_ms = np.array([ev_rs[w][0].elapsed_time(ev_rs[w][1]) for w in range(n_warm, n_total)])
-    hp = setup["hposes"].cpu().numpy()
-
-    def tracking(e):
-        errs = []
-        for w in range(n_warm, n_total):
-            for g in range(G):
-                pts = sc.spheres[sc.hidden_type[g], :sc.n_spheres[sc.hidden_type[g]], :3]
-                errs.append(add_distance(pts, e[w, :7, g], hp[w, :7, g]))
-        return {"mean": round(1e3 * float(np.mean(errs)), 3), "p90": round(1e3 * float(np.quantile(errs, 0.9)), 3)}
-
-    b.close()
-    out = {"value": round(K * T * n_win / wall, 1), "unit": "env-steps/s",
-           "per_step_ms": {"p50": round(float(np.median(step_ms)), 3),
-                           "p99": round(float(np.quantile(step_ms, 0.99)), 3)},
-           "budget_30hz_met": bool(np.quantile(step_ms, 0.99) < 1000.0 / 30.0),
-           "resample_ms_per_window": round(float(np.median(rs_ms)), 4),
-           "tracking_error_mm": tracking(est.cpu().numpy()),
-           "waves_per_workgroup": tuned,
-           "window_kernel": {"bound": "alu", "achieved": round(w_flops / win_s / 1e12, 4), "peak": 78.6,
-                             "unit": "TFLOP/s", "frac": round(w_flops / win_s / 1e12 / 78.6, 5),
-                             "avg_window_ms": round(win_s / n_win * 1e3, 3),
-                             "flop_per_env_step": round(w_flops / max(d_env, 1), 1)}}
-    if not adapt:
-        out["open_loop_tracking_error_mm"] = tracking(est_olp.cpu().numpy())
-    if describe:
-        out = {"workload": f"{cfg.name}: {K} simulations in {G} groups (one {int(sc.n_spheres[0])}-sphere "
-                           f"superquadric object each) + {G} observed, {L} capsule links, C_max={cfg.C_max}, "
-                           f"{cfg.newton_iters} Newton iterations, {T}-step windows, elite refinement (3 steps) and "
-                           f"resampling after every window, {n_win} timed windows", **out}
-    return out
-
-
-def plain_run(pt, sc, dev, solve_precision, steps, warmup):
-    """The plain per-step path on a scene (step, observe, cost with the
-    argmin, the resampler every T steps): env-steps/s over `steps` timed
-    steps after `warmup`."""
-    import torch
-    K, G, T = sc.K, sc.G, sc.cfg.T
-    gts = observed_forces(pt, sc, dev, solve_precision, warmup + steps)
-    u_all = torch.as_tensor(sc.u.astype("float32"), device=dev)
-    b = pt.Batch.from_scene(sc, solve_precision=solve_precision)
-    cost = torch.zeros(K, device=dev)
-    best = torch.zeros(G, dtype=torch.int32, device=dev)
-    parent = torch.zeros(K, dtype=torch.int32, device=dev)
-    obs = b.new_obs()
-
-    def one(t):
-        b.step(u_all[max(t - 1, 0)], u_all[t])
-        b.observe(obs)
-        b.cost(obs, gts[t], cost, best)
-        if (t + 1) % T == 0:
-            b.resample(cost, (t + 1) // T - 1, parent)
-
-    for t in range(warmup):
-        one(t)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for t in range(warmup, warmup + steps):
-        one(t)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    b.close()
-    return {"value": round(K * steps / wall, 1), "unit": "env-steps/s", "ms_per_step": round(wall / steps * 1e3, 4)}
+def describe(cfg, sc):
+    objs = sorted(set(int(x) for x in sc.n_spheres))
+    kind = cfg.objects[0].kind
+    return (f"{cfg.name}: {sc.K} simulations in {sc.G} group{'s' if sc.G > 1 else ''} + {sc.G} observed, "
+            f"{sc.L} capsule links, {'/'.join(map(str, objs))}-sphere {kind} object{'s' if len(objs) > 1 else ''}, "
+            f"C_max={cfg.C_max}, {cfg.newton_iters} Newton iterations, {cfg.T}-step windows")
 
 
 def main():
@@ -438,189 +529,150 @@ def main():
     import torch
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
     if args.copy_calibration:
-        a = torch.ones(64 * 1024 * 1024, device="cuda")
+        lib = ctypes.CDLL(os.path.join(ROOT, "paper_2002_12160_amd", "libptceil.so"))
+        lib.ptc_copy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, ctypes.c_void_p]
+        nbytes = 256 << 20
+        a = torch.ones(nbytes // 4, device=dev)
         b = torch.empty_like(a)
-        torch.cuda.synchronize()
+        s = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
         for _ in range(3):
-            b.copy_(a)
+            assert lib.ptc_copy(ctypes.c_void_p(a.data_ptr()), ctypes.c_void_p(b.data_ptr()), nbytes, 2048, s) == 0
         torch.cuda.synchronize()
-        print(json.dumps({"copy_calibration_bytes": a.numel() * 4, "copies": 3}), flush=True)
+        print(json.dumps({"copy_calibration_bytes": nbytes, "copies": 3}), flush=True)
         return
 
     from paper_2002_12160_amd import pt
     from paper_2002_12160_amd import scene as S
 
-    dev = torch.device("cuda:0")
-    cfg = S.CONFIGS[args.config]
-    total_steps = args.warmup + args.steps
+    sp = args.solve_precision
+    cfg = S.CONFIGS["realtime16384"]
     T = cfg.T
-    sc = S.make_scene(cfg, steps=max(total_steps, cfg.steps) + 2 * cfg.T + 1)
+    n_win = max(MIN_WINDOWS, -(-args.steps // T))
+    n_warm = max(1, -(-args.warmup // T))
+    runs = 1 if args.profile else args.runs
+    if args.profile:
+        n_win = 3
+    print(f"bench: headline {cfg.name}, {runs} runs of {n_win} windows after {n_warm}", file=sys.stderr, flush=True)
+    setup = make_setup(pt, S, dev, sp, cfg, n_warm + n_win)
+    head = repeat(lambda: windows_run(pt, setup, dev, sp, n_win, n_warm), runs)
+    print(f"bench: headline {head['value']:.4g} env-steps/s", file=sys.stderr, flush=True)
+    sc = setup["sc"]
     K, G, L = sc.K, sc.G, sc.L
-    u_all = torch.as_tensor(sc.u.astype(np.float32), device=dev)
-
-    # ---------------- plain per-step path ----------------------------------
-    # step, observe, cost against the resident observed forces, argmin; the
-    # resampler every T steps
-    gts = observed_forces(pt, sc, dev, args.solve_precision, total_steps)
-    main_b = pt.Batch.from_scene(sc, solve_precision=args.solve_precision)
-    cost = torch.zeros(K, device=dev)
-    best = torch.zeros(G, dtype=torch.int32, device=dev)
-    parent = torch.zeros(K, dtype=torch.int32, device=dev)
-    obs = main_b.new_obs()
-    stream = torch.cuda.current_stream()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
-    window = 0
-    torch.cuda.synchronize()
-
-    def plain_step(t, timed_idx=None):
-        nonlocal window
-        up, u = u_all[max(t - 1, 0)], u_all[t]
-        if timed_idx is not None:
-            ev[timed_idx][0].record(stream)
-        main_b.step(up, u)
-        if timed_idx is not None:
-            ev[timed_idx][1].record(stream)
-        main_b.observe(obs)
-        main_b.cost(obs, gts[t], cost, best)
-        if (t + 1) % T == 0:
-            main_b.resample(cost, window, parent)
-            window += 1
-
-    for t in range(args.warmup):
-        plain_step(t)
-    torch.cuda.synchronize()
-    stats0 = main_b.read_stats()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        plain_step(args.warmup + i, i)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    stats1 = main_b.read_stats()
-    step_ms = [a.elapsed_time(b) for a, b in ev]
-    env_steps = K * args.steps
-    plain_value = env_steps / wall
-    d_env = stats1["env_steps"] - stats0["env_steps"]
-    d_con = stats1["contacts"] - stats0["contacts"]
-    d_cand = stats1["candidates"] - stats0["candidates"]
-    S_sph = int(sc.n_spheres[0])
-    flops = algorithmic_flops(S_sph, L, cfg.newton_iters, d_env, d_con)
-    step_kernel_s = sum(step_ms) / 1e3
-    achieved_tflops = flops / step_kernel_s / 1e12
-    main_b.close()
-
+    wk = head["window_kernel"]
+    achieved = wk["flop_per_launch"] / (wk["avg_launch_us"] * 1e-6) / 1e12
+    m = measured("k_window_realtime16384")
+    launch_s = wk["avg_launch_us"] * 1e-6
+    roofline = {"bound": "alu", "kernel": "k_window (float64 solve; the 10-step window of all 16384 simulations)",
+                "achieved": round(achieved, 3), "peak": PEAK_F64_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK_F64_TFLOPS, 4),
+                "traffic": m["traffic"] if m else None,
+                "flop_per_env_step": round(wk["flop_per_launch"] / wk["env_steps_per_launch"], 1),
+                "env_steps_per_launch": int(wk["env_steps_per_launch"]),
+                "avg_launch_us": wk["avg_launch_us"],
+                "hbm_bytes_per_env_step": round(window_bytes(cfg.C_max, T, L), 1),
+                "hbm_gbps": round(window_bytes(cfg.C_max, T, L) * wk["env_steps_per_launch"] / launch_s / 1e9, 2),
+                "valu": ({"issue_frac": round(m["valu_insts"] * 4 / (SIMDS * CLOCK_HZ * launch_s), 4),
+                          "busy_frac": round(m["valu_busy_quads"] * 4 / (SIMDS * CLOCK_HZ * launch_s), 4)}
+                         if m else None)}
     result = {
-        "metric": "env-steps/sec (step+observe+cost) plain vs batched vs +adjoint, 30Hz budget met",
-        "value": round(plain_value, 1),
+        "metric": METRIC,
+        "value": round(head["value"], 1),
         "unit": "env-steps/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(wall / args.steps * 1e3, 4),
+        "steps": n_win * T,
+        "warmup": n_warm * T,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if args.solve_precision == 32 else "f32+f64solve",
+        "dtype": "f32" if sp == 32 else "f32+f64solve",
         "data": "synthetic",
-        "config": {"workload": f"{cfg.name}: {K} simulations + {G} observed, {args.steps} timed steps at "
-                               f"{1 / cfg.consts.dt:.0f} Hz, {L} capsule links, {S_sph}-sphere object, "
-                               f"C_max={cfg.C_max}, {cfg.newton_iters} Newton iterations, PBO every {T} steps",
-                   "path": "plain per-step launches", "solve_precision": args.solve_precision,
-                   "observed_forces": "precomputed by the observed simulation, resident in HBM"},
-        "per_step_ms": {"p50": round(float(np.median(step_ms)), 4), "p99": round(float(np.quantile(step_ms, 0.99)), 4)},
-        "budget_30hz_met": bool(wall / args.steps < 1.0 / 30.0),
-        "contacts_per_env_step": round(d_con / max(d_env, 1), 2),
-        "candidates_per_env_step": round(d_cand / max(d_env, 1), 2),
-        "roofline": {"bound": "alu", "kernel": "k_step (hand kinematics evaluated inside it)",
-                     "achieved": round(achieved_tflops, 4), "peak": 78.6,
-                     "unit": "TFLOP/s", "frac": None,
-                     "traffic": MEASURED_TRAFFIC.get((cfg.name, args.solve_precision)),
-                     "flop_per_env_step": round(flops / max(d_env, 1), 1),
-                     "hbm_bytes_per_env_step": algorithmic_bytes(cfg.C_max),
-                     "hbm_gbps": round(algorithmic_bytes(cfg.C_max) * d_env / step_kernel_s / 1e9, 3),
-                     "avg_launch_us": round(step_kernel_s / args.steps * 1e6, 2),
-                     "valu": valu_figures((cfg.name, args.solve_precision), step_kernel_s / args.steps, K)},
+        "config": {"workload": describe(cfg, sc) + f", {n_win * T} timed steps ({n_win * T / 30:.0f} s at 30 Hz)",
+                   "path": "batched: persistent window kernel replayed from a HIP graph, then adjoint refinement of "
+                           "the elites (3 gradient steps), then PBO resampling, every window",
+                   "runs": runs, "steps_requested": args.steps,
+                   "observed_forces": "precomputed by the observed simulations, resident in HBM"},
+        "per_step_ms": head["per_step_ms"],
+        "budget_30hz_met": head["budget_30hz_met"],
+        "tracking_error_mm": head["tracking_error_mm"],
+        "runs": head["runs"],
+        "roofline": roofline,
     }
-    result["roofline"]["frac"] = round(result["roofline"]["achieved"] / result["roofline"]["peak"], 6)
+    if args.profile:
+        print(json.dumps(result), flush=True)
+        return
 
-    # ---------------- batched path (persistent kernel + graph) -------------
-    if not args.no_batched:
-        n_win = max(1, args.steps // T)
-        n_warm = max(1, args.warmup // T)
-        bat = batched_run(pt, S, sc, dev, args.solve_precision, n_win, n_warm, adjoint=False)
-        bat["speedup_vs_plain"] = round(bat["value"] / plain_value, 3)
-        result["batched"] = bat
-        if not args.no_adjoint:
-            adj = batched_run(pt, S, sc, dev, args.solve_precision, n_win, n_warm, adjoint=True)
-            adj["speedup_vs_plain"] = round(adj["value"] / plain_value, 3)
-            result["batched_adjoint"] = adj
-            # the differentiation workload: 1024 simulations, 64-sphere cuboid
-            acfg = S.CONFIGS["adjoint1024"]
-            asc = S.make_scene(acfg, steps=(n_win + n_warm + 2) * acfg.T + 1)
-            a_b = batched_run(pt, S, asc, dev, args.solve_precision, n_win, n_warm, adjoint=False)
-            a_a = batched_run(pt, S, asc, dev, args.solve_precision, n_win, n_warm, adjoint=True)
-            result["adjoint1024"] = {
-                "workload": f"{acfg.name}: {asc.K} simulations + {asc.G} observed, {asc.L} capsule links, "
-                            f"{int(asc.n_spheres[0])}-sphere cuboid, C_max={acfg.C_max}, "
-                            f"{acfg.newton_iters} Newton iterations, {acfg.T}-step windows",
-                "batched": a_b, "batched_adjoint": a_a,
-                "adjoint_cost_ratio": round(a_b["value"] / a_a["value"], 3)}
-            # the batching workload: 4096 simulations of three object
-            # types (32-, 64- and 128-sphere), 64-contact cap, plain
-            # per-step launches against the persistent kernel + graph
-            bcfg = S.CONFIGS["batched4096"]
-            bsc = S.make_scene(bcfg, steps=max(total_steps, (n_win + n_warm + 2) * bcfg.T) + 1)
-            b_p = plain_run(pt, bsc, dev, args.solve_precision, args.steps, args.warmup)
-            b_b = batched_run(pt, S, bsc, dev, args.solve_precision, n_win, n_warm, adjoint=False)
-            result["batched4096"] = {
-                "workload": f"{bcfg.name}: {bsc.K} simulations + {bsc.G} observed, {bsc.L} capsule links, "
-                            f"objects of {sorted(set(int(x) for x in bsc.n_spheres))} spheres, "
-                            f"C_max={bcfg.C_max}, {bcfg.newton_iters} Newton iterations, {bcfg.T}-step windows",
-                "plain": b_p, "batched": b_b, "speedup_vs_plain": round(b_b["value"] / b_p["value"], 3)}
+    # the other two paths on the same workload
+    plain_steps = min(n_win * T, 300)
+    plain = repeat(lambda: plain_run(pt, setup, dev, sp, plain_steps, n_warm * T), runs)
+    print(f"bench: plain {plain['value']:.4g}", file=sys.stderr, flush=True)
+    batched = repeat(lambda: windows_run(pt, setup, dev, sp, n_win, n_warm, refine=False), runs)
+    print(f"bench: batched {batched['value']:.4g}", file=sys.stderr, flush=True)
+    pv = plain["value"]
+    result["paths"] = {
+        "plain": rounded(plain),
+        "batched": dict(rounded(batched), speedup_vs_plain=round(batched["value"] / pv, 3)),
+        "batched_adjoint": {"value": result["value"], "speedup_vs_plain": round(head["value"] / pv, 3),
+                            "vs_batched": round(head["value"] / batched["value"], 3),
+                            "resample_ms_per_window": head["resample_ms_per_window"],
+                            "elites_improved_frac": head.get("elites_improved_frac")},
+    }
+    result["ceilings"] = ceilings(dev)
+    result["roofline"]["frac_of_measured_fma"] = round(achieved / result["ceilings"]["fma_f64_tflops"], 4)
 
-    # ---------------- real-time workload (16384 simulations) -------------
-    if not args.no_batched and not args.no_adjoint and args.realtime_windows > 0:
-        n_rt = args.realtime_windows if not args.profile else 3
-        rt_setup = realtime_setup(pt, S, dev, args.solve_precision, n_rt + 2)
-        result["realtime16384"] = realtime_run(pt, S, dev, args.solve_precision, n_rt, setup=rt_setup,
-                                               describe=True)
-        if not args.no_optimizers:
-            # the paper's other optimisers and its identity baseline on the
-            # same workload (Sec. III-D, Sec. IV), same windows and refinement
-            result["realtime16384"]["optimizers"] = {
-                "wrs": {"lambda": WRS_LAMBDA,
-                        **realtime_run(pt, S, dev, args.solve_precision, n_rt, optimizer="wrs", setup=rt_setup)},
-                "reps": {"epsilon": REPS_EPS,
-                         **realtime_run(pt, S, dev, args.solve_precision, n_rt, optimizer="reps", setup=rt_setup)},
-                "eye": realtime_run(pt, S, dev, args.solve_precision, n_rt, optimizer="eye", setup=rt_setup),
-                # the cost itself: PBO without refinement (the full cost has no
-                # gradient) on the force terms and on the full Eq. 3
-                "pbo_no_refinement": realtime_run(pt, S, dev, args.solve_precision, n_rt, setup=rt_setup,
-                                                  refine=False)}
-            eq3_setup = realtime_setup(pt, S, dev, args.solve_precision, n_rt + 2, cost_mode=1)
-            w_eq3 = eq3_weights(pt, eq3_setup, dev, args.solve_precision)
-            sc3 = eq3_setup["sc"]
-            cfg3 = sc3.cfg.with_(consts=dataclasses.replace(sc3.cfg.consts, w_eq3=w_eq3))
-            eq3_setup.update(cfg=cfg3, sc=dataclasses.replace(sc3, cfg=cfg3))
-            result["realtime16384"]["optimizers"]["pbo_eq3_cost"] = {
-                "w4_w10": [round(x, 4) for x in w_eq3],
-                **realtime_run(pt, S, dev, args.solve_precision, n_rt, setup=eq3_setup, refine=False)}
+    # the other workloads, the paths their definitions name
+    if not args.no_workloads:
+        wl = {}
+        for name, paths in (("small", ("plain", "batched")), ("plain256", ("plain", "batched", "batched_adjoint")),
+                            ("batched4096", ("plain", "batched")), ("adjoint1024", ("batched", "batched_adjoint"))):
+            wcfg = S.CONFIGS[name]
+            nw = MIN_WINDOWS * 3
+            wsetup = make_setup(pt, S, dev, sp, wcfg, n_warm + nw)
+            entry = {"workload": describe(wcfg, wsetup["sc"])}
+            for p in paths:
+                if p == "plain":
+                    r = repeat(lambda: plain_run(pt, wsetup, dev, sp, nw * wcfg.T, n_warm * wcfg.T), runs)
+                else:
+                    r = repeat(lambda: windows_run(pt, wsetup, dev, sp, nw, n_warm, refine=p == "batched_adjoint"),
+                               runs)
+                keep = {k: r[k] for k in ("value", "unit", "ms_per_step", "per_step_ms", "runs", "waves_per_workgroup",
+                                          "elites_improved_frac") if k in r}
+                entry[p] = rounded(keep)
+            if "plain" in entry:
+                for p in ("batched", "batched_adjoint"):
+                    if p in entry:
+                        entry[p]["speedup_vs_plain"] = round(entry[p]["value"] / entry["plain"]["value"], 3)
+            wl[name] = entry
+            print(f"bench: {name} done", file=sys.stderr, flush=True)
+        result["workloads"] = wl
 
-    # ---------------- CPU baseline: the FP64 oracle ----------------------
-    if not args.no_cpu_baseline and not args.profile:
-        import oracle
-        nthreads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-        osc = S.make_scene(cfg, steps=args.cpu_sample_steps + 1)
-        tr = oracle.Tracker(osc)
-        c0 = time.perf_counter()
-        for _ in range(args.cpu_sample_steps):
-            tr.step()
-        csec = time.perf_counter() - c0
-        result["cpu_baseline"] = {"value": round(osc.K * args.cpu_sample_steps / csec, 2), "unit": "env-steps/s",
-                                  "cores": nthreads, "kind": "oracle",
-                                  "sample": f"first {args.cpu_sample_steps} steps of the same workload, all {osc.K} "
-                                            f"simulations + {osc.G} observed, FP64 dense-Newton oracle, "
-                                            f"{csec:.1f} s"}
+    # the paper's other optimisers, its identity baseline and the full cost
+    # on the real-time workload (same windows; tracking error is the point)
+    if not args.no_optimizers:
+        opt = {
+            "wrs": {"lambda": WRS_LAMBDA, **windows_run(pt, setup, dev, sp, n_win, n_warm, optimizer="wrs")},
+            "reps": {"epsilon": REPS_EPS, **windows_run(pt, setup, dev, sp, n_win, n_warm, optimizer="reps")},
+            "eye": windows_run(pt, setup, dev, sp, n_win, n_warm, optimizer="eye"),
+            "pbo_no_refinement": batched,
+        }
+        cfg3 = cfg.with_(consts=dataclasses.replace(cfg.consts, cost_mode=1))
+        eq3_setup = make_setup(pt, S, dev, sp, cfg3, n_warm + n_win)
+        w_eq3 = eq3_weights(pt, eq3_setup, dev, sp)
+        cfg3 = cfg3.with_(consts=dataclasses.replace(cfg3.consts, w_eq3=w_eq3))
+        eq3_setup.update(cfg=cfg3, sc=dataclasses.replace(eq3_setup["sc"], cfg=cfg3))
+        opt["pbo_eq3_cost"] = {"w4_w10": [round(x, 4) for x in w_eq3],
+                               **windows_run(pt, eq3_setup, dev, sp, n_win, n_warm, refine=False)}
+        keep = ("lambda", "epsilon", "w4_w10", "value", "tracking_error_mm", "open_loop_tracking_error_mm",
+                "resample_ms_per_window", "per_step_ms")
+        result["optimizers"] = {k: rounded({x: v[x] for x in keep if x in v}) for k, v in opt.items()}
+        print("bench: optimizers done", file=sys.stderr, flush=True)
+
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(S, cfg, args.cpu_sample_steps)
+    result["context"] = ("the paper's only throughput figure: about 30 Hz with 40 simulations on one GTX 1080 Ti "
+                         "(about 1200 env-steps/s, Sec. IV-A), another machine and another simulator")
     print(json.dumps(result), flush=True)
 
 

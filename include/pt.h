@@ -151,8 +151,8 @@ PT_API pt_status pt_create_batch(const pt_batch_desc *desc, pt_batch *out);
  * device); the caller's buffers are untouched.  NULL is accepted. */
 PT_API pt_status pt_destroy_batch(pt_batch b);
 
-/* One world step of all K simulations (Alg. 1: "step simulation" with the
- * same command in every simulation).  u_prev, u: device [D] joint commands
+/* One world step of all K simulations, every one with the same command
+ * (Alg. 1, inner loop).  u_prev, u: device [D] joint commands
  * of the previous and the current step (the hand moves from FK(u_prev) to
  * FK(u) during the step; pass u_prev == u for the first step).  Updates
  * state, params (f_pert consumed) and warm in place and keeps the solved

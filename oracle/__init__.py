@@ -115,6 +115,8 @@ def lib():
         L.or_add.restype = C.c_double
         L.or_window_cost.argtypes = [mp, C.c_int, dp, dp, C.c_void_p, C.c_void_p, C.c_int, dp, dp]
         L.or_window_cost.restype = C.c_double
+        L.or_max_threads.restype = C.c_int
+        L.or_set_threads.argtypes = [C.c_int]
         _lib = L
     return _lib
 
@@ -284,6 +286,15 @@ class Oracle:
                                     _vp(None if wr0 is None else np.ascontiguousarray(wr0, dtype=np.float64)),
                                     T, _dp(np.ascontiguousarray(u_seq, dtype=np.float64)),
                                     _dp(np.ascontiguousarray(obs_gt, dtype=np.float64)))
+
+
+def max_threads():
+    """OpenMP threads the batched oracle calls use."""
+    return int(lib().or_max_threads())
+
+
+def set_threads(n):
+    lib().or_set_threads(int(n))
 
 
 def argmin(v):

@@ -10,6 +10,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 /* ------------------------------------------------------------------ */
 /* small vector / quaternion helpers                                   */
@@ -1148,4 +1151,26 @@ double or_window_cost(const or_model *m, int type, const double *st0, const doub
     }
     free(seg0); free(seg1); free(obs);
     return total;
+}
+
+/* ------------------------------------------------------------------ */
+/* threads (for timing the oracle)                                      */
+/* ------------------------------------------------------------------ */
+
+int or_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+void or_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
 }

@@ -215,4 +215,8 @@ double or_window_cost(const or_model *m, int type, const double *st0, const doub
                       const int32_t *wkey0, const double *wr0, int T,
                       const double *u_seq, const double *obs_gt);
 
+/* OpenMP threads the batched calls use, and a way to set them (timing). */
+int or_max_threads(void);
+void or_set_threads(int n);
+
 #endif

@@ -81,7 +81,8 @@ _lib.pt_refine_elites.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp, C.c_int32, 
 _lib.pt_elite_count.argtypes = [_vp]
 _lib.pt_elite_count.restype = C.c_int32
 for _f in ("pt_create_batch", "pt_destroy_batch", "pt_step", "pt_observe", "pt_cost", "pt_resample",
-           "pt_resample_wrs", "pt_resample_reps", "pt_run_window", "pt_autotune", "pt_read_stats", "pt_set_tuning", "pt_window_grad",
+           "pt_resample_wrs", "pt_resample_reps", "pt_run_window", "pt_autotune",
+           "pt_read_stats", "pt_set_tuning", "pt_window_grad",
            "pt_refine_elites"):
     getattr(_lib, _f).restype = C.c_int
 
@@ -305,8 +306,13 @@ class Batch:
             raise PtError(1, name, f"expected a contiguous {dtype} tensor of shape {tuple(shape)}, "
                                    f"got {t.dtype} {tuple(t.shape)}{'' if t.is_contiguous() else ' (not contiguous)'}")
 
+    def _need_cmd(self, t, shape, name):
+        # a hand without joints (D = 0) reads no commands
+        if self.D > 0:
+            self._need(t, shape, name)
+
     def _need_window(self, u_win, obs_gt_win):
-        self._need(u_win, (self.T + 1, self.D), "u_win")
+        self._need_cmd(u_win, (self.T + 1, self.D), "u_win")
         self._need(obs_gt_win, (self.T, self.obs_rows, self.L, self.G), "obs_gt_win")
 
     # -- the hot path ------------------------------------------------------
@@ -315,8 +321,8 @@ class Batch:
         return torch.zeros(shape, dtype=torch.float32, device=self.device)
 
     def step(self, u_prev, u, stream=None):
-        self._need(u_prev, (self.D,), "u_prev")
-        self._need(u, (self.D,), "u")
+        self._need_cmd(u_prev, (self.D,), "u_prev")
+        self._need_cmd(u, (self.D,), "u")
         pt_step(self.handle, u_prev, u, stream)
 
     def observe(self, obs=None, stream=None):

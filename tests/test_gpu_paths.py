@@ -134,7 +134,7 @@ def test_deep_work_queue_bitwise_and_oracle(pt):
     # the persistent kernel takes several simulations from the work queue
     # one after another, reusing its LDS and registers.  Bit for bit equal
     # to the plain path over two windows with resampling (graph and no
-    # graph), and the first window of 64 sampled simulations against the
+    # graph), and the first window of 256 sampled simulations against the
     # oracle on the clear ones.
     cfg = S.CONFIGS["small"].with_(group_types=(0, 0, 0, 0))
     K, T = 65536, cfg.T
@@ -146,7 +146,7 @@ def test_deep_work_queue_bitwise_and_oracle(pt):
         _assert_same(ref, got, f"K={K} graph={graph}")
         del got
     # the sampled simulations' first window against the oracle
-    idx = np.linspace(0, K - 1, 64).astype(int)
+    idx = np.linspace(0, K - 1, 256).astype(int)
     o = oracle.Oracle.from_scene(sc)
     probes = PU.Probes(o)
     wk, wr = o.new_warm(len(idx))

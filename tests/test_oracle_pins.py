@@ -909,3 +909,19 @@ def test_fixed_n_newton_and_armijo_schedule():
     flat = [x for a in seen for x in a]
     assert n_table >= 80 and len(seen) - n_table >= 60
     assert {1.0, 0.5, 0.125} <= set(flat), set(flat)
+
+
+def test_bench_tracking_error_is_the_oracles_add():
+    # the benchmark's tracking error (ADD of the estimate against the
+    # observed pose, its own numpy code) equals the oracle's ADD
+    import bench
+    cfg = S.CONFIGS["realtime16384"]
+    sc = S.make_scene(cfg, K=16, steps=2)
+    o = oracle.Oracle.from_scene(sc)
+    rng = np.random.default_rng(4)
+    for t in range(sc.spheres.shape[0]):
+        pts = sc.spheres[t, :sc.n_spheres[t], :3]
+        for _ in range(5):
+            pa = np.concatenate([rng.normal(scale=0.01, size=3), rng.normal(size=4)])
+            pb = np.concatenate([rng.normal(scale=0.01, size=3), rng.normal(size=4)])
+            np.testing.assert_allclose(bench.add_distance(pts, pa, pb), o.add(t, pa, pb), rtol=1e-12)
