@@ -229,6 +229,23 @@ PT_API pt_status pt_resample_reps(pt_batch b, float *cost_sum, int32_t n_steps, 
 PT_API pt_status pt_run_window(pt_batch b, const float *u_win, const float *obs_gt_win, float *cost_sum,
                         int32_t *best, float *obs_out, int32_t graph, pt_stream s);
 
+/* pt_run_window without allocation or graph capture, for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation.  Runs the same kernels as pt_run_window
+ * with graph == 0 and gives the same results bit for bit; the window's
+ * scratch (the work-queue counters and the T x L hand segment records) lives
+ * in a static device array of 256 KiB that every GPU the library runs on
+ * holds until the process ends, instead of in the batch.  The array's
+ * address on a device is resolved when the first batch is created on it.
+ * Limits: T x L <= 4096 (PT_E_UNSUPPORTED beyond, before any launch).  Every
+ * call on a GPU shares that GPU's array: calls that overlap on one GPU (on
+ * different streams, or from different host threads) race and must not be
+ * issued; calls in one stream are ordered and safe.  The counters are
+ * cleared by a kernel at the start of every call.  Arguments, layouts and
+ * errors as pt_run_window. */
+PT_API pt_status pt_run_window_static(pt_batch b, const float *u_win, const float *obs_gt_win, float *cost_sum,
+                                      int32_t *best, float *obs_out, pt_stream s);
+
 /* Chooses the persistent kernel's environments per workgroup (waves per
  * workgroup, {1,2,4,8}; at most 4 with the float64 solve) by timing windows
  * on scratch copies of the state; the widest choice is kept unless a

@@ -6,6 +6,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -48,6 +49,43 @@ struct GraphKey {
     }
 };
 
+// Scratch of pt_run_window_static, for callers that cannot allocate: the
+// window's work-queue counters (the first 256 bytes) and its hand segment
+// records, T x L of them at most.  Every GPU the library runs on holds its
+// own copy until the process ends; host code never uses the array's name
+// as an address, only the per-device address hipGetSymbolAddress returns.
+constexpr size_t STATIC_COUNTER_INTS = 64;
+constexpr size_t STATIC_SEG_RECORDS = 4096;
+constexpr size_t STATIC_SCRATCH_FLOATS = STATIC_COUNTER_INTS + STATIC_SEG_RECORDS * pt::SEG_STRIDE;
+static __device__ __align__(256) float scratch[STATIC_SCRATCH_FLOATS];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[MAX_DEVICES] = {};
+
+// the scratch array's address on `device` (current), resolved once per device
+hipError_t static_scratch(int device, void **out)
+{
+    if (device < 0 || device >= MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[device] = p;
+    }
+    *out = g_scratch_ptr[device];
+    return hipSuccess;
+}
+
+// n int32 words set to v (a kernel, so that a captured stream records no
+// memset node)
+__global__ void k_fill_i32(int32_t *p, int n, int32_t v)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
 }  // namespace
 
 struct pt_batch_s {
@@ -75,6 +113,7 @@ struct pt_batch_s {
     int32_t *d_elite = nullptr;  // [n_elite]
     float *d_ref = nullptr;      // see refine_layout
     float *d_snap = nullptr;     // [18][K] + [K][C_max][4]: parents' copies for the weighted resamplers
+    void *static_scratch = nullptr; // this device's pt_run_window_static scratch (not owned)
     // caller-owned state
     float *state, *params, *warm;
     // host copies
@@ -268,6 +307,8 @@ pt_status pt_create_batch(const pt_batch_desc *d, pt_batch *out)
 
     HIP_TRY_C(hipGetDevice(&b->device));
     HIP_TRY_C(hipDeviceGetAttribute(&b->num_cu, hipDeviceAttributeMultiprocessorCount, b->device));
+    // this device's copy of pt_run_window_static's scratch, once per device
+    HIP_TRY_C(static_scratch(b->device, &b->static_scratch));
     HIP_TRY_C(set_lds_limits(160 * 1024));
     HIP_TRY_C(set_grad_lds_limits(160 * 1024));
     HIP_TRY_C(set_draw_lds_limits(160 * 1024));
@@ -431,20 +472,22 @@ pt_status pt_resample_reps(pt_batch b, float *cost_sum, int32_t n_steps, uint32_
 // the launches of one window, in stream order
 static pt_status enqueue_window(pt_batch b, const float *u_win, const float *obs_gt_win, float *cost_sum,
                                 int32_t *best, float *obs_out, int wpb, float *state, float *params, float *warm,
-                                float *ckpt, hipStream_t st)
+                                float *ckpt, hipStream_t st, float *seg_win = nullptr, int32_t *queue = nullptr)
 {
     const Consts &P = b->P;
+    if (!seg_win) seg_win = b->d_seg_win;
+    if (!queue) queue = b->d_queue;
     int bpc = 0;
     HIP_TRY(window_occupancy(P, wpb, &bpc));
     if (bpc < 1) return fail(PT_E_UNSUPPORTED, "persistent kernel does not fit with %d waves per workgroup", wpb);
     int want = (P.K + wpb - 1) / wpb;
     int blocks = std::min(want, bpc * b->num_cu);
-    HIP_TRY(launch_hand_fk(b->d_hand, P.L, P.D, P.dt, u_win, u_win + P.D, P.D, P.T, b->d_seg_win, st));
+    HIP_TRY(launch_hand_fk(b->d_hand, P.L, P.D, P.dt, u_win, u_win + P.D, P.D, P.T, seg_win, st));
     // the window kernel's last workgroup puts the work queue back to 0 and,
     // for populations up to FUSED_ARGMIN_MAX, ranks the groups
     const bool fused = best && P.K <= pt::FUSED_ARGMIN_MAX;
-    HIP_TRY(launch_window(P, tables_of(b), b->d_seg_win, state, params, warm, obs_gt_win, cost_sum, obs_out,
-                          b->d_order, b->d_queue, b->d_stats, wpb, blocks, ckpt, b->d_group_start,
+    HIP_TRY(launch_window(P, tables_of(b), seg_win, state, params, warm, obs_gt_win, cost_sum, obs_out,
+                          b->d_order, queue, b->d_stats, wpb, blocks, ckpt, b->d_group_start,
                           fused ? best : nullptr, st));
     if (best && !fused) HIP_TRY(launch_argmin(P.G, b->d_group_start, cost_sum, best, st));
     return PT_OK;
@@ -500,6 +543,27 @@ pt_status pt_run_window(pt_batch b, const float *u_win, const float *obs_gt_win,
     b->graph_used[slot] = ++b->graph_clock;
     HIP_TRY(hipGraphLaunch(b->graph_exec[slot], st));
     return PT_OK;
+}
+
+pt_status pt_run_window_static(pt_batch b, const float *u_win, const float *obs_gt_win, float *cost_sum,
+                               int32_t *best, float *obs_out, pt_stream s)
+{
+    if (!b) return fail(PT_E_ARG, "batch is NULL");
+    if (!u_win || !obs_gt_win || !cost_sum) return fail(PT_E_ARG, "u_win/obs_gt_win/cost_sum is NULL");
+    const Consts &P = b->P;
+    if ((size_t)P.T * P.L > STATIC_SEG_RECORDS)
+        return fail(PT_E_UNSUPPORTED, "T x L = %d x %d exceeds the static scratch's %zu hand segment records", P.T,
+                    P.L, STATIC_SEG_RECORDS);
+    if (!b->static_scratch) return fail(PT_E_STATE, "static scratch not resolved for device %d", b->device);
+    hipStream_t st = (hipStream_t)s;
+    int32_t *queue = static_cast<int32_t *>(b->static_scratch);
+    float *seg_win = static_cast<float *>(b->static_scratch) + STATIC_COUNTER_INTS;
+    // the work-queue and last-workgroup counters start at 0 (the array keeps
+    // whatever the last call on this GPU left)
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, queue, 4, 0);
+    HIP_TRY(hipGetLastError());
+    return enqueue_window(b, u_win, obs_gt_win, cost_sum, best, obs_out, b->wpb, b->state, b->params, b->warm,
+                          b->d_wckpt, st, seg_win, queue);
 }
 
 pt_status pt_autotune(pt_batch b, const float *u_win, const float *obs_gt_win, int32_t *result, pt_stream s)

@@ -73,6 +73,7 @@ _lib.pt_resample.argtypes = [_vp, _vp, C.c_uint32, _vp, _vp]
 _lib.pt_resample_wrs.argtypes = [_vp, _vp, C.c_int32, C.c_uint32, C.c_float, _vp, _vp, _vp]
 _lib.pt_resample_reps.argtypes = [_vp, _vp, C.c_int32, C.c_uint32, C.c_float, _vp, _vp, _vp, _vp]
 _lib.pt_run_window.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, C.c_int32, _vp]
+_lib.pt_run_window_static.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp]
 _lib.pt_autotune.argtypes = [_vp, _vp, _vp, C.POINTER(C.c_int32), _vp]
 _lib.pt_read_stats.argtypes = [_vp, C.POINTER(C.c_int64), _vp]
 _lib.pt_set_tuning.argtypes = [_vp, C.c_int32]
@@ -81,7 +82,7 @@ _lib.pt_refine_elites.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp, C.c_int32, 
 _lib.pt_elite_count.argtypes = [_vp]
 _lib.pt_elite_count.restype = C.c_int32
 for _f in ("pt_create_batch", "pt_destroy_batch", "pt_step", "pt_observe", "pt_cost", "pt_resample",
-           "pt_resample_wrs", "pt_resample_reps", "pt_run_window", "pt_autotune",
+           "pt_resample_wrs", "pt_resample_reps", "pt_run_window", "pt_run_window_static", "pt_autotune",
            "pt_read_stats", "pt_set_tuning", "pt_window_grad",
            "pt_refine_elites"):
     getattr(_lib, _f).restype = C.c_int
@@ -148,6 +149,11 @@ def pt_resample_reps(h, cost_sum, n_steps, window_idx, eps, parent, weights=None
 def pt_run_window(h, u_win, obs_gt_win, cost_sum, best=None, obs_out=None, graph=True, stream=None):
     _check(_lib.pt_run_window(h, _ptr(u_win), _ptr(obs_gt_win), _ptr(cost_sum), _ptr(best), _ptr(obs_out),
                               1 if graph else 0, _stream(stream)), "pt_run_window")
+
+
+def pt_run_window_static(h, u_win, obs_gt_win, cost_sum, best=None, obs_out=None, stream=None):
+    _check(_lib.pt_run_window_static(h, _ptr(u_win), _ptr(obs_gt_win), _ptr(cost_sum), _ptr(best), _ptr(obs_out),
+                                     _stream(stream)), "pt_run_window_static")
 
 
 def pt_autotune(h, u_win, obs_gt_win, stream=None):
@@ -363,6 +369,15 @@ class Batch:
         self._need(best, (self.G,), "best", torch.int32)
         self._need(obs_out, (self.T, self.obs_rows, self.L, self.K), "obs_out")
         pt_run_window(self.handle, u_win, obs_gt_win, cost_sum, best, obs_out, graph, stream)
+
+    def run_window_static(self, u_win, obs_gt_win, cost_sum, best=None, obs_out=None, stream=None):
+        """pt_run_window without allocation or graph capture (scratch in a
+        static device array; see include/pt.h)."""
+        self._need_window(u_win, obs_gt_win)
+        self._need(cost_sum, (self.K,), "cost_sum")
+        self._need(best, (self.G,), "best", torch.int32)
+        self._need(obs_out, (self.T, self.obs_rows, self.L, self.K), "obs_out")
+        pt_run_window_static(self.handle, u_win, obs_gt_win, cost_sum, best, obs_out, stream)
 
     def autotune(self, u_win, obs_gt_win, stream=None):
         self._need_window(u_win, obs_gt_win)
