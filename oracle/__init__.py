@@ -46,6 +46,7 @@ class Model(C.Structure):
         ("n_spheres", C.POINTER(C.c_int32)), ("inv_inertia", C.POINTER(C.c_double)),
         ("cost_mode", C.c_int32), ("tau_slip", C.c_double), ("tau_spin", C.c_double), ("w_eq3", C.c_double * 7),
         ("geom_f32", C.c_int32),
+        ("kp", C.c_double), ("kd", C.c_double), ("link_mass", C.c_double), ("w_q", C.c_double),
     ]
 
 
@@ -115,6 +116,12 @@ def lib():
         L.or_add.restype = C.c_double
         L.or_window_cost.argtypes = [mp, C.c_int, dp, dp, C.c_void_p, C.c_void_p, C.c_int, dp, dp]
         L.or_window_cost.restype = C.c_double
+        L.or_env_step_pd.argtypes = [mp, dp, C.c_int, dp, dp, dp, ip, dp, C.c_void_p, C.c_void_p]
+        L.or_env_step_pd.restype = C.c_int
+        L.or_hand_mass.argtypes = [mp, dp, dp]
+        L.or_batch_step_pd.argtypes = [mp, C.c_int, ip, dp, dp, dp, dp, ip, dp, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.or_step_cost_pd.argtypes = [mp, dp, dp, dp, dp]
+        L.or_step_cost_pd.restype = C.c_double
         L.or_max_threads.restype = C.c_int
         L.or_set_threads.argtypes = [C.c_int]
         _lib = L
@@ -169,6 +176,9 @@ class Oracle:
             m.w_eq3[i] = wv
         # diagnostic: geometry rounded to float32 (see oracle.h)
         m.geom_f32 = int(geom_f32)
+        m.kp, m.kd = getattr(consts, "kp", 1.5), getattr(consts, "kd", 0.05)
+        m.link_mass, m.w_q = getattr(consts, "link_mass", 0.03), getattr(consts, "w_q", 100.0)
+        self.hand_mode = int(getattr(consts, "hand_mode", 0))
         m.hand = _dp(self.hand)
         m.spheres = _dp(self.spheres)
         m.n_spheres = _ip(self.n_spheres)
@@ -235,6 +245,44 @@ class Oracle:
                  _dp(np.ascontiguousarray(obs_gt, dtype=np.float64)))
 
     # -- batch -----------------------------------------------------------
+    # -- PD-controlled hand ------------------------------------------------
+    def hand_mass(self, q):
+        M = np.zeros((self.D, self.D))
+        lib().or_hand_mass(C.byref(self.m), _dp(np.ascontiguousarray(q, dtype=np.float64)), _dp(M))
+        return M
+
+    def env_step_pd(self, u, typ, st, pr, hq, wkey, wr):
+        """In-place PD-hand step of one env (hq = [q, qdot]); returns
+        (contacts, diag)."""
+        cont = np.zeros(self.C_max, dtype=CONTACT_DTYPE)
+        dg = np.zeros(1, dtype=DIAG_DTYPE)
+        nc = lib().or_env_step_pd(C.byref(self.m), _dp(np.ascontiguousarray(u, dtype=np.float64)), int(typ), _dp(st),
+                                  _dp(pr), _dp(hq), _ip(wkey), _dp(wr), _vp(cont), _vp(dg))
+        return cont[:nc], dg[0]
+
+    def batch_step_pd(self, env_type, u, state, params, hstate, wkey, wr, want_contacts=False, want_diag=False):
+        """In-place PD-hand step of K envs; returns (obs [K][L][4], contacts,
+        diag); the joint angles are hstate[:, :D]."""
+        K = state.shape[0]
+        obs = np.zeros((K, self.L, 4))
+        cont = np.zeros((K, self.C_max), dtype=CONTACT_DTYPE) if want_contacts else None
+        dg = np.zeros(K, dtype=DIAG_DTYPE) if want_diag else None
+        lib().or_batch_step_pd(C.byref(self.m), K, _ip(env_type), _dp(np.ascontiguousarray(u, dtype=np.float64)),
+                               _dp(state), _dp(params), _dp(hstate), _ip(wkey), _dp(wr), _vp(cont), _vp(dg), _vp(obs))
+        return obs, cont, dg
+
+    def step_cost_pd(self, obs, q, obs_gt, q_gt):
+        return lib().or_step_cost_pd(C.byref(self.m), _dp(np.ascontiguousarray(obs, dtype=np.float64)),
+                                     _dp(np.ascontiguousarray(q, dtype=np.float64)),
+                                     _dp(np.ascontiguousarray(obs_gt, dtype=np.float64)),
+                                     _dp(np.ascontiguousarray(q_gt, dtype=np.float64)))
+
+    def new_hand(self, K, u0):
+        """Hand state [K][2D] at rest at the command u0."""
+        h = np.zeros((K, 2 * self.D))
+        h[:, :self.D] = np.asarray(u0, dtype=np.float64)
+        return h
+
     def new_warm(self, K):
         return np.full((K, self.C_max), -1, dtype=np.int32), np.zeros((K, self.C_max, 3))
 
@@ -338,15 +386,31 @@ class Tracker:
         self.rcfg = resample_cfg(scene.cfg)
         self.t = 0
         self.window = 0
+        self.pd = self.o.hand_mode == 1
+        if self.pd:
+            # the hands start at rest at the first command
+            self.hand = self.o.new_hand(scene.K, scene.u[0])
+            self.hhand = self.o.new_hand(scene.G, scene.u[0])
 
     def step(self, want=False):
         s = self.scene
         u_prev = s.u[max(self.t - 1, 0)]
         u = s.u[self.t]
-        obs_gt, _, _ = self.o.batch_step(s.hidden_type, u_prev, u, self.hstate, self.hparams, self.hkey, self.hr)
-        obs, cont, dg = self.o.batch_step(s.env_type, u_prev, u, self.state, self.params, self.wkey, self.wr,
-                                          want_contacts=want, want_diag=want)
-        self.o.batch_cost(s.group_start, obs, obs_gt, self.cost_sum)
+        if self.pd:
+            obs_gt, _, _ = self.o.batch_step_pd(s.hidden_type, u, self.hstate, self.hparams, self.hhand, self.hkey,
+                                                self.hr)
+            obs, cont, dg = self.o.batch_step_pd(s.env_type, u, self.state, self.params, self.hand, self.wkey,
+                                                 self.wr, want_contacts=want, want_diag=want)
+            D = self.o.D
+            for g in range(s.G):
+                for i in range(s.group_start[g], s.group_start[g + 1]):
+                    self.cost_sum[i] += self.o.step_cost_pd(obs[i], self.hand[i, :D], obs_gt[g], self.hhand[g, :D])
+        else:
+            obs_gt, _, _ = self.o.batch_step(s.hidden_type, u_prev, u, self.hstate, self.hparams, self.hkey,
+                                             self.hr)
+            obs, cont, dg = self.o.batch_step(s.env_type, u_prev, u, self.state, self.params, self.wkey, self.wr,
+                                              want_contacts=want, want_diag=want)
+            self.o.batch_cost(s.group_start, obs, obs_gt, self.cost_sum)
         best = [s.group_start[g] + argmin(self.cost_sum[s.group_start[g]:s.group_start[g + 1]])
                 for g in range(s.G)]
         self.t += 1
@@ -354,5 +418,10 @@ class Tracker:
         if self.t % s.cfg.T == 0:
             parent = self.o.resample(self.rcfg, s.group_start, self.window, self.cost_sum, self.state, self.params,
                                      self.wkey, self.wr)
+            if self.pd:
+                # a copy takes its parent's hand with its body (parents are
+                # elites, which the resampler leaves unchanged)
+                for j in np.nonzero(parent >= 0)[0]:
+                    self.hand[j] = self.hand[parent[j]]
             self.window += 1
         return dict(obs=obs, obs_gt=obs_gt, best=best, contacts=cont, diag=dg, parent=parent)

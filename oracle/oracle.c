@@ -566,24 +566,22 @@ int or_env_system(const or_model *m, const double *seg0, const double *seg1, int
     return y.C;
 }
 
-int or_env_step(const or_model *m, const double *seg0, const double *seg1, int type,
-                double *st, double *pr, int32_t *wkey, double *wr,
-                or_contact *cont_out, or_diag *dg)
+/* Step 10 of the model: warm start from the previous impulses of the same
+ * keys, then the smoothed Fischer-Burmeister Newton iteration with the
+ * Armijo schedule (fixed N, or until converged).  r [3C] receives the
+ * impulses; the diagnostics go to nd. */
+typedef struct {
+    int iters, nfull, nfall;
+    double psi_first, psi, armijo_margin;
+} newton_diag;
+
+static void newton_solve(const or_model *m, int C, double mu, double mass, const or_contact *cc, const double *W,
+                         const double *uf, const int32_t *wkey, const double *wr, double *r, newton_diag *nd)
 {
     const int Cmax = m->C_max;
     const double dt = m->dt;
-    const double *inv = m->inv_inertia + 3 * type;
-    sys_t y;
-    build_system(m, seg0, seg1, type, st, pr, &y);
-    const double mass = y.mass, mu = y.mu;
-    const double *x = y.x, *q = y.q, *R = y.R, *Iinv = y.Iinv, *vs = y.vs, *ws = y.ws;
-    const int C = y.C, ncand = y.ncand;
-    or_contact *cc = y.cc;
-    const double *J = y.J, *uf = y.uf, *W = y.W;
     int n3 = 3 * C;
-
-    /* 10. warm start and Newton */
-    double *r = (double *)calloc((size_t)(n3 > 0 ? n3 : 1), sizeof(double));
+    for (int i = 0; i < n3; ++i) r[i] = 0.0;
     for (int c = 0; c < C; ++c)
         for (int j = 0; j < Cmax; ++j)
             if (wkey[j] == cc[c].key) {
@@ -652,6 +650,37 @@ int or_env_step(const or_model *m, const double *seg0, const double *seg1, int t
         psi = merit(m, C, mu, W, uf, r, u);
     }
 
+    nd->iters = iters;
+    nd->nfull = nfull;
+    nd->nfall = nfall;
+    nd->psi_first = psi_first;
+    nd->psi = psi;
+    nd->armijo_margin = armijo_margin;
+    free(u); free(A); free(Phi); free(dr); free(rt);
+}
+
+int or_env_step(const or_model *m, const double *seg0, const double *seg1, int type,
+                double *st, double *pr, int32_t *wkey, double *wr,
+                or_contact *cont_out, or_diag *dg)
+{
+    const int Cmax = m->C_max;
+    const double dt = m->dt;
+    const double *inv = m->inv_inertia + 3 * type;
+    sys_t y;
+    build_system(m, seg0, seg1, type, st, pr, &y);
+    const double mass = y.mass, mu = y.mu;
+    const double *x = y.x, *q = y.q, *R = y.R, *Iinv = y.Iinv, *vs = y.vs, *ws = y.ws;
+    const int C = y.C, ncand = y.ncand;
+    or_contact *cc = y.cc;
+    const double *J = y.J, *uf = y.uf, *W = y.W;
+    int n3 = 3 * C;
+
+    /* 10. warm start and Newton */
+    double *r = (double *)calloc((size_t)(n3 > 0 ? n3 : 1), sizeof(double));
+    double *u = (double *)calloc((size_t)(n3 > 0 ? n3 : 1), sizeof(double));
+    newton_diag nd;
+    newton_solve(m, C, mu, mass, cc, W, uf, wkey, wr, r, &nd);
+
     /* 11. integrate */
     double dv[3] = {0, 0, 0}, dL[3] = {0, 0, 0};
     for (int c = 0; c < C; ++c)
@@ -710,21 +739,428 @@ int or_env_step(const or_model *m, const double *seg0, const double *seg1, int t
     if (dg) {
         dg->n_candidates = ncand;
         dg->n_contacts = C;
-        dg->iters = iters;
-        dg->n_full_steps = nfull;
-        dg->psi_first = psi_first;
-        dg->psi_final = psi;
+        dg->iters = nd.iters;
+        dg->n_full_steps = nd.nfull;
+        dg->psi_first = nd.psi_first;
+        dg->psi_final = nd.psi;
         dg->d_last_kept = y.d_last_kept;
         dg->d_first_dropped = y.d_first_dropped;
-        dg->armijo_margin = armijo_margin;
+        dg->armijo_margin = nd.armijo_margin;
         dg->tangent_tie = y.tangent_tie;
         dg->margin_gap = y.margin_gap;
-        dg->n_fallback = nfall;
+        dg->n_fallback = nd.nfall;
         dg->reserved = 0;
     }
-    free(r); free(u); free(A); free(Phi); free(dr); free(rt);
+    free(r); free(u);
     sys_free(&y);
     return C;
+}
+
+/* ------------------------------------------------------------------ */
+/* PD-controlled articulated hand (hand_mode 1)                         */
+/* ------------------------------------------------------------------ */
+
+/* The hand at joint angles q: per link its frame rotation Rl, origin ol,
+ * tip bl and centre of mass (the segment midpoint); per joint its world axis
+ * and origin (the origin of the link it turns); chain[l][j] = 1 when joint j
+ * moves link l (its own joints and its ancestors'). */
+typedef struct {
+    double *R, *o, *b, *com; /* [L][9], [L][3] x 3 */
+    double *axis, *jo;       /* [D][3] */
+    unsigned char *chain;    /* [L][D] */
+} hand_kin;
+
+static void hand_kin_alloc(const or_model *m, hand_kin *hk)
+{
+    size_t L = (size_t)m->L, D = (size_t)(m->D > 0 ? m->D : 1);
+    hk->R = (double *)calloc(L * 9, sizeof(double));
+    hk->o = (double *)calloc(L * 3, sizeof(double));
+    hk->b = (double *)calloc(L * 3, sizeof(double));
+    hk->com = (double *)calloc(L * 3, sizeof(double));
+    hk->axis = (double *)calloc(D * 3, sizeof(double));
+    hk->jo = (double *)calloc(D * 3, sizeof(double));
+    hk->chain = (unsigned char *)calloc(L * D, 1);
+}
+
+static void hand_kin_free(hand_kin *hk)
+{
+    free(hk->R); free(hk->o); free(hk->b); free(hk->com); free(hk->axis); free(hk->jo); free(hk->chain);
+}
+
+static void hand_kinematics_pd(const or_model *m, const double *q, hand_kin *hk)
+{
+    int L = m->L, D = m->D;
+    double *tipq = (double *)malloc(sizeof(double) * 4 * (size_t)L);
+    for (int l = 0; l < L; ++l) {
+        const double *h = m->hand + (size_t)l * OR_HAND_STRIDE;
+        int parent = (int)h[0], j0 = (int)h[1], j1 = (int)h[2];
+        double pq[4] = {1, 0, 0, 0}, pp[3] = {0, 0, 0};
+        unsigned char *ch = hk->chain + (size_t)l * D;
+        if (parent >= 0) {
+            memcpy(pq, tipq + 4 * parent, sizeof pq);
+            memcpy(pp, hk->b + 3 * parent, sizeof pp);
+            memcpy(ch, hk->chain + (size_t)parent * D, (size_t)D);
+        }
+        double Rp[9];
+        qmat(pq, Rp);
+        double off[3];
+        matvec(Rp, h + 9, off);
+        double *o = hk->o + 3 * l;
+        o[0] = pp[0] + off[0]; o[1] = pp[1] + off[1]; o[2] = pp[2] + off[2];
+        double qf[4];
+        qmul(pq, h + 12, qf);
+        const int js[2] = {j0, j1};
+        for (int k = 0; k < 2; ++k) {
+            int j = js[k];
+            if (j < 0) continue;
+            const double *ax = h + 3 + 3 * k;
+            double Rf[9];
+            qmat(qf, Rf);
+            matvec(Rf, ax, hk->axis + 3 * j);
+            memcpy(hk->jo + 3 * j, o, 3 * sizeof(double));
+            ch[j] = 1;
+            double qj[4], t[4];
+            qaxis(ax, q[j], qj);
+            qmul(qf, qj, t);
+            memcpy(qf, t, sizeof qf);
+        }
+        double *R = hk->R + 9 * l;
+        qmat(qf, R);
+        double len = h[16];
+        for (int i = 0; i < 3; ++i) {
+            hk->b[3 * l + i] = o[i] + len * R[3 * i];
+            hk->com[3 * l + i] = o[i] + 0.5 * len * R[3 * i];
+        }
+        memcpy(tipq + 4 * l, qf, sizeof qf);
+    }
+    free(tipq);
+}
+
+/* Joint-space mass matrix M(q) [D][D]: sum over links of
+ * m J_v^T J_v + J_w^T I_w J_w with J_w[:, j] = axis_j and
+ * J_v[:, j] = axis_j x (com - origin_j) over the link's chain; a link is a
+ * solid cylinder of the hand's link mass (axial inertia m R^2 / 2,
+ * transverse m (3 R^2 + len^2) / 12 about its centre). */
+static void hand_mass(const or_model *m, const hand_kin *hk, double *M)
+{
+    int L = m->L, D = m->D;
+    memset(M, 0, sizeof(double) * (size_t)D * D);
+    double ml = m->link_mass;
+    for (int l = 0; l < L; ++l) {
+        const double *h = m->hand + (size_t)l * OR_HAND_STRIDE;
+        double len = h[16], rad = h[17];
+        double Ib[3] = {0.5 * ml * rad * rad, ml * (3 * rad * rad + len * len) / 12.0,
+                        ml * (3 * rad * rad + len * len) / 12.0};
+        const double *R = hk->R + 9 * l;
+        double Iw[9];
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) {
+                double s_ = 0;
+                for (int k = 0; k < 3; ++k) s_ += R[3 * i + k] * Ib[k] * R[3 * j + k];
+                Iw[3 * i + j] = s_;
+            }
+        const unsigned char *ch = hk->chain + (size_t)l * D;
+        const double *c = hk->com + 3 * l;
+        for (int i = 0; i < D; ++i) {
+            if (!ch[i]) continue;
+            double ri[3] = {c[0] - hk->jo[3 * i], c[1] - hk->jo[3 * i + 1], c[2] - hk->jo[3 * i + 2]}, vi[3];
+            cross3(hk->axis + 3 * i, ri, vi);
+            double Iwi[3];
+            matvec(Iw, hk->axis + 3 * i, Iwi);
+            for (int j = 0; j < D; ++j) {
+                if (!ch[j]) continue;
+                double rj[3] = {c[0] - hk->jo[3 * j], c[1] - hk->jo[3 * j + 1], c[2] - hk->jo[3 * j + 2]}, vj[3];
+                cross3(hk->axis + 3 * j, rj, vj);
+                M[(size_t)i * D + j] += ml * dot3(vi, vj) + dot3(hk->axis + 3 * j, Iwi);
+            }
+        }
+    }
+}
+
+void or_hand_mass(const or_model *m, const double *q, double *M)
+{
+    hand_kin hk;
+    hand_kin_alloc(m, &hk);
+    hand_kinematics_pd(m, q, &hk);
+    hand_mass(m, &hk, M);
+    hand_kin_free(&hk);
+}
+
+/* inverse of an n x n matrix by LU with partial pivoting on the identity */
+static int mat_inverse(int n, const double *A, double *Ainv)
+{
+    double *T = (double *)malloc(sizeof(double) * (size_t)n * n);
+    double *e = (double *)malloc(sizeof(double) * (size_t)n);
+    int rc = 0;
+    for (int col = 0; col < n && rc == 0; ++col) {
+        memcpy(T, A, sizeof(double) * (size_t)n * n);
+        for (int i = 0; i < n; ++i) e[i] = i == col ? 1.0 : 0.0;
+        rc = lu_solve(n, T, e);
+        for (int i = 0; i < n; ++i) Ainv[(size_t)i * n + col] = e[i];
+    }
+    free(T);
+    free(e);
+    return rc;
+}
+
+/* One step of one environment with the PD-controlled hand: the object's
+ * steps 1-9 and 11 of the model, with the hand's joint rates as further
+ * degrees of freedom.  Generalised velocity nu = (v, w, qdot) (6 + D); the
+ * hand's implicit PD law gives (M + dt kd I + dt^2 kp I) qdot+ =
+ * M qdot + dt kp (u - q) + (contact impulses), q+ = q + dt qdot+.  A
+ * contact between sphere k and link l at the object's contact point p has
+ * the Jacobian rows F [I, -(p - x)^, -G_l(p)] with G_l(p)[:, j] =
+ * axis_j x (p - origin_j) over the link's chain (the velocity of the
+ * object's point relative to the link's material point at p); the table's
+ * rows have no hand columns.  hq [2D]: q, qdot, updated in place. */
+int or_env_step_pd(const or_model *m, const double *u_cmd, int type, double *st, double *pr, double *hq,
+                   int32_t *wkey, double *wr, or_contact *cont_out, or_diag *dg)
+{
+    const int L = m->L, D = m->D, Cmax = m->C_max;
+    const int nd = 6 + D;
+    const double dt = m->dt;
+    const double mass = pr[0], mu = pr[1];
+    const double *fp = pr + 2;
+    const double *inv = m->inv_inertia + 3 * type;
+    const int S = m->n_spheres[type];
+    const double *sph = m->spheres + (size_t)type * m->S_max * 4;
+    const double *qh = hq, *qdh = hq + D;
+
+    /* object pose, rotation, inverse inertia, free velocity */
+    double x[3] = {st[0], st[1], st[2]}, q[4] = {st[3], st[4], st[5], st[6]}, R[9];
+    qnormalize(q);
+    qmat(q, R);
+    double Iinv[9];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            double s_ = 0;
+            for (int k = 0; k < 3; ++k) s_ += R[3 * i + k] * (inv[k] / mass) * R[3 * j + k];
+            Iinv[3 * i + j] = s_;
+        }
+    double *nus = (double *)calloc((size_t)nd, sizeof(double));
+    double *nup = (double *)calloc((size_t)nd, sizeof(double));
+    for (int i = 0; i < 3; ++i) {
+        nus[i] = st[7 + i] + dt * (m->gravity[i] + fp[i] / mass);
+        nus[3 + i] = st[10 + i];
+    }
+
+    /* hand: kinematics at q, mass matrix, PD-implicit effective mass and
+     * free joint rates */
+    hand_kin hk;
+    hand_kin_alloc(m, &hk);
+    hand_kinematics_pd(m, qh, &hk);
+    double *Mh = (double *)calloc((size_t)(D > 0 ? D * D : 1), sizeof(double));
+    double *Ah = (double *)calloc((size_t)(D > 0 ? D * D : 1), sizeof(double));
+    double *Ahinv = (double *)calloc((size_t)(D > 0 ? D * D : 1), sizeof(double));
+    hand_mass(m, &hk, Mh);
+    for (int i = 0; i < D * D; ++i) Ah[i] = Mh[i];
+    for (int i = 0; i < D; ++i) Ah[(size_t)i * D + i] += dt * m->kd + dt * dt * m->kp;
+    if (D > 0) mat_inverse(D, Ah, Ahinv);
+    {
+        double *pmom = (double *)calloc((size_t)(D > 0 ? D : 1), sizeof(double));
+        for (int i = 0; i < D; ++i) {
+            double s_ = dt * m->kp * (u_cmd[i] - qh[i]);
+            for (int j = 0; j < D; ++j) s_ += Mh[(size_t)i * D + j] * qdh[j];
+            pmom[i] = s_;
+        }
+        for (int i = 0; i < D; ++i) {
+            double s_ = 0;
+            for (int j = 0; j < D; ++j) s_ += Ahinv[(size_t)i * D + j] * pmom[j];
+            nus[6 + i] = s_;
+        }
+        free(pmom);
+    }
+
+    /* segments of the links at q (velocities enter through the Jacobian) */
+    double *seg = (double *)malloc(sizeof(double) * 6 * (size_t)L);
+    for (int l = 0; l < L; ++l)
+        for (int i = 0; i < 3; ++i) {
+            seg[6 * l + i] = hk.o[3 * l + i];
+            seg[6 * l + 3 + i] = hk.b[3 * l + i];
+        }
+
+    /* candidates and the cap, as in the kinematic model */
+    int npair = S * (L + 1);
+    cand_t *cand = (cand_t *)malloc(sizeof(cand_t) * (size_t)(npair > 0 ? npair : 1));
+    int ncand = 0;
+    double margin_gap = INFINITY;
+    for (int k = 0; k < S; ++k) {
+        double c[3];
+        matvec(R, sph + 4 * k, c);
+        c[0] += x[0]; c[1] += x[1]; c[2] += x[2];
+        for (int l = 0; l <= L; ++l) {
+            double d, n[3], p[3], vl[3];
+            pair_geometry(m, seg, seg, l, c, sph[4 * k + 3], &d, n, p, vl);
+            if (fabs(d - m->margin) < margin_gap) margin_gap = fabs(d - m->margin);
+            if (d < m->margin) {
+                cand[ncand].d = d;
+                cand[ncand].key = k * (L + 1) + l;
+                ++ncand;
+            }
+        }
+    }
+    qsort(cand, (size_t)ncand, sizeof(cand_t), cand_cmp);
+    int C = ncand < Cmax ? ncand : Cmax;
+    int n3 = 3 * C;
+    or_contact *cc = (or_contact *)calloc((size_t)(C > 0 ? C : 1), sizeof(or_contact));
+    double *J = (double *)calloc((size_t)(n3 > 0 ? n3 : 1) * nd, sizeof(double));
+    double *uf = (double *)calloc((size_t)(n3 > 0 ? n3 : 1), sizeof(double));
+    for (int c = 0; c < C; ++c) {
+        int key = cand[c].key;
+        int k = key / (L + 1), l = key % (L + 1);
+        double ctr[3];
+        matvec(R, sph + 4 * k, ctr);
+        ctr[0] += x[0]; ctr[1] += x[1]; ctr[2] += x[2];
+        or_contact *o_ = cc + c;
+        o_->key = key;
+        o_->link = l;
+        pair_geometry(m, seg, seg, l, ctr, sph[4 * k + 3], &o_->d, o_->n, o_->p, o_->vlink);
+        tangent_frame(o_->n, o_->t1, o_->t2);
+        double rho[3] = {o_->p[0] - x[0], o_->p[1] - x[1], o_->p[2] - x[2]};
+        const double *dirs[3] = {o_->n, o_->t1, o_->t2};
+        for (int i = 0; i < 3; ++i) {
+            double *row = J + (size_t)(3 * c + i) * nd;
+            double rc[3];
+            cross3(rho, dirs[i], rc);
+            row[0] = dirs[i][0]; row[1] = dirs[i][1]; row[2] = dirs[i][2];
+            row[3] = rc[0]; row[4] = rc[1]; row[5] = rc[2];
+            if (l < L) {
+                const unsigned char *ch = hk.chain + (size_t)l * D;
+                for (int j = 0; j < D; ++j) {
+                    if (!ch[j]) continue;
+                    double rj[3] = {o_->p[0] - hk.jo[3 * j], o_->p[1] - hk.jo[3 * j + 1], o_->p[2] - hk.jo[3 * j + 2]};
+                    double g[3];
+                    cross3(hk.axis + 3 * j, rj, g);
+                    row[6 + j] = -dot3(dirs[i], g);
+                }
+            }
+            double s_ = 0;
+            for (int t = 0; t < nd; ++t) s_ += row[t] * nus[t];
+            uf[3 * c + i] = s_;
+        }
+        uf[3 * c] += o_->d >= 0 ? o_->d / dt : m->erp * o_->d / dt;
+    }
+    /* inverse generalised mass blockdiag(I3 / m, I_w^-1, A_h^-1) and
+     * W = J M^-1 J^T + eps I */
+    double *Minv = (double *)calloc((size_t)nd * nd, sizeof(double));
+    for (int i = 0; i < 3; ++i) Minv[(size_t)i * nd + i] = 1.0 / mass;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) Minv[(size_t)(3 + i) * nd + 3 + j] = Iinv[3 * i + j];
+    for (int i = 0; i < D; ++i)
+        for (int j = 0; j < D; ++j) Minv[(size_t)(6 + i) * nd + 6 + j] = Ahinv[(size_t)i * D + j];
+    double *MJt = (double *)calloc((size_t)nd * (n3 > 0 ? n3 : 1), sizeof(double)); /* [nd][3C] */
+    for (int a = 0; a < nd; ++a)
+        for (int c = 0; c < n3; ++c) {
+            double s_ = 0;
+            for (int t = 0; t < nd; ++t) s_ += Minv[(size_t)a * nd + t] * J[(size_t)c * nd + t];
+            MJt[(size_t)a * n3 + c] = s_;
+        }
+    double *W = (double *)calloc((size_t)(n3 > 0 ? n3 * n3 : 1), sizeof(double));
+    for (int i = 0; i < n3; ++i)
+        for (int j = 0; j < n3; ++j) {
+            double s_ = 0;
+            for (int t = 0; t < nd; ++t) s_ += J[(size_t)i * nd + t] * MJt[(size_t)t * n3 + j];
+            W[(size_t)i * n3 + j] = s_ + (i == j ? m->compliance : 0.0);
+        }
+
+    /* the contact solve */
+    double *r = (double *)calloc((size_t)(n3 > 0 ? n3 : 1), sizeof(double));
+    newton_diag ndg;
+    newton_solve(m, C, mu, mass, cc, W, uf, wkey, wr, r, &ndg);
+
+    /* integrate: nu+ = nu* + M^-1 J^T r */
+    for (int a = 0; a < nd; ++a) {
+        double s_ = nus[a];
+        for (int c = 0; c < n3; ++c) s_ += MJt[(size_t)a * n3 + c] * r[c];
+        nup[a] = s_;
+    }
+    double xn[3] = {x[0] + dt * nup[0], x[1] + dt * nup[1], x[2] + dt * nup[2]};
+    double th[3] = {dt * nup[3], dt * nup[4], dt * nup[5]};
+    double eq[4], qn[4];
+    qexp(th, eq);
+    qmul(eq, q, qn);
+    qnormalize(qn);
+    double wb[3], hb[3], hmom[3], Rn[9], hn[3], wn[3];
+    mattvec(R, nup + 3, wb);
+    for (int i = 0; i < 3; ++i) hb[i] = inv[i] > 0 ? wb[i] * mass / inv[i] : 0.0;
+    matvec(R, hb, hmom);
+    qmat(qn, Rn);
+    mattvec(Rn, hmom, hn);
+    for (int i = 0; i < 3; ++i) hn[i] *= inv[i] / mass;
+    matvec(Rn, hn, wn);
+    st[0] = xn[0]; st[1] = xn[1]; st[2] = xn[2];
+    st[3] = qn[0]; st[4] = qn[1]; st[5] = qn[2]; st[6] = qn[3];
+    st[7] = nup[0]; st[8] = nup[1]; st[9] = nup[2];
+    st[10] = wn[0]; st[11] = wn[1]; st[12] = wn[2];
+    pr[2] = pr[3] = pr[4] = 0.0;
+    for (int j = 0; j < D; ++j) {
+        hq[D + j] = nup[6 + j];
+        hq[j] = qh[j] + dt * nup[6 + j];
+    }
+
+    /* warm cache and outputs */
+    for (int j = 0; j < Cmax; ++j) {
+        wkey[j] = -1;
+        wr[3 * j] = wr[3 * j + 1] = wr[3 * j + 2] = 0;
+    }
+    for (int c = 0; c < C; ++c) {
+        wkey[c] = cc[c].key;
+        wr[3 * c] = r[3 * c]; wr[3 * c + 1] = r[3 * c + 1]; wr[3 * c + 2] = r[3 * c + 2];
+    }
+    if (cont_out) {
+        double *uu = (double *)calloc((size_t)(n3 > 0 ? n3 : 1), sizeof(double));
+        if (C > 0) apply_W(n3, W, r, uf, uu);
+        for (int c = 0; c < C; ++c) {
+            for (int i = 0; i < 3; ++i) { cc[c].r[i] = r[3 * c + i]; cc[c].u[i] = uu[3 * c + i]; }
+            cont_out[c] = cc[c];
+        }
+        free(uu);
+    }
+    if (dg) {
+        memset(dg, 0, sizeof *dg);
+        dg->n_candidates = ncand;
+        dg->n_contacts = C;
+        dg->iters = ndg.iters;
+        dg->n_full_steps = ndg.nfull;
+        dg->psi_first = ndg.psi_first;
+        dg->psi_final = ndg.psi;
+        dg->d_last_kept = C > 0 ? cand[C - 1].d : -INFINITY;
+        dg->d_first_dropped = ncand > C ? cand[C].d : INFINITY;
+        dg->armijo_margin = ndg.armijo_margin;
+        dg->tangent_tie = INFINITY;
+        dg->margin_gap = margin_gap;
+        dg->n_fallback = ndg.nfall;
+    }
+    free(cand); free(cc); free(J); free(uf); free(Minv); free(MJt); free(W); free(r); free(seg);
+    free(Mh); free(Ah); free(Ahinv); free(nus); free(nup);
+    hand_kin_free(&hk);
+    return C;
+}
+
+double or_step_cost_pd(const or_model *m, const double *obs, const double *qo, const double *obs_gt,
+                       const double *q_gt)
+{
+    double s_ = or_step_cost(m, obs, obs_gt);
+    for (int j = 0; j < m->D; ++j) s_ += m->w_q * (qo[j] - q_gt[j]) * (qo[j] - q_gt[j]);
+    return s_;
+}
+
+void or_batch_step_pd(const or_model *m, int K, const int32_t *env_type, const double *u, double *state,
+                      double *params, double *hstate, int32_t *wkey, double *wr, or_contact *cont, or_diag *diag,
+                      double *obs)
+{
+    int L = m->L, Cmax = m->C_max, D = m->D;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int i = 0; i < K; ++i) {
+        or_contact local[OR_MAX_CMAX];
+        or_contact *cp = cont ? cont + (size_t)i * Cmax : local;
+        int nc = or_env_step_pd(m, u, env_type[i], state + 13 * (size_t)i, params + 5 * (size_t)i,
+                                hstate + 2 * (size_t)D * i, wkey + (size_t)i * Cmax, wr + (size_t)i * Cmax * 3, cp,
+                                diag ? diag + i : NULL);
+        if (cont)
+            for (int c = nc; c < Cmax; ++c) { memset(cp + c, 0, sizeof(or_contact)); cp[c].key = -1; }
+        if (obs) or_observe(m, nc, cp, obs + (size_t)i * L * 4);
+    }
 }
 
 /* ------------------------------------------------------------------ */

@@ -69,6 +69,9 @@ typedef struct {
                                 * far a step's result moves under such rounding;
                                 * 2: also move each rounded value one float32
                                 * step, up or down by a hash of its bits */
+    /* PD-controlled hand (or_env_step_pd): joint gains, the mass of every
+     * capsule link and the weight of the joint-angle term of the cost */
+    double kp, kd, link_mass, w_q;
 } or_model;
 
 typedef struct {
@@ -139,6 +142,35 @@ void or_observe(const or_model *m, int nc, const or_contact *cont, double *obs);
 
 /* Step cost of one simulation's observation against the observed one. */
 double or_step_cost(const or_model *m, const double *obs, const double *obs_gt);
+
+/* PD-controlled hand (the hand's joints are state; Sec. IV-A's PD hand).
+ * Every joint of the link table is revolute; q and qdot [D] are per
+ * simulation (hq = [q, qdot]).  Each capsule link is a solid cylinder of
+ * mass link_mass; the controller compensates the hand's gravity and the
+ * step neglects velocity-product forces.  Implicit PD toward the command u:
+ * (M(q) + dt kd I + dt^2 kp I) qdot+ = M(q) qdot + dt kp (u - q) + J_h^T r,
+ * q+ = q + dt qdot+.  A sphere-link contact couples the object's velocity
+ * and the joint rates of the link's chain (the velocity of the object's
+ * contact point relative to the link's material point there); the contact
+ * model, cap, solve and object integration are those of or_env_step.  Links
+ * touch the object only.  u [D] is the step's command.  Returns C. */
+int or_env_step_pd(const or_model *m, const double *u, int type, double *st, double *pr, double *hq,
+                   int32_t *wkey, double *wr, or_contact *cont, or_diag *dg);
+
+/* Joint-space mass matrix M(q) [D][D] of the PD hand (sum over links of
+ * m J_v^T J_v + J_w^T I_w J_w at the link's centre of mass). */
+void or_hand_mass(const or_model *m, const double *q, double *M);
+
+/* K environments of or_env_step_pd (OpenMP); hstate [K][2D]; obs [K][L][4]
+ * the force observation (the joint angles are hstate's first D columns). */
+void or_batch_step_pd(const or_model *m, int K, const int32_t *env_type, const double *u, double *state,
+                      double *params, double *hstate, int32_t *wkey, double *wr, or_contact *cont, or_diag *diag,
+                      double *obs);
+
+/* Step cost with the joint-angle term: or_step_cost + w_q |q - q_gt|^2
+ * (Eq. 3's first term, squared like the force terms). */
+double or_step_cost_pd(const or_model *m, const double *obs, const double *q, const double *obs_gt,
+                       const double *q_gt);
 
 /* Observation of Eq. 3 (cost_mode 1), per sensor l, obs[l][7]:
  * |c|, c/|c| (0 when |c| <= tau_contact), d (2), rot, where, over the

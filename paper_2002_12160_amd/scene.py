@@ -54,6 +54,13 @@ class ModelConsts:
     tau_slip: float = 0.005      # translational slip threshold [m/s]
     tau_spin: float = 0.1        # rotational slip threshold [rad/s]
     w_eq3: tuple = (1.0, 1.0, 0.6366197723675814, 1.0, 0.6366197723675814, 1.0, 1.0)  # w4..w10
+    # the PD-controlled hand (hand_mode 1): its joints are state, driven
+    # toward the commands by an implicit PD law
+    hand_mode: int = 0           # 0: kinematic hand (joints follow u_t); 1: PD-controlled hand
+    kp: float = 1.5              # joint stiffness [N m / rad]
+    kd: float = 0.05             # joint damping [N m s / rad]
+    link_mass: float = 0.03      # mass of every capsule link [kg]
+    w_q: float = 100.0           # weight of the joint-angle term |q - q_gt|^2 [1 / rad^2]
 
 
 @dataclass(frozen=True)
