@@ -930,6 +930,8 @@ int or_env_step_pd(const or_model *m, const double *u_cmd, int type, double *st,
     double x[3] = {st[0], st[1], st[2]}, q[4] = {st[3], st[4], st[5], st[6]}, R[9];
     qnormalize(q);
     qmat(q, R);
+    geom_round(m, q, 4);
+    geom_round(m, R, 9);
     double Iinv[9];
     for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j) {
@@ -937,12 +939,14 @@ int or_env_step_pd(const or_model *m, const double *u_cmd, int type, double *st,
             for (int k = 0; k < 3; ++k) s_ += R[3 * i + k] * (inv[k] / mass) * R[3 * j + k];
             Iinv[3 * i + j] = s_;
         }
+    geom_round(m, Iinv, 9);
     double *nus = (double *)calloc((size_t)nd, sizeof(double));
     double *nup = (double *)calloc((size_t)nd, sizeof(double));
     for (int i = 0; i < 3; ++i) {
         nus[i] = st[7 + i] + dt * (m->gravity[i] + fp[i] / mass);
         nus[3 + i] = st[10 + i];
     }
+    geom_round(m, nus, 3);
 
     /* hand: kinematics at q, mass matrix, PD-implicit effective mass and
      * free joint rates */
@@ -978,6 +982,7 @@ int or_env_step_pd(const or_model *m, const double *u_cmd, int type, double *st,
             seg[6 * l + i] = hk.o[3 * l + i];
             seg[6 * l + 3 + i] = hk.b[3 * l + i];
         }
+    geom_round(m, seg, 6 * L);
 
     /* candidates and the cap, as in the kinematic model */
     int npair = S * (L + 1);
@@ -988,9 +993,11 @@ int or_env_step_pd(const or_model *m, const double *u_cmd, int type, double *st,
         double c[3];
         matvec(R, sph + 4 * k, c);
         c[0] += x[0]; c[1] += x[1]; c[2] += x[2];
+        geom_round(m, c, 3);
         for (int l = 0; l <= L; ++l) {
             double d, n[3], p[3], vl[3];
             pair_geometry(m, seg, seg, l, c, sph[4 * k + 3], &d, n, p, vl);
+            geom_round(m, &d, 1);
             if (fabs(d - m->margin) < margin_gap) margin_gap = fabs(d - m->margin);
             if (d < m->margin) {
                 cand[ncand].d = d;
@@ -1005,18 +1012,34 @@ int or_env_step_pd(const or_model *m, const double *u_cmd, int type, double *st,
     or_contact *cc = (or_contact *)calloc((size_t)(C > 0 ? C : 1), sizeof(or_contact));
     double *J = (double *)calloc((size_t)(n3 > 0 ? n3 : 1) * nd, sizeof(double));
     double *uf = (double *)calloc((size_t)(n3 > 0 ? n3 : 1), sizeof(double));
+    double tangent_tie = INFINITY;
     for (int c = 0; c < C; ++c) {
         int key = cand[c].key;
         int k = key / (L + 1), l = key % (L + 1);
         double ctr[3];
         matvec(R, sph + 4 * k, ctr);
         ctr[0] += x[0]; ctr[1] += x[1]; ctr[2] += x[2];
+        geom_round(m, ctr, 3);
         or_contact *o_ = cc + c;
         o_->key = key;
         o_->link = l;
         pair_geometry(m, seg, seg, l, ctr, sph[4 * k + 3], &o_->d, o_->n, o_->p, o_->vlink);
+        geom_round(m, &o_->d, 1);
+        geom_round(m, o_->n, 3);
+        geom_round(m, o_->p, 3);
         tangent_frame(o_->n, o_->t1, o_->t2);
+        geom_round(m, o_->t1, 3);
+        geom_round(m, o_->t2, 3);
+        if (l < L) {
+            /* distance of the tangent-axis rule from a tie (as in the
+             * kinematic step) */
+            double a0 = fabs(o_->n[0]), a1 = fabs(o_->n[1]), a2 = fabs(o_->n[2]);
+            double lo = fmin(a0, fmin(a1, a2)), hi = fmax(a0, fmax(a1, a2));
+            double mid = a0 + a1 + a2 - lo - hi;
+            if (mid - lo < tangent_tie) tangent_tie = mid - lo;
+        }
         double rho[3] = {o_->p[0] - x[0], o_->p[1] - x[1], o_->p[2] - x[2]};
+        geom_round(m, rho, 3);
         const double *dirs[3] = {o_->n, o_->t1, o_->t2};
         for (int i = 0; i < 3; ++i) {
             double *row = J + (size_t)(3 * c + i) * nd;
@@ -1127,7 +1150,7 @@ int or_env_step_pd(const or_model *m, const double *u_cmd, int type, double *st,
         dg->d_last_kept = C > 0 ? cand[C - 1].d : -INFINITY;
         dg->d_first_dropped = ncand > C ? cand[C].d : INFINITY;
         dg->armijo_margin = ndg.armijo_margin;
-        dg->tangent_tie = INFINITY;
+        dg->tangent_tie = tangent_tie;
         dg->margin_gap = margin_gap;
         dg->n_fallback = ndg.nfall;
     }
