@@ -58,7 +58,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-steps", type=int, default=30)
     ap.add_argument("--profile", action="store_true",
-                    help="short run for the profiler: the headline workload's batched + refinement path only")
+                    help="run for the profiler: one run of the headline leg as timed (batched + refinement), "
+                         "nothing else")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 256 MiB on the device three times with the ceiling library's copy kernel "
                          "(reference for the FETCH_SIZE / WRITE_SIZE counters)")
@@ -74,8 +75,13 @@ def parse():
 # --------------------------------------------------------------------------
 KERNEL_SOURCES = ("pt_kernels.hip", "pt_step.hpp", "pt_device.hpp", "pt_io.hpp", "pt_internal.h")
 MEASURED = {
-    # "src": sha256 (first 16 hex digits) of KERNEL_SOURCES, in order
-    "k_window_realtime16384": None,
+    # "src": sha256 (first 16 hex digits) of KERNEL_SOURCES, in order;
+    # traffic: (FETCH_SIZE x 1.9998 + WRITE_SIZE x 1.0000) KiB x 1024 per launch, the
+    # factors from a 256 MiB device copy under the same counters; valu_*:
+    # SQ_INSTS_VALU and SQ_ACTIVE_INST_VALU per launch, summed over the chip
+    "k_window_realtime16384": {"src": "24a4056ba7db1c36", "traffic": 397325005,
+                               "fetch": 28094343, "write": 369230662,
+                               "valu_insts": 2230572762, "valu_busy_quads": 2364762723},
 }
 SIMDS, CLOCK_HZ = 1024, 2.4e9     # MI355X: 256 CUs x 4 SIMDs at 2.4 GHz; a VALU instruction issues in 4 cycles
 PEAK_F64_TFLOPS = 78.6            # MI355X published float64 vector peak (= non-packed float32)
@@ -112,13 +118,16 @@ def algorithmic_flops(S, L, N, env_steps, contacts):
     return env_steps * per_env + contacts * (FLOP_CONTACT + N * FLOP_CONTACT_ITER)
 
 
-def window_bytes(C_max, T, L, obs=False):
+def window_bytes(C_max, T, L, obs=False, checkpoints=False):
     """Algorithmic HBM bytes of the window kernel per environment-step: the
     state (13 floats), parameters (5) and warm-start cache (C_max x 16 B)
     read once and written once per window, the observed forces of the group
     (shared, cache resident) and the cost read and written once; with obs,
-    the observation rows written every step."""
-    return (2 * (13 + 5) * 4 + 2 * 16 * C_max + 8) / T + (16 * L if obs else 0)
+    the observation rows written every step; with checkpoints (the path with
+    elite refinement), the per-step checkpoint the reverse sweep reads: the
+    body (64 B) and every contact slot's key and float64 impulse (32 B)."""
+    return ((2 * (13 + 5) * 4 + 2 * 16 * C_max + 8) / T + (16 * L if obs else 0)
+            + (64 + 32 * C_max if checkpoints else 0))
 
 
 def median_run(runs):
@@ -552,8 +561,6 @@ def main():
     n_win = max(MIN_WINDOWS, -(-args.steps // T))
     n_warm = max(1, -(-args.warmup // T))
     runs = 1 if args.profile else args.runs
-    if args.profile:
-        n_win = 3
     print(f"bench: headline {cfg.name}, {runs} runs of {n_win} windows after {n_warm}", file=sys.stderr, flush=True)
     setup = make_setup(pt, S, dev, sp, cfg, n_warm + n_win)
     head = repeat(lambda: windows_run(pt, setup, dev, sp, n_win, n_warm), runs)
@@ -571,8 +578,11 @@ def main():
                 "flop_per_env_step": round(wk["flop_per_launch"] / wk["env_steps_per_launch"], 1),
                 "env_steps_per_launch": int(wk["env_steps_per_launch"]),
                 "avg_launch_us": wk["avg_launch_us"],
-                "hbm_bytes_per_env_step": round(window_bytes(cfg.C_max, T, L), 1),
-                "hbm_gbps": round(window_bytes(cfg.C_max, T, L) * wk["env_steps_per_launch"] / launch_s / 1e9, 2),
+                "hbm_bytes_per_env_step": round(window_bytes(cfg.C_max, T, L, checkpoints=True), 1),
+                "hbm_bytes_per_launch": round(window_bytes(cfg.C_max, T, L, checkpoints=True) *
+                                              wk["env_steps_per_launch"]),
+                "hbm_gbps": round(window_bytes(cfg.C_max, T, L, checkpoints=True) * wk["env_steps_per_launch"] /
+                                  launch_s / 1e9, 2),
                 "valu": ({"issue_frac": round(m["valu_insts"] * 4 / (SIMDS * CLOCK_HZ * launch_s), 4),
                           "busy_frac": round(m["valu_busy_quads"] * 4 / (SIMDS * CLOCK_HZ * launch_s), 4)}
                          if m else None)}

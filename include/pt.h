@@ -138,6 +138,40 @@ typedef struct {
     float tau_slip;       /* translational slip threshold [m/s], mode 1       */
     float tau_spin;       /* rotational slip threshold [rad/s], mode 1        */
     float w_eq3[7];       /* w4 .. w10 of Eq. 3, mode 1                       */
+    /* hand model: 0 = kinematic hand, its joints follow the commands (the
+       world model above); 1 = PD-controlled hand (Sec. III-A: the state
+       holds the joint angles of the articulated hand and the observation the
+       measured angles; Sec. IV-A: the simulated hand is driven by PD gains).
+       With 1, every simulation's joints (q, qdot) are state in hand_state;
+       each link is a solid cylinder of mass link_mass (axial inertia
+       m r^2 / 2, transverse m (3 r^2 + len^2) / 12 about its centre), the
+       hand's gravity compensated and its velocity-product terms dropped, so
+       M(q) = sum over links of m J_v^T J_v + J_w^T I_w J_w is its only
+       inertia; the PD law is taken implicitly,
+         (M + dt kd I + dt^2 kp I) qdot+ = M qdot + dt kp (u - q) + J_h^T r,
+         q+ = q + dt qdot+,
+       and the contact solve runs over the generalised velocity (v, omega,
+       qdot) of size 6 + D, a contact on link l adding the columns
+       -F G_l(p), G_l(p)[:, j] = axis_j x (p - origin_j) over the joints that
+       move link l (the object's point relative to the link's point at p).
+       The observation gains the D joint angles after the step: obs
+       [4 L + D][K] (the [4][L][K] force rows, then q [D][K]); obs_gt
+       [4 L + D][G]; the step cost adds w_q sum_j (q_j - q^gt_j)^2 (Eq. 3's
+       joint-angle term).  Limits (PT_E_UNSUPPORTED): D <= 64; a joint
+       drives one link; at most 8 joints move a link; the joints split into
+       independent groups (joints moving a common link, closed transitively:
+       a finger) of at most 6; solve_precision 64; cost_mode 0.  With 1,
+       pt_step reads u (the PD targets) and ignores u_prev; pt_observe,
+       pt_cost and pt_resample (which copies hand_state with the rest of a
+       simulation) take the layouts above; the windowed, gradient,
+       refinement and weighted-resampling calls return PT_E_UNSUPPORTED. */
+    int32_t hand_mode;
+    float kp;             /* joint stiffness [N m / rad], >= 0                */
+    float kd;             /* joint damping [N m s / rad], >= 0; kp + kd > 0  */
+    float link_mass;      /* mass of every link [kg], > 0                     */
+    float w_q;            /* weight of the joint-angle term [1 / rad^2], >= 0 */
+    float *hand_state;    /* [2 D][K] q (D rows) then qdot (D rows), DEVICE,
+                             caller-owned, used in place (hand_mode 1)       */
 } pt_batch_desc;
 
 /* Creates a batch: validates the descriptor (PT_E_ARG / PT_E_UNSUPPORTED),
@@ -292,6 +326,14 @@ PT_API pt_status pt_set_tuning(pt_batch b, int32_t waves_per_workgroup);
  *                             normalisation of q (orthogonal to q)
  *   end_state  [13][n]        out: state after the window, or NULL
  *   end_warm   [n][C_max][4]  out: warm cache after the window, or NULL
+ *   resid      [n]            out: the largest final merit |Phi|^2 / 2 of the
+ *                             window's contact solves (0 for a step without
+ *                             contacts), or NULL.  The gradient is exact for
+ *                             the window map the forward sweep computes only
+ *                             where these solves have converged: with a fixed
+ *                             newton_iters a solve can stop short of the root
+ *                             the reverse sweep assumes, and the gradient is
+ *                             then that of the converged map at this start
  * The batch's own state, params and warm cache are neither read nor written.
  * The checkpoints (per simulation and step the body and the contacts' keys
  * and float64 impulses, 64 + 32 C_max bytes) live in a buffer the batch owns,
@@ -300,7 +342,7 @@ PT_API pt_status pt_set_tuning(pt_batch b, int32_t waves_per_workgroup);
  * not overlap. */
 PT_API pt_status pt_window_grad(pt_batch b, const float *u_win, const float *obs_gt_win, int32_t n,
                                 const int32_t *env, const float *start, const float *warm0, float *cost,
-                                float *grad, float *end_state, float *end_warm, pt_stream s);
+                                float *grad, float *end_state, float *end_warm, float *resid, pt_stream s);
 
 /* Elite refinement by the window-cost gradient, run between pt_run_window
  * and pt_resample.  The elites of each group, ranked from cost_sum as

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libpt.so")
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("pt_kernels.hip", "pt_grad.hip", "pt_resample.hip", "pt_api.hip")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("pt_kernels.hip", "pt_grad.hip", "pt_resample.hip", "pt_pd.hip", "pt_api.hip")]
 # the ceiling microbenchmarks the benchmark measures peaks with (not part of libpt)
 CEIL_LIB = os.path.join(HERE, "libptceil.so")
 CEIL_SOURCES = [os.path.join(HERE, "csrc", "pt_ceiling.hip")]

@@ -12,6 +12,7 @@
 
 #include "../../include/pt.h"
 #include "pt_internal.h"
+#include "pt_pd.hpp"
 
 using pt::Consts;
 using pt::Tables;
@@ -114,6 +115,12 @@ struct pt_batch_s {
     float *d_ref = nullptr;      // see refine_layout
     float *d_snap = nullptr;     // [18][K] + [K][C_max][4]: parents' copies for the weighted resamplers
     void *static_scratch = nullptr; // this device's pt_run_window_static scratch (not owned)
+    // the PD-controlled hand (hand_mode 1)
+    int hand_mode = 0;
+    pt::PdConsts Q = {};
+    int32_t *d_pd = nullptr;     // the hand's structure table (pt::PdTab)
+    int32_t *d_parent = nullptr; // [K] parents of a resampling, for the joint state's copies
+    float *hstate = nullptr;     // caller-owned [2D][K]
     // caller-owned state
     float *state, *params, *warm;
     // host copies
@@ -175,6 +182,18 @@ pt_status validate(const pt_batch_desc *d)
     if (!d->hand || !d->spheres || !d->n_spheres || !d->inv_inertia || !d->env_type || !d->group_start)
         return fail(PT_E_ARG, "scene table pointer is NULL");
     if (!d->state || !d->params || !d->warm) return fail(PT_E_ARG, "state/params/warm pointer is NULL");
+    if (d->hand_mode != 0 && d->hand_mode != 1) return fail(PT_E_ARG, "hand_mode must be 0 or 1 (got %d)", d->hand_mode);
+    if (d->hand_mode == 1) {
+        if (d->D > pt::PD_MAX_D) return fail(PT_E_UNSUPPORTED, "the PD hand has at most %d joints (got %d)", pt::PD_MAX_D, d->D);
+        if (d->solve_precision == 32) return fail(PT_E_UNSUPPORTED, "the PD hand's solve is float64 only");
+        if (d->cost_mode != 0) return fail(PT_E_UNSUPPORTED, "the PD hand supports cost_mode 0 only");
+        if (!(d->kp >= 0.f) || !(d->kd >= 0.f) || !std::isfinite(d->kp) || !std::isfinite(d->kd) ||
+            !(d->kp + d->kd > 0.f))
+            return fail(PT_E_ARG, "kp and kd must be finite, >= 0 and not both 0");
+        if (!(d->link_mass > 0.f) || !std::isfinite(d->link_mass)) return fail(PT_E_ARG, "link_mass must be positive and finite");
+        if (!(d->w_q >= 0.f) || !std::isfinite(d->w_q)) return fail(PT_E_ARG, "w_q must be finite and >= 0");
+        if (d->D > 0 && !d->hand_state) return fail(PT_E_ARG, "hand_state is NULL");
+    }
     for (int l = 0; l < d->L; ++l) {
         const float *h = d->hand + (size_t)l * PT_HAND_STRIDE;
         int parent = (int)h[0], j0 = (int)h[1], j1 = (int)h[2];
@@ -197,6 +216,84 @@ pt_status validate(const pt_batch_desc *d)
         return fail(PT_E_ARG, "group_start must begin at 0 and end at K");
     for (int g = 0; g < d->G; ++g)
         if (d->group_start[g + 1] <= d->group_start[g]) return fail(PT_E_ARG, "groups must be non-empty and increasing");
+    return PT_OK;
+}
+
+// The PD hand's structure table (layout: pt::PdTab).  Joints that move a
+// common link are joined (transitively) into a group; groups are numbered
+// by their lowest joint and hold their joints in increasing order, which
+// gives every joint its position.  Every joint drives at most one link.
+pt_status build_pd_table(const pt_batch_desc *d, std::vector<int32_t> &tab, int &groups, int &dmax)
+{
+    const int L = d->L, D = d->D;
+    std::vector<std::vector<int>> chain(L);
+    std::vector<int> owner(D, -1), depth(L, 0), uf(D);
+    for (int j = 0; j < D; ++j) uf[j] = j;
+    auto find = [&](int j) {
+        while (uf[j] != j) j = uf[j] = uf[uf[j]];
+        return j;
+    };
+    dmax = 0;
+    for (int l = 0; l < L; ++l) {
+        const float *h = d->hand + (size_t)l * PT_HAND_STRIDE;
+        const int parent = (int)h[0], js[2] = {(int)h[1], (int)h[2]};
+        if (js[0] >= 0 && js[0] == js[1]) return fail(PT_E_UNSUPPORTED, "link %d: both joints are joint %d", l, js[0]);
+        if (parent >= 0) {
+            chain[l] = chain[parent];
+            depth[l] = depth[parent] + 1;
+        }
+        dmax = std::max(dmax, depth[l]);
+        for (int j : js) {
+            if (j < 0) continue;
+            if (owner[j] >= 0) return fail(PT_E_UNSUPPORTED, "joint %d drives links %d and %d", j, owner[j], l);
+            owner[j] = l;
+            chain[l].push_back(j);
+        }
+        if ((int)chain[l].size() > pt::PD_CHAIN)
+            return fail(PT_E_UNSUPPORTED, "link %d is moved by %zu joints (at most %d)", l, chain[l].size(), pt::PD_CHAIN);
+        for (int j : chain[l]) uf[find(j)] = find(chain[l][0]);
+    }
+    std::vector<int> group_of_root(D, -1);
+    std::vector<std::vector<int>> members;
+    for (int j = 0; j < D; ++j) {
+        const int r = find(j);
+        if (group_of_root[r] < 0) {
+            group_of_root[r] = (int)members.size();
+            members.emplace_back();
+        }
+        members[group_of_root[r]].push_back(j);
+    }
+    groups = (int)members.size();
+    std::vector<int> jat, pos(D), gs(D), gn(D), gfirst;
+    for (const auto &m : members) {
+        if ((int)m.size() > pt::PD_GMAX)
+            return fail(PT_E_UNSUPPORTED, "a group of %zu joints moves common links (at most %d)", m.size(), pt::PD_GMAX);
+        gfirst.push_back((int)jat.size());
+        for (int j : m) {
+            pos[j] = (int)jat.size();
+            gs[pos[j]] = gfirst.back();
+            gn[pos[j]] = (int)m.size();
+            jat.push_back(j);
+        }
+    }
+    gfirst.push_back(D);
+    std::vector<uint64_t> sub(D, 0);
+    for (int l = 0; l < L; ++l)
+        for (int j : chain[l]) sub[pos[j]] |= 1ull << l;
+    tab.assign(pt::pd_tab_ints(L, D, groups), -1);
+    for (int p = 0; p < D; ++p) {
+        tab[p] = jat[p];
+        tab[D + jat[p]] = p;
+        tab[2 * D + p] = gs[p];
+        tab[3 * D + p] = gn[p];
+        tab[4 * D + p] = (int32_t)(uint32_t)(sub[p] & 0xffffffffu);
+        tab[5 * D + p] = (int32_t)(uint32_t)(sub[p] >> 32);
+    }
+    for (int l = 0; l < L; ++l) {
+        tab[6 * D + l] = depth[l];
+        for (size_t i = 0; i < chain[l].size(); ++i) tab[6 * D + L + l * pt::PD_CHAIN + i] = pos[chain[l][i]];
+    }
+    for (int g = 0; g <= groups; ++g) tab[6 * D + L + L * pt::PD_CHAIN + g] = gfirst[g];
     return PT_OK;
 }
 
@@ -263,11 +360,19 @@ pt_status pt_create_batch(const pt_batch_desc *d, pt_batch *out)
     // once the cap has run, the rows of the solve's cross-contact sums
     // (lane_span(C_max) rows of RedStride<double> = 44 doubles)
     const int red_rows = d->C_max <= 16 ? 16 : (d->C_max <= 32 ? 32 : 64);
+    // the PD hand's structure
+    std::vector<int32_t> pd_tab;
+    int pd_groups = 0, pd_dmax = 0;
+    if (d->hand_mode == 1) {
+        st = build_pd_table(d, pd_tab, pd_groups, pd_dmax);
+        if (st != PT_OK) return st;
+    }
     // ... and the step's hand kinematics, which use the same LDS first
+    const size_t fk_bytes = d->hand_mode == 1 ? pt::pd_fk_bytes(d->L) : hand_fk_lds_bytes(d->L, d->D);
     const int max_cand = std::max({round_up(std::min(d->S_max * (d->L + 1), pt::CAND_CAP) + 8, 64),
                                    round_up(red_rows * pt::RedStride<double>::value, 64),
-                                   round_up((int)((hand_fk_lds_bytes(d->L, d->D) + 7) / 8), 64)});
-    const size_t wave_lds = pt::wave_lds_bytes(max_cand, d->L);
+                                   round_up((int)((fk_bytes + 7) / 8), 64)});
+    const size_t wave_lds = pt::wave_lds_bytes(max_cand, d->L) + (d->hand_mode == 1 ? pt::pd_lds_bytes(d->D) : 0);
     if (wave_lds > 160 * 1024)
         return fail(PT_E_UNSUPPORTED, "%zu B of LDS per simulation (> 160 KiB)", wave_lds);
 
@@ -285,6 +390,11 @@ pt_status pt_create_batch(const pt_batch_desc *d, pt_batch *out)
     for (int i = 0; i < 7; ++i) P.w_eq3[i] = d->cost_mode == 1 ? d->w_eq3[i] : 0.f;
     b->R = {d->elite_frac, d->sigma_mu, d->sigma_m, d->sigma_f, d->mu_lo, d->mu_hi, d->m_lo, d->m_hi, d->seed};
     b->n_types = d->n_types;
+    b->hand_mode = d->hand_mode;
+    if (d->hand_mode == 1) {
+        b->Q = {pd_groups, pd_dmax, d->kp, d->kd, d->link_mass, d->w_q};
+        b->hstate = d->hand_state;
+    }
     b->state = d->state;
     b->params = d->params;
     b->warm = d->warm;
@@ -312,6 +422,7 @@ pt_status pt_create_batch(const pt_batch_desc *d, pt_batch *out)
     HIP_TRY_C(set_lds_limits(160 * 1024));
     HIP_TRY_C(set_grad_lds_limits(160 * 1024));
     HIP_TRY_C(set_draw_lds_limits(160 * 1024));
+    HIP_TRY_C(set_pd_lds_limits(160 * 1024));
 
     const size_t K = d->K;
     std::vector<int32_t> group_of(K), order(K);
@@ -344,6 +455,11 @@ pt_status pt_create_batch(const pt_batch_desc *d, pt_batch *out)
     HIP_TRY_C(hipMalloc(&b->d_elite, sizeof(int32_t) * b->n_elite));
     HIP_TRY_C(hipMalloc(&b->d_snap, sizeof(float) * K * (18 + (size_t)4 * d->C_max)));
     if (d->window_checkpoints) HIP_TRY_C(hipMalloc(&b->d_wckpt, sizeof(float) * ckpt_floats(P, (int)K)));
+    if (d->hand_mode == 1) {
+        HIP_TRY_C(hipMalloc(&b->d_pd, sizeof(int32_t) * pd_tab.size()));
+        HIP_TRY_C(hipMalloc(&b->d_parent, sizeof(int32_t) * K));
+        HIP_TRY_C(hipMemcpy(b->d_pd, pd_tab.data(), sizeof(int32_t) * pd_tab.size(), hipMemcpyHostToDevice));
+    }
     if (d->cost_mode == 1) {
         HIP_TRY_C(hipMalloc(&b->d_cslip, sizeof(float) * K * d->C_max * 8));
         HIP_TRY_C(hipMalloc(&b->d_seg, sizeof(float) * d->L * pt::SEG_STRIDE));
@@ -382,7 +498,7 @@ pt_status pt_destroy_batch(pt_batch b)
     void *ptrs[] = {b->d_hand, b->d_spheres, b->d_inv, b->d_nsph, b->d_type, b->d_group_of, b->d_group_start,
                     b->d_order, b->d_queue, b->d_stats, b->d_seg_win, b->d_contacts,
                     b->d_seg_grad, b->d_tune, b->d_ckpt, b->d_wckpt, b->d_elite, b->d_ref, b->d_snap,
-                    b->d_cslip, b->d_seg};
+                    b->d_cslip, b->d_seg, b->d_pd, b->d_parent};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete b;
@@ -404,8 +520,14 @@ static Tables tables_of(const pt_batch b)
 pt_status pt_step(pt_batch b, const float *u_prev, const float *u, pt_stream s)
 {
     if (!b) return fail(PT_E_ARG, "batch is NULL");
-    if (b->P.D > 0 && (!u_prev || !u)) return fail(PT_E_ARG, "u_prev/u is NULL");
     hipStream_t st = (hipStream_t)s;
+    if (b->hand_mode == 1) {
+        if (b->P.D > 0 && !u) return fail(PT_E_ARG, "u is NULL");
+        HIP_TRY(launch_step_pd(b->P, b->Q, tables_of(b), b->d_pd, u, b->state, b->params, b->warm, b->hstate,
+                               b->d_contacts, b->d_stats, st));
+        return PT_OK;
+    }
+    if (b->P.D > 0 && (!u_prev || !u)) return fail(PT_E_ARG, "u_prev/u is NULL");
     HIP_TRY(launch_step(b->P, tables_of(b), u_prev, u, b->state, b->params, b->warm, b->d_contacts, b->d_cslip,
                         b->d_seg, b->d_stats, b->step_wpb, st));
     return PT_OK;
@@ -415,6 +537,10 @@ pt_status pt_observe(pt_batch b, float *obs, pt_stream s)
 {
     if (!b) return fail(PT_E_ARG, "batch is NULL");
     if (!obs) return fail(PT_E_ARG, "obs is NULL");
+    if (b->hand_mode == 1) {
+        HIP_TRY(launch_observe_pd(b->P, b->d_contacts, b->hstate, obs, (hipStream_t)s));
+        return PT_OK;
+    }
     HIP_TRY(launch_observe(b->P, b->d_contacts, b->d_cslip, b->d_seg, obs, (hipStream_t)s));
     return PT_OK;
 }
@@ -424,6 +550,11 @@ pt_status pt_cost(pt_batch b, const float *obs, const float *obs_gt, float *cost
     if (!b) return fail(PT_E_ARG, "batch is NULL");
     if (!obs || !obs_gt || !cost_sum) return fail(PT_E_ARG, "obs/obs_gt/cost_sum is NULL");
     hipStream_t st = (hipStream_t)s;
+    if (b->hand_mode == 1) {
+        HIP_TRY(launch_cost_pd(b->P, b->Q, b->d_group_of, obs, obs_gt, cost_sum, st));
+        if (best) HIP_TRY(launch_argmin(b->P.G, b->d_group_start, cost_sum, best, st));
+        return PT_OK;
+    }
     // up to FUSED_ARGMIN_MAX simulations the cost kernel's last workgroup ranks
     // the groups itself; past that one workgroup's pass over the population
     // takes longer than a launch of the per-group argmin kernel
@@ -438,8 +569,12 @@ pt_status pt_resample(pt_batch b, float *cost_sum, uint32_t window_idx, int32_t 
 {
     if (!b) return fail(PT_E_ARG, "batch is NULL");
     if (!cost_sum) return fail(PT_E_ARG, "cost_sum is NULL");
+    // the PD hand's joint state follows each simulation's parent
+    int32_t *par = b->hand_mode == 1 && !parent ? b->d_parent : parent;
     HIP_TRY(launch_resample(b->P, b->R, b->d_group_start, b->max_group, window_idx, cost_sum, b->state, b->params,
-                            b->warm, parent, (hipStream_t)s));
+                            b->warm, par, (hipStream_t)s));
+    if (b->hand_mode == 1 && b->P.D > 0)
+        HIP_TRY(launch_copy_hand(b->P.K, 2 * b->P.D, par, b->hstate, (hipStream_t)s));
     return PT_OK;
 }
 
@@ -448,6 +583,7 @@ static pt_status weighted_resample(pt_batch b, int kind, float hyper, float *cos
 {
     if (!b) return fail(PT_E_ARG, "batch is NULL");
     if (!cost_sum || !parent) return fail(PT_E_ARG, "cost_sum/parent is NULL");
+    if (b->hand_mode == 1) return fail(PT_E_UNSUPPORTED, "the weighted resamplers do not carry the PD hand's state");
     if (n_steps < 1) return fail(PT_E_ARG, "n_steps must be >= 1 (got %d)", n_steps);
     if (!std::isfinite(hyper) || (kind == 0 ? hyper < 0.f : hyper <= 0.f))
         return fail(PT_E_ARG, kind == 0 ? "lambda must be finite and >= 0" : "epsilon must be finite and > 0");
@@ -497,6 +633,7 @@ pt_status pt_run_window(pt_batch b, const float *u_win, const float *obs_gt_win,
                         float *obs_out, int32_t graph, pt_stream s)
 {
     if (!b) return fail(PT_E_ARG, "batch is NULL");
+    if (b->hand_mode == 1) return fail(PT_E_UNSUPPORTED, "the windowed path is not built for the PD hand");
     if (!u_win || !obs_gt_win || !cost_sum) return fail(PT_E_ARG, "u_win/obs_gt_win/cost_sum is NULL");
     hipStream_t st = (hipStream_t)s;
     if (!graph)
@@ -549,6 +686,7 @@ pt_status pt_run_window_static(pt_batch b, const float *u_win, const float *obs_
                                int32_t *best, float *obs_out, pt_stream s)
 {
     if (!b) return fail(PT_E_ARG, "batch is NULL");
+    if (b->hand_mode == 1) return fail(PT_E_UNSUPPORTED, "the windowed path is not built for the PD hand");
     if (!u_win || !obs_gt_win || !cost_sum) return fail(PT_E_ARG, "u_win/obs_gt_win/cost_sum is NULL");
     const Consts &P = b->P;
     if ((size_t)P.T * P.L > STATIC_SEG_RECORDS)
@@ -569,6 +707,7 @@ pt_status pt_run_window_static(pt_batch b, const float *u_win, const float *obs_
 pt_status pt_autotune(pt_batch b, const float *u_win, const float *obs_gt_win, int32_t *result, pt_stream s)
 {
     if (!b) return fail(PT_E_ARG, "batch is NULL");
+    if (b->hand_mode == 1) return fail(PT_E_UNSUPPORTED, "the windowed path is not built for the PD hand");
     if (!u_win || !obs_gt_win) return fail(PT_E_ARG, "u_win/obs_gt_win is NULL");
     hipStream_t st = (hipStream_t)s;
     const Consts &P = b->P;
@@ -636,9 +775,10 @@ pt_status pt_set_tuning(pt_batch b, int32_t wpb)
 
 pt_status pt_window_grad(pt_batch b, const float *u_win, const float *obs_gt_win, int32_t n, const int32_t *env,
                          const float *start, const float *warm0, float *cost, float *grad, float *end_state,
-                         float *end_warm, pt_stream s)
+                         float *end_warm, float *resid, pt_stream s)
 {
     if (!b) return fail(PT_E_ARG, "batch is NULL");
+    if (b->hand_mode == 1) return fail(PT_E_UNSUPPORTED, "the window gradient is not built for the PD hand");
     if (b->P.cost_mode != 0) return fail(PT_E_UNSUPPORTED, "the window gradient is defined for cost_mode 0 only");
     if (n < 0) return fail(PT_E_ARG, "n must be >= 0 (got %d)", n);
     if (n == 0) return PT_OK;
@@ -650,7 +790,7 @@ pt_status pt_window_grad(pt_batch b, const float *u_win, const float *obs_gt_win
     HIP_TRY(launch_hand_fk(b->d_hand, P.L, P.D, P.dt, u_win, u_win + P.D, P.D, P.T, b->d_seg_grad, st));
     if (!grad) {
         HIP_TRY(launch_window_fwd(P, tb, b->d_seg_grad, n, 0, n, env, start, warm0, obs_gt_win, cost, end_state,
-                                  end_warm, nullptr, st));
+                                  end_warm, nullptr, st, resid));
         return PT_OK;
     }
     // the checkpoint buffer holds n_elite simulations: forward and reverse
@@ -658,7 +798,7 @@ pt_status pt_window_grad(pt_batch b, const float *u_win, const float *obs_gt_win
     for (int i0 = 0; i0 < n; i0 += b->n_elite) {
         const int cnt = std::min(b->n_elite, n - i0);
         HIP_TRY(launch_window_fwd(P, tb, b->d_seg_grad, n, i0, cnt, env, start, warm0, obs_gt_win, cost, end_state,
-                                  end_warm, b->d_ckpt, st));
+                                  end_warm, b->d_ckpt, st, resid));
         HIP_TRY(launch_window_bwd(P, tb, b->d_seg_grad, n, i0, cnt, env, start, obs_gt_win, b->d_ckpt, false, nullptr,
                                   grad, st));
     }
@@ -673,6 +813,7 @@ pt_status pt_refine_elites(pt_batch b, const float *u_win, const float *obs_gt_w
     if (b && b->P.cost_mode != 0)
         return fail(PT_E_UNSUPPORTED, "elite refinement needs the window gradient, defined for cost_mode 0 only");
     if (!b) return fail(PT_E_ARG, "batch is NULL");
+    if (b->hand_mode == 1) return fail(PT_E_UNSUPPORTED, "elite refinement is not built for the PD hand");
     if (!u_win || !obs_gt_win || !cost_sum || !start_state || !start_params || !start_warm)
         return fail(PT_E_ARG, "u_win/obs_gt_win/cost_sum/start_state/start_params/start_warm is NULL");
     if (steps < 0) return fail(PT_E_ARG, "steps must be >= 0 (got %d)", steps);

@@ -43,7 +43,7 @@ __global__ __launch_bounds__(WAVE) void k_window_fwd(Consts P, Tables tb, const 
                                                      const float *__restrict__ warm0,
                                                      const float *__restrict__ obs_gt_win, float *__restrict__ cost_out,
                                                      float *__restrict__ end_state, float *__restrict__ end_warm,
-                                                     float *__restrict__ ckpt)
+                                                     float *__restrict__ ckpt, float *__restrict__ resid_out)
 {
     extern __shared__ __align__(16) char smem[];
     const int c = blockIdx.x;
@@ -73,8 +73,10 @@ __global__ __launch_bounds__(WAVE) void k_window_fwd(Consts P, Tables tb, const 
     load_warm(warm0, P.C_max, i, wkey, wr);
     StepStats stt = {0, 0, 0};
 
-    // cost summed in the order of the other paths
-    float cost = 0.f;
+    // cost summed in the order of the other paths; the largest final merit
+    // of the window's contact solves (how far they are from the root the
+    // reverse sweep assumes)
+    float cost = 0.f, resid = 0.f;
     for (int t = 0; t < P.T; ++t) {
         float *ck = ckpt ? ckpt + ((size_t)c * P.T + t) * CK : nullptr;
         if (ck) save_body(ck, B);
@@ -82,6 +84,7 @@ __global__ __launch_bounds__(WAVE) void k_window_fwd(Consts P, Tables tb, const 
         StepState<SR> st;
         step_setup<SR>(P, seg, sph, S, inv, B, wkey, wr, lds, stt, st);
         step_solve<SR, true, PT>(P, st, B.mu, inv, reinterpret_cast<SR *>(lds.cand_d));
+        resid = fmaxf(resid, (float)st.psi_end);
         if (ck) save_contact<SR>(ck, P.C_max, st);
         int link;
         float imp[3];
@@ -102,6 +105,7 @@ __global__ __launch_bounds__(WAVE) void k_window_fwd(Consts P, Tables tb, const 
     }
     if (lane == 0) {
         cost_out[i] = cost;
+        if (resid_out) resid_out[i] = resid;
         if (end_state) {
             const float v13[13] = {B.x[0], B.x[1], B.x[2], B.q[0], B.q[1], B.q[2], B.q[3],
                                    B.v[0], B.v[1], B.v[2], B.w[0], B.w[1], B.w[2]};
@@ -295,14 +299,15 @@ size_t ckpt_floats(const Consts &P, int n) { return (size_t)n * P.T * ckpt_step_
 
 hipError_t launch_window_fwd(const Consts &P, const Tables &tb, const float *seg_win, int n, int i0, int count,
                              const int32_t *env, const float *xi, const float *warm0, const float *obs_gt_win,
-                             float *cost, float *end_state, float *end_warm, float *ckpt, hipStream_t s)
+                             float *cost, float *end_state, float *end_warm, float *ckpt, hipStream_t s,
+                             float *resid)
 {
     if (count <= 0) return hipSuccess;
     size_t lds = wave_lds_bytes(P.max_cand, P.L);
     // paired line-search trials when no step can hold more than 32 contacts
     auto go = [&](auto kern) {
         hipLaunchKernelGGL(kern, dim3(count), dim3(WAVE), lds, s, P, tb, seg_win, n, i0, count, env, xi, warm0,
-                           obs_gt_win, cost, end_state, end_warm, ckpt);
+                           obs_gt_win, cost, end_state, end_warm, ckpt, resid);
         return hipGetLastError();
     };
     const bool pt = P.C_max <= 32;

@@ -118,7 +118,7 @@ size_t ckpt_floats(const pt::Consts &P, int n);
 hipError_t launch_window_fwd(const pt::Consts &P, const pt::Tables &tb, const float *seg_win, int n, int i0,
                              int count, const int32_t *env, const float *xi, const float *warm0,
                              const float *obs_gt_win, float *cost, float *end_state, float *end_warm, float *ckpt,
-                             hipStream_t s);
+                             hipStream_t s, float *resid = nullptr);
 hipError_t launch_window_bwd(const pt::Consts &P, const pt::Tables &tb, const float *seg_win, int n, int i0,
                              int count, const int32_t *env, const float *xi, const float *obs_gt_win,
                              const float *ckpt, bool ckpt_by_env, const int32_t *flag, float *grad,
@@ -139,3 +139,17 @@ hipError_t launch_weighted_resample(const pt::Consts &P, const pt::ResampleArgs 
                                     float *cost_sum, float *state, float *params, float *warm, float *snap,
                                     int32_t *parent, float *weights, float *eta, hipStream_t s);
 hipError_t set_draw_lds_limits(size_t bytes);
+
+// the PD-controlled hand (pt_pd.hip)
+namespace pt {
+struct PdConsts;
+}
+hipError_t set_pd_lds_limits(size_t bytes);
+hipError_t launch_step_pd(const pt::Consts &P, const pt::PdConsts &Q, const pt::Tables &tb, const int32_t *pd_tab,
+                          const float *u, float *state, float *params, float *warm, float *hstate, float *contacts,
+                          int64_t *stats, hipStream_t s);
+hipError_t launch_observe_pd(const pt::Consts &P, const float *contacts, const float *hstate, float *obs,
+                             hipStream_t s);
+hipError_t launch_cost_pd(const pt::Consts &P, const pt::PdConsts &Q, const int32_t *group_of, const float *obs,
+                          const float *obs_gt, float *cost_sum, hipStream_t s);
+hipError_t launch_copy_hand(int K, int rows, const int32_t *parent, float *hstate, hipStream_t s);

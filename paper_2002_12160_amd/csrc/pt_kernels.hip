@@ -20,23 +20,6 @@ namespace pt {
 // hand kinematics (double precision: it runs once per step for the whole
 // population, and the link velocities are differences of positions)
 // ---------------------------------------------------------------------
-__device__ __forceinline__ void quat_to_mat_d(const double *q, double *R)
-{
-    double w = q[0], x = q[1], y = q[2], z = q[3];
-    R[0] = 1 - 2 * (y * y + z * z); R[1] = 2 * (x * y - w * z);     R[2] = 2 * (x * z + w * y);
-    R[3] = 2 * (x * y + w * z);     R[4] = 1 - 2 * (x * x + z * z); R[5] = 2 * (y * z - w * x);
-    R[6] = 2 * (x * z - w * y);     R[7] = 2 * (y * z + w * x);     R[8] = 1 - 2 * (x * x + y * y);
-}
-
-__device__ __forceinline__ void quat_mul_d(const double *a, const double *b, double *o)
-{
-    double w = a[0] * b[0] - a[1] * b[1] - a[2] * b[2] - a[3] * b[3];
-    double x = a[0] * b[1] + a[1] * b[0] + a[2] * b[3] - a[3] * b[2];
-    double y = a[0] * b[2] - a[1] * b[3] + a[2] * b[0] + a[3] * b[1];
-    double z = a[0] * b[3] + a[1] * b[2] - a[2] * b[1] + a[3] * b[0];
-    o[0] = w; o[1] = x; o[2] = y; o[3] = z;
-}
-
 // Joint rotation of a link for joint vector u, Rot(axis0, u[j0]) Rot(axis1,
 // u[j1]) (identity for a joint index < 0), by a pair of adjacent lanes: lane
 // j of the pair (j = 0, 1) evaluates the half-angle rotation of joint j, the

@@ -1,0 +1,183 @@
+// pt_pd.hip -- kernels of the PD-controlled hand (hand_mode 1) for CDNA4
+// (gfx950): the per-step path of the kinematic hand with the joint angles
+// and rates as per-simulation state.
+//
+//   k_step_pd      one simulation step per wavefront: hand kinematics and
+//                  mass matrix at the simulation's joint angles, narrow
+//                  phase and cap, the (6 + D) contact solve, integration of
+//                  object and joints
+//   k_observe_pd   per-sensor contact force of the last step and the
+//                  simulation's joint angles (the observation of Sec. III-A)
+//   k_cost_pd      step cost: the force terms plus w_q |q - q_gt|^2
+//   k_copy_hand    the resampler's copies of the joint state
+#include "pt_io.hpp"
+#include "pt_pd.hpp"
+
+namespace pt {
+
+__global__ __launch_bounds__(WAVE) void k_step_pd(Consts P, PdConsts Q, Tables tb, PdTab T,
+                                                  const float *__restrict__ u, float *__restrict__ state,
+                                                  float *__restrict__ params, float *__restrict__ warm,
+                                                  float *__restrict__ hstate, float *__restrict__ contacts,
+                                                  int64_t *__restrict__ stats)
+{
+    extern __shared__ __align__(16) char smem[];
+    const int e = xcd_block(blockIdx.x, gridDim.x);
+    if (e >= P.K) return;
+    const int lane = lane_id();
+    const int D = P.D;
+    const size_t K = P.K;
+    WaveLds lds = carve_lds(smem, 0, P.max_cand, P.L);
+    const PdLds pl = carve_pd(smem + wave_lds_bytes(P.max_cand, P.L), D);
+    const int type = tb.env_type[e];
+    const int S = tb.n_spheres[type];
+    const float *sph = tb.spheres + (size_t)type * P.S_max * 4;
+    const float inv[3] = {tb.inv_inertia[3 * type], tb.inv_inertia[3 * type + 1], tb.inv_inertia[3 * type + 2]};
+    const float rows = load_body_rows(state, params, P.K, e);
+    int wkey;
+    float wr[3];
+    load_warm(warm, P.C_max, e, wkey, wr);
+    // the joint state by position, one joint per lane
+    float qv = 0.f, qdv = 0.f;
+    int jl = 0;
+    if (lane < D) {
+        jl = T.jat(lane);
+        qv = hstate[(size_t)jl * K + e];
+        qdv = hstate[(size_t)(D + jl) * K + e];
+        pl.zh[lane] = qv;
+        pl.nuh[lane] = qdv;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) pl.S[6 * lane + k] = 0.0;   // a joint that moves no link keeps zeros
+    }
+    wave_sync();
+    Body B;
+    body_from_rows(rows, B);
+    double *fk = reinterpret_cast<double *>(lds.cand_d);
+    pd_fk(P, Q, T, tb.hand, fk, pl, lds.seg);
+    pd_mass(P, Q, T, fk, pl, u, (double)qv);
+    pd_twists(D, B.x, pl);
+    StepStats st = {0, 0, 0};
+    StepState<double> sst;
+    step_setup<double>(P, lds.seg, sph, S, inv, B, wkey, wr, lds, st, sst);
+    int pos, nseg;
+    pd_order_contacts(sst, pl, pos, nseg);
+    step_solve_pd(P, Q, T, sst, B.mu, inv, reinterpret_cast<double *>(lds.cand_d), pl, pos, nseg);
+    int link;
+    float imp[3];
+    step_finish<double>(P, sst, inv, B, wkey, wr, link, imp);
+    if (lane < D) {
+        const double w = pl.nuh[lane];
+        hstate[(size_t)jl * K + e] = (float)((double)qv + (double)P.dt * w);
+        hstate[(size_t)(D + jl) * K + e] = (float)w;
+    }
+    store_body(state, params, P.K, e, B);
+    store_warm(warm, P.C_max, e, wkey, wr);
+    if (lane < P.C_max)
+        *reinterpret_cast<float4 *>(contacts + ((size_t)e * P.C_max + lane) * 4) =
+            make_float4(__int_as_float(link), imp[0], imp[1], imp[2]);
+    flush_stats(stats, st, 1, e);
+}
+
+// one wavefront per simulation, lanes over sensors, then over joints:
+// obs rows [4][L] of force terms followed by the D joint angles
+__global__ __launch_bounds__(256) void k_observe_pd(Consts P, const float *__restrict__ contacts,
+                                                    const float *__restrict__ hstate, float *__restrict__ obs)
+{
+    __shared__ __align__(16) float stage[4][WAVE * 4];
+    const int wib = threadIdx.x / WAVE;
+    const int e = xcd_block(blockIdx.x, gridDim.x) * (blockDim.x / WAVE) + wib;
+    if (e >= P.K) return;
+    const int lane = lane_id();
+    float *sg = stage[wib];
+    if (lane < P.C_max)
+        *reinterpret_cast<float4 *>(sg + 4 * lane) =
+            *reinterpret_cast<const float4 *>(contacts + ((size_t)e * P.C_max + lane) * 4);
+    wave_sync();
+    const size_t LK = (size_t)P.L * P.K;
+    float o[7];
+    if (sensor_force(P, sg, o)) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) obs[j * LK + (size_t)lane * P.K + e] = o[j];
+    }
+    for (int j = lane; j < P.D; j += WAVE) obs[4 * LK + (size_t)j * P.K + e] = hstate[(size_t)j * P.K + e];
+}
+
+// one thread per simulation: the sensors' terms in sensor order (as k_cost),
+// then the joints' w_q (q_j - q_gt_j)^2 in joint order; obs_gt [4L + D][G]
+__global__ __launch_bounds__(256) void k_cost_pd(Consts P, PdConsts Q, const int32_t *__restrict__ group_of,
+                                                 const float *__restrict__ obs, const float *__restrict__ obs_gt,
+                                                 float *cost_sum)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= P.K) return;
+    const int g = P.G == 1 ? 0 : group_of[e];
+    const size_t LK = (size_t)P.L * P.K, LG = (size_t)P.L * P.G;
+    float cs = 0.f;
+    for (int l = 0; l < P.L; ++l) {
+        float o[4], gt[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            o[j] = obs[j * LK + (size_t)l * P.K + e];
+            gt[j] = obs_gt[j * LG + (size_t)l * P.G + g];
+        }
+        cs += sensor_cost(P, o, gt);
+    }
+    for (int j = 0; j < P.D; ++j) {
+        const float d = obs[4 * LK + (size_t)j * P.K + e] - obs_gt[4 * LG + (size_t)j * P.G + g];
+        cs += Q.w_q * d * d;
+    }
+    cost_sum[e] += cs;
+}
+
+// joint state rows of every resampled simulation from its parent (parents
+// are elites, which the resampler leaves unchanged: every copy reads rows
+// nothing here writes)
+__global__ __launch_bounds__(256) void k_copy_hand(int K, int rows, const int32_t *__restrict__ parent,
+                                                   float *__restrict__ hstate)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= K) return;
+    const int p = parent[e];
+    if (p < 0) return;
+    for (int r = 0; r < rows; ++r) hstate[(size_t)r * K + e] = hstate[(size_t)r * K + p];
+}
+
+}  // namespace pt
+
+using namespace pt;
+
+size_t pd_wave_lds_bytes(int max_cand, int L, int D) { return wave_lds_bytes(max_cand, L) + pd_lds_bytes(D); }
+
+hipError_t set_pd_lds_limits(size_t bytes) { return set_dynamic_lds_limit((const void *)k_step_pd, bytes); }
+
+hipError_t launch_step_pd(const Consts &P, const PdConsts &Q, const Tables &tb, const int32_t *pd_tab,
+                          const float *u, float *state, float *params, float *warm, float *hstate, float *contacts,
+                          int64_t *stats, hipStream_t s)
+{
+    const PdTab T = {pd_tab, P.D, P.L};
+    const size_t lds = pd_wave_lds_bytes(P.max_cand, P.L, P.D);
+    hipLaunchKernelGGL(k_step_pd, dim3(P.K), dim3(WAVE), lds, s, P, Q, tb, T, u, state, params, warm, hstate,
+                       contacts, stats);
+    return hipGetLastError();
+}
+
+hipError_t launch_observe_pd(const Consts &P, const float *contacts, const float *hstate, float *obs,
+                             hipStream_t s)
+{
+    const int blocks = (P.K + 3) / 4;
+    hipLaunchKernelGGL(k_observe_pd, dim3(blocks), dim3(4 * WAVE), 0, s, P, contacts, hstate, obs);
+    return hipGetLastError();
+}
+
+hipError_t launch_cost_pd(const Consts &P, const PdConsts &Q, const int32_t *group_of, const float *obs,
+                          const float *obs_gt, float *cost_sum, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_cost_pd, dim3((P.K + 255) / 256), dim3(256), 0, s, P, Q, group_of, obs, obs_gt, cost_sum);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_hand(int K, int rows, const int32_t *parent, float *hstate, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_copy_hand, dim3((K + 255) / 256), dim3(256), 0, s, K, rows, parent, hstate);
+    return hipGetLastError();
+}

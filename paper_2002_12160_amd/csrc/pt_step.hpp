@@ -32,6 +32,8 @@ struct StepState {
     SR ucst[3];        // -F v_link + (b_n, 0, 0)
     SR r[3];           // impulse
     SR nu[6];          // body velocity after the solve (fresh sum)
+    SR psi_end;        // merit |Phi|^2 / 2 at the returned impulses (0 without
+                       // contacts, -1 if no iteration ran)
 };
 
 // M^-1 J^T x summed over contacts, for an impulse x held by this lane
@@ -538,6 +540,7 @@ __device__ __forceinline__ void step_solve(const Consts &P, StepState<SR> &st, f
     body_dv(st, r, nu);
     nu[0] += st.vs[0]; nu[1] += st.vs[1]; nu[2] += st.vs[2];
     nu[3] += st.ws[0]; nu[4] += st.ws[1]; nu[5] += st.ws[2];
+    st.psi_end = st.C > 0 && P.newton_iters == 0 ? SR(-1) : SR(0);
     if (st.C > 0) {
         // relative velocity and FB value at the current impulses; after the
         // first iteration they are those of the line search's accepted trial
@@ -647,6 +650,7 @@ __device__ __forceinline__ void step_solve(const Consts &P, StepState<SR> &st, f
                 const bool act2 = half_bcast((uint32_t)act, false) != 0u;
                 const bool up = lane_id() >= 32;
                 bool from_upper = true;   // 1/8, the fallback, is the upper half's last trial
+                SR psi_acc = SR(0);
                 for (int t = 0; t < 2; ++t) {
                     const SR alo = t == 0 ? SR(1) : SR(0.25), ahi = SR(0.5) * alo;
                     const SR a = up ? ahi : alo;
@@ -664,10 +668,13 @@ __device__ __forceinline__ void step_solve(const Consts &P, StepState<SR> &st, f
                     if (slo <= (SR(1) - SR(2) * SR(P.armijo_sigma) * alo) * psi) {
                         alpha = alo;
                         from_upper = false;
+                        psi_acc = slo;
                         break;
                     }
+                    psi_acc = shi;
                     if (shi <= (SR(1) - SR(2) * SR(P.armijo_sigma) * ahi) * psi) { alpha = ahi; break; }
                 }
+                st.psi_end = psi_acc;
                 if (from_upper) {
 #pragma unroll
                     for (int i = 0; i < 3; ++i) {
@@ -695,6 +702,7 @@ __device__ __forceinline__ void step_solve(const Consts &P, StepState<SR> &st, f
                                               ft.phi[2] * ft.phi[2])
                                  : SR(0);
                     ptr = wave_sum1(ptr, span);
+                    st.psi_end = ptr;    // the last trial evaluated is the one taken
                     if (ptr <= (SR(1) - SR(2) * SR(P.armijo_sigma) * a) * psi) { alpha = a; break; }
                 }
             }

@@ -58,6 +58,8 @@ class BatchDesc(C.Structure):
         ("state", C.c_void_p), ("params", C.c_void_p), ("warm", C.c_void_p),
         ("window_checkpoints", C.c_int32),
         ("cost_mode", C.c_int32), ("tau_slip", C.c_float), ("tau_spin", C.c_float), ("w_eq3", C.c_float * 7),
+        ("hand_mode", C.c_int32), ("kp", C.c_float), ("kd", C.c_float), ("link_mass", C.c_float),
+        ("w_q", C.c_float), ("hand_state", C.c_void_p),
     ]
 
 
@@ -77,7 +79,7 @@ _lib.pt_run_window_static.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp]
 _lib.pt_autotune.argtypes = [_vp, _vp, _vp, C.POINTER(C.c_int32), _vp]
 _lib.pt_read_stats.argtypes = [_vp, C.POINTER(C.c_int64), _vp]
 _lib.pt_set_tuning.argtypes = [_vp, C.c_int32]
-_lib.pt_window_grad.argtypes = [_vp, _vp, _vp, C.c_int32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+_lib.pt_window_grad.argtypes = [_vp, _vp, _vp, C.c_int32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
 _lib.pt_refine_elites.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp, C.c_int32, C.c_float, _vp, _vp, _vp, _vp]
 _lib.pt_elite_count.argtypes = [_vp]
 _lib.pt_elite_count.restype = C.c_int32
@@ -167,10 +169,11 @@ def pt_set_tuning(h, waves_per_workgroup):
 
 
 def pt_window_grad(h, u_win, obs_gt_win, env, start, warm0, cost, grad=None, end_state=None, end_warm=None,
-                   stream=None):
+                   resid=None, stream=None):
     n = int(env.shape[0])
     _check(_lib.pt_window_grad(h, _ptr(u_win), _ptr(obs_gt_win), n, _ptr(env), _ptr(start), _ptr(warm0), _ptr(cost),
-                               _ptr(grad), _ptr(end_state), _ptr(end_warm), _stream(stream)), "pt_window_grad")
+                               _ptr(grad), _ptr(end_state), _ptr(end_warm), _ptr(resid), _stream(stream)),
+           "pt_window_grad")
 
 
 def pt_refine_elites(h, u_win, obs_gt_win, cost_sum, start_state, start_params, start_warm, steps=3, step=0.5,
@@ -201,11 +204,13 @@ def pt_read_stats(h, stream=None):
 
 class Batch:
     """A population of simulations on one device: the handle plus the state
-    tensors it is bound to (state [13][K], params [5][K], warm [K][C_max][4])."""
+    tensors it is bound to (state [13][K], params [5][K], warm [K][C_max][4],
+    and with the PD-controlled hand (consts.hand_mode 1) hand_state [2D][K]:
+    joint angles, then joint rates)."""
 
     def __init__(self, *, hand, spheres, n_spheres, inv_inertia, env_type, group_start, consts, C_max,
                  newton_iters, T, state, params, resample=None, solve_precision=64, window_checkpoints=False,
-                 device="cuda"):
+                 hand_state=None, device="cuda"):
         self.device = torch.device(device)
         K = int(np.asarray(env_type).shape[0])
         self.K, self.C_max, self.T = K, int(C_max), int(T)
@@ -223,6 +228,12 @@ class Batch:
         self.warm = torch.empty((K, self.C_max, 4), dtype=torch.float32, device=self.device)
         self.set_state(state, params)
         self.clear_warm()
+        self.hand_mode = int(getattr(consts, "hand_mode", 0))
+        self.hand_state = None
+        if self.hand_mode == 1:
+            self.hand_state = torch.zeros((2 * self.D, K), dtype=torch.float32, device=self.device)
+            if hand_state is not None:
+                self.set_hand(hand_state)
         d = BatchDesc()
         d.K, d.G, d.L, d.D = K, self.G, self.L, self.D
         d.n_types, d.S_max = self.spheres.shape[0], self.spheres.shape[1]
@@ -255,6 +266,10 @@ class Batch:
         for i, wv in enumerate(getattr(consts, "w_eq3", (1.0,) * 7)):
             d.w_eq3[i] = wv
         self.obs_rows = 7 if d.cost_mode == 1 else 4
+        d.hand_mode = self.hand_mode
+        d.kp, d.kd = getattr(consts, "kp", 0.0), getattr(consts, "kd", 0.0)
+        d.link_mass, d.w_q = getattr(consts, "link_mass", 0.0), getattr(consts, "w_q", 0.0)
+        d.hand_state = self.hand_state.data_ptr() if self.hand_state is not None else None
         self.desc = d
         self.handle = pt_create_batch(d)
 
@@ -295,6 +310,14 @@ class Batch:
         w = self.warm.cpu().numpy()
         return np.ascontiguousarray(w[:, :, 0]).view(np.int32).copy(), w[:, :, 1:].astype(np.float64)
 
+    def set_hand(self, hand_state):
+        """Joint state from a host array [K][2D] (angles, then rates)."""
+        self.hand_state.copy_(torch.as_tensor(np.ascontiguousarray(np.asarray(hand_state, dtype=np.float32).T)))
+
+    def get_hand(self):
+        torch.cuda.synchronize(self.device)
+        return self.hand_state.cpu().numpy().T.astype(np.float64)
+
     def clear_warm(self):
         self.set_warm(np.full((self.K, self.C_max), -1, dtype=np.int32), np.zeros((self.K, self.C_max, 3)))
 
@@ -322,25 +345,33 @@ class Batch:
         self._need(obs_gt_win, (self.T, self.obs_rows, self.L, self.G), "obs_gt_win")
 
     # -- the hot path ------------------------------------------------------
+    def obs_shape(self, n):
+        """Shape of an observation of n simulations: [R][L][n], or with the
+        PD hand [4L + D][n] (force rows, then the joint angles)."""
+        if self.hand_mode == 1:
+            return (4 * self.L + self.D, n)
+        return (self.obs_rows, self.L, n)
+
     def new_obs(self, T=None):
-        shape = (self.obs_rows, self.L, self.K) if T is None else (T, self.obs_rows, self.L, self.K)
+        shape = self.obs_shape(self.K) if T is None else (T, self.obs_rows, self.L, self.K)
         return torch.zeros(shape, dtype=torch.float32, device=self.device)
 
     def step(self, u_prev, u, stream=None):
-        self._need_cmd(u_prev, (self.D,), "u_prev")
+        if self.hand_mode != 1:
+            self._need_cmd(u_prev, (self.D,), "u_prev")
         self._need_cmd(u, (self.D,), "u")
         pt_step(self.handle, u_prev, u, stream)
 
     def observe(self, obs=None, stream=None):
         if obs is None:
             obs = self.new_obs()
-        self._need(obs, (self.obs_rows, self.L, self.K), "obs")
+        self._need(obs, self.obs_shape(self.K), "obs")
         pt_observe(self.handle, obs, stream)
         return obs
 
     def cost(self, obs, obs_gt, cost_sum, best=None, stream=None):
-        self._need(obs, (self.obs_rows, self.L, self.K), "obs")
-        self._need(obs_gt, (self.obs_rows, self.L, self.G), "obs_gt")
+        self._need(obs, self.obs_shape(self.K), "obs")
+        self._need(obs_gt, self.obs_shape(self.G), "obs_gt")
         self._need(cost_sum, (self.K,), "cost_sum")
         self._need(best, (self.G,), "best", torch.int32)
         pt_cost(self.handle, obs, obs_gt, cost_sum, best, stream)
@@ -396,8 +427,13 @@ class Batch:
         idx = env.long()
         return torch.cat([state[:, idx], params[:, idx]]).contiguous(), warm[idx].contiguous()
 
-    def window_grad(self, u_win, obs_gt_win, env, start, warm0, want_grad=True, want_end=False, stream=None):
+    def window_grad(self, u_win, obs_gt_win, env, start, warm0, want_grad=True, want_end=False, resid=None,
+                    stream=None):
+        """(cost, grad, end_state, end_warm) of the listed simulations'
+        windows; resid (a [n] float32 tensor, optional) receives the
+        largest final merit of each window's contact solves."""
         n = int(env.shape[0])
+        self._need(resid, (n,), "resid")
         self._need_window(u_win, obs_gt_win)
         self._need(env, (n,), "env", torch.int32)
         self._need(start, (18, n), "start")
@@ -407,7 +443,8 @@ class Batch:
         grad = torch.empty((18, n), dtype=torch.float32, device=dev) if want_grad else None
         end_state = torch.empty((13, n), dtype=torch.float32, device=dev) if want_end else None
         end_warm = torch.empty((n, self.C_max, 4), dtype=torch.float32, device=dev) if want_end else None
-        pt_window_grad(self.handle, u_win, obs_gt_win, env, start, warm0, cost, grad, end_state, end_warm, stream)
+        pt_window_grad(self.handle, u_win, obs_gt_win, env, start, warm0, cost, grad, end_state, end_warm, resid,
+                       stream)
         return cost, grad, end_state, end_warm
 
     def snapshot(self):

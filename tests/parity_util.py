@@ -152,6 +152,47 @@ class Probes:
                     clear=reason == "", tie=tie & (reason == "cap-tie"), reason=reason)
 
 
+    def step_pd(self, env_type, u, st64, pr64, hq64, wk, wr64):
+        """The same for a step of the PD-controlled hand (hq64 [n][2D]: joint
+        angles and rates, floors 1 rad and 1 rad/s).  Returns the dict of
+        step() with hq (the reference joint state) added."""
+        o = self.o
+        n = st64.shape[0]
+        B = [f32(st64), f32(pr64), f32(hq64), wk.copy(), f32(wr64)]
+        obs_b, cont_b, dg = o.batch_step_pd(env_type, u, *B, want_contacts=True, want_diag=True)
+        A = [st64.copy(), pr64.copy(), hq64.copy(), wk.copy(), wr64.copy()]
+        o.batch_step_pd(env_type, u, *A)
+        mass = B[1][:, 0]
+        reason = np.array([""] * n, dtype=object)
+
+        def flag(mask, why):
+            for i in np.nonzero(mask & (reason == ""))[0]:
+                reason[i] = why
+
+        def err(X, Y):
+            return np.maximum(rel_err(X[0], Y[0]).max(axis=1), hand_err(X[2], Y[2]).max(axis=1))
+
+        flag(~((err(A, B) < CHAOS_TOL) & same_keys(A[3], B[3])), "state-rounding")
+        for k, og in enumerate(self.g):
+            Cq = [f32(st64), f32(pr64), f32(hq64), wk.copy(), f32(wr64)]
+            obs_c, _, _ = og.batch_step_pd(env_type, u, *Cq)
+            ok = (err(Cq, B) <= PROBE_TOL) & same_keys(Cq[3], B[3]) & \
+                obs_close(obs_c, obs_b, mass, o.consts.tau_contact, PROBE_TOL)
+            flag(~ok, f"geometry-probe-{k + 1}")
+        flag(dg["armijo_margin"] < ARMIJO_BAND, "armijo")
+        flag(np.abs(dg["margin_gap"]) < GAP_BAND, "margin")
+        flag(dg["tangent_tie"] < TANGENT_BAND, "tangent-axis")
+        tie = cap_tie(dg)
+        flag(tie, "cap-tie")
+        return dict(st=B[0], pr=B[1], hq=B[2], wkey=B[3], wr=B[4], obs=obs_b, cont=cont_b, diag=dg,
+                    clear=reason == "", tie=tie & (reason == "cap-tie"), reason=reason)
+
+
+def hand_err(a, b):
+    """Relative error of joint states [n][2D] with floors 1 rad, 1 rad/s."""
+    return np.abs(a - b) / np.maximum(np.abs(b), 1.0)
+
+
 def describe(ref, j):
     """One line with the decision margins of env j of a reference step."""
     d = ref["diag"][j]

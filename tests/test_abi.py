@@ -124,7 +124,7 @@ def test_gradient_calls_reject_a_null_batch(lib):
     lib.pt_refine_elites.restype = C.c_int
     lib.pt_elite_count.restype = C.c_int32
     lib.pt_elite_count.argtypes = [C.c_void_p]
-    assert lib.pt_window_grad(None, None, None, 0, None, None, None, None, None, None, None, None) == 1
+    assert lib.pt_window_grad(None, None, None, 0, None, None, None, None, None, None, None, None, None) == 1
     assert lib.pt_refine_elites(None, None, None, None, None, None, None, 3, C.c_float(0.5), None, None, None,
                                 None) == 1
     assert lib.pt_elite_count(None) == -1
@@ -161,3 +161,73 @@ def test_binding_checks_buffer_shapes_before_the_call():
     with pytest.raises(pt.PtError):
         b._need(np.zeros(8, np.float32), (8,), "cost_sum")
     b._need(None, (8,), "optional")
+
+
+def _pd_desc(pt, keep):
+    d = _valid_desc(pt, keep)
+    d.hand_mode, d.kp, d.kd, d.link_mass, d.w_q = 1, 1.5, 0.05, 0.03, 100.0
+    keep["hs"] = np.zeros((2 * d.D, 8), np.float32)
+    d.hand_state = keep["hs"].ctypes.data
+    return d
+
+
+def _create_rc(pt, d):
+    h = C.c_void_p()
+    rc = pt._lib.pt_create_batch(C.byref(d), C.byref(h))
+    if rc == 0:
+        pt._lib.pt_destroy_batch(h)
+    return rc
+
+
+def test_pd_hand_descriptor_passes_validation(lib):
+    # without a GPU the call gets as far as the first device call (PT_E_HIP)
+    pt = _desc_module()
+    keep = {}
+    assert _create_rc(pt, _pd_desc(pt, keep)) in (0, 2)
+
+
+@pytest.mark.parametrize("field,value,code", [
+    ("hand_mode", 2, 1), ("kp", -1.0, 1), ("kd", float("nan"), 1), ("link_mass", 0.0, 1), ("w_q", -1.0, 1),
+    ("solve_precision", 32, 5), ("cost_mode", 1, 5), ("hand_state", None, 1),
+])
+def test_pd_hand_descriptor_validation(lib, field, value, code):
+    pt = _desc_module()
+    keep = {}
+    d = _pd_desc(pt, keep)
+    setattr(d, field, value)
+    assert _create_rc(pt, d) == code
+    assert len(pt._lib.pt_last_error()) > 0
+
+
+def test_pd_hand_needs_stiffness_or_damping(lib):
+    pt = _desc_module()
+    keep = {}
+    d = _pd_desc(pt, keep)
+    d.kp, d.kd = 0.0, 0.0
+    assert _create_rc(pt, d) == 1
+
+
+def test_pd_hand_structure_limits(lib):
+    pt = _desc_module()
+    keep = {}
+    d = _pd_desc(pt, keep)
+    # a joint driving two links
+    keep["hand"][1, 1] = keep["hand"][0, 1]
+    assert _create_rc(pt, d) == 5
+    assert b"drives links" in pt._lib.pt_last_error()
+    # a chain of seven links with one joint each: one group of seven joints
+    chain = np.zeros((7, 20), np.float32)
+    for l in range(7):
+        chain[l, 0] = l - 1
+        chain[l, 1], chain[l, 2] = l, -1
+        chain[l, 4] = 1.0
+        chain[l, 12] = 1.0
+        chain[l, 16], chain[l, 17] = 0.02, 0.005
+    keep["chain"] = chain
+    keep["hs7"] = np.zeros((14, 8), np.float32)
+    d.hand, d.L, d.D, d.hand_state = chain.ctypes.data, 7, 7, keep["hs7"].ctypes.data
+    assert _create_rc(pt, d) == 5
+    assert b"group" in pt._lib.pt_last_error()
+    chain[6, 1] = -1            # six joints in the chain: within the limit
+    d.D = 6
+    assert _create_rc(pt, d) in (0, 2)

@@ -3,14 +3,17 @@ with implicit differentiation of the contact solve) against central finite
 differences of the FP64 oracle's window cost; the forward sweep against
 pt_run_window; torch.autograd through WindowFn; the elite refinement.
 
-Finite-difference reference: the oracle in converged mode (Newton run to
-|Phi|^2 < 1e-26, so its window cost is the exact function the implicit
-adjoint differentiates), central differences with h = 1e-6 per start
-component (cold warm start on both sides).  A component is compared where
-the window map is smooth across the stencil: the h and 4h differences agree
-to 1e-4 of the environment's largest gradient entry (a contact that appears
-or vanishes inside the stencil breaks this).  Bar: |g - fd| <= 1e-3 |fd| +
-1e-3 max|fd| over the environment's 18 components."""
+Finite-difference reference: central differences with h = 1e-6 per start
+component (cold warm start on both sides), of the oracle in converged mode
+(Newton run to |Phi|^2 < 1e-26, so its window cost is the exact function the
+implicit adjoint differentiates), or in fixed-N mode at the production
+iteration count on windows whose solves the GPU reports as converged.  A
+component is compared where the window map is smooth across the stencil:
+the h and 4h differences agree to 1e-2 of the difference itself (plus the
+rounding floor); a contact that appears or vanishes inside the stencil
+breaks this.  Bar, per component: |g - fd| <= 1e-3 |fd| + |fd_h - fd_4h| +
+floor, with floor = 1e-8 max(window cost, 1) (the rounding error of a
+central difference at h = 1e-6)."""
 from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
@@ -68,10 +71,11 @@ def _gpu_inputs(st0, pr0, gt, u_win, C_max):
     return start, _cold_warm(st0.shape[0], C_max), u_t, gt_t
 
 
-def oracle_fd(sc, st0, pr0, gt, u_win, envs, h=FD_H):
-    """Central differences of the converged oracle's window cost: returns the
-    base costs, fd(h) and fd(4h), each [n][18]."""
-    o = oracle.Oracle.from_scene(sc, converged=True)
+def oracle_fd(sc, st0, pr0, gt, u_win, envs, h=FD_H, converged=True):
+    """Central differences of the oracle's window cost (converged mode, or
+    fixed-N at the scene's iteration count): returns the base costs, fd(h)
+    and fd(4h), each [n][18]."""
+    o = oracle.Oracle.from_scene(sc, converged=converged)
     g_of = np.searchsorted(sc.group_start, np.arange(sc.K), side="right") - 1
 
     def wc(j, x):
@@ -98,19 +102,42 @@ def oracle_fd(sc, st0, pr0, gt, u_win, envs, h=FD_H):
             fp[(a, c, s)] = v
     fd1 = np.zeros((n, 18))
     fd4 = np.zeros((n, 18))
+    kink = np.zeros((n, 18))
     for a in range(n):
         for c in range(18):
             fd1[a, c] = (fp[(a, c, h)] - fp[(a, c, -h)]) / (2 * h)
             fd4[a, c] = (fp[(a, c, 4 * h)] - fp[(a, c, -4 * h)]) / (8 * h)
-    return base, fd1, fd4
+            # forward minus backward slope: a kink at the start shows here
+            # even when the two central differences straddle it alike
+            kink[a, c] = (fp[(a, c, h)] - 2 * base[a] + fp[(a, c, -h)]) / h
+    return base, fd1, fd4, kink
 
 
-def compare_grad(g, fd1, fd4):
-    """Per (env, component): smooth?, within the bar?"""
-    scale = np.maximum(np.abs(fd1).max(axis=1, keepdims=True), 1e-12)
-    smooth = np.abs(fd1 - fd4) <= 1e-4 * scale
-    ok = np.abs(g - fd1) <= GRAD_RTOL * np.abs(fd1) + GRAD_RTOL * scale
-    return smooth, ok
+GROUPS = {"position": range(0, 3), "orientation": range(3, 7), "velocity": range(7, 10),
+          "angular velocity": range(10, 13), "mass": range(13, 14), "friction": range(14, 15),
+          "force": range(15, 18)}
+
+
+def compare_grad(g, fd1, fd4, base, kink, f32_floor=False):
+    """Per (env, component): smooth?, within the bar?, and the floor.
+
+    The floor is 1e-8 of the cost (the finite differences' own resolution).
+    With f32_floor it is eight float32 ulps of the cost instead: where a
+    component vanishes analytically (a sphere's cost does not depend on its
+    orientation) the GPU, which keeps geometry and state in float32, leaves
+    rounding noise of ~1e-7 of the cost there."""
+    rel = 8 * float(np.finfo(np.float32).eps) if f32_floor else 1e-8
+    floor = rel * np.maximum(np.abs(base), 1.0)[:, None]
+    smooth = (np.abs(fd1 - fd4) <= 1e-2 * np.abs(fd1) + floor) & (np.abs(kink) <= 1e-2 * np.abs(fd1) + 2 * floor)
+    ok = np.abs(g - fd1) <= GRAD_RTOL * np.abs(fd1) + np.abs(fd1 - fd4) + floor
+    return smooth, ok, floor
+
+
+def checked_groups(smooth, fd1, floor):
+    """Parameter groups with at least one smooth component clearly above
+    its floor somewhere (so that the group is checked, not only bounded)."""
+    big = smooth & (np.abs(fd1) > 100 * floor)
+    return {name: bool(big[:, list(cols)].any()) for name, cols in GROUPS.items()}
 
 
 @pytest.mark.parametrize("cfg_name,K,W0", [("adjoint1024", 8, 15), ("small", 8, 20)])
@@ -123,23 +150,81 @@ def test_window_grad_matches_oracle_fd(pt, cfg_name, K, W0):
     b = pt.Batch.from_scene(sc, T=T, newton_iters=100)
     start, warm0, u_t, gt_t = _gpu_inputs(st0, pr0, gt, u_win, sc.cfg.C_max)
     env = torch.arange(K, dtype=torch.int32, device="cuda")
-    cost, grad, _, _ = b.window_grad(u_t, gt_t, env, start, warm0)
+    resid = torch.empty(K, device="cuda")
+    cost, grad, _, _ = b.window_grad(u_t, gt_t, env, start, warm0, resid=resid)
     torch.cuda.synchronize()
     g = grad.cpu().numpy().T.astype(np.float64)          # [K][18]
     c_gpu = cost.cpu().numpy().astype(np.float64)
+    res = resid.cpu().numpy().astype(np.float64)
     b.close()
-    base, fd1, fd4 = oracle_fd(sc, st0, pr0, gt, u_win, list(range(K)))
-    smooth, ok = compare_grad(g, fd1, fd4)
+    base, fd1, fd4, kink = oracle_fd(sc, st0, pr0, gt, u_win, list(range(K)))
+    smooth, ok, floor = compare_grad(g, fd1, fd4, base, kink)
     names = ["x0", "x1", "x2", "qw", "qx", "qy", "qz", "v0", "v1", "v2", "w0", "w1", "w2", "m", "mu", "f0", "f1", "f2"]
     for a in range(K):
         bad = [f"{names[c]}: gpu {g[a, c]:.6e} fd {fd1[a, c]:.6e} (4h {fd4[a, c]:.6e})"
                for c in range(18) if smooth[a, c] and not ok[a, c]]
-        _say(f"env {a}: cost gpu {c_gpu[a]:.6e} oracle {base[a]:.6e}; smooth {int(smooth[a].sum())}/18; "
-             f"outside {len(bad)}" + ("; " + "; ".join(bad[:6]) if bad else ""))
+        _say(f"env {a}: residual {res[a]:.1e} cost gpu {c_gpu[a]:.6e} oracle {base[a]:.6e}; "
+             f"smooth {int(smooth[a].sum())}/18; outside {len(bad)}" + ("; " + "; ".join(bad[:6]) if bad else ""))
     np.testing.assert_allclose(c_gpu, base, rtol=1e-4, atol=1e-6)
-    assert smooth.sum() >= 0.75 * smooth.size, "too few smooth components to check"
-    assert np.all(ok[smooth]), f"{int((~ok & smooth).sum())} of {int(smooth.sum())} components outside the bar"
-    assert np.abs(fd1).max() > 0, "vacuous: zero gradient everywhere"
+    # the implicit gradient is the derivative of the window map where the
+    # solves reached the root; 100 iterations do not always get there from a
+    # cold start under a squeeze
+    conv = res < 1e-20
+    chk = smooth & conv[:, None]
+    groups = checked_groups(chk, fd1, floor)
+    _say(f"{int(conv.sum())} of {K} windows converged; smooth and checked {int(chk.sum())}/{smooth.size}; "
+         f"parameter groups checked: {groups}")
+    assert conv.sum() >= K // 2, "too few windows converged"
+    assert np.all(ok[chk]), f"{int((~ok & chk).sum())} of {int(chk.sum())} components outside the bar"
+    # the force rows matter only through the first step; every other group
+    # must have components well above the rounding floor that were checked
+    assert all(v for k, v in groups.items() if k != "force"), groups
+
+
+@pytest.mark.parametrize("cfg_name,W0", [("small", 35), ("adjoint1024", 30)])
+def test_window_grad_at_production_newton_iterations(pt, cfg_name, W0):
+    # The production path runs 10 Newton iterations per step.  Where every
+    # solve of the window has converged (the residual pt_window_grad reports
+    # is below 1e-20), the fixed-N window map is the converged one and the
+    # gradient must match central differences of the oracle's fixed-N window
+    # cost component by component.  Elsewhere the solves stop short of the
+    # root the implicit adjoint assumes and the gradient is that of the
+    # converged map at the start: reported (direction agreement), not
+    # asserted -- the refinement only ever keeps a trial whose replayed
+    # window cost is lower.
+    T, K = 10, 64
+    sc, st0, pr0, gt, u_win = window_case(cfg_name, K, W0, T)
+    N = sc.cfg.newton_iters
+    _say(f"window gradient at N={N}: {cfg_name} K={K} start step {W0}")
+    b = pt.Batch.from_scene(sc, T=T)
+    start, warm0, u_t, gt_t = _gpu_inputs(st0, pr0, gt, u_win, sc.cfg.C_max)
+    env = torch.arange(K, dtype=torch.int32, device="cuda")
+    resid = torch.empty(K, device="cuda")
+    cost, grad, _, _ = b.window_grad(u_t, gt_t, env, start, warm0, resid=resid)
+    torch.cuda.synchronize()
+    g = grad.cpu().numpy().T.astype(np.float64)
+    c_gpu = cost.cpu().numpy().astype(np.float64)
+    res = resid.cpu().numpy().astype(np.float64)
+    b.close()
+    conv = [int(i) for i in np.nonzero(res < 1e-20)[0]]
+    other = [int(i) for i in np.nonzero(res >= 1e-20)[0][:6]]
+    _say(f"{len(conv)} of {K} windows with converged solves; residual quantiles 50/90: "
+         f"{np.quantile(res, 0.5):.1e} {np.quantile(res, 0.9):.1e}")
+    envs = conv + other
+    base, fd1, fd4, kink = oracle_fd(sc, st0, pr0, gt, u_win, envs, converged=False)
+    gs = g[envs]
+    np.testing.assert_allclose(c_gpu[conv], base[:len(conv)], rtol=1e-4, atol=1e-6)
+    smooth, ok, floor = compare_grad(gs, fd1, fd4, base, kink)
+    nc = len(conv)
+    for a, i in enumerate(envs):
+        sm = smooth[a]
+        cosv = float(gs[a, sm] @ fd1[a, sm] / max(np.linalg.norm(gs[a, sm]) * np.linalg.norm(fd1[a, sm]), 1e-300))
+        _say(f"env {i}: residual {res[i]:.1e} cost {c_gpu[i]:.4e}; smooth {int(sm.sum())}/18, "
+             f"{int((ok[a] & sm).sum())} within the bar, cosine to the fixed-N differences {cosv:.4f}")
+    # in these scenes a window whose ten-iteration solves all converge is
+    # one without a sensed contact (its gradient is zero); the converged
+    # windows with contact are pinned by the single-contact test below
+    assert np.all(ok[:nc][smooth[:nc]]), f"{int((~ok[:nc] & smooth[:nc]).sum())} components outside the bar"
 
 
 def test_window_grad_without_contact_is_zero(pt):
@@ -411,3 +496,87 @@ def test_window_grad_resting_sphere_analytic(pt):
     # order), does not change the gap
     assert abs(gr[0]) <= 1e-4 * abs(want[2]) and abs(gr[1]) <= 1e-4 * abs(want[2])
     b.close()
+
+
+def test_window_grad_at_production_iterations_single_contact(pt):
+    # A solid ball resting on a horizontal sensor link far above the table;
+    # the link tilts on its joint (0.06 rad sinusoid), so the ball rolls and
+    # slides on it.  One contact: ten Newton iterations converge (the
+    # reported residual shows it), so at the production iteration count the
+    # fixed-N window map is the converged one, and the gradient must match
+    # central differences of the oracle's fixed-N window cost, component by
+    # component, with the per-component bar.
+    from tests import tiny
+    T, N, K = 10, 10, 8
+    rho, R, z0 = 0.01, 0.008, 0.5
+    row = tiny.link_row((-0.05, 0.0, z0), (0.05, 0.0, z0), R, joint=0, axis=(0.0, 1.0, 0.0))
+    hand = PU.f32(np.array([row]))
+    ii = 1.0 / (0.4 * rho * rho)
+    sph = PU.f32(np.array([[[0.0, 0.0, 0.0, rho]]]))
+    nsph, inv = np.array([1], np.int32), PU.f32(np.array([[ii, ii, ii]]))
+    c = tiny.consts()
+    rng = np.random.default_rng(31)
+    st = np.zeros((K, 13))
+    st[:, 0] = 0.02 + rng.normal(scale=0.003, size=K)
+    st[:, 2] = z0 + R + rho - 1e-4
+    st[:, 3] = 1.0
+    st[:, 7:10] = rng.normal(scale=0.02, size=(K, 3))
+    st[:, 10:13] = rng.normal(scale=0.5, size=(K, 3))
+    pr = np.zeros((K, 5))
+    pr[:, 0] = rng.uniform(0.05, 0.2, size=K)
+    pr[:, 1] = rng.uniform(0.2, 0.6, size=K)
+    st, pr = PU.f32(st), PU.f32(pr)
+    u_win = PU.f32(0.06 * np.sin(np.arange(T + 1)[:, None] * 0.4 + 0.3))     # [T+1][1]
+    o = oracle.Oracle(hand, sph, nsph, inv, c, C_max=4, newton_iters=N, D=1, converged=False)
+    # the observed forces: the first simulation with the observed parameters
+    hs, hp = st[:1].copy(), pr[:1].copy()
+    hp[0, :2] = (0.1, 0.4)
+    hk, hr = o.new_warm(1)
+    gts = []
+    for t in range(T):
+        obs, _, _ = o.batch_step(np.zeros(1, np.int32), u_win[t], u_win[t + 1], hs, hp, hk, hr)
+        gts.append(PU.f32(obs[0]))
+    gt = np.array(gts)                                                    # [T][L][4]
+    b = pt.Batch(hand=hand, spheres=sph, n_spheres=nsph, inv_inertia=inv, env_type=np.zeros(K, np.int32),
+                 group_start=np.array([0, K], np.int32), consts=c, C_max=4, newton_iters=N, T=T, state=st, params=pr)
+    start = torch.as_tensor(np.concatenate([st.T, pr.T]).astype(np.float32), device="cuda").contiguous()
+    warm0 = _cold_warm(K, 4)
+    u_t = torch.as_tensor(u_win.astype(np.float32), device="cuda")
+    gt_t = torch.as_tensor(gt[:, None].transpose(0, 3, 2, 1).astype(np.float32).copy(), device="cuda")
+    env = torch.arange(K, dtype=torch.int32, device="cuda")
+    resid = torch.empty(K, device="cuda")
+    cost, grad, _, _ = b.window_grad(u_t, gt_t, env, start, warm0, resid=resid)
+    torch.cuda.synchronize()
+    g = grad.cpu().numpy().T.astype(np.float64)
+    c_gpu = cost.cpu().numpy().astype(np.float64)
+    res = resid.cpu().numpy().astype(np.float64)
+    b.close()
+    h = FD_H
+    base = np.zeros(K)
+    fd1, fd4, kink = np.zeros((K, 18)), np.zeros((K, 18)), np.zeros((K, 18))
+    for a in range(K):
+        x0 = np.concatenate([st[a], pr[a]])
+        wc = lambda x: o.window_cost(0, x[:13], x[13:], u_win, gt)     # noqa: E731
+        base[a] = wc(x0)
+        for ci in range(18):
+            f = {}
+            for sft in (h, -h, 4 * h, -4 * h):
+                x = x0.copy()
+                x[ci] += sft
+                f[sft] = wc(x)
+            fd1[a, ci] = (f[h] - f[-h]) / (2 * h)
+            fd4[a, ci] = (f[4 * h] - f[-4 * h]) / (8 * h)
+            kink[a, ci] = (f[h] - 2 * base[a] + f[-h]) / h
+    smooth, ok, floor = compare_grad(g, fd1, fd4, base, kink, f32_floor=True)
+    names = ["x0", "x1", "x2", "qw", "qx", "qy", "qz", "v0", "v1", "v2", "w0", "w1", "w2", "m", "mu", "f0", "f1", "f2"]
+    for a in range(K):
+        bad = [f"{names[ci]}: gpu {g[a, ci]:.6e} fd {fd1[a, ci]:.6e}" for ci in range(18) if smooth[a, ci] and not ok[a, ci]]
+        _say(f"env {a}: residual {res[a]:.1e} cost gpu {c_gpu[a]:.6e} oracle {base[a]:.6e}; max |fd| "
+             f"{np.abs(fd1[a]).max():.2e}; smooth {int(smooth[a].sum())}/18; outside {len(bad)}" + ("; " + "; ".join(bad) if bad else ""))
+    np.testing.assert_allclose(c_gpu, base, rtol=1e-4, atol=1e-6)
+    assert np.all(res < 1e-20), res
+    groups = checked_groups(smooth, fd1, floor)
+    _say(f"parameter groups checked: {groups}")
+    # a sphere's cost does not depend on its orientation
+    assert all(v for k, v in groups.items() if k != "orientation"), groups
+    assert np.all(ok[smooth]), f"{int((~ok & smooth).sum())} of {int(smooth.sum())} components outside the bar"
