@@ -47,6 +47,8 @@ class Model(C.Structure):
         ("cost_mode", C.c_int32), ("tau_slip", C.c_double), ("tau_spin", C.c_double), ("w_eq3", C.c_double * 7),
         ("geom_f32", C.c_int32),
         ("kp", C.c_double), ("kd", C.c_double), ("link_mass", C.c_double), ("w_q", C.c_double),
+        ("collision_mode", C.c_int32), ("link_samples", C.c_int32), ("sdf_n", C.c_int32),
+        ("sdf", C.POINTER(C.c_double)), ("sdf_box", C.POINTER(C.c_double)),
     ]
 
 
@@ -122,6 +124,8 @@ def lib():
         L.or_batch_step_pd.argtypes = [mp, C.c_int, ip, dp, dp, dp, dp, ip, dp, C.c_void_p, C.c_void_p, C.c_void_p]
         L.or_step_cost_pd.argtypes = [mp, dp, dp, dp, dp]
         L.or_step_cost_pd.restype = C.c_double
+        L.or_sdf_eval.argtypes = [mp, C.c_int, dp, dp]
+        L.or_sdf_eval.restype = C.c_double
         L.or_max_threads.restype = C.c_int
         L.or_set_threads.argtypes = [C.c_int]
         _lib = L
@@ -146,7 +150,8 @@ class Oracle:
     """Holds one scene description (hand, objects, constants) for the C oracle."""
 
     def __init__(self, hand, spheres, n_spheres, inv_inertia, consts, C_max, newton_iters,
-                 D=None, converged=False, conv_tol=1e-26, conv_max_iters=100, geom_f32=False):
+                 D=None, converged=False, conv_tol=1e-26, conv_max_iters=100, geom_f32=False, sdf=None,
+                 sdf_box=None):
         self.hand = np.ascontiguousarray(hand, dtype=np.float64)
         self.spheres = np.ascontiguousarray(spheres, dtype=np.float64)
         self.n_spheres = np.ascontiguousarray(n_spheres, dtype=np.int32)
@@ -179,6 +184,19 @@ class Oracle:
         m.kp, m.kd = getattr(consts, "kp", 1.5), getattr(consts, "kd", 0.05)
         m.link_mass, m.w_q = getattr(consts, "link_mass", 0.03), getattr(consts, "w_q", 100.0)
         self.hand_mode = int(getattr(consts, "hand_mode", 0))
+        # links against the objects' distance fields (grids [n_types][n][n][n], z, y, x)
+        m.collision_mode = int(getattr(consts, "collision_mode", 0))
+        m.link_samples = int(getattr(consts, "link_samples", 8))
+        self.sdf = self.sdf_box = None
+        if m.collision_mode == 1:
+            assert sdf is not None and sdf_box is not None, "collision_mode 1 needs the distance fields"
+            self.sdf = np.ascontiguousarray(sdf, dtype=np.float64)
+            self.sdf_box = np.ascontiguousarray(sdf_box, dtype=np.float64)
+            assert self.sdf.ndim == 4 and self.sdf.shape[1] == self.sdf.shape[2] == self.sdf.shape[3]
+            assert self.sdf_box.shape == (self.sdf.shape[0], 4)
+            m.sdf_n = self.sdf.shape[1]
+            m.sdf = _dp(self.sdf)
+            m.sdf_box = _dp(self.sdf_box)
         m.hand = _dp(self.hand)
         m.spheres = _dp(self.spheres)
         m.n_spheres = _ip(self.n_spheres)
@@ -193,6 +211,8 @@ class Oracle:
         cfg = scene.cfg
         kw.setdefault("C_max", cfg.C_max)
         kw.setdefault("newton_iters", cfg.newton_iters)
+        kw.setdefault("sdf", getattr(scene, "sdf", None))
+        kw.setdefault("sdf_box", getattr(scene, "sdf_box", None))
         return cls(scene.hand, scene.spheres, scene.n_spheres, scene.inv_inertia, cfg.consts, D=scene.D, **kw)
 
     # -- kinematics ------------------------------------------------------
@@ -246,6 +266,12 @@ class Oracle:
 
     # -- batch -----------------------------------------------------------
     # -- PD-controlled hand ------------------------------------------------
+    def sdf_eval(self, typ, p):
+        """(phi, gradient) of object type typ's distance field at object-frame point p."""
+        g = np.zeros(3)
+        v = lib().or_sdf_eval(C.byref(self.m), int(typ), _dp(np.ascontiguousarray(p, dtype=np.float64)), _dp(g))
+        return v, g
+
     def hand_mass(self, q):
         M = np.zeros((self.D, self.D))
         lib().or_hand_mass(C.byref(self.m), _dp(np.ascontiguousarray(q, dtype=np.float64)), _dp(M))

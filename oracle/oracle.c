@@ -228,6 +228,91 @@ static void pair_geometry(const or_model *m, const double *seg0, const double *s
     }
 }
 
+/* Signed distance field of object type `type` at object-frame point p and
+ * its gradient g: trilinear interpolation of the grid nodes (exact for
+ * affine fields); outside the grid's box, the value at the nearest box
+ * point plus the distance to it, with that point's gradient. */
+static double sdf_eval(const or_model *m, int type, const double *p, double *g)
+{
+    const int n = m->sdf_n;
+    const double *box = m->sdf_box + 4 * type;
+    const double *v = m->sdf + (size_t)type * n * n * n;
+    const double h = box[3];
+    double out2 = 0.0, f[3];
+    int i0[3];
+    for (int a = 0; a < 3; ++a) {
+        double hi = box[a] + (n - 1) * h;
+        double c = p[a] < box[a] ? box[a] : (p[a] > hi ? hi : p[a]);
+        out2 += (p[a] - c) * (p[a] - c);
+        double u = (c - box[a]) / h;
+        int i = (int)floor(u);
+        if (i > n - 2) i = n - 2;
+        if (i < 0) i = 0;
+        i0[a] = i;
+        f[a] = u - i;
+    }
+    double val = 0.0;
+    g[0] = g[1] = g[2] = 0.0;
+    for (int dz = 0; dz < 2; ++dz)
+        for (int dy = 0; dy < 2; ++dy)
+            for (int dx = 0; dx < 2; ++dx) {
+                double node = v[((size_t)(i0[2] + dz) * n + (i0[1] + dy)) * n + (i0[0] + dx)];
+                double wx = dx ? f[0] : 1.0 - f[0], wy = dy ? f[1] : 1.0 - f[1], wz = dz ? f[2] : 1.0 - f[2];
+                double sx = dx ? 1.0 : -1.0, sy = dy ? 1.0 : -1.0, sz = dz ? 1.0 : -1.0;
+                val += wx * wy * wz * node;
+                g[0] += sx * wy * wz * node / h;
+                g[1] += wx * sy * wz * node / h;
+                g[2] += wx * wy * sz * node / h;
+            }
+    return val + sqrt(out2);
+}
+
+/* Geometry of sample k of link l against the object's distance field (the
+ * object at pose x, R): the sample s on the link's axis, its object-frame
+ * point, the field's value phi and gradient there; gap phi - radius, normal
+ * (link -> object) minus the world unit gradient, contact point s - phi
+ * times that gradient (the object's surface point nearest the sample), and
+ * the link's velocity at s. */
+static void sdf_link_geometry(const or_model *m, const double *seg0, const double *seg1, int type,
+                              const double *R, const double *x, int l, int k, double *d, double *n, double *p,
+                              double *vl)
+{
+    const int M = m->link_samples;
+    const double t = M > 1 ? (double)k / (double)(M - 1) : 0.5;
+    const double *a = seg0 + 6 * l, *b = seg0 + 6 * l + 3;
+    const double *a1 = seg1 + 6 * l, *b1 = seg1 + 6 * l + 3;
+    double s[3], rel[3], po[3], g[3];
+    for (int i = 0; i < 3; ++i) s[i] = a[i] + t * (b[i] - a[i]);
+    geom_round(m, s, 3);
+    for (int i = 0; i < 3; ++i) rel[i] = s[i] - x[i];
+    mattvec(R, rel, po);
+    geom_round(m, po, 3);
+    double phi = sdf_eval(m, type, po, g);
+    geom_round(m, &phi, 1);
+    geom_round(m, g, 3);
+    double gn = norm3(g), go[3];
+    if (gn < 1e-12) {
+        go[0] = 0; go[1] = 0; go[2] = 1;
+    } else {
+        go[0] = g[0] / gn; go[1] = g[1] / gn; go[2] = g[2] / gn;
+    }
+    double gw[3];
+    matvec(R, go, gw);
+    *d = phi - m->hand[(size_t)l * OR_HAND_STRIDE + 17];
+    for (int i = 0; i < 3; ++i) {
+        n[i] = -gw[i];
+        p[i] = s[i] - phi * gw[i];
+    }
+    const double dt = m->dt;
+    for (int i = 0; i < 3; ++i) {
+        double va = (a1[i] - a[i]) / dt, vb = (b1[i] - b[i]) / dt;
+        vl[i] = (1 - t) * va + t * vb;
+    }
+}
+
+/* the field and its gradient at an object-frame point (for the pins) */
+double or_sdf_eval(const or_model *m, int type, const double *p, double *g) { return sdf_eval(m, type, p, g); }
+
 /* Tangent frame: e is the axis where |n_i| is smallest (lowest index on ties),
  * t1 = normalize(n x e), t2 = n x t1. */
 static void tangent_frame(const double *n, double *t1, double *t2)
@@ -460,7 +545,7 @@ static void build_system(const or_model *m, const double *seg0, const double *se
         c[0] += x[0]; c[1] += x[1]; c[2] += x[2];
         geom_round(m, c, 3);
         double rho = sph[4 * k + 3];
-        for (int l = 0; l <= L; ++l) {
+        for (int l = m->collision_mode == 1 ? L : 0; l <= L; ++l) {
             double d, n[3], p[3], vl[3];
             pair_geometry(m, seg0, seg1, l, c, rho, &d, n, p, vl);
             geom_round(m, &d, 1);
@@ -471,6 +556,22 @@ static void build_system(const or_model *m, const double *seg0, const double *se
                 ++ncand;
             }
         }
+    }
+    /* links against the object's distance field */
+    if (m->collision_mode == 1) {
+        cand = (cand_t *)realloc(cand, sizeof(cand_t) * (size_t)(ncand + L * m->link_samples + 1));
+        for (int l = 0; l < L; ++l)
+            for (int k = 0; k < m->link_samples; ++k) {
+                double d, n[3], p[3], vl[3];
+                sdf_link_geometry(m, seg0, seg1, type, R, x, l, k, &d, n, p, vl);
+                geom_round(m, &d, 1);
+                if (fabs(d - m->margin) < y->margin_gap) y->margin_gap = fabs(d - m->margin);
+                if (d < m->margin) {
+                    cand[ncand].d = d;
+                    cand[ncand].key = k * (L + 1) + l;
+                    ++ncand;
+                }
+            }
     }
     /* 6. cap: the C_max smallest (d, key) */
     qsort(cand, (size_t)ncand, sizeof(cand_t), cand_cmp);
@@ -489,14 +590,18 @@ static void build_system(const or_model *m, const double *seg0, const double *se
     for (int c = 0; c < C; ++c) {
         int key = cand[c].key;
         int k = key / (L + 1), l = key % (L + 1);
-        double ctr[3];
-        matvec(R, sph + 4 * k, ctr);
-        ctr[0] += x[0]; ctr[1] += x[1]; ctr[2] += x[2];
-        geom_round(m, ctr, 3);
         or_contact *o = cc + c;
         o->key = key;
         o->link = l;
-        pair_geometry(m, seg0, seg1, l, ctr, sph[4 * k + 3], &o->d, o->n, o->p, o->vlink);
+        if (m->collision_mode == 1 && l < L) {
+            sdf_link_geometry(m, seg0, seg1, type, R, x, l, k, &o->d, o->n, o->p, o->vlink);
+        } else {
+            double ctr[3];
+            matvec(R, sph + 4 * k, ctr);
+            ctr[0] += x[0]; ctr[1] += x[1]; ctr[2] += x[2];
+            geom_round(m, ctr, 3);
+            pair_geometry(m, seg0, seg1, l, ctr, sph[4 * k + 3], &o->d, o->n, o->p, o->vlink);
+        }
         geom_round(m, &o->d, 1);
         geom_round(m, o->n, 3);
         geom_round(m, o->p, 3);
@@ -994,7 +1099,7 @@ int or_env_step_pd(const or_model *m, const double *u_cmd, int type, double *st,
         matvec(R, sph + 4 * k, c);
         c[0] += x[0]; c[1] += x[1]; c[2] += x[2];
         geom_round(m, c, 3);
-        for (int l = 0; l <= L; ++l) {
+        for (int l = m->collision_mode == 1 ? L : 0; l <= L; ++l) {
             double d, n[3], p[3], vl[3];
             pair_geometry(m, seg, seg, l, c, sph[4 * k + 3], &d, n, p, vl);
             geom_round(m, &d, 1);
@@ -1006,6 +1111,21 @@ int or_env_step_pd(const or_model *m, const double *u_cmd, int type, double *st,
             }
         }
     }
+    if (m->collision_mode == 1) {
+        cand = (cand_t *)realloc(cand, sizeof(cand_t) * (size_t)(ncand + L * m->link_samples + 1));
+        for (int l = 0; l < L; ++l)
+            for (int k = 0; k < m->link_samples; ++k) {
+                double d, n[3], p[3], vl[3];
+                sdf_link_geometry(m, seg, seg, type, R, x, l, k, &d, n, p, vl);
+                geom_round(m, &d, 1);
+                if (fabs(d - m->margin) < margin_gap) margin_gap = fabs(d - m->margin);
+                if (d < m->margin) {
+                    cand[ncand].d = d;
+                    cand[ncand].key = k * (L + 1) + l;
+                    ++ncand;
+                }
+            }
+    }
     qsort(cand, (size_t)ncand, sizeof(cand_t), cand_cmp);
     int C = ncand < Cmax ? ncand : Cmax;
     int n3 = 3 * C;
@@ -1016,14 +1136,18 @@ int or_env_step_pd(const or_model *m, const double *u_cmd, int type, double *st,
     for (int c = 0; c < C; ++c) {
         int key = cand[c].key;
         int k = key / (L + 1), l = key % (L + 1);
-        double ctr[3];
-        matvec(R, sph + 4 * k, ctr);
-        ctr[0] += x[0]; ctr[1] += x[1]; ctr[2] += x[2];
-        geom_round(m, ctr, 3);
         or_contact *o_ = cc + c;
         o_->key = key;
         o_->link = l;
-        pair_geometry(m, seg, seg, l, ctr, sph[4 * k + 3], &o_->d, o_->n, o_->p, o_->vlink);
+        if (m->collision_mode == 1 && l < L) {
+            sdf_link_geometry(m, seg, seg, type, R, x, l, k, &o_->d, o_->n, o_->p, o_->vlink);
+        } else {
+            double ctr[3];
+            matvec(R, sph + 4 * k, ctr);
+            ctr[0] += x[0]; ctr[1] += x[1]; ctr[2] += x[2];
+            geom_round(m, ctr, 3);
+            pair_geometry(m, seg, seg, l, ctr, sph[4 * k + 3], &o_->d, o_->n, o_->p, o_->vlink);
+        }
         geom_round(m, &o_->d, 1);
         geom_round(m, o_->n, 3);
         geom_round(m, o_->p, 3);

@@ -72,6 +72,17 @@ typedef struct {
     /* PD-controlled hand (or_env_step_pd): joint gains, the mass of every
      * capsule link and the weight of the joint-angle term of the cost */
     double kp, kd, link_mass, w_q;
+    /* Link-object collision (collision_mode): 0 = the object's sphere set;
+     * 1 = the object's signed distance field, sampled on a regular grid in
+     * the object frame and interpolated trilinearly, queried at link_samples
+     * points along each link's axis (t = m / (link_samples - 1); the middle
+     * for one sample): sample m of link l is a contact candidate with key
+     * m*(L+1)+l and gap phi - radius_l, its normal minus the field's unit
+     * gradient, its point on the object the sample moved by -phi along the
+     * gradient.  Object-table contacts stay with the sphere set. */
+    int32_t collision_mode, link_samples, sdf_n;
+    const double *sdf;         /* [n_types][sdf_n^3] node values, x fastest, then y, z */
+    const double *sdf_box;     /* [n_types][4] grid origin (object frame) and node spacing */
 } or_model;
 
 typedef struct {
@@ -250,5 +261,9 @@ double or_window_cost(const or_model *m, int type, const double *st0, const doub
 /* OpenMP threads the batched calls use, and a way to set them (timing). */
 int or_max_threads(void);
 void or_set_threads(int n);
+
+/* Distance field of object type `type` at object-frame point p (value
+ * returned, gradient into g[3]); collision_mode 1 only. */
+double or_sdf_eval(const or_model *m, int type, const double *p, double *g);
 
 #endif

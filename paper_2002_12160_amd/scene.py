@@ -61,6 +61,13 @@ class ModelConsts:
     kd: float = 0.05             # joint damping [N m s / rad]
     link_mass: float = 0.03      # mass of every capsule link [kg]
     w_q: float = 100.0           # weight of the joint-angle term |q - q_gt|^2 [1 / rad^2]
+    # link-object collision: 0 = the object's sphere set; 1 = the object's
+    # signed distance field (a regular grid of sdf_res^3 nodes, interpolated
+    # trilinearly) against link_samples points on each link's axis
+    collision_mode: int = 0
+    link_samples: int = 8
+    sdf_res: int = 32
+    sdf_pad: float = 0.02        # grid margin around the object's bounding box [m]
 
 
 @dataclass(frozen=True)
@@ -354,6 +361,44 @@ def build_object(spec: ObjectSpec, rng: np.random.Generator | None = None):
     return spheres.astype(np.float64), 1.0 / inertia, dims, exps
 
 
+def build_sdf(spec: ObjectSpec, dims, exps, n: int, pad: float, n_surface: int = 40000):
+    """Signed distance field of an object's shape (negative inside) on a
+    cubic grid of n^3 nodes [n][n][n] (z, y, x), and its box: origin (object
+    frame, 3) and node spacing.  The cuboid's field is the exact box
+    distance; the ellipsoid's and the superquadric's are the distance to a
+    dense sampling of the surface, signed by the shape's implicit function."""
+    a = np.asarray(dims, dtype=np.float64) / (2.0 if spec.kind == "cuboid" else 1.0)
+    half = float(a.max()) + pad
+    h = 2.0 * half / (n - 1)
+    xs = -half + h * np.arange(n)
+    Z, Y, X = np.meshgrid(xs, xs, xs, indexing="ij")
+    P = np.stack([X, Y, Z], axis=-1).reshape(-1, 3)
+    if spec.kind == "cuboid":
+        q = np.abs(P) - a
+        phi = np.linalg.norm(np.maximum(q, 0.0), axis=1) + np.minimum(q.max(axis=1), 0.0)
+    else:
+        from scipy.spatial import cKDTree
+        u = _fibonacci_sphere(n_surface)
+        if spec.kind == "ellipsoid":
+            surf = u * a
+            inside = ((P / a) ** 2).sum(axis=1) <= 1.0
+        else:
+            e1, e2 = exps
+            eta = np.arcsin(np.clip(u[:, 2], -1, 1))
+            om = np.arctan2(u[:, 1], u[:, 0])
+
+            def spow(x, p):
+                return np.sign(x) * np.abs(x) ** p
+            surf = np.stack([a[0] * spow(np.cos(eta), e1) * spow(np.cos(om), e2),
+                             a[1] * spow(np.cos(eta), e1) * spow(np.sin(om), e2),
+                             a[2] * spow(np.sin(eta), e1)], axis=1)
+            inside = _sq_inside(P, a, exps)
+        dist, _ = cKDTree(surf).query(P)
+        phi = np.where(inside, -dist, dist)
+    box = np.array([-half, -half, -half, h])
+    return phi.reshape(n, n, n), box
+
+
 # --------------------------------------------------------------------------
 # full scene
 # --------------------------------------------------------------------------
@@ -375,6 +420,8 @@ class Scene:
     hidden_state: np.ndarray    # [G][13]
     hidden_params: np.ndarray   # [G][5]
     rest_pose: np.ndarray       # [n_types][7] unperturbed pose p0 of each object
+    sdf: np.ndarray | None = None      # [n_types][n][n][n] distance fields (collision_mode 1)
+    sdf_box: np.ndarray | None = None  # [n_types][4] grid origin and spacing
 
     @property
     def L(self):
@@ -420,11 +467,12 @@ def make_scene(cfg: TrackerConfig, K: int | None = None, steps: int | None = Non
     hand, mean = build_hand(cfg.hand)
     u = joint_trajectory(cfg.hand, mean, steps, cfg.consts.dt, rng)
 
-    sph_list, inv_list = [], []
+    sph_list, inv_list, shapes = [], [], []
     for ospec in cfg.objects:
-        s, inv, _, _ = build_object(ospec, rng)
+        s, inv, dims, exps = build_object(ospec, rng)
         sph_list.append(s)
         inv_list.append(inv)
+        shapes.append((ospec, dims, exps))
     n_types = len(sph_list)
     S_max = max(s.shape[0] for s in sph_list)
     spheres = np.zeros((n_types, S_max, 4))
@@ -465,10 +513,16 @@ def make_scene(cfg: TrackerConfig, K: int | None = None, steps: int | None = Non
         hidden_state[g, 0:7] = rest[hidden_type[g]]
         hidden_params[g, 0] = cfg.hidden_m
         hidden_params[g, 1] = cfg.hidden_mu
+    sdf = sdf_box = None
+    if cfg.consts.collision_mode == 1:
+        c = cfg.consts
+        grids = [build_sdf(o, d, e, c.sdf_res, c.sdf_pad) for o, d, e in shapes]
+        sdf = np.array([g for g, _ in grids])
+        sdf_box = np.array([b for _, b in grids])
     return Scene(cfg=cfg, hand=hand, mean_angles=mean, u=u, spheres=spheres, n_spheres=n_sph,
                  inv_inertia=inv_inertia, env_type=env_type, group_start=gs, state=state,
                  params=params, hidden_type=hidden_type, hidden_state=hidden_state,
-                 hidden_params=hidden_params, rest_pose=rest)
+                 hidden_params=hidden_params, rest_pose=rest, sdf=sdf, sdf_box=sdf_box)
 
 
 def round_to_f32(scene: Scene) -> Scene:
@@ -480,4 +534,6 @@ def round_to_f32(scene: Scene) -> Scene:
     return dataclasses.replace(scene, hand=r(scene.hand), u=r(scene.u), spheres=r(scene.spheres),
                                inv_inertia=r(scene.inv_inertia), state=r(scene.state),
                                params=r(scene.params), hidden_state=r(scene.hidden_state),
-                               hidden_params=r(scene.hidden_params))
+                               hidden_params=r(scene.hidden_params),
+                               sdf=None if scene.sdf is None else r(scene.sdf),
+                               sdf_box=None if scene.sdf_box is None else r(scene.sdf_box))

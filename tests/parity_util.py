@@ -114,7 +114,7 @@ class Probes:
         self.o = o
         m = o.m
         kw = dict(C_max=o.C_max, newton_iters=m.newton_iters, D=o.D, converged=bool(m.converged),
-                  conv_tol=m.conv_tol, conv_max_iters=m.conv_max_iters)
+                  conv_tol=m.conv_tol, conv_max_iters=m.conv_max_iters, sdf=o.sdf, sdf_box=o.sdf_box)
         self.g = [oracle.Oracle(o.hand, o.spheres, o.n_spheres, o.inv_inertia, o.consts, geom_f32=mode, **kw)
                   for mode in (1, 2)]
 
