@@ -172,6 +172,28 @@ typedef struct {
     float w_q;            /* weight of the joint-angle term [1 / rad^2], >= 0 */
     float *hand_state;    /* [2 D][K] q (D rows) then qdot (D rows), DEVICE,
                              caller-owned, used in place (hand_mode 1)       */
+    /* link-object collision (Sec. IV-A simplifies the objects' collision
+       geometry; here it may be a signed distance field): 0 = the sphere
+       set; 1 = the object's signed distance field phi (negative inside),
+       node values on a cubic grid in the object frame interpolated
+       trilinearly (outside the grid: the value at the nearest grid point plus
+       the distance to it), queried at link_samples points a + t (b - a),
+       t = m / (link_samples - 1) (the middle for one sample), along each
+       link's axis: sample m of link l is a contact candidate with key
+       m*(L+1)+l and gap phi - radius_l, normal minus the world unit gradient
+       of phi, contact point the sample moved by -phi along that gradient.
+       Object-table contacts stay with the sphere set.  Limits
+       (PT_E_UNSUPPORTED): L x link_samples + S_max <= 1536;
+       solve_precision 64; cost_mode 0; the windowed, gradient and refinement
+       calls return PT_E_UNSUPPORTED.  Both hand modes. */
+    int32_t collision_mode;
+    int32_t link_samples; /* 1..64                                             */
+    int32_t sdf_n;        /* grid nodes per axis, 2..128                       */
+    const float *sdf;     /* HOST [n_types][sdf_n][sdf_n][sdf_n] node values,
+                             x fastest (index (k sdf_n + j) sdf_n + i for the
+                             node origin + spacing (i, j, k)), copied        */
+    const float *sdf_box; /* HOST [n_types][4] grid origin (object frame, 3)
+                             and node spacing (> 0), copied                  */
 } pt_batch_desc;
 
 /* Creates a batch: validates the descriptor (PT_E_ARG / PT_E_UNSUPPORTED),

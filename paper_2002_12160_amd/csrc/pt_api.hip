@@ -121,6 +121,8 @@ struct pt_batch_s {
     int32_t *d_pd = nullptr;     // the hand's structure table (pt::PdTab)
     int32_t *d_parent = nullptr; // [K] parents of a resampling, for the joint state's copies
     float *hstate = nullptr;     // caller-owned [2D][K]
+    // the objects' distance fields (collision_mode 1)
+    float *d_sdf = nullptr, *d_sdf_box = nullptr;
     // caller-owned state
     float *state, *params, *warm;
     // host copies
@@ -193,6 +195,27 @@ pt_status validate(const pt_batch_desc *d)
         if (!(d->link_mass > 0.f) || !std::isfinite(d->link_mass)) return fail(PT_E_ARG, "link_mass must be positive and finite");
         if (!(d->w_q >= 0.f) || !std::isfinite(d->w_q)) return fail(PT_E_ARG, "w_q must be finite and >= 0");
         if (d->D > 0 && !d->hand_state) return fail(PT_E_ARG, "hand_state is NULL");
+    }
+    if (d->collision_mode != 0 && d->collision_mode != 1)
+        return fail(PT_E_ARG, "collision_mode must be 0 or 1 (got %d)", d->collision_mode);
+    if (d->collision_mode == 1) {
+        if (d->link_samples < 1 || d->link_samples > 64) return fail(PT_E_ARG, "link_samples must be in [1, 64]");
+        if (d->sdf_n < 2 || d->sdf_n > 128) return fail(PT_E_UNSUPPORTED, "sdf_n must be in [2, 128] (got %d)", d->sdf_n);
+        if (!d->sdf || !d->sdf_box) return fail(PT_E_ARG, "sdf/sdf_box is NULL");
+        if (d->solve_precision == 32) return fail(PT_E_UNSUPPORTED, "the distance-field path solves in float64 only");
+        if (d->cost_mode != 0) return fail(PT_E_UNSUPPORTED, "the distance-field path supports cost_mode 0 only");
+        if (d->L * d->link_samples + d->S_max > pt::CAND_CAP)
+            return fail(PT_E_UNSUPPORTED, "L x link_samples + S_max = %d exceeds %d candidates",
+                        d->L * d->link_samples + d->S_max, pt::CAND_CAP);
+        for (int t = 0; t < d->n_types; ++t) {
+            const float *bx = d->sdf_box + 4 * t;
+            if (!std::isfinite(bx[0]) || !std::isfinite(bx[1]) || !std::isfinite(bx[2]) || !(bx[3] > 0.f) ||
+                !std::isfinite(bx[3]))
+                return fail(PT_E_ARG, "sdf_box[%d]: origin must be finite and spacing positive", t);
+        }
+        const size_t nv = (size_t)d->n_types * d->sdf_n * d->sdf_n * d->sdf_n;
+        for (size_t i = 0; i < nv; ++i)
+            if (!std::isfinite(d->sdf[i])) return fail(PT_E_ARG, "sdf value %zu is not finite", i);
     }
     for (int l = 0; l < d->L; ++l) {
         const float *h = d->hand + (size_t)l * PT_HAND_STRIDE;
@@ -369,7 +392,8 @@ pt_status pt_create_batch(const pt_batch_desc *d, pt_batch *out)
     }
     // ... and the step's hand kinematics, which use the same LDS first
     const size_t fk_bytes = d->hand_mode == 1 ? pt::pd_fk_bytes(d->L) : hand_fk_lds_bytes(d->L, d->D);
-    const int max_cand = std::max({round_up(std::min(d->S_max * (d->L + 1), pt::CAND_CAP) + 8, 64),
+    const int n_pairs = d->collision_mode == 1 ? d->L * d->link_samples + d->S_max : d->S_max * (d->L + 1);
+    const int max_cand = std::max({round_up(std::min(n_pairs, pt::CAND_CAP) + 8, 64),
                                    round_up(red_rows * pt::RedStride<double>::value, 64),
                                    round_up((int)((fk_bytes + 7) / 8), 64)});
     const size_t wave_lds = pt::wave_lds_bytes(max_cand, d->L) + (d->hand_mode == 1 ? pt::pd_lds_bytes(d->D) : 0);
@@ -388,6 +412,9 @@ pt_status pt_create_batch(const pt_batch_desc *d, pt_batch *out)
     P.cost_mode = d->cost_mode;
     P.tau_slip = d->tau_slip; P.tau_spin = d->tau_spin;
     for (int i = 0; i < 7; ++i) P.w_eq3[i] = d->cost_mode == 1 ? d->w_eq3[i] : 0.f;
+    P.collision_mode = d->collision_mode;
+    P.link_samples = d->collision_mode == 1 ? d->link_samples : 0;
+    P.sdf_n = d->collision_mode == 1 ? d->sdf_n : 0;
     b->R = {d->elite_frac, d->sigma_mu, d->sigma_m, d->sigma_f, d->mu_lo, d->mu_hi, d->m_lo, d->m_hi, d->seed};
     b->n_types = d->n_types;
     b->hand_mode = d->hand_mode;
@@ -455,6 +482,13 @@ pt_status pt_create_batch(const pt_batch_desc *d, pt_batch *out)
     HIP_TRY_C(hipMalloc(&b->d_elite, sizeof(int32_t) * b->n_elite));
     HIP_TRY_C(hipMalloc(&b->d_snap, sizeof(float) * K * (18 + (size_t)4 * d->C_max)));
     if (d->window_checkpoints) HIP_TRY_C(hipMalloc(&b->d_wckpt, sizeof(float) * ckpt_floats(P, (int)K)));
+    if (d->collision_mode == 1) {
+        const size_t nv = (size_t)d->n_types * d->sdf_n * d->sdf_n * d->sdf_n;
+        HIP_TRY_C(hipMalloc(&b->d_sdf, sizeof(float) * nv));
+        HIP_TRY_C(hipMalloc(&b->d_sdf_box, sizeof(float) * 4 * d->n_types));
+        HIP_TRY_C(hipMemcpy(b->d_sdf, d->sdf, sizeof(float) * nv, hipMemcpyHostToDevice));
+        HIP_TRY_C(hipMemcpy(b->d_sdf_box, d->sdf_box, sizeof(float) * 4 * d->n_types, hipMemcpyHostToDevice));
+    }
     if (d->hand_mode == 1) {
         HIP_TRY_C(hipMalloc(&b->d_pd, sizeof(int32_t) * pd_tab.size()));
         HIP_TRY_C(hipMalloc(&b->d_parent, sizeof(int32_t) * K));
@@ -498,7 +532,7 @@ pt_status pt_destroy_batch(pt_batch b)
     void *ptrs[] = {b->d_hand, b->d_spheres, b->d_inv, b->d_nsph, b->d_type, b->d_group_of, b->d_group_start,
                     b->d_order, b->d_queue, b->d_stats, b->d_seg_win, b->d_contacts,
                     b->d_seg_grad, b->d_tune, b->d_ckpt, b->d_wckpt, b->d_elite, b->d_ref, b->d_snap,
-                    b->d_cslip, b->d_seg, b->d_pd, b->d_parent};
+                    b->d_cslip, b->d_seg, b->d_pd, b->d_parent, b->d_sdf, b->d_sdf_box};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete b;
@@ -514,6 +548,8 @@ static Tables tables_of(const pt_batch b)
     tb.inv_inertia = b->d_inv;
     tb.env_type = b->d_type;
     tb.group_of = b->d_group_of;
+    tb.sdf = b->d_sdf;
+    tb.sdf_box = b->d_sdf_box;
     return tb;
 }
 
@@ -634,6 +670,7 @@ pt_status pt_run_window(pt_batch b, const float *u_win, const float *obs_gt_win,
 {
     if (!b) return fail(PT_E_ARG, "batch is NULL");
     if (b->hand_mode == 1) return fail(PT_E_UNSUPPORTED, "the windowed path is not built for the PD hand");
+    if (b->P.collision_mode == 1) return fail(PT_E_UNSUPPORTED, "the windowed path is not built for the distance-field collision");
     if (!u_win || !obs_gt_win || !cost_sum) return fail(PT_E_ARG, "u_win/obs_gt_win/cost_sum is NULL");
     hipStream_t st = (hipStream_t)s;
     if (!graph)
@@ -687,6 +724,7 @@ pt_status pt_run_window_static(pt_batch b, const float *u_win, const float *obs_
 {
     if (!b) return fail(PT_E_ARG, "batch is NULL");
     if (b->hand_mode == 1) return fail(PT_E_UNSUPPORTED, "the windowed path is not built for the PD hand");
+    if (b->P.collision_mode == 1) return fail(PT_E_UNSUPPORTED, "the windowed path is not built for the distance-field collision");
     if (!u_win || !obs_gt_win || !cost_sum) return fail(PT_E_ARG, "u_win/obs_gt_win/cost_sum is NULL");
     const Consts &P = b->P;
     if ((size_t)P.T * P.L > STATIC_SEG_RECORDS)
@@ -708,6 +746,7 @@ pt_status pt_autotune(pt_batch b, const float *u_win, const float *obs_gt_win, i
 {
     if (!b) return fail(PT_E_ARG, "batch is NULL");
     if (b->hand_mode == 1) return fail(PT_E_UNSUPPORTED, "the windowed path is not built for the PD hand");
+    if (b->P.collision_mode == 1) return fail(PT_E_UNSUPPORTED, "the windowed path is not built for the distance-field collision");
     if (!u_win || !obs_gt_win) return fail(PT_E_ARG, "u_win/obs_gt_win is NULL");
     hipStream_t st = (hipStream_t)s;
     const Consts &P = b->P;
@@ -779,6 +818,7 @@ pt_status pt_window_grad(pt_batch b, const float *u_win, const float *obs_gt_win
 {
     if (!b) return fail(PT_E_ARG, "batch is NULL");
     if (b->hand_mode == 1) return fail(PT_E_UNSUPPORTED, "the window gradient is not built for the PD hand");
+    if (b->P.collision_mode == 1) return fail(PT_E_UNSUPPORTED, "the window gradient is not built for the distance-field collision");
     if (b->P.cost_mode != 0) return fail(PT_E_UNSUPPORTED, "the window gradient is defined for cost_mode 0 only");
     if (n < 0) return fail(PT_E_ARG, "n must be >= 0 (got %d)", n);
     if (n == 0) return PT_OK;
@@ -814,6 +854,7 @@ pt_status pt_refine_elites(pt_batch b, const float *u_win, const float *obs_gt_w
         return fail(PT_E_UNSUPPORTED, "elite refinement needs the window gradient, defined for cost_mode 0 only");
     if (!b) return fail(PT_E_ARG, "batch is NULL");
     if (b->hand_mode == 1) return fail(PT_E_UNSUPPORTED, "elite refinement is not built for the PD hand");
+    if (b->P.collision_mode == 1) return fail(PT_E_UNSUPPORTED, "elite refinement is not built for the distance-field collision");
     if (!u_win || !obs_gt_win || !cost_sum || !start_state || !start_params || !start_warm)
         return fail(PT_E_ARG, "u_win/obs_gt_win/cost_sum/start_state/start_params/start_warm is NULL");
     if (steps < 0) return fail(PT_E_ARG, "steps must be >= 0 (got %d)", steps);

@@ -27,6 +27,8 @@ struct Consts {
     float tau_contact, w_mag, w_dir;
     int cost_mode;             // 0: force terms, obs rows 4; 1: Eq. 3, obs rows 7
     float tau_slip, tau_spin, w_eq3[7];
+    int collision_mode;        // 0: sphere set; 1: links against the object's distance field
+    int link_samples, sdf_n;   // collision_mode 1: samples per link axis, grid nodes per axis
 };
 
 struct Tables {
@@ -36,6 +38,8 @@ struct Tables {
     const float *inv_inertia;   // [n_types][3]
     const int32_t *env_type;    // [K]
     const int32_t *group_of;    // [K]
+    const float *sdf;           // [n_types][sdf_n^3] distance-field nodes (collision_mode 1)
+    const float *sdf_box;       // [n_types][4] grid origin and node spacing
 };
 
 // uniform per-simulation state held in registers
@@ -333,6 +337,93 @@ __device__ __forceinline__ void pair_contact(const float *__restrict__ seg, int 
     }
     p[0] = c[0] - rho * n[0]; p[1] = c[1] - rho * n[1]; p[2] = c[2] - rho * n[2];
     float u = 1.f - t;
+    vl[0] = u * s[8] + t * s[12];
+    vl[1] = u * s[9] + t * s[13];
+    vl[2] = u * s[10] + t * s[14];
+}
+
+// ---------------------------------------------------------------------
+// link-object collision against the object's signed distance field
+// (collision_mode 1): node values on a regular grid in the object frame,
+// interpolated trilinearly
+// ---------------------------------------------------------------------
+struct SdfRef {
+    const float *v = nullptr;    // [n^3] node values of the object's type, x fastest
+    const float *box = nullptr;  // grid origin (3) and node spacing
+    int n = 0;                   // nodes per axis
+    int M = 0;                   // samples per link axis
+};
+
+// the field at object-frame point p (outside the grid's box: the value at
+// the nearest box point plus the distance to it) and, with g, its gradient
+// (that of the interpolant, at the nearest box point)
+__device__ __forceinline__ float sdf_eval(const SdfRef &f, const float *p, float *g)
+{
+    const int n = f.n;
+    const float h = f.box[3];
+    float out2 = 0.f, fr[3];
+    int i0[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float lo = f.box[a], hi = lo + (float)(n - 1) * h;
+        const float c = fminf(fmaxf(p[a], lo), hi);
+        out2 += (p[a] - c) * (p[a] - c);
+        const float u = (c - lo) / h;
+        const int i = min(max((int)floorf(u), 0), n - 2);
+        i0[a] = i;
+        fr[a] = u - (float)i;
+    }
+    const float *b = f.v + ((size_t)i0[2] * n + i0[1]) * n + i0[0];
+    const size_t sy = n, sz = (size_t)n * n;
+    const float v000 = b[0], v100 = b[1], v010 = b[sy], v110 = b[sy + 1];
+    const float v001 = b[sz], v101 = b[sz + 1], v011 = b[sz + sy], v111 = b[sz + sy + 1];
+    const float fx = fr[0], fy = fr[1], fz = fr[2], gx = 1.f - fx, gy = 1.f - fy, gz = 1.f - fz;
+    const float val = gz * (gy * (gx * v000 + fx * v100) + fy * (gx * v010 + fx * v110)) +
+                      fz * (gy * (gx * v001 + fx * v101) + fy * (gx * v011 + fx * v111));
+    if (g) {
+        const float ih = 1.f / h;
+        g[0] = (gz * (gy * (v100 - v000) + fy * (v110 - v010)) + fz * (gy * (v101 - v001) + fy * (v111 - v011))) * ih;
+        g[1] = (gz * (gx * (v010 - v000) + fx * (v110 - v100)) + fz * (gx * (v011 - v001) + fx * (v111 - v101))) * ih;
+        g[2] = (gy * (gx * (v001 - v000) + fx * (v101 - v100)) + fy * (gx * (v011 - v010) + fx * (v111 - v110))) * ih;
+    }
+    return val + sqrtf(out2);
+}
+
+// the point of sample m of the link whose record starts at s: a + t (b - a),
+// t = m / (M - 1) (the middle for one sample)
+__device__ __forceinline__ float sdf_sample_t(int m, int M) { return M > 1 ? (float)m / (float)(M - 1) : 0.5f; }
+
+// full contact geometry of sample m of link l against the field (object at
+// x, R): gap phi - radius, normal (link -> object) minus the world unit
+// gradient, contact point the sample moved by -phi along it, velocity of the
+// link at the sample
+__device__ __forceinline__ void sdf_contact(const SdfRef &f, const float *__restrict__ seg, int l, int m,
+                                            const float *x, const float *R, float &d, float *n, float *p, float *vl,
+                                            float &t)
+{
+    const float *s = seg + l * SEG_STRIDE;
+    t = sdf_sample_t(m, f.M);
+    const float sp[3] = {s[0] + t * s[4], s[1] + t * s[5], s[2] + t * s[6]};
+    const float r[3] = {sp[0] - x[0], sp[1] - x[1], sp[2] - x[2]};
+    const float po[3] = {R[0] * r[0] + R[3] * r[1] + R[6] * r[2], R[1] * r[0] + R[4] * r[1] + R[7] * r[2],
+                         R[2] * r[0] + R[5] * r[1] + R[8] * r[2]};
+    float g[3];
+    const float phi = sdf_eval(f, po, g);
+    const float gn = sqrtf(dot3(g, g));
+    float go[3] = {0.f, 0.f, 1.f};
+    if (gn >= 1e-12f) {
+        const float ig = 1.f / gn;
+        go[0] = g[0] * ig; go[1] = g[1] * ig; go[2] = g[2] * ig;
+    }
+    const float gw[3] = {R[0] * go[0] + R[1] * go[1] + R[2] * go[2], R[3] * go[0] + R[4] * go[1] + R[5] * go[2],
+                         R[6] * go[0] + R[7] * go[1] + R[8] * go[2]};
+    d = phi - s[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        n[i] = -gw[i];
+        p[i] = sp[i] - phi * gw[i];
+    }
+    const float u = 1.f - t;
     vl[0] = u * s[8] + t * s[12];
     vl[1] = u * s[9] + t * s[13];
     vl[2] = u * s[10] + t * s[14];

@@ -237,8 +237,9 @@ struct StepBounds {
 };
 
 // EQ3: the observation of Eq. 3 (cost_mode 1) compiled in; the default
-// force-only kernels carry none of its registers
-template <typename SR, bool EQ3>
+// force-only kernels carry none of its registers.  SDF: links against the
+// object's distance field (collision_mode 1)
+template <typename SR, bool EQ3, bool SDF = false>
 __global__ __launch_bounds__(StepBounds<SR>::threads) void k_step(Consts P, Tables tb,
                                                const float *__restrict__ u_prev, const float *__restrict__ u,
                                                float *__restrict__ state, float *__restrict__ params,
@@ -275,7 +276,14 @@ __global__ __launch_bounds__(StepBounds<SR>::threads) void k_step(Consts P, Tabl
     int link;
     float imp[3];
     StepState<SR> sst;
-    step_setup<SR>(P, seg, sph, S, inv, B, wkey, wr, lds, st, sst);
+    SdfRef sdf;
+    if (SDF) {
+        sdf.v = tb.sdf + (size_t)type * P.sdf_n * P.sdf_n * P.sdf_n;
+        sdf.box = tb.sdf_box + 4 * type;
+        sdf.n = P.sdf_n;
+        sdf.M = P.link_samples;
+    }
+    step_setup<SR, SDF>(P, seg, sph, S, inv, B, wkey, wr, lds, st, sst, sdf);
     step_solve<SR, false, true>(P, sst, B.mu, inv, reinterpret_cast<SR *>(lds.cand_d));
     step_finish<SR>(P, sst, inv, B, wkey, wr, link, imp);
     const int lane = lane_id();
@@ -650,7 +658,10 @@ hipError_t launch_step(const Consts &P, const Tables &tb, const float *u_prev, c
     size_t lds = (size_t)waves_per_block * wave_lds_bytes(P.max_cand, P.L);
     const dim3 grid(blocks), block(WAVE * waves_per_block);
     const bool eq3 = P.cost_mode == 1;
-    if (P.solve_fp64 && !eq3)
+    if (P.collision_mode == 1)   // float64 solve and force terms only (checked at batch creation)
+        hipLaunchKernelGGL((k_step<double, false, true>), grid, block, lds, s, P, tb, u_prev, u, state, params,
+                           warm, contacts, cslip, seg_out, stats);
+    else if (P.solve_fp64 && !eq3)
         hipLaunchKernelGGL((k_step<double, false>), grid, block, lds, s, P, tb, u_prev, u, state, params, warm,
                            contacts, cslip, seg_out, stats);
     else if (P.solve_fp64)
@@ -754,6 +765,7 @@ hipError_t set_lds_limits(size_t bytes)
                         reinterpret_cast<const void *>(k_step<double, false>),
                         reinterpret_cast<const void *>(k_step<float, true>),
                         reinterpret_cast<const void *>(k_step<double, true>),
+                        reinterpret_cast<const void *>(k_step<double, false, true>),
                         reinterpret_cast<const void *>(k_resample)};
     for (const void *f : fs) {
         hipError_t e = set_dynamic_lds_limit(f, bytes);

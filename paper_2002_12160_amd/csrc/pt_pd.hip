@@ -2,7 +2,8 @@
 // (gfx950): the per-step path of the kinematic hand with the joint angles
 // and rates as per-simulation state.
 //
-//   k_step_pd      one simulation step per wavefront: hand kinematics and
+//   k_step_pd      one simulation step per wavefront (links against the
+//                  object's sphere set or its distance field): hand kinematics and
 //                  mass matrix at the simulation's joint angles, narrow
 //                  phase and cap, the (6 + D) contact solve, integration of
 //                  object and joints
@@ -15,6 +16,7 @@
 
 namespace pt {
 
+template <bool SDF>
 __global__ __launch_bounds__(WAVE) void k_step_pd(Consts P, PdConsts Q, Tables tb, PdTab T,
                                                   const float *__restrict__ u, float *__restrict__ state,
                                                   float *__restrict__ params, float *__restrict__ warm,
@@ -58,7 +60,14 @@ __global__ __launch_bounds__(WAVE) void k_step_pd(Consts P, PdConsts Q, Tables t
     pd_twists(D, B.x, pl);
     StepStats st = {0, 0, 0};
     StepState<double> sst;
-    step_setup<double>(P, lds.seg, sph, S, inv, B, wkey, wr, lds, st, sst);
+    SdfRef sdf;
+    if (SDF) {
+        sdf.v = tb.sdf + (size_t)type * P.sdf_n * P.sdf_n * P.sdf_n;
+        sdf.box = tb.sdf_box + 4 * type;
+        sdf.n = P.sdf_n;
+        sdf.M = P.link_samples;
+    }
+    step_setup<double, SDF>(P, lds.seg, sph, S, inv, B, wkey, wr, lds, st, sst, sdf);
     int pos, nseg;
     pd_order_contacts(sst, pl, pos, nseg);
     step_solve_pd(P, Q, T, sst, B.mu, inv, reinterpret_cast<double *>(lds.cand_d), pl, pos, nseg);
@@ -148,7 +157,11 @@ using namespace pt;
 
 size_t pd_wave_lds_bytes(int max_cand, int L, int D) { return wave_lds_bytes(max_cand, L) + pd_lds_bytes(D); }
 
-hipError_t set_pd_lds_limits(size_t bytes) { return set_dynamic_lds_limit((const void *)k_step_pd, bytes); }
+hipError_t set_pd_lds_limits(size_t bytes)
+{
+    hipError_t e = set_dynamic_lds_limit((const void *)k_step_pd<false>, bytes);
+    return e != hipSuccess ? e : set_dynamic_lds_limit((const void *)k_step_pd<true>, bytes);
+}
 
 hipError_t launch_step_pd(const Consts &P, const PdConsts &Q, const Tables &tb, const int32_t *pd_tab,
                           const float *u, float *state, float *params, float *warm, float *hstate, float *contacts,
@@ -156,8 +169,12 @@ hipError_t launch_step_pd(const Consts &P, const PdConsts &Q, const Tables &tb, 
 {
     const PdTab T = {pd_tab, P.D, P.L};
     const size_t lds = pd_wave_lds_bytes(P.max_cand, P.L, P.D);
-    hipLaunchKernelGGL(k_step_pd, dim3(P.K), dim3(WAVE), lds, s, P, Q, tb, T, u, state, params, warm, hstate,
-                       contacts, stats);
+    if (P.collision_mode == 1)
+        hipLaunchKernelGGL(k_step_pd<true>, dim3(P.K), dim3(WAVE), lds, s, P, Q, tb, T, u, state, params, warm,
+                           hstate, contacts, stats);
+    else
+        hipLaunchKernelGGL(k_step_pd<false>, dim3(P.K), dim3(WAVE), lds, s, P, Q, tb, T, u, state, params, warm,
+                           hstate, contacts, stats);
     return hipGetLastError();
 }
 

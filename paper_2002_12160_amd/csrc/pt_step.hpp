@@ -114,10 +114,10 @@ __device__ __forceinline__ void step_pose(const Consts &P, const float *inv_in, 
 
 // phase 4: geometry of the contact with key `key` held by this lane (key < 0:
 // an empty slot), impulse reset to 0
-template <typename SR>
+template <typename SR, bool SDF = false>
 __device__ __forceinline__ void contact_setup(const Consts &P, const float *__restrict__ seg,
                                               const float *__restrict__ sph, const Body &B, int key,
-                                              StepState<SR> &st)
+                                              StepState<SR> &st, const SdfRef &sdf = SdfRef())
 {
     const int L = P.L;
     const float dt = P.dt;
@@ -142,23 +142,31 @@ __device__ __forceinline__ void contact_setup(const Consts &P, const float *__re
         int l = st.key - k * (L + 1);
         st.k = k;
         st.l = l;
-        const float4 t = *reinterpret_cast<const float4 *>(sph + 4 * k);
-        float s4[4] = {t.x, t.y, t.z, t.w};
-        float *c = st.c;
-        c[0] = B.x[0] + R[0] * s4[0] + R[1] * s4[1] + R[2] * s4[2];
-        c[1] = B.x[1] + R[3] * s4[0] + R[4] * s4[1] + R[5] * s4[2];
-        c[2] = B.x[2] + R[6] * s4[0] + R[7] * s4[1] + R[8] * s4[2];
         float d, *n = st.n, *p = st.p, *vl = st.vl;
-        pair_contact(seg, l, L, c, s4[3], d, n, p, vl);
-        st.d = d;
-        if (l < L) {
-            const float *sg = seg + l * SEG_STRIDE;
-            float ca[3] = {c[0] - sg[0], c[1] - sg[1], c[2] - sg[2]};
-            float tr = (ca[0] * sg[4] + ca[1] * sg[5] + ca[2] * sg[6]) * sg[7];
-            st.interior = tr > 0.f && tr < 1.f;
-            st.tpar = fminf(fmaxf(tr, 0.f), 1.f);
-            st.dist = d + s4[3] + sg[3];
+        if (SDF && l < L) {
+            // sample k of link l against the object's distance field
+            float t;
+            sdf_contact(sdf, seg, l, k, B.x, R, d, n, p, vl, t);
+            st.tpar = t;
+            st.c[0] = st.c[1] = st.c[2] = 0.f;
+        } else {
+            const float4 t = *reinterpret_cast<const float4 *>(sph + 4 * k);
+            const float s4[4] = {t.x, t.y, t.z, t.w};
+            float *c = st.c;
+            c[0] = B.x[0] + R[0] * s4[0] + R[1] * s4[1] + R[2] * s4[2];
+            c[1] = B.x[1] + R[3] * s4[0] + R[4] * s4[1] + R[5] * s4[2];
+            c[2] = B.x[2] + R[6] * s4[0] + R[7] * s4[1] + R[8] * s4[2];
+            pair_contact(seg, l, L, c, s4[3], d, n, p, vl);
+            if (l < L) {
+                const float *sg = seg + l * SEG_STRIDE;
+                float ca[3] = {c[0] - sg[0], c[1] - sg[1], c[2] - sg[2]};
+                float tr = (ca[0] * sg[4] + ca[1] * sg[5] + ca[2] * sg[6]) * sg[7];
+                st.interior = tr > 0.f && tr < 1.f;
+                st.tpar = fminf(fmaxf(tr, 0.f), 1.f);
+                st.dist = d + s4[3] + sg[3];
+            }
         }
+        st.d = d;
         float t1[3], t2[3];
         tangent_frame(n, t1, t2);
         {
@@ -420,12 +428,61 @@ __device__ __forceinline__ void narrow_phase(const Consts &P, const WaveLds &lds
     }
 }
 
+// Narrow phase against the object's distance field: lanes over the links'
+// (link, sample) pairs, then over the spheres for the table, candidates
+// appended to LDS by ballot + prefix count (the list holds them all: the
+// batch is created only when L x samples + S_max fit).
+__device__ __forceinline__ void narrow_phase_sdf(const Consts &P, const WaveLds &lds, const SdfRef &sdf,
+                                                 const float *__restrict__ seg, const float *__restrict__ sph, int S,
+                                                 const float *x, const float *R, int &ncand)
+{
+    const int lane = lane_id();
+    const int L = P.L, M = sdf.M, nq = L * M;
+    auto append = [&](bool cand, float d, int key) {
+        const uint64_t mask = __ballot(cand);
+        if (cand) {
+            const int pos = ncand + mask_rank(mask);
+            lds.cand_d[pos] = d;
+            lds.cand_k[pos] = key;
+        }
+        ncand += __popcll(mask);
+    };
+    for (int i0 = 0; i0 < nq; i0 += WAVE) {
+        const int i = i0 + lane;
+        const bool valid = i < nq;
+        float d = 0.f;
+        int key = 0;
+        if (valid) {
+            const int l = i / M, m = i - (i / M) * M;
+            const float *s = seg + l * SEG_STRIDE;
+            const float t = sdf_sample_t(m, M);
+            const float r[3] = {s[0] + t * s[4] - x[0], s[1] + t * s[5] - x[1], s[2] + t * s[6] - x[2]};
+            const float po[3] = {R[0] * r[0] + R[3] * r[1] + R[6] * r[2], R[1] * r[0] + R[4] * r[1] + R[7] * r[2],
+                                 R[2] * r[0] + R[5] * r[1] + R[8] * r[2]};
+            d = sdf_eval(sdf, po, nullptr) - s[3];
+            key = m * (L + 1) + l;
+        }
+        append(valid && d < P.margin, d, key);
+    }
+    for (int kb = 0; kb < S; kb += WAVE) {
+        const int k = kb + lane;
+        const bool valid = k < S;
+        float d = 0.f;
+        if (valid) {
+            const float4 t = *reinterpret_cast<const float4 *>(sph + 4 * k);
+            const float cz = x[2] + R[6] * t.x + R[7] * t.y + R[8] * t.z;
+            d = cz - t.w;
+        }
+        append(valid && d < P.margin, d, k * (L + 1) + L);
+    }
+}
+
 // phases 1-4: pose, free velocity, narrow phase, cap, contact setup, warm start
-template <typename SR>
+template <typename SR, bool SDF = false>
 __device__ __forceinline__ void step_setup(const Consts &P, const float *__restrict__ seg,
                                            const float *__restrict__ sph, int S, const float *inv_in, const Body &B,
                                            int wkey, const float *wr, const WaveLds &lds, StepStats &stats,
-                                           StepState<SR> &st)
+                                           StepState<SR> &st, const SdfRef &sdf = SdfRef())
 {
     const int lane = lane_id();
     const int L = P.L;
@@ -447,7 +504,9 @@ __device__ __forceinline__ void step_setup(const Consts &P, const float *__restr
     // can find more candidates than that runs the bounded form
     const int cap = P.max_cand - 8;
     int ncand = 0, removed = 0;
-    if (S * (L + 1) <= cap)
+    if (SDF)
+        narrow_phase_sdf(P, lds, sdf, seg, sph, S, B.x, R, ncand);
+    else if (S * (L + 1) <= cap)
         narrow_phase<false>(P, lds, sgr, sph, S, B.x, R, cap, ncand, removed);
     else
         narrow_phase<true>(P, lds, sgr, sph, S, B.x, R, cap, ncand, removed);
@@ -491,7 +550,7 @@ __device__ __forceinline__ void step_setup(const Consts &P, const float *__restr
     // 4. contact setup, one contact per lane, and the warm start from the
     //    previous step's impulse of the same key
     //    (keys of the previous cache are unique; eight compared per round)
-    contact_setup<SR>(P, seg, sph, B, lane < C ? lds.sel[lane] : -1, st);
+    contact_setup<SR, SDF>(P, seg, sph, B, lane < C ? lds.sel[lane] : -1, st, sdf);
     if (st.act) {
         int hit = -1;
         for (int j = 0; j < P.C_max; j += 8) {

@@ -60,6 +60,8 @@ class BatchDesc(C.Structure):
         ("cost_mode", C.c_int32), ("tau_slip", C.c_float), ("tau_spin", C.c_float), ("w_eq3", C.c_float * 7),
         ("hand_mode", C.c_int32), ("kp", C.c_float), ("kd", C.c_float), ("link_mass", C.c_float),
         ("w_q", C.c_float), ("hand_state", C.c_void_p),
+        ("collision_mode", C.c_int32), ("link_samples", C.c_int32), ("sdf_n", C.c_int32),
+        ("sdf", C.c_void_p), ("sdf_box", C.c_void_p),
     ]
 
 
@@ -210,7 +212,7 @@ class Batch:
 
     def __init__(self, *, hand, spheres, n_spheres, inv_inertia, env_type, group_start, consts, C_max,
                  newton_iters, T, state, params, resample=None, solve_precision=64, window_checkpoints=False,
-                 hand_state=None, device="cuda"):
+                 hand_state=None, sdf=None, sdf_box=None, device="cuda"):
         self.device = torch.device(device)
         K = int(np.asarray(env_type).shape[0])
         self.K, self.C_max, self.T = K, int(C_max), int(T)
@@ -270,6 +272,18 @@ class Batch:
         d.kp, d.kd = getattr(consts, "kp", 0.0), getattr(consts, "kd", 0.0)
         d.link_mass, d.w_q = getattr(consts, "link_mass", 0.0), getattr(consts, "w_q", 0.0)
         d.hand_state = self.hand_state.data_ptr() if self.hand_state is not None else None
+        # links against the objects' distance fields: grids [n_types][n][n][n] (z, y, x), boxes [n_types][4]
+        d.collision_mode = int(getattr(consts, "collision_mode", 0))
+        d.link_samples = int(getattr(consts, "link_samples", 8))
+        self.sdf = self.sdf_box = None
+        if d.collision_mode == 1:
+            if sdf is None or sdf_box is None:
+                raise PtError(1, "Batch", "collision_mode 1 needs sdf and sdf_box")
+            self.sdf = np.ascontiguousarray(sdf, dtype=np.float32)
+            self.sdf_box = np.ascontiguousarray(sdf_box, dtype=np.float32)
+            d.sdf_n = self.sdf.shape[1]
+            d.sdf = self.sdf.ctypes.data
+            d.sdf_box = self.sdf_box.ctypes.data
         self.desc = d
         self.handle = pt_create_batch(d)
 
@@ -281,7 +295,8 @@ class Batch:
                       newton_iters=kw.pop("newton_iters", cfg.newton_iters), T=kw.pop("T", cfg.T),
                       resample=dict(elite_frac=cfg.elite_frac, sigma_mu=cfg.sigma_mu, sigma_m=cfg.sigma_m,
                                     sigma_f=cfg.sigma_f, mu_range=cfg.mu_range, m_range=cfg.m_range,
-                                    seed=cfg.seed), device=device)
+                                    seed=cfg.seed), sdf=getattr(scene, "sdf", None),
+                      sdf_box=getattr(scene, "sdf_box", None), device=device)
         if hidden:
             G = scene.G
             return cls(env_type=scene.hidden_type, group_start=np.arange(G + 1, dtype=np.int32),

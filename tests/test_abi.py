@@ -231,3 +231,49 @@ def test_pd_hand_structure_limits(lib):
     chain[6, 1] = -1            # six joints in the chain: within the limit
     d.D = 6
     assert _create_rc(pt, d) in (0, 2)
+
+
+def _sdf_desc(pt, keep, n=8):
+    d = _valid_desc(pt, keep)
+    d.collision_mode, d.link_samples, d.sdf_n = 1, 8, n
+    keep["sdf"] = np.zeros((1, n, n, n), np.float32)
+    keep["sdf_box"] = np.array([[-0.05, -0.05, -0.05, 0.1 / (n - 1)]], np.float32)
+    d.sdf, d.sdf_box = keep["sdf"].ctypes.data, keep["sdf_box"].ctypes.data
+    return d
+
+
+def test_sdf_descriptor_passes_validation(lib):
+    pt = _desc_module()
+    keep = {}
+    assert _create_rc(pt, _sdf_desc(pt, keep)) in (0, 2)
+
+
+@pytest.mark.parametrize("field,value,code", [
+    ("collision_mode", 2, 1), ("link_samples", 0, 1), ("link_samples", 65, 1), ("sdf_n", 1, 5),
+    ("sdf_n", 129, 5), ("sdf", None, 1), ("sdf_box", None, 1), ("solve_precision", 32, 5), ("cost_mode", 1, 5),
+])
+def test_sdf_descriptor_validation(lib, field, value, code):
+    pt = _desc_module()
+    keep = {}
+    d = _sdf_desc(pt, keep)
+    setattr(d, field, value)
+    assert _create_rc(pt, d) == code
+    assert len(pt._lib.pt_last_error()) > 0
+
+
+def test_sdf_tables_are_checked(lib):
+    pt = _desc_module()
+    keep = {}
+    d = _sdf_desc(pt, keep)
+    keep["sdf_box"][0, 3] = 0.0             # zero spacing
+    assert _create_rc(pt, d) == 1
+    keep["sdf_box"][0, 3] = 0.01
+    keep["sdf"][0, 3, 4, 5] = np.nan        # a node value that is not finite
+    assert _create_rc(pt, d) == 1
+    keep["sdf"][0, 3, 4, 5] = 0.0
+    d.link_samples = 64                     # 9 links x 64 samples + 26 spheres: 602 candidates
+    d.L = 9
+    assert _create_rc(pt, d) in (0, 2)
+    keep["hand25"] = np.tile(keep["hand"][:1], (25, 1))
+    d.hand, d.L = keep["hand25"].ctypes.data, 25   # 25 x 64 + 26 > 1536
+    assert _create_rc(pt, d) == 5
