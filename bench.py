@@ -369,6 +369,64 @@ def plain_run(pt, setup, dev, solve_precision, steps, warmup):
             "contacts_per_env_step": round(d_con / max(d_env, 1), 2)}
 
 
+def pd_run(pt, S, dev, cfg, steps, warmup):
+    """The PD-controlled hand on the plain per-step path: the observed
+    simulations' forces and joint angles first (resident in HBM), then step,
+    observe, cost with the argmin and the resampler every T steps, timed as
+    plain_run."""
+    import numpy as np
+    import torch
+    cfg = cfg.with_(consts=dataclasses.replace(cfg.consts, hand_mode=1))
+    sc = S.make_scene(cfg, steps=warmup + steps + 1)
+    K, G, T, D = sc.K, sc.G, cfg.T, sc.D
+    u_all = torch.as_tensor(sc.u.astype("float32"), device=dev)
+    rest = np.concatenate([sc.u[0], np.zeros(D)])
+    h = pt.Batch.from_scene(sc, hidden=True, hand_state=np.tile(rest, (G, 1)))
+    gts = torch.empty((warmup + steps,) + h.obs_shape(G), device=dev)
+    for t in range(warmup + steps):
+        h.step(None, u_all[t])
+        h.observe(gts[t])
+    torch.cuda.synchronize()
+    h.close()
+    b = pt.Batch.from_scene(sc, hand_state=np.tile(rest, (K, 1)))
+    cost = torch.zeros(K, device=dev)
+    best = torch.zeros(G, dtype=torch.int32, device=dev)
+    parent = torch.zeros(K, dtype=torch.int32, device=dev)
+    obs = b.new_obs()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+
+    def one(t, i=None):
+        if i is not None:
+            ev[i][0].record()
+        b.step(None, u_all[t])
+        b.observe(obs)
+        b.cost(obs, gts[t], cost, best)
+        if i is not None:
+            ev[i][1].record()
+        if (t + 1) % T == 0:
+            b.resample(cost, (t + 1) // T - 1, parent)
+
+    for t in range(warmup):
+        one(t)
+    torch.cuda.synchronize()
+    stats0 = b.read_stats()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        one(warmup + i, i)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    stats1 = b.read_stats()
+    b.close()
+    step_ms = np.array([a.elapsed_time(c) for a, c in ev])
+    d_env = stats1["env_steps"] - stats0["env_steps"]
+    d_con = stats1["contacts"] - stats0["contacts"]
+    return {"value": K * steps / wall, "unit": "env-steps/s", "steps": steps,
+            "ms_per_step": round(wall / steps * 1e3, 4),
+            "per_step_ms": {"p50": round(float(np.median(step_ms)), 4),
+                            "p99": round(float(np.quantile(step_ms, 0.99)), 4)},
+            "contacts_per_env_step": round(d_con / max(d_env, 1), 2)}
+
+
 def repeat(fn, runs):
     return median_run([fn() for _ in range(runs)])
 
@@ -631,6 +689,32 @@ def main():
     }
     result["ceilings"] = ceilings(dev)
     result["roofline"]["frac_of_measured_fma"] = round(achieved / result["ceilings"]["fma_f64_tflops"], 4)
+
+    # the PD-controlled hand (joint state per simulation) on the plain path
+    if not args.no_workloads:
+        pd = {}
+        for name in ("realtime16384", "small"):
+            wcfg = S.CONFIGS[name]
+            r = repeat(lambda: pd_run(pt, S, dev, wcfg, min(n_win * T, 300), n_warm * T), runs)
+            pd[name] = rounded({k: r[k] for k in ("value", "unit", "steps", "ms_per_step", "per_step_ms",
+                                                  "contacts_per_env_step", "runs") if k in r})
+        pd["path"] = ("plain per-step path of the PD-controlled hand: step (hand kinematics, mass matrix and the "
+                      "(6 + D) contact solve per simulation), observe (forces and joint angles), cost with the "
+                      "joint term, PBO resampling every window")
+        result["pd_hand"] = pd
+        print("bench: PD hand done", file=sys.stderr, flush=True)
+        # links against the objects' signed distance fields (32^3 grids, 8 samples per link)
+        scfg = cfg.with_(consts=dataclasses.replace(cfg.consts, collision_mode=1))
+        n_sdf = min(n_win * T, 300)
+        ssetup = make_setup(pt, S, dev, sp, scfg, n_warm + -(-n_sdf // T))
+        r = repeat(lambda: plain_run(pt, ssetup, dev, sp, n_sdf, n_warm * T), runs)
+        result["distance_field"] = {
+            "path": "plain per-step path with the links tested at 8 points each against the objects' signed "
+                    "distance fields (32^3 grids, trilinear) instead of the sphere sets",
+            "realtime16384": rounded({k: r[k] for k in ("value", "unit", "steps", "ms_per_step", "per_step_ms",
+                                                        "contacts_per_env_step", "runs") if k in r}),
+            "vs_sphere_set_plain": round(r["value"] / plain["value"], 3)}
+        print("bench: distance field done", file=sys.stderr, flush=True)
 
     # the other workloads, the paths their definitions name
     if not args.no_workloads:
