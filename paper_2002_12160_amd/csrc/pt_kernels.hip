@@ -523,7 +523,7 @@ __global__ __launch_bounds__(1024) void k_resample(Consts P, ResampleArgs R, con
 // wavefronts per SIMD leave, is held to two with a small spill: ~12% more
 // throughput on the 16384-simulation workload)
 template <typename SR, bool EQ3, bool PT>
-__global__ __launch_bounds__(StepBounds<SR>::threads) __attribute__((amdgpu_waves_per_eu(EQ3 && !PT ? 2 : 1))) void
+__global__ __launch_bounds__(StepBounds<SR>::threads) __attribute__((amdgpu_waves_per_eu(!PT ? 2 : 1))) void
 k_window(Consts P, Tables tb, const float *__restrict__ seg_win, float *__restrict__ state,
          float *__restrict__ params, float *__restrict__ warm, const float *__restrict__ obs_gt_win,
          float *__restrict__ cost_sum, float *__restrict__ obs_out, const int32_t *__restrict__ env_order,

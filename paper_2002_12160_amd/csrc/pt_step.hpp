@@ -361,6 +361,13 @@ __device__ __forceinline__ int compact_candidates(const WaveLds &lds, int n, int
 // Narrow phase: lanes over spheres, candidates appended to LDS in (sphere
 // block, link) order by ballot + prefix count, the table (l == L) after the
 // links, two links' gaps at a time so that their arithmetic interleaves.
+// A link that no sphere can reach is skipped: a sphere's gap to a link is
+// at least the gap from the object centre x to the link less |c - x| + rho
+// (the distance to a segment is 1-Lipschitz), so a link farther from x than
+// the object's largest |c - x| + rho plus the margin (and 10 um for
+// rounding) holds no candidate; the reachable links are paired in
+// increasing order, so the candidates appended, and their order, are those
+// of the full loop.
 // Bounded: the list may fill up; a batch that would overflow it first cuts
 // the list to its C_max lowest, and from then on only candidates below the
 // last kept one are appended (removed counts the others).
@@ -373,6 +380,15 @@ __device__ __forceinline__ void narrow_phase(const Consts &P, const WaveLds &lds
     const int L = P.L;
     bool bar = false;
     uint64_t thr = 0;
+    // the links any sphere can reach (bit l; wave-uniform)
+    float reach = 0.f;
+    for (int k = lane; k < S; k += WAVE) {
+        const float4 t = *reinterpret_cast<const float4 *>(sph + 4 * k);
+        reach = fmaxf(reach, sqrtf(t.x * t.x + t.y * t.y + t.z * t.z) + t.w);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) reach = fmaxf(reach, __shfl_xor(reach, o));
+    const uint64_t near = __ballot(lane < L && segment_gap(sgr, x, 0.f) - reach < P.margin + 1e-5f);
     for (int kb = 0; kb < S; kb += WAVE) {
         const int k = kb + lane;
         const bool valid = k < S;
@@ -412,8 +428,12 @@ __device__ __forceinline__ void narrow_phase(const Consts &P, const WaveLds &lds
             }
             ncand += __popcll(mask);
         };
-        for (int l = 0; l < L; l += 2) {
-            const int l1 = l + 1 < L ? l + 1 : l;
+        // the reachable links in increasing order, two at a time
+        for (uint64_t m = near; m;) {
+            const int l = __builtin_ctzll(m);
+            m &= m - 1;
+            const int l1 = m ? __builtin_ctzll(m) : l;
+            if (m) m &= m - 1;
             float sa[8], sb[8];
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
@@ -422,7 +442,7 @@ __device__ __forceinline__ void narrow_phase(const Consts &P, const WaveLds &lds
             }
             const float da = segment_gap(sa, c, s4[3]), db = segment_gap(sb, c, s4[3]);
             append(da, l);
-            if (l + 1 < L) append(db, l + 1);
+            if (l1 != l) append(db, l1);
         }
         append(c[2] - s4[3], L);
     }
