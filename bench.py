@@ -708,12 +708,19 @@ def main():
         n_sdf = min(n_win * T, 300)
         ssetup = make_setup(pt, S, dev, sp, scfg, n_warm + -(-n_sdf // T))
         r = repeat(lambda: plain_run(pt, ssetup, dev, sp, n_sdf, n_warm * T), runs)
+        sw = -(-n_sdf // T)
+        rb = repeat(lambda: windows_run(pt, ssetup, dev, sp, sw, n_warm, refine=False), runs)
         result["distance_field"] = {
-            "path": "plain per-step path with the links tested at 8 points each against the objects' signed "
-                    "distance fields (32^3 grids, trilinear) instead of the sphere sets",
+            "path": "the links tested at 8 points each against the objects' signed distance fields (32^3 grids, "
+                    "trilinear) instead of the sphere sets: the plain per-step path, and the batched windows "
+                    "with PBO resampling",
             "realtime16384": rounded({k: r[k] for k in ("value", "unit", "steps", "ms_per_step", "per_step_ms",
                                                         "contacts_per_env_step", "runs") if k in r}),
-            "vs_sphere_set_plain": round(r["value"] / plain["value"], 3)}
+            "realtime16384_batched": rounded({k: rb[k] for k in ("value", "unit", "windows", "ms_per_step",
+                                                                 "per_step_ms", "tracking_error_mm",
+                                                                 "waves_per_workgroup", "runs") if k in rb}),
+            "vs_sphere_set_plain": round(r["value"] / plain["value"], 3),
+            "batched_vs_sphere_set_batched": round(rb["value"] / batched["value"], 3)}
         print("bench: distance field done", file=sys.stderr, flush=True)
 
     # the other workloads, the paths their definitions name

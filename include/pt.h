@@ -184,8 +184,9 @@ typedef struct {
        of phi, contact point the sample moved by -phi along that gradient.
        Object-table contacts stay with the sphere set.  Limits
        (PT_E_UNSUPPORTED): L x link_samples + S_max <= 1536;
-       solve_precision 64; cost_mode 0; the windowed, gradient and refinement
-       calls return PT_E_UNSUPPORTED.  Both hand modes. */
+       solve_precision 64; cost_mode 0; the gradient and refinement calls
+       return PT_E_UNSUPPORTED.  Both hand modes (the windowed calls with
+       the kinematic hand only, as for the sphere set). */
     int32_t collision_mode;
     int32_t link_samples; /* 1..64                                             */
     int32_t sdf_n;        /* grid nodes per axis, 2..128                       */

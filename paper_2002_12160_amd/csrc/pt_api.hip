@@ -670,7 +670,6 @@ pt_status pt_run_window(pt_batch b, const float *u_win, const float *obs_gt_win,
 {
     if (!b) return fail(PT_E_ARG, "batch is NULL");
     if (b->hand_mode == 1) return fail(PT_E_UNSUPPORTED, "the windowed path is not built for the PD hand");
-    if (b->P.collision_mode == 1) return fail(PT_E_UNSUPPORTED, "the windowed path is not built for the distance-field collision");
     if (!u_win || !obs_gt_win || !cost_sum) return fail(PT_E_ARG, "u_win/obs_gt_win/cost_sum is NULL");
     hipStream_t st = (hipStream_t)s;
     if (!graph)
@@ -724,7 +723,6 @@ pt_status pt_run_window_static(pt_batch b, const float *u_win, const float *obs_
 {
     if (!b) return fail(PT_E_ARG, "batch is NULL");
     if (b->hand_mode == 1) return fail(PT_E_UNSUPPORTED, "the windowed path is not built for the PD hand");
-    if (b->P.collision_mode == 1) return fail(PT_E_UNSUPPORTED, "the windowed path is not built for the distance-field collision");
     if (!u_win || !obs_gt_win || !cost_sum) return fail(PT_E_ARG, "u_win/obs_gt_win/cost_sum is NULL");
     const Consts &P = b->P;
     if ((size_t)P.T * P.L > STATIC_SEG_RECORDS)
@@ -746,7 +744,6 @@ pt_status pt_autotune(pt_batch b, const float *u_win, const float *obs_gt_win, i
 {
     if (!b) return fail(PT_E_ARG, "batch is NULL");
     if (b->hand_mode == 1) return fail(PT_E_UNSUPPORTED, "the windowed path is not built for the PD hand");
-    if (b->P.collision_mode == 1) return fail(PT_E_UNSUPPORTED, "the windowed path is not built for the distance-field collision");
     if (!u_win || !obs_gt_win) return fail(PT_E_ARG, "u_win/obs_gt_win is NULL");
     hipStream_t st = (hipStream_t)s;
     const Consts &P = b->P;

@@ -522,7 +522,8 @@ __global__ __launch_bounds__(1024) void k_resample(Consts P, ResampleArgs R, con
 // (the Eq. 3 kernel for large caps, a few registers over what two
 // wavefronts per SIMD leave, is held to two with a small spill: ~12% more
 // throughput on the 16384-simulation workload)
-template <typename SR, bool EQ3, bool PT>
+// SDF: links against the object's distance field (collision_mode 1)
+template <typename SR, bool EQ3, bool PT, bool SDF = false>
 __global__ __launch_bounds__(StepBounds<SR>::threads) __attribute__((amdgpu_waves_per_eu(!PT ? 2 : 1))) void
 k_window(Consts P, Tables tb, const float *__restrict__ seg_win, float *__restrict__ state,
          float *__restrict__ params, float *__restrict__ warm, const float *__restrict__ obs_gt_win,
@@ -549,6 +550,13 @@ k_window(Consts P, Tables tb, const float *__restrict__ seg_win, float *__restri
         const int S = tb.n_spheres[type];
         const float *sph = tb.spheres + (size_t)type * P.S_max * 4;
         const float inv[3] = {tb.inv_inertia[3 * type], tb.inv_inertia[3 * type + 1], tb.inv_inertia[3 * type + 2]};
+        SdfRef sdf;
+        if (SDF) {
+            sdf.v = tb.sdf + (size_t)type * P.sdf_n * P.sdf_n * P.sdf_n;
+            sdf.box = tb.sdf_box + 4 * type;
+            sdf.n = P.sdf_n;
+            sdf.M = P.link_samples;
+        }
         Body B;
         load_body(state, params, P.K, e, B);
         int wkey;
@@ -565,7 +573,7 @@ k_window(Consts P, Tables tb, const float *__restrict__ seg_win, float *__restri
             float *ck = ckpt ? ckpt + ((size_t)e * P.T + t) * ckpt_step_floats(P.C_max) : nullptr;
             if (ck) save_body(ck, B);
             StepState<SR> sst;
-            step_setup<SR>(P, seg, sph, S, inv, B, wkey, wr, lds, st, sst);
+            step_setup<SR, SDF>(P, seg, sph, S, inv, B, wkey, wr, lds, st, sst, sdf);
             step_solve<SR, true, PT>(P, sst, B.mu, inv, reinterpret_cast<SR *>(lds.cand_d));
             if (ck) save_contact<SR>(ck, P.C_max, sst);
             step_finish<SR>(P, sst, inv, B, wkey, wr, link, imp);
@@ -715,11 +723,14 @@ hipError_t launch_resample(const Consts &P, const ResampleArgs &R, const int32_t
 
 // the window kernel for a batch: solve precision, cost mode, and the paired
 // line-search trials when no step can hold more than 32 contacts (C_max <=
-// 32: latency-bound populations, where the extra registers cost nothing)
+// 32: latency-bound populations, where the extra registers cost nothing);
+// the distance-field collision with the float64 solve and the force terms
+// only (checked at batch creation)
 template <typename F>
 static hipError_t with_window_kernel(const Consts &P, F f)
 {
     const bool eq3 = P.cost_mode == 1, pt = P.C_max <= 32;
+    if (P.collision_mode == 1) return pt ? f(k_window<double, false, true, true>) : f(k_window<double, false, false, true>);
     if (P.solve_fp64) {
         if (eq3) return pt ? f(k_window<double, true, true>) : f(k_window<double, true, false>);
         return pt ? f(k_window<double, false, true>) : f(k_window<double, false, false>);
@@ -761,6 +772,8 @@ hipError_t set_lds_limits(size_t bytes)
                         reinterpret_cast<const void *>(k_window<double, false, true>),
                         reinterpret_cast<const void *>(k_window<float, true, true>),
                         reinterpret_cast<const void *>(k_window<double, true, true>),
+                        reinterpret_cast<const void *>(k_window<double, false, false, true>),
+                        reinterpret_cast<const void *>(k_window<double, false, true, true>),
                         reinterpret_cast<const void *>(k_step<float, false>),
                         reinterpret_cast<const void *>(k_step<double, false>),
                         reinterpret_cast<const void *>(k_step<float, true>),

@@ -3,8 +3,9 @@ GPU against the FP64 oracle: per-step parity of state, contacts and
 observation where the parity rule of tests/parity_util.py calls a step
 clear, with no exceptions there -- the exact box field of the small
 workload's cuboid, the sampled fields of the real-time workload's sixteen
-superquadrics, and the PD-controlled hand on the box field; and the calls
-the distance-field path does not support."""
+superquadrics, and the PD-controlled hand on the box field; the batched
+window bit for bit equal to the per-step path; and the calls the
+distance-field path does not support."""
 import dataclasses
 
 import numpy as np
@@ -63,15 +64,33 @@ def test_sdf_pd_hand_per_step_parity(pt):
     assert not fails
 
 
+@pytest.mark.parametrize("cfg_name,K", [("small", 37), ("realtime16384", 48), ("small/C_max=64", 37)])
+def test_sdf_batched_equals_plain_bitwise(pt, cfg_name, K):
+    # the window kernel's distance-field instantiations against the per-step
+    # kernel's, with and without the graph (C_max <= 32 pairs the line
+    # search's trials in the window kernel)
+    from tests.test_gpu_paths import _assert_same, run_batched, run_plain
+    name, _, cap = cfg_name.partition("/C_max=")
+    cfg = _sdf_cfg(name)
+    if cap:
+        cfg = cfg.with_(C_max=int(cap))
+    _say(f"distance field, plain vs batched: {cfg_name} K={K}")
+    sc = S.make_scene(cfg, K=K, steps=40)
+    ref = run_plain(pt, sc, 3, cfg.T)
+    for graph in (False, True):
+        got = run_batched(pt, sc, 3, cfg.T, graph=graph)
+        _assert_same(ref, got, f"graph={graph}")
+
+
 def test_sdf_rejects_the_calls_it_does_not_support(pt):
     cfg = _sdf_cfg("small")
     sc = S.make_scene(cfg.with_(T=10), K=8, steps=12)
     b = pt.Batch.from_scene(sc, T=10)
     u_win = torch.as_tensor(sc.u[:11].astype(np.float32), device="cuda")
     gt = torch.zeros((10, 4, b.L, 1), device="cuda")
-    cost = torch.zeros(8, device="cuda")
-    for call in (lambda: b.run_window(u_win, gt, cost), lambda: b.run_window_static(u_win, gt, cost)):
-        with pytest.raises(pt.PtError) as ei:
-            call()
-        assert ei.value.code == 5
+    env = torch.arange(8, dtype=torch.int32, device="cuda")
+    start, warm0 = b.start_of(env)
+    with pytest.raises(pt.PtError) as ei:
+        b.window_grad(u_win, gt, env, start, warm0)
+    assert ei.value.code == 5
     b.close()
