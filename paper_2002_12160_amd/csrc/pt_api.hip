@@ -246,7 +246,7 @@ pt_status validate(const pt_batch_desc *d)
 // common link are joined (transitively) into a group; groups are numbered
 // by their lowest joint and hold their joints in increasing order, which
 // gives every joint its position.  Every joint drives at most one link.
-pt_status build_pd_table(const pt_batch_desc *d, std::vector<int32_t> &tab, int &groups, int &dmax)
+pt_status build_pd_table(const pt_batch_desc *d, std::vector<int32_t> &tab, int &groups, int &dmax, int &gmax)
 {
     const int L = d->L, D = d->D;
     std::vector<std::vector<int>> chain(L);
@@ -287,6 +287,8 @@ pt_status build_pd_table(const pt_batch_desc *d, std::vector<int32_t> &tab, int 
         members[group_of_root[r]].push_back(j);
     }
     groups = (int)members.size();
+    gmax = 0;
+    for (const auto &m : members) gmax = std::max(gmax, (int)m.size());
     std::vector<int> jat, pos(D), gs(D), gn(D), gfirst;
     for (const auto &m : members) {
         if ((int)m.size() > pt::PD_GMAX)
@@ -385,9 +387,9 @@ pt_status pt_create_batch(const pt_batch_desc *d, pt_batch *out)
     const int red_rows = d->C_max <= 16 ? 16 : (d->C_max <= 32 ? 32 : 64);
     // the PD hand's structure
     std::vector<int32_t> pd_tab;
-    int pd_groups = 0, pd_dmax = 0;
+    int pd_groups = 0, pd_dmax = 0, pd_gmax = 0;
     if (d->hand_mode == 1) {
-        st = build_pd_table(d, pd_tab, pd_groups, pd_dmax);
+        st = build_pd_table(d, pd_tab, pd_groups, pd_dmax, pd_gmax);
         if (st != PT_OK) return st;
     }
     // ... and the step's hand kinematics, which use the same LDS first
@@ -419,7 +421,7 @@ pt_status pt_create_batch(const pt_batch_desc *d, pt_batch *out)
     b->n_types = d->n_types;
     b->hand_mode = d->hand_mode;
     if (d->hand_mode == 1) {
-        b->Q = {pd_groups, pd_dmax, d->kp, d->kd, d->link_mass, d->w_q};
+        b->Q = {pd_groups, pd_dmax, pd_gmax, d->kp, d->kd, d->link_mass, d->w_q};
         b->hstate = d->hand_state;
     }
     b->state = d->state;

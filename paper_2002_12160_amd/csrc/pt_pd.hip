@@ -16,7 +16,9 @@
 
 namespace pt {
 
-template <bool SDF>
+// G: the batch's largest joint group, rounded up to 4 or PD_GMAX (the size
+// of the group eliminations)
+template <bool SDF, int G>
 __global__ __launch_bounds__(WAVE) void k_step_pd(Consts P, PdConsts Q, Tables tb, PdTab T,
                                                   const float *__restrict__ u, float *__restrict__ state,
                                                   float *__restrict__ params, float *__restrict__ warm,
@@ -68,9 +70,10 @@ __global__ __launch_bounds__(WAVE) void k_step_pd(Consts P, PdConsts Q, Tables t
         sdf.M = P.link_samples;
     }
     step_setup<double, SDF>(P, lds.seg, sph, S, inv, B, wkey, wr, lds, st, sst, sdf);
-    int pos, nseg;
-    pd_order_contacts(sst, pl, pos, nseg);
-    step_solve_pd(P, Q, T, sst, B.mu, inv, reinterpret_cast<double *>(lds.cand_d), pl, pos, nseg);
+    int pos;
+    uint64_t ends;
+    pd_order_contacts(sst, pl, pos, ends);
+    step_solve_pd<G>(P, Q, T, sst, B.mu, inv, reinterpret_cast<double *>(lds.cand_d), pl, pos, ends);
     int link;
     float imp[3];
     step_finish<double>(P, sst, inv, B, wkey, wr, link, imp);
@@ -159,8 +162,13 @@ size_t pd_wave_lds_bytes(int max_cand, int L, int D) { return wave_lds_bytes(max
 
 hipError_t set_pd_lds_limits(size_t bytes)
 {
-    hipError_t e = set_dynamic_lds_limit((const void *)k_step_pd<false>, bytes);
-    return e != hipSuccess ? e : set_dynamic_lds_limit((const void *)k_step_pd<true>, bytes);
+    const void *fs[] = {(const void *)k_step_pd<false, 4>, (const void *)k_step_pd<true, 4>,
+                        (const void *)k_step_pd<false, PD_GMAX>, (const void *)k_step_pd<true, PD_GMAX>};
+    for (const void *f : fs) {
+        hipError_t e = set_dynamic_lds_limit(f, bytes);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_step_pd(const Consts &P, const PdConsts &Q, const Tables &tb, const int32_t *pd_tab,
@@ -169,12 +177,15 @@ hipError_t launch_step_pd(const Consts &P, const PdConsts &Q, const Tables &tb, 
 {
     const PdTab T = {pd_tab, P.D, P.L};
     const size_t lds = pd_wave_lds_bytes(P.max_cand, P.L, P.D);
+    auto go = [&](auto kern) {
+        hipLaunchKernelGGL(kern, dim3(P.K), dim3(WAVE), lds, s, P, Q, tb, T, u, state, params, warm, hstate,
+                           contacts, stats);
+    };
+    const bool small = Q.gmax <= 4;
     if (P.collision_mode == 1)
-        hipLaunchKernelGGL(k_step_pd<true>, dim3(P.K), dim3(WAVE), lds, s, P, Q, tb, T, u, state, params, warm,
-                           hstate, contacts, stats);
+        small ? go(k_step_pd<true, 4>) : go(k_step_pd<true, PD_GMAX>);
     else
-        hipLaunchKernelGGL(k_step_pd<false>, dim3(P.K), dim3(WAVE), lds, s, P, Q, tb, T, u, state, params, warm,
-                           hstate, contacts, stats);
+        small ? go(k_step_pd<false, 4>) : go(k_step_pd<false, PD_GMAX>);
     return hipGetLastError();
 }
 

@@ -53,6 +53,7 @@ constexpr int PD_YS = 8;      // row stride of the group solutions (7 columns us
 struct PdConsts {
     int groups;        // independent joint groups
     int dmax;          // deepest link of the tree (roots at 0)
+    int gmax;          // joints in the largest group
     float kp, kd, link_mass, w_q;
 };
 
@@ -95,14 +96,13 @@ struct PdLds {
     double *tot;    // [48] sums over all contacts
     double *acc;    // [48] the object's reduced system
     int *rowlink;   // [64] link of each row of the ordered contacts
-    int *segrow;    // [65] first row of each link's run of rows
-    int *seglink;   // [64] link of each run
+    int *linkrow;   // [64] first row of each link's run of rows (-1: no contact on the link)
 };
 
 __host__ __device__ constexpr size_t pd_lds_bytes(int D)
 {
     return (size_t)8 * ((size_t)D * (6 + PD_GMAX + 1 + 6 + 6 + 1 + PD_GMAX + PD_YS + 1 + 1) + 96) +
-           (size_t)4 * (64 + 72 + 64);
+           (size_t)4 * (64 + 64);
 }
 
 // LDS of the hand kinematics (in the candidate list, before the narrow
@@ -128,8 +128,7 @@ __device__ __forceinline__ PdLds carve_pd(char *p, int D)
     s.acc = d; d += 48;
     int *i = reinterpret_cast<int *>(d);
     s.rowlink = i; i += 64;
-    s.segrow = i; i += 72;
-    s.seglink = i;
+    s.linkrow = i;
     return s;
 }
 
@@ -293,9 +292,11 @@ __device__ __forceinline__ void pd_twists(int D, const float *x, const PdLds &pl
     wave_sync();
 }
 
-// Orders the contacts by (link, lane): pos = this contact's row; the runs
-// of rows with one link (segrow, seglink, nseg of them) for the per-link sums.
-__device__ __forceinline__ void pd_order_contacts(const StepState<double> &st, const PdLds &pl, int &pos, int &nseg)
+// Orders the contacts by (link, lane): pos = this contact's row; ends (bit r)
+// marks the rows that close a run of rows with one link, and linkrow the
+// first row of each link's run (-1: no contact on the link).
+__device__ __forceinline__ void pd_order_contacts(const StepState<double> &st, const PdLds &pl, int &pos,
+                                                  uint64_t &ends)
 {
     const int lane = lane_id(), C = st.C;
     const int lk = st.act ? st.l : 0x7fffffff;
@@ -305,27 +306,25 @@ __device__ __forceinline__ void pd_order_contacts(const StepState<double> &st, c
         ps += (o < lk || (o == lk && c < lane)) ? 1 : 0;
     }
     pos = ps;
+    pl.linkrow[lane] = -1;
     if (st.act) pl.rowlink[ps] = lk;
     wave_sync();
     const bool start = lane < C && (lane == 0 || pl.rowlink[lane - 1] != pl.rowlink[lane]);
-    const uint64_t sm = __ballot(start);
-    nseg = __popcll(sm);
-    if (start) {
-        const int s = mask_rank(sm);
-        pl.segrow[s] = lane;
-        pl.seglink[s] = pl.rowlink[lane];
-    }
-    if (lane == 0) pl.segrow[nseg] = C;
+    const bool end = lane < C && (lane == C - 1 || pl.rowlink[lane + 1] != pl.rowlink[lane]);
+    if (start) pl.linkrow[pl.rowlink[lane]] = lane;
+    ends = __ballot(end);
     wave_sync();
 }
 
 // Sums of N values per contact over each run of rows (one link) and over all
-// contacts: an active lane writes its values as row `pos`; lanes e < N scan
-// the rows in order, each run's sum overwriting its first row (a lane only
-// rewrites its own column of a row it has read) and the total landing in
-// tot[e].  buf: rows of RedStride<double> doubles.
+// contacts: an active lane writes its values as row `pos`; lanes e < N then
+// read the C rows sixteen at a time and add them in row order, each run's
+// sum overwriting its first row (a lane only rewrites its own column of a
+// row it has read) and the total landing in tot[e].  The runs' ends (bit r
+// of ends) are wave-uniform, so the scan branches on them in scalar code.
+// buf: rows of RedStride<double> doubles.
 template <int N>
-__device__ __forceinline__ void pd_segsum(const double (&v)[N], bool act, int pos, const int *segrow, int nseg,
+__device__ __forceinline__ void pd_segsum(const double (&v)[N], bool act, int pos, int C, uint64_t ends,
                                           double *buf, double *tot)
 {
     constexpr int RS = RedStride<double>::value;
@@ -338,19 +337,24 @@ __device__ __forceinline__ void pd_segsum(const double (&v)[N], bool act, int po
     }
     wave_sync();
     if (lane < N) {
-        double t = 0.0;
-        for (int s = 0; s < nseg; ++s) {
-            const int r0 = segrow[s], r1 = segrow[s + 1];
-            double a = 0.0;
-            int r = r0;
-            for (; r + 4 <= r1; r += 4) {
-                const double x0 = buf[r * RS + lane], x1 = buf[(r + 1) * RS + lane];
-                const double x2 = buf[(r + 2) * RS + lane], x3 = buf[(r + 3) * RS + lane];
-                a += x0; a += x1; a += x2; a += x3;
+        double t = 0.0, a = 0.0;
+        int start = 0;
+        for (int r0 = 0; r0 < C; r0 += 16) {
+            double x[16];
+#pragma unroll
+            for (int k = 0; k < 16; ++k) x[k] = r0 + k < C ? buf[(r0 + k) * RS + lane] : 0.0;
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                const int r = r0 + k;
+                if (r >= C) continue;
+                a += x[k];
+                if ((ends >> r) & 1ull) {
+                    buf[start * RS + lane] = a;
+                    t += a;
+                    a = 0.0;
+                    start = r + 1;
+                }
             }
-            for (; r < r1; ++r) a += buf[r * RS + lane];
-            buf[r0 * RS + lane] = a;
-            t += a;
         }
         tot[lane] = t;
     }
@@ -360,7 +364,9 @@ __device__ __forceinline__ void pd_segsum(const double (&v)[N], bool act, int po
 // X_g y = b for every group g and right-hand side c (one lane per pair):
 // b's entry at position p is B1[p ld1 + c] for c < n1 and B2[p] for c == n1
 // (when B2 is given); y goes to Y[p ldy + c].  Gaussian elimination with
-// partial pivoting on the block padded to PD_GMAX with the identity.
+// partial pivoting on the block padded to G (the batch's largest group,
+// at most PD_GMAX; rows of X at stride PD_GMAX) with the identity.
+template <int G>
 __device__ __forceinline__ void pd_group_solve(const PdTab &T, int groups, const double *X, const double *B1, int ld1,
                                                int n1, const double *B2, double *Y, int ldy)
 {
@@ -368,21 +374,21 @@ __device__ __forceinline__ void pd_group_solve(const PdTab &T, int groups, const
     for (int t = lane_id(); t < groups * ncol; t += WAVE) {
         const int g = t / ncol, c = t - g * ncol;
         const int g0 = T.gfirst(g), n = T.gfirst(g + 1) - g0;
-        double a[PD_GMAX][PD_GMAX], y[PD_GMAX];
+        double a[G][G], y[G];
 #pragma unroll
-        for (int i = 0; i < PD_GMAX; ++i) {
+        for (int i = 0; i < G; ++i) {
 #pragma unroll
-            for (int k = 0; k < PD_GMAX; ++k)
+            for (int k = 0; k < G; ++k)
                 a[i][k] = (i < n && k < n) ? X[PD_GMAX * (g0 + i) + k] : (i == k ? 1.0 : 0.0);
             y[i] = i < n ? (c < n1 ? B1[(size_t)(g0 + i) * ld1 + c] : B2[g0 + i]) : 0.0;
         }
 #pragma unroll
-        for (int k = 0; k < PD_GMAX; ++k) {
+        for (int k = 0; k < G; ++k) {
 #pragma unroll
-            for (int i = k + 1; i < PD_GMAX; ++i) {
+            for (int i = k + 1; i < G; ++i) {
                 const bool sw = fabs(a[i][k]) > fabs(a[k][k]);
 #pragma unroll
-                for (int m = k; m < PD_GMAX; ++m) {
+                for (int m = k; m < G; ++m) {
                     const double hi = a[i][m], lo = a[k][m];
                     a[k][m] = sw ? hi : lo;
                     a[i][m] = sw ? lo : hi;
@@ -393,22 +399,22 @@ __device__ __forceinline__ void pd_group_solve(const PdTab &T, int groups, const
             }
             const double inv = 1.0 / a[k][k];
 #pragma unroll
-            for (int i = k + 1; i < PD_GMAX; ++i) {
+            for (int i = k + 1; i < G; ++i) {
                 const double f = a[i][k] * inv;
 #pragma unroll
-                for (int m = k + 1; m < PD_GMAX; ++m) a[i][m] -= f * a[k][m];
+                for (int m = k + 1; m < G; ++m) a[i][m] -= f * a[k][m];
                 y[i] -= f * y[k];
             }
         }
 #pragma unroll
-        for (int k = PD_GMAX - 1; k >= 0; --k) {
+        for (int k = G - 1; k >= 0; --k) {
             double s = y[k];
 #pragma unroll
-            for (int m = k + 1; m < PD_GMAX; ++m) s -= a[k][m] * y[m];
+            for (int m = k + 1; m < G; ++m) s -= a[k][m] * y[m];
             y[k] = s / a[k][k];
         }
 #pragma unroll
-        for (int i = 0; i < PD_GMAX; ++i)
+        for (int i = 0; i < G; ++i)
             if (i < n) Y[(size_t)(g0 + i) * ldy + c] = y[i];
     }
 }
@@ -433,12 +439,13 @@ __device__ __forceinline__ void pd_link_twist(const PdTab &T, int l, int L, cons
 // Joint rates for the impulses st.r: A_h qdot = pm + (joint impulse of the
 // contacts), the joint impulse -s_p . (sum of the wrenches (f, rho x f)
 // about x on the links p moves), f the impulse on the object.  To pl.nuh.
+template <int G>
 __device__ __forceinline__ void pd_hand_rates(const Consts &P, const PdConsts &Q, const PdTab &T,
-                                              const StepState<double> &st, int pos, int nseg, double *red,
+                                              const StepState<double> &st, int pos, uint64_t ends, double *red,
                                               const PdLds &pl)
 {
     constexpr int RS = RedStride<double>::value;
-    const int lane = lane_id(), L = P.L, D = P.D;
+    const int lane = lane_id(), D = P.D;
     double w6[6] = {0, 0, 0, 0, 0, 0};
     if (st.act) {
         const double *F = st.F, *r = st.r;
@@ -449,15 +456,14 @@ __device__ __forceinline__ void pd_hand_rates(const Consts &P, const PdConsts &Q
         w6[0] = f[0]; w6[1] = f[1]; w6[2] = f[2];
         w6[3] = t[0]; w6[4] = t[1]; w6[5] = t[2];
     }
-    pd_segsum<6>(w6, st.act, pos, pl.segrow, nseg, red, pl.tot);
+    pd_segsum<6>(w6, st.act, pos, st.C, ends, red, pl.tot);
     if (lane < D) {
-        const uint64_t sb = T.sub(lane);
         const double *sp = pl.S + 6 * lane;
         double tau = 0.0;
-        for (int s = 0; s < nseg; ++s) {
-            const int l = pl.seglink[s];
-            if (l < L && ((sb >> l) & 1ull)) {
-                const double *row = red + pl.segrow[s] * RS;
+        for (uint64_t sb = T.sub(lane); sb; sb &= sb - 1) {
+            const int r0 = pl.linkrow[__builtin_ctzll(sb)];
+            if (r0 >= 0) {
+                const double *row = red + r0 * RS;
 #pragma unroll
                 for (int k = 0; k < 6; ++k) tau -= sp[k] * row[k];
             }
@@ -465,16 +471,17 @@ __device__ __forceinline__ void pd_hand_rates(const Consts &P, const PdConsts &Q
         pl.zh[lane] = pl.pm[lane] + tau;
     }
     wave_sync();
-    pd_group_solve(T, Q.groups, pl.Ah, pl.zh, 1, 1, nullptr, pl.nuh, 1);
+    pd_group_solve<G>(T, Q.groups, pl.Ah, pl.zh, 1, 1, nullptr, pl.nuh, 1);
     wave_sync();
 }
 
 // The contact solve of a PD step (the kinematic path's Newton method over
 // the generalised velocity (v, w, qdot)); leaves st.r, st.nu (object) and
 // pl.nuh (joint rates) for the final impulses.
+template <int G>
 __device__ __forceinline__ void step_solve_pd(const Consts &P, const PdConsts &Q, const PdTab &T,
                                               StepState<double> &st, float mu_f, const float *inv_in, double *red,
-                                              const PdLds &pl, int pos, int nseg)
+                                              const PdLds &pl, int pos, uint64_t ends)
 {
     using SR = double;
     constexpr int RS = RedStride<double>::value;
@@ -489,7 +496,7 @@ __device__ __forceinline__ void step_solve_pd(const Consts &P, const PdConsts &Q
     body_dv(st, r, nu);
     nu[0] += st.vs[0]; nu[1] += st.vs[1]; nu[2] += st.vs[2];
     nu[3] += st.ws[0]; nu[4] += st.ws[1]; nu[5] += st.ws[2];
-    pd_hand_rates(P, Q, T, st, pos, nseg, red, pl);
+    pd_hand_rates<G>(P, Q, T, st, pos, ends, red, pl);
     st.psi_end = st.C > 0 && P.newton_iters == 0 ? SR(-1) : SR(0);
     if (st.C > 0) {
         SR u[3];
@@ -533,18 +540,17 @@ __device__ __forceinline__ void step_solve_pd(const Consts &P, const PdConsts &Q
             schur_contribution(Qw, gw, rho, acc);
             acc[42] = SR(0.5) * (fo.phi[0] * fo.phi[0] + fo.phi[1] * fo.phi[1] + fo.phi[2] * fo.phi[2]);
             // 1. per-link and total sums
-            pd_segsum<43>(acc, act, pos, pl.segrow, nseg, red, pl.tot);
+            pd_segsum<43>(acc, act, pos, st.C, ends, red, pl.tot);
             const SR psi = pl.tot[42];
             // 2. object-hand blocks
             for (int t = lane; t < 6 * D; t += WAVE) {
                 const int p = t / 6, k = t - 6 * (t / 6);
-                const uint64_t sb = T.sub(p);
                 const SR *sp = pl.S + 6 * p;
                 SR aoh = 0, aho = 0, bh = 0;
-                for (int s = 0; s < nseg; ++s) {
-                    const int l = pl.seglink[s];
-                    if (l < L && ((sb >> l) & 1ull)) {
-                        const SR *K = red + pl.segrow[s] * RS;
+                for (uint64_t sb = T.sub(p); sb; sb &= sb - 1) {
+                    const int r0 = pl.linkrow[__builtin_ctzll(sb)];
+                    if (r0 >= 0) {
+                        const SR *K = red + r0 * RS;
 #pragma unroll
                         for (int m = 0; m < 6; ++m) {
                             aoh -= K[6 * k + m] * sp[m];
@@ -578,7 +584,7 @@ __device__ __forceinline__ void step_solve_pd(const Consts &P, const PdConsts &Q
             }
             wave_sync();
             // 3. Y = X^-1 [A_ho | b_h] per group
-            pd_group_solve(T, Q.groups, pl.X, pl.Aho, 6, 6, pl.bh, pl.Y, PD_YS);
+            pd_group_solve<G>(T, Q.groups, pl.X, pl.Aho, 6, 6, pl.bh, pl.Y, PD_YS);
             wave_sync();
             // 4. the object's reduced 6x6 system and its solve
             if (lane < 42) {
@@ -648,7 +654,7 @@ __device__ __forceinline__ void step_solve_pd(const Consts &P, const PdConsts &Q
     body_dv(st, r, st.nu);
     st.nu[0] += st.vs[0]; st.nu[1] += st.vs[1]; st.nu[2] += st.vs[2];
     st.nu[3] += st.ws[0]; st.nu[4] += st.ws[1]; st.nu[5] += st.ws[2];
-    pd_hand_rates(P, Q, T, st, pos, nseg, red, pl);
+    pd_hand_rates<G>(P, Q, T, st, pos, ends, red, pl);
 }
 
 }  // namespace pt

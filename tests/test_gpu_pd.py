@@ -144,6 +144,18 @@ def test_pd_per_step_parity_two_joint_fingers(pt):
     assert not fails
 
 
+def test_pd_per_step_parity_five_joint_fingers(pt):
+    # the real-time hand with an abduction joint on every finger: groups of
+    # 5 joints (the elimination sized for up to 6), D = 25, 16 object types
+    _say("PD hand per-step parity: 5 fingers x 5 joints, real-time objects, K=32, 20 steps")
+    cfg = _pd_cfg("realtime16384")
+    cfg = cfg.with_(hand=dataclasses.replace(cfg.hand, abduction=True))
+    n_chk, n_ok, n_contact, fails = pd_parity(pt, cfg, 32, 20)
+    assert n_contact >= 0.25 * n_chk
+    assert n_ok >= 0.15 * n_chk
+    assert not fails
+
+
 def test_pd_free_hand_tracks_the_oracle_without_contacts(pt):
     # the object far away: only the joints move (PD law and mass matrix)
     cfg = _pd_cfg("small")
