@@ -132,6 +132,11 @@ struct pt_batch_s {
     int wpb = 4;
     int step_wpb = 4;
     hipStream_t capture_stream = nullptr;
+    // parts 1.. of the elite refinement run on these streams, forked from
+    // and joined back to the caller's stream by the events
+    static constexpr int REFINE_PARTS = 3;
+    hipStream_t side_stream[REFINE_PARTS - 1] = {};
+    hipEvent_t ev_fork = nullptr, ev_join[REFINE_PARTS - 1] = {};
     // captured windows, keyed by their buffers (a driver that double-buffers
     // its inputs alternates between a few); least recently used is evicted
     static constexpr int N_GRAPHS = 4;
@@ -513,6 +518,11 @@ pt_status pt_create_batch(const pt_batch_desc *d, pt_batch *out)
     HIP_TRY_C(hipMemset(b->d_stats, 0, sizeof(int64_t) * pt::STATS_SLOTS * pt::STATS_STRIDE));
     HIP_TRY_C(hipMemset(b->d_contacts, 0, sizeof(float) * K * d->C_max * 4));
     HIP_TRY_C(hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking));
+    HIP_TRY_C(hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming));
+    for (int k = 0; k < pt_batch_s::REFINE_PARTS - 1; ++k) {
+        HIP_TRY_C(hipStreamCreateWithFlags(&b->side_stream[k], hipStreamNonBlocking));
+        HIP_TRY_C(hipEventCreateWithFlags(&b->ev_join[k], hipEventDisableTiming));
+    }
     // environments per workgroup within the LDS budget (autotuned later)
     b->wpb = 4;
     while (b->wpb > 1 && ((size_t)b->wpb * wave_lds > 160 * 1024 || b->wpb > max_wpb(P))) b->wpb >>= 1;
@@ -531,6 +541,11 @@ pt_status pt_destroy_batch(pt_batch b)
     (void)hipDeviceSynchronize();
     b->drop_graphs();
     if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
+    for (int k = 0; k < pt_batch_s::REFINE_PARTS - 1; ++k) {
+        if (b->side_stream[k]) (void)hipStreamDestroy(b->side_stream[k]);
+        if (b->ev_join[k]) (void)hipEventDestroy(b->ev_join[k]);
+    }
+    if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
     void *ptrs[] = {b->d_hand, b->d_spheres, b->d_inv, b->d_nsph, b->d_type, b->d_group_of, b->d_group_start,
                     b->d_order, b->d_queue, b->d_stats, b->d_seg_win, b->d_contacts,
                     b->d_seg_grad, b->d_tune, b->d_ckpt, b->d_wckpt, b->d_elite, b->d_ref, b->d_snap,
@@ -881,24 +896,56 @@ pt_status pt_refine_elites(pt_batch b, const float *u_win, const float *obs_gt_w
         const bool from_window = b->d_wckpt != nullptr;
         HIP_TRY(launch_refine_gather(n, P.K, P.C_max, b->d_elite, start_state, start_params, start_warm,
                                      from_window ? cost_sum : nullptr, r.xi, r.warm0, r.cost, r.rho, step, st));
-        if (!from_window)
-            HIP_TRY(launch_window_fwd(P, tb, b->d_seg_grad, n, 0, n, b->d_elite, r.xi, r.warm0, obs_gt_win, r.cost,
-                                      nullptr, nullptr, b->d_ckpt, st));
-        HIP_TRY(launch_window_bwd(P, tb, b->d_seg_grad, n, 0, n, b->d_elite, r.xi, obs_gt_win,
-                                  from_window ? b->d_wckpt : b->d_ckpt, from_window, nullptr, r.g, st));
+        // every elite's chain of replays and sweeps is its own, so the elites
+        // go in parts on streams of their own: one part's short kernels and
+        // the tail of its replay overlap the others' replays (the same bits
+        // as one launch over all of them); each part has its own checkpoints
+        constexpr int NP = pt_batch_s::REFINE_PARTS;
+        struct Part {
+            int i0, count;
+            hipStream_t s;
+            float *ckpt;
+        } part[NP];
+        int np = 0;
+        for (int k = 0, i0 = 0; k < NP; ++k) {
+            const int cnt = (n - i0) / (NP - k) + ((n - i0) % (NP - k) != 0);
+            if (cnt <= 0) break;
+            part[np++] = {i0, cnt, k == 0 ? st : b->side_stream[k - 1], b->d_ckpt + ckpt_floats(P, i0)};
+            i0 += cnt;
+        }
+        if (np > 1) {
+            HIP_TRY(hipEventRecord(b->ev_fork, st));
+            for (int k = 1; k < np; ++k) HIP_TRY(hipStreamWaitEvent(part[k].s, b->ev_fork, 0));
+        }
+        for (int k = 0; k < np; ++k) {
+            const Part &c = part[k];
+            if (!from_window)
+                HIP_TRY(launch_window_fwd(P, tb, b->d_seg_grad, n, c.i0, c.count, b->d_elite, r.xi, r.warm0,
+                                          obs_gt_win, r.cost, nullptr, nullptr, c.ckpt, c.s));
+            HIP_TRY(launch_window_bwd(P, tb, b->d_seg_grad, n, c.i0, c.count, b->d_elite, r.xi, obs_gt_win,
+                                      from_window ? b->d_wckpt : c.ckpt, from_window, nullptr, r.g, c.s));
+        }
         for (int it = 0; it < steps; ++it) {
             // trial, its replay (checkpointed unless it is the last), keep or
             // halve, then the gradient at the kept trials only
             const bool last = it == steps - 1;
-            HIP_TRY(launch_refine_propose(n, A, r.xi, r.g, r.rho, r.xi_try, st));
-            HIP_TRY(launch_window_fwd(P, tb, b->d_seg_grad, n, 0, n, b->d_elite, r.xi_try, r.warm0, obs_gt_win,
-                                      r.cost_try, r.end_state, r.end_warm, last ? nullptr : b->d_ckpt, st));
-            HIP_TRY(launch_refine_accept(n, P.K, P.C_max, b->d_elite, r.cost, r.cost_try, r.xi, r.xi_try, r.rho,
-                                         r.flag, r.end_state, r.end_warm, b->state, b->params, b->warm, cost_sum,
-                                         st));
-            if (!last)
-                HIP_TRY(launch_window_bwd(P, tb, b->d_seg_grad, n, 0, n, b->d_elite, r.xi, obs_gt_win, b->d_ckpt,
-                                          false, r.flag, r.g, st));
+            for (int k = 0; k < np; ++k) {
+                const Part &c = part[k];
+                HIP_TRY(launch_refine_propose(n, c.i0, c.count, A, r.xi, r.g, r.rho, r.xi_try, c.s));
+                HIP_TRY(launch_window_fwd(P, tb, b->d_seg_grad, n, c.i0, c.count, b->d_elite, r.xi_try, r.warm0,
+                                          obs_gt_win, r.cost_try, r.end_state, r.end_warm, last ? nullptr : c.ckpt,
+                                          c.s));
+                HIP_TRY(launch_refine_accept(n, c.i0, c.count, P.K, P.C_max, b->d_elite, r.cost, r.cost_try, r.xi,
+                                             r.xi_try, r.rho, r.flag, r.end_state, r.end_warm, b->state, b->params,
+                                             b->warm, cost_sum, c.s));
+                if (!last)
+                    HIP_TRY(launch_window_bwd(P, tb, b->d_seg_grad, n, c.i0, c.count, b->d_elite, r.xi, obs_gt_win,
+                                              c.ckpt, false, r.flag, r.g, c.s));
+            }
+        }
+        for (int k = 1; k < np; ++k) {
+            HIP_TRY(hipEventRecord(b->ev_join[k - 1], part[k].s));
+            HIP_TRY(hipStreamWaitEvent(st, b->ev_join[k - 1], 0));
         }
     }
     if (best) HIP_TRY(launch_argmin(P.G, b->d_group_start, cost_sum, best, st));

@@ -229,12 +229,15 @@ __global__ void k_refine_gather(int n, int K, int C_max, const int32_t *__restri
 }
 
 // trial start: xi - rho (s o s o g) / |s o g| over (x, q, v, w, m, mu), then
-// q renormalised and m, mu clamped; the one-step force is kept
-__global__ void k_refine_propose(int n, RefineArgs A, const float *__restrict__ xi, const float *__restrict__ grad,
-                                 const float *__restrict__ rho, float *__restrict__ xi_try)
+// q renormalised and m, mu clamped; the one-step force is kept (elites
+// i0 .. i0+count-1 of arrays with row stride n)
+__global__ void k_refine_propose(int n, int i0, int count, RefineArgs A, const float *__restrict__ xi,
+                                 const float *__restrict__ grad, const float *__restrict__ rho,
+                                 float *__restrict__ xi_try)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= count) return;
+    const int i = i0 + c;
     float x[XI_ROWS];
     for (int r = 0; r < XI_ROWS; ++r) x[r] = xi[(size_t)r * n + i];
     float sg2 = 0.f;
@@ -258,16 +261,18 @@ __global__ void k_refine_propose(int n, RefineArgs A, const float *__restrict__ 
 // keep the trial where its replayed window cost is lower (the batch slot then
 // takes the replay's end-of-window state, mass, friction and warm cache, and
 // its window cost; flag[i] = 1 asks for the gradient at the new start);
-// otherwise halve the step (flag[i] = 0)
-__global__ void k_refine_accept(int n, int K, int C_max, const int32_t *__restrict__ env, float *__restrict__ cost_cur,
+// otherwise halve the step (flag[i] = 0); elites i0 .. i0+count-1
+__global__ void k_refine_accept(int n, int i0, int count, int K, int C_max, const int32_t *__restrict__ env,
+                                float *__restrict__ cost_cur,
                                 const float *__restrict__ cost_try, float *__restrict__ xi,
                                 const float *__restrict__ xi_try, float *__restrict__ rho, int32_t *__restrict__ flag,
                                 const float *__restrict__ end_state, const float *__restrict__ end_warm,
                                 float *__restrict__ state, float *__restrict__ params, float *__restrict__ warm,
                                 float *__restrict__ cost_sum)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= count) return;
+    const int i = i0 + c;
     flag[i] = 0;
     const int e = env[i];
     if (e < 0 || e >= K) return;
@@ -350,22 +355,23 @@ hipError_t launch_refine_gather(int n, int K, int C_max, const int32_t *env, con
     return hipGetLastError();
 }
 
-hipError_t launch_refine_propose(int n, const RefineArgs &A, const float *xi, const float *grad, const float *rho,
-                                 float *xi_try, hipStream_t s)
+hipError_t launch_refine_propose(int n, int i0, int count, const RefineArgs &A, const float *xi, const float *grad,
+                                 const float *rho, float *xi_try, hipStream_t s)
 {
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_refine_propose, dim3((n + 63) / 64), dim3(64), 0, s, n, A, xi, grad, rho, xi_try);
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_refine_propose, dim3((count + 63) / 64), dim3(64), 0, s, n, i0, count, A, xi, grad, rho,
+                       xi_try);
     return hipGetLastError();
 }
 
-hipError_t launch_refine_accept(int n, int K, int C_max, const int32_t *env, float *cost_cur, const float *cost_try,
-                                float *xi, const float *xi_try, float *rho, int32_t *flag, const float *end_state,
-                                const float *end_warm, float *state, float *params, float *warm, float *cost_sum,
-                                hipStream_t s)
+hipError_t launch_refine_accept(int n, int i0, int count, int K, int C_max, const int32_t *env, float *cost_cur,
+                                const float *cost_try, float *xi, const float *xi_try, float *rho, int32_t *flag,
+                                const float *end_state, const float *end_warm, float *state, float *params,
+                                float *warm, float *cost_sum, hipStream_t s)
 {
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_refine_accept, dim3((n + 63) / 64), dim3(64), 0, s, n, K, C_max, env, cost_cur, cost_try,
-                       xi, xi_try, rho, flag, end_state, end_warm, state, params, warm, cost_sum);
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_refine_accept, dim3((count + 63) / 64), dim3(64), 0, s, n, i0, count, K, C_max, env,
+                       cost_cur, cost_try, xi, xi_try, rho, flag, end_state, end_warm, state, params, warm, cost_sum);
     return hipGetLastError();
 }
 

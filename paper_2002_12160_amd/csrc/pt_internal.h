@@ -128,12 +128,12 @@ hipError_t launch_select_elites(int G, int max_group, float elite_frac, const in
 hipError_t launch_refine_gather(int n, int K, int C_max, const int32_t *env, const float *state, const float *params,
                                 const float *warm, const float *cost_sum, float *xi, float *warm0, float *cost,
                                 float *rho, float rho0, hipStream_t s);
-hipError_t launch_refine_propose(int n, const pt::RefineArgs &A, const float *xi, const float *grad, const float *rho,
-                                 float *xi_try, hipStream_t s);
-hipError_t launch_refine_accept(int n, int K, int C_max, const int32_t *env, float *cost_cur, const float *cost_try,
-                                float *xi, const float *xi_try, float *rho, int32_t *flag, const float *end_state,
-                                const float *end_warm, float *state, float *params, float *warm, float *cost_sum,
-                                hipStream_t s);
+hipError_t launch_refine_propose(int n, int i0, int count, const pt::RefineArgs &A, const float *xi,
+                                 const float *grad, const float *rho, float *xi_try, hipStream_t s);
+hipError_t launch_refine_accept(int n, int i0, int count, int K, int C_max, const int32_t *env, float *cost_cur,
+                                const float *cost_try, float *xi, const float *xi_try, float *rho, int32_t *flag,
+                                const float *end_state, const float *end_warm, float *state, float *params,
+                                float *warm, float *cost_sum, hipStream_t s);
 hipError_t launch_weighted_resample(const pt::Consts &P, const pt::ResampleArgs &R, int kind, float hyper,
                                     const int32_t *group_start, int max_group, int n_steps, uint32_t window_idx,
                                     float *cost_sum, float *state, float *params, float *warm, float *snap,

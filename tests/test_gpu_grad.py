@@ -447,6 +447,41 @@ def test_refine_from_window_checkpoints_is_identical(pt):
         assert torch.equal(x, y)
 
 
+def test_refine_on_another_stream_is_identical(pt):
+    # the refinement forks its parts onto the batch's own streams and joins
+    # them back to the caller's stream: the same bits whichever stream calls,
+    # readable on that stream right after the call
+    _say("elite refinement on the default stream and on a side stream, bitwise")
+    T = 10
+    K = 96
+    cfg = S.CONFIGS["adjoint1024"].with_(T=T)
+    sc = S.make_scene(cfg, K=K, steps=2 * T)
+    outs = []
+    for side in (False, True):
+        b = pt.Batch.from_scene(sc, window_checkpoints=True)
+        h = pt.Batch.from_scene(sc, hidden=True)
+        assert b.elite_count() >= 3
+        gtw = torch.zeros((T, 4, sc.L, sc.G), device="cuda")
+        cost = torch.zeros(K, device="cuda")
+        best = torch.zeros(sc.G, dtype=torch.int32, device="cuda")
+        u_t = torch.as_tensor(np.array([sc.u[0]] + [sc.u[t] for t in range(T)], dtype=np.float32), device="cuda")
+        h.run_window(u_t, torch.zeros_like(gtw), torch.zeros(sc.G, device="cuda"), None, gtw, graph=False)
+        snap = b.snapshot()
+        b.run_window(u_t, gtw, cost, None, None, graph=False)
+        s = torch.cuda.Stream() if side else torch.cuda.current_stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            b.refine_elites(u_t, gtw, cost, snap, steps=3, step=0.5, best=best)
+            # read on the calling stream, before any synchronisation
+            got = [x.view(torch.int32).clone() for x in (b.state, b.params, b.warm, cost, best)]
+        torch.cuda.synchronize()
+        outs.append(got)
+        b.close()
+        h.close()
+    for x, y in zip(*outs):
+        assert torch.equal(x, y)
+
+
 def test_window_grad_resting_sphere_analytic(pt):
     # One step of a sphere at rest on a horizontal sensor link, penetrating it
     # by `pen`: the single contact is closed, u_n = 0, so
