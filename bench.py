@@ -369,11 +369,13 @@ def plain_run(pt, setup, dev, solve_precision, steps, warmup):
             "contacts_per_env_step": round(d_con / max(d_env, 1), 2)}
 
 
-def pd_run(pt, S, dev, cfg, steps, warmup):
-    """The PD-controlled hand on the plain per-step path: the observed
-    simulations' forces and joint angles first (resident in HBM), then step,
+def pd_run(pt, S, dev, cfg, steps, warmup, batched=False):
+    """The PD-controlled hand: the observed simulations' forces and joint
+    angles first (resident in HBM), then on the plain per-step path step,
     observe, cost with the argmin and the resampler every T steps, timed as
-    plain_run."""
+    plain_run; or (batched) one window call per T steps (the window kernel
+    replayed from its graph, with the argmin) and the resampler, timed per
+    window."""
     import numpy as np
     import torch
     cfg = cfg.with_(consts=dataclasses.replace(cfg.consts, hand_mode=1))
@@ -393,7 +395,14 @@ def pd_run(pt, S, dev, cfg, steps, warmup):
     best = torch.zeros(G, dtype=torch.int32, device=dev)
     parent = torch.zeros(K, dtype=torch.int32, device=dev)
     obs = b.new_obs()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    if batched:
+        assert steps % T == 0 and warmup % T == 0
+        u_win = torch.empty((T + 1, D), device=dev)
+        gt_win = torch.empty((T,) + h.obs_shape(G), device=dev)
+        n_ev = steps // T
+    else:
+        n_ev = steps
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n_ev)]
 
     def one(t, i=None):
         if i is not None:
@@ -406,18 +415,37 @@ def pd_run(pt, S, dev, cfg, steps, warmup):
         if (t + 1) % T == 0:
             b.resample(cost, (t + 1) // T - 1, parent)
 
-    for t in range(warmup):
-        one(t)
+    def window(w, i=None):
+        t0_ = w * T
+        u_win.copy_(u_all[t0_ - 1: t0_ + T] if t0_ > 0 else torch.cat([u_all[:1], u_all[:T]], 0))
+        gt_win.copy_(gts[t0_: t0_ + T])
+        if i is not None:
+            ev[i][0].record()
+        b.run_window(u_win, gt_win, cost, best, None, graph=True)
+        if i is not None:
+            ev[i][1].record()
+        b.resample(cost, w, parent)
+
+    if batched:
+        for w in range(warmup // T):
+            window(w)
+    else:
+        for t in range(warmup):
+            one(t)
     torch.cuda.synchronize()
     stats0 = b.read_stats()
     t0 = time.perf_counter()
-    for i in range(steps):
-        one(warmup + i, i)
+    if batched:
+        for i in range(n_ev):
+            window(warmup // T + i, i)
+    else:
+        for i in range(steps):
+            one(warmup + i, i)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     stats1 = b.read_stats()
     b.close()
-    step_ms = np.array([a.elapsed_time(c) for a, c in ev])
+    step_ms = np.array([a.elapsed_time(c) for a, c in ev]) / (T if batched else 1)
     d_env = stats1["env_steps"] - stats0["env_steps"]
     d_con = stats1["contacts"] - stats0["contacts"]
     return {"value": K * steps / wall, "unit": "env-steps/s", "steps": steps,
@@ -695,12 +723,16 @@ def main():
         pd = {}
         for name in ("realtime16384", "small"):
             wcfg = S.CONFIGS[name]
+            keys = ("value", "unit", "steps", "ms_per_step", "per_step_ms", "contacts_per_env_step", "runs")
             r = repeat(lambda: pd_run(pt, S, dev, wcfg, min(n_win * T, 300), n_warm * T), runs)
-            pd[name] = rounded({k: r[k] for k in ("value", "unit", "steps", "ms_per_step", "per_step_ms",
-                                                  "contacts_per_env_step", "runs") if k in r})
-        pd["path"] = ("plain per-step path of the PD-controlled hand: step (hand kinematics, mass matrix and the "
-                      "(6 + D) contact solve per simulation), observe (forces and joint angles), cost with the "
-                      "joint term, PBO resampling every window")
+            pd[name] = rounded({k: r[k] for k in keys if k in r})
+            r = repeat(lambda: pd_run(pt, S, dev, wcfg, min(n_win * T, 300), n_warm * T, batched=True), runs)
+            pd[name + "_batched"] = rounded({k: r[k] for k in keys if k in r})
+            pd[name + "_batched_vs_plain"] = round(pd[name + "_batched"]["value"] / pd[name]["value"], 3)
+        pd["path"] = ("the PD-controlled hand: plain per-step path (step: hand kinematics, mass matrix and the "
+                      "(6 + D) contact solve per simulation; observe: forces and joint angles; cost with the "
+                      "joint term) and batched windows (the T steps of a simulation, its observations and costs in "
+                      "one wavefront, replayed from a HIP graph), PBO resampling every window")
         result["pd_hand"] = pd
         print("bench: PD hand done", file=sys.stderr, flush=True)
         # links against the objects' signed distance fields (32^3 grids, 8 samples per link)

@@ -163,8 +163,10 @@ typedef struct {
        a finger) of at most 6; solve_precision 64; cost_mode 0.  With 1,
        pt_step reads u (the PD targets) and ignores u_prev; pt_observe,
        pt_cost and pt_resample (which copies hand_state with the rest of a
-       simulation) take the layouts above; the windowed, gradient,
-       refinement and weighted-resampling calls return PT_E_UNSUPPORTED. */
+       simulation) take the layouts above, and so do pt_run_window and
+       pt_run_window_static (one wavefront per simulation's window);
+       window_checkpoints, pt_autotune, the gradient, refinement and
+       weighted-resampling calls return PT_E_UNSUPPORTED. */
     int32_t hand_mode;
     float kp;             /* joint stiffness [N m / rad], >= 0                */
     float kd;             /* joint damping [N m s / rad], >= 0; kp + kd > 0  */
@@ -282,7 +284,16 @@ PT_API pt_status pt_resample_reps(pt_batch b, float *cost_sum, int32_t n_steps, 
  *   cost_sum   [K]        accumulated (not reset)
  *   best       [G]        argmin of cost_sum after the window (may be NULL)
  *   obs_out    [T][4][L][K] or NULL
- * Equivalent to T rounds of pt_step/pt_observe/pt_cost. */
+ * Equivalent to T rounds of pt_step/pt_observe/pt_cost.
+ * With the PD hand (hand_mode 1) the kinematics depend on each simulation's
+ * joint angles: up to one simulation per SIMD (K <= 4 x compute units) one
+ * wavefront runs each simulation's whole window; beyond, the call enqueues
+ * the per-step kernels of the T steps (which fit two wavefronts per SIMD),
+ * staging contacts and observations in buffers the batch allocated at
+ * creation.  The rows are those of pt_observe and pt_cost for that hand,
+ * obs_gt_win [T][4L + D][G] and obs_out [T][4L + D][K]; the joint state
+ * advances in hand_state; the results are those of T rounds of
+ * pt_step/pt_observe/pt_cost bit for bit either way. */
 PT_API pt_status pt_run_window(pt_batch b, const float *u_win, const float *obs_gt_win, float *cost_sum,
                         int32_t *best, float *obs_out, int32_t graph, pt_stream s);
 
@@ -298,8 +309,9 @@ PT_API pt_status pt_run_window(pt_batch b, const float *u_win, const float *obs_
  * call on a GPU shares that GPU's array: calls that overlap on one GPU (on
  * different streams, or from different host threads) race and must not be
  * issued; calls in one stream are ordered and safe.  The counters are
- * cleared by a kernel at the start of every call.  Arguments, layouts and
- * errors as pt_run_window. */
+ * cleared by a kernel at the start of every call (the PD hand's window
+ * uses none of the array, only the batch's own buffers).  Arguments, layouts
+ * and errors as pt_run_window. */
 PT_API pt_status pt_run_window_static(pt_batch b, const float *u_win, const float *obs_gt_win, float *cost_sum,
                                       int32_t *best, float *obs_out, pt_stream s);
 
@@ -309,7 +321,8 @@ PT_API pt_status pt_run_window_static(pt_batch b, const float *u_win, const floa
  * narrower one is at least 2% faster (fuller workgroups leave compute units
  * free for work on other streams).  The batch's own buffers are not
  * modified.  Synchronises the stream.  result (host, may be NULL) receives
- * the chosen value. */
+ * the chosen value.  PT_E_UNSUPPORTED with the PD hand (its window has one
+ * simulation per wavefront, nothing to choose). */
 PT_API pt_status pt_autotune(pt_batch b, const float *u_win, const float *obs_gt_win, int32_t *result, pt_stream s);
 
 /* Sets the persistent kernel's environments per workgroup (1, 2, 4 or 8)

@@ -120,6 +120,7 @@ struct pt_batch_s {
     pt::PdConsts Q = {};
     int32_t *d_pd = nullptr;     // the hand's structure table (pt::PdTab)
     int32_t *d_parent = nullptr; // [K] parents of a resampling, for the joint state's copies
+    float *d_pd_obs = nullptr;   // [4L + D][K] a step's observation inside a window of per-step kernels
     float *hstate = nullptr;     // caller-owned [2D][K]
     // the objects' distance fields (collision_mode 1)
     float *d_sdf = nullptr, *d_sdf_box = nullptr;
@@ -200,6 +201,8 @@ pt_status validate(const pt_batch_desc *d)
         if (!(d->link_mass > 0.f) || !std::isfinite(d->link_mass)) return fail(PT_E_ARG, "link_mass must be positive and finite");
         if (!(d->w_q >= 0.f) || !std::isfinite(d->w_q)) return fail(PT_E_ARG, "w_q must be finite and >= 0");
         if (d->D > 0 && !d->hand_state) return fail(PT_E_ARG, "hand_state is NULL");
+        if (d->window_checkpoints)
+            return fail(PT_E_UNSUPPORTED, "the PD hand has no window gradient, so no window checkpoints");
     }
     if (d->collision_mode != 0 && d->collision_mode != 1)
         return fail(PT_E_ARG, "collision_mode must be 0 or 1 (got %d)", d->collision_mode);
@@ -499,6 +502,7 @@ pt_status pt_create_batch(const pt_batch_desc *d, pt_batch *out)
     if (d->hand_mode == 1) {
         HIP_TRY_C(hipMalloc(&b->d_pd, sizeof(int32_t) * pd_tab.size()));
         HIP_TRY_C(hipMalloc(&b->d_parent, sizeof(int32_t) * K));
+        HIP_TRY_C(hipMalloc(&b->d_pd_obs, sizeof(float) * (4 * (size_t)d->L + d->D) * K));
         HIP_TRY_C(hipMemcpy(b->d_pd, pd_tab.data(), sizeof(int32_t) * pd_tab.size(), hipMemcpyHostToDevice));
     }
     if (d->cost_mode == 1) {
@@ -549,7 +553,7 @@ pt_status pt_destroy_batch(pt_batch b)
     void *ptrs[] = {b->d_hand, b->d_spheres, b->d_inv, b->d_nsph, b->d_type, b->d_group_of, b->d_group_start,
                     b->d_order, b->d_queue, b->d_stats, b->d_seg_win, b->d_contacts,
                     b->d_seg_grad, b->d_tune, b->d_ckpt, b->d_wckpt, b->d_elite, b->d_ref, b->d_snap,
-                    b->d_cslip, b->d_seg, b->d_pd, b->d_parent, b->d_sdf, b->d_sdf_box};
+                    b->d_cslip, b->d_seg, b->d_pd, b->d_parent, b->d_pd_obs, b->d_sdf, b->d_sdf_box};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete b;
@@ -664,6 +668,29 @@ static pt_status enqueue_window(pt_batch b, const float *u_win, const float *obs
                                 float *ckpt, hipStream_t st, float *seg_win = nullptr, int32_t *queue = nullptr)
 {
     const Consts &P = b->P;
+    if (b->hand_mode == 1) {
+        // the PD hand (its kinematics depend on each simulation's joint
+        // angles): up to one simulation per SIMD, one wavefront runs each
+        // simulation's whole window; beyond, where occupancy counts, the
+        // per-step kernels run it step by step (the window kernel holds one
+        // wavefront per SIMD, the step kernel two), the same bits either way
+        const Tables tb = tables_of(b);
+        if (P.K <= 4 * b->num_cu) {
+            HIP_TRY(launch_window_pd(P, b->Q, tb, b->d_pd, u_win, state, params, warm, b->hstate, obs_gt_win,
+                                     cost_sum, obs_out, b->d_stats, st));
+        } else {
+            const size_t RG = (4 * (size_t)P.L + P.D) * P.G, RK = (4 * (size_t)P.L + P.D) * P.K;
+            for (int t = 0; t < P.T; ++t) {
+                float *obs = obs_out ? obs_out + (size_t)t * RK : b->d_pd_obs;
+                HIP_TRY(launch_step_pd(P, b->Q, tb, b->d_pd, u_win + (size_t)(t + 1) * P.D, state, params, warm,
+                                       b->hstate, b->d_contacts, b->d_stats, st));
+                HIP_TRY(launch_observe_pd(P, b->d_contacts, b->hstate, obs, st));
+                HIP_TRY(launch_cost_pd(P, b->Q, b->d_group_of, obs, obs_gt_win + (size_t)t * RG, cost_sum, st));
+            }
+        }
+        if (best) HIP_TRY(launch_argmin(P.G, b->d_group_start, cost_sum, best, st));
+        return PT_OK;
+    }
     if (!seg_win) seg_win = b->d_seg_win;
     if (!queue) queue = b->d_queue;
     int bpc = 0;
@@ -686,7 +713,6 @@ pt_status pt_run_window(pt_batch b, const float *u_win, const float *obs_gt_win,
                         float *obs_out, int32_t graph, pt_stream s)
 {
     if (!b) return fail(PT_E_ARG, "batch is NULL");
-    if (b->hand_mode == 1) return fail(PT_E_UNSUPPORTED, "the windowed path is not built for the PD hand");
     if (!u_win || !obs_gt_win || !cost_sum) return fail(PT_E_ARG, "u_win/obs_gt_win/cost_sum is NULL");
     hipStream_t st = (hipStream_t)s;
     if (!graph)
@@ -739,7 +765,6 @@ pt_status pt_run_window_static(pt_batch b, const float *u_win, const float *obs_
                                int32_t *best, float *obs_out, pt_stream s)
 {
     if (!b) return fail(PT_E_ARG, "batch is NULL");
-    if (b->hand_mode == 1) return fail(PT_E_UNSUPPORTED, "the windowed path is not built for the PD hand");
     if (!u_win || !obs_gt_win || !cost_sum) return fail(PT_E_ARG, "u_win/obs_gt_win/cost_sum is NULL");
     const Consts &P = b->P;
     if ((size_t)P.T * P.L > STATIC_SEG_RECORDS)
@@ -760,7 +785,8 @@ pt_status pt_run_window_static(pt_batch b, const float *u_win, const float *obs_
 pt_status pt_autotune(pt_batch b, const float *u_win, const float *obs_gt_win, int32_t *result, pt_stream s)
 {
     if (!b) return fail(PT_E_ARG, "batch is NULL");
-    if (b->hand_mode == 1) return fail(PT_E_UNSUPPORTED, "the windowed path is not built for the PD hand");
+    if (b->hand_mode == 1)
+        return fail(PT_E_UNSUPPORTED, "the PD hand's window runs one simulation per wavefront: nothing to tune");
     if (!u_win || !obs_gt_win) return fail(PT_E_ARG, "u_win/obs_gt_win is NULL");
     hipStream_t st = (hipStream_t)s;
     const Consts &P = b->P;

@@ -148,6 +148,9 @@ hipError_t set_pd_lds_limits(size_t bytes);
 hipError_t launch_step_pd(const pt::Consts &P, const pt::PdConsts &Q, const pt::Tables &tb, const int32_t *pd_tab,
                           const float *u, float *state, float *params, float *warm, float *hstate, float *contacts,
                           int64_t *stats, hipStream_t s);
+hipError_t launch_window_pd(const pt::Consts &P, const pt::PdConsts &Q, const pt::Tables &tb, const int32_t *pd_tab,
+                            const float *u_win, float *state, float *params, float *warm, float *hstate,
+                            const float *obs_gt_win, float *cost_sum, float *obs_out, int64_t *stats, hipStream_t s);
 hipError_t launch_observe_pd(const pt::Consts &P, const float *contacts, const float *hstate, float *obs,
                              hipStream_t s);
 hipError_t launch_cost_pd(const pt::Consts &P, const pt::PdConsts &Q, const int32_t *group_of, const float *obs,

@@ -99,10 +99,18 @@ struct PdLds {
     int *linkrow;   // [64] first row of each link's run of rows (-1: no contact on the link)
 };
 
+// Up to PD_SPARE_D joints the group solve's X and Y live in the wave's cap
+// slots, warm-cache lookup and contact stage (sel .. the stage's end, 576
+// words), which nothing reads between the warm start and the integration:
+// on the real-time hand (D = 20) that keeps the wave under 32 KiB, five
+// wavefronts per compute unit instead of four.
+constexpr int PD_SPARE_WORDS = 9 * 64;
+constexpr int PD_SPARE_D = 4 * PD_SPARE_WORDS / (8 * (PD_GMAX + PD_YS));
+
 __host__ __device__ constexpr size_t pd_lds_bytes(int D)
 {
-    return (size_t)8 * ((size_t)D * (6 + PD_GMAX + 1 + 6 + 6 + 1 + PD_GMAX + PD_YS + 1 + 1) + 96) +
-           (size_t)4 * (64 + 64);
+    return (size_t)8 * ((size_t)D * (6 + PD_GMAX + 1 + 6 + 6 + 1 + 1 + 1) + 96) +
+           (D <= PD_SPARE_D ? 0 : (size_t)8 * D * (PD_GMAX + PD_YS)) + (size_t)4 * (64 + 64);
 }
 
 // LDS of the hand kinematics (in the candidate list, before the narrow
@@ -110,7 +118,8 @@ __host__ __device__ constexpr size_t pd_lds_bytes(int D)
 // and the world inertia
 __host__ __device__ constexpr size_t pd_fk_bytes(int L) { return (size_t)8 * 19 * L; }
 
-__device__ __forceinline__ PdLds carve_pd(char *p, int D)
+// p: the PD area after the wave's WaveLds; spare: that WaveLds's sel
+__device__ __forceinline__ PdLds carve_pd(char *p, int D, int *spare)
 {
     PdLds s;
     double *d = reinterpret_cast<double *>(p);
@@ -120,8 +129,13 @@ __device__ __forceinline__ PdLds carve_pd(char *p, int D)
     s.Aoh = d; d += 6 * D;
     s.Aho = d; d += 6 * D;
     s.bh = d; d += D;
-    s.X = d; d += PD_GMAX * D;
-    s.Y = d; d += PD_YS * D;
+    if (D <= PD_SPARE_D) {
+        s.X = reinterpret_cast<double *>(spare);
+        s.Y = s.X + PD_GMAX * D;
+    } else {
+        s.X = d; d += PD_GMAX * D;
+        s.Y = d; d += PD_YS * D;
+    }
     s.zh = d; d += D;
     s.nuh = d; d += D;
     s.tot = d; d += 48;
@@ -655,6 +669,53 @@ __device__ __forceinline__ void step_solve_pd(const Consts &P, const PdConsts &Q
     st.nu[0] += st.vs[0]; st.nu[1] += st.vs[1]; st.nu[2] += st.vs[2];
     st.nu[3] += st.ws[0]; st.nu[4] += st.ws[1]; st.nu[5] += st.ws[2];
     pd_hand_rates<G>(P, Q, T, st, pos, ends, red, pl);
+}
+
+// The joint state of a step staged by position (lane p: the joint at
+// position p), twist rows cleared (a joint that moves no link keeps zeros).
+__device__ __forceinline__ void pd_stage_joints(int D, const PdLds &pl, float q, float qd)
+{
+    const int lane = lane_id();
+    if (lane < D) {
+        pl.zh[lane] = q;
+        pl.nuh[lane] = qd;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) pl.S[6 * lane + k] = 0.0;
+    }
+    wave_sync();
+}
+
+// One step of one simulation with the PD hand, the joint state staged by
+// pd_stage_joints (q_lane: this lane's joint angle): kinematics and mass
+// matrix at the joint angles, narrow phase and cap, the (6 + D) contact
+// solve and the object's integration.  The joint rates leave in pl.nuh;
+// link and imp are this lane's kept contact (as step_finish gives them).
+template <bool SDF, int G>
+__device__ __forceinline__ void pd_step(const Consts &P, const PdConsts &Q, const Tables &tb, const PdTab &T,
+                                        const float *__restrict__ u, const WaveLds &lds, const PdLds &pl,
+                                        const float *__restrict__ sph, int S, const float *inv, const SdfRef &sdf,
+                                        float q_lane, Body &B, int &wkey, float *wr, StepStats &stats, int &link,
+                                        float *imp)
+{
+    double *fk = reinterpret_cast<double *>(lds.cand_d);
+    pd_fk(P, Q, T, tb.hand, fk, pl, lds.seg);
+    pd_mass(P, Q, T, fk, pl, u, (double)q_lane);
+    pd_twists(P.D, B.x, pl);
+    StepState<double> sst;
+    step_setup<double, SDF>(P, lds.seg, sph, S, inv, B, wkey, wr, lds, stats, sst, sdf);
+    int pos;
+    uint64_t ends;
+    pd_order_contacts(sst, pl, pos, ends);
+    step_solve_pd<G>(P, Q, T, sst, B.mu, inv, reinterpret_cast<double *>(lds.cand_d), pl, pos, ends);
+    step_finish<double>(P, sst, inv, B, wkey, wr, link, imp);
+}
+
+// The joint-angle term of the step cost (Eq. 3's w_1 term), added to the
+// running sum cs: w_q (q - q_gt)^2.
+__device__ __forceinline__ float pd_joint_cost(float cs, float w_q, float q, float q_gt)
+{
+    const float d = q - q_gt;
+    return cs + w_q * d * d;
 }
 
 }  // namespace pt

@@ -357,7 +357,7 @@ class Batch:
 
     def _need_window(self, u_win, obs_gt_win):
         self._need_cmd(u_win, (self.T + 1, self.D), "u_win")
-        self._need(obs_gt_win, (self.T, self.obs_rows, self.L, self.G), "obs_gt_win")
+        self._need(obs_gt_win, (self.T, *self.obs_shape(self.G)), "obs_gt_win")
 
     # -- the hot path ------------------------------------------------------
     def obs_shape(self, n):
@@ -368,7 +368,7 @@ class Batch:
         return (self.obs_rows, self.L, n)
 
     def new_obs(self, T=None):
-        shape = self.obs_shape(self.K) if T is None else (T, self.obs_rows, self.L, self.K)
+        shape = self.obs_shape(self.K) if T is None else (T, *self.obs_shape(self.K))
         return torch.zeros(shape, dtype=torch.float32, device=self.device)
 
     def step(self, u_prev, u, stream=None):
@@ -413,7 +413,7 @@ class Batch:
         self._need_window(u_win, obs_gt_win)
         self._need(cost_sum, (self.K,), "cost_sum")
         self._need(best, (self.G,), "best", torch.int32)
-        self._need(obs_out, (self.T, self.obs_rows, self.L, self.K), "obs_out")
+        self._need(obs_out, (self.T, *self.obs_shape(self.K)), "obs_out")
         pt_run_window(self.handle, u_win, obs_gt_win, cost_sum, best, obs_out, graph, stream)
 
     def run_window_static(self, u_win, obs_gt_win, cost_sum, best=None, obs_out=None, stream=None):
@@ -422,7 +422,7 @@ class Batch:
         self._need_window(u_win, obs_gt_win)
         self._need(cost_sum, (self.K,), "cost_sum")
         self._need(best, (self.G,), "best", torch.int32)
-        self._need(obs_out, (self.T, self.obs_rows, self.L, self.K), "obs_out")
+        self._need(obs_out, (self.T, *self.obs_shape(self.K)), "obs_out")
         pt_run_window_static(self.handle, u_win, obs_gt_win, cost_sum, best, obs_out, stream)
 
     def autotune(self, u_win, obs_gt_win, stream=None):

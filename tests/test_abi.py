@@ -146,7 +146,7 @@ def test_binding_checks_buffer_shapes_before_the_call():
 
     b = pt.Batch.__new__(pt.Batch)
     b.device = torch.device("cpu")
-    b.K, b.G, b.L, b.D, b.T, b.C_max, b.obs_rows = 8, 2, 3, 4, 10, 16, 4
+    b.K, b.G, b.L, b.D, b.T, b.C_max, b.obs_rows, b.hand_mode = 8, 2, 3, 4, 10, 16, 4, 0
     ok_u = torch.zeros((11, 4))
     ok_gt = torch.zeros((10, 4, 3, 2))
     b._need_window(ok_u, ok_gt)
@@ -161,6 +161,11 @@ def test_binding_checks_buffer_shapes_before_the_call():
     with pytest.raises(pt.PtError):
         b._need(np.zeros(8, np.float32), (8,), "cost_sum")
     b._need(None, (8,), "optional")
+    # the PD hand's window rows: 4 L force rows, then the D joint angles
+    b.hand_mode = 1
+    b._need_window(ok_u, torch.zeros((10, 4 * 3 + 4, 2)))
+    with pytest.raises(pt.PtError):
+        b._need_window(ok_u, ok_gt)
 
 
 def _pd_desc(pt, keep):
@@ -188,7 +193,7 @@ def test_pd_hand_descriptor_passes_validation(lib):
 
 @pytest.mark.parametrize("field,value,code", [
     ("hand_mode", 2, 1), ("kp", -1.0, 1), ("kd", float("nan"), 1), ("link_mass", 0.0, 1), ("w_q", -1.0, 1),
-    ("solve_precision", 32, 5), ("cost_mode", 1, 5), ("hand_state", None, 1),
+    ("solve_precision", 32, 5), ("cost_mode", 1, 5), ("hand_state", None, 1), ("window_checkpoints", 1, 5),
 ])
 def test_pd_hand_descriptor_validation(lib, field, value, code):
     pt = _desc_module()

@@ -222,15 +222,86 @@ def test_pd_resample_copies_the_joint_state(pt):
     assert (par >= 0).sum() == 64 - 16
 
 
+def _pd_windows(pt, cfg, K, n_win, batched, graph=False, static=False, seed=3):
+    """n_win windows of T steps, each followed by a resampling, on the plain
+    path (T rounds of step/observe/cost) or the batched window; returns every
+    output's raw bits after each window."""
+    T = cfg.T
+    sc = _scene(cfg.with_(T=10 ** 6), K, n_win * T + 1)
+    o = oracle.Oracle.from_scene(sc)
+    rng = np.random.default_rng(seed)
+    hq = o.new_hand(K, sc.u[0]) + rng.normal(scale=0.02, size=(K, 2 * o.D))
+    b = pt.Batch.from_scene(sc, T=T, hand_state=hq)
+    G = b.G
+    u_all = _u(sc.u)
+    # observed rows: the plain path's own observation of a perturbed copy
+    gts = torch.as_tensor(rng.normal(scale=0.3, size=(n_win * T, *b.obs_shape(G))).astype(np.float32),
+                          device="cuda").abs().contiguous()
+    cost = torch.zeros(K, device="cuda")
+    best = torch.zeros(G, dtype=torch.int32, device="cuda")
+    parent = torch.zeros(K, dtype=torch.int32, device="cuda")
+    obs_win = b.new_obs(T)
+    obs = b.new_obs()
+    out = []
+    for w in range(n_win):
+        t0 = w * T
+        gt_win = gts[t0:t0 + T].contiguous()
+        if batched:
+            u_win = u_all[max(t0 - 1, 0):t0 + T].contiguous() if t0 > 0 else torch.cat([u_all[:1], u_all[:T]], 0)
+            if static:
+                b.run_window_static(u_win.contiguous(), gt_win, cost, best, obs_win)
+            else:
+                b.run_window(u_win.contiguous(), gt_win, cost, best, obs_win, graph=graph)
+        else:
+            for t in range(T):
+                b.step(None, u_all[t0 + t].contiguous())
+                b.observe(obs)
+                obs_win[t].copy_(obs)
+                b.cost(obs, gt_win[t], cost, best if t == T - 1 else None)
+        rec = [x.view(torch.int32).clone() for x in (b.state, b.params, b.warm, b.hand_state, cost, best, obs_win)]
+        b.resample(cost, w, parent)
+        rec.append(parent.clone())
+        out.append(rec)
+    torch.cuda.synchronize()
+    b.close()
+    return out
+
+
+@pytest.mark.parametrize("cfg_name,K,abduction,sdf", [("small", 37, False, False), ("plain256", 40, False, False),
+                                                       ("realtime16384", 48, True, False), ("small", 37, False, True),
+                                                       ("small", 1100, False, False)])
+def test_pd_window_equals_plain_bitwise(pt, cfg_name, K, abduction, sdf):
+    # groups of 3 and 4 joints (the small elimination), of 5 (the large one),
+    # and the distance-field collision; the window kernel against T rounds
+    # of the per-step kernels, with and without the graph, and the
+    # allocation-free entry point; two windows with a resampling between.
+    # Past one simulation per SIMD (1100 > 4 x 256 compute units) the window
+    # runs as per-step kernels inside the call: offsets of commands, rows and
+    # observations
+    cfg = _pd_cfg(cfg_name, collision_mode=1 if sdf else 0)
+    if abduction:
+        cfg = cfg.with_(hand=dataclasses.replace(cfg.hand, abduction=True))
+    _say(f"PD window vs plain path: {cfg_name} K={K} abduction={abduction} distance field={sdf}")
+    ref = _pd_windows(pt, cfg, K, 2, batched=False)
+    for kw in ({"graph": False}, {"graph": True}, {"static": True}):
+        got = _pd_windows(pt, cfg, K, 2, batched=True, **kw)
+        names = ("state", "params", "warm", "hand_state", "cost", "best", "obs", "parent")
+        for w in range(2):
+            for n, x, y in zip(names, ref[w], got[w]):
+                assert torch.equal(x, y), f"{kw} window {w}: {n} differs"
+
+
 def test_pd_rejects_the_calls_it_does_not_support(pt):
     cfg = _pd_cfg("small")
     sc = _scene(cfg.with_(T=10 ** 6), 8, 12)
     o = oracle.Oracle.from_scene(sc)
     b = pt.Batch.from_scene(sc, T=10, hand_state=o.new_hand(8, sc.u[0]))
     u_win = _u(sc.u[:11])
-    gt = torch.zeros((10, 4, b.L, 1), device="cuda")
+    gt = torch.zeros((10, *b.obs_shape(1)), device="cuda")
     cost = torch.zeros(8, device="cuda")
-    for call in (lambda: b.run_window(u_win, gt, cost), lambda: b.run_window_static(u_win, gt, cost),
+    env = torch.arange(8, dtype=torch.int32, device="cuda")
+    for call in (lambda: b.autotune(u_win, gt),
+                 lambda: b.window_grad(u_win, gt, env, *b.start_of(env)),
                  lambda: b.resample_wrs(cost, 10, 0, 1.0, torch.zeros(8, dtype=torch.int32, device="cuda"))):
         with pytest.raises(pt.PtError) as ei:
             call()
