@@ -403,17 +403,30 @@ pt_status pt_create_batch(const pt_batch_desc *d, pt_batch *out)
     // ... and the step's hand kinematics, which use the same LDS first
     const size_t fk_bytes = d->hand_mode == 1 ? pt::pd_fk_bytes(d->L) : hand_fk_lds_bytes(d->L, d->D);
     const int n_pairs = d->collision_mode == 1 ? d->L * d->link_samples + d->S_max : d->S_max * (d->L + 1);
-    const int max_cand = std::max({round_up(std::min(n_pairs, pt::CAND_CAP) + 8, 64),
-                                   round_up(red_rows * pt::RedStride<double>::value, 64),
-                                   round_up((int)((fk_bytes + 7) / 8), 64)});
-    const size_t wave_lds = pt::wave_lds_bytes(max_cand, d->L) + (d->hand_mode == 1 ? pt::pd_lds_bytes(d->D) : 0);
+    const int list = std::min(n_pairs, pt::CAND_CAP) + 8, rows = red_rows * pt::RedStride<double>::value,
+              fk = (int)((fk_bytes + 7) / 8);
+    int max_cand, max_cand_rows;
+    if (d->hand_mode == 1) {
+        // the PD solve keeps its group solutions in the spare words
+        max_cand = std::max({round_up(list, 64), round_up(rows, 64), round_up(fk, 64)});
+        max_cand_rows = max_cand;
+    } else {
+        // the sum rows may run on into the spare words after the list
+        // (3 KB less per wavefront at the 64-contact cap: seven window
+        // wavefronts per compute unit instead of six); the reverse sweep,
+        // which stages its own data there, keeps them whole in the list
+        max_cand = std::max({round_up(list, 32), round_up(rows - pt::WAVE_SPARE_BYTES / 8, 32), round_up(fk, 32)});
+        max_cand_rows = std::max(max_cand, round_up(rows, 32));
+    }
+    const size_t wave_lds = std::max(pt::wave_lds_bytes(max_cand, d->L), pt::wave_lds_bytes(max_cand_rows, 0)) +
+                            (d->hand_mode == 1 ? pt::pd_lds_bytes(d->D) : 0);
     if (wave_lds > 160 * 1024)
         return fail(PT_E_UNSUPPORTED, "%zu B of LDS per simulation (> 160 KiB)", wave_lds);
 
     pt_batch b = new pt_batch_s();
     Consts &P = b->P;
     P.K = d->K; P.G = d->G; P.L = d->L; P.D = d->D; P.S_max = d->S_max; P.C_max = d->C_max;
-    P.newton_iters = d->newton_iters; P.T = d->T; P.max_cand = max_cand;
+    P.newton_iters = d->newton_iters; P.T = d->T; P.max_cand = max_cand; P.max_cand_rows = max_cand_rows;
     P.solve_fp64 = d->solve_precision == 32 ? 0 : 1;
     P.dt = d->dt; P.gx = d->gravity[0]; P.gy = d->gravity[1]; P.gz = d->gravity[2];
     P.margin = d->margin; P.erp = d->erp; P.compliance = d->compliance; P.kappa = d->kappa;
@@ -529,7 +542,8 @@ pt_status pt_create_batch(const pt_batch_desc *d, pt_batch *out)
     }
     // environments per workgroup within the LDS budget (autotuned later)
     b->wpb = 4;
-    while (b->wpb > 1 && ((size_t)b->wpb * wave_lds > 160 * 1024 || b->wpb > max_wpb(P))) b->wpb >>= 1;
+    const size_t win_lds = pt::wave_lds_bytes(max_cand, 0);
+    while (b->wpb > 1 && ((size_t)b->wpb * win_lds > 160 * 1024 || b->wpb > max_wpb(P))) b->wpb >>= 1;
     // the per-step launch: one simulation per workgroup, so that up to one
     // wavefront per compute unit has its LDS, caches and issue to itself
     // (measured faster than four per workgroup at 256 simulations)
@@ -796,7 +810,7 @@ pt_status pt_autotune(pt_batch b, const float *u_win, const float *obs_gt_win, i
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
-    const size_t wave_lds = pt::wave_lds_bytes(P.max_cand, P.L);
+    const size_t wave_lds = pt::wave_lds_bytes(P.max_cand, 0);
     int best_wpb = b->wpb;
     float best_ms = 1e30f;
     pt_status rc = PT_OK;
@@ -844,7 +858,7 @@ pt_status pt_set_tuning(pt_batch b, int32_t wpb)
 {
     if (!b) return fail(PT_E_ARG, "batch is NULL");
     if (wpb != 1 && wpb != 2 && wpb != 4 && wpb != 8) return fail(PT_E_ARG, "waves per workgroup must be 1, 2, 4 or 8");
-    if ((size_t)wpb * pt::wave_lds_bytes(b->P.max_cand, b->P.L) > 160 * 1024)
+    if ((size_t)wpb * pt::wave_lds_bytes(b->P.max_cand, 0) > 160 * 1024)
         return fail(PT_E_UNSUPPORTED, "%d simulations per workgroup exceed the LDS", wpb);
     if (wpb > max_wpb(b->P))
         return fail(PT_E_UNSUPPORTED, "at most %d simulations per workgroup with this solve precision", max_wpb(b->P));

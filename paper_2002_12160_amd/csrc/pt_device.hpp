@@ -23,6 +23,7 @@ constexpr int WARM_STRIDE = 4;  // key bits + r(3)
 // ---------------------------------------------------------------------
 struct Consts {
     int K, G, L, D, S_max, C_max, newton_iters, T, max_cand, solve_fp64;
+    int max_cand_rows;         // list entries that hold the solve's sum rows whole (the reverse sweep)
     float dt, gx, gy, gz, margin, erp, compliance, kappa, fb_delta, armijo_sigma;
     float tau_contact, w_mag, w_dir;
     int cost_mode;             // 0: force terms, obs rows 4; 1: Eq. 3, obs rows 7

@@ -56,7 +56,7 @@ __global__ __launch_bounds__(WAVE) void k_window_fwd(Consts P, Tables tb, const 
         if (lane == 0) cost_out[i] = __int_as_float(0x7fc00000);
         return;
     }
-    WaveLds lds = carve_lds(smem, 0, P.max_cand, P.L);
+    WaveLds lds = carve_lds(smem, 0, P.max_cand, 0);
     float *stage = contact_stage(lds);
     const int type = tb.env_type[e];
     const int g = tb.group_of[e];
@@ -139,7 +139,8 @@ __global__ __launch_bounds__(WAVE) void k_window_bwd(Consts P, Tables tb, const 
             for (int r = 0; r < XI_ROWS; ++r) grad[(size_t)r * n + i] = 0.f;
         return;
     }
-    WaveLds lds = carve_lds(smem, 0, P.max_cand, P.L);
+    // the sum rows whole in the list: the adjoint stages data in the words after it
+    WaveLds lds = carve_lds(smem, 0, P.max_cand_rows, 0);
     float *stage = contact_stage(lds);
     const int type = tb.env_type[e];
     const int g = tb.group_of[e];
@@ -308,7 +309,7 @@ hipError_t launch_window_fwd(const Consts &P, const Tables &tb, const float *seg
                              float *resid)
 {
     if (count <= 0) return hipSuccess;
-    size_t lds = wave_lds_bytes(P.max_cand, P.L);
+    size_t lds = wave_lds_bytes(P.max_cand, 0);
     // paired line-search trials when no step can hold more than 32 contacts
     auto go = [&](auto kern) {
         hipLaunchKernelGGL(kern, dim3(count), dim3(WAVE), lds, s, P, tb, seg_win, n, i0, count, env, xi, warm0,
@@ -325,7 +326,7 @@ hipError_t launch_window_bwd(const Consts &P, const Tables &tb, const float *seg
                              bool ckpt_by_env, const int32_t *flag, float *grad, hipStream_t s)
 {
     if (count <= 0) return hipSuccess;
-    size_t lds = wave_lds_bytes(P.max_cand, P.L);
+    size_t lds = wave_lds_bytes(P.max_cand_rows, 0);
     const int by_env = ckpt_by_env ? 1 : 0;
     if (P.solve_fp64)
         hipLaunchKernelGGL(k_window_bwd<double>, dim3(count), dim3(WAVE), lds, s, P, tb, seg_win, n, i0, count, env,

@@ -75,11 +75,17 @@ __host__ __device__ constexpr size_t resample_lds_bytes(int max_group)
 
 // bytes of LDS per wavefront: candidate (d, key) list, selected keys,
 // previous warm keys and impulses, contact staging for the observation, the
-// step's L hand segment records
+// step's L hand segment records (L = 0 for the window kernels, which read
+// them from HBM)
 __host__ __device__ constexpr size_t wave_lds_bytes(int max_cand, int L)
 {
     return (size_t)8 * max_cand + 4 * 64 + 4 * 64 + 12 * 64 + 16 * 64 + (size_t)64 * L;
 }
+
+// the selected keys, warm-cache lookup and contact stage after the
+// candidate list: nothing reads them between the warm start and the end of
+// a step's solve, so the solve's sum rows may run on into them
+constexpr int WAVE_SPARE_BYTES = 4 * 64 + 4 * 64 + 12 * 64 + 16 * 64;
 
 }  // namespace pt
 

@@ -534,7 +534,7 @@ k_window(Consts P, Tables tb, const float *__restrict__ seg_win, float *__restri
     extern __shared__ __align__(16) char smem[];
     const int wib = threadIdx.x / WAVE;
     const int lane = lane_id();
-    WaveLds lds = carve_lds(smem, wib, P.max_cand, P.L);
+    WaveLds lds = carve_lds(smem, wib, P.max_cand, 0);
     float *stage = contact_stage(lds);
     StepStats st = {0, 0, 0};
     int64_t done = 0;
@@ -744,7 +744,7 @@ hipError_t launch_window(const Consts &P, const Tables &tb, const float *seg_win
                          const int32_t *env_order, int32_t *queue, int64_t *stats, int waves_per_block, int blocks,
                          float *ckpt, const int32_t *group_start, int32_t *best, hipStream_t s)
 {
-    size_t lds = (size_t)waves_per_block * wave_lds_bytes(P.max_cand, P.L);
+    size_t lds = (size_t)waves_per_block * wave_lds_bytes(P.max_cand, 0);
     const dim3 grid(blocks), block(WAVE * waves_per_block);
     return with_window_kernel(P, [&](auto kern) {
         hipLaunchKernelGGL(kern, grid, block, lds, s, P, tb, seg_win, state, params, warm, obs_gt_win, cost_sum,
@@ -755,7 +755,7 @@ hipError_t launch_window(const Consts &P, const Tables &tb, const float *seg_win
 
 hipError_t window_occupancy(const Consts &P, int waves_per_block, int *blocks_per_cu)
 {
-    size_t lds = (size_t)waves_per_block * wave_lds_bytes(P.max_cand, P.L);
+    size_t lds = (size_t)waves_per_block * wave_lds_bytes(P.max_cand, 0);
     return with_window_kernel(P, [&](auto kern) {
         return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, reinterpret_cast<const void *>(kern),
                                                             WAVE * waves_per_block, lds);

@@ -589,6 +589,8 @@ __device__ __forceinline__ void step_setup(const Consts &P, const float *__restr
             st.r[0] = lds.wr[3 * hit]; st.r[1] = lds.wr[3 * hit + 1]; st.r[2] = lds.wr[3 * hit + 2];
         }
     }
+    // the solve's sum rows may run on over the cap slots and the lookup's words
+    wave_sync();
 }
 
 // Newton on the smoothed FB system.  The 3C x 3C Newton matrix
