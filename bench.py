@@ -79,9 +79,9 @@ MEASURED = {
     # traffic: (FETCH_SIZE x 1.9998 + WRITE_SIZE x 1.0000) KiB x 1024 per launch, the
     # factors from a 256 MiB device copy under the same counters; valu_*:
     # SQ_INSTS_VALU and SQ_ACTIVE_INST_VALU per launch, summed over the chip
-    "k_window_realtime16384": {"src": "5b9447a11fa66a68", "traffic": 399736396,
-                               "fetch": 29500956, "write": 370235440,
-                               "valu_insts": 2129995103, "valu_busy_quads": 2240072828},
+    "k_window_realtime16384": {"src": "23ba6e944c33dab1", "traffic": 399777680,
+                               "fetch": 29364313, "write": 370413366,
+                               "valu_insts": 2130233154, "valu_busy_quads": 2240311390},
 }
 SIMDS, CLOCK_HZ = 1024, 2.4e9     # MI355X: 256 CUs x 4 SIMDs at 2.4 GHz; a VALU instruction issues in 4 cycles
 PEAK_F64_TFLOPS = 78.6            # MI355X published float64 vector peak (= non-packed float32)

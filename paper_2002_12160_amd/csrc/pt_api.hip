@@ -936,19 +936,23 @@ pt_status pt_refine_elites(pt_batch b, const float *u_win, const float *obs_gt_w
         const bool from_window = b->d_wckpt != nullptr;
         HIP_TRY(launch_refine_gather(n, P.K, P.C_max, b->d_elite, start_state, start_params, start_warm,
                                      from_window ? cost_sum : nullptr, r.xi, r.warm0, r.cost, r.rho, step, st));
-        // every elite's chain of replays and sweeps is its own, so the elites
-        // go in parts on streams of their own: one part's short kernels and
-        // the tail of its replay overlap the others' replays (the same bits
-        // as one launch over all of them); each part has its own checkpoints
+        // every elite's chain of replays and sweeps is its own, so when the
+        // elites outnumber the wavefronts the GPU holds at once (two rounds
+        // of eight per compute unit) they go in parts on streams of their
+        // own: one part's short kernels and the tail of its replay overlap
+        // the others' replays (the same bits as one launch over all of
+        // them); each part has its own checkpoints.  Fewer elites all run at
+        // once in one launch, and parts would only add launches.
         constexpr int NP = pt_batch_s::REFINE_PARTS;
+        const int parts = n >= 16 * b->num_cu ? NP : 1;
         struct Part {
             int i0, count;
             hipStream_t s;
             float *ckpt;
         } part[NP];
         int np = 0;
-        for (int k = 0, i0 = 0; k < NP; ++k) {
-            const int cnt = (n - i0) / (NP - k) + ((n - i0) % (NP - k) != 0);
+        for (int k = 0, i0 = 0; k < parts; ++k) {
+            const int cnt = (n - i0) / (parts - k) + ((n - i0) % (parts - k) != 0);
             if (cnt <= 0) break;
             part[np++] = {i0, cnt, k == 0 ? st : b->side_stream[k - 1], b->d_ckpt + ckpt_floats(P, i0)};
             i0 += cnt;

@@ -447,13 +447,14 @@ def test_refine_from_window_checkpoints_is_identical(pt):
         assert torch.equal(x, y)
 
 
-def test_refine_on_another_stream_is_identical(pt):
-    # the refinement forks its parts onto the batch's own streams and joins
-    # them back to the caller's stream: the same bits whichever stream calls,
+@pytest.mark.parametrize("K", [96, 16384])
+def test_refine_on_another_stream_is_identical(pt, K):
+    # from 16 elites per compute unit on (4096 on 256 compute units) the
+    # refinement forks parts onto the batch's own streams and joins them
+    # back to the caller's stream: the same bits whichever stream calls,
     # readable on that stream right after the call
-    _say("elite refinement on the default stream and on a side stream, bitwise")
+    _say(f"elite refinement on the default stream and on a side stream, bitwise: K={K}")
     T = 10
-    K = 96
     cfg = S.CONFIGS["adjoint1024"].with_(T=T)
     sc = S.make_scene(cfg, K=K, steps=2 * T)
     outs = []
