@@ -83,7 +83,7 @@ __global__ __launch_bounds__(WAVE) void k_window_fwd(Consts P, Tables tb, const 
         const float *seg = seg_win + (size_t)t * P.L * SEG_STRIDE;
         StepState<SR> st;
         step_setup<SR>(P, seg, sph, S, inv, B, wkey, wr, lds, stt, st);
-        step_solve<SR, true, PT>(P, st, B.mu, inv, reinterpret_cast<SR *>(lds.cand_d));
+        step_solve<SR, PT>(P, st, B.mu, inv, reinterpret_cast<SR *>(lds.cand_d));
         resid = fmaxf(resid, (float)st.psi_end);
         if (ck) save_contact<SR>(ck, P.C_max, st);
         int link;

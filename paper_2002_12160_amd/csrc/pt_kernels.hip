@@ -284,7 +284,7 @@ __global__ __launch_bounds__(StepBounds<SR>::threads) void k_step(Consts P, Tabl
         sdf.M = P.link_samples;
     }
     step_setup<SR, SDF>(P, seg, sph, S, inv, B, wkey, wr, lds, st, sst, sdf);
-    step_solve<SR, false, true>(P, sst, B.mu, inv, reinterpret_cast<SR *>(lds.cand_d));
+    step_solve<SR, true>(P, sst, B.mu, inv, reinterpret_cast<SR *>(lds.cand_d));
     step_finish<SR>(P, sst, inv, B, wkey, wr, link, imp);
     const int lane = lane_id();
     if (EQ3) {
@@ -574,7 +574,7 @@ k_window(Consts P, Tables tb, const float *__restrict__ seg_win, float *__restri
             if (ck) save_body(ck, B);
             StepState<SR> sst;
             step_setup<SR, SDF>(P, seg, sph, S, inv, B, wkey, wr, lds, st, sst, sdf);
-            step_solve<SR, true, PT>(P, sst, B.mu, inv, reinterpret_cast<SR *>(lds.cand_d));
+            step_solve<SR, PT>(P, sst, B.mu, inv, reinterpret_cast<SR *>(lds.cand_d));
             if (ck) save_contact<SR>(ck, P.C_max, sst);
             step_finish<SR>(P, sst, inv, B, wkey, wr, link, imp);
             uniform_body(B);
