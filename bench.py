@@ -290,13 +290,27 @@ def windows_run(pt, setup, dev, solve_precision, n_win, n_warm, optimizer="pbo",
     flops = algorithmic_flops(int(sc.n_spheres.max()), L, cfg.newton_iters, d_env, d_con)
     hp = setup["hposes"].cpu().numpy()
 
+    # windows in which the observed object touches a sensor at all (touch is
+    # the tracker's only information: an object that left the hand cannot
+    # be followed)
+    fo = gts[:n_total * T, 0].sum(dim=1).reshape(n_total, T, G).amax(dim=1).cpu().numpy()
+    touching = fo > 0.0
+
     def tracking(e):
-        errs = []
+        errs, errs_t = [], []
         for w in range(n_warm, n_total):
             for g in range(G):
                 pts = sc.spheres[sc.hidden_type[g], :sc.n_spheres[sc.hidden_type[g]], :3]
-                errs.append(add_distance(pts, e[w, :7, g], hp[w, :7, g]))
-        return {"mean": round(1e3 * float(np.mean(errs)), 3), "p90": round(1e3 * float(np.quantile(errs, 0.9)), 3)}
+                d = add_distance(pts, e[w, :7, g], hp[w, :7, g])
+                errs.append(d)
+                if touching[w, g]:
+                    errs_t.append(d)
+        out = {"mean": round(1e3 * float(np.mean(errs)), 3), "p90": round(1e3 * float(np.quantile(errs, 0.9)), 3)}
+        if errs_t:
+            out["touching"] = {"mean": round(1e3 * float(np.mean(errs_t)), 3),
+                               "p90": round(1e3 * float(np.quantile(errs_t, 0.9)), 3),
+                               "windows_frac": round(len(errs_t) / len(errs), 3)}
+        return out
 
     n_elite = b.elite_count()
     b.close()

@@ -152,20 +152,6 @@ __device__ __forceinline__ uint64_t pack_gap_key(float d, int k)
     return ((uint64_t)u << 32) | (uint32_t)k;
 }
 
-// Word x of lane src (any lane of the wave) through the LDS crossbar
-// (ds_bpermute per 32-bit word, no LDS memory)
-__device__ __forceinline__ float lane_gather(float x, int src)
-{
-    return __int_as_float(__builtin_amdgcn_ds_bpermute(src << 2, __float_as_int(x)));
-}
-__device__ __forceinline__ double lane_gather(double x, int src)
-{
-    const long long b = __double_as_longlong(x);
-    const int lo = __builtin_amdgcn_ds_bpermute(src << 2, (int)(b & 0xffffffffll));
-    const int hi = __builtin_amdgcn_ds_bpermute(src << 2, (int)(b >> 32));
-    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-
 // One half-wave's values in both halves: lanes i and i + 32 both end with
 // what lane i held (from_upper false) or what lane i + 32 held (true).  One
 // ds_bpermute per 32-bit word (the LDS crossbar, no LDS memory).
@@ -858,78 +844,6 @@ __device__ __forceinline__ void schur_solve(const SR *acc, const BodyMass<SR> &M
             z[3 + i] = -(Iinv[3 * i] * acc[39] + Iinv[3 * i + 1] * acc[40] + Iinv[3 * i + 2] * acc[41]);
     }
     solve6(S6, z);
-}
-
-// schur_solve spread over the lanes: lane 8 i + j (i < 6, j < 7) holds
-// entry (i, j) of the augmented system [S | r] that schur_solve forms from
-// the summed rows in red (S = M + A6, r = -b6 with finite inertias; else
-// S = I + M^-1 A6, r = -M^-1 b6), then Gauss-Jordan elimination in the
-// natural pivot order (no pivoting, as schur_solve: S's leading blocks stay
-// well away from singular), each step taking the pivot and the pivot row's
-// and column's entries through the LDS crossbar: ~60 instructions per wave
-// instead of the ~190 the register form runs in every lane.  z_i ends in
-// column 6 of row i and goes to every lane through LDS.
-// madd: this lane's entry of M in the inertia form (lane_mass).
-// (entries are copied to locals before the per-lane selects: a select between
-// the struct's members would become a select of addresses and put the struct
-// in scratch memory)
-template <typename SR>
-__device__ __forceinline__ SR lane_mass(const BodyMass<SR> &M)
-{
-    const int lane = lane_id(), i = lane >> 3, j = lane & 7;
-    SR b[9];
-#pragma unroll
-    for (int k = 0; k < 9; ++k) b[k] = M.blk[k];
-    SR m = (i < 3 && j == i) ? M.sc : SR(0);
-#pragma unroll
-    for (int r = 0; r < 3; ++r)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) m = (i == 3 + r && j == 3 + c) ? b[3 * r + c] : m;
-    return m;
-}
-
-template <typename SR>
-__device__ __forceinline__ void schur_solve_lanes(const SR *red, const BodyMass<SR> &M, SR madd, SR (&z)[6])
-{
-    // the lane index made opaque here, so that the row and column tests are
-    // taken afresh in each call instead of being held (as masks in scalar
-    // registers) through the whole Newton loop
-    int lane = lane_id();
-    asm volatile("" : "+v"(lane));
-    const int i = lane >> 3, j = lane & 7;
-    SR a = SR(0);
-    if (i < 6 && j < 7) {
-        if (M.inertia_form) {
-            a = j < 6 ? red[6 * i + j] + madd : -red[36 + i];
-        } else if (i < 3) {
-            const SR im = M.sc;
-            a = j < 6 ? red[6 * i + j] * im + (j == i ? SR(1) : SR(0)) : -red[36 + i] * im;
-        } else {
-            // row i - 3 of the inverse inertia (wave-uniform rows picked per lane)
-            SR b[9];
-#pragma unroll
-            for (int k = 0; k < 9; ++k) b[k] = M.blk[k];
-            const SR c0 = i == 3 ? b[0] : (i == 4 ? b[3] : b[6]);
-            const SR c1 = i == 3 ? b[1] : (i == 4 ? b[4] : b[7]);
-            const SR c2 = i == 3 ? b[2] : (i == 4 ? b[5] : b[8]);
-            a = j < 6 ? c0 * red[18 + j] + c1 * red[24 + j] + c2 * red[30 + j] + (j == i ? SR(1) : SR(0))
-                      : -(c0 * red[39] + c1 * red[40] + c2 * red[41]);
-        }
-    }
-#pragma unroll
-    for (int k = 0; k < 6; ++k) {
-        const SR rp = recip(lane_gather(a, 9 * k));
-        const SR akj = lane_gather(a, 8 * k + j), aik = lane_gather(a, 8 * i + k);
-        a = i == k ? a * rp : a - (aik * rp) * akj;
-    }
-    // z through the words after the sums (row 1 of the summed rows, read
-    // before the solve): vector registers in every lane, no scalar ones
-    SR *zs = const_cast<SR *>(red) + 48;
-    if (i < 6 && j == 6) zs[i] = a;
-    wave_sync();
-#pragma unroll
-    for (int k = 0; k < 6; ++k) z[k] = zs[k];
-    wave_sync();
 }
 
 // ---------------------------------------------------------------------

@@ -599,10 +599,10 @@ __device__ __forceinline__ void step_setup(const Consts &P, const float *__restr
 // -M^-1 sum_c J_c^T P_c^-1 Phi_c with P_c = JX_c + eps JY_c, B_c = JY_c; then
 // dr_c = -P_c^-1 (Phi_c + B_c J_c dnu).  Leaves st.r and the fresh st.nu.
 // red: LDS for the cross-contact sum of the 6x6 system (the wave's candidate
-// list, free once the cap has run); the 6x6 solve runs across the lanes on
-// the sums there.  PairTrials: with at most 32 contacts the line search runs
-// its trials two at a time, one per half-wave (the same trials, sums and
-// choice; the worst case of four trials costs two).
+// list, free once the cap has run); the 6x6 solve reads the sums there.
+// PairTrials: with at most 32 contacts the line search runs its trials two
+// at a time, one per half-wave (the same trials, sums and choice; the worst
+// case of four trials costs two).
 template <typename SR, bool PairTrials = false>
 __device__ __forceinline__ void step_solve(const Consts &P, StepState<SR> &st, float mu_f, const float *inv_in,
                                            SR *red)
@@ -610,7 +610,6 @@ __device__ __forceinline__ void step_solve(const Consts &P, StepState<SR> &st, f
     const SR eps = P.compliance, kap = P.kappa, del = P.fb_delta, mu = mu_f;
     BodyMass<SR> Mb;
     body_mass<SR>(st.m, st.Iinv, inv_in, Mb);
-    const SR madd = lane_mass(Mb);
     const bool act = st.act;
     const int span = st.span;
     SR *r = st.r;
@@ -664,11 +663,13 @@ __device__ __forceinline__ void step_solve(const Consts &P, StepState<SR> &st, f
 #pragma unroll
                 for (int i = 0; i < 43; ++i) acc[i] = SR(0);
             }
-            // the sums stay valid in LDS until the next iteration's rows
+            // the sums stay valid in LDS until the next iteration's rows; the
+            // 6x6 solve reads them from there as it goes (fewer live
+            // registers than loading all 43 at once)
             SR rhs[6];
             lds_colsum<SR, 43>(acc, st.C, red);
             const SR psi = red[42];
-            schur_solve_lanes(red, Mb, madd, rhs);
+            schur_solve(red, Mb, rhs);
             // dr = -g - Q F (dv + dw x rho)
             SR dp[3];
             SR dw3[3] = {rhs[3], rhs[4], rhs[5]};
