@@ -60,6 +60,9 @@ def parse():
     ap.add_argument("--profile", action="store_true",
                     help="run for the profiler: one run of the headline leg as timed (batched + refinement), "
                          "nothing else")
+    ap.add_argument("--profile-leg", choices=["pd_hand", "distance_field"],
+                    help="run for the profiler: one run of that leg on the real-time workload (the per-step path; "
+                         "for the distance field also its batched windows), nothing else")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 256 MiB on the device three times with the ceiling library's copy kernel "
                          "(reference for the FETCH_SIZE / WRITE_SIZE counters)")
@@ -116,6 +119,30 @@ FLOP_ENV_ITER = 390         # per Newton iteration: 6x6 assembly, LU, velocity u
 def algorithmic_flops(S, L, N, env_steps, contacts):
     per_env = FLOP_ENV + FLOP_ENV_PER_LINK * L + S * FLOP_SPHERE + S * L * FLOP_PAIR + N * FLOP_ENV_ITER
     return env_steps * per_env + contacts * (FLOP_CONTACT + N * FLOP_CONTACT_ITER)
+
+
+# links against the objects' distance fields: per link sample its point, the
+# point in the object frame and the trilinear value less the radius; per
+# sphere its height over the table (the field's gradient at the kept
+# contacts is not counted, so the figure is a lower bound)
+FLOP_SAMPLE = 76
+FLOP_TABLE = 7
+
+
+def algorithmic_flops_sdf(S, L, M, N, env_steps, contacts):
+    per_env = FLOP_ENV + FLOP_ENV_PER_LINK * L + S * FLOP_TABLE + L * M * FLOP_SAMPLE + N * FLOP_ENV_ITER
+    return env_steps * per_env + contacts * (FLOP_CONTACT + N * FLOP_CONTACT_ITER)
+
+
+def step_roofline(kernel, flops, env_steps, kernel_us, launches):
+    """The ALU roofline of a per-step or window kernel: algorithmic flop per
+    launch over its average launch time from HIP events on its stream."""
+    per_launch = flops / launches
+    achieved = per_launch / (kernel_us * 1e-6) / 1e12
+    return {"bound": "alu", "kernel": kernel, "achieved": round(achieved, 3), "peak": PEAK_F64_TFLOPS,
+            "unit": "TFLOP/s", "frac": round(achieved / PEAK_F64_TFLOPS, 4),
+            "flop_per_env_step": round(flops / env_steps, 1), "env_steps_per_launch": round(env_steps / launches),
+            "avg_launch_us": round(kernel_us, 2)}
 
 
 def window_bytes(C_max, T, L, obs=False, checkpoints=False):
@@ -287,7 +314,11 @@ def windows_run(pt, setup, dev, solve_precision, n_win, n_warm, optimizer="pbo",
     # refinement's own replays do not count their steps in the statistics)
     d_env = stats1["env_steps"] - stats0["env_steps"]
     d_con = stats1["contacts"] - stats0["contacts"]
-    flops = algorithmic_flops(int(sc.n_spheres.max()), L, cfg.newton_iters, d_env, d_con)
+    if cfg.consts.collision_mode == 1:
+        flops = algorithmic_flops_sdf(int(sc.n_spheres.max()), L, cfg.consts.link_samples, cfg.newton_iters, d_env,
+                                      d_con)
+    else:
+        flops = algorithmic_flops(int(sc.n_spheres.max()), L, cfg.newton_iters, d_env, d_con)
     hp = setup["hposes"].cpu().numpy()
 
     # windows in which the observed object touches a sensor at all (touch is
@@ -348,12 +379,16 @@ def plain_run(pt, setup, dev, solve_precision, steps, warmup):
     best = torch.zeros(G, dtype=torch.int32, device=dev)
     parent = torch.zeros(K, dtype=torch.int32, device=dev)
     obs = b.new_obs()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    mk = lambda: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))  # noqa: E731
+    ev, ev_k = [mk() for _ in range(steps)], [mk() for _ in range(steps)]
 
     def one(t, i=None):
         if i is not None:
             ev[i][0].record()
+            ev_k[i][0].record()
         b.step(u_all[max(t - 1, 0)], u_all[t])
+        if i is not None:
+            ev_k[i][1].record()
         b.observe(obs)
         b.cost(obs, gts[t], cost, best)
         if i is not None:
@@ -373,14 +408,22 @@ def plain_run(pt, setup, dev, solve_precision, steps, warmup):
     stats1 = b.read_stats()
     b.close()
     step_ms = np.array([a.elapsed_time(c) for a, c in ev])
+    kernel_us = 1e3 * float(np.mean([a.elapsed_time(c) for a, c in ev_k]))
     d_env = stats1["env_steps"] - stats0["env_steps"]
     d_con = stats1["contacts"] - stats0["contacts"]
+    c = cfg.consts
+    if c.collision_mode == 1:
+        flops = algorithmic_flops_sdf(int(sc.n_spheres.max()), sc.L, c.link_samples, cfg.newton_iters, d_env, d_con)
+    else:
+        flops = algorithmic_flops(int(sc.n_spheres.max()), sc.L, cfg.newton_iters, d_env, d_con)
     return {"value": K * steps / wall, "unit": "env-steps/s", "steps": steps,
             "ms_per_step": round(wall / steps * 1e3, 4),
             "per_step_ms": {"p50": round(float(np.median(step_ms)), 4),
                             "p99": round(float(np.quantile(step_ms, 0.99)), 4)},
             "budget_30hz_met": bool(np.quantile(step_ms, 0.99) < 1000.0 / 30.0),
-            "contacts_per_env_step": round(d_con / max(d_env, 1), 2)}
+            "contacts_per_env_step": round(d_con / max(d_env, 1), 2),
+            "step_kernel": {"avg_launch_us": round(kernel_us, 2), "flops": flops, "env_steps": d_env,
+                            "launches": steps}}
 
 
 def pd_run(pt, S, dev, cfg, steps, warmup, batched=False):
@@ -416,12 +459,16 @@ def pd_run(pt, S, dev, cfg, steps, warmup, batched=False):
         n_ev = steps // T
     else:
         n_ev = steps
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n_ev)]
+    mk = lambda: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))  # noqa: E731
+    ev, ev_k = [mk() for _ in range(n_ev)], [mk() for _ in range(n_ev)]
 
     def one(t, i=None):
         if i is not None:
             ev[i][0].record()
+            ev_k[i][0].record()
         b.step(None, u_all[t])
+        if i is not None:
+            ev_k[i][1].record()
         b.observe(obs)
         b.cost(obs, gts[t], cost, best)
         if i is not None:
@@ -462,11 +509,22 @@ def pd_run(pt, S, dev, cfg, steps, warmup, batched=False):
     step_ms = np.array([a.elapsed_time(c) for a, c in ev]) / (T if batched else 1)
     d_env = stats1["env_steps"] - stats0["env_steps"]
     d_con = stats1["contacts"] - stats0["contacts"]
-    return {"value": K * steps / wall, "unit": "env-steps/s", "steps": steps,
-            "ms_per_step": round(wall / steps * 1e3, 4),
-            "per_step_ms": {"p50": round(float(np.median(step_ms)), 4),
-                            "p99": round(float(np.quantile(step_ms, 0.99)), 4)},
-            "contacts_per_env_step": round(d_con / max(d_env, 1), 2)}
+    out = {"value": K * steps / wall, "unit": "env-steps/s", "steps": steps,
+           "ms_per_step": round(wall / steps * 1e3, 4),
+           "per_step_ms": {"p50": round(float(np.median(step_ms)), 4),
+                           "p99": round(float(np.quantile(step_ms, 0.99)), 4)},
+           "contacts_per_env_step": round(d_con / max(d_env, 1), 2)}
+    if not batched:
+        # the kinematic step's arithmetic only (the PD step does all of it,
+        # plus the hand's kinematics, mass matrix, hand blocks and group
+        # eliminations, not counted): a lower bound
+        c = cfg.consts
+        flops = (algorithmic_flops_sdf(int(sc.n_spheres.max()), sc.L, c.link_samples, cfg.newton_iters, d_env, d_con)
+                 if c.collision_mode == 1 else
+                 algorithmic_flops(int(sc.n_spheres.max()), sc.L, cfg.newton_iters, d_env, d_con))
+        out["step_kernel"] = {"avg_launch_us": round(1e3 * float(np.mean([a.elapsed_time(c_) for a, c_ in ev_k])), 2),
+                              "flops": flops, "env_steps": d_env, "launches": steps}
+    return out
 
 
 def repeat(fn, runs):
@@ -660,6 +718,27 @@ def main():
     T = cfg.T
     n_win = max(MIN_WINDOWS, -(-args.steps // T))
     n_warm = max(1, -(-args.warmup // T))
+    if args.profile_leg:
+        steps = min(n_win * T, 300)
+        if args.profile_leg == "pd_hand":
+            r = pd_run(pt, S, dev, cfg, steps, n_warm * T)
+            sk = r.pop("step_kernel")
+            r["roofline"] = step_roofline("k_step_pd", sk["flops"], sk["env_steps"], sk["avg_launch_us"],
+                                          sk["launches"])
+        else:
+            scfg = cfg.with_(consts=dataclasses.replace(cfg.consts, collision_mode=1))
+            nw = -(-steps // T)
+            ssetup = make_setup(pt, S, dev, sp, scfg, n_warm + nw)
+            r = plain_run(pt, ssetup, dev, sp, steps, n_warm * T)
+            sk = r.pop("step_kernel")
+            r["roofline"] = step_roofline("k_step<double, false, true>", sk["flops"], sk["env_steps"],
+                                          sk["avg_launch_us"], sk["launches"])
+            rb = windows_run(pt, ssetup, dev, sp, nw, n_warm, refine=False)
+            wk = rb["window_kernel"]
+            r["batched_roofline"] = step_roofline("k_window<double, false, false, true>", wk["flop_per_launch"] * nw,
+                                                  wk["env_steps_per_launch"] * nw, wk["avg_launch_us"], nw)
+        print(json.dumps({"leg": args.profile_leg, **rounded(r)}), flush=True)
+        return
     runs = 1 if args.profile else args.runs
     print(f"bench: headline {cfg.name}, {runs} runs of {n_win} windows after {n_warm}", file=sys.stderr, flush=True)
     setup = make_setup(pt, S, dev, sp, cfg, n_warm + n_win)
@@ -740,6 +819,10 @@ def main():
             keys = ("value", "unit", "steps", "ms_per_step", "per_step_ms", "contacts_per_env_step", "runs")
             r = repeat(lambda: pd_run(pt, S, dev, wcfg, min(n_win * T, 300), n_warm * T), runs)
             pd[name] = rounded({k: r[k] for k in keys if k in r})
+            sk = r["step_kernel"]
+            pd[name]["roofline"] = step_roofline(
+                "k_step_pd (one PD step of every simulation; flop of the kinematic step only, a lower bound)",
+                sk["flops"], sk["env_steps"], sk["avg_launch_us"], sk["launches"])
             r = repeat(lambda: pd_run(pt, S, dev, wcfg, min(n_win * T, 300), n_warm * T, batched=True), runs)
             pd[name + "_batched"] = rounded({k: r[k] for k in keys if k in r})
             pd[name + "_batched_vs_plain"] = round(pd[name + "_batched"]["value"] / pd[name]["value"], 3)
@@ -747,6 +830,8 @@ def main():
                       "(6 + D) contact solve per simulation; observe: forces and joint angles; cost with the "
                       "joint term) and batched windows (the T steps of a simulation, its observations and costs in "
                       "one wavefront, replayed from a HIP graph), PBO resampling every window")
+        if not args.no_cpu_baseline:
+            pd["cpu_baseline"] = cpu_baseline(S, cfg.with_(consts=dataclasses.replace(cfg.consts, hand_mode=1)), 10)
         result["pd_hand"] = pd
         print("bench: PD hand done", file=sys.stderr, flush=True)
         # links against the objects' signed distance fields (32^3 grids, 8 samples per link)
@@ -765,8 +850,18 @@ def main():
             "realtime16384_batched": rounded({k: rb[k] for k in ("value", "unit", "windows", "ms_per_step",
                                                                  "per_step_ms", "tracking_error_mm",
                                                                  "waves_per_workgroup", "runs") if k in rb}),
+            "roofline": {
+                "plain": step_roofline("k_step<double, false, true> (one step of every simulation)",
+                                       r["step_kernel"]["flops"], r["step_kernel"]["env_steps"],
+                                       r["step_kernel"]["avg_launch_us"], r["step_kernel"]["launches"]),
+                "batched": step_roofline("k_window<double, false, false, true> (the 10-step window)",
+                                         rb["window_kernel"]["flop_per_launch"] * sw,
+                                         rb["window_kernel"]["env_steps_per_launch"] * sw,
+                                         rb["window_kernel"]["avg_launch_us"], sw)},
             "vs_sphere_set_plain": round(r["value"] / plain["value"], 3),
             "batched_vs_sphere_set_batched": round(rb["value"] / batched["value"], 3)}
+        if not args.no_cpu_baseline:
+            result["distance_field"]["cpu_baseline"] = cpu_baseline(S, scfg, 10)
         print("bench: distance field done", file=sys.stderr, flush=True)
 
     # the other workloads, the paths their definitions name
