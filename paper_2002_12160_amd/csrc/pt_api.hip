@@ -937,12 +937,13 @@ pt_status pt_refine_elites(pt_batch b, const float *u_win, const float *obs_gt_w
         HIP_TRY(launch_refine_gather(n, P.K, P.C_max, b->d_elite, start_state, start_params, start_warm,
                                      from_window ? cost_sum : nullptr, r.xi, r.warm0, r.cost, r.rho, step, st));
         // every elite's chain of replays and sweeps is its own, so when the
-        // elites outnumber the wavefronts the GPU holds at once (two rounds
-        // of eight per compute unit) they go in parts on streams of their
-        // own: one part's short kernels and the tail of its replay overlap
-        // the others' replays (the same bits as one launch over all of
-        // them); each part has its own checkpoints.  Fewer elites all run at
-        // once in one launch, and parts would only add launches.
+        // elites outnumber what the GPU holds at once (from 16 per compute
+        // unit: more than two rounds of the at most seven replay wavefronts
+        // a compute unit holds) they go in parts on streams of their own:
+        // one part's short kernels and the tail of its replay overlap the
+        // others' replays (the same bits as one launch over all of them);
+        // each part has its own checkpoints.  Fewer elites all run at once
+        // in one launch, and parts would only add launches.
         constexpr int NP = pt_batch_s::REFINE_PARTS;
         const int parts = n >= 16 * b->num_cu ? NP : 1;
         struct Part {
