@@ -800,6 +800,12 @@ def main():
     batched = repeat(lambda: windows_run(pt, setup, dev, sp, n_win, n_warm, refine=False), runs)
     print(f"bench: batched {batched['value']:.4g}", file=sys.stderr, flush=True)
     pv = plain["value"]
+    sk, wk = plain.pop("step_kernel"), batched.pop("window_kernel")
+    plain["roofline"] = step_roofline("k_step<double, false, false> (one step of every simulation)", sk["flops"],
+                                      sk["env_steps"], sk["avg_launch_us"], sk["launches"])
+    batched["roofline"] = step_roofline("k_window<double, false, false, false> (the window, no checkpoints)",
+                                        wk["flop_per_launch"], wk["env_steps_per_launch"], wk["avg_launch_us"], 1)
+    batched["contacts_per_env_step"] = wk["contacts_per_env_step"]
     result["paths"] = {
         "plain": rounded(plain),
         "batched": dict(rounded(batched), speedup_vs_plain=round(batched["value"] / pv, 3)),
