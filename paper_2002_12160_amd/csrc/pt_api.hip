@@ -391,8 +391,10 @@ pt_status pt_create_batch(const pt_batch_desc *d, pt_batch *out)
     // step with more cuts its list to the C_max lowest and goes on -- plus 8
     // entries of padding for the cap's 16-byte reads); the same LDS holds,
     // once the cap has run, the rows of the solve's cross-contact sums
-    // (lane_span(C_max) rows of RedStride<double> = 44 doubles)
-    const int red_rows = d->C_max <= 16 ? 16 : (d->C_max <= 32 ? 32 : 64);
+    // (rows of RedStride<double> = 44 doubles: one per contact slot for the
+    // PD solve's per-link sums, at most 32 for the kinematic solve's sums,
+    // which fold the upper half-wave's contacts onto the lower one's)
+    const int red_rows = d->C_max <= 16 ? 16 : (d->C_max <= 32 || d->hand_mode == 0 ? 32 : 64);
     // the PD hand's structure
     std::vector<int32_t> pd_tab;
     int pd_groups = 0, pd_dmax = 0, pd_gmax = 0;
@@ -411,10 +413,9 @@ pt_status pt_create_batch(const pt_batch_desc *d, pt_batch *out)
         max_cand = std::max({round_up(list, 64), round_up(rows, 64), round_up(fk, 64)});
         max_cand_rows = max_cand;
     } else {
-        // the sum rows may run on into the spare words after the list
-        // (3 KB less per wavefront at the 64-contact cap: seven window
-        // wavefronts per compute unit instead of six); the reverse sweep,
-        // which stages its own data there, keeps them whole in the list
+        // the sum rows may run on into the spare words after a shorter
+        // list; the reverse sweep, which stages its own data there, keeps
+        // them whole in the list
         max_cand = std::max({round_up(list, 32), round_up(rows - pt::WAVE_SPARE_BYTES / 8, 32), round_up(fk, 32)});
         max_cand_rows = std::max(max_cand, round_up(rows, 32));
     }
@@ -938,8 +939,8 @@ pt_status pt_refine_elites(pt_batch b, const float *u_win, const float *obs_gt_w
                                      from_window ? cost_sum : nullptr, r.xi, r.warm0, r.cost, r.rho, step, st));
         // every elite's chain of replays and sweeps is its own, so when the
         // elites outnumber what the GPU holds at once (from 16 per compute
-        // unit: more than two rounds of the at most seven replay wavefronts
-        // a compute unit holds) they go in parts on streams of their own:
+        // unit: two or more rounds of the at most eight replay wavefronts a
+        // compute unit holds) they go in parts on streams of their own:
         // one part's short kernels and the tail of its replay overlap the
         // others' replays (the same bits as one launch over all of them);
         // each part has its own checkpoints.  Fewer elites all run at once

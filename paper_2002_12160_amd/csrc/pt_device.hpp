@@ -642,8 +642,8 @@ __device__ __forceinline__ void solve6(const T (&S)[36], T (&b)[6])
 // Row stride (elements) of the LDS reduction buffer: rows 16-byte aligned,
 // and the 16-byte row writes of eight consecutive lanes on distinct banks
 // (44 doubles = 88 dwords, rows 24 banks apart); for doubles the narrowest
-// stride that holds the 43 sums, since with caps above 32 its 64 rows set
-// a simulation's LDS and with it how many wavefronts a compute unit holds
+// stride that holds the 43 sums folded in two halves of 22, since with caps
+// above 16 its 32 rows size the solve's share of a simulation's LDS
 template <typename T>
 struct RedStride {
     static constexpr int value = sizeof(T) == 8 ? 44 : 68;
@@ -676,42 +676,68 @@ __device__ __forceinline__ void load16<float>(const float *p, float *v)
     v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
 }
 
+// Two half-wave folds in one: lane l < 32 gets a[l] + a[l + 32], lane
+// l >= 32 gets b[l - 32] + b[l] (the lower lane's value first).  The swap of
+// a's upper half-wave with b's lower one puts both addends of every lane in
+// the two swapped registers, with no LDS round trip.
+__device__ __forceinline__ double fold_halves(double a, double b)
+{
+    const auto lo = __builtin_amdgcn_permlane32_swap(__double2loint(a), __double2loint(b), false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap(__double2hiint(a), __double2hiint(b), false, false);
+    return __hiloint2double((int)hi[0], (int)lo[0]) + __hiloint2double((int)hi[1], (int)lo[1]);
+}
+__device__ __forceinline__ float fold_halves(float a, float b)
+{
+    const auto s = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    return __uint_as_float(s[0]) + __uint_as_float(s[1]);
+}
+
 // Sum of v[0..N) over lanes [0, n) through LDS, for wide vectors where DPP
-// rounds would cost N instructions each: the lanes below n16 = n rounded up
-// to 16 write their values as rows (lanes n .. n16-1 must hold zeros), lane
-// j < N adds column j over the rows, 32 reads in flight at a time (16 for a
-// last odd block) into four interleaved partial sums in a fixed order, and the N sums land in
-// buf[0..N), where every lane can read them (the same bits for every lane).
-// Lanes >= n16 do not take part.  buf: 16-byte aligned, n16 rows of
-// RedStride<T> elements.  The sums stay valid until the next write to buf.
+// rounds would cost N instructions each.  Every lane >= n must hold zeros.
+// First each pair (v[2k], v[2k+1]) is folded across the half-waves
+// (fold_halves), so that row r < 32 holds lane r's and lane r + 32's values
+// added: the even-indexed sums in its first H = ceil(N / 2) entries (written
+// by lane r), the odd-indexed ones in the next H (written by lane r + 32),
+// each half padded to whole 16-byte words.  Rows up to n16 = n rounded up to
+// 16 (at most 32) are written; lane j < N then adds its sum's column over
+// them, 32 (or 16) reads in flight into four interleaved partial sums in a
+// fixed order, and the N sums land in buf[0..N) in their natural order, where
+// every lane can read them (the same bits for every lane).  With n <= 32 the
+// folds add zeros and the sums are those of the plain column sum over n16
+// rows.  buf: 16-byte aligned, n16 rows of RedStride<T> elements.  The sums
+// stay valid until the next write to buf.
 template <typename T, int N>
 __device__ __forceinline__ void lds_colsum(const T (&v)[N], int n, T *buf)
 {
     constexpr int RS = RedStride<T>::value;
     constexpr int PER = 16 / (int)sizeof(T);
-    static_assert(N <= RS && N <= 64, "vector too long for the reduction buffer");
+    constexpr int H = (N + 1) / 2, HP = (H + PER - 1) / PER * PER;
+    static_assert(2 * HP <= RS && N <= 64, "vector too long for the reduction buffer");
     const int lane = lane_id();
-    const int n16 = (n + 15) & ~15;
-    if (lane < n16) {
-        T *row = buf + lane * RS;
+    const int n16 = min((n + 15) & ~15, 32);
+    {
+        T f[HP];
 #pragma unroll
-        for (int j = 0; j + PER <= N; j += PER) store16<T>(row + j, v + j);
+        for (int k = 0; k < H; ++k) f[k] = fold_halves(v[2 * k], 2 * k + 1 < N ? v[2 * k + 1] : T(0));
 #pragma unroll
-        for (int j = N - N % PER; j < N; ++j) row[j] = v[j];
+        for (int k = H; k < HP; ++k) f[k] = T(0);
+        if ((lane & 31) < n16) {
+            T *row = buf + (lane & 31) * RS + (lane >> 5) * HP;
+#pragma unroll
+            for (int j = 0; j < HP; j += PER) store16<T>(row + j, f + j);
+        }
     }
     wave_sync();
     T s4[4] = {T(0), T(0), T(0), T(0)};
     if (lane < N) {
-        const T *col = buf + lane;
-        int r0 = 0;
-        for (; r0 + 32 <= n16; r0 += 32, col += 32 * RS) {
+        const T *col = buf + (lane & 1) * HP + (lane >> 1);
+        if (n16 == 32) {
             T x[32];
 #pragma unroll
             for (int k = 0; k < 32; ++k) x[k] = col[k * RS];
 #pragma unroll
             for (int k = 0; k < 32; ++k) s4[k & 3] += x[k];
-        }
-        if (r0 < n16) {
+        } else if (n16 == 16) {
             T x[16];
 #pragma unroll
             for (int k = 0; k < 16; ++k) x[k] = col[k * RS];
