@@ -698,14 +698,15 @@ __device__ __forceinline__ float fold_halves(float a, float b)
 // (fold_halves), so that row r < 32 holds lane r's and lane r + 32's values
 // added: the even-indexed sums in its first H = ceil(N / 2) entries (written
 // by lane r), the odd-indexed ones in the next H (written by lane r + 32),
-// each half padded to whole 16-byte words.  Rows up to n16 = n rounded up to
-// 16 (at most 32) are written; lane j < N then adds its sum's column over
-// them, 32 (or 16) reads in flight into four interleaved partial sums in a
-// fixed order, and the N sums land in buf[0..N) in their natural order, where
-// every lane can read them (the same bits for every lane).  With n <= 32 the
-// folds add zeros and the sums are those of the plain column sum over n16
-// rows.  buf: 16-byte aligned, n16 rows of RedStride<T> elements.  The sums
-// stay valid until the next write to buf.
+// each half padded to whole 16-byte words.  With n <= 32 there is nothing to
+// fold and lane r < n16 writes both halves of row r itself (the same bits the
+// fold would give: it would add zeros).  Rows up to n16 = n rounded up to 16
+// (at most 32) are written; lane j < N then adds its sum's column over them,
+// 32 (or 16) reads in flight into four interleaved partial sums in a fixed
+// order, and the N sums land in buf[0..N) in their natural order, where every
+// lane can read them (the same bits for every lane).  buf: 16-byte aligned,
+// n16 rows of RedStride<T> elements.  The sums stay valid until the next
+// write to buf.
 template <typename T, int N>
 __device__ __forceinline__ void lds_colsum(const T (&v)[N], int n, T *buf)
 {
@@ -715,17 +716,28 @@ __device__ __forceinline__ void lds_colsum(const T (&v)[N], int n, T *buf)
     static_assert(2 * HP <= RS && N <= 64, "vector too long for the reduction buffer");
     const int lane = lane_id();
     const int n16 = min((n + 15) & ~15, 32);
-    {
+    if (n > 32) {
         T f[HP];
 #pragma unroll
         for (int k = 0; k < H; ++k) f[k] = fold_halves(v[2 * k], 2 * k + 1 < N ? v[2 * k + 1] : T(0));
 #pragma unroll
         for (int k = H; k < HP; ++k) f[k] = T(0);
-        if ((lane & 31) < n16) {
-            T *row = buf + (lane & 31) * RS + (lane >> 5) * HP;
+        T *row = buf + (lane & 31) * RS + (lane >> 5) * HP;
 #pragma unroll
-            for (int j = 0; j < HP; j += PER) store16<T>(row + j, f + j);
+        for (int j = 0; j < HP; j += PER) store16<T>(row + j, f + j);
+    } else if (lane < n16) {
+        // nothing to fold: each lane writes both halves of its own row
+        T e[HP], o[HP];
+#pragma unroll
+        for (int k = 0; k < HP; ++k) {
+            e[k] = 2 * k < N ? v[2 * k] : T(0);
+            o[k] = 2 * k + 1 < N ? v[2 * k + 1] : T(0);
         }
+        T *row = buf + lane * RS;
+#pragma unroll
+        for (int j = 0; j < HP; j += PER) store16<T>(row + j, e + j);
+#pragma unroll
+        for (int j = 0; j < HP; j += PER) store16<T>(row + HP + j, o + j);
     }
     wave_sync();
     T s4[4] = {T(0), T(0), T(0), T(0)};
