@@ -402,8 +402,8 @@ PT_API pt_status pt_window_grad(pt_batch b, const float *u_win, const float *obs
  *                  (groups in order, by rank within a group), or NULL
  * The elites' starts, gradients and checkpoints use buffers the batch holds
  * from pt_create_batch on; calls on different streams must not overlap.
- * From 16 elites per compute unit on, the elites run in three parts, two of
- * them on streams the batch owns, forked from `s` and joined back to it with
+ * From 16 elites per compute unit on, the elites run in two parts, the second
+ * on a stream the batch owns, forked from `s` and joined back to it with
  * events: the call is ordered on `s` as a whole (and can be captured there),
  * and its results are those of one launch over all elites. */
 PT_API pt_status pt_refine_elites(pt_batch b, const float *u_win, const float *obs_gt_win, float *cost_sum,

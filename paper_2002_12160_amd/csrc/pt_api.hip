@@ -135,7 +135,7 @@ struct pt_batch_s {
     hipStream_t capture_stream = nullptr;
     // parts 1.. of the elite refinement run on these streams, forked from
     // and joined back to the caller's stream by the events
-    static constexpr int REFINE_PARTS = 3;
+    static constexpr int REFINE_PARTS = 2;
     hipStream_t side_stream[REFINE_PARTS - 1] = {};
     hipEvent_t ev_fork = nullptr, ev_join[REFINE_PARTS - 1] = {};
     // captured windows, keyed by their buffers (a driver that double-buffers
