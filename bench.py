@@ -731,7 +731,7 @@ def main():
             ssetup = make_setup(pt, S, dev, sp, scfg, n_warm + nw)
             r = plain_run(pt, ssetup, dev, sp, steps, n_warm * T)
             sk = r.pop("step_kernel")
-            r["roofline"] = step_roofline("k_step<double, false, true>", sk["flops"], sk["env_steps"],
+            r["roofline"] = step_roofline("k_hand_fk + k_step<double, false, true, true>", sk["flops"], sk["env_steps"],
                                           sk["avg_launch_us"], sk["launches"])
             rb = windows_run(pt, ssetup, dev, sp, nw, n_warm, refine=False)
             wk = rb["window_kernel"]
@@ -801,8 +801,8 @@ def main():
     print(f"bench: batched {batched['value']:.4g}", file=sys.stderr, flush=True)
     pv = plain["value"]
     sk, wk = plain.pop("step_kernel"), batched.pop("window_kernel")
-    plain["roofline"] = step_roofline("k_step<double, false, false> (one step of every simulation)", sk["flops"],
-                                      sk["env_steps"], sk["avg_launch_us"], sk["launches"])
+    plain["roofline"] = step_roofline("k_hand_fk + k_step<double, false, false, true> (one step of every simulation)",
+                                      sk["flops"], sk["env_steps"], sk["avg_launch_us"], sk["launches"])
     batched["roofline"] = step_roofline("k_window<double, false, false, false> (the window, no checkpoints)",
                                         wk["flop_per_launch"], wk["env_steps_per_launch"], wk["avg_launch_us"], 1)
     batched["contacts_per_env_step"] = wk["contacts_per_env_step"]
@@ -857,7 +857,7 @@ def main():
                                                                  "per_step_ms", "tracking_error_mm",
                                                                  "waves_per_workgroup", "runs") if k in rb}),
             "roofline": {
-                "plain": step_roofline("k_step<double, false, true> (one step of every simulation)",
+                "plain": step_roofline("k_hand_fk + k_step<double, false, true, true> (one step of every simulation)",
                                        r["step_kernel"]["flops"], r["step_kernel"]["env_steps"],
                                        r["step_kernel"]["avg_launch_us"], r["step_kernel"]["launches"]),
                 "batched": step_roofline("k_window<double, false, false, true> (the 10-step window)",

@@ -215,7 +215,10 @@ PT_API pt_status pt_destroy_batch(pt_batch b);
  * of the previous and the current step (the hand moves from FK(u_prev) to
  * FK(u) during the step; pass u_prev == u for the first step).  Updates
  * state, params (f_pert consumed) and warm in place and keeps the solved
- * contacts for pt_observe. */
+ * contacts for pt_observe.  With the float64 solve and K at least eight per
+ * compute unit, the step's hand kinematics run once, in a launch of their
+ * own on s ahead of the step's; otherwise every simulation's wavefront
+ * evaluates them (the same bits either way). */
 PT_API pt_status pt_step(pt_batch b, const float *u_prev, const float *u, pt_stream s);
 
 /* Per-sensor observation of the last pt_step (Sec. III-A: the force vector

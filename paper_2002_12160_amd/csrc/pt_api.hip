@@ -109,7 +109,7 @@ struct pt_batch_s {
     float *d_ckpt = nullptr;
     float *d_wckpt = nullptr;    // per-step checkpoints of every simulation's window (window_checkpoints)
     float *d_cslip = nullptr;    // [K][C_max][8] per-contact slip data of the last step (cost_mode 1)
-    float *d_seg = nullptr;      // [L][16] the last step's hand segments (cost_mode 1)
+    float *d_seg = nullptr;      // [L][16] the last step's hand segments (kinematic hand)
     int n_elite = 0;
     int32_t *d_elite = nullptr;  // [n_elite]
     float *d_ref = nullptr;      // see refine_layout
@@ -132,6 +132,7 @@ struct pt_batch_s {
     // batched-path configuration
     int wpb = 4;
     int step_wpb = 4;
+    bool step_fk_once = false;   // pt_step: hand kinematics in a launch of their own
     hipStream_t capture_stream = nullptr;
     // parts 1.. of the elite refinement run on these streams, forked from
     // and joined back to the caller's stream by the events
@@ -519,9 +520,9 @@ pt_status pt_create_batch(const pt_batch_desc *d, pt_batch *out)
         HIP_TRY_C(hipMalloc(&b->d_pd_obs, sizeof(float) * (4 * (size_t)d->L + d->D) * K));
         HIP_TRY_C(hipMemcpy(b->d_pd, pd_tab.data(), sizeof(int32_t) * pd_tab.size(), hipMemcpyHostToDevice));
     }
+    if (d->hand_mode == 0) HIP_TRY_C(hipMalloc(&b->d_seg, sizeof(float) * d->L * pt::SEG_STRIDE));
     if (d->cost_mode == 1) {
         HIP_TRY_C(hipMalloc(&b->d_cslip, sizeof(float) * K * d->C_max * 8));
-        HIP_TRY_C(hipMalloc(&b->d_seg, sizeof(float) * d->L * pt::SEG_STRIDE));
         HIP_TRY_C(hipMemset(b->d_cslip, 0, sizeof(float) * K * d->C_max * 8));
     }
     HIP_TRY_C(hipMemcpy(b->d_hand, d->hand, sizeof(float) * d->L * PT_HAND_STRIDE, hipMemcpyHostToDevice));
@@ -549,6 +550,11 @@ pt_status pt_create_batch(const pt_batch_desc *d, pt_batch *out)
     // wavefront per compute unit has its LDS, caches and issue to itself
     // (measured faster than four per workgroup at 256 simulations)
     b->step_wpb = 1;
+    // from a full round of the GPU's step wavefronts (eight per compute
+    // unit) the hand kinematics run once per step in a launch of their own
+    // rather than in every wavefront; below that the step is latency-bound
+    // and the per-wavefront evaluation overlaps its state loads
+    b->step_fk_once = d->hand_mode == 0 && P.solve_fp64 && K >= 8 * b->num_cu;
 #undef HIP_TRY_C
     *out = b;
     return PT_OK;
@@ -600,8 +606,10 @@ pt_status pt_step(pt_batch b, const float *u_prev, const float *u, pt_stream s)
         return PT_OK;
     }
     if (b->P.D > 0 && (!u_prev || !u)) return fail(PT_E_ARG, "u_prev/u is NULL");
+    if (b->step_fk_once)
+        HIP_TRY(launch_hand_fk(b->d_hand, b->P.L, b->P.D, b->P.dt, u_prev, u, 0, 1, b->d_seg, st));
     HIP_TRY(launch_step(b->P, tables_of(b), u_prev, u, b->state, b->params, b->warm, b->d_contacts, b->d_cslip,
-                        b->d_seg, b->d_stats, b->step_wpb, st));
+                        b->d_seg, b->d_stats, b->step_wpb, b->step_fk_once, st));
     return PT_OK;
 }
 

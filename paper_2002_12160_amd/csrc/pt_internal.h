@@ -101,9 +101,11 @@ inline hipError_t set_dynamic_lds_limit(const void *f, size_t bytes)
 
 hipError_t launch_hand_fk(const float *hand, int L, int D, float dt, const float *u_prev, const float *u,
                           int stride, int nsteps, float *seg_out, hipStream_t s);
+// seg_in: the step's segments are already in seg_out (k_hand_fk), for the
+// float64 solve; otherwise every wavefront evaluates them
 hipError_t launch_step(const pt::Consts &P, const pt::Tables &tb, const float *u_prev, const float *u, float *state,
                        float *params, float *warm, float *contacts, float *cslip, float *seg_out, int64_t *stats,
-                       int waves_per_block, hipStream_t s);
+                       int waves_per_block, bool seg_in, hipStream_t s);
 size_t hand_fk_lds_bytes(int L, int D);
 hipError_t launch_observe(const pt::Consts &P, const float *contacts, const float *cslip, const float *seg, float *obs,
                           hipStream_t s);

@@ -238,8 +238,11 @@ struct StepBounds {
 
 // EQ3: the observation of Eq. 3 (cost_mode 1) compiled in; the default
 // force-only kernels carry none of its registers.  SDF: links against the
-// object's distance field (collision_mode 1)
-template <typename SR, bool EQ3, bool SDF = false>
+// object's distance field (collision_mode 1).  SEGIN: the step's hand
+// segments come from k_hand_fk (in seg_out) instead of every wavefront's own
+// hand kinematics -- the same bits, one evaluation per step instead of one
+// per simulation, for launches that fill the GPU
+template <typename SR, bool EQ3, bool SDF = false, bool SEGIN = false>
 __global__ __launch_bounds__(StepBounds<SR>::threads) void k_step(Consts P, Tables tb,
                                                const float *__restrict__ u_prev, const float *__restrict__ u,
                                                float *__restrict__ state, float *__restrict__ params,
@@ -253,7 +256,7 @@ __global__ __launch_bounds__(StepBounds<SR>::threads) void k_step(Consts P, Tabl
     const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
     const int e = xcd_block(blockIdx.x, gridDim.x) * (blockDim.x / WAVE) + wib;
     if (e >= P.K) return;
-    WaveLds lds = carve_lds(smem, wib, P.max_cand, P.L);
+    WaveLds lds = carve_lds(smem, wib, P.max_cand, SEGIN ? 0 : P.L);
     const int type = tb.env_type[e];
     const int S = tb.n_spheres[type];
     const float *sph = tb.spheres + (size_t)type * P.S_max * 4;
@@ -262,16 +265,17 @@ __global__ __launch_bounds__(StepBounds<SR>::threads) void k_step(Consts P, Tabl
     int wkey;
     float wr[3];
     load_warm(warm, P.C_max, e, wkey, wr);
-    // every wavefront evaluates the step's hand kinematics itself (the
-    // candidate list's LDS as scratch), while its state loads are in flight:
-    // no launch of its own on the per-step path, and the same bits as
-    // k_hand_fk
-    hand_kinematics(tb.hand, P.L, P.D, P.dt, u_prev, u, carve_fk(reinterpret_cast<char *>(lds.cand_d), P.L, P.D),
-                    lds.seg,
-                    lane_id(), WAVE, [] { wave_sync(); });
+    // otherwise every wavefront evaluates the step's hand kinematics itself
+    // (the candidate list's LDS as scratch), while its state loads are in
+    // flight: no launch of its own on the per-step path, and the same bits
+    // as k_hand_fk
+    if (!SEGIN)
+        hand_kinematics(tb.hand, P.L, P.D, P.dt, u_prev, u,
+                        carve_fk(reinterpret_cast<char *>(lds.cand_d), P.L, P.D), lds.seg, lane_id(), WAVE,
+                        [] { wave_sync(); });
     Body B;
     body_from_rows(rows, B);
-    const float *seg = lds.seg;
+    const float *seg = SEGIN ? seg_out : lds.seg;
     StepStats st = {0, 0, 0};
     int link;
     float imp[3];
@@ -297,7 +301,7 @@ __global__ __launch_bounds__(StepBounds<SR>::threads) void k_step(Consts P, Tabl
             o[0] = make_float4(rec[0], rec[1], rec[2], rec[3]);
             o[1] = make_float4(rec[4], rec[5], rec[6], rec[7]);
         }
-        if (e == 0)
+        if (!SEGIN && e == 0)
             for (int i = lane; i < P.L * SEG_STRIDE; i += WAVE) seg_out[i] = seg[i];
     }
     store_body(state, params, P.K, e, B);
@@ -660,13 +664,24 @@ hipError_t launch_hand_fk(const float *hand, int L, int D, float dt, const float
 
 hipError_t launch_step(const Consts &P, const Tables &tb, const float *u_prev, const float *u, float *state,
                        float *params, float *warm, float *contacts, float *cslip, float *seg_out, int64_t *stats,
-                       int waves_per_block, hipStream_t s)
+                       int waves_per_block, bool seg_in, hipStream_t s)
 {
     int blocks = (P.K + waves_per_block - 1) / waves_per_block;
-    size_t lds = (size_t)waves_per_block * wave_lds_bytes(P.max_cand, P.L);
+    seg_in = seg_in && P.solve_fp64;
+    size_t lds = (size_t)waves_per_block * wave_lds_bytes(P.max_cand, seg_in ? 0 : P.L);
     const dim3 grid(blocks), block(WAVE * waves_per_block);
     const bool eq3 = P.cost_mode == 1;
-    if (P.collision_mode == 1)   // float64 solve and force terms only (checked at batch creation)
+    if (seg_in) {
+        if (P.collision_mode == 1)
+            hipLaunchKernelGGL((k_step<double, false, true, true>), grid, block, lds, s, P, tb, u_prev, u, state,
+                               params, warm, contacts, cslip, seg_out, stats);
+        else if (!eq3)
+            hipLaunchKernelGGL((k_step<double, false, false, true>), grid, block, lds, s, P, tb, u_prev, u, state,
+                               params, warm, contacts, cslip, seg_out, stats);
+        else
+            hipLaunchKernelGGL((k_step<double, true, false, true>), grid, block, lds, s, P, tb, u_prev, u, state,
+                               params, warm, contacts, cslip, seg_out, stats);
+    } else if (P.collision_mode == 1)   // float64 solve and force terms only (checked at batch creation)
         hipLaunchKernelGGL((k_step<double, false, true>), grid, block, lds, s, P, tb, u_prev, u, state, params,
                            warm, contacts, cslip, seg_out, stats);
     else if (P.solve_fp64 && !eq3)
