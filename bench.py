@@ -82,8 +82,8 @@ MEASURED = {
     # traffic: (FETCH_SIZE x 1.9998 + WRITE_SIZE x 1.0000) KiB x 1024 per launch, the
     # factors from a 256 MiB device copy under the same counters; valu_*:
     # SQ_INSTS_VALU and SQ_ACTIVE_INST_VALU per launch, summed over the chip
-    "k_window_realtime16384": {"src": "12175c902dc18122", "traffic": 403867250,
-                               "fetch": 31804754, "write": 372062496,
+    "k_window_realtime16384": {"src": "10211d1d59a9e1e3", "traffic": 404130685,
+                               "fetch": 32036583, "write": 372094102,
                                "valu_insts": 2174533529, "valu_busy_quads": 2355665904},
 }
 SIMDS, CLOCK_HZ = 1024, 2.4e9     # MI355X: 256 CUs x 4 SIMDs at 2.4 GHz; a VALU instruction issues in 4 cycles
