@@ -163,10 +163,14 @@ def test_eq3_observation_matches_oracle(pt):
     assert not fails, fails[:20]
 
 
-def test_eq3_batched_equals_plain_bitwise(pt):
-    _say("Eq. 3: plain vs batched, small K=37")
+@pytest.mark.parametrize("full", [False, True])
+def test_eq3_batched_equals_plain_bitwise(pt, full):
+    # full: past eight simulations per compute unit, where the per-step
+    # path takes the step's hand segments from k_hand_fk
+    K = 8 * torch.cuda.get_device_properties(0).multi_processor_count + 37 if full else 37
+    _say(f"Eq. 3: plain vs batched, small K={K}")
     cfg = _eq3(S.CONFIGS["small"])
-    sc = S.make_scene(cfg, K=37, steps=40)
+    sc = S.make_scene(cfg, K=K, steps=40)
     ref = run_plain(pt, sc, 3, cfg.T)
     assert ref["obs"].shape[1] == 7
     for graph in (False, True):

@@ -64,11 +64,15 @@ def test_sdf_pd_hand_per_step_parity(pt):
     assert not fails
 
 
-@pytest.mark.parametrize("cfg_name,K", [("small", 37), ("realtime16384", 48), ("small/C_max=64", 37)])
+@pytest.mark.parametrize("cfg_name,K", [("small", 37), ("realtime16384", 48), ("small/C_max=64", 37), ("small", 0)])
 def test_sdf_batched_equals_plain_bitwise(pt, cfg_name, K):
     # the window kernel's distance-field instantiations against the per-step
     # kernel's, with and without the graph (C_max <= 32 pairs the line
-    # search's trials in the window kernel)
+    # search's trials in the window kernel); K = 0 stands for past eight
+    # simulations per compute unit, where the per-step path takes the
+    # step's hand segments from k_hand_fk
+    if K == 0:
+        K = 8 * torch.cuda.get_device_properties(0).multi_processor_count + 37
     from tests.test_gpu_paths import _assert_same, run_batched, run_plain
     name, _, cap = cfg_name.partition("/C_max=")
     cfg = _sdf_cfg(name)
