@@ -331,12 +331,15 @@ __device__ __forceinline__ void pd_order_contacts(const StepState<double> &st, c
 }
 
 // Sums of N values per contact over each run of rows (one link) and over all
-// contacts: an active lane writes its values as row `pos`; lanes e < N then
-// read the C rows sixteen at a time and add them in row order, each run's
-// sum overwriting its first row (a lane only rewrites its own column of a
-// row it has read) and the total landing in tot[e].  The runs' ends (bit r
-// of ends) are wave-uniform, so the scan branches on them in scalar code.
-// buf: rows of RedStride<double> doubles.
+// contacts: an active lane writes its values as row `pos` (the contacts are
+// lanes 0 .. C-1) and lanes C .. C16-1 zero rows C .. C16-1 (C16 = C rounded
+// up to 16), so that lanes e < N then read the rows sixteen at a time with
+// no bounds test and add them in row order (the zeros after the last run
+// change nothing), each run's sum overwriting its first row (a lane only
+// rewrites its own column of a row it has read) and the total landing in
+// tot[e].  The runs' ends (bit r of ends, r < C) are wave-uniform, so the
+// scan branches on them in scalar code.  buf: 16-byte aligned rows of
+// RedStride<double> doubles, at least C16 of them.
 template <int N>
 __device__ __forceinline__ void pd_segsum(const double (&v)[N], bool act, int pos, int C, uint64_t ends,
                                           double *buf, double *tot)
@@ -344,10 +347,18 @@ __device__ __forceinline__ void pd_segsum(const double (&v)[N], bool act, int po
     constexpr int RS = RedStride<double>::value;
     static_assert(N <= RS, "row too long");
     const int lane = lane_id();
+    const int C16 = (C + 15) & ~15;
     if (act) {
         double *row = buf + pos * RS;
 #pragma unroll
-        for (int j = 0; j < N; ++j) row[j] = v[j];
+        for (int j = 0; j + 2 <= N; j += 2) store16<double>(row + j, v + j);
+        if (N % 2) row[N - 1] = v[N - 1];
+    } else if (lane >= C && lane < C16) {
+        double *row = buf + lane * RS;
+        const double z[2] = {0.0, 0.0};
+#pragma unroll
+        for (int j = 0; j + 2 <= N; j += 2) store16<double>(row + j, z);
+        if (N % 2) row[N - 1] = 0.0;
     }
     wave_sync();
     if (lane < N) {
@@ -356,11 +367,10 @@ __device__ __forceinline__ void pd_segsum(const double (&v)[N], bool act, int po
         for (int r0 = 0; r0 < C; r0 += 16) {
             double x[16];
 #pragma unroll
-            for (int k = 0; k < 16; ++k) x[k] = r0 + k < C ? buf[(r0 + k) * RS + lane] : 0.0;
+            for (int k = 0; k < 16; ++k) x[k] = buf[(r0 + k) * RS + lane];
 #pragma unroll
             for (int k = 0; k < 16; ++k) {
                 const int r = r0 + k;
-                if (r >= C) continue;
                 a += x[k];
                 if ((ends >> r) & 1ull) {
                     buf[start * RS + lane] = a;
