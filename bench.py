@@ -60,7 +60,7 @@ def parse():
     ap.add_argument("--profile", action="store_true",
                     help="run for the profiler: one run of the headline leg as timed (batched + refinement), "
                          "nothing else")
-    ap.add_argument("--profile-leg", choices=["pd_hand", "distance_field"],
+    ap.add_argument("--profile-leg", choices=["plain", "pd_hand", "distance_field"],
                     help="run for the profiler: one run of that leg on the real-time workload (the per-step path; "
                          "for the distance field also its batched windows), nothing else")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -720,7 +720,13 @@ def main():
     n_warm = max(1, -(-args.warmup // T))
     if args.profile_leg:
         steps = min(n_win * T, 300)
-        if args.profile_leg == "pd_hand":
+        if args.profile_leg == "plain":
+            psetup = make_setup(pt, S, dev, sp, cfg, n_warm + -(-steps // T))
+            r = plain_run(pt, psetup, dev, sp, steps, n_warm * T)
+            sk = r.pop("step_kernel")
+            r["roofline"] = step_roofline("k_hand_fk + k_step<double, false, false, true>", sk["flops"],
+                                          sk["env_steps"], sk["avg_launch_us"], sk["launches"])
+        elif args.profile_leg == "pd_hand":
             r = pd_run(pt, S, dev, cfg, steps, n_warm * T)
             sk = r.pop("step_kernel")
             r["roofline"] = step_roofline("k_step_pd", sk["flops"], sk["env_steps"], sk["avg_launch_us"],
